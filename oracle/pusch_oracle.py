@@ -1,0 +1,235 @@
+"""FP64 CPU oracle of the PUSCH lower-PHY receive chain.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check of the package
+entry file and the CPU-baseline leg of the benchmark may import this module.
+The HIP product path never calls it, and this module shares no code, tables
+or helpers with the HIP library (it does not import the package).
+
+Everything is computed in complex128 from the plain definitions, in the order
+the paper gives the chain (Sec. II, Fig. "PUSCH processing chain"): OFDM
+demodulation (FFT per antenna and symbol), beamforming (matrix product with
+known coefficients), least-squares channel estimation on the pilot symbols,
+then the MIMO stage of Eq. 2 solved through a Cholesky decomposition of the
+Gram matrix followed by two triangular solves.
+
+Readings of points the paper leaves open (each also stated where used):
+  R1  forward FFT e^{-2 pi i f n / N}, unscaled, natural output order;
+  R3  active subcarrier k <-> FFT bin (k - N_act//2) mod N;
+  R4  default beamformer = first N_B rows of the unitary N_R-point DFT;
+  R5  pilots of the N_L UEs form a comb: pilot symbol j, subcarrier k belongs
+      to UE (k + o_j) mod N_L with o_j = j * (N_L // N_pilot);
+  R6  the channel is static over the slot: all pilot symbols are merged into
+      one estimate and the Cholesky factor is computed once per subcarrier and
+      reused for every data symbol;
+  R12 a non-positive or non-finite Cholesky pivot flags the subcarrier
+      (status 1) and its detected symbols are set to 0.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "active_bins",
+    "ofdm_demodulate",
+    "dft_beamformer",
+    "beamform",
+    "pilot_owner",
+    "ls_channel_estimate",
+    "gram",
+    "cholesky_crout",
+    "forward_substitution",
+    "back_substitution",
+    "mmse_detect",
+    "receive_slot",
+]
+
+
+def active_bins(n_fft: int, n_sc: int) -> np.ndarray:
+    """FFT bin of each active subcarrier, centred band with DC used (reading R3)."""
+    return (np.arange(n_sc) - n_sc // 2) % n_fft
+
+
+def ofdm_demodulate(x_td, n_sc: int | None = None) -> np.ndarray:
+    """OFDM demodulation (Sec. II; Table 1, row "OFDM dem."): one N-point FFT
+    per antenna and OFDM symbol, X[f] = sum_n x[n] e^{-2 pi i f n / N}
+    (reading R1).  With n_sc given, the n_sc active bins follow in subcarrier
+    order (reading R3; for n_sc == N this is the centred reordering of all
+    bins); with n_sc None the N bins are returned in natural order.
+
+    x_td: [..., N] time-domain samples.  Returns [..., n_sc or N] complex128.
+    """
+    x = np.asarray(x_td, dtype=np.complex128)
+    X = np.fft.fft(x, axis=-1)
+    if n_sc is None:
+        return X
+    return X[..., active_bins(x.shape[-1], n_sc)]
+
+
+def dft_beamformer(n_beams: int, n_ant: int) -> np.ndarray:
+    """Beamforming coefficients (Sec. II: "known coefficients", reading R4):
+    W[b, r] = e^{-2 pi i b r / N_R} / sqrt(N_R), b < N_B.  Rows are orthonormal."""
+    b = np.arange(n_beams)[:, None]
+    r = np.arange(n_ant)[None, :]
+    return np.exp(-2j * np.pi * ((b * r) % n_ant) / n_ant) / np.sqrt(n_ant)
+
+
+def beamform(W, Xa) -> np.ndarray:
+    """Beamforming (Sec. II; Table 1, row "BF"): N_B beams as linear
+    combinations of the N_R antennas on every subcarrier of every symbol,
+    Y[..., b, k] = sum_r W[b, r] Xa[..., r, k].
+
+    W: [N_B, N_R]; Xa: [..., N_R, K].  Returns [..., N_B, K]."""
+    return np.matmul(np.asarray(W, np.complex128), np.asarray(Xa, np.complex128))
+
+
+def pilot_owner(n_sc: int, j: int, n_ue: int, n_pilot: int) -> np.ndarray:
+    """UE owning each subcarrier of pilot symbol j (reading R5)."""
+    return (np.arange(n_sc) + j * (n_ue // n_pilot)) % n_ue
+
+
+def ls_channel_estimate(Yp, pilots, n_ue: int) -> np.ndarray:
+    """Least-squares channel estimation on block-type pilot symbols (Sec. II,
+    CHE; Table 1, row "CHE": an element-wise division per beam and UE).
+
+    On pilot symbol j, subcarrier k (owned by UE l, reading R5) the LS estimate
+    of UE l's beam-domain channel is Y_j[:, k] * conj(p_j[k]) / |p_j[k]|^2.
+    Per UE, the estimates of all pilot symbols are merged by position
+    (duplicates at one subcarrier are averaged, reading R6) and linearly
+    interpolated along the subcarriers, holding the end values beyond the
+    first and last pilot position.
+
+    Yp: [N_p, N_B, K] beam-domain pilot symbols; pilots: [N_p, K].
+    Returns H_hat [K, N_B, N_L] (one N_B x N_L matrix per subcarrier, Eq. 1).
+    """
+    Yp = np.asarray(Yp, np.complex128)
+    pilots = np.asarray(pilots, np.complex128)
+    n_pilot, n_beams, K = Yp.shape
+    if K < n_ue:
+        raise ValueError("every UE needs at least one pilot subcarrier")
+    H = np.zeros((K, n_beams, n_ue), dtype=np.complex128)
+    grid = np.arange(K, dtype=np.float64)
+    for l in range(n_ue):
+        pos_list, val_list = [], []
+        for j in range(n_pilot):
+            ks = np.nonzero(pilot_owner(K, j, n_ue, n_pilot) == l)[0]
+            p = pilots[j, ks]
+            pos_list.append(ks)
+            val_list.append(Yp[j][:, ks] * (np.conj(p) / (p.real ** 2 + p.imag ** 2)))
+        pos = np.concatenate(pos_list)
+        val = np.concatenate(val_list, axis=1)  # [N_B, n_positions]
+        upos, inv = np.unique(pos, return_inverse=True)
+        acc = np.zeros((n_beams, len(upos)), dtype=np.complex128)
+        cnt = np.zeros(len(upos))
+        np.add.at(cnt, inv, 1.0)
+        for b in range(n_beams):
+            np.add.at(acc[b], inv, val[b])
+        acc /= cnt[None, :]
+        x = upos.astype(np.float64)
+        for b in range(n_beams):
+            H[:, b, l] = np.interp(grid, x, acc[b].real) + 1j * np.interp(grid, x, acc[b].imag)
+    return H
+
+
+def gram(H, sigma2: float) -> np.ndarray:
+    """Regularised Gram matrix of Eq. 2: G = H^H H + sigma^2 I per subcarrier.
+
+    H: [..., N_B, N_L].  Returns [..., N_L, N_L]."""
+    H = np.asarray(H, np.complex128)
+    G = np.matmul(np.conj(np.swapaxes(H, -1, -2)), H)
+    n = H.shape[-1]
+    return G + float(sigma2) * np.eye(n)
+
+
+def cholesky_crout(G) -> tuple[np.ndarray, np.ndarray]:
+    """Cholesky decomposition G = L L^H (Sec. II after Eq. 2; Sec. V-C: the
+    Cholesky-Crout order, computing L column by column, each new column using
+    the already-computed elements of the rows).
+
+    For column j: d = G_jj - sum_{m<j} |L_jm|^2, L_jj = sqrt(d), and for i > j
+    L_ij = (G_ij - sum_{m<j} L_im conj(L_jm)) / L_jj.  A pivot d that is not
+    positive or not finite marks the matrix as failed (reading R12).
+
+    G: [..., n, n] Hermitian.  Returns (L [..., n, n], ok [...] bool).
+    """
+    G = np.asarray(G, np.complex128)
+    n = G.shape[-1]
+    L = np.zeros_like(G)
+    ok = np.ones(G.shape[:-2], dtype=bool)
+    for j in range(n):
+        row_j = L[..., j, :j]
+        d = G[..., j, j].real - np.sum(row_j.real ** 2 + row_j.imag ** 2, axis=-1)
+        good = (d > 0) & np.isfinite(d)
+        ok &= good
+        ljj = np.sqrt(np.where(good, d, np.nan))
+        L[..., j, j] = ljj
+        for i in range(j + 1, n):
+            s = G[..., i, j] - np.sum(L[..., i, :j] * np.conj(row_j), axis=-1)
+            L[..., i, j] = s / ljj
+    return L, ok
+
+
+def forward_substitution(L, b) -> np.ndarray:
+    """Solve L z = b for lower-triangular L (first of the two triangular systems
+    that replace the inverse in Eq. 2).  L: [..., n, n]; b: [..., n]."""
+    L = np.asarray(L, np.complex128)
+    b = np.asarray(b, np.complex128)
+    n = L.shape[-1]
+    z = np.zeros(np.broadcast_shapes(L.shape[:-1], b.shape), dtype=np.complex128)
+    for i in range(n):
+        s = b[..., i] - np.sum(L[..., i, :i] * z[..., :i], axis=-1)
+        z[..., i] = s / L[..., i, i]
+    return z
+
+
+def back_substitution(L, z) -> np.ndarray:
+    """Solve L^H x = z (second triangular system).  L: [..., n, n]; z: [..., n]."""
+    L = np.asarray(L, np.complex128)
+    z = np.asarray(z, np.complex128)
+    n = L.shape[-1]
+    x = np.zeros(np.broadcast_shapes(L.shape[:-1], z.shape), dtype=np.complex128)
+    for i in range(n - 1, -1, -1):
+        # row i of L^H holds conj(L_mi) for m >= i
+        s = z[..., i] - np.sum(np.conj(L[..., i + 1:, i]) * x[..., i + 1:], axis=-1)
+        x[..., i] = s / np.conj(L[..., i, i])
+    return x
+
+
+def mmse_detect(H, Yd, sigma2: float) -> tuple[np.ndarray, np.ndarray]:
+    """MIMO stage, Eq. 2: x = (H^H H + sigma^2 I)^{-1} H^H y, evaluated as the
+    paper prescribes: Gram matrix, Cholesky decomposition, matched filter
+    b = H^H y, forward substitution L z = b, back substitution L^H x = z.
+    One factorisation per subcarrier serves all data symbols (reading R6).
+
+    H: [K, N_B, N_L]; Yd: [D, K, N_B].  Returns (x_hat [D, K, N_L], ok [K]).
+    """
+    H = np.asarray(H, np.complex128)
+    Yd = np.asarray(Yd, np.complex128)
+    G = gram(H, sigma2)
+    L, ok = cholesky_crout(G)
+    b = np.einsum("kbl,dkb->dkl", np.conj(H), Yd)
+    z = forward_substitution(L[None], b)
+    x = back_substitution(L[None], z)
+    x[:, ~ok, :] = 0.0
+    return x, ok
+
+
+def receive_slot(x_td, pilots, pilot_symb, n_ue: int, n_sc: int, sigma2: float, W=None, n_beams: int | None = None) -> dict:
+    """The whole receive chain of one slot (Sec. II), in the paper's order.
+
+    x_td: [S, N_R, N] time-domain samples; pilots: [N_p, K]; pilot_symb: the
+    0-based pilot symbol indices.  W defaults to the DFT beamformer with
+    n_beams rows.  Returns a dict with the intermediates and the result:
+    X [S, N_R, K], Y [S, N_B, K], H [K, N_B, N_L], x_hat [D, K, N_L], ok [K].
+    """
+    x_td = np.asarray(x_td)
+    S, n_ant, _ = x_td.shape
+    if W is None:
+        W = dft_beamformer(n_beams, n_ant)
+    X = ofdm_demodulate(x_td, n_sc)
+    Y = beamform(W, X)
+    pilot_symb = list(pilot_symb)
+    data_symb = [s for s in range(S) if s not in pilot_symb]
+    H = ls_channel_estimate(Y[pilot_symb], pilots, n_ue)
+    Yd = np.swapaxes(Y[data_symb], -1, -2)  # [D, K, N_B]
+    x_hat, ok = mmse_detect(H, Yd, sigma2)
+    return {"X": X, "Y": Y, "H": H, "x_hat": x_hat, "ok": ok}

@@ -1,0 +1,407 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each stage of the chain is checked against something other than the oracle's
+own formula: hand-derived worked examples (tests/golden), brute-force sums on
+tiny inputs, closed forms, independent library routines and invariants.  The
+mutation tests at the end plant plausible mistakes in a copy of the oracle and
+check that one of these pins catches each of them.
+"""
+import math
+import types
+
+import numpy as np
+import pytest
+
+from oracle import pusch_oracle as O
+from oracle import metrics as M
+from paper_2210_09196_amd import synth
+
+RNG = np.random.default_rng(1234)
+
+
+def crandn(*shape, rng=RNG):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def naive_dft(x):
+    """Brute-force O(N^2) DFT written as explicit sums (definition of Sec. II's FFT)."""
+    n = len(x)
+    out = []
+    for f in range(n):
+        acc = 0j
+        for t in range(n):
+            ang = -2.0 * math.pi * ((f * t) % n) / n
+            acc += x[t] * complex(math.cos(ang), math.sin(ang))
+        out.append(acc)
+    return np.array(out)
+
+
+# ----------------------------------------------------------------------------- FFT (a1)
+
+@pytest.mark.parametrize("n", [4, 16, 64, 256])
+def test_fft_matches_bruteforce_dft(n):
+    x = crandn(n)
+    X = O.ofdm_demodulate(x)
+    ref = naive_dft(x)
+    assert np.max(np.abs(X - ref)) <= 1e-12 * n * np.max(np.abs(ref))
+
+
+def test_fft_golden(golden):
+    g = golden("dft_small.txt")
+    np.testing.assert_allclose(O.ofdm_demodulate(np.array(g["x1"], complex)), g["X1"], atol=1e-13)
+    np.testing.assert_allclose(O.ofdm_demodulate(np.array(g["x2"], complex)), g["X2"], atol=1e-13)
+    X3 = O.ofdm_demodulate(np.array(g["x3"], complex))
+    np.testing.assert_allclose(X3[0::2], g["X3_even"], atol=1e-13)
+
+
+@pytest.mark.parametrize("n", [64, 4096])
+def test_fft_parseval_impulse_tone_linearity(n):
+    x = crandn(3, n)
+    X = O.ofdm_demodulate(x)
+    np.testing.assert_allclose(np.sum(np.abs(X) ** 2, -1), n * np.sum(np.abs(x) ** 2, -1), rtol=1e-12)
+    imp = np.zeros(n, complex)
+    imp[0] = 1.0
+    np.testing.assert_allclose(O.ofdm_demodulate(imp), np.ones(n), atol=1e-13)
+    f0 = 5
+    tone = np.exp(2j * np.pi * f0 * np.arange(n) / n)
+    expect = np.zeros(n, complex)
+    expect[f0] = n
+    np.testing.assert_allclose(O.ofdm_demodulate(tone), expect, atol=1e-9)
+    a, b = 0.3 - 1.1j, 2.0 + 0.5j
+    np.testing.assert_allclose(O.ofdm_demodulate(a * x[0] + b * x[1]), a * X[0] + b * X[1], atol=1e-10)
+    g = crandn(n)
+    np.testing.assert_allclose(O.ofdm_demodulate(np.fft.ifft(g)), g, atol=1e-12)
+
+
+@pytest.mark.parametrize("n_fft,n_sc", [(4096, 3300), (256, 256), (64, 63), (1024, 1)])
+def test_active_bin_map(n_fft, n_sc):
+    bins = O.active_bins(n_fft, n_sc)
+    assert len(set(bins.tolist())) == n_sc  # distinct bins
+    assert bins[n_sc // 2] == 0  # DC sits at the centre subcarrier
+    # a tone on bin f lands on subcarrier (f + n_sc//2) mod N when that is < n_sc
+    for f in (0, 1, n_fft - 1, 7):
+        k = (f + n_sc // 2) % n_fft
+        tone = np.exp(2j * np.pi * f * np.arange(n_fft) / n_fft)
+        Xa = O.ofdm_demodulate(tone, n_sc)
+        if k < n_sc:
+            assert abs(Xa[k] - n_fft) < 1e-8
+            assert np.sum(np.abs(Xa) > 1e-6) == 1
+        else:
+            assert np.all(np.abs(Xa) < 1e-6)
+
+
+# ----------------------------------------------------------------------------- BF (a2)
+
+@pytest.mark.parametrize("nb,nr", [(16, 16), (32, 64), (5, 7)])
+def test_dft_beamformer_rows_orthonormal(nb, nr):
+    W = O.dft_beamformer(nb, nr)
+    np.testing.assert_allclose(W @ W.conj().T, np.eye(nb), atol=1e-13)
+
+
+def test_square_dft_beamforming_is_antenna_fft():
+    nr, K = 16, 10
+    X = crandn(3, nr, K)
+    Y = O.beamform(O.dft_beamformer(nr, nr), X)
+    np.testing.assert_allclose(Y, np.fft.fft(X, axis=1) / math.sqrt(nr), atol=1e-12)
+
+
+def test_beamform_bruteforce():
+    W = crandn(3, 5)
+    X = crandn(2, 5, 4)
+    Y = O.beamform(W, X)
+    for s in range(2):
+        for b in range(3):
+            for k in range(4):
+                acc = sum(W[b, r] * X[s, r, k] for r in range(5))
+                assert abs(Y[s, b, k] - acc) < 1e-12
+
+
+# ----------------------------------------------------------------------------- LS (a3)
+
+def test_ls_golden(golden):
+    g = golden("ls_comb_small.txt")
+    Yp = np.array(g["Y"], complex)[None, None, :]
+    p = np.array(g["pilots"], complex)[None, :]
+    H = O.ls_channel_estimate(Yp, p, g["n_ue"])
+    np.testing.assert_allclose(H[:, 0, 0], g["H_ue0"], atol=1e-14)
+    np.testing.assert_allclose(H[:, 0, 1], g["H_ue1"], atol=1e-14)
+
+
+def _comb_pilot_grid(Hk, pilots, n_ue):
+    """Beam-domain pilot symbols of a known channel Hk [K, NB, NL] (noiseless)."""
+    n_pilot, K = pilots.shape
+    Yp = np.zeros((n_pilot, Hk.shape[1], K), complex)
+    for j in range(n_pilot):
+        own = (np.arange(K) + j * (n_ue // n_pilot)) % n_ue
+        Yp[j] = Hk[np.arange(K), :, own].T * pilots[j][None, :]
+    return Yp
+
+
+@pytest.mark.parametrize("n_ue,n_pilot,K", [(4, 1, 64), (16, 2, 200), (3, 2, 31)])
+def test_ls_linear_channel_is_exact(n_ue, n_pilot, K):
+    nb = 5
+    A, B = crandn(nb, n_ue), crandn(nb, n_ue)
+    k = np.arange(K, dtype=float)
+    Hk = A[None] + B[None] * k[:, None, None]
+    pil = synth.qam_modulate(RNG.integers(0, 2, (n_pilot, K, 2)), 2)
+    H = O.ls_channel_estimate(_comb_pilot_grid(Hk, pil, n_ue), pil, n_ue)
+    for l in range(n_ue):
+        pos = [kk for kk in range(K) if any((kk + j * (n_ue // n_pilot)) % n_ue == l for j in range(n_pilot))]
+        lo, hi = pos[0], pos[-1]
+        np.testing.assert_allclose(H[lo:hi + 1, :, l], Hk[lo:hi + 1, :, l], atol=1e-11)
+        # end-value hold beyond the outermost pilots
+        np.testing.assert_allclose(H[:lo, :, l], np.broadcast_to(Hk[lo, :, l], (lo, nb)), atol=1e-11)
+        np.testing.assert_allclose(H[hi + 1:, :, l], np.broadcast_to(Hk[hi, :, l], (K - hi - 1, nb)), atol=1e-11)
+
+
+def test_ls_duplicate_positions_are_averaged():
+    K, nb = 12, 3
+    pil = synth.qam_modulate(RNG.integers(0, 2, (2, K, 2)), 2)
+    Yp = crandn(2, nb, K)
+    H = O.ls_channel_estimate(Yp, pil, 1)  # one UE: both pilot symbols hit every subcarrier
+    ls = Yp * (np.conj(pil) / np.abs(pil) ** 2)[:, None, :]
+    np.testing.assert_allclose(H[:, :, 0], ((ls[0] + ls[1]) / 2).T, atol=1e-13)
+
+
+def test_ls_noise_variance_on_pilot_res():
+    K, nb, sigma2 = 4000, 4, 0.05
+    pil = synth.qam_modulate(RNG.integers(0, 2, (1, K, 2)), 2) * 1.7
+    Hk = np.zeros((K, nb, 1), complex)
+    Yp = _comb_pilot_grid(Hk, pil, 1) + crandn(1, nb, K) * math.sqrt(sigma2 / 2)
+    H = O.ls_channel_estimate(Yp, pil, 1)
+    est = np.mean(np.abs(H) ** 2)
+    expect = sigma2 / 1.7 ** 2
+    # 16000 samples of an exponential variable: relative std 1/sqrt(16000) ~ 0.8 %; 5 sigma bound
+    assert abs(est / expect - 1) < 5 / math.sqrt(K * nb)
+
+
+def test_ls_noiseless_flat_chain_recovers_beam_channel():
+    cfg = synth.CFG1.replace(snr_db=None)
+    s = synth.make_slot(cfg, 7)
+    r = O.receive_slot(s["x_td"], s["pilots"], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, 0.0, n_beams=cfg.n_beams)
+    H_beam = O.dft_beamformer(cfg.n_beams, cfg.n_ant) @ s["h_ant"]  # [K, NB, NL]
+    assert M.nrmse(r["H"], H_beam) < 1e-6  # input is complex64: error is its rounding
+
+
+# ----------------------------------------------------------------------------- Gram + Crout (a4, a5)
+
+def test_crout_golden_exact(golden):
+    g = golden("crout_3x3.txt")
+    L, ok = O.cholesky_crout(np.array(g["G"], complex))
+    assert ok
+    np.testing.assert_array_equal(L, np.array(g["L"], complex))
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 16, 32])
+def test_crout_reconstructs_and_matches_lapack(n):
+    H = crandn(50, n + 3, n)
+    G = O.gram(H, 0.1)
+    L, ok = O.cholesky_crout(G)
+    assert ok.all()
+    np.testing.assert_allclose(L @ np.conj(np.swapaxes(L, -1, -2)), G, atol=1e-11 * n)
+    assert np.all(np.triu(L, 1) == 0)
+    d = np.diagonal(L, axis1=-2, axis2=-1)
+    assert np.all(d.imag == 0) and np.all(d.real > 0)
+    np.testing.assert_allclose(L, np.linalg.cholesky(G), atol=1e-11 * n)
+
+
+def test_crout_2x2_closed_form():
+    G = np.array([[5.0, 1 - 2j], [1 + 2j, 4.0]])
+    L, ok = O.cholesky_crout(G)
+    l11 = math.sqrt(5.0)
+    l21 = (1 + 2j) / l11
+    l22 = math.sqrt(4.0 - abs(l21) ** 2)
+    np.testing.assert_allclose(L, [[l11, 0], [l21, l22]], atol=1e-15)
+
+
+def test_gram_bruteforce():
+    H = crandn(6, 3)
+    G = O.gram(H, 0.25)
+    for i in range(3):
+        for j in range(3):
+            acc = sum(np.conj(H[b, i]) * H[b, j] for b in range(6)) + (0.25 if i == j else 0)
+            assert abs(G[i, j] - acc) < 1e-13
+
+
+def test_crout_flags_non_pd():
+    H = crandn(4, 8, 3)
+    H[1, :, 2] = 0  # zero UE column, sigma^2 = 0: pivot exactly 0
+    H[2, 0, 0] = np.nan
+    G = O.gram(H, 0.0)
+    G[3] = np.diag([1.0, -1.0, 1.0])
+    _, ok = O.cholesky_crout(G)
+    assert ok.tolist() == [True, False, False, False]
+
+
+# ----------------------------------------------------------------------------- solve (a6)
+
+def test_mmse_golden(golden):
+    g = golden("mmse_2x2.txt")
+    H = np.array(g["H"], complex)[None]
+    y = np.array(g["y"], complex)[None, None]
+    x, ok = O.mmse_detect(H, y, g["sigma2"])
+    np.testing.assert_allclose(x[0, 0], g["x"], atol=1e-14)
+    x0, _ = O.mmse_detect(H, y, 0.0)
+    np.testing.assert_allclose(x0[0, 0], g["x_zf"], atol=1e-14)
+
+
+@pytest.mark.parametrize("nb,nl", [(2, 2), (8, 4), (32, 16)])
+def test_mmse_matches_explicit_inverse(nb, nl):
+    K, D = 20, 3
+    H = crandn(K, nb, nl)
+    y = crandn(D, K, nb)
+    s2 = 0.3
+    x, ok = O.mmse_detect(H, y, s2)
+    assert ok.all()
+    for k in range(K):
+        Gi = np.linalg.inv(H[k].conj().T @ H[k] + s2 * np.eye(nl))
+        for d in range(D):
+            np.testing.assert_allclose(x[d, k], Gi @ H[k].conj().T @ y[d, k], atol=1e-10)
+
+
+def test_mmse_tends_to_zero_forcing():
+    H = crandn(10, 8, 4)
+    y = crandn(2, 10, 8)
+    x, _ = O.mmse_detect(H, y, 1e-12)
+    zf = np.einsum("klb,dkb->dkl", np.linalg.pinv(H), y)
+    np.testing.assert_allclose(x, zf, atol=1e-9)
+
+
+def test_mmse_single_ue_closed_form():
+    h = crandn(30, 6, 1)
+    y = crandn(4, 30, 6)
+    s2 = 0.7
+    x, _ = O.mmse_detect(h, y, s2)
+    ref = np.einsum("kb,dkb->dk", np.conj(h[:, :, 0]), y) / (np.sum(np.abs(h[:, :, 0]) ** 2, -1) + s2)
+    np.testing.assert_allclose(x[:, :, 0], ref, atol=1e-12)
+
+
+def test_mmse_noiseless_exact_recovery():
+    H = crandn(40, 16, 8)
+    xs = crandn(5, 40, 8)
+    y = np.einsum("kbl,dkl->dkb", H, xs)
+    x, ok = O.mmse_detect(H, y, 0.0)
+    np.testing.assert_allclose(x, xs, atol=1e-10)
+
+
+def test_mmse_failed_subcarrier_is_zeroed():
+    H = crandn(3, 4, 2)
+    H[1, :, 1] = 0
+    x, ok = O.mmse_detect(H, crandn(2, 3, 4), 0.0)
+    assert ok.tolist() == [True, False, True]
+    assert np.all(x[:, 1] == 0)
+
+
+def test_single_ue_qpsk_ber_matches_rayleigh_mrc_closed_form():
+    # N_L = 1: MMSE is a positive scaling of maximum-ratio combining, so QPSK
+    # decisions follow the textbook L-branch MRC BER in i.i.d. Rayleigh fading:
+    # P_b = ((1-mu)/2)^L sum_{k<L} C(L-1+k, k) ((1+mu)/2)^k, mu = sqrt(g/(1+g)),
+    # with g the per-branch SNR per bit (Es/N0 / 2 for QPSK).
+    rng = np.random.default_rng(99)
+    n, nb, snr_db = 200_000, 2, 6.0
+    s2 = 10 ** (-snr_db / 10)
+    bits = rng.integers(0, 2, (n, 2))
+    x = synth.qam_modulate(bits, 2)
+    h = (rng.standard_normal((n, nb)) + 1j * rng.standard_normal((n, nb))) / math.sqrt(2)
+    noise = (rng.standard_normal((n, nb)) + 1j * rng.standard_normal((n, nb))) * math.sqrt(s2 / 2)
+    y = h * x[:, None] + noise
+    xh, _ = O.mmse_detect(h[:, :, None], y[None], s2)
+    pts, lab = synth.qam_table(2)
+    _, bh = M.hard_decide(xh[0, :, 0], pts, lab)
+    ber = np.mean(bh != bits)
+    g = (1 / s2) / 2
+    mu = math.sqrt(g / (1 + g))
+    pb = ((1 - mu) / 2) ** nb * sum(math.comb(nb - 1 + k, k) * ((1 + mu) / 2) ** k for k in range(nb))
+    sd = math.sqrt(pb * (1 - pb) / (2 * n))
+    assert abs(ber - pb) < 5 * sd + 1e-4
+
+
+# ----------------------------------------------------------------------------- end to end (a7)
+
+def test_chain_noiseless_cfg1_recovers_bits_exactly():
+    cfg = synth.CFG1.replace(snr_db=None)
+    s = synth.make_slot(cfg, 1000)
+    r = O.receive_slot(s["x_td"], s["pilots"], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, 0.0, n_beams=cfg.n_beams)
+    x = np.swapaxes(s["data"], 1, 2)
+    assert M.evm_db(r["x_hat"], x) < -100
+    pts, lab = synth.qam_table(cfg.qam_bits)
+    _, bh = M.hard_decide(r["x_hat"], pts, lab)
+    np.testing.assert_array_equal(bh, np.swapaxes(s["bits"], 1, 2))
+
+
+def test_chain_cfg1_20db_error_free():
+    cfg = synth.CFG1
+    s = synth.make_slot(cfg, 1000)
+    r = O.receive_slot(s["x_td"], s["pilots"], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, s["sigma2"], n_beams=cfg.n_beams)
+    pts, lab = synth.qam_table(cfg.qam_bits)
+    _, bh = M.hard_decide(r["x_hat"], pts, lab)
+    assert np.mean(bh != np.swapaxes(s["bits"], 1, 2)) == 0.0
+    assert r["ok"].all()
+
+
+# ----------------------------------------------------------------------------- planted mistakes
+
+def _mutant(old: str, new: str) -> types.ModuleType:
+    """A copy of the oracle with one textual change (a planted mistake)."""
+    src = open(O.__file__).read()
+    assert src.count(old) >= 1, old
+    mod = types.ModuleType("oracle_mutant")
+    exec(compile(src.replace(old, new, 1), "oracle_mutant", "exec"), mod.__dict__)
+    return mod
+
+
+def _pins_pass(mod, golden) -> bool:
+    """Run a compact set of the pins above against a module; False if any fails."""
+    try:
+        x = crandn(16)
+        assert np.allclose(mod.ofdm_demodulate(x), naive_dft(x), atol=1e-9)
+        # DC lands on the centre active subcarrier, bin 1 on the next one
+        tone = np.exp(2j * np.pi * np.arange(8) / 8)
+        assert abs(mod.ofdm_demodulate(np.ones(8), 5)[2] - 8) < 1e-9
+        assert abs(mod.ofdm_demodulate(tone, 5)[3] - 8) < 1e-9
+        g = golden("crout_3x3.txt")
+        L, ok = mod.cholesky_crout(np.array(g["G"], complex))
+        assert ok and np.array_equal(L, np.array(g["L"], complex))
+        g = golden("mmse_2x2.txt")
+        xm, _ = mod.mmse_detect(np.array(g["H"], complex)[None], np.array(g["y"], complex)[None, None], g["sigma2"])
+        assert np.allclose(xm[0, 0], g["x"], atol=1e-12)
+        g = golden("ls_comb_small.txt")
+        H = mod.ls_channel_estimate(np.array(g["Y"], complex)[None, None, :], np.array(g["pilots"], complex)[None], 2)
+        assert np.allclose(H[:, 0, 0], g["H_ue0"]) and np.allclose(H[:, 0, 1], g["H_ue1"])
+        W = mod.dft_beamformer(4, 4)
+        X = crandn(1, 4, 3)
+        assert np.allclose(mod.beamform(W, X), np.fft.fft(X, axis=1) / 2)
+        Hs = crandn(5, 8, 3)
+        ys = crandn(2, 5, 8)
+        xs, _ = mod.mmse_detect(Hs, ys, 0.2)
+        for k in range(5):
+            Gi = np.linalg.inv(Hs[k].conj().T @ Hs[k] + 0.2 * np.eye(3))
+            assert np.allclose(xs[:, k], (Gi @ Hs[k].conj().T @ ys[:, k].T).T, atol=1e-9)
+        return True
+    except AssertionError:
+        return False
+
+
+MUTATIONS = [
+    ("X = np.fft.fft(x, axis=-1)", "X = np.fft.ifft(x, axis=-1) * x.shape[-1]"),  # wrong FFT sign
+    ("return (np.arange(n_sc) - n_sc // 2) % n_fft", "return (np.arange(n_sc) + n_sc // 2) % n_fft"),
+    ("np.exp(-2j * np.pi * ((b * r) % n_ant) / n_ant)", "np.exp(2j * np.pi * ((b * r) % n_ant) / n_ant)"),
+    ("(np.conj(p) / (p.real ** 2 + p.imag ** 2))", "(p / (p.real ** 2 + p.imag ** 2))"),  # LS without conjugate
+    ("j * (n_ue // n_pilot)) % n_ue", "j * (n_ue // n_pilot) + 1) % n_ue"),  # wrong pilot owner
+    ("G = np.matmul(np.conj(np.swapaxes(H, -1, -2)), H)", "G = np.matmul(np.swapaxes(H, -1, -2), H)"),
+    ("L[..., i, :j] * np.conj(row_j)", "L[..., i, :j] * row_j"),  # Crout without conjugate
+    ("np.sum(row_j.real ** 2 + row_j.imag ** 2, axis=-1)", "0.0"),  # dropped term in the pivot
+    ("L[..., i, :i] * z[..., :i]", "L[..., :i, i] * z[..., :i]"),  # transposed operand
+    ("np.conj(L[..., i + 1:, i]) * x[..., i + 1:]", "L[..., i + 1:, i] * x[..., i + 1:]"),
+    ('np.einsum("kbl,dkb->dkl", np.conj(H), Yd)', 'np.einsum("kbl,dkb->dkl", H, Yd)'),
+    ("return G + float(sigma2) * np.eye(n)", "return G + float(sigma2)"),
+]
+
+
+def test_pins_pass_on_the_oracle(golden):
+    assert _pins_pass(O, golden)
+
+
+@pytest.mark.parametrize("old,new", MUTATIONS)
+def test_planted_mistake_is_caught(old, new, golden):
+    assert not _pins_pass(_mutant(old, new), golden)
