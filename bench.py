@@ -1,0 +1,205 @@
+"""Throughput of the fused PUSCH receive chain on one MI355X.
+
+One step = one pusch_slot call over a batch of 16 synthetic slots of the
+paper-scale workload (64 receive antennas, 4096-point FFT with 3300 active
+subcarriers, 14 OFDM symbols with pilots on symbols 2 and 11, 32 DFT beams,
+16 UEs with 64-QAM, 8-tap 300 ns exponential-PDP channel, 20 dB SNR): FFT of
+every antenna and symbol, beamforming, LS channel estimation and MMSE
+detection.  Inputs sit in HBM before the timed region starts.
+
+Prints ONE JSON line with slots/s, us/slot (p50/p99 over steps), the per-stage
+device time measured with HIP events recorded by the library on the launch
+stream during the timed steps, the roofline of the dominant kernel and the
+serial FP64 CPU oracle timed on a bounded sample of the same slots.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+N_SLOT = 16
+SEEDS = list(range(2000, 2000 + N_SLOT))
+
+# Algorithmic bytes moved by each stage per slot of the workload (compulsory
+# inputs + outputs of that stage; complex64 = 8 B, status int32 = 4 B).
+S, R, N, K, B, L, NP = 14, 64, 4096, 3300, 32, 16, 2
+D = S - NP
+STAGE_BYTES = {
+    "fft": S * R * N * 8 + S * R * K * 8,
+    "beamform": S * R * K * 8 + B * R * 8 + S * K * B * 8,
+    "chest": NP * K * B * 8 + NP * K * 8 + K * L * B * 8,
+    "mmse": K * L * B * 8 + D * K * B * 8 + D * K * L * 8 + K * 4,
+}
+STAGE_KERNEL = {
+    "fft": "k_fft<4096>",
+    "beamform": "k_beamform<2>",
+    "chest": "k_chest",
+    "mmse": "k_mmse<16>",
+}
+STAGE_SOURCE = {"fft": "fft.hip", "beamform": "beamform.hip", "chest": "chest.hip", "mmse": "mmse.hip"}
+TRAFFIC_FILE = {"fft": "profiles/fft4096_paper_scale_traffic.md"}
+
+
+def _source_sha(stage: str) -> str:
+    path = os.path.join(ROOT, "paper_2210_09196_amd", "csrc", STAGE_SOURCE[stage])
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def _traffic(stage: str) -> float | None:
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; otherwise None."""
+    rel = TRAFFIC_FILE.get(stage)
+    if not rel or not os.path.exists(os.path.join(ROOT, rel)):
+        return None
+    vals = {}
+    for line in open(os.path.join(ROOT, rel)):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256_16") != _source_sha(stage):
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(batch: dict, seconds: float) -> dict:
+    """The FP64 oracle, serial (one BLAS thread), on as many of the slots as fit in `seconds`."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import pusch_oracle
+    from paper_2210_09196_amd import synth
+
+    cfg = synth.CFG2
+    done, t0 = 0, time.perf_counter()
+    with threadpool_limits(limits=1):
+        while done < N_SLOT:
+            pusch_oracle.receive_slot(batch["x_td"][done], batch["pilots"][done], cfg.pilot_symb, cfg.n_ue, cfg.n_sc,
+                                      batch["sigma2"], n_beams=cfg.n_beams)
+            done += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "slots/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} slot(s) of the same workload (seeds {SEEDS[0]}..{SEEDS[0] + done - 1}), "
+                      f"FP64 NumPy oracle, one thread, {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); slots are independent, so a "
+              f"multi-GPU run would split the slot batch with no communication -- see the design notes.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2210_09196_amd import pusch, synth
+
+    if not os.path.exists(pusch.LIB_PATH):
+        from paper_2210_09196_amd.build import build
+        build()
+    cfg = synth.CFG2
+    print(f"[bench] generating {N_SLOT} synthetic slots", file=sys.stderr, flush=True)
+    batch = synth.make_batch(cfg, SEEDS)
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(batch["x_td"]).to(dev)
+    p = torch.from_numpy(batch["pilots"]).to(dev)
+    slot = pusch.Slot(cfg.n_ant, cfg.n_fft, cfg.n_sc, cfg.n_symb, cfg.n_beams, cfg.n_ue, cfg.pilot_symb,
+                      batch["sigma2"], N_SLOT, device=dev)
+    x_hat = torch.empty(N_SLOT, cfg.n_data, cfg.n_sc, cfg.n_ue, dtype=torch.complex64, device=dev)
+    status = torch.empty(N_SLOT, cfg.n_sc, dtype=torch.int32, device=dev)
+
+    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        slot(x, p, x_hat, status)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    pusch.profile_begin(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(args.steps):
+        slot(x, p, x_hat, status)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    calls, stage_ms = pusch.profile_end()
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
+    total_ms = ev[0].elapsed_time(ev[-1])
+    ms_per_step = total_ms / args.steps
+    bad = int(status.sum().item())
+    print(f"[bench] {args.steps} steps in {total_ms:.2f} ms (wall {wall * 1e3:.1f} ms), status flags {bad}",
+          file=sys.stderr, flush=True)
+
+    us_slot = 1e3 * step_ms / N_SLOT
+    stages = {}
+    for name, ms in stage_ms.items():
+        per_launch_s = ms / 1e3 / calls
+        gbs = STAGE_BYTES[name] * N_SLOT / per_launch_s / 1e9
+        stages[name] = {"kernel": STAGE_KERNEL[name], "us_per_launch": round(per_launch_s * 1e6, 2),
+                        "us_per_slot": round(per_launch_s * 1e6 / N_SLOT, 3),
+                        "alg_bytes_per_launch": STAGE_BYTES[name] * N_SLOT, "achieved_GBs": round(gbs, 1),
+                        "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    dom = max(stages, key=lambda k: stages[k]["us_per_launch"])
+    traffic = _traffic(dom)
+    roofline = {"bound": "hbm", "achieved": stages[dom]["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": stages[dom]["hbm_frac"], "traffic": traffic, "kernel": stages[dom]["kernel"],
+                "alg_bytes_per_launch": stages[dom]["alg_bytes_per_launch"],
+                "us_per_launch": stages[dom]["us_per_launch"]}
+    chain_bytes = sum(STAGE_BYTES.values()) * N_SLOT
+    out = {
+        "metric": "PUSCH slots/s & us/slot, 64ant x 4096-FFT, FP32 chain",
+        "value": round(N_SLOT / (ms_per_step / 1e3), 1),
+        "unit": "slots/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "us_per_slot": round(1e3 * ms_per_step / N_SLOT, 3),
+        "us_per_slot_p50": round(float(np.percentile(us_slot, 50)), 3),
+        "us_per_slot_p99": round(float(np.percentile(us_slot, 99)), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "paper-scale PUSCH slot batch: 16 slots x (64 rx ant, 4096-FFT, 3300 active sc, "
+                               "14 symb, pilots 2+11, 32 DFT beams, 16 UEs 64-QAM, TDL-8 300 ns, 20 dB)",
+                   "n_slot": N_SLOT, "n_ant": 64, "n_fft": 4096, "n_sc": 3300, "n_symb": 14, "n_beams": 32,
+                   "n_ue": 16},
+        "chain_hbm_frac": round(chain_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "stages": stages,
+        "roofline": roofline,
+        "cpu_baseline": None,
+        "status_flags": bad,
+    }
+    if not args.no_cpu_baseline:
+        print(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

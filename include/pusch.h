@@ -1,0 +1,192 @@
+/*
+ * pusch.h -- C ABI of the MI355X (gfx950) PUSCH lower-PHY receive chain.
+ *
+ * The chain follows Sec. II of "Efficient Parallelization of 5G-PUSCH on a
+ * Scalable RISC-V Many-core Processor": OFDM demodulation (one FFT per antenna
+ * and OFDM symbol), beamforming (a matrix product with known coefficients),
+ * least-squares channel estimation on block-type pilot symbols, and the MIMO
+ * stage of Eq. 2, x = (H^H H + sigma^2 I)^{-1} H^H y, evaluated through a
+ * Cholesky decomposition of the Gram matrix and two triangular solves.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Numbers     complex values are interleaved FP32 pairs (pusch_c32, the same
+ *             bytes as torch.complex64); all arithmetic on the GPU is FP32.
+ * Pointers    every data pointer is a caller-owned DEVICE buffer on the
+ *             current HIP device.  The library never frees, retains or
+ *             reallocates one after the call returns.  Buffers must be 8-byte
+ *             aligned (16-byte alignment gives faster loads).
+ * Streams     `stream` is a hipStream_t passed as void* (NULL = the legacy
+ *             default stream).  Calls only enqueue work and return; outputs
+ *             and status arrays are valid once the stream has been
+ *             synchronised.  No call synchronises the device or allocates in
+ *             steady state.  The first call on a device builds small
+ *             immutable tables (FFT twiddles, DFT beamformers) once.
+ * Errors      arguments are checked on the host before any device work; a
+ *             rejected call returns a negative code and enqueues nothing.
+ *             Launch failures return PUSCH_EHIP.  Numerical failure of one
+ *             subcarrier (non-positive Cholesky pivot) is reported in the
+ *             per-subcarrier status array, not in the return code.
+ * Layouts     row-major; the innermost index is listed last.  "RE-major"
+ *             beam-domain grids store, for every resource element (RE), its
+ *             N_B beam values contiguously -- the per-subcarrier vector y of
+ *             Eq. 1.
+ * Subcarriers active subcarrier k (0 <= k < n_sc) sits on FFT bin
+ *             (k - n_sc/2) mod n_fft (centred band, DC used, integer halving).
+ * Pilots      block-type pilot symbols (whole OFDM symbols).  The n_ue UEs
+ *             share each pilot symbol as a frequency comb: on pilot symbol j
+ *             (0-based among the pilot symbols) subcarrier k carries the pilot
+ *             of UE (k + j * (n_ue / n_pilot)) mod n_ue.  Pilot values must be
+ *             non-zero.
+ */
+#ifndef PUSCH_H_
+#define PUSCH_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  float re, im;
+} pusch_c32;
+
+enum {
+  PUSCH_OK = 0,
+  PUSCH_EINVAL = -1,       /* bad argument (null pointer, size out of range, overlap) */
+  PUSCH_EUNSUPPORTED = -2, /* valid request outside what this build implements */
+  PUSCH_EHIP = -3,         /* HIP runtime / launch failure */
+  PUSCH_ENOMEM = -4        /* workspace too small, or device table allocation failed */
+};
+
+/* Limits of this build. */
+#define PUSCH_MAX_BEAMS 64
+#define PUSCH_MAX_UES 32
+#define PUSCH_MAX_PILOTS 4
+#define PUSCH_MAX_SYMBOLS 16
+
+/* Human-readable text for a return code (static storage). */
+const char* pusch_strerror(int code);
+
+/* Build the per-device immutable tables for the current device now instead
+ * of on first use.  Returns PUSCH_OK or PUSCH_EHIP. */
+int pusch_init(void);
+
+/*
+ * OFDM demodulation (Sec. II; Table 1, row "OFDM dem.").
+ * For each of `batch` time-domain vectors x_i of n_fft samples computes the
+ * unscaled forward DFT X_i[f] = sum_n x_i[n] exp(-2 pi i f n / n_fft).
+ *   n_fft  in {64, 256, 1024, 2048, 4096}, else PUSCH_EUNSUPPORTED.
+ *   n_sc   0: write all n_fft bins in natural order, X is [batch][n_fft];
+ *          1..n_fft: write only the n_sc active subcarriers in subcarrier
+ *          order (bin (k - n_sc/2) mod n_fft), X is [batch][n_sc].
+ *   x      [batch][n_fft].  x == X is allowed when n_sc is 0 or n_fft; any
+ *          other overlap of x and X is PUSCH_EINVAL.
+ *   batch  >= 0 (0 is a no-op).
+ */
+int pusch_fft(const pusch_c32* x, pusch_c32* X, int n_fft, int n_sc, long long batch, void* stream);
+
+/*
+ * Beamforming (Sec. II; Table 1, row "BF"): for every batch item i and RE n,
+ *   Y_i[n][b] = sum_a W[b][a] X_i[a][n],   b < n_beams, a < n_ant, n < n_re.
+ *   W      [n_beams][n_ant] known coefficients, or NULL for the built-in
+ *          beamformer W[b][a] = exp(-2 pi i b a / n_ant) / sqrt(n_ant) (rows
+ *          of the unitary DFT; requires n_beams <= n_ant).
+ *   X      [batch][n_ant][ld_x] antenna-domain grid (antenna-major, as
+ *          pusch_fft writes it), ld_x >= n_re.
+ *   Y      [batch][n_re][n_beams] RE-major beam-domain grid.  Must not
+ *          overlap X or W.
+ *   1 <= n_beams <= PUSCH_MAX_BEAMS, 1 <= n_ant <= 1024, n_re >= 0, batch >= 0.
+ */
+int pusch_beamform(const pusch_c32* W, const pusch_c32* X, pusch_c32* Y, int n_beams, int n_ant, int n_re,
+                   long long ld_x, long long batch, void* stream);
+
+/*
+ * Least-squares channel estimation (Sec. II, CHE; Table 1, row "CHE").
+ * On pilot symbol j, subcarrier k (owned by UE l, see "Pilots") the LS value
+ * of UE l's beam-domain channel is Yp_j[k][:] * conj(p_j[k]) / |p_j[k]|^2.
+ * Per UE the values of all pilot symbols are merged by subcarrier (averaged
+ * where two pilot symbols hit the same subcarrier) and interpolated linearly
+ * along k, holding the first / last value beyond the outermost pilots.
+ *   Yp     [batch][n_pilot][n_sc][n_beams] RE-major beam-domain pilot symbols.
+ *   pilots [batch][n_pilot][n_sc] pilot value on each pilot RE (non-zero).
+ *   H      [batch][n_sc][n_ue][n_beams]: per subcarrier, row l is UE l's
+ *          channel across the beams (column l of H in Eq. 1).
+ *   1 <= n_pilot <= PUSCH_MAX_PILOTS, 1 <= n_ue <= min(PUSCH_MAX_UES, n_beams),
+ *   n_ue <= n_sc, 1 <= n_beams <= PUSCH_MAX_BEAMS, batch >= 0.
+ */
+int pusch_chest(const pusch_c32* Yp, const pusch_c32* pilots, pusch_c32* H, int n_beams, int n_ue, int n_sc,
+                int n_pilot, long long batch, void* stream);
+
+/*
+ * MMSE MIMO detection (Eq. 2) per subcarrier: G = H^H H + sigma2 I, the
+ * Cholesky factor G = L L^H (Crout order, Sec. V-C), then for every data
+ * symbol the matched filter b = H^H y, forward substitution L z = b and back
+ * substitution L^H x = z.  One factorisation per subcarrier serves all data
+ * symbols of the call.
+ *   H      [batch][n_sc][n_ue][n_beams] as written by pusch_chest.
+ *   Yd     [batch][n_data][n_sc][n_beams] RE-major data symbols.
+ *   Xhat   [batch][n_data][n_sc][n_ue] detected symbols (0 where status = 1).
+ *   status [batch][n_sc] int32 or NULL: 0 ok, 1 when a Cholesky pivot is not
+ *          positive and finite.
+ *   sigma2 >= 0 and finite.  1 <= n_ue <= min(PUSCH_MAX_UES, n_beams),
+ *   1 <= n_beams <= PUSCH_MAX_BEAMS, n_sc >= 0, n_data >= 1, batch >= 0.
+ */
+int pusch_mmse_solve(const pusch_c32* H, const pusch_c32* Yd, float sigma2, pusch_c32* Xhat, int n_beams,
+                     int n_ue, int n_sc, int n_data, long long batch, int32_t* status, void* stream);
+
+/* One slot's geometry for pusch_slot (Sec. II use-case parameters). */
+typedef struct {
+  int n_ant;                        /* N_R receive antennas, 1..1024 */
+  int n_fft;                        /* FFT size, as pusch_fft */
+  int n_sc;                         /* active subcarriers, n_ue..n_fft */
+  int n_symb;                       /* OFDM symbols per slot, 2..PUSCH_MAX_SYMBOLS */
+  int n_beams;                      /* N_B, 1..PUSCH_MAX_BEAMS */
+  int n_ue;                         /* N_L, 1..min(PUSCH_MAX_UES, n_beams) */
+  int n_pilot;                      /* pilot symbols, 1..min(PUSCH_MAX_PILOTS, n_symb - 1) */
+  int pilot_symb[PUSCH_MAX_PILOTS]; /* 0-based pilot symbol indices, strictly ascending */
+  float sigma2;                     /* noise variance per RE after beamforming, >= 0 */
+  const pusch_c32* W;               /* device [n_beams][n_ant], or NULL = built-in DFT rows */
+  const pusch_c32* pilots;          /* device [n_slot][n_pilot][n_sc] */
+} pusch_slot_desc;
+
+/* Bytes of device workspace pusch_slot needs for n_slot slots (0 on bad input). */
+size_t pusch_slot_workspace_bytes(const pusch_slot_desc* d, long long n_slot);
+/* (Depends on the geometry fields only; W, pilots and sigma2 are not read.) */
+
+/*
+ * The fused receive chain (Sec. II, Fig. "PUSCH processing chain") for n_slot
+ * independent slots, enqueued on one stream: OFDM demodulation of every
+ * antenna and symbol to the n_sc active subcarriers, beamforming, LS channel
+ * estimation on the pilot symbols, MMSE detection of every other ("data")
+ * symbol in ascending symbol order.
+ *   x_td   [n_slot][n_symb][n_ant][n_fft] time-domain samples.
+ *   x_hat  [n_slot][n_data][n_sc][n_ue], n_data = n_symb - n_pilot.
+ *   status [n_slot][n_sc] int32 or NULL, as pusch_mmse_solve.
+ *   ws     device workspace of at least pusch_slot_workspace_bytes(d, n_slot)
+ *          bytes, 256-byte aligned, not overlapping any other argument.
+ */
+int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td, pusch_c32* x_hat, int32_t* status,
+               void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Stage timing for measurement.  pusch_profile_begin(max_calls) creates
+ * HIP events (allocation happens here, not in pusch_slot); while active, each
+ * pusch_slot call records an event before and after each of its
+ * PUSCH_SLOT_STAGES launches on its stream, for up to max_calls calls.
+ * pusch_profile_end(stage_ms, n) synchronises on the last event, writes the
+ * summed device time of each stage (ms; order: fft, beamform, chest, mmse)
+ * into stage_ms[0..n-1], releases the events and returns the number of calls
+ * recorded (or a negative code).
+ */
+#define PUSCH_SLOT_STAGES 4
+int pusch_profile_begin(int max_calls);
+int pusch_profile_end(float* stage_ms, int n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PUSCH_H_ */

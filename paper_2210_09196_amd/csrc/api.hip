@@ -1,0 +1,404 @@
+// C-ABI entry points of the PUSCH receive chain (declared in include/pusch.h):
+// host-side argument validation, per-device immutable tables, workspace
+// layout and the launch sequence of the fused slot.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "kernels.h"
+#include "pusch.h"
+
+using pusch::cf;
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+constexpr long long kMaxAnt = 1024;
+
+struct DeviceTables {
+  std::once_flag once;
+  int status = PUSCH_EHIP;
+  cf* twiddles = nullptr;
+  int n_cu = 1;
+  std::mutex mu;
+  std::map<std::pair<int, int>, cf*> dft_w;  // (n_beams, n_ant) -> device table
+};
+DeviceTables g_dev[kMaxDevices];
+
+int device_tables(DeviceTables** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PUSCH_EHIP;
+  DeviceTables& t = g_dev[dev];
+  std::call_once(t.once, [&t, dev]() {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0) return;
+    const pusch::TwiddleLayout lay = pusch::fft_twiddle_layout();
+    std::vector<cf> host(lay.total);
+    pusch::fft_fill_twiddles(host.data());
+    void* d = nullptr;
+    if (hipMalloc(&d, host.size() * sizeof(cf)) != hipSuccess) {
+      t.status = PUSCH_ENOMEM;
+      return;
+    }
+    if (hipMemcpy(d, host.data(), host.size() * sizeof(cf), hipMemcpyHostToDevice) != hipSuccess) return;
+    t.twiddles = static_cast<cf*>(d);
+    t.n_cu = ncu;
+    t.status = PUSCH_OK;
+  });
+  *out = &t;
+  return t.status;
+}
+
+// Built-in beamformer: rows 0..n_beams-1 of the unitary n_ant-point DFT,
+// computed in FP64 on the host and rounded once to FP32.
+int dft_beamformer(DeviceTables* t, int n_beams, int n_ant, const cf** out) {
+  std::lock_guard<std::mutex> lock(t->mu);
+  auto key = std::make_pair(n_beams, n_ant);
+  auto it = t->dft_w.find(key);
+  if (it != t->dft_w.end()) {
+    *out = it->second;
+    return PUSCH_OK;
+  }
+  std::vector<cf> host((size_t)n_beams * n_ant);
+  const double two_pi = 6.283185307179586476925286766559;
+  const double scale = 1.0 / std::sqrt((double)n_ant);
+  for (int b = 0; b < n_beams; ++b)
+    for (int a = 0; a < n_ant; ++a) {
+      const double ang = -two_pi * (double)(((long)b * a) % n_ant) / (double)n_ant;
+      host[(size_t)b * n_ant + a] = cf{(float)(std::cos(ang) * scale), (float)(std::sin(ang) * scale)};
+    }
+  void* d = nullptr;
+  if (hipMalloc(&d, host.size() * sizeof(cf)) != hipSuccess) return PUSCH_ENOMEM;
+  if (hipMemcpy(d, host.data(), host.size() * sizeof(cf), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    return PUSCH_EHIP;
+  }
+  t->dft_w[key] = static_cast<cf*>(d);
+  *out = static_cast<cf*>(d);
+  return PUSCH_OK;
+}
+
+bool overlap(const void* a, long long abytes, const void* b, long long bbytes) {
+  if (!a || !b || abytes <= 0 || bbytes <= 0) return false;
+  const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+  return pa < pb + (uintptr_t)bbytes && pb < pa + (uintptr_t)abytes;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? PUSCH_OK : PUSCH_EHIP; }
+
+// ---------------------------------------------------------------- stage timing
+struct Profile {
+  std::mutex mu;
+  bool active = false;
+  int max_calls = 0;
+  int calls = 0;
+  std::vector<hipEvent_t> ev;  // (PUSCH_SLOT_STAGES + 1) per call
+} g_prof;
+
+constexpr int kEvPerCall = PUSCH_SLOT_STAGES + 1;
+
+}  // namespace
+
+extern "C" {
+
+const char* pusch_strerror(int code) {
+  switch (code) {
+    case PUSCH_OK: return "success";
+    case PUSCH_EINVAL: return "invalid argument";
+    case PUSCH_EUNSUPPORTED: return "unsupported size or configuration";
+    case PUSCH_EHIP: return "HIP runtime or launch failure";
+    case PUSCH_ENOMEM: return "workspace too small or device allocation failed";
+    default: return "unknown error code";
+  }
+}
+
+int pusch_init(void) {
+  DeviceTables* t = nullptr;
+  return device_tables(&t);
+}
+
+int pusch_fft(const pusch_c32* x, pusch_c32* X, int n_fft, int n_sc, long long batch, void* stream) {
+  if (!x || !X || batch < 0) return PUSCH_EINVAL;
+  if (pusch::fft_size_index(n_fft) < 0) return PUSCH_EUNSUPPORTED;
+  if (n_sc < 0 || n_sc > n_fft) return PUSCH_EINVAL;
+  const int out_len = n_sc == 0 ? n_fft : n_sc;
+  const int shift = n_sc == 0 ? 0 : n_sc / 2;
+  if ((const void*)x == (const void*)X) {
+    if (out_len != n_fft) return PUSCH_EINVAL;
+  } else if (overlap(x, batch * n_fft * 8LL, X, batch * out_len * 8LL)) {
+    return PUSCH_EINVAL;
+  }
+  if (batch == 0) return PUSCH_OK;
+  DeviceTables* t = nullptr;
+  if (int rc = device_tables(&t)) return rc;
+  return hip_status(pusch::launch_fft(reinterpret_cast<const cf*>(x), reinterpret_cast<cf*>(X), n_fft, batch, out_len,
+                                      shift, t->twiddles, t->n_cu, static_cast<hipStream_t>(stream)));
+}
+
+int pusch_beamform(const pusch_c32* W, const pusch_c32* X, pusch_c32* Y, int n_beams, int n_ant, int n_re,
+                   long long ld_x, long long batch, void* stream) {
+  if (!X || !Y || batch < 0 || n_re < 0) return PUSCH_EINVAL;
+  if (n_beams < 1 || n_beams > PUSCH_MAX_BEAMS || n_ant < 1 || n_ant > kMaxAnt) return PUSCH_EINVAL;
+  if (ld_x < n_re || ld_x < 1) return PUSCH_EINVAL;
+  if (!W && n_beams > n_ant) return PUSCH_EINVAL;
+  const long long xbytes = batch * n_ant * ld_x * 8LL, ybytes = batch * (long long)n_re * n_beams * 8LL;
+  if (overlap(X, xbytes, Y, ybytes) || overlap(W, (long long)n_beams * n_ant * 8, Y, ybytes)) return PUSCH_EINVAL;
+  if (batch == 0 || n_re == 0) return PUSCH_OK;
+  DeviceTables* t = nullptr;
+  if (int rc = device_tables(&t)) return rc;
+  const cf* w = reinterpret_cast<const cf*>(W);
+  if (!w)
+    if (int rc = dft_beamformer(t, n_beams, n_ant, &w)) return rc;
+  return hip_status(pusch::launch_beamform(w, reinterpret_cast<const cf*>(X), reinterpret_cast<cf*>(Y), n_beams, n_ant,
+                                           n_re, ld_x, (long long)n_ant * ld_x, (long long)n_re * n_beams, batch,
+                                           t->n_cu, static_cast<hipStream_t>(stream)));
+}
+
+int pusch_chest(const pusch_c32* Yp, const pusch_c32* pilots, pusch_c32* H, int n_beams, int n_ue, int n_sc,
+                int n_pilot, long long batch, void* stream) {
+  if (!Yp || !pilots || !H || batch < 0) return PUSCH_EINVAL;
+  if (n_pilot < 1 || n_pilot > PUSCH_MAX_PILOTS) return PUSCH_EINVAL;
+  if (n_beams < 1 || n_beams > PUSCH_MAX_BEAMS) return PUSCH_EINVAL;
+  if (n_ue < 1 || n_ue > PUSCH_MAX_UES || n_ue > n_beams || n_sc < n_ue) return PUSCH_EINVAL;
+  const long long hb = batch * n_sc * (long long)n_ue * n_beams * 8;
+  if (overlap(Yp, batch * n_pilot * (long long)n_sc * n_beams * 8, H, hb) ||
+      overlap(pilots, batch * n_pilot * (long long)n_sc * 8, H, hb))
+    return PUSCH_EINVAL;
+  if (batch == 0) return PUSCH_OK;
+  pusch::ChestGeom g{};
+  g.n_beams = n_beams;
+  g.n_ue = n_ue;
+  g.n_sc = n_sc;
+  g.n_pilot = n_pilot;
+  g.y_batch = (long long)n_pilot * n_sc * n_beams;
+  for (int j = 0; j < n_pilot; ++j) g.y_pilot[j] = (long long)j * n_sc * n_beams;
+  g.p_batch = (long long)n_pilot * n_sc;
+  g.h_batch = (long long)n_sc * n_ue * n_beams;
+  return hip_status(pusch::launch_chest(reinterpret_cast<const cf*>(Yp), reinterpret_cast<const cf*>(pilots),
+                                        reinterpret_cast<cf*>(H), g, batch, static_cast<hipStream_t>(stream)));
+}
+
+int pusch_mmse_solve(const pusch_c32* H, const pusch_c32* Yd, float sigma2, pusch_c32* Xhat, int n_beams, int n_ue,
+                     int n_sc, int n_data, long long batch, int32_t* status, void* stream) {
+  if (!H || !Yd || !Xhat || batch < 0 || n_sc < 0 || n_data < 1) return PUSCH_EINVAL;
+  if (!(sigma2 >= 0.f) || !std::isfinite(sigma2)) return PUSCH_EINVAL;
+  if (n_beams < 1 || n_beams > PUSCH_MAX_BEAMS) return PUSCH_EINVAL;
+  if (n_ue < 1 || n_ue > PUSCH_MAX_UES || n_ue > n_beams) return PUSCH_EINVAL;
+  const long long xb = batch * n_data * (long long)n_sc * n_ue * 8;
+  const long long hb = batch * (long long)n_sc * n_ue * n_beams * 8;
+  const long long yb = batch * n_data * (long long)n_sc * n_beams * 8;
+  const long long sb = batch * (long long)n_sc * 4;
+  if (overlap(Xhat, xb, H, hb) || overlap(Xhat, xb, Yd, yb) || overlap(Xhat, xb, status, sb) ||
+      overlap(status, sb, H, hb) || overlap(status, sb, Yd, yb))
+    return PUSCH_EINVAL;
+  if (batch == 0 || n_sc == 0) return PUSCH_OK;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int d0 = 0; d0 < n_data; d0 += pusch::kMaxSymbols) {
+    const int nd = n_data - d0 < pusch::kMaxSymbols ? n_data - d0 : pusch::kMaxSymbols;
+    pusch::MmseGeom g{};
+    g.n_beams = n_beams;
+    g.n_ue = n_ue;
+    g.n_sc = n_sc;
+    g.n_data = nd;
+    g.sigma2 = sigma2;
+    g.h_batch = (long long)n_sc * n_ue * n_beams;
+    g.y_batch = (long long)n_data * n_sc * n_beams;
+    for (int d = 0; d < nd; ++d) g.y_sym[d] = (long long)(d0 + d) * n_sc * n_beams;
+    g.x_batch = (long long)n_data * n_sc * n_ue;
+    g.st_batch = n_sc;
+    const hipError_t e =
+        pusch::launch_mmse(reinterpret_cast<const cf*>(H), reinterpret_cast<const cf*>(Yd),
+                           reinterpret_cast<cf*>(Xhat) + (long long)d0 * n_sc * n_ue, status, g, batch, s);
+    if (e != hipSuccess) return PUSCH_EHIP;
+  }
+  return PUSCH_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct SlotLayout {
+  size_t off_xa, off_y, off_h, total;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Geometry only (what the workspace size depends on).
+int check_geom(const pusch_slot_desc* d) {
+  if (!d) return PUSCH_EINVAL;
+  if (pusch::fft_size_index(d->n_fft) < 0) return PUSCH_EUNSUPPORTED;
+  if (d->n_ant < 1 || d->n_ant > kMaxAnt) return PUSCH_EINVAL;
+  if (d->n_beams < 1 || d->n_beams > PUSCH_MAX_BEAMS) return PUSCH_EINVAL;
+  if (d->n_ue < 1 || d->n_ue > PUSCH_MAX_UES || d->n_ue > d->n_beams) return PUSCH_EINVAL;
+  if (d->n_sc < d->n_ue || d->n_sc > d->n_fft) return PUSCH_EINVAL;
+  if (d->n_symb < 2 || d->n_symb > PUSCH_MAX_SYMBOLS) return PUSCH_EINVAL;
+  if (d->n_pilot < 1 || d->n_pilot > PUSCH_MAX_PILOTS || d->n_pilot >= d->n_symb) return PUSCH_EINVAL;
+  for (int j = 0; j < d->n_pilot; ++j) {
+    if (d->pilot_symb[j] < 0 || d->pilot_symb[j] >= d->n_symb) return PUSCH_EINVAL;
+    if (j > 0 && d->pilot_symb[j] <= d->pilot_symb[j - 1]) return PUSCH_EINVAL;
+  }
+  if (!d->W && d->n_beams > d->n_ant) return PUSCH_EINVAL;
+  return PUSCH_OK;
+}
+
+int check_desc(const pusch_slot_desc* d) {
+  if (int rc = check_geom(d)) return rc;
+  if (!(d->sigma2 >= 0.f) || !std::isfinite(d->sigma2)) return PUSCH_EINVAL;
+  if (!d->pilots) return PUSCH_EINVAL;
+  return PUSCH_OK;
+}
+
+SlotLayout slot_layout(const pusch_slot_desc* d, long long n_slot) {
+  const size_t S = d->n_symb, R = d->n_ant, K = d->n_sc, B = d->n_beams, L = d->n_ue, n = (size_t)n_slot;
+  SlotLayout lay;
+  lay.off_xa = 0;
+  lay.off_y = align256(n * S * R * K * 8);
+  lay.off_h = lay.off_y + align256(n * S * K * B * 8);
+  lay.total = lay.off_h + align256(n * K * L * B * 8);
+  return lay;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pusch_slot_workspace_bytes(const pusch_slot_desc* d, long long n_slot) {
+  if (check_geom(d) != PUSCH_OK || n_slot < 0) return 0;
+  return slot_layout(d, n_slot).total;
+}
+
+int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td, pusch_c32* x_hat, int32_t* status,
+               void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_desc(d)) return rc;
+  if (n_slot < 0 || !x_td || !x_hat || !ws) return PUSCH_EINVAL;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return PUSCH_EINVAL;
+  const SlotLayout lay = slot_layout(d, n_slot);
+  if (ws_bytes < lay.total) return PUSCH_ENOMEM;
+  const int S = d->n_symb, R = d->n_ant, K = d->n_sc, B = d->n_beams, L = d->n_ue, P = d->n_pilot;
+  const int D = S - P;
+  const long long xb = n_slot * (long long)S * R * d->n_fft * 8, ob = n_slot * (long long)D * K * L * 8,
+                  sb = n_slot * (long long)K * 4, wb = (long long)lay.total;
+  if (overlap(x_hat, ob, x_td, xb) || overlap(x_hat, ob, ws, wb) || overlap(x_hat, ob, status, sb) ||
+      overlap(ws, wb, x_td, xb) || overlap(status, sb, x_td, xb) || overlap(status, sb, ws, wb) ||
+      overlap(ws, wb, d->pilots, n_slot * (long long)P * K * 8) || overlap(ws, wb, d->W, (long long)B * R * 8))
+    return PUSCH_EINVAL;
+  if (n_slot == 0) return PUSCH_OK;
+
+  DeviceTables* t = nullptr;
+  if (int rc = device_tables(&t)) return rc;
+  const cf* w = reinterpret_cast<const cf*>(d->W);
+  if (!w)
+    if (int rc = dft_beamformer(t, B, R, &w)) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+
+  char* base = static_cast<char*>(ws);
+  cf* Xa = reinterpret_cast<cf*>(base + lay.off_xa);
+  cf* Y = reinterpret_cast<cf*>(base + lay.off_y);
+  cf* H = reinterpret_cast<cf*>(base + lay.off_h);
+
+  hipEvent_t* ev = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    if (g_prof.active && g_prof.calls < g_prof.max_calls) ev = &g_prof.ev[(size_t)g_prof.calls++ * kEvPerCall];
+  }
+  auto mark = [&](int i) -> bool { return !ev || hipEventRecord(ev[i], s) == hipSuccess; };
+
+  // a1: OFDM demodulation of every antenna and symbol, active bins only
+  if (!mark(0)) return PUSCH_EHIP;
+  if (pusch::launch_fft(reinterpret_cast<const cf*>(x_td), Xa, d->n_fft, n_slot * S * R, K, K / 2, t->twiddles,
+                        t->n_cu, s) != hipSuccess)
+    return PUSCH_EHIP;
+  // a2: beamforming of every symbol, RE-major output
+  if (!mark(1)) return PUSCH_EHIP;
+  if (pusch::launch_beamform(w, Xa, Y, B, R, K, K, (long long)R * K, (long long)K * B, n_slot * S, t->n_cu, s) !=
+      hipSuccess)
+    return PUSCH_EHIP;
+  // a3: LS channel estimate from the pilot symbols
+  if (!mark(2)) return PUSCH_EHIP;
+  pusch::ChestGeom cg{};
+  cg.n_beams = B;
+  cg.n_ue = L;
+  cg.n_sc = K;
+  cg.n_pilot = P;
+  cg.y_batch = (long long)S * K * B;
+  for (int j = 0; j < P; ++j) cg.y_pilot[j] = (long long)d->pilot_symb[j] * K * B;
+  cg.p_batch = (long long)P * K;
+  cg.h_batch = (long long)K * L * B;
+  if (pusch::launch_chest(Y, reinterpret_cast<const cf*>(d->pilots), H, cg, n_slot, s) != hipSuccess)
+    return PUSCH_EHIP;
+  // a4-a6: Gram, Cholesky, matched filter and substitutions for the data symbols
+  if (!mark(3)) return PUSCH_EHIP;
+  pusch::MmseGeom mg{};
+  mg.n_beams = B;
+  mg.n_ue = L;
+  mg.n_sc = K;
+  mg.n_data = D;
+  mg.sigma2 = d->sigma2;
+  mg.h_batch = (long long)K * L * B;
+  mg.y_batch = (long long)S * K * B;
+  for (int s_ = 0, dd = 0, j = 0; s_ < S; ++s_) {
+    if (j < P && d->pilot_symb[j] == s_) {
+      ++j;
+      continue;
+    }
+    mg.y_sym[dd++] = (long long)s_ * K * B;
+  }
+  mg.x_batch = (long long)D * K * L;
+  mg.st_batch = K;
+  if (pusch::launch_mmse(H, Y, reinterpret_cast<cf*>(x_hat), status, mg, n_slot, s) != hipSuccess) return PUSCH_EHIP;
+  if (!mark(4)) return PUSCH_EHIP;
+  return PUSCH_OK;
+}
+
+int pusch_profile_begin(int max_calls) {
+  if (max_calls < 1 || max_calls > (1 << 20)) return PUSCH_EINVAL;
+  std::lock_guard<std::mutex> lock(g_prof.mu);
+  if (g_prof.active) return PUSCH_EINVAL;
+  g_prof.ev.assign((size_t)max_calls * kEvPerCall, nullptr);
+  for (auto& e : g_prof.ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (auto& f : g_prof.ev)
+        if (f) (void)hipEventDestroy(f);
+      g_prof.ev.clear();
+      return PUSCH_EHIP;
+    }
+  g_prof.max_calls = max_calls;
+  g_prof.calls = 0;
+  g_prof.active = true;
+  return PUSCH_OK;
+}
+
+int pusch_profile_end(float* stage_ms, int n) {
+  std::lock_guard<std::mutex> lock(g_prof.mu);
+  if (!g_prof.active) return PUSCH_EINVAL;
+  int rc = PUSCH_OK;
+  double sum[PUSCH_SLOT_STAGES] = {0, 0, 0, 0};
+  if (g_prof.calls > 0) {
+    if (hipEventSynchronize(g_prof.ev[(size_t)g_prof.calls * kEvPerCall - 1]) != hipSuccess) rc = PUSCH_EHIP;
+    for (int c = 0; c < g_prof.calls && rc == PUSCH_OK; ++c)
+      for (int st = 0; st < PUSCH_SLOT_STAGES; ++st) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, g_prof.ev[(size_t)c * kEvPerCall + st],
+                                g_prof.ev[(size_t)c * kEvPerCall + st + 1]) != hipSuccess) {
+          rc = PUSCH_EHIP;
+          break;
+        }
+        sum[st] += ms;
+      }
+  }
+  for (int st = 0; st < n && st < PUSCH_SLOT_STAGES; ++st)
+    if (stage_ms) stage_ms[st] = (float)sum[st];
+  for (auto& e : g_prof.ev) (void)hipEventDestroy(e);
+  g_prof.ev.clear();
+  g_prof.active = false;
+  const int calls = g_prof.calls;
+  g_prof.calls = 0;
+  return rc == PUSCH_OK ? calls : rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,290 @@
+// OFDM-demodulation FFT (Sec. II; Table 1, row "OFDM dem.") for gfx950.
+//
+// N = R0 * 16^P with R0 in {4, 8, 16}: one radix-R0 pass followed by P
+// radix-16 passes of the Stockham autosort formulation, so the result comes
+// out in natural order without a digit-reversal step.  The paper's kernel is
+// a radix-4 decimation-in-frequency FFT whose operands are folded into each
+// core's local banks (Sec. V-A); here each 16-point butterfly is done in a
+// thread's registers (a 4x4 split), and the data exchange between passes goes
+// through LDS with one padding slot per 16 elements, which keeps every
+// 8-byte LDS access of a wavefront conflict-free for all supported sizes.
+//
+// One workgroup of 256 threads owns 4096/N transforms at a time (N/16 threads
+// per transform, 16 values per thread) and loops over the batch, so each
+// thread loads its pass twiddles once, into registers.  Twiddles come from an
+// FP32 table computed in FP64 on the host.  The final pass writes straight
+// from registers to global memory, optionally keeping only the active
+// subcarriers (fused gather).
+#include <cmath>
+#include <vector>
+
+#include "kernels.h"
+
+namespace pusch {
+namespace {
+
+__device__ __forceinline__ cf cadd(cf a, cf b) { return {a.r + b.r, a.i + b.i}; }
+__device__ __forceinline__ cf csub(cf a, cf b) { return {a.r - b.r, a.i - b.i}; }
+__device__ __forceinline__ cf cmul(cf a, cf b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ cf mul_mi(cf a) { return {a.i, -a.r}; }  // * (-i)
+
+// exp(-2 pi i m / 16) for the factors that occur inside a 16-point DFT.
+constexpr float kC1 = 0.92387953251128675613f;  // cos(pi/8)
+constexpr float kS1 = 0.38268343236508977173f;  // sin(pi/8)
+constexpr float kR2 = 0.70710678118654752440f;  // sqrt(2)/2
+
+__device__ __forceinline__ cf w16_1(cf a) { return {kC1 * a.r + kS1 * a.i, kC1 * a.i - kS1 * a.r}; }
+__device__ __forceinline__ cf w16_2(cf a) { return {kR2 * (a.r + a.i), kR2 * (a.i - a.r)}; }
+__device__ __forceinline__ cf w16_3(cf a) { return {kS1 * a.r + kC1 * a.i, kS1 * a.i - kC1 * a.r}; }
+__device__ __forceinline__ cf w16_6(cf a) { return {kR2 * (a.i - a.r), -kR2 * (a.r + a.i)}; }
+__device__ __forceinline__ cf w16_9(cf a) { return {-kC1 * a.r - kS1 * a.i, kS1 * a.r - kC1 * a.i}; }
+
+// 4-point DFT of v[0], v[S], v[2S], v[3S], in place, natural order.
+template <int S>
+__device__ __forceinline__ void dft4s(cf* v) {
+  const cf a = v[0], b = v[S], c = v[2 * S], d = v[3 * S];
+  const cf t0 = cadd(a, c), t1 = csub(a, c), t2 = cadd(b, d), t3 = mul_mi(csub(b, d));
+  v[0] = cadd(t0, t2);
+  v[2 * S] = csub(t0, t2);
+  v[S] = cadd(t1, t3);
+  v[3 * S] = csub(t1, t3);
+}
+
+template <int R>
+__device__ __forceinline__ void dft(cf* v);
+
+template <>
+__device__ __forceinline__ void dft<4>(cf* v) {
+  dft4s<1>(v);
+}
+
+// 8 = 4 x 2: q = 2 q1 + q2, k = k1 + 4 k2.
+template <>
+__device__ __forceinline__ void dft<8>(cf* v) {
+  dft4s<2>(v);
+  dft4s<2>(v + 1);
+  v[3] = w16_2(v[3]);   // w8^1
+  v[5] = mul_mi(v[5]);  // w8^2
+  v[7] = w16_6(v[7]);   // w8^3
+  cf o[8];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    o[k1] = cadd(v[2 * k1], v[2 * k1 + 1]);
+    o[k1 + 4] = csub(v[2 * k1], v[2 * k1 + 1]);
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = o[i];
+}
+
+// 16 = 4 x 4: q = 4 q1 + q2, k = k1 + 4 k2.
+template <>
+__device__ __forceinline__ void dft<16>(cf* v) {
+  dft4s<4>(v);
+  dft4s<4>(v + 1);
+  dft4s<4>(v + 2);
+  dft4s<4>(v + 3);
+  // position q2 + 4 k1 holds the inner DFT value; scale by w16^(k1 q2)
+  v[5] = w16_1(v[5]);
+  v[6] = w16_2(v[6]);
+  v[7] = w16_3(v[7]);
+  v[9] = w16_2(v[9]);
+  v[10] = mul_mi(v[10]);
+  v[11] = w16_6(v[11]);
+  v[13] = w16_3(v[13]);
+  v[14] = w16_6(v[14]);
+  v[15] = w16_9(v[15]);
+  dft4s<1>(v);
+  dft4s<1>(v + 4);
+  dft4s<1>(v + 8);
+  dft4s<1>(v + 12);
+  cf o[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = o[i];
+}
+
+template <int N>
+struct Shape;
+template <>
+struct Shape<64> {
+  static constexpr int R0 = 4, P = 1;
+};
+template <>
+struct Shape<256> {
+  static constexpr int R0 = 16, P = 1;
+};
+template <>
+struct Shape<1024> {
+  static constexpr int R0 = 4, P = 2;
+};
+template <>
+struct Shape<2048> {
+  static constexpr int R0 = 8, P = 2;
+};
+template <>
+struct Shape<4096> {
+  static constexpr int R0 = 16, P = 2;
+};
+
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
+
+constexpr int kThreads = 256;
+
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_fft(const cf* __restrict__ x, cf* __restrict__ X,
+                                                  const cf* __restrict__ tw, long long batch, int out_len,
+                                                  int shift) {
+  constexpr int T = N / 16;         // threads per transform
+  constexpr int FPB = kThreads / T;  // transforms per workgroup
+  constexpr int R0 = Shape<N>::R0;
+  constexpr int P = Shape<N>::P;
+  constexpr int LSTR = lds_pad(N);
+  __shared__ cf lds[FPB * LSTR];
+
+  const int fl = threadIdx.x / T;
+  const int t = threadIdx.x % T;
+  cf* L = lds + fl * LSTR;
+
+  // Pass p (1..P) has stride Ns = R0 * 16^(p-1); this thread's twiddles are
+  // exp(-2 pi i (t mod Ns) r / (16 Ns)), r = 1..15, table block [(r-1)*Ns + k].
+  cf w[P][15];
+  {
+    int off = 0, ns = R0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int k = t % ns;
+#pragma unroll
+      for (int r = 1; r < 16; ++r) w[p][r - 1] = tw[off + (r - 1) * ns + k];
+      off += 15 * ns;
+      ns *= 16;
+    }
+  }
+
+  for (long long f0 = (long long)blockIdx.x * FPB; f0 < batch; f0 += (long long)gridDim.x * FPB) {
+    const long long fft = f0 + fl;
+    const bool act = fft < batch;
+    cf v[16];
+    if (act) {
+      const cf* src = x + fft * N;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) v[m] = src[t + m * T];
+    } else {
+#pragma unroll
+      for (int m = 0; m < 16; ++m) v[m] = cf{0.f, 0.f};
+    }
+
+    // Pass 0: radix R0, Ns = 1 (no twiddles).  Butterfly j = t + u*T reads
+    // x[j + r*N/R0] = v[u + r*16/R0] and writes element j*R0 + r.
+#pragma unroll
+    for (int u = 0; u < 16 / R0; ++u) {
+      cf b[R0];
+#pragma unroll
+      for (int r = 0; r < R0; ++r) b[r] = v[u + r * (16 / R0)];
+      dft<R0>(b);
+      const int j = t + u * T;
+#pragma unroll
+      for (int r = 0; r < R0; ++r) L[lds_pad(j * R0 + r)] = b[r];
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int ns = R0 << (4 * p);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = L[lds_pad(t + r * T)];
+      __syncthreads();
+#pragma unroll
+      for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w[p][r - 1]);
+      dft<16>(v);
+      if (p < P - 1) {
+        const int base = (t / ns) * 16 * ns + (t % ns);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) L[lds_pad(base + r * ns)] = v[r];
+        __syncthreads();
+      } else if (act) {
+        // last pass: Ns = N/16 = T, so bin f = t + r*T
+        cf* dst = X + fft * out_len;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          int k = t + r * T + shift;
+          if (k >= N) k -= N;
+          if (k < out_len) dst[k] = v[r];
+        }
+      }
+    }
+  }
+}
+
+constexpr int kSizes[5] = {64, 256, 1024, 2048, 4096};
+constexpr int kR0[5] = {4, 16, 4, 8, 16};
+constexpr int kP[5] = {1, 1, 2, 2, 2};
+
+}  // namespace
+
+int fft_size_index(int n_fft) {
+  for (int i = 0; i < 5; ++i)
+    if (kSizes[i] == n_fft) return i;
+  return -1;
+}
+
+TwiddleLayout fft_twiddle_layout() {
+  TwiddleLayout t{};
+  int off = 0;
+  for (int s = 0; s < 5; ++s) {
+    t.offset[s] = off;
+    int ns = kR0[s];
+    for (int p = 0; p < kP[s]; ++p) {
+      off += 15 * ns;
+      ns *= 16;
+    }
+  }
+  t.total = off;
+  return t;
+}
+
+void fft_fill_twiddles(cf* host) {
+  const TwiddleLayout lay = fft_twiddle_layout();
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int s = 0; s < 5; ++s) {
+    int off = lay.offset[s];
+    int ns = kR0[s];
+    for (int p = 0; p < kP[s]; ++p) {
+      const long m = 16L * ns;
+      for (int r = 1; r < 16; ++r)
+        for (int k = 0; k < ns; ++k) {
+          const long e = ((long)k * r) % m;
+          const double ang = -two_pi * (double)e / (double)m;
+          host[off + (r - 1) * ns + k] = cf{(float)std::cos(ang), (float)std::sin(ang)};
+        }
+      off += 15 * ns;
+      ns *= 16;
+    }
+  }
+}
+
+hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_len, int shift, const cf* twiddles,
+                      int n_cu, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  const int si = fft_size_index(n_fft);
+  const TwiddleLayout lay = fft_twiddle_layout();
+  const cf* tw = twiddles + lay.offset[si];
+  const long long fpb = kThreads / (n_fft / 16);
+  long long blocks = (batch + fpb - 1) / fpb;
+  const long long cap = (long long)n_cu * 4;  // four 35 KB workgroups fit one CU's LDS
+  if (blocks > cap) blocks = cap;
+  const dim3 grid((unsigned)blocks), block(kThreads);
+  switch (n_fft) {
+    case 64: hipLaunchKernelGGL(k_fft<64>, grid, block, 0, s, x, X, tw, batch, out_len, shift); break;
+    case 256: hipLaunchKernelGGL(k_fft<256>, grid, block, 0, s, x, X, tw, batch, out_len, shift); break;
+    case 1024: hipLaunchKernelGGL(k_fft<1024>, grid, block, 0, s, x, X, tw, batch, out_len, shift); break;
+    case 2048: hipLaunchKernelGGL(k_fft<2048>, grid, block, 0, s, x, X, tw, batch, out_len, shift); break;
+    case 4096: hipLaunchKernelGGL(k_fft<4096>, grid, block, 0, s, x, X, tw, batch, out_len, shift); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pusch

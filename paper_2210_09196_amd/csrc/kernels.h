@@ -1,0 +1,64 @@
+// Internal interface between the C-ABI host code (api.hip) and the gfx950
+// kernels of the PUSCH receive chain.  Not installed; include/pusch.h is the
+// public boundary.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pusch {
+
+// Interleaved FP32 complex, byte-compatible with pusch_c32 / torch.complex64.
+struct cf {
+  float r, i;
+};
+
+constexpr int kMaxSymbols = 16;
+constexpr int kMaxPilots = 4;
+
+// ---------------------------------------------------------------- FFT
+// Offsets (in cf elements) of each FFT size's twiddle block inside the
+// per-device table, and the table length.  Filled by fft_twiddle_layout().
+struct TwiddleLayout {
+  int offset[5];  // for n_fft = 64, 256, 1024, 2048, 4096
+  int total;
+};
+TwiddleLayout fft_twiddle_layout();
+// Writes the FP32 twiddle table (computed in FP64 on the host) into `host`
+// (length fft_twiddle_layout().total).
+void fft_fill_twiddles(cf* host);
+int fft_size_index(int n_fft);  // 0..4, or -1 if unsupported
+
+// X_i[(f + shift) mod n_fft] = DFT(x_i)[f] for the targets below out_len.
+hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_len, int shift, const cf* twiddles,
+                      int n_cu, hipStream_t s);
+
+// ---------------------------------------------------------------- beamforming
+// Y_i[n][b] = sum_a W[b][a] X_i[a][n]; X_i = X + i*sx (row pitch ldx),
+// Y_i = Y + i*sy (RE-major, n_beams values per RE).
+hipError_t launch_beamform(const cf* W, const cf* X, cf* Y, int n_beams, int n_ant, int n_re, long long ldx,
+                           long long sx, long long sy, long long batch, int n_cu, hipStream_t s);
+
+// ---------------------------------------------------------------- LS channel estimation
+struct ChestGeom {
+  long long y_batch;                // Y elements between batch items
+  long long y_pilot[kMaxPilots];    // offset of pilot symbol j's RE-major grid [n_sc][n_beams]
+  long long p_batch;                // pilots elements between batch items ([n_pilot][n_sc] each)
+  long long h_batch;                // H elements between batch items ([n_sc][n_ue][n_beams] each)
+  int n_beams, n_ue, n_sc, n_pilot;
+};
+hipError_t launch_chest(const cf* Y, const cf* pilots, cf* H, const ChestGeom& g, long long batch, hipStream_t s);
+
+// ---------------------------------------------------------------- MMSE detection
+struct MmseGeom {
+  long long h_batch;              // H elements between batch items
+  long long y_batch;              // Y elements between batch items
+  long long y_sym[kMaxSymbols];   // offset of data symbol d's RE-major grid [n_sc][n_beams]
+  long long x_batch;              // Xhat elements between batch items ([n_data][n_sc][n_ue] block)
+  long long st_batch;             // status elements between batch items
+  int n_beams, n_ue, n_sc, n_data;
+  float sigma2;
+};
+hipError_t launch_mmse(const cf* H, const cf* Y, cf* Xhat, int* status, const MmseGeom& g, long long batch,
+                       hipStream_t s);
+
+}  // namespace pusch

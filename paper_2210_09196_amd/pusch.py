@@ -1,0 +1,254 @@
+"""Python binding of libpusch.so (include/pusch.h) for torch device tensors.
+
+Argument marshalling only: every stage runs in the library's HIP kernels on
+the caller's current torch stream.  There is no fallback path -- if the shared
+library is missing or fails to load, every call raises.  Calls with an empty
+batch return their (empty) outputs without entering the library, since torch
+gives empty tensors a null data pointer.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpusch.so")
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "pusch.h")
+
+MAX_PILOTS = 4
+SLOT_STAGES = ("fft", "beamform", "chest", "mmse")
+
+
+class PuschError(RuntimeError):
+    """A libpusch call returned a negative status code."""
+
+
+class SlotDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_ant", ctypes.c_int),
+        ("n_fft", ctypes.c_int),
+        ("n_sc", ctypes.c_int),
+        ("n_symb", ctypes.c_int),
+        ("n_beams", ctypes.c_int),
+        ("n_ue", ctypes.c_int),
+        ("n_pilot", ctypes.c_int),
+        ("pilot_symb", ctypes.c_int * MAX_PILOTS),
+        ("sigma2", ctypes.c_float),
+        ("W", ctypes.c_void_p),
+        ("pilots", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_LL = ctypes.c_longlong
+_F = ctypes.c_float
+_SIG = {
+    "pusch_strerror": (ctypes.c_char_p, [_I]),
+    "pusch_init": (_I, []),
+    "pusch_fft": (_I, [_P, _P, _I, _I, _LL, _P]),
+    "pusch_beamform": (_I, [_P, _P, _P, _I, _I, _I, _LL, _LL, _P]),
+    "pusch_chest": (_I, [_P, _P, _P, _I, _I, _I, _I, _LL, _P]),
+    "pusch_mmse_solve": (_I, [_P, _P, _F, _P, _I, _I, _I, _I, _LL, _P, _P]),
+    "pusch_slot_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SlotDesc), _LL]),
+    "pusch_slot": (_I, [ctypes.POINTER(SlotDesc), _LL, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "pusch_profile_begin": (_I, [_I]),
+    "pusch_profile_end": (_I, [ctypes.POINTER(_F), _I]),
+}
+
+
+def header_symbols(path: str = HEADER) -> list[str]:
+    """Names of the functions include/pusch.h declares."""
+    text = open(path).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*|int|size_t)\s+(pusch_\w+)\s*\(", text, re.M)))
+
+
+def lib() -> ctypes.CDLL:
+    """Load libpusch.so once and attach the C signatures; raise if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PuschError(f"{LIB_PATH} is not built; run `python -m paper_2210_09196_amd.build`")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIG.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().pusch_strerror(int(code)).decode()
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        raise PuschError(f"{what}: {strerror(rc)} ({rc})")
+    return rc
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _c64(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise PuschError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.complex64:
+        raise PuschError(f"{name} must be complex64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise PuschError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def init() -> None:
+    _check(lib().pusch_init(), "pusch_init")
+
+
+def fft(x: torch.Tensor, n_sc: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Unscaled forward FFT over the last axis; n_sc > 0 keeps the centred active bins."""
+    _c64(x, "x")
+    n_fft = x.shape[-1]
+    batch = x.numel() // n_fft if n_fft else 0
+    out_len = n_sc if n_sc else n_fft
+    if out is None:
+        out = torch.empty(*x.shape[:-1], out_len, dtype=torch.complex64, device=x.device)
+    _c64(out, "out")
+    if out.numel() != batch * out_len:
+        raise PuschError("fft: output has the wrong size")
+    if batch == 0:
+        return out
+    _check(lib().pusch_fft(x.data_ptr(), out.data_ptr(), n_fft, n_sc, batch, _stream()), "pusch_fft")
+    return out
+
+
+def beamform(X: torch.Tensor, n_beams: int, W: torch.Tensor | None = None, n_re: int | None = None,
+             out: torch.Tensor | None = None) -> torch.Tensor:
+    """Y[i, n, b] = sum_a W[b, a] X[i, a, n] for X [batch, n_ant, ld_x]; returns [batch, n_re, n_beams]."""
+    _c64(X, "X")
+    if X.dim() == 2:
+        X = X.unsqueeze(0)
+    batch, n_ant, ld_x = X.shape
+    n_re = ld_x if n_re is None else n_re
+    if W is not None:
+        _c64(W, "W")
+        if tuple(W.shape) != (n_beams, n_ant):
+            raise PuschError("beamform: W must be [n_beams, n_ant]")
+    if out is None:
+        out = torch.empty(batch, n_re, n_beams, dtype=torch.complex64, device=X.device)
+    _c64(out, "out")
+    if batch == 0 or n_re == 0:
+        return out
+    _check(lib().pusch_beamform(_ptr(W), X.data_ptr(), out.data_ptr(), n_beams, n_ant, n_re, ld_x, batch, _stream()),
+           "pusch_beamform")
+    return out
+
+
+def chest(Yp: torch.Tensor, pilots: torch.Tensor, n_ue: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """LS channel estimate: Yp [batch, n_pilot, n_sc, n_beams], pilots [batch, n_pilot, n_sc]
+    -> H [batch, n_sc, n_ue, n_beams]."""
+    _c64(Yp, "Yp")
+    _c64(pilots, "pilots")
+    batch, n_pilot, n_sc, n_beams = Yp.shape
+    if tuple(pilots.shape) != (batch, n_pilot, n_sc):
+        raise PuschError("chest: pilots must be [batch, n_pilot, n_sc]")
+    if out is None:
+        out = torch.empty(batch, n_sc, n_ue, n_beams, dtype=torch.complex64, device=Yp.device)
+    _c64(out, "out")
+    if batch == 0:
+        return out
+    _check(lib().pusch_chest(Yp.data_ptr(), pilots.data_ptr(), out.data_ptr(), n_beams, n_ue, n_sc, n_pilot, batch,
+                             _stream()), "pusch_chest")
+    return out
+
+
+def mmse_solve(H: torch.Tensor, Yd: torch.Tensor, sigma2: float, out: torch.Tensor | None = None,
+               status: torch.Tensor | None | bool = True):
+    """MMSE detection: H [batch, n_sc, n_ue, n_beams], Yd [batch, n_data, n_sc, n_beams]
+    -> (x_hat [batch, n_data, n_sc, n_ue], status [batch, n_sc] int32 or None)."""
+    _c64(H, "H")
+    _c64(Yd, "Yd")
+    batch, n_sc, n_ue, n_beams = H.shape
+    if Yd.dim() != 4 or Yd.shape[0] != batch or Yd.shape[2] != n_sc or Yd.shape[3] != n_beams:
+        raise PuschError("mmse_solve: Yd must be [batch, n_data, n_sc, n_beams]")
+    n_data = Yd.shape[1]
+    if out is None:
+        out = torch.empty(batch, n_data, n_sc, n_ue, dtype=torch.complex64, device=H.device)
+    _c64(out, "out")
+    if status is True:
+        status = torch.empty(batch, n_sc, dtype=torch.int32, device=H.device)
+    elif status is False:
+        status = None
+    if batch == 0 or n_sc == 0:
+        return out, status
+    _check(lib().pusch_mmse_solve(H.data_ptr(), Yd.data_ptr(), float(sigma2), out.data_ptr(), n_beams, n_ue, n_sc,
+                                  n_data, batch, _ptr(status), _stream()), "pusch_mmse_solve")
+    return out, status
+
+
+class Slot:
+    """A fixed slot geometry with its device workspace, for repeated pusch_slot calls."""
+
+    def __init__(self, n_ant: int, n_fft: int, n_sc: int, n_symb: int, n_beams: int, n_ue: int, pilot_symb,
+                 sigma2: float, n_slot: int, W: torch.Tensor | None = None, device="cuda"):
+        pilot_symb = list(pilot_symb)
+        if not 1 <= len(pilot_symb) <= MAX_PILOTS:
+            raise PuschError("1..4 pilot symbols")
+        self.desc = SlotDesc()
+        d = self.desc
+        d.n_ant, d.n_fft, d.n_sc, d.n_symb = n_ant, n_fft, n_sc, n_symb
+        d.n_beams, d.n_ue, d.n_pilot = n_beams, n_ue, len(pilot_symb)
+        for j, s in enumerate(pilot_symb):
+            d.pilot_symb[j] = s
+        d.sigma2 = float(sigma2)
+        self.W = None if W is None else _c64(W, "W")
+        d.W = _ptr(self.W)
+        self.n_slot = n_slot
+        self.n_data = n_symb - len(pilot_symb)
+        nbytes = lib().pusch_slot_workspace_bytes(ctypes.byref(d), n_slot)
+        if nbytes == 0 and n_slot > 0:
+            raise PuschError("pusch_slot_workspace_bytes rejected the slot geometry")
+        self.ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        self.ws_bytes = int(nbytes)
+
+    def __call__(self, x_td: torch.Tensor, pilots: torch.Tensor, x_hat: torch.Tensor | None = None,
+                 status: torch.Tensor | None | bool = True):
+        d = self.desc
+        _c64(x_td, "x_td")
+        _c64(pilots, "pilots")
+        if tuple(x_td.shape) != (self.n_slot, d.n_symb, d.n_ant, d.n_fft):
+            raise PuschError(f"x_td must be [{self.n_slot}, {d.n_symb}, {d.n_ant}, {d.n_fft}]")
+        if tuple(pilots.shape) != (self.n_slot, d.n_pilot, d.n_sc):
+            raise PuschError(f"pilots must be [{self.n_slot}, {d.n_pilot}, {d.n_sc}]")
+        if x_hat is None:
+            x_hat = torch.empty(self.n_slot, self.n_data, d.n_sc, d.n_ue, dtype=torch.complex64, device=x_td.device)
+        _c64(x_hat, "x_hat")
+        if status is True:
+            status = torch.empty(self.n_slot, d.n_sc, dtype=torch.int32, device=x_td.device)
+        elif status is False:
+            status = None
+        if self.n_slot == 0:
+            return x_hat, status
+        d.pilots = pilots.data_ptr()
+        _check(lib().pusch_slot(ctypes.byref(d), self.n_slot, x_td.data_ptr(), x_hat.data_ptr(), _ptr(status),
+                                self.ws.data_ptr(), self.ws_bytes, _stream()), "pusch_slot")
+        return x_hat, status
+
+
+def profile_begin(max_calls: int) -> None:
+    _check(lib().pusch_profile_begin(int(max_calls)), "pusch_profile_begin")
+
+
+def profile_end() -> tuple[int, dict]:
+    """Returns (calls recorded, {stage: summed device ms})."""
+    buf = (ctypes.c_float * len(SLOT_STAGES))()
+    calls = _check(lib().pusch_profile_end(buf, len(SLOT_STAGES)), "pusch_profile_end")
+    return calls, {name: float(buf[i]) for i, name in enumerate(SLOT_STAGES)}

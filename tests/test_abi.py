@@ -1,0 +1,137 @@
+"""Host-side checks of the C-ABI library: it loads, exports every declared
+symbol, and rejects bad arguments before any device work (no GPU needed)."""
+import ctypes
+import os
+
+import pytest
+
+from paper_2210_09196_amd import pusch
+
+# Non-null but never dereferenced: every call below fails validation first.
+FAKE = ctypes.c_void_p(0x10000)
+FAKE2 = ctypes.c_void_p(0x90000000)
+EINVAL, EUNSUP, ENOMEM = -1, -2, -4
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pusch.LIB_PATH):
+        from paper_2210_09196_amd.build import build
+        build()
+    return pusch.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = pusch.header_symbols()
+    assert len(names) == 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(pusch._SIG)
+
+
+def test_strerror(lib):
+    assert pusch.strerror(0) == "success"
+    assert "invalid" in pusch.strerror(EINVAL)
+    assert pusch.strerror(12345) == "unknown error code"
+
+
+def test_fft_validation(lib):
+    f = lib.pusch_fft
+    assert f(None, FAKE2, 4096, 0, 1, None) == EINVAL
+    assert f(FAKE, FAKE2, 100, 0, 1, None) == EUNSUP
+    assert f(FAKE, FAKE2, 4096, 4097, 1, None) == EINVAL
+    assert f(FAKE, FAKE2, 4096, -1, 1, None) == EINVAL
+    assert f(FAKE, FAKE2, 4096, 0, -1, None) == EINVAL
+    assert f(FAKE, FAKE, 4096, 3300, 1, None) == EINVAL  # in place needs the full output
+    assert f(FAKE, ctypes.c_void_p(0x10000 + 8), 64, 0, 2, None) == EINVAL  # partial overlap
+    assert f(FAKE, FAKE2, 4096, 0, 0, None) == 0  # empty batch: no-op, no device touched
+
+
+def test_beamform_validation(lib):
+    f = lib.pusch_beamform
+    assert f(None, None, FAKE2, 32, 64, 3300, 3300, 1, None) == EINVAL
+    assert f(None, FAKE, FAKE2, 65, 64, 3300, 3300, 1, None) == EINVAL  # too many beams
+    assert f(None, FAKE, FAKE2, 0, 64, 3300, 3300, 1, None) == EINVAL
+    assert f(None, FAKE, FAKE2, 32, 16, 100, 100, 1, None) == EINVAL  # built-in DFT needs beams <= antennas
+    assert f(None, FAKE, FAKE2, 32, 64, 3300, 3000, 1, None) == EINVAL  # ld_x < n_re
+    assert f(FAKE2, FAKE, FAKE2, 32, 64, 3300, 3300, 1, None) == EINVAL  # W overlaps Y
+    assert f(None, FAKE, FAKE2, 32, 64, 0, 1, 5, None) == 0
+
+
+def test_chest_validation(lib):
+    f = lib.pusch_chest
+    assert f(FAKE, None, FAKE2, 32, 16, 3300, 2, 1, None) == EINVAL
+    assert f(FAKE, FAKE, FAKE2, 32, 16, 3300, 5, 1, None) == EINVAL  # too many pilot symbols
+    assert f(FAKE, FAKE, FAKE2, 8, 16, 3300, 2, 1, None) == EINVAL  # more UEs than beams
+    assert f(FAKE, FAKE, FAKE2, 32, 16, 15, 2, 1, None) == EINVAL  # a UE without pilots
+    assert f(FAKE, FAKE, FAKE2, 64, 33, 3300, 2, 1, None) == EINVAL
+    assert f(FAKE, FAKE, FAKE2, 32, 16, 3300, 2, 0, None) == 0
+
+
+def test_mmse_validation(lib):
+    f = lib.pusch_mmse_solve
+    assert f(FAKE, FAKE, -1.0, FAKE2, 32, 16, 3300, 12, 1, None, None) == EINVAL
+    assert f(FAKE, FAKE, float("nan"), FAKE2, 32, 16, 3300, 12, 1, None, None) == EINVAL
+    assert f(FAKE, FAKE, float("inf"), FAKE2, 32, 16, 3300, 12, 1, None, None) == EINVAL
+    assert f(FAKE, FAKE, 0.1, FAKE2, 32, 16, 3300, 0, 1, None, None) == EINVAL
+    assert f(FAKE, FAKE, 0.1, FAKE2, 8, 16, 3300, 12, 1, None, None) == EINVAL
+    assert f(FAKE, FAKE, 0.1, FAKE, 32, 16, 3300, 12, 1, None, None) == EINVAL  # output overlaps input
+    assert f(FAKE, FAKE, 0.1, FAKE2, 32, 16, 3300, 12, 0, None, None) == 0
+
+
+def _desc(**kw):
+    d = pusch.SlotDesc()
+    vals = dict(n_ant=64, n_fft=4096, n_sc=3300, n_symb=14, n_beams=32, n_ue=16, n_pilot=2, sigma2=0.01)
+    vals.update(kw)
+    for k, v in vals.items():
+        setattr(d, k, v)
+    ps = kw.get("pilot_symb", (2, 11))
+    for j, s in enumerate(ps):
+        d.pilot_symb[j] = s
+    d.pilots = kw.get("pilots", 0x20000)
+    return d
+
+
+def test_slot_workspace_bytes(lib):
+    d = _desc()
+    n = 16
+    xa = n * 14 * 64 * 3300 * 8
+    y = n * 14 * 3300 * 32 * 8
+    h = n * 3300 * 16 * 32 * 8
+    a = lambda v: (v + 255) // 256 * 256
+    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d), n) == a(xa) + a(y) + a(h)
+    assert lib.pusch_slot_workspace_bytes(ctypes.byref(_desc(n_fft=1000)), n) == 0
+    assert lib.pusch_slot_workspace_bytes(ctypes.byref(_desc(pilot_symb=(11, 2))), n) == 0
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n_fft=3000), EUNSUP),
+    (dict(n_sc=4097), EINVAL),
+    (dict(n_sc=8), EINVAL),  # fewer subcarriers than UEs
+    (dict(n_symb=17), EINVAL),
+    (dict(n_pilot=0), EINVAL),
+    (dict(pilot_symb=(2, 2)), EINVAL),
+    (dict(pilot_symb=(2, 14)), EINVAL),
+    (dict(sigma2=-0.5), EINVAL),
+    (dict(n_ue=33, n_beams=64), EINVAL),
+    (dict(n_beams=70), EINVAL),
+    (dict(pilots=0), EINVAL),
+])
+def test_slot_validation(lib, kw, code):
+    d = _desc(**kw)
+    ws = ctypes.c_void_p(0x4000000000)
+    assert lib.pusch_slot(ctypes.byref(d), 1, FAKE, FAKE2, None, ws, 1 << 40, None) == code
+
+
+def test_slot_workspace_errors(lib):
+    d = _desc()
+    need = lib.pusch_slot_workspace_bytes(ctypes.byref(d), 2)
+    ws = ctypes.c_void_p(0x4000000000)
+    assert lib.pusch_slot(ctypes.byref(d), 2, FAKE, FAKE2, None, ws, need - 1, None) == ENOMEM
+    assert lib.pusch_slot(ctypes.byref(d), 2, FAKE, FAKE2, None, ctypes.c_void_p(0x4000000010), need, None) == EINVAL
+    assert lib.pusch_slot(ctypes.byref(d), 0, FAKE, FAKE2, None, ws, need, None) == 0
+
+
+def test_profile_arguments(lib):
+    assert lib.pusch_profile_begin(0) == EINVAL
+    assert lib.pusch_profile_end(None, 0) == EINVAL  # not active
