@@ -161,7 +161,8 @@ size_t pusch_slot_workspace_bytes(const pusch_slot_desc* d, long long n_slot);
  * independent slots, enqueued on one stream: OFDM demodulation of every
  * antenna and symbol to the n_sc active subcarriers, beamforming, LS channel
  * estimation on the pilot symbols, MMSE detection of every other ("data")
- * symbol in ascending symbol order.
+ * symbol in ascending symbol order.  With n_ue <= 16 the channel estimate is
+ * computed inside the detection kernel and never stored.
  *   x_td   [n_slot][n_symb][n_ant][n_fft] time-domain samples.
  *   x_hat  [n_slot][n_data][n_sc][n_ue], n_data = n_symb - n_pilot.
  *   status [n_slot][n_sc] int32 or NULL, as pusch_mmse_solve.

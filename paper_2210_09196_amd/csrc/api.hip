@@ -259,7 +259,9 @@ SlotLayout slot_layout(const pusch_slot_desc* d, long long n_slot) {
   lay.off_xa = 0;
   lay.off_y = align256(n * S * R * K * 8);
   lay.off_h = lay.off_y + align256(n * S * K * B * 8);
-  lay.total = lay.off_h + align256(n * K * L * B * 8);
+  // with n_ue <= 16 the detection kernel estimates the channel itself and no
+  // stored estimate is needed
+  lay.total = lay.off_h + (pusch::mmse_fusable(d->n_ue) ? 0 : align256(n * K * L * B * 8));
   return lay;
 }
 
@@ -313,10 +315,21 @@ int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td
   if (pusch::launch_fft(reinterpret_cast<const cf*>(x_td), Xa, d->n_fft, n_slot * S * R, K, K / 2, t->twiddles,
                         t->n_cu, s) != hipSuccess)
     return PUSCH_EHIP;
-  // a2: beamforming of every symbol, RE-major output
+  // a2: beamforming of every symbol, RE-major output; when the detection
+  // kernel estimates the channel itself, the pilot symbols leave this stage
+  // already divided by their pilots (the LS division of a3)
+  const bool fused = pusch::mmse_fusable(L);
+  pusch::PilotScale psc{};
+  if (fused) {
+    psc.pilots = reinterpret_cast<const cf*>(d->pilots);
+    psc.p_slot = (long long)P * K;
+    psc.n_symb = S;
+    for (int s_ = 0; s_ < pusch::kMaxSymbols; ++s_) psc.pilot_of[s_] = -1;
+    for (int j = 0; j < P; ++j) psc.pilot_of[d->pilot_symb[j]] = (signed char)j;
+  }
   if (!mark(1)) return PUSCH_EHIP;
-  if (pusch::launch_beamform(w, Xa, Y, B, R, K, K, (long long)R * K, (long long)K * B, n_slot * S, t->n_cu, s) !=
-      hipSuccess)
+  if (pusch::launch_beamform(w, Xa, Y, B, R, K, K, (long long)R * K, (long long)K * B, n_slot * S, t->n_cu, s,
+                             fused ? &psc : nullptr) != hipSuccess)
     return PUSCH_EHIP;
   // a3: LS channel estimate from the pilot symbols
   if (!mark(2)) return PUSCH_EHIP;
@@ -329,9 +342,10 @@ int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td
   for (int j = 0; j < P; ++j) cg.y_pilot[j] = (long long)d->pilot_symb[j] * K * B;
   cg.p_batch = (long long)P * K;
   cg.h_batch = (long long)K * L * B;
-  if (pusch::launch_chest(Y, reinterpret_cast<const cf*>(d->pilots), H, cg, n_slot, s) != hipSuccess)
+  if (!fused && pusch::launch_chest(Y, reinterpret_cast<const cf*>(d->pilots), H, cg, n_slot, s) != hipSuccess)
     return PUSCH_EHIP;
-  // a4-a6: Gram, Cholesky, matched filter and substitutions for the data symbols
+  // a4-a6: Gram, Cholesky, matched filter and substitutions for the data
+  // symbols (with the a3 estimate computed inside when fused)
   if (!mark(3)) return PUSCH_EHIP;
   pusch::MmseGeom mg{};
   mg.n_beams = B;
@@ -350,7 +364,10 @@ int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td
   }
   mg.x_batch = (long long)D * K * L;
   mg.st_batch = K;
-  if (pusch::launch_mmse(H, Y, reinterpret_cast<cf*>(x_hat), status, mg, n_slot, s) != hipSuccess) return PUSCH_EHIP;
+  const hipError_t me =
+      fused ? pusch::launch_mmse_fused(Y, cg, reinterpret_cast<cf*>(x_hat), status, mg, n_slot, s)
+            : pusch::launch_mmse(H, Y, reinterpret_cast<cf*>(x_hat), status, mg, n_slot, s);
+  if (me != hipSuccess) return PUSCH_EHIP;
   if (!mark(4)) return PUSCH_EHIP;
   return PUSCH_OK;
 }

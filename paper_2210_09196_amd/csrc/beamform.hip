@@ -4,13 +4,21 @@
 //
 // The paper computes 4x4 output windows per core in registers (Sec. V-B).
 // Here one wavefront owns an output tile of (16*MT beams) x 32 REs and walks
-// the antenna axis four at a time with v_mfma_f32_16x16x4_f32.  The complex
-// product is split into four real products on the interleaved operands,
-//   Yr += Wr Xr - Wi Xi,  Yi += Wr Xi + Wi Xr,
-// so a lane's single 8-byte load of X[a][n] feeds both the real and the
-// imaginary MFMA without any de-interleaving pass.  Operand layouts of the
-// 16x16x4 instruction: lane l supplies A[l%16][l/16] and B[l/16][l%16] and
-// receives D[4*(l/16)+v][l%16], v = 0..3.
+// the antenna axis four at a time with v_mfma_f32_16x16x4_f32.  Each complex
+// step takes three real products (Gauss/Karatsuba):
+//   T1 = Wr Xr,  T2 = Wi Xi,  T3 = (Wr + Wi)(Xr + Xi),
+//   Yr = T1 - T2,  Yi = T3 - T1 - T2,
+// 25% fewer matrix-core operations than the four-product form.  W is staged
+// once per workgroup in LDS in operand order (Wr, Wi, Wr + Wi per lane).  The
+// two 16-column MFMA tiles of a wavefront take interleaved columns (lane c
+// owns columns 2c and 2c+1), so one 16-byte load of the interleaved complex
+// grid feeds both tiles.  Operand layouts of the 16x16x4 instruction: lane l
+// supplies A[l%16][l/16] and B[l/16][l%16] and receives D[4*(l/16)+v][l%16].
+//
+// Optional epilogue for the fused slot: outputs of pilot symbols are turned
+// into LS channel values y * conj(p) / |p|^2 before they are stored (the
+// element-wise division of the paper's channel-estimation step).
+#include "comb_ls.h"
 #include "kernels.h"
 
 namespace pusch {
@@ -19,89 +27,165 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 4;
-constexpr int kNT = 2;  // 16-column MFMA tiles per wavefront tile
+constexpr int kTileN = 32;  // REs per wavefront tile (two interleaved 16-column MFMA tiles)
 
-template <int MT>
+__device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int MT, bool W_LDS>
 __global__ __launch_bounds__(64 * kWaves) void k_beamform(const cf* __restrict__ W, const cf* __restrict__ X,
-                                                          cf* __restrict__ Y, int nb, int na, int nre,
-                                                          long long ldx, long long sx, long long sy,
-                                                          long long batch, long long ntn) {
+                                                          cf* __restrict__ Y, int nb, int na, int nre, long long ldx,
+                                                          long long sx, long long sy, long long batch, long long ntn,
+                                                          PilotScale ps) {
+  extern __shared__ float4 wl[];  // [ks][m][lane] = (Wr, Wi, Wr + Wi, 0)
   const int lane = threadIdx.x & 63;
   const int col = lane & 15;  // A row / B column / D column inside a 16x16 tile
   const int kq = lane >> 4;   // A column / B row (antenna within the step of 4)
-  const long long nwave = (long long)gridDim.x * kWaves;
   const int ksteps = (na + 3) >> 2;
 
+  if (W_LDS) {
+    for (int e = threadIdx.x; e < ksteps * MT * 64; e += blockDim.x) {
+      const int l = e & 63, m = (e >> 6) % MT, ks = (e >> 6) / MT;
+      const int b = m * 16 + (l & 15), a = ks * 4 + (l >> 4);
+      const cf w = (a < na && b < nb) ? W[b * na + a] : cf{0.f, 0.f};
+      wl[e] = make_float4(w.r, w.i, w.r + w.i, 0.f);
+    }
+    __syncthreads();
+  }
+
+  const long long nwave = (long long)gridDim.x * kWaves;
+  const bool vec = ((ldx | sx) & 1) == 0;  // 16-byte aligned column pairs
   for (long long tile = (long long)blockIdx.x * kWaves + (threadIdx.x >> 6); tile < batch * ntn; tile += nwave) {
     const long long bi = tile / ntn;
-    const int n0 = (int)(tile - bi * ntn) * (16 * kNT);
+    const int n0 = (int)(tile - bi * ntn) * kTileN;
+    const int nc = n0 + 2 * col;  // this lane's two columns: nc, nc + 1
     const cf* Xb = X + bi * sx;
-    f32x4 yr[MT][kNT], yi[MT][kNT];
+    f32x4 t1[MT][2], t2[MT][2], t3[MT][2];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
-      for (int t = 0; t < kNT; ++t) yr[m][t] = yi[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int t = 0; t < 2; ++t) t1[m][t] = t2[m][t] = t3[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     for (int ks = 0; ks < ksteps; ++ks) {
       const int a = ks * 4 + kq;
-      const bool a_ok = a < na;
-      cf xv[kNT];
-#pragma unroll
-      for (int t = 0; t < kNT; ++t) {
-        const int n = n0 + t * 16 + col;
-        xv[t] = (a_ok && n < nre) ? Xb[(long long)a * ldx + n] : cf{0.f, 0.f};
+      cf x0 = cf{0.f, 0.f}, x1 = cf{0.f, 0.f};
+      if (a < na) {
+        const cf* p = Xb + (long long)a * ldx + nc;
+        if (vec && nc + 1 < nre) {
+          const float4 v = *reinterpret_cast<const float4*>(p);
+          x0 = cf{v.x, v.y};
+          x1 = cf{v.z, v.w};
+        } else {
+          if (nc < nre) x0 = p[0];
+          if (nc + 1 < nre) x1 = p[1];
+        }
       }
+      const float s0 = x0.r + x0.i, s1 = x1.r + x1.i;
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
-        const int b = m * 16 + col;
-        const cf wv = (a_ok && b < nb) ? W[b * na + a] : cf{0.f, 0.f};
-        const float nwi = -wv.i;
+        float4 w;
+        if (W_LDS) {
+          w = wl[(ks * MT + m) * 64 + lane];
+        } else {
+          const int b = m * 16 + col;
+          const cf c = (a < na && b < nb) ? W[b * na + a] : cf{0.f, 0.f};
+          w = make_float4(c.r, c.i, c.r + c.i, 0.f);
+        }
+        t1[m][0] = mfma(w.x, x0.r, t1[m][0]);
+        t2[m][0] = mfma(w.y, x0.i, t2[m][0]);
+        t3[m][0] = mfma(w.z, s0, t3[m][0]);
+        t1[m][1] = mfma(w.x, x1.r, t1[m][1]);
+        t2[m][1] = mfma(w.y, x1.i, t2[m][1]);
+        t3[m][1] = mfma(w.z, s1, t3[m][1]);
+      }
+    }
+
+    // optional LS epilogue for pilot symbols
+    cf sc[2] = {cf{1.f, 0.f}, cf{1.f, 0.f}};
+    bool scaled = false;
+    if (ps.pilots) {
+      const long long slot = bi / ps.n_symb;
+      const int j = ps.pilot_of[bi - slot * ps.n_symb];
+      if (j >= 0) {
+        scaled = true;
+        const cf* pv = ps.pilots + slot * ps.p_slot + (long long)j * nre;
 #pragma unroll
-        for (int t = 0; t < kNT; ++t) {
-          yr[m][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.r, xv[t].r, yr[m][t], 0, 0, 0);
-          yr[m][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(nwi, xv[t].i, yr[m][t], 0, 0, 0);
-          yi[m][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.r, xv[t].i, yi[m][t], 0, 0, 0);
-          yi[m][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.i, xv[t].r, yi[m][t], 0, 0, 0);
+        for (int t = 0; t < 2; ++t) {
+          if (nc + t < nre) {
+            const cf p = pv[nc + t];
+            const float inv = fast_rcp(p.r * p.r + p.i * p.i);
+            sc[t] = cf{p.r * inv, -p.i * inv};
+          }
         }
       }
     }
 
     cf* Yb = Y + bi * sy;
 #pragma unroll
-    for (int t = 0; t < kNT; ++t) {
-      const int n = n0 + t * 16 + col;
+    for (int t = 0; t < 2; ++t) {
+      const int n = nc + t;
       if (n >= nre) continue;
 #pragma unroll
-      for (int m = 0; m < MT; ++m)
+      for (int m = 0; m < MT; ++m) {
+        const int b0 = m * 16 + kq * 4;
+        cf o[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int b = m * 16 + kq * 4 + v;
-          if (b < nb) Yb[(long long)n * nb + b] = cf{yr[m][t][v], yi[m][t][v]};
+          const float re = t1[m][t][v] - t2[m][t][v];
+          const float im = t3[m][t][v] - t1[m][t][v] - t2[m][t][v];
+          o[v] = scaled ? cf{re * sc[t].r - im * sc[t].i, re * sc[t].i + im * sc[t].r} : cf{re, im};
         }
+        cf* dst = Yb + (long long)n * nb + b0;
+        if (b0 + 3 < nb && (nb & 1) == 0) {
+          reinterpret_cast<float4*>(dst)[0] = make_float4(o[0].r, o[0].i, o[1].r, o[1].i);
+          reinterpret_cast<float4*>(dst)[1] = make_float4(o[2].r, o[2].i, o[3].r, o[3].i);
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (b0 + v < nb) dst[v] = o[v];
+        }
+      }
     }
   }
+}
+
+constexpr size_t kWLdsMax = 64 * 1024;
+
+template <int MT>
+hipError_t launch_mt(const cf* W, const cf* X, cf* Y, int nb, int na, int nre, long long ldx, long long sx,
+                     long long sy, long long batch, long long ntn, const PilotScale& ps, dim3 grid, hipStream_t s) {
+  const size_t lds = (size_t)((na + 3) / 4) * MT * 64 * sizeof(float4);
+  if (lds <= kWLdsMax)
+    hipLaunchKernelGGL((k_beamform<MT, true>), grid, dim3(64 * kWaves), lds, s, W, X, Y, nb, na, nre, ldx, sx, sy,
+                       batch, ntn, ps);
+  else
+    hipLaunchKernelGGL((k_beamform<MT, false>), grid, dim3(64 * kWaves), 0, s, W, X, Y, nb, na, nre, ldx, sx, sy,
+                       batch, ntn, ps);
+  return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_beamform(const cf* W, const cf* X, cf* Y, int n_beams, int n_ant, int n_re, long long ldx,
-                           long long sx, long long sy, long long batch, int n_cu, hipStream_t s) {
+                           long long sx, long long sy, long long batch, int n_cu, hipStream_t s,
+                           const PilotScale* pilot_scale) {
   if (batch <= 0 || n_re <= 0) return hipSuccess;
-  const long long ntn = (n_re + 16 * kNT - 1) / (16 * kNT);
+  const long long ntn = (n_re + kTileN - 1) / kTileN;
   const long long tiles = batch * ntn;
   long long blocks = (tiles + kWaves - 1) / kWaves;
   const long long cap = (long long)n_cu * 8;
   if (blocks > cap) blocks = cap;
-  const dim3 grid((unsigned)blocks), block(64 * kWaves);
-  const int mt = (n_beams + 15) / 16;
-  switch (mt) {
-    case 1: hipLaunchKernelGGL(k_beamform<1>, grid, block, 0, s, W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ntn); break;
-    case 2: hipLaunchKernelGGL(k_beamform<2>, grid, block, 0, s, W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ntn); break;
-    case 3: hipLaunchKernelGGL(k_beamform<3>, grid, block, 0, s, W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ntn); break;
-    case 4: hipLaunchKernelGGL(k_beamform<4>, grid, block, 0, s, W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ntn); break;
+  const dim3 grid((unsigned)blocks);
+  PilotScale ps{};
+  if (pilot_scale) ps = *pilot_scale;
+  switch ((n_beams + 15) / 16) {
+    case 1: return launch_mt<1>(W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ntn, ps, grid, s);
+    case 2: return launch_mt<2>(W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ntn, ps, grid, s);
+    case 3: return launch_mt<3>(W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ntn, ps, grid, s);
+    case 4: return launch_mt<4>(W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ntn, ps, grid, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace pusch

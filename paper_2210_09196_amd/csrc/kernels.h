@@ -33,10 +33,20 @@ hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_le
                       int n_cu, hipStream_t s);
 
 // ---------------------------------------------------------------- beamforming
+// Optional beamforming epilogue of the fused slot: the outputs of pilot
+// symbols are multiplied by conj(p)/|p|^2 (the LS division), batch item
+// i = slot * n_symb + symbol.
+struct PilotScale {
+  const cf* pilots;                 // [n_slot][n_pilot][n_re], nullptr = no epilogue
+  long long p_slot;                 // pilots elements between slots
+  int n_symb;
+  signed char pilot_of[kMaxSymbols];  // pilot index of each symbol, or -1
+};
 // Y_i[n][b] = sum_a W[b][a] X_i[a][n]; X_i = X + i*sx (row pitch ldx),
 // Y_i = Y + i*sy (RE-major, n_beams values per RE).
 hipError_t launch_beamform(const cf* W, const cf* X, cf* Y, int n_beams, int n_ant, int n_re, long long ldx,
-                           long long sx, long long sy, long long batch, int n_cu, hipStream_t s);
+                           long long sx, long long sy, long long batch, int n_cu, hipStream_t s,
+                           const PilotScale* pilot_scale = nullptr);
 
 // ---------------------------------------------------------------- LS channel estimation
 struct ChestGeom {
@@ -60,5 +70,12 @@ struct MmseGeom {
 };
 hipError_t launch_mmse(const cf* H, const cf* Y, cf* Xhat, int* status, const MmseGeom& g, long long batch,
                        hipStream_t s);
+// Same detection, with the channel interpolated on the fly from pilot
+// symbols of Y that already hold LS values y*conj(p)/|p|^2 (PilotScale
+// epilogue; grid offsets in cg as for launch_chest) instead of read from a
+// stored estimate.  Requires mmse_fusable(n_ue).
+bool mmse_fusable(int n_ue);
+hipError_t launch_mmse_fused(const cf* Y, const ChestGeom& cg, cf* Xhat, int* status, const MmseGeom& g,
+                             long long batch, hipStream_t s);
 
 }  // namespace pusch

@@ -1,19 +1,29 @@
 // MMSE MIMO detection (Eq. 2) per subcarrier: G = H^H H + sigma^2 I,
 // Cholesky G = L L^H in Crout order (column by column, Sec. V-C), then for
 // every data symbol the matched filter b = H^H y, forward substitution
-// L z = b and back substitution L^H x = z.
+// L z = b and back substitution L^H x = z.  The factor is computed once per
+// subcarrier and reused for every data symbol.
 //
 // The paper runs many independent small decompositions per core between
-// barriers (Sec. VI).  Here one wavefront handles 64/LPS subcarriers at once;
-// each subcarrier owns LPS = pow2 >= n_ue lanes and lane i holds row i of G,
-// later of L, in registers.  The subcarriers' H blocks and data-symbol beam
-// vectors are staged in LDS (rows padded so the broadcast and strided reads
-// of a wavefront stay conflict-free), the Crout column step broadcasts row j
-// of L inside the lane group with cross-lane shuffles, and the substitutions
-// run column-oriented over all data symbols at once, so the factor is
-// computed once per subcarrier and reused for every symbol.
+// barriers (Sec. VI).  Two gfx950 kernels:
+//
+// k_mmse_mfma (n_ue <= 16): one wavefront takes 4 subcarriers per pass.
+//   Phase A runs the two dense products of each subcarrier -- the Gram
+//   matrix H^H H and the matched filter H^H [y_1 .. y_D] -- as 16x16x4 FP32
+//   MFMAs, the complex products split into four real ones; a lane's single
+//   fragment of H feeds both operands of the Gram product.  Phase B does the
+//   Crout factorisation with one lane per row of L (16 lanes per subcarrier,
+//   row j broadcast by cross-lane shuffles).  Phase C runs both
+//   substitutions with one lane per data symbol, reading L from LDS by
+//   broadcast.  With FUSED the kernel interpolates H itself (comb_ls.h) from
+//   the LS values that the beamforming epilogue leaves in the pilot symbols,
+//   so the fused slot never writes or re-reads a channel estimate.
+//
+// k_mmse_rows (n_ue <= 32): lane i of a group of LPS lanes holds row i of G
+//   and L; Gram and matched filter from LDS-staged H and y on the VALU.
 #include <cmath>
 
+#include "comb_ls.h"
 #include "kernels.h"
 
 namespace pusch {
@@ -21,6 +31,11 @@ namespace {
 
 constexpr int kMaxD = 16;  // data symbols per kernel call (host splits larger requests)
 constexpr int kDCh = 4;    // data symbols staged in LDS at a time
+
+// Value of v in the lane whose byte address (4 * lane) is src_byte.
+__device__ __forceinline__ float lane_bcast(float v, int src_byte) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src_byte, __float_as_int(v)));
+}
 
 struct LdsGeom {
   int hrow, hgrp;  // H rows (beams) and per-subcarrier stride, in cf
@@ -31,7 +46,7 @@ struct LdsGeom {
 };
 
 template <int LPS>
-__global__ __launch_bounds__(64) void k_mmse(const cf* __restrict__ H, const cf* __restrict__ Y, cf* __restrict__ Xh,
+__global__ __launch_bounds__(64) void k_mmse_rows(const cf* __restrict__ H, const cf* __restrict__ Y, cf* __restrict__ Xh,
                                              int* __restrict__ st, MmseGeom g, LdsGeom lg, long long nblk,
                                              int nblk_batch) {
   extern __shared__ cf sm[];
@@ -114,7 +129,7 @@ __global__ __launch_bounds__(64) void k_mmse(const cf* __restrict__ H, const cf*
     }
 
     // Cholesky-Crout: column j uses row j of L (lane j of the group)
-    bool fail = false;
+    int fail = 0;
     float invd = 0.f;
     cf L[LPS];
 #pragma unroll
@@ -122,26 +137,22 @@ __global__ __launch_bounds__(64) void k_mmse(const cf* __restrict__ H, const cf*
 #pragma unroll
     for (int j = 0; j < LPS; ++j) {
       if (j >= nue) continue;
+      const int src = (gbase + j) << 2;
       cf t = L[j];
 #pragma unroll
       for (int m = 0; m < j; ++m) {
-        const float cr = __shfl(L[m].r, gbase + j);
-        const float ci = __shfl(L[m].i, gbase + j);
+        const float cr = lane_bcast(L[m].r, src);
+        const float ci = lane_bcast(L[m].i, src);
         t.r -= L[m].r * cr + L[m].i * ci;  // L_im * conj(L_jm)
         t.i -= L[m].i * cr - L[m].r * ci;
       }
-      const float dpiv = __shfl(t.r, gbase + j);
-      fail = fail || !(dpiv > 0.f) || !(dpiv <= 3.402823466e38f);
+      const float dpiv = lane_bcast(t.r, src);
+      fail |= (dpiv > 0.f && dpiv <= 3.402823466e38f) ? 0 : 1;
       const float ljj = sqrtf(dpiv);
       const float inv = 1.0f / ljj;
-      if (i == j) {
-        L[j] = cf{ljj, 0.f};
-        invd = inv;
-      } else if (i > j) {
-        L[j] = cf{t.r * inv, t.i * inv};
-      } else {
-        L[j] = cf{0.f, 0.f};
-      }
+      const cf lij = cf{t.r * inv, t.i * inv};
+      L[j] = i == j ? cf{ljj, 0.f} : (i > j ? lij : cf{0.f, 0.f});
+      invd = i == j ? inv : invd;
     }
 
     // rows of L to LDS (reusing the H region) for the transposed reads of
@@ -158,8 +169,8 @@ __global__ __launch_bounds__(64) void k_mmse(const cf* __restrict__ H, const cf*
 #pragma unroll
       for (int d = 0; d < kMaxD; ++d) {
         if (d >= nd) continue;
-        const float zr = __shfl(rr[d].r * invd, gbase + m);
-        const float zi = __shfl(rr[d].i * invd, gbase + m);
+        const float zr = lane_bcast(rr[d].r * invd, (gbase + m) << 2);
+        const float zi = lane_bcast(rr[d].i * invd, (gbase + m) << 2);
         if (i == m) {
           rr[d] = cf{zr, zi};
         } else if (i > m) {
@@ -176,8 +187,8 @@ __global__ __launch_bounds__(64) void k_mmse(const cf* __restrict__ H, const cf*
 #pragma unroll
       for (int d = 0; d < kMaxD; ++d) {
         if (d >= nd) continue;
-        const float xr = __shfl(rr[d].r * invd, gbase + m);
-        const float xi = __shfl(rr[d].i * invd, gbase + m);
+        const float xr = lane_bcast(rr[d].r * invd, (gbase + m) << 2);
+        const float xi = lane_bcast(rr[d].i * invd, (gbase + m) << 2);
         if (i == m) {
           rr[d] = cf{xr, xi};
         } else if (i < m) {
@@ -222,23 +233,257 @@ hipError_t launch_lps(const cf* H, const cf* Y, cf* Xh, int* st, const MmseGeom&
   if (nblk <= 0) return hipSuccess;
   long long blocks = nblk;
   if (blocks > (1LL << 30)) blocks = 1LL << 30;
-  hipLaunchKernelGGL(k_mmse<LPS>, dim3((unsigned)blocks), dim3(64), (size_t)lg.total * sizeof(cf), s, H, Y, Xh, st, g,
+  hipLaunchKernelGGL(k_mmse_rows<LPS>, dim3((unsigned)blocks), dim3(64), (size_t)lg.total * sizeof(cf), s, H, Y, Xh, st, g,
                      lg, nblk, nblk_batch);
   return hipGetLastError();
 }
 
 }  // namespace
 
+
+// ---------------------------------------------------------------- MFMA path (n_ue <= 16)
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kSPW = 4;              // subcarriers per wavefront pass
+constexpr int kRow = 17;             // padded LDS row of a 16x16 matrix (cf)
+constexpr int kMat = 16 * kRow + 1;  // padded matrix stride: the 4 groups' broadcasts hit distinct banks
+constexpr int kDinv = 17;
+
+__device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// acc -= a * b and acc -= conj(a) * b, as explicit FMAs
+__device__ __forceinline__ void csub_mul(cf& acc, cf a, cf b) {
+  acc.r = __builtin_fmaf(-a.r, b.r, __builtin_fmaf(a.i, b.i, acc.r));
+  acc.i = __builtin_fmaf(-a.r, b.i, __builtin_fmaf(-a.i, b.r, acc.i));
+}
+__device__ __forceinline__ void csub_conj_mul(cf& acc, cf a, cf b) {
+  acc.r = __builtin_fmaf(-a.r, b.r, __builtin_fmaf(-a.i, b.i, acc.r));
+  acc.i = __builtin_fmaf(-a.r, b.i, __builtin_fmaf(a.i, b.r, acc.i));
+}
+
+// Fragment slot s of the lane with A-column / B-row index q holds beam
+// 8*(s/2) + 2*q + s%2: each lane owns pairs of adjacent beams (16-byte loads)
+// and every K-step still sees four distinct beams.
+__device__ __forceinline__ int frag_beam(int s, int q) { return 8 * (s >> 1) + 2 * q + (s & 1); }
+
+// Beams b, b+1 of an RE-major row (zero beyond nb or when !ok).
+__device__ __forceinline__ void load_pair(cf& v0, cf& v1, const cf* __restrict__ row, int b, int nb, bool ok,
+                                          bool vec) {
+  v0 = v1 = cf{0.f, 0.f};
+  if (!ok) return;
+  if (vec && b + 1 < nb) {
+    const float4 t = *reinterpret_cast<const float4*>(row + b);
+    v0 = cf{t.x, t.y};
+    v1 = cf{t.z, t.w};
+  } else {
+    if (b < nb) v0 = row[b];
+    if (b + 1 < nb) v1 = row[b + 1];
+  }
+}
+
+template <int KS, bool FUSED>
+__global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, const cf* __restrict__ Y,
+                                                  cf* __restrict__ Xh, int* __restrict__ st, MmseGeom g,
+                                                  ChestGeom cg, long long nblk, int nblk_batch) {
+  __shared__ cf Gs[kSPW * kMat];  // G, then L in place
+  __shared__ cf Ps[kSPW * kMat];  // P[i][d] = (H^H y_d)_i
+  __shared__ float Dinv[kSPW * kDinv];
+  const int lane = threadIdx.x;
+  const int c16 = lane & 15, q = lane >> 4;
+  const int nb = g.n_beams, nue = g.n_ue, nsc = g.n_sc, nd = g.n_data;
+  const bool vec = (nb & 1) == 0;
+  // offset of this lane's data symbol (B operand of the matched filter)
+  long long ysym = 0;
+#pragma unroll
+  for (int d = 0; d < kMaxD; ++d) ysym = (d == c16) ? g.y_sym[d] : ysym;
+
+  for (long long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const long long bi = blk / nblk_batch;
+    const int k0 = (int)(blk - bi * nblk_batch) * kSPW;
+    __syncthreads();
+
+    // ---- phase A: Gram and matched filter of each subcarrier on MFMA
+#pragma unroll 1
+    for (int sc = 0; sc < kSPW; ++sc) {
+      const int k = k0 + sc;
+      f32x4 gr = {0.f, 0.f, 0.f, 0.f}, gi = gr, pr = gr, pi = gr;
+      if (k < nsc) {
+        cf h[KS], y[KS];
+        if (FUSED) {
+          // this lane's fragment of H (UE c16, its beams), interpolated from
+          // the LS values the beamforming epilogue left in the pilot symbols
+          if (c16 < nue) {
+            const cf* LSb = Y + bi * cg.y_batch;
+            const CombBracket cb = comb_bracket(k, c16, nue, cg.n_pilot, nsc);
+#pragma unroll
+            for (int s = 0; s < KS; s += 2) {
+              const int b = frag_beam(s, q);
+              cf lo[2] = {cf{0.f, 0.f}, cf{0.f, 0.f}}, hi[2];
+              if (b + 1 < nb) {
+                merged_at<2>(lo, LSb, cg.y_pilot, cb.mlo, cb.lo, b, nb);
+                if (cb.hi != cb.lo) {
+                  merged_at<2>(hi, LSb, cg.y_pilot, cb.mhi, cb.hi, b, nb);
+                  lerp<2>(lo, hi, cb.w);
+                }
+              } else if (b < nb) {
+                cf l1[1], h1[1];
+                merged_at<1>(l1, LSb, cg.y_pilot, cb.mlo, cb.lo, b, nb);
+                if (cb.hi != cb.lo) {
+                  merged_at<1>(h1, LSb, cg.y_pilot, cb.mhi, cb.hi, b, nb);
+                  lerp<1>(l1, h1, cb.w);
+                }
+                lo[0] = l1[0];
+              }
+              h[s] = lo[0];
+              h[s + 1] = lo[1];
+            }
+          } else {
+#pragma unroll
+            for (int s = 0; s < KS; ++s) h[s] = cf{0.f, 0.f};
+          }
+        } else {
+          const cf* hrow = H + bi * g.h_batch + ((long long)k * nue + (c16 < nue ? c16 : 0)) * nb;
+#pragma unroll
+          for (int s = 0; s < KS; s += 2) load_pair(h[s], h[s + 1], hrow, frag_beam(s, q), nb, c16 < nue, vec);
+        }
+        const cf* yrow = Y + bi * g.y_batch + ysym + (long long)k * nb;
+#pragma unroll
+        for (int s = 0; s < KS; s += 2) load_pair(y[s], y[s + 1], yrow, frag_beam(s, q), nb, c16 < nd, vec);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const float hr = h[s].r, hi = h[s].i, nhi = -h[s].i;
+          gr = mfma(hr, hr, gr);
+          gr = mfma(hi, hi, gr);
+          gi = mfma(hr, hi, gi);
+          gi = mfma(nhi, hr, gi);
+          pr = mfma(hr, y[s].r, pr);
+          pr = mfma(hi, y[s].i, pr);
+          pi = mfma(hr, y[s].i, pi);
+          pi = mfma(nhi, y[s].r, pi);
+        }
+      }
+      // lane holds rows 4q..4q+3 of column c16; regularise the diagonal
+      // (padding rows beyond n_ue get 1 so their part of L is the identity)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * q + v;
+        float dr = gr[v];
+        if (i == c16) dr += (i < nue && k < nsc) ? g.sigma2 : 1.0f;
+        Gs[sc * kMat + i * kRow + c16] = cf{dr, gi[v]};
+        Ps[sc * kMat + i * kRow + c16] = cf{pr[v], pi[v]};
+      }
+    }
+    __syncthreads();
+
+    // ---- phase B: Crout factorisation, lane (q, c16) holds row c16 of subcarrier q
+    const int grp = q, i = c16, gbase = grp * 16;
+    cf* Gm = Gs + grp * kMat;
+    cf L[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) L[j] = Gm[i * kRow + j];
+    int fail = 0;
+    float invd = 0.f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      if (j >= nue) continue;  // padded columns: rows beyond n_ue are the identity
+      const int src = (gbase + j) << 2;
+      cf t = L[j];
+#pragma unroll
+      for (int m = 0; m < j; ++m) {
+        const cf c = cf{lane_bcast(L[m].r, src), lane_bcast(L[m].i, src)};
+        csub_mul(t, L[m], cf{c.r, -c.i});  // t -= L_im * conj(L_jm)
+      }
+      const float dpiv = lane_bcast(t.r, src);
+      fail |= (dpiv > 0.f && dpiv <= 3.402823466e38f) ? 0 : 1;
+      const float inv = rsqrtf(dpiv);  // 1 / L_jj
+      const cf lij = cf{t.r * inv, t.i * inv};
+      L[j] = i == j ? cf{dpiv * inv, 0.f} : (i > j ? lij : cf{0.f, 0.f});
+      invd = i == j ? inv : invd;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) Gm[i * kRow + j] = L[j];
+    Dinv[grp * kDinv + i] = invd;
+    __syncthreads();
+
+    // ---- phase C: forward and back substitution, lane (q, c16) solves data symbol c16
+    const int d = c16;
+    const float* dv = Dinv + grp * kDinv;
+    cf z[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) z[r] = Ps[grp * kMat + r * kRow + d];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {  // L z = b
+      if (r >= nue) continue;
+#pragma unroll
+      for (int m = 0; m < r; ++m) csub_mul(z[r], Gm[r * kRow + m], z[m]);
+      const float s = dv[r];
+      z[r] = cf{z[r].r * s, z[r].i * s};
+    }
+#pragma unroll
+    for (int r = 15; r >= 0; --r) {  // L^H x = z: x_r = (z_r - sum_{m>r} conj(L_mr) x_m) / L_rr
+      if (r >= nue) continue;
+#pragma unroll
+      for (int m = r + 1; m < 16; ++m)
+        if (m < nue) csub_conj_mul(z[r], Gm[m * kRow + r], z[m]);
+      const float s = dv[r];
+      z[r] = cf{z[r].r * s, z[r].i * s};
+    }
+    const int k = k0 + grp;
+    if (k < nsc) {
+      if (d < nd) {
+        cf* dst = Xh + bi * g.x_batch + ((long long)d * nsc + k) * nue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          if (r < nue) dst[r] = fail ? cf{0.f, 0.f} : z[r];
+      }
+      if (d == 0 && st) st[bi * g.st_batch + k] = fail;
+    }
+  }
+}
+
+template <int KS, bool FUSED>
+hipError_t launch_mfma(const cf* H, const cf* Y, const ChestGeom& cg, cf* Xh, int* st, const MmseGeom& g,
+                       long long batch, hipStream_t s) {
+  const int nblk_batch = (g.n_sc + kSPW - 1) / kSPW;
+  const long long nblk = batch * nblk_batch;
+  if (nblk <= 0) return hipSuccess;
+  const long long blocks = nblk < (1LL << 30) ? nblk : (1LL << 30);
+  hipLaunchKernelGGL((k_mmse_mfma<KS, FUSED>), dim3((unsigned)blocks), dim3(64), 0, s, H, Y, Xh, st, g, cg, nblk,
+                     nblk_batch);
+  return hipGetLastError();
+}
+
+template <bool FUSED>
+hipError_t dispatch_mfma(const cf* H, const cf* Y, const ChestGeom& cg, cf* Xh, int* st, const MmseGeom& g,
+                         long long batch, hipStream_t s) {
+  const int nb = g.n_beams;
+  if (nb <= 8) return launch_mfma<2, FUSED>(H, Y, cg, Xh, st, g, batch, s);
+  if (nb <= 16) return launch_mfma<4, FUSED>(H, Y, cg, Xh, st, g, batch, s);
+  if (nb <= 32) return launch_mfma<8, FUSED>(H, Y, cg, Xh, st, g, batch, s);
+  if (nb <= 64) return launch_mfma<16, FUSED>(H, Y, cg, Xh, st, g, batch, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool mmse_fusable(int n_ue) { return n_ue >= 1 && n_ue <= 16; }
+
 hipError_t launch_mmse(const cf* H, const cf* Y, cf* Xhat, int* status, const MmseGeom& g, long long batch,
                        hipStream_t s) {
-  if (g.n_data > kMaxD) return hipErrorInvalidValue;
-  if (g.n_ue <= 1) return launch_lps<1>(H, Y, Xhat, status, g, batch, s);
-  if (g.n_ue <= 2) return launch_lps<2>(H, Y, Xhat, status, g, batch, s);
-  if (g.n_ue <= 4) return launch_lps<4>(H, Y, Xhat, status, g, batch, s);
-  if (g.n_ue <= 8) return launch_lps<8>(H, Y, Xhat, status, g, batch, s);
-  if (g.n_ue <= 16) return launch_lps<16>(H, Y, Xhat, status, g, batch, s);
+  if (g.n_data > kMaxD || g.n_data < 1) return hipErrorInvalidValue;
+  if (g.n_ue <= 16) return dispatch_mfma<false>(H, Y, ChestGeom{}, Xhat, status, g, batch, s);
   if (g.n_ue <= 32) return launch_lps<32>(H, Y, Xhat, status, g, batch, s);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_mmse_fused(const cf* Y, const ChestGeom& cg, cf* Xhat, int* status, const MmseGeom& g,
+                             long long batch, hipStream_t s) {
+  if (g.n_data > kMaxD || g.n_data < 1 || !mmse_fusable(g.n_ue)) return hipErrorInvalidValue;
+  return dispatch_mfma<true>(nullptr, Y, cg, Xhat, status, g, batch, s);
 }
 
 }  // namespace pusch

@@ -309,7 +309,10 @@ def test_slot_equals_chained_stage_calls():
     H = pusch.chest(Yp, p, cfg.n_ue)
     Yd = Y[list(cfg.data_symb)].unsqueeze(0).contiguous()
     xh, st = pusch.mmse_solve(H, Yd, s["sigma2"])
-    assert torch.equal(xh, xh_slot) and torch.equal(st, st_slot)
+    # the slot estimates the channel inside the detection kernel; same arithmetic, so agreement is at the
+    # level of FP32 rounding (contraction of the interpolation may differ between the two kernels)
+    assert torch.equal(st, st_slot)
+    assert M.nrmse(host(xh), host(xh_slot)) <= 1e-6
 
 
 def test_slot_deterministic_and_profiled():
