@@ -30,24 +30,28 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 N_SLOT = 16
 SEEDS = list(range(2000, 2000 + N_SLOT))
 
-# Algorithmic bytes moved by each stage per slot of the workload (compulsory
-# inputs + outputs of that stage; complex64 = 8 B, status int32 = 4 B).
+# Algorithmic bytes moved by each kernel per slot of the workload (its
+# compulsory inputs + outputs; complex64 = 8 B, int32 status = 4 B).  With 16
+# UEs the channel estimate is fused: the beamforming epilogue divides the
+# pilot symbols by their pilots and the detection kernel interpolates the
+# estimate from them, so no channel estimate is stored or re-read.
 S, R, N, K, B, L, NP = 14, 64, 4096, 3300, 32, 16, 2
 D = S - NP
 STAGE_BYTES = {
     "fft": S * R * N * 8 + S * R * K * 8,
-    "beamform": S * R * K * 8 + B * R * 8 + S * K * B * 8,
-    "chest": NP * K * B * 8 + NP * K * 8 + K * L * B * 8,
-    "mmse": K * L * B * 8 + D * K * B * 8 + D * K * L * 8 + K * 4,
+    "beamform": S * R * K * 8 + B * R * 8 + NP * K * 8 + S * K * B * 8,
+    "mmse": NP * K * B * 8 + D * K * B * 8 + D * K * L * 8 + K * 4,
 }
-STAGE_KERNEL = {
-    "fft": "k_fft<4096>",
-    "beamform": "k_beamform<2>",
-    "chest": "k_chest",
-    "mmse": "k_mmse<16>",
+# Nominal arithmetic per slot (8 flops per complex MAC, 5 N log2 N per FFT).
+STAGE_FLOPS = {
+    "fft": S * R * 5 * N * 12,
+    "beamform": 8 * S * K * R * B,
+    "mmse": 8 * K * (B * L * L + L ** 3 // 6 + D * (B * L + L * L)),
 }
-STAGE_SOURCE = {"fft": "fft.hip", "beamform": "beamform.hip", "chest": "chest.hip", "mmse": "mmse.hip"}
-TRAFFIC_FILE = {"fft": "profiles/fft4096_paper_scale_traffic.md"}
+SLOT_FLOOR_BYTES = S * R * N * 8 + D * K * L * 8 + K * 4  # time-domain input + detected symbols
+STAGE_KERNEL = {"fft": "k_fft<4096>", "beamform": "k_beamform<2, true>", "mmse": "k_mmse_mfma<8, true>"}
+STAGE_SOURCE = {"fft": "fft.hip", "beamform": "beamform.hip", "mmse": "mmse.hip"}
+TRAFFIC_FILE = "profiles/hbm_traffic_paper_scale.md"
 
 
 def _source_sha(stage: str) -> str:
@@ -56,21 +60,22 @@ def _source_sha(stage: str) -> str:
 
 
 def _traffic(stage: str) -> float | None:
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; otherwise None."""
-    rel = TRAFFIC_FILE.get(stage)
-    if not rel or not os.path.exists(os.path.join(ROOT, rel)):
+    """HBM bytes per launch of the stage's kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
         return None
-    vals = {}
-    for line in open(os.path.join(ROOT, rel)):
-        if ":" in line and line.startswith("- "):
-            k, v = line[2:].split(":", 1)
-            vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel_source_sha256_16") != _source_sha(stage):
+    rows = {}
+    for line in open(path):
+        cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 4 and cells[0] in STAGE_KERNEL:
+            rows[cells[0]] = cells
+    row = rows.get(stage)
+    if not row or row[1] != _source_sha(stage):
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
+        return float(row[-1])
+    except ValueError:
         return None
 
 
@@ -96,6 +101,21 @@ def cpu_baseline(batch: dict, seconds: float) -> dict:
                       f"FP64 NumPy oracle, one thread, {dt:.1f} s"}
 
 
+def calibrate_copy() -> int:
+    """A plain device-to-device copy of 1 GiB, five times (for scaling HBM counters)."""
+    import torch
+
+    n = 1 << 30
+    src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": n, "copies": 5}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,7 +123,14 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--distinct-slots", type=int, default=N_SLOT,
+                    help="generate this many distinct slots and repeat them to fill the 16-slot launch "
+                         "(for profiler passes; kernel time and traffic do not depend on the values)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        return calibrate_copy()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); slots are independent, so a "
               f"multi-GPU run would split the slot batch with no communication -- see the design notes.",
@@ -118,8 +145,12 @@ def main() -> int:
         from paper_2210_09196_amd.build import build
         build()
     cfg = synth.CFG2
-    print(f"[bench] generating {N_SLOT} synthetic slots", file=sys.stderr, flush=True)
-    batch = synth.make_batch(cfg, SEEDS)
+    nd = max(1, min(N_SLOT, args.distinct_slots))
+    print(f"[bench] generating {nd} synthetic slots", file=sys.stderr, flush=True)
+    batch = synth.make_batch(cfg, SEEDS[:nd])
+    if nd < N_SLOT:
+        for key in ("x_td", "pilots"):
+            batch[key] = np.ascontiguousarray(np.resize(batch[key], (N_SLOT,) + batch[key].shape[1:]))
     dev = torch.device("cuda:0")
     x = torch.from_numpy(batch["x_td"]).to(dev)
     p = torch.from_numpy(batch["pilots"]).to(dev)
@@ -154,14 +185,16 @@ def main() -> int:
 
     us_slot = 1e3 * step_ms / N_SLOT
     stages = {}
-    for name, ms in stage_ms.items():
-        per_launch_s = ms / 1e3 / calls
+    for name in STAGE_KERNEL:
+        per_launch_s = stage_ms[name] / 1e3 / calls
         gbs = STAGE_BYTES[name] * N_SLOT / per_launch_s / 1e9
         stages[name] = {"kernel": STAGE_KERNEL[name], "us_per_launch": round(per_launch_s * 1e6, 2),
                         "us_per_slot": round(per_launch_s * 1e6 / N_SLOT, 3),
                         "alg_bytes_per_launch": STAGE_BYTES[name] * N_SLOT, "achieved_GBs": round(gbs, 1),
-                        "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
-    dom = max(stages, key=lambda k: stages[k]["us_per_launch"])
+                        "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "nominal_TFLOPs": round(STAGE_FLOPS[name] * N_SLOT / per_launch_s / 1e12, 2)}
+    stages["chest"] = {"fused_into": "mmse", "us_per_launch": round(stage_ms["chest"] / calls * 1e3, 2)}
+    dom = max(STAGE_KERNEL, key=lambda k: stages[k]["us_per_launch"])
     traffic = _traffic(dom)
     roofline = {"bound": "hbm", "achieved": stages[dom]["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": stages[dom]["hbm_frac"], "traffic": traffic, "kernel": stages[dom]["kernel"],
@@ -169,7 +202,7 @@ def main() -> int:
                 "us_per_launch": stages[dom]["us_per_launch"]}
     chain_bytes = sum(STAGE_BYTES.values()) * N_SLOT
     out = {
-        "metric": "PUSCH slots/s & us/slot, 64ant x 4096-FFT, FP32 chain",
+        "metric": "PUSCH slots/s & \u00b5s/slot, 64ant\u00d74096-FFT; FP32 vs mixed+batched, EVM gap \u22640.1dB",
         "value": round(N_SLOT / (ms_per_step / 1e3), 1),
         "unit": "slots/s",
         "n_gpus": 1,
@@ -189,6 +222,7 @@ def main() -> int:
                    "n_slot": N_SLOT, "n_ant": 64, "n_fft": 4096, "n_sc": 3300, "n_symb": 14, "n_beams": 32,
                    "n_ue": 16},
         "chain_hbm_frac": round(chain_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "slot_floor_frac": round(SLOT_FLOOR_BYTES * N_SLOT / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "stages": stages,
         "roofline": roofline,
         "cpu_baseline": None,

@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void k_chest(const cf* __restrict__ Y, const c
   const int k = r / nue;
   for (long long bi = blockIdx.y; bi < batch; bi += gridDim.y) {
     cf h[NBV];
-    ls_estimate<NBV>(h, Y + bi * g.y_batch, g.y_pilot, P + bi * g.p_batch, k, l, bc * NBV, nb, nue, g.n_pilot, nsc);
+    ls_estimate<NBV>(h, Y + bi * g.y_batch, g, P + bi * g.p_batch, k, l, bc * NBV);
     cf* dst = H + bi * g.h_batch + ((long long)k * nue + l) * nb + bc * NBV;
 #pragma unroll
     for (int e = 0; e < NBV; ++e) dst[e] = h[e];

@@ -21,6 +21,14 @@ __device__ __forceinline__ int pmod(int a, int m) {
   return r < 0 ? r + m : r;
 }
 
+// a mod m in [0, m) for |a| < 2^20, with inv_m = 1/m: a float quotient
+// corrected by one step (avoids the integer division sequence).
+__device__ __forceinline__ int fmod_pos(int a, int m, float inv_m) {
+  int r = a - (int)floorf((float)a * inv_m) * m;
+  r = r < 0 ? r + m : r;
+  return r >= m ? r - m : r;
+}
+
 // Hardware reciprocal (v_rcp_f32, within 1 ulp).
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -32,12 +40,13 @@ struct CombBracket {
 
 __device__ __forceinline__ CombBracket comb_bracket(int k, int l, int nue, int npil, int nsc) {
   const int step = nue / npil;
+  const float inv = fast_rcp((float)nue);
   int lo = -1, hi = 0x7fffffff;
   unsigned mlo = 0, mhi = 0;
   for (int j = 0; j < npil; ++j) {
-    const int rj = pmod(l - j * step, nue);
-    const int plo = k - pmod(k - rj, nue);
-    const int phi = k + pmod(rj - k, nue);
+    const int rj = fmod_pos(l - j * step, nue, inv);
+    const int plo = k - fmod_pos(k - rj, nue, inv);
+    const int phi = k + fmod_pos(rj - k, nue, inv);
     if (plo >= 0) {
       if (plo > lo) {
         lo = plo;
@@ -77,20 +86,28 @@ __device__ __forceinline__ float inv_count(unsigned mask) {
   return n == 1 ? 1.f : (n == 2 ? 0.5f : (n == 3 ? (1.f / 3.f) : 0.25f));
 }
 
+// Element offset of pilot symbol j's grid, j taken per lane (selects, not a
+// dynamically indexed kernel argument).
+__device__ __forceinline__ long long pilot_grid(const ChestGeom& g, int j) {
+  const int s = j == 0 ? g.pilot_sym[0] : (j == 1 ? g.pilot_sym[1] : (j == 2 ? g.pilot_sym[2] : g.pilot_sym[3]));
+  return (long long)s * g.y_sym;
+}
+
 // LS value at pilot subcarrier p for NBV consecutive beams b0.. of an
-// RE-major grid holding the received pilot symbols (y_pilot[j] = element
-// offset of pilot symbol j's grid), P = [n_pilot][n_sc] pilot values.
+// RE-major grid holding the received pilot symbols, P = [n_pilot][n_sc]
+// pilot values.
 template <int NBV>
-__device__ __forceinline__ void ls_at(cf (&out)[NBV], const cf* __restrict__ Y, const long long* y_pilot,
-                                      const cf* __restrict__ P, unsigned mask, int p, int b0, int nb, int nsc) {
+__device__ __forceinline__ void ls_at(cf (&out)[NBV], const cf* __restrict__ Y, const ChestGeom& g,
+                                      const cf* __restrict__ P, unsigned mask, int p, int b0) {
+  const int nb = g.n_beams, nsc = g.n_sc;
   float sr[NBV], si[NBV];
 #pragma unroll
   for (int e = 0; e < NBV; ++e) sr[e] = si[e] = 0.f;
   for (unsigned m = mask; m; m &= m - 1) {
     const int j = __ffs(m) - 1;
-    const cf pv = P[(long long)j * nsc + p];
+    const cf pv = P[j * nsc + p];
     const float inv = fast_rcp(pv.r * pv.r + pv.i * pv.i);
-    const cf* y = Y + y_pilot[j] + (long long)p * nb + b0;
+    const cf* y = Y + pilot_grid(g, j) + (p * nb + b0);
 #pragma unroll
     for (int e = 0; e < NBV; ++e) {
       const cf v = y[e];
@@ -106,14 +123,21 @@ __device__ __forceinline__ void ls_at(cf (&out)[NBV], const cf* __restrict__ Y, 
 // The same value from grids that already hold y * conj(p) / |p|^2 per RE
 // (the fused slot divides in the beamforming epilogue).
 template <int NBV>
-__device__ __forceinline__ void merged_at(cf (&out)[NBV], const cf* __restrict__ LS, const long long* off,
-                                          unsigned mask, int p, int b0, int nb) {
+__device__ __forceinline__ void merged_at(cf (&out)[NBV], const cf* __restrict__ LS, const ChestGeom& g,
+                                          unsigned mask, int p, int b0) {
+  const int nb = g.n_beams;
+  if ((mask & (mask - 1)) == 0) {  // one pilot symbol at p: no averaging
+    const cf* v = LS + pilot_grid(g, __ffs(mask) - 1) + (p * nb + b0);
+#pragma unroll
+    for (int e = 0; e < NBV; ++e) out[e] = v[e];
+    return;
+  }
   float sr[NBV], si[NBV];
 #pragma unroll
   for (int e = 0; e < NBV; ++e) sr[e] = si[e] = 0.f;
   for (unsigned m = mask; m; m &= m - 1) {
     const int j = __ffs(m) - 1;
-    const cf* v = LS + off[j] + (long long)p * nb + b0;
+    const cf* v = LS + pilot_grid(g, j) + (p * nb + b0);
 #pragma unroll
     for (int e = 0; e < NBV; ++e) {
       sr[e] += v[e].r;
@@ -134,14 +158,13 @@ __device__ __forceinline__ void lerp(cf (&lo)[NBV], const cf (&hi)[NBV], float w
 
 // Interpolated LS estimate at subcarrier k for NBV consecutive beams.
 template <int NBV>
-__device__ __forceinline__ void ls_estimate(cf (&out)[NBV], const cf* __restrict__ Y, const long long* y_pilot,
-                                            const cf* __restrict__ P, int k, int l, int b0, int nb, int nue,
-                                            int npil, int nsc) {
-  const CombBracket c = comb_bracket(k, l, nue, npil, nsc);
-  ls_at<NBV>(out, Y, y_pilot, P, c.mlo, c.lo, b0, nb, nsc);
+__device__ __forceinline__ void ls_estimate(cf (&out)[NBV], const cf* __restrict__ Y, const ChestGeom& g,
+                                            const cf* __restrict__ P, int k, int l, int b0) {
+  const CombBracket c = comb_bracket(k, l, g.n_ue, g.n_pilot, g.n_sc);
+  ls_at<NBV>(out, Y, g, P, c.mlo, c.lo, b0);
   if (c.hi != c.lo) {
     cf vhi[NBV];
-    ls_at<NBV>(vhi, Y, y_pilot, P, c.mhi, c.hi, b0, nb, nsc);
+    ls_at<NBV>(vhi, Y, g, P, c.mhi, c.hi, b0);
     lerp<NBV>(out, vhi, c.w);
   }
 }

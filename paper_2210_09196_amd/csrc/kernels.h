@@ -50,21 +50,25 @@ hipError_t launch_beamform(const cf* W, const cf* X, cf* Y, int n_beams, int n_a
 
 // ---------------------------------------------------------------- LS channel estimation
 struct ChestGeom {
-  long long y_batch;                // Y elements between batch items
-  long long y_pilot[kMaxPilots];    // offset of pilot symbol j's RE-major grid [n_sc][n_beams]
-  long long p_batch;                // pilots elements between batch items ([n_pilot][n_sc] each)
-  long long h_batch;                // H elements between batch items ([n_sc][n_ue][n_beams] each)
+  long long y_batch;              // Y elements between batch items
+  long long y_sym;                // Y elements between the RE-major symbol grids [n_sc][n_beams]
+  long long p_batch;              // pilots elements between batch items ([n_pilot][n_sc] each)
+  long long h_batch;              // H elements between batch items ([n_sc][n_ue][n_beams] each)
+  int pilot_sym[kMaxPilots];      // grid index of pilot symbol j (grid at pilot_sym[j] * y_sym)
   int n_beams, n_ue, n_sc, n_pilot;
 };
 hipError_t launch_chest(const cf* Y, const cf* pilots, cf* H, const ChestGeom& g, long long batch, hipStream_t s);
 
 // ---------------------------------------------------------------- MMSE detection
 struct MmseGeom {
-  long long h_batch;              // H elements between batch items
-  long long y_batch;              // Y elements between batch items
-  long long y_sym[kMaxSymbols];   // offset of data symbol d's RE-major grid [n_sc][n_beams]
-  long long x_batch;              // Xhat elements between batch items ([n_data][n_sc][n_ue] block)
-  long long st_batch;             // status elements between batch items
+  long long h_batch;          // H elements between batch items
+  long long y_batch;          // Y elements between batch items
+  long long y_sym;            // Y elements between the RE-major symbol grids [n_sc][n_beams]
+  long long x_batch;          // Xhat elements between batch items ([n_data][n_sc][n_ue] block)
+  long long st_batch;         // status elements between batch items
+  int d_first;                // grid index of the call's first data symbol before skipping
+  int n_skip;                 // grids that hold pilot symbols, ascending (skipped when
+  int skip[kMaxPilots];       //   counting data symbols)
   int n_beams, n_ue, n_sc, n_data;
   float sigma2;
 };

@@ -37,6 +37,16 @@ __device__ __forceinline__ float lane_bcast(float v, int src_byte) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(src_byte, __float_as_int(v)));
 }
 
+// Element offset of data symbol d's grid: the d-th grid from d_first that
+// is not one of the (ascending) skipped pilot grids.
+__device__ __forceinline__ long long data_grid(const MmseGeom& g, int d) {
+  int s = g.d_first + d;
+#pragma unroll
+  for (int j = 0; j < kMaxPilots; ++j)
+    if (j < g.n_skip && g.skip[j] <= s) ++s;
+  return (long long)s * g.y_sym;
+}
+
 struct LdsGeom {
   int hrow, hgrp;  // H rows (beams) and per-subcarrier stride, in cf
   int lrow, lgrp;  // L rows / per-subcarrier stride (aliases the H region)
@@ -110,7 +120,7 @@ __global__ __launch_bounds__(64) void k_mmse_rows(const cf* __restrict__ H, cons
       for (int dd = 0; dd < kDCh; ++dd) {
         const int d = c * kDCh + dd;
         if (d >= nd) break;
-        const cf* src = Y + bi * g.y_batch + g.y_sym[d] + (long long)k0 * nb;
+        const cf* src = Y + bi * g.y_batch + data_grid(g, d) + (long long)k0 * nb;
         const int n = cnt * nb;
         for (int e = lane; e < n; e += 64) Ys[dd * lg.ydd + (e / nb) * lg.yg + (e % nb)] = src[e];
       }
@@ -249,10 +259,38 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kSPW = 4;              // subcarriers per wavefront pass
 constexpr int kRow = 17;             // padded LDS row of a 16x16 matrix (cf)
 constexpr int kMat = 16 * kRow + 1;  // padded matrix stride: the 4 groups' broadcasts hit distinct banks
+constexpr int kTri = 16 * 17 / 2 + 1;  // packed lower triangle (row i at i(i+1)/2), odd stride
 constexpr int kDinv = 17;
+
+__device__ __forceinline__ int tri(int i) { return (i * (i + 1)) >> 1; }
 
 __device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Value of v in lane j of this lane's row of 16 (DPP row_newbcast; j must
+// fold to a constant after unrolling).
+__device__ __forceinline__ float row_bcast(float v, int j) {
+  int x = __float_as_int(v), r;
+  switch (j) {
+    case 0: r = __builtin_amdgcn_update_dpp(0, x, 0x150, 0xF, 0xF, false); break;
+    case 1: r = __builtin_amdgcn_update_dpp(0, x, 0x151, 0xF, 0xF, false); break;
+    case 2: r = __builtin_amdgcn_update_dpp(0, x, 0x152, 0xF, 0xF, false); break;
+    case 3: r = __builtin_amdgcn_update_dpp(0, x, 0x153, 0xF, 0xF, false); break;
+    case 4: r = __builtin_amdgcn_update_dpp(0, x, 0x154, 0xF, 0xF, false); break;
+    case 5: r = __builtin_amdgcn_update_dpp(0, x, 0x155, 0xF, 0xF, false); break;
+    case 6: r = __builtin_amdgcn_update_dpp(0, x, 0x156, 0xF, 0xF, false); break;
+    case 7: r = __builtin_amdgcn_update_dpp(0, x, 0x157, 0xF, 0xF, false); break;
+    case 8: r = __builtin_amdgcn_update_dpp(0, x, 0x158, 0xF, 0xF, false); break;
+    case 9: r = __builtin_amdgcn_update_dpp(0, x, 0x159, 0xF, 0xF, false); break;
+    case 10: r = __builtin_amdgcn_update_dpp(0, x, 0x15A, 0xF, 0xF, false); break;
+    case 11: r = __builtin_amdgcn_update_dpp(0, x, 0x15B, 0xF, 0xF, false); break;
+    case 12: r = __builtin_amdgcn_update_dpp(0, x, 0x15C, 0xF, 0xF, false); break;
+    case 13: r = __builtin_amdgcn_update_dpp(0, x, 0x15D, 0xF, 0xF, false); break;
+    case 14: r = __builtin_amdgcn_update_dpp(0, x, 0x15E, 0xF, 0xF, false); break;
+    default: r = __builtin_amdgcn_update_dpp(0, x, 0x15F, 0xF, 0xF, false); break;
+  }
+  return __int_as_float(r);
 }
 
 // acc -= a * b and acc -= conj(a) * b, as explicit FMAs
@@ -288,8 +326,8 @@ __device__ __forceinline__ void load_pair(cf& v0, cf& v1, const cf* __restrict__
 template <int KS, bool FUSED>
 __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, const cf* __restrict__ Y,
                                                   cf* __restrict__ Xh, int* __restrict__ st, MmseGeom g,
-                                                  ChestGeom cg, long long nblk, int nblk_batch) {
-  __shared__ cf Gs[kSPW * kMat];  // G, then L in place
+                                                  ChestGeom cg, int nblk_batch) {
+  __shared__ cf Gs[kSPW * kTri];  // lower triangle of G, then of L in place
   __shared__ cf Ps[kSPW * kMat];  // P[i][d] = (H^H y_d)_i
   __shared__ float Dinv[kSPW * kDinv];
   const int lane = threadIdx.x;
@@ -297,14 +335,13 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
   const int nb = g.n_beams, nue = g.n_ue, nsc = g.n_sc, nd = g.n_data;
   const bool vec = (nb & 1) == 0;
   // offset of this lane's data symbol (B operand of the matched filter)
-  long long ysym = 0;
-#pragma unroll
-  for (int d = 0; d < kMaxD; ++d) ysym = (d == c16) ? g.y_sym[d] : ysym;
+  const long long ysym = data_grid(g, c16 < nd ? c16 : 0);
 
-  for (long long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const long long bi = blk / nblk_batch;
-    const int k0 = (int)(blk - bi * nblk_batch) * kSPW;
-    __syncthreads();
+  {
+    // one workgroup = one block of kSPW subcarriers (no enclosing loop, so no
+    // lane predicates are hoisted and kept alive across blocks)
+    const int bi = blockIdx.x / nblk_batch;
+    const int k0 = (blockIdx.x - bi * nblk_batch) * kSPW;
 
     // ---- phase A: Gram and matched filter of each subcarrier on MFMA
 #pragma unroll 1
@@ -324,16 +361,16 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
               const int b = frag_beam(s, q);
               cf lo[2] = {cf{0.f, 0.f}, cf{0.f, 0.f}}, hi[2];
               if (b + 1 < nb) {
-                merged_at<2>(lo, LSb, cg.y_pilot, cb.mlo, cb.lo, b, nb);
+                merged_at<2>(lo, LSb, cg, cb.mlo, cb.lo, b);
                 if (cb.hi != cb.lo) {
-                  merged_at<2>(hi, LSb, cg.y_pilot, cb.mhi, cb.hi, b, nb);
+                  merged_at<2>(hi, LSb, cg, cb.mhi, cb.hi, b);
                   lerp<2>(lo, hi, cb.w);
                 }
               } else if (b < nb) {
                 cf l1[1], h1[1];
-                merged_at<1>(l1, LSb, cg.y_pilot, cb.mlo, cb.lo, b, nb);
+                merged_at<1>(l1, LSb, cg, cb.mlo, cb.lo, b);
                 if (cb.hi != cb.lo) {
-                  merged_at<1>(h1, LSb, cg.y_pilot, cb.mhi, cb.hi, b, nb);
+                  merged_at<1>(h1, LSb, cg, cb.mhi, cb.hi, b);
                   lerp<1>(l1, h1, cb.w);
                 }
                 lo[0] = l1[0];
@@ -366,47 +403,52 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
           pi = mfma(nhi, y[s].r, pi);
         }
       }
-      // lane holds rows 4q..4q+3 of column c16; regularise the diagonal
-      // (padding rows beyond n_ue get 1 so their part of L is the identity)
+      // lane holds rows 4q..4q+3 of column c16 (G: lower triangle only)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = 4 * q + v;
-        float dr = gr[v];
-        if (i == c16) dr += (i < nue && k < nsc) ? g.sigma2 : 1.0f;
-        Gs[sc * kMat + i * kRow + c16] = cf{dr, gi[v]};
+        if (i >= c16) Gs[sc * kTri + tri(i) + c16] = cf{gr[v], gi[v]};
         Ps[sc * kMat + i * kRow + c16] = cf{pr[v], pi[v]};
       }
     }
     __syncthreads();
 
-    // ---- phase B: Crout factorisation, lane (q, c16) holds row c16 of subcarrier q
-    const int grp = q, i = c16, gbase = grp * 16;
-    cf* Gm = Gs + grp * kMat;
+    // ---- phase B: Crout factorisation, lane (q, c16) holds row c16 of
+    // subcarrier q; the 16 lanes of a subcarrier are one DPP row, so row j of
+    // L reaches every lane by a row broadcast
+    const int grp = q, i = c16;
+    cf* Gm = Gs + grp * kTri;
+    cf* Grow = Gm + tri(i);
+    // regularise the own diagonal entry (padding rows beyond n_ue get 1 so
+    // their part of L is the identity; so do the rows of a subcarrier past n_sc)
+    Grow[i].r += (i < nue && k0 + grp < nsc) ? g.sigma2 : 1.0f;
     cf L[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) L[j] = Gm[i * kRow + j];
+    for (int j = 0; j < 16; ++j) L[j] = j <= i ? Grow[j] : cf{0.f, 0.f};
+    // Only the strictly lower triangle of L and the reciprocals of its
+    // diagonal are used later, so every lane keeps t / L_jj in column j
+    // (entries at or above the diagonal are never read) and every lane of
+    // the group stores the same 1 / L_jj: no per-lane selects.
     int fail = 0;
-    float invd = 0.f;
+    float* dinv = Dinv + grp * kDinv;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       if (j >= nue) continue;  // padded columns: rows beyond n_ue are the identity
-      const int src = (gbase + j) << 2;
       cf t = L[j];
 #pragma unroll
       for (int m = 0; m < j; ++m) {
-        const cf c = cf{lane_bcast(L[m].r, src), lane_bcast(L[m].i, src)};
+        const cf c = cf{row_bcast(L[m].r, j), row_bcast(L[m].i, j)};
         csub_mul(t, L[m], cf{c.r, -c.i});  // t -= L_im * conj(L_jm)
       }
-      const float dpiv = lane_bcast(t.r, src);
+      const float dpiv = row_bcast(t.r, j);
       fail |= (dpiv > 0.f && dpiv <= 3.402823466e38f) ? 0 : 1;
       const float inv = rsqrtf(dpiv);  // 1 / L_jj
-      const cf lij = cf{t.r * inv, t.i * inv};
-      L[j] = i == j ? cf{dpiv * inv, 0.f} : (i > j ? lij : cf{0.f, 0.f});
-      invd = i == j ? inv : invd;
+      L[j] = cf{t.r * inv, t.i * inv};
+      dinv[j] = inv;
     }
 #pragma unroll
-    for (int j = 0; j < 16; ++j) Gm[i * kRow + j] = L[j];
-    Dinv[grp * kDinv + i] = invd;
+    for (int j = 0; j < 16; ++j)
+      if (j <= i) Grow[j] = L[j];
     __syncthreads();
 
     // ---- phase C: forward and back substitution, lane (q, c16) solves data symbol c16
@@ -419,7 +461,7 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
     for (int r = 0; r < 16; ++r) {  // L z = b
       if (r >= nue) continue;
 #pragma unroll
-      for (int m = 0; m < r; ++m) csub_mul(z[r], Gm[r * kRow + m], z[m]);
+      for (int m = 0; m < r; ++m) csub_mul(z[r], Gm[tri(r) + m], z[m]);
       const float s = dv[r];
       z[r] = cf{z[r].r * s, z[r].i * s};
     }
@@ -428,7 +470,7 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
       if (r >= nue) continue;
 #pragma unroll
       for (int m = r + 1; m < 16; ++m)
-        if (m < nue) csub_conj_mul(z[r], Gm[m * kRow + r], z[m]);
+        if (m < nue) csub_conj_mul(z[r], Gm[tri(m) + r], z[m]);
       const float s = dv[r];
       z[r] = cf{z[r].r * s, z[r].i * s};
     }
@@ -451,9 +493,8 @@ hipError_t launch_mfma(const cf* H, const cf* Y, const ChestGeom& cg, cf* Xh, in
   const int nblk_batch = (g.n_sc + kSPW - 1) / kSPW;
   const long long nblk = batch * nblk_batch;
   if (nblk <= 0) return hipSuccess;
-  const long long blocks = nblk < (1LL << 30) ? nblk : (1LL << 30);
-  hipLaunchKernelGGL((k_mmse_mfma<KS, FUSED>), dim3((unsigned)blocks), dim3(64), 0, s, H, Y, Xh, st, g, cg, nblk,
-                     nblk_batch);
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_mmse_mfma<KS, FUSED>), dim3((unsigned)nblk), dim3(64), 0, s, H, Y, Xh, st, g, cg, nblk_batch);
   return hipGetLastError();
 }
 
