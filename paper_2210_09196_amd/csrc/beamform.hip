@@ -33,7 +33,30 @@ __device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <int MT, bool W_LDS>
+// X operand of K-step ks for this lane: antenna ks*4 + kq, columns nc and
+// nc+1.  load_x_raw reads from a clamped in-bounds address with no branch;
+// mask_x zeroes the out-of-range entries when the operand is consumed, so a
+// prefetched load has no consumer until the next chunk.  VEC: one 16-byte
+// load (even row pitch, batch stride and RE count).
+template <bool VEC>
+__device__ __forceinline__ int4 load_x_raw(const cf* __restrict__ Xb, long long ldx, int ks, int kq, int na, int nc,
+                                           int nre) {
+  const int a = ks * 4 + kq;
+  const cf* row = Xb + (long long)(a < na ? a : na - 1) * ldx;
+  if (VEC) return *reinterpret_cast<const int4*>(row + (nc < nre ? nc : nre - 2));
+  const int2 v0 = *reinterpret_cast<const int2*>(row + (nc < nre ? nc : nre - 1));
+  const int2 v1 = *reinterpret_cast<const int2*>(row + (nc + 1 < nre ? nc + 1 : nre - 1));
+  return make_int4(v0.x, v0.y, v1.x, v1.y);
+}
+
+__device__ __forceinline__ float4 mask_x(int4 v, int ks, int kq, int na, int nc, int nre) {
+  const bool ok = ks * 4 + kq < na;
+  const int m0 = -(int)(ok && nc < nre), m1 = -(int)(ok && nc + 1 < nre);
+  return make_float4(__int_as_float(v.x & m0), __int_as_float(v.y & m0), __int_as_float(v.z & m1),
+                     __int_as_float(v.w & m1));
+}
+
+template <int MT, bool W_LDS, bool VEC>
 __global__ __launch_bounds__(64 * kWaves) void k_beamform(const cf* __restrict__ W, const cf* __restrict__ X,
                                                           cf* __restrict__ Y, int nb, int na, int nre, long long ldx,
                                                           long long sx, long long sy, long long batch, long long ntn,
@@ -43,9 +66,10 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform(const cf* __restrict__
   const int col = lane & 15;  // A row / B column / D column inside a 16x16 tile
   const int kq = lane >> 4;   // A column / B row (antenna within the step of 4)
   const int ksteps = (na + 3) >> 2;
+  const int kspad = (ksteps + 3) & ~3;  // whole chunks of 4 steps
 
   if (W_LDS) {
-    for (int e = threadIdx.x; e < ksteps * MT * 64; e += blockDim.x) {
+    for (int e = threadIdx.x; e < kspad * MT * 64; e += blockDim.x) {
       const int l = e & 63, m = (e >> 6) % MT, ks = (e >> 6) / MT;
       const int b = m * 16 + (l & 15), a = ks * 4 + (l >> 4);
       const cf w = (a < na && b < nb) ? W[b * na + a] : cf{0.f, 0.f};
@@ -55,7 +79,6 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform(const cf* __restrict__
   }
 
   const long long nwave = (long long)gridDim.x * kWaves;
-  const bool vec = ((ldx | sx) & 1) == 0;  // 16-byte aligned column pairs
   for (long long tile = (long long)blockIdx.x * kWaves + (threadIdx.x >> 6); tile < batch * ntn; tile += nwave) {
     const long long bi = tile / ntn;
     const int n0 = (int)(tile - bi * ntn) * kTileN;
@@ -67,38 +90,54 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform(const cf* __restrict__
 #pragma unroll
       for (int t = 0; t < 2; ++t) t1[m][t] = t2[m][t] = t3[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int ks = 0; ks < ksteps; ++ks) {
-      const int a = ks * 4 + kq;
-      cf x0 = cf{0.f, 0.f}, x1 = cf{0.f, 0.f};
-      if (a < na) {
-        const cf* p = Xb + (long long)a * ldx + nc;
-        if (vec && nc + 1 < nre) {
-          const float4 v = *reinterpret_cast<const float4*>(p);
-          x0 = cf{v.x, v.y};
-          x1 = cf{v.z, v.w};
-        } else {
-          if (nc < nre) x0 = p[0];
-          if (nc + 1 < nre) x1 = p[1];
-        }
-      }
-      const float s0 = x0.r + x0.i, s1 = x1.r + x1.i;
+    // K loop in chunks of 4 steps (16 antennas): the next chunk's loads are
+    // issued before the current chunk's 48 MFMAs (double buffering)
+    constexpr int CH = 4;
+    int4 xa[CH], xb[CH];
+    // one chunk of CH K-steps: 12*MT MFMAs per step
+    auto chunk = [&](const int4 (&xr)[CH], int kc) {
 #pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        float4 w;
-        if (W_LDS) {
-          w = wl[(ks * MT + m) * 64 + lane];
-        } else {
-          const int b = m * 16 + col;
-          const cf c = (a < na && b < nb) ? W[b * na + a] : cf{0.f, 0.f};
-          w = make_float4(c.r, c.i, c.r + c.i, 0.f);
+      for (int u = 0; u < CH; ++u) {
+        const int ks = kc + u;
+        const float4 xv = mask_x(xr[u], ks, kq, na, nc, nre);
+        const cf x0 = cf{xv.x, xv.y}, x1 = cf{xv.z, xv.w};
+        const float s0 = x0.r + x0.i, s1 = x1.r + x1.i;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          float4 w;
+          if (W_LDS) {
+            w = wl[(ks * MT + m) * 64 + lane];
+          } else {
+            const int b = m * 16 + col, a = ks * 4 + kq;
+            const cf c = (a < na && b < nb) ? W[b * na + a] : cf{0.f, 0.f};
+            w = make_float4(c.r, c.i, c.r + c.i, 0.f);
+          }
+          t1[m][0] = mfma(w.x, x0.r, t1[m][0]);
+          t2[m][0] = mfma(w.y, x0.i, t2[m][0]);
+          t3[m][0] = mfma(w.z, s0, t3[m][0]);
+          t1[m][1] = mfma(w.x, x1.r, t1[m][1]);
+          t2[m][1] = mfma(w.y, x1.i, t2[m][1]);
+          t3[m][1] = mfma(w.z, s1, t3[m][1]);
         }
-        t1[m][0] = mfma(w.x, x0.r, t1[m][0]);
-        t2[m][0] = mfma(w.y, x0.i, t2[m][0]);
-        t3[m][0] = mfma(w.z, s0, t3[m][0]);
-        t1[m][1] = mfma(w.x, x1.r, t1[m][1]);
-        t2[m][1] = mfma(w.y, x1.i, t2[m][1]);
-        t3[m][1] = mfma(w.z, s1, t3[m][1]);
       }
+    };
+    // ping-pong double buffering: the next chunk's loads are issued before
+    // the current chunk's MFMAs and are never copied while in flight (the
+    // last prefetches re-read a clamped step and are dropped)
+    const int klast = (ksteps - 1) & ~(CH - 1);  // first step of the last chunk
+#pragma unroll
+    for (int u = 0; u < CH; ++u) xa[u] = load_x_raw<VEC>(Xb, ldx, u, kq, na, nc, nre);
+    for (int kc = 0; kc < ksteps; kc += 2 * CH) {
+      const int k1 = kc + CH <= klast ? kc + CH : klast;
+#pragma unroll
+      for (int u = 0; u < CH; ++u) xb[u] = load_x_raw<VEC>(Xb, ldx, k1 + u, kq, na, nc, nre);
+      __builtin_amdgcn_sched_barrier(0);
+      chunk(xa, kc);
+      const int k2 = kc + 2 * CH <= klast ? kc + 2 * CH : klast;
+#pragma unroll
+      for (int u = 0; u < CH; ++u) xa[u] = load_x_raw<VEC>(Xb, ldx, k2 + u, kq, na, nc, nre);
+      __builtin_amdgcn_sched_barrier(0);
+      if (kc + CH < ksteps) chunk(xb, kc + CH);
     }
 
     // optional LS epilogue for pilot symbols
@@ -152,17 +191,25 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform(const cf* __restrict__
 
 constexpr size_t kWLdsMax = 64 * 1024;
 
+template <int MT, bool VEC>
+hipError_t launch_mtv(const cf* W, const cf* X, cf* Y, int nb, int na, int nre, long long ldx, long long sx,
+                      long long sy, long long batch, long long ntn, const PilotScale& ps, dim3 grid, hipStream_t s) {
+  const size_t lds = (size_t)((((na + 3) / 4) + 3) & ~3) * MT * 64 * sizeof(float4);
+  if (lds <= kWLdsMax)
+    hipLaunchKernelGGL((k_beamform<MT, true, VEC>), grid, dim3(64 * kWaves), lds, s, W, X, Y, nb, na, nre, ldx, sx,
+                       sy, batch, ntn, ps);
+  else
+    hipLaunchKernelGGL((k_beamform<MT, false, VEC>), grid, dim3(64 * kWaves), 0, s, W, X, Y, nb, na, nre, ldx, sx,
+                       sy, batch, ntn, ps);
+  return hipGetLastError();
+}
+
 template <int MT>
 hipError_t launch_mt(const cf* W, const cf* X, cf* Y, int nb, int na, int nre, long long ldx, long long sx,
                      long long sy, long long batch, long long ntn, const PilotScale& ps, dim3 grid, hipStream_t s) {
-  const size_t lds = (size_t)((na + 3) / 4) * MT * 64 * sizeof(float4);
-  if (lds <= kWLdsMax)
-    hipLaunchKernelGGL((k_beamform<MT, true>), grid, dim3(64 * kWaves), lds, s, W, X, Y, nb, na, nre, ldx, sx, sy,
-                       batch, ntn, ps);
-  else
-    hipLaunchKernelGGL((k_beamform<MT, false>), grid, dim3(64 * kWaves), 0, s, W, X, Y, nb, na, nre, ldx, sx, sy,
-                       batch, ntn, ps);
-  return hipGetLastError();
+  const bool vec = ((ldx | sx | nre) & 1) == 0 && nre >= 2;
+  return vec ? launch_mtv<MT, true>(W, X, Y, nb, na, nre, ldx, sx, sy, batch, ntn, ps, grid, s)
+             : launch_mtv<MT, false>(W, X, Y, nb, na, nre, ldx, sx, sy, batch, ntn, ps, grid, s);
 }
 
 }  // namespace
