@@ -226,7 +226,7 @@ int pusch_mmse_solve(const pusch_c32* H, const pusch_c32* Yd, float sigma2, pusc
 namespace {
 
 struct SlotLayout {
-  size_t off_xa, off_y, off_h, total;
+  size_t off_xa, off_y, off_h, off_comb, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -264,7 +264,9 @@ SlotLayout slot_layout(const pusch_slot_desc* d, long long n_slot) {
   lay.off_h = lay.off_y + align256(n * S * K * B * 8);
   // with n_ue <= 16 the detection kernel estimates the channel itself and no
   // stored estimate is needed
-  lay.total = lay.off_h + (pusch::mmse_fusable(d->n_ue) ? 0 : align256(n * K * L * B * 8));
+  lay.off_comb = lay.off_h + (pusch::mmse_fusable(d->n_ue) ? 0 : align256(n * K * L * B * 8));
+  // comb interpolation brackets (fused path), one table for all slots
+  lay.total = lay.off_comb + (pusch::mmse_fusable(d->n_ue) ? align256(K * L * 16) : 0);
   return lay;
 }
 
@@ -365,8 +367,10 @@ int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td
   for (int j = 0; j < P; ++j) mg.skip[j] = d->pilot_symb[j];
   mg.x_batch = (long long)D * K * L;
   mg.st_batch = K;
+  int4* comb = reinterpret_cast<int4*>(base + lay.off_comb);
+  if (fused && pusch::launch_comb_table(comb, K, L, P, s) != hipSuccess) return PUSCH_EHIP;
   const hipError_t me =
-      fused ? pusch::launch_mmse_fused(Y, cg, reinterpret_cast<cf*>(x_hat), status, mg, n_slot, s)
+      fused ? pusch::launch_mmse_fused(Y, comb, cg, reinterpret_cast<cf*>(x_hat), status, mg, n_slot, s)
             : pusch::launch_mmse(H, Y, reinterpret_cast<cf*>(x_hat), status, mg, n_slot, s);
   if (me != hipSuccess) return PUSCH_EHIP;
   if (!mark(4)) return PUSCH_EHIP;

@@ -35,7 +35,22 @@ __global__ __launch_bounds__(256) void k_chest(const cf* __restrict__ Y, const c
   }
 }
 
+__global__ __launch_bounds__(256) void k_comb_table(int4* __restrict__ tab, int nsc, int nue, int npil) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nsc * nue) return;
+  const int l = idx % nue, k = idx / nue;
+  const CombBracket c = comb_bracket(k, l, nue, npil, nsc);
+  tab[idx] = make_int4(c.lo, c.hi, (int)(c.mlo | (c.mhi << 8)), __float_as_int(c.w));
+}
+
 }  // namespace
+
+hipError_t launch_comb_table(int4* tab, int n_sc, int n_ue, int n_pilot, hipStream_t s) {
+  const int n = n_sc * n_ue;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_comb_table, dim3((n + 255) / 256), dim3(256), 0, s, tab, n_sc, n_ue, n_pilot);
+  return hipGetLastError();
+}
 
 hipError_t launch_chest(const cf* Y, const cf* pilots, cf* H, const ChestGeom& g, long long batch, hipStream_t s) {
   if (batch <= 0 || g.n_sc <= 0) return hipSuccess;

@@ -58,6 +58,10 @@ struct ChestGeom {
   int n_beams, n_ue, n_sc, n_pilot;
 };
 hipError_t launch_chest(const cf* Y, const cf* pilots, cf* H, const ChestGeom& g, long long batch, hipStream_t s);
+// Comb-pilot interpolation brackets of every (subcarrier k, UE l), the same
+// for every slot of a geometry: tab[k * n_ue + l] = {lo, hi, mlo | mhi << 8,
+// bits of w} (nearest pilot positions, pilot-symbol masks, weight of hi).
+hipError_t launch_comb_table(int4* tab, int n_sc, int n_ue, int n_pilot, hipStream_t s);
 
 // ---------------------------------------------------------------- MMSE detection
 struct MmseGeom {
@@ -76,10 +80,11 @@ hipError_t launch_mmse(const cf* H, const cf* Y, cf* Xhat, int* status, const Mm
                        hipStream_t s);
 // Same detection, with the channel interpolated on the fly from pilot
 // symbols of Y that already hold LS values y*conj(p)/|p|^2 (PilotScale
-// epilogue; grid offsets in cg as for launch_chest) instead of read from a
-// stored estimate.  Requires mmse_fusable(n_ue).
+// epilogue; grid offsets in cg as for launch_chest), using the brackets of
+// launch_comb_table, instead of read from a stored estimate.  Requires
+// mmse_fusable(n_ue).
 bool mmse_fusable(int n_ue);
-hipError_t launch_mmse_fused(const cf* Y, const ChestGeom& cg, cf* Xhat, int* status, const MmseGeom& g,
-                             long long batch, hipStream_t s);
+hipError_t launch_mmse_fused(const cf* Y, const int4* comb, const ChestGeom& cg, cf* Xhat, int* status,
+                             const MmseGeom& g, long long batch, hipStream_t s);
 
 }  // namespace pusch

@@ -325,8 +325,8 @@ __device__ __forceinline__ void load_pair(cf& v0, cf& v1, const cf* __restrict__
 
 template <int KS, bool FUSED>
 __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, const cf* __restrict__ Y,
-                                                  cf* __restrict__ Xh, int* __restrict__ st, MmseGeom g,
-                                                  ChestGeom cg, int nblk_batch) {
+                                                  const int4* __restrict__ comb, cf* __restrict__ Xh,
+                                                  int* __restrict__ st, MmseGeom g, ChestGeom cg, int nblk_batch) {
   __shared__ cf Gs[kSPW * kTri];  // lower triangle of G, then of L in place
   __shared__ cf Ps[kSPW * kMat];  // P[i][d] = (H^H y_d)_i
   __shared__ float Dinv[kSPW * kDinv];
@@ -355,7 +355,13 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
           // the LS values the beamforming epilogue left in the pilot symbols
           if (c16 < nue) {
             const cf* LSb = Y + bi * cg.y_batch;
-            const CombBracket cb = comb_bracket(k, c16, nue, cg.n_pilot, nsc);
+            const int4 e = comb[k * nue + c16];
+            CombBracket cb;
+            cb.lo = e.x;
+            cb.hi = e.y;
+            cb.mlo = (unsigned)e.z & 0xffu;
+            cb.mhi = (unsigned)e.z >> 8;
+            cb.w = __int_as_float(e.w);
 #pragma unroll
             for (int s = 0; s < KS; s += 2) {
               const int b = frag_beam(s, q);
@@ -432,8 +438,7 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
     int fail = 0;
     float* dinv = Dinv + grp * kDinv;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      if (j >= nue) continue;  // padded columns: rows beyond n_ue are the identity
+    for (int j = 0; j < 16; ++j) {  // padded rows / columns beyond n_ue stay the identity
       cf t = L[j];
 #pragma unroll
       for (int m = 0; m < j; ++m) {
@@ -458,7 +463,7 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
 #pragma unroll
     for (int r = 0; r < 16; ++r) z[r] = Ps[grp * kMat + r * kRow + d];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {  // L z = b
+    for (int r = 0; r < 16; ++r) {  // L z = b, row by row
       if (r >= nue) continue;
 #pragma unroll
       for (int m = 0; m < r; ++m) csub_mul(z[r], Gm[tri(r) + m], z[m]);
@@ -466,13 +471,12 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
       z[r] = cf{z[r].r * s, z[r].i * s};
     }
 #pragma unroll
-    for (int r = 15; r >= 0; --r) {  // L^H x = z: x_r = (z_r - sum_{m>r} conj(L_mr) x_m) / L_rr
-      if (r >= nue) continue;
+    for (int m = 15; m >= 0; --m) {  // L^H x = z, column by column: x_m is final, remove it from rows r < m
+      if (m >= nue) continue;
+      const float s = dv[m];
+      z[m] = cf{z[m].r * s, z[m].i * s};
 #pragma unroll
-      for (int m = r + 1; m < 16; ++m)
-        if (m < nue) csub_conj_mul(z[r], Gm[tri(m) + r], z[m]);
-      const float s = dv[r];
-      z[r] = cf{z[r].r * s, z[r].i * s};
+      for (int r = 0; r < m; ++r) csub_conj_mul(z[r], Gm[tri(m) + r], z[m]);  // z_r -= conj(L_mr) x_m
     }
     const int k = k0 + grp;
     if (k < nsc) {
@@ -488,24 +492,25 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
 }
 
 template <int KS, bool FUSED>
-hipError_t launch_mfma(const cf* H, const cf* Y, const ChestGeom& cg, cf* Xh, int* st, const MmseGeom& g,
-                       long long batch, hipStream_t s) {
+hipError_t launch_mfma(const cf* H, const cf* Y, const int4* comb, const ChestGeom& cg, cf* Xh, int* st,
+                       const MmseGeom& g, long long batch, hipStream_t s) {
   const int nblk_batch = (g.n_sc + kSPW - 1) / kSPW;
   const long long nblk = batch * nblk_batch;
   if (nblk <= 0) return hipSuccess;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_mmse_mfma<KS, FUSED>), dim3((unsigned)nblk), dim3(64), 0, s, H, Y, Xh, st, g, cg, nblk_batch);
+  hipLaunchKernelGGL((k_mmse_mfma<KS, FUSED>), dim3((unsigned)nblk), dim3(64), 0, s, H, Y, comb, Xh, st, g, cg,
+                     nblk_batch);
   return hipGetLastError();
 }
 
 template <bool FUSED>
-hipError_t dispatch_mfma(const cf* H, const cf* Y, const ChestGeom& cg, cf* Xh, int* st, const MmseGeom& g,
-                         long long batch, hipStream_t s) {
+hipError_t dispatch_mfma(const cf* H, const cf* Y, const int4* comb, const ChestGeom& cg, cf* Xh, int* st,
+                         const MmseGeom& g, long long batch, hipStream_t s) {
   const int nb = g.n_beams;
-  if (nb <= 8) return launch_mfma<2, FUSED>(H, Y, cg, Xh, st, g, batch, s);
-  if (nb <= 16) return launch_mfma<4, FUSED>(H, Y, cg, Xh, st, g, batch, s);
-  if (nb <= 32) return launch_mfma<8, FUSED>(H, Y, cg, Xh, st, g, batch, s);
-  if (nb <= 64) return launch_mfma<16, FUSED>(H, Y, cg, Xh, st, g, batch, s);
+  if (nb <= 8) return launch_mfma<2, FUSED>(H, Y, comb, cg, Xh, st, g, batch, s);
+  if (nb <= 16) return launch_mfma<4, FUSED>(H, Y, comb, cg, Xh, st, g, batch, s);
+  if (nb <= 32) return launch_mfma<8, FUSED>(H, Y, comb, cg, Xh, st, g, batch, s);
+  if (nb <= 64) return launch_mfma<16, FUSED>(H, Y, comb, cg, Xh, st, g, batch, s);
   return hipErrorInvalidValue;
 }
 
@@ -516,15 +521,15 @@ bool mmse_fusable(int n_ue) { return n_ue >= 1 && n_ue <= 16; }
 hipError_t launch_mmse(const cf* H, const cf* Y, cf* Xhat, int* status, const MmseGeom& g, long long batch,
                        hipStream_t s) {
   if (g.n_data > kMaxD || g.n_data < 1) return hipErrorInvalidValue;
-  if (g.n_ue <= 16) return dispatch_mfma<false>(H, Y, ChestGeom{}, Xhat, status, g, batch, s);
+  if (g.n_ue <= 16) return dispatch_mfma<false>(H, Y, nullptr, ChestGeom{}, Xhat, status, g, batch, s);
   if (g.n_ue <= 32) return launch_lps<32>(H, Y, Xhat, status, g, batch, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_mmse_fused(const cf* Y, const ChestGeom& cg, cf* Xhat, int* status, const MmseGeom& g,
-                             long long batch, hipStream_t s) {
+hipError_t launch_mmse_fused(const cf* Y, const int4* comb, const ChestGeom& cg, cf* Xhat, int* status,
+                             const MmseGeom& g, long long batch, hipStream_t s) {
   if (g.n_data > kMaxD || g.n_data < 1 || !mmse_fusable(g.n_ue)) return hipErrorInvalidValue;
-  return dispatch_mfma<true>(nullptr, Y, cg, Xhat, status, g, batch, s);
+  return dispatch_mfma<true>(nullptr, Y, comb, cg, Xhat, status, g, batch, s);
 }
 
 }  // namespace pusch

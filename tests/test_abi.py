@@ -99,8 +99,9 @@ def test_slot_workspace_bytes(lib):
     y = n * 14 * 3300 * 32 * 8
     h = n * 3300 * 16 * 32 * 8
     a = lambda v: (v + 255) // 256 * 256
-    # 16 UEs: the channel is estimated inside the detection kernel, no stored estimate
-    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d), n) == a(xa) + a(y)
+    # 16 UEs: the channel is estimated inside the detection kernel, no stored
+    # estimate; a table of interpolation brackets (16 B per subcarrier and UE) instead
+    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d), n) == a(xa) + a(y) + a(3300 * 16 * 16)
     d32 = _desc(n_ue=32, n_beams=64)
     xa, y, h = n * 14 * 64 * 3300 * 8, n * 14 * 3300 * 64 * 8, n * 3300 * 32 * 64 * 8
     assert lib.pusch_slot_workspace_bytes(ctypes.byref(d32), n) == a(xa) + a(y) + a(h)
