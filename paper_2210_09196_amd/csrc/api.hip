@@ -262,11 +262,12 @@ SlotLayout slot_layout(const pusch_slot_desc* d, long long n_slot) {
   lay.off_xa = 0;
   lay.off_y = align256(n * S * R * K * 8);
   lay.off_h = lay.off_y + align256(n * S * K * B * 8);
-  // with n_ue <= 16 the detection kernel estimates the channel itself and no
-  // stored estimate is needed
-  lay.off_comb = lay.off_h + (pusch::mmse_fusable(d->n_ue) ? 0 : align256(n * K * L * B * 8));
-  // comb interpolation brackets (fused path), one table for all slots
-  lay.total = lay.off_comb + (pusch::mmse_fusable(d->n_ue) ? align256(K * L * 16) : 0);
+  // when the detection kernel estimates the channel itself (up to 16 UEs, an
+  // even number of beams) no stored estimate is needed
+  const bool fused = pusch::mmse_fusable(d->n_ue, d->n_beams, (long long)d->n_symb * K * B);
+  lay.off_comb = lay.off_h + (fused ? 0 : align256(n * K * L * B * 8));
+  // channel interpolation taps (fused path), one table for all slots
+  lay.total = lay.off_comb + (fused ? align256(K * L * pusch::comb_taps(d->n_ue, d->n_pilot) * 8) : 0);
   return lay;
 }
 
@@ -315,15 +316,15 @@ int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td
   }
   auto mark = [&](int i) -> bool { return !ev || hipEventRecord(ev[i], s) == hipSuccess; };
 
-  // a1: OFDM demodulation of every antenna and symbol, active bins only
+  // OFDM demodulation (FFT) of every antenna and symbol, active bins only
   if (!mark(0)) return PUSCH_EHIP;
   if (pusch::launch_fft(reinterpret_cast<const cf*>(x_td), Xa, d->n_fft, n_slot * S * R, K, K / 2, t->twiddles,
                         t->n_cu, s) != hipSuccess)
     return PUSCH_EHIP;
-  // a2: beamforming of every symbol, RE-major output; when the detection
+  // beamforming of every symbol, RE-major output; when the detection
   // kernel estimates the channel itself, the pilot symbols leave this stage
-  // already divided by their pilots (the LS division of a3)
-  const bool fused = pusch::mmse_fusable(L);
+  // already divided by their pilots (the LS division of the channel estimate)
+  const bool fused = pusch::mmse_fusable(L, B, (long long)S * K * B);
   pusch::PilotScale psc{};
   if (fused) {
     psc.pilots = reinterpret_cast<const cf*>(d->pilots);
@@ -336,7 +337,7 @@ int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td
   if (pusch::launch_beamform(w, Xa, Y, B, R, K, K, (long long)R * K, (long long)K * B, n_slot * S, t->n_cu, s,
                              fused ? &psc : nullptr) != hipSuccess)
     return PUSCH_EHIP;
-  // a3: LS channel estimate from the pilot symbols
+  // LS channel estimate from the pilot symbols
   if (!mark(2)) return PUSCH_EHIP;
   pusch::ChestGeom cg{};
   cg.n_beams = B;
@@ -350,8 +351,8 @@ int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td
   cg.h_batch = (long long)K * L * B;
   if (!fused && pusch::launch_chest(Y, reinterpret_cast<const cf*>(d->pilots), H, cg, n_slot, s) != hipSuccess)
     return PUSCH_EHIP;
-  // a4-a6: Gram, Cholesky, matched filter and substitutions for the data
-  // symbols (with the a3 estimate computed inside when fused)
+  // MMSE detection: Gram, Cholesky, matched filter and substitutions for the data
+  // symbols (with the channel estimate computed inside when fused)
   if (!mark(3)) return PUSCH_EHIP;
   pusch::MmseGeom mg{};
   mg.n_beams = B;
@@ -367,10 +368,11 @@ int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td
   for (int j = 0; j < P; ++j) mg.skip[j] = d->pilot_symb[j];
   mg.x_batch = (long long)D * K * L;
   mg.st_batch = K;
-  int4* comb = reinterpret_cast<int4*>(base + lay.off_comb);
-  if (fused && pusch::launch_comb_table(comb, K, L, P, s) != hipSuccess) return PUSCH_EHIP;
+  int2* taps = reinterpret_cast<int2*>(base + lay.off_comb);
+  const int n_tap = pusch::comb_taps(L, P);
+  if (fused && pusch::launch_comb_taps(taps, cg, n_tap, s) != hipSuccess) return PUSCH_EHIP;
   const hipError_t me =
-      fused ? pusch::launch_mmse_fused(Y, comb, cg, reinterpret_cast<cf*>(x_hat), status, mg, n_slot, s)
+      fused ? pusch::launch_mmse_fused(Y, taps, n_tap, cg, reinterpret_cast<cf*>(x_hat), status, mg, n_slot, s)
             : pusch::launch_mmse(H, Y, reinterpret_cast<cf*>(x_hat), status, mg, n_slot, s);
   if (me != hipSuccess) return PUSCH_EHIP;
   if (!mark(4)) return PUSCH_EHIP;

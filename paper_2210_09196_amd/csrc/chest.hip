@@ -35,20 +35,45 @@ __global__ __launch_bounds__(256) void k_chest(const cf* __restrict__ Y, const c
   }
 }
 
-__global__ __launch_bounds__(256) void k_comb_table(int4* __restrict__ tab, int nsc, int nue, int npil) {
+__global__ __launch_bounds__(256) void k_comb_taps(int2* __restrict__ tab, ChestGeom g, int ntap) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nsc * nue) return;
-  const int l = idx % nue, k = idx / nue;
-  const CombBracket c = comb_bracket(k, l, nue, npil, nsc);
-  tab[idx] = make_int4(c.lo, c.hi, (int)(c.mlo | (c.mhi << 8)), __float_as_int(c.w));
+  if (idx >= g.n_sc * g.n_ue) return;
+  const int l = idx % g.n_ue, k = idx / g.n_ue;
+  const CombBracket c = comb_bracket(k, l, g.n_ue, g.n_pilot, g.n_sc);
+  // lo end: average over the pilot symbols in mlo, times (1 - w); hi end
+  // likewise with w (absent when the estimate is held, lo == hi)
+  const bool two = c.hi != c.lo;
+  const float wlo = (two ? 1.f - c.w : 1.f) * inv_count(c.mlo);
+  const float whi = c.w * inv_count(c.mhi);
+  int2* dst = tab + (long long)idx * ntap;
+  int t = 0, first = -1;
+  for (unsigned m = c.mlo; m; m &= m - 1) {
+    const int off = (int)pilot_grid(g, __ffs(m) - 1) + c.lo * g.n_beams;
+    first = first < 0 ? off : first;
+    dst[t++] = make_int2(off, __float_as_int(wlo));
+  }
+  if (two)
+    for (unsigned m = c.mhi; m; m &= m - 1)
+      dst[t++] = make_int2((int)pilot_grid(g, __ffs(m) - 1) + c.hi * g.n_beams, __float_as_int(whi));
+  for (; t < ntap; ++t) dst[t] = make_int2(first, 0);
 }
 
 }  // namespace
 
-hipError_t launch_comb_table(int4* tab, int n_sc, int n_ue, int n_pilot, hipStream_t s) {
-  const int n = n_sc * n_ue;
+int comb_taps(int n_ue, int n_pilot) {
+  // pilot symbols j, j' put UE l's pilot on the same subcarriers when
+  // (j - j') * step = 0 mod n_ue, step = n_ue / n_pilot: then a bracket end
+  // averages several of them
+  const int step = n_ue / n_pilot;
+  for (int j = 1; j < n_pilot; ++j)
+    if ((j * step) % n_ue == 0) return 2 * kMaxPilots;
+  return 2;
+}
+
+hipError_t launch_comb_taps(int2* tab, const ChestGeom& g, int n_tap, hipStream_t s) {
+  const int n = g.n_sc * g.n_ue;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_comb_table, dim3((n + 255) / 256), dim3(256), 0, s, tab, n_sc, n_ue, n_pilot);
+  hipLaunchKernelGGL(k_comb_taps, dim3((n + 255) / 256), dim3(256), 0, s, tab, g, n_tap);
   return hipGetLastError();
 }
 

@@ -58,10 +58,15 @@ struct ChestGeom {
   int n_beams, n_ue, n_sc, n_pilot;
 };
 hipError_t launch_chest(const cf* Y, const cf* pilots, cf* H, const ChestGeom& g, long long batch, hipStream_t s);
-// Comb-pilot interpolation brackets of every (subcarrier k, UE l), the same
-// for every slot of a geometry: tab[k * n_ue + l] = {lo, hi, mlo | mhi << 8,
-// bits of w} (nearest pilot positions, pilot-symbol masks, weight of hi).
-hipError_t launch_comb_table(int4* tab, int n_sc, int n_ue, int n_pilot, hipStream_t s);
+// Channel interpolation of the fused detection as taps: the estimate of UE l
+// at subcarrier k, beam b, is sum_t w_t * LS[off_t + b] over the n_tap taps
+// of (k, l), LS being one batch item of the RE-major grids that hold per-RE
+// LS values, off_t an element offset into it (pilot grid of the pilot symbol
+// plus position * n_beams).  tab[(k * n_ue + l) * n_tap + t] = {off_t, bits
+// of w_t}; unused taps repeat the first offset with weight 0.  The same for
+// every slot of a geometry.
+int comb_taps(int n_ue, int n_pilot);  // taps per (k, l) the geometry needs: 2 or 8
+hipError_t launch_comb_taps(int2* tab, const ChestGeom& g, int n_tap, hipStream_t s);
 
 // ---------------------------------------------------------------- MMSE detection
 struct MmseGeom {
@@ -80,11 +85,11 @@ hipError_t launch_mmse(const cf* H, const cf* Y, cf* Xhat, int* status, const Mm
                        hipStream_t s);
 // Same detection, with the channel interpolated on the fly from pilot
 // symbols of Y that already hold LS values y*conj(p)/|p|^2 (PilotScale
-// epilogue; grid offsets in cg as for launch_chest), using the brackets of
-// launch_comb_table, instead of read from a stored estimate.  Requires
-// mmse_fusable(n_ue).
-bool mmse_fusable(int n_ue);
-hipError_t launch_mmse_fused(const cf* Y, const int4* comb, const ChestGeom& cg, cf* Xhat, int* status,
+// epilogue; grid offsets in cg as for launch_chest), using the taps of
+// launch_comb_taps, instead of read from a stored estimate.  Requires
+// mmse_fusable(n_ue, n_beams, y_batch).
+bool mmse_fusable(int n_ue, int n_beams, long long y_batch);
+hipError_t launch_mmse_fused(const cf* Y, const int2* taps, int n_tap, const ChestGeom& cg, cf* Xhat, int* status,
                              const MmseGeom& g, long long batch, hipStream_t s);
 
 }  // namespace pusch

@@ -273,24 +273,49 @@ __device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
 __device__ __forceinline__ float row_bcast(float v, int j) {
   int x = __float_as_int(v), r;
   switch (j) {
-    case 0: r = __builtin_amdgcn_update_dpp(0, x, 0x150, 0xF, 0xF, false); break;
-    case 1: r = __builtin_amdgcn_update_dpp(0, x, 0x151, 0xF, 0xF, false); break;
-    case 2: r = __builtin_amdgcn_update_dpp(0, x, 0x152, 0xF, 0xF, false); break;
-    case 3: r = __builtin_amdgcn_update_dpp(0, x, 0x153, 0xF, 0xF, false); break;
-    case 4: r = __builtin_amdgcn_update_dpp(0, x, 0x154, 0xF, 0xF, false); break;
-    case 5: r = __builtin_amdgcn_update_dpp(0, x, 0x155, 0xF, 0xF, false); break;
-    case 6: r = __builtin_amdgcn_update_dpp(0, x, 0x156, 0xF, 0xF, false); break;
-    case 7: r = __builtin_amdgcn_update_dpp(0, x, 0x157, 0xF, 0xF, false); break;
-    case 8: r = __builtin_amdgcn_update_dpp(0, x, 0x158, 0xF, 0xF, false); break;
-    case 9: r = __builtin_amdgcn_update_dpp(0, x, 0x159, 0xF, 0xF, false); break;
-    case 10: r = __builtin_amdgcn_update_dpp(0, x, 0x15A, 0xF, 0xF, false); break;
-    case 11: r = __builtin_amdgcn_update_dpp(0, x, 0x15B, 0xF, 0xF, false); break;
-    case 12: r = __builtin_amdgcn_update_dpp(0, x, 0x15C, 0xF, 0xF, false); break;
-    case 13: r = __builtin_amdgcn_update_dpp(0, x, 0x15D, 0xF, 0xF, false); break;
-    case 14: r = __builtin_amdgcn_update_dpp(0, x, 0x15E, 0xF, 0xF, false); break;
-    default: r = __builtin_amdgcn_update_dpp(0, x, 0x15F, 0xF, 0xF, false); break;
+    case 0: r = __builtin_amdgcn_update_dpp(0, x, 0x150, 0xF, 0xF, true); break;
+    case 1: r = __builtin_amdgcn_update_dpp(0, x, 0x151, 0xF, 0xF, true); break;
+    case 2: r = __builtin_amdgcn_update_dpp(0, x, 0x152, 0xF, 0xF, true); break;
+    case 3: r = __builtin_amdgcn_update_dpp(0, x, 0x153, 0xF, 0xF, true); break;
+    case 4: r = __builtin_amdgcn_update_dpp(0, x, 0x154, 0xF, 0xF, true); break;
+    case 5: r = __builtin_amdgcn_update_dpp(0, x, 0x155, 0xF, 0xF, true); break;
+    case 6: r = __builtin_amdgcn_update_dpp(0, x, 0x156, 0xF, 0xF, true); break;
+    case 7: r = __builtin_amdgcn_update_dpp(0, x, 0x157, 0xF, 0xF, true); break;
+    case 8: r = __builtin_amdgcn_update_dpp(0, x, 0x158, 0xF, 0xF, true); break;
+    case 9: r = __builtin_amdgcn_update_dpp(0, x, 0x159, 0xF, 0xF, true); break;
+    case 10: r = __builtin_amdgcn_update_dpp(0, x, 0x15A, 0xF, 0xF, true); break;
+    case 11: r = __builtin_amdgcn_update_dpp(0, x, 0x15B, 0xF, 0xF, true); break;
+    case 12: r = __builtin_amdgcn_update_dpp(0, x, 0x15C, 0xF, 0xF, true); break;
+    case 13: r = __builtin_amdgcn_update_dpp(0, x, 0x15D, 0xF, 0xF, true); break;
+    case 14: r = __builtin_amdgcn_update_dpp(0, x, 0x15E, 0xF, 0xF, true); break;
+    default: r = __builtin_amdgcn_update_dpp(0, x, 0x15F, 0xF, 0xF, true); break;
   }
   return __int_as_float(r);
+}
+
+// Complex value of lane j of this lane's row of 16: one 64-bit DPP
+// broadcast (v_mov_b64 with row_newbcast; j must fold to a constant).
+__device__ __forceinline__ cf row_bcast_c(cf v, int j) {
+  long long x = (long long)(unsigned)__float_as_int(v.r) | ((long long)__float_as_int(v.i) << 32), r;
+  switch (j) {
+    case 0: r = __builtin_amdgcn_update_dpp(x, x, 0x150, 0xF, 0xF, true); break;
+    case 1: r = __builtin_amdgcn_update_dpp(x, x, 0x151, 0xF, 0xF, true); break;
+    case 2: r = __builtin_amdgcn_update_dpp(x, x, 0x152, 0xF, 0xF, true); break;
+    case 3: r = __builtin_amdgcn_update_dpp(x, x, 0x153, 0xF, 0xF, true); break;
+    case 4: r = __builtin_amdgcn_update_dpp(x, x, 0x154, 0xF, 0xF, true); break;
+    case 5: r = __builtin_amdgcn_update_dpp(x, x, 0x155, 0xF, 0xF, true); break;
+    case 6: r = __builtin_amdgcn_update_dpp(x, x, 0x156, 0xF, 0xF, true); break;
+    case 7: r = __builtin_amdgcn_update_dpp(x, x, 0x157, 0xF, 0xF, true); break;
+    case 8: r = __builtin_amdgcn_update_dpp(x, x, 0x158, 0xF, 0xF, true); break;
+    case 9: r = __builtin_amdgcn_update_dpp(x, x, 0x159, 0xF, 0xF, true); break;
+    case 10: r = __builtin_amdgcn_update_dpp(x, x, 0x15A, 0xF, 0xF, true); break;
+    case 11: r = __builtin_amdgcn_update_dpp(x, x, 0x15B, 0xF, 0xF, true); break;
+    case 12: r = __builtin_amdgcn_update_dpp(x, x, 0x15C, 0xF, 0xF, true); break;
+    case 13: r = __builtin_amdgcn_update_dpp(x, x, 0x15D, 0xF, 0xF, true); break;
+    case 14: r = __builtin_amdgcn_update_dpp(x, x, 0x15E, 0xF, 0xF, true); break;
+    default: r = __builtin_amdgcn_update_dpp(x, x, 0x15F, 0xF, 0xF, true); break;
+  }
+  return cf{__int_as_float((int)(r & 0xffffffffll)), __int_as_float((int)(r >> 32))};
 }
 
 // acc -= a * b and acc -= conj(a) * b, as explicit FMAs
@@ -323,9 +348,17 @@ __device__ __forceinline__ void load_pair(cf& v0, cf& v1, const cf* __restrict__
   }
 }
 
-template <int KS, bool FUSED>
+// Beams b, b+1 of an RE-major row with an even number of beams, one 16-byte
+// load; past the last beam the load reads beams 0, 1 instead (valid memory;
+// the caller discards or zeroes what it gets there).
+__device__ __forceinline__ float4 load_pair_even(const cf* __restrict__ row, int b, int nb) {
+  return *reinterpret_cast<const float4*>(row + (b < nb ? b : 0));
+}
+
+// FUSED: NT interpolation taps per (subcarrier, UE), 0 when H is read.
+template <int KS, bool FUSED, int NT>
 __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, const cf* __restrict__ Y,
-                                                  const int4* __restrict__ comb, cf* __restrict__ Xh,
+                                                  const int2* __restrict__ taps, cf* __restrict__ Xh,
                                                   int* __restrict__ st, MmseGeom g, ChestGeom cg, int nblk_batch) {
   __shared__ cf Gs[kSPW * kTri];  // lower triangle of G, then of L in place
   __shared__ cf Ps[kSPW * kMat];  // P[i][d] = (H^H y_d)_i
@@ -350,43 +383,37 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
       f32x4 gr = {0.f, 0.f, 0.f, 0.f}, gi = gr, pr = gr, pi = gr;
       if (k < nsc) {
         cf h[KS], y[KS];
-        if (FUSED) {
+        if constexpr (FUSED) {
           // this lane's fragment of H (UE c16, its beams), interpolated from
-          // the LS values the beamforming epilogue left in the pilot symbols
-          if (c16 < nue) {
-            const cf* LSb = Y + bi * cg.y_batch;
-            const int4 e = comb[k * nue + c16];
-            CombBracket cb;
-            cb.lo = e.x;
-            cb.hi = e.y;
-            cb.mlo = (unsigned)e.z & 0xffu;
-            cb.mhi = (unsigned)e.z >> 8;
-            cb.w = __int_as_float(e.w);
+          // the LS values the beamforming epilogue left in the pilot symbols;
+          // lanes past n_ue take UE 0's taps with weight 0 (zero rows of H)
+          const cf* LSb = Y + bi * cg.y_batch;
+          const int4* tp = reinterpret_cast<const int4*>(taps + ((long long)k * nue + (c16 < nue ? c16 : 0)) * NT);
+          int off[NT];
+          float w[NT];
 #pragma unroll
-            for (int s = 0; s < KS; s += 2) {
-              const int b = frag_beam(s, q);
-              cf lo[2] = {cf{0.f, 0.f}, cf{0.f, 0.f}}, hi[2];
-              if (b + 1 < nb) {
-                merged_at<2>(lo, LSb, cg, cb.mlo, cb.lo, b);
-                if (cb.hi != cb.lo) {
-                  merged_at<2>(hi, LSb, cg, cb.mhi, cb.hi, b);
-                  lerp<2>(lo, hi, cb.w);
-                }
-              } else if (b < nb) {
-                cf l1[1], h1[1];
-                merged_at<1>(l1, LSb, cg, cb.mlo, cb.lo, b);
-                if (cb.hi != cb.lo) {
-                  merged_at<1>(h1, LSb, cg, cb.mhi, cb.hi, b);
-                  lerp<1>(l1, h1, cb.w);
-                }
-                lo[0] = l1[0];
-              }
-              h[s] = lo[0];
-              h[s + 1] = lo[1];
+          for (int t = 0; t < NT; t += 2) {
+            const int4 e = tp[t / 2];
+            off[t] = e.x;
+            off[t + 1] = e.z;
+            w[t] = c16 < nue ? __int_as_float(e.y) : 0.f;
+            w[t + 1] = c16 < nue ? __int_as_float(e.w) : 0.f;
+          }
+#pragma unroll
+          for (int s = 0; s < KS; s += 2) {
+            const int b = frag_beam(s, q);
+            float4 a = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+              const float4 v = load_pair_even(LSb + off[t], b, nb);
+              a.x = __builtin_fmaf(w[t], v.x, a.x);
+              a.y = __builtin_fmaf(w[t], v.y, a.y);
+              a.z = __builtin_fmaf(w[t], v.z, a.z);
+              a.w = __builtin_fmaf(w[t], v.w, a.w);
             }
-          } else {
-#pragma unroll
-            for (int s = 0; s < KS; ++s) h[s] = cf{0.f, 0.f};
+            const bool bv = b < nb;  // beams past n_beams: zero columns of H
+            h[s] = cf{bv ? a.x : 0.f, bv ? a.y : 0.f};
+            h[s + 1] = cf{bv ? a.z : 0.f, bv ? a.w : 0.f};
           }
         } else {
           const cf* hrow = H + bi * g.h_batch + ((long long)k * nue + (c16 < nue ? c16 : 0)) * nb;
@@ -394,8 +421,20 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
           for (int s = 0; s < KS; s += 2) load_pair(h[s], h[s + 1], hrow, frag_beam(s, q), nb, c16 < nue, vec);
         }
         const cf* yrow = Y + bi * g.y_batch + ysym + (long long)k * nb;
+        if constexpr (FUSED) {
+          // even n_beams: one 16-byte load per beam pair; columns of lanes
+          // past n_data only feed columns of P that are never read, and beams
+          // past n_beams meet zero columns of H
 #pragma unroll
-        for (int s = 0; s < KS; s += 2) load_pair(y[s], y[s + 1], yrow, frag_beam(s, q), nb, c16 < nd, vec);
+          for (int s = 0; s < KS; s += 2) {
+            const float4 v = load_pair_even(yrow, frag_beam(s, q), nb);
+            y[s] = cf{v.x, v.y};
+            y[s + 1] = cf{v.z, v.w};
+          }
+        } else {
+#pragma unroll
+          for (int s = 0; s < KS; s += 2) load_pair(y[s], y[s + 1], yrow, frag_beam(s, q), nb, c16 < nd, vec);
+        }
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
           const float hr = h[s].r, hi = h[s].i, nhi = -h[s].i;
@@ -439,12 +478,19 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
     float* dinv = Dinv + grp * kDinv;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {  // padded rows / columns beyond n_ue stay the identity
-      cf t = L[j];
+      // sum_m L_im conj(L_jm) as positive multiply-adds of broadcast values
+      // (each one can take the broadcast as its DPP operand), then t
+      float sr = 0.f, sp = 0.f, sm = 0.f;
 #pragma unroll
       for (int m = 0; m < j; ++m) {
-        const cf c = cf{row_bcast(L[m].r, j), row_bcast(L[m].i, j)};
-        csub_mul(t, L[m], cf{c.r, -c.i});  // t -= L_im * conj(L_jm)
+        const cf c = row_bcast_c(L[m], j);
+        const float cr = c.r, ci = c.i;
+        sr = __builtin_fmaf(cr, L[m].r, sr);
+        sr = __builtin_fmaf(ci, L[m].i, sr);
+        sp = __builtin_fmaf(cr, L[m].i, sp);
+        sm = __builtin_fmaf(ci, L[m].r, sm);
       }
+      const cf t = cf{L[j].r - sr, L[j].i - (sp - sm)};
       const float dpiv = row_bcast(t.r, j);
       fail |= (dpiv > 0.f && dpiv <= 3.402823466e38f) ? 0 : 1;
       const float inv = rsqrtf(dpiv);  // 1 / L_jj
@@ -491,45 +537,50 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
   }
 }
 
-template <int KS, bool FUSED>
-hipError_t launch_mfma(const cf* H, const cf* Y, const int4* comb, const ChestGeom& cg, cf* Xh, int* st,
+template <int KS, bool FUSED, int NT>
+hipError_t launch_mfma(const cf* H, const cf* Y, const int2* taps, const ChestGeom& cg, cf* Xh, int* st,
                        const MmseGeom& g, long long batch, hipStream_t s) {
   const int nblk_batch = (g.n_sc + kSPW - 1) / kSPW;
   const long long nblk = batch * nblk_batch;
   if (nblk <= 0) return hipSuccess;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_mmse_mfma<KS, FUSED>), dim3((unsigned)nblk), dim3(64), 0, s, H, Y, comb, Xh, st, g, cg,
+  hipLaunchKernelGGL((k_mmse_mfma<KS, FUSED, NT>), dim3((unsigned)nblk), dim3(64), 0, s, H, Y, taps, Xh, st, g, cg,
                      nblk_batch);
   return hipGetLastError();
 }
 
-template <bool FUSED>
-hipError_t dispatch_mfma(const cf* H, const cf* Y, const int4* comb, const ChestGeom& cg, cf* Xh, int* st,
+template <bool FUSED, int NT>
+hipError_t dispatch_mfma(const cf* H, const cf* Y, const int2* taps, const ChestGeom& cg, cf* Xh, int* st,
                          const MmseGeom& g, long long batch, hipStream_t s) {
   const int nb = g.n_beams;
-  if (nb <= 8) return launch_mfma<2, FUSED>(H, Y, comb, cg, Xh, st, g, batch, s);
-  if (nb <= 16) return launch_mfma<4, FUSED>(H, Y, comb, cg, Xh, st, g, batch, s);
-  if (nb <= 32) return launch_mfma<8, FUSED>(H, Y, comb, cg, Xh, st, g, batch, s);
-  if (nb <= 64) return launch_mfma<16, FUSED>(H, Y, comb, cg, Xh, st, g, batch, s);
+  if (nb <= 8) return launch_mfma<2, FUSED, NT>(H, Y, taps, cg, Xh, st, g, batch, s);
+  if (nb <= 16) return launch_mfma<4, FUSED, NT>(H, Y, taps, cg, Xh, st, g, batch, s);
+  if (nb <= 32) return launch_mfma<8, FUSED, NT>(H, Y, taps, cg, Xh, st, g, batch, s);
+  if (nb <= 64) return launch_mfma<16, FUSED, NT>(H, Y, taps, cg, Xh, st, g, batch, s);
   return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-bool mmse_fusable(int n_ue) { return n_ue >= 1 && n_ue <= 16; }
+bool mmse_fusable(int n_ue, int n_beams, long long y_batch) {
+  // MFMA tile of 16 UEs; paired 16-byte beam loads; 32-bit tap offsets
+  return n_ue >= 1 && n_ue <= 16 && n_beams >= 2 && n_beams <= 64 && n_beams % 2 == 0 && y_batch < (1ll << 31);
+}
 
 hipError_t launch_mmse(const cf* H, const cf* Y, cf* Xhat, int* status, const MmseGeom& g, long long batch,
                        hipStream_t s) {
   if (g.n_data > kMaxD || g.n_data < 1) return hipErrorInvalidValue;
-  if (g.n_ue <= 16) return dispatch_mfma<false>(H, Y, nullptr, ChestGeom{}, Xhat, status, g, batch, s);
+  if (g.n_ue <= 16) return dispatch_mfma<false, 0>(H, Y, nullptr, ChestGeom{}, Xhat, status, g, batch, s);
   if (g.n_ue <= 32) return launch_lps<32>(H, Y, Xhat, status, g, batch, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_mmse_fused(const cf* Y, const int4* comb, const ChestGeom& cg, cf* Xhat, int* status,
+hipError_t launch_mmse_fused(const cf* Y, const int2* taps, int n_tap, const ChestGeom& cg, cf* Xhat, int* status,
                              const MmseGeom& g, long long batch, hipStream_t s) {
-  if (g.n_data > kMaxD || g.n_data < 1 || !mmse_fusable(g.n_ue)) return hipErrorInvalidValue;
-  return dispatch_mfma<true>(nullptr, Y, comb, cg, Xhat, status, g, batch, s);
+  if (g.n_data > kMaxD || g.n_data < 1 || !mmse_fusable(g.n_ue, g.n_beams, cg.y_batch)) return hipErrorInvalidValue;
+  if (n_tap == 2) return dispatch_mfma<true, 2>(nullptr, Y, taps, cg, Xhat, status, g, batch, s);
+  if (n_tap == 2 * kMaxPilots) return dispatch_mfma<true, 2 * kMaxPilots>(nullptr, Y, taps, cg, Xhat, status, g, batch, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace pusch

@@ -100,11 +100,21 @@ def test_slot_workspace_bytes(lib):
     h = n * 3300 * 16 * 32 * 8
     a = lambda v: (v + 255) // 256 * 256
     # 16 UEs: the channel is estimated inside the detection kernel, no stored
-    # estimate; a table of interpolation brackets (16 B per subcarrier and UE) instead
-    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d), n) == a(xa) + a(y) + a(3300 * 16 * 16)
+    # estimate; a table of interpolation taps instead (two 8-byte taps per
+    # subcarrier and UE: no two pilot symbols share a UE's subcarriers)
+    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d), n) == a(xa) + a(y) + a(3300 * 16 * 2 * 8)
     d32 = _desc(n_ue=32, n_beams=64)
     xa, y, h = n * 14 * 64 * 3300 * 8, n * 14 * 3300 * 64 * 8, n * 3300 * 32 * 64 * 8
     assert lib.pusch_slot_workspace_bytes(ctypes.byref(d32), n) == a(xa) + a(y) + a(h)
+    # odd number of beams: separate estimation kernel, stored estimate
+    d31 = _desc(n_beams=31)
+    xa, y, h = n * 14 * 64 * 3300 * 8, n * 14 * 3300 * 31 * 8, n * 3300 * 16 * 31 * 8
+    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d31), n) == a(xa) + a(y) + a(h)
+    # one UE, two pilot symbols on the same subcarriers: each bracket end
+    # averages them, 8 taps per subcarrier
+    d1 = _desc(n_ue=1)
+    y = n * 14 * 3300 * 32 * 8
+    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d1), n) == a(n * 14 * 64 * 3300 * 8) + a(y) + a(3300 * 8 * 8)
     assert lib.pusch_slot_workspace_bytes(ctypes.byref(_desc(n_fft=1000)), n) == 0
     assert lib.pusch_slot_workspace_bytes(ctypes.byref(_desc(pilot_symb=(11, 2))), n) == 0
 

@@ -273,6 +273,12 @@ def test_slot_cfg2_full_batch_sampled():
     dict(n_ant=16, n_fft=1024, n_sc=825, n_beams=8, n_ue=4, pilot_symb=(0,), qam_bits=2, channel="tdl"),
     dict(n_ant=32, n_fft=2048, n_sc=1650, n_beams=16, n_ue=8, pilot_symb=(0, 4, 7, 11), qam_bits=8, channel="tdl"),
     dict(n_ant=8, n_fft=64, n_sc=60, n_beams=8, n_ue=3, pilot_symb=(3, 9), qam_bits=4, channel="flat"),
+    # pilot symbols that put a UE's pilot on the same subcarriers: each end of
+    # the interpolation averages two (one UE) or four (two UEs) of them
+    dict(n_ant=8, n_fft=256, n_sc=100, n_beams=4, n_ue=1, pilot_symb=(2, 11), qam_bits=4, channel="tdl"),
+    dict(n_ant=16, n_fft=256, n_sc=200, n_beams=6, n_ue=2, pilot_symb=(0, 4, 7, 11), qam_bits=6, channel="tdl"),
+    # odd number of beams: stand-alone estimation kernel and stored estimate
+    dict(n_ant=16, n_fft=256, n_sc=256, n_beams=15, n_ue=4, pilot_symb=(2,), qam_bits=4, channel="flat"),
 ])
 def test_slot_other_geometries(geom):
     cfg = synth.CFG1.replace(snr_db=25.0, **geom)

@@ -36,7 +36,7 @@ def naive_dft(x):
     return np.array(out)
 
 
-# ----------------------------------------------------------------------------- FFT (a1)
+# ----------------------------------------------------------------------------- OFDM demodulation (FFT)
 
 @pytest.mark.parametrize("n", [4, 16, 64, 256])
 def test_fft_matches_bruteforce_dft(n):
@@ -90,7 +90,7 @@ def test_active_bin_map(n_fft, n_sc):
             assert np.all(np.abs(Xa) < 1e-6)
 
 
-# ----------------------------------------------------------------------------- BF (a2)
+# ----------------------------------------------------------------------------- beamforming
 
 @pytest.mark.parametrize("nb,nr", [(16, 16), (32, 64), (5, 7)])
 def test_dft_beamformer_rows_orthonormal(nb, nr):
@@ -116,7 +116,7 @@ def test_beamform_bruteforce():
                 assert abs(Y[s, b, k] - acc) < 1e-12
 
 
-# ----------------------------------------------------------------------------- LS (a3)
+# ----------------------------------------------------------------------------- LS channel estimation
 
 def test_ls_golden(golden):
     g = golden("ls_comb_small.txt")
@@ -183,7 +183,7 @@ def test_ls_noiseless_flat_chain_recovers_beam_channel():
     assert M.nrmse(r["H"], H_beam) < 1e-6  # input is complex64: error is its rounding
 
 
-# ----------------------------------------------------------------------------- Gram + Crout (a4, a5)
+# ----------------------------------------------------------------------------- Gram + Crout
 
 def test_crout_golden_exact(golden):
     g = golden("crout_3x3.txt")
@@ -233,7 +233,7 @@ def test_crout_flags_non_pd():
     assert ok.tolist() == [True, False, False, False]
 
 
-# ----------------------------------------------------------------------------- solve (a6)
+# ----------------------------------------------------------------------------- matched filter + substitution
 
 def test_mmse_golden(golden):
     g = golden("mmse_2x2.txt")
@@ -316,7 +316,7 @@ def test_single_ue_qpsk_ber_matches_rayleigh_mrc_closed_form():
     assert abs(ber - pb) < 5 * sd + 1e-4
 
 
-# ----------------------------------------------------------------------------- end to end (a7)
+# ----------------------------------------------------------------------------- end to end
 
 def test_chain_noiseless_cfg1_recovers_bits_exactly():
     cfg = synth.CFG1.replace(snr_db=None)
