@@ -377,76 +377,93 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
     const int k0 = (blockIdx.x - bi * nblk_batch) * kSPW;
 
     // ---- phase A: Gram and matched filter of each subcarrier on MFMA
+    // 8 MFMAs of one K-step: G += h^H h, P += h^H y (complex as real parts)
+    auto kstep = [](f32x4& gr, f32x4& gi, f32x4& pr, f32x4& pi, cf h, cf y) {
+      const float nhi = -h.i;
+      gr = mfma(h.r, h.r, gr);
+      gr = mfma(h.i, h.i, gr);
+      gi = mfma(h.r, h.i, gi);
+      gi = mfma(nhi, h.r, gi);
+      pr = mfma(h.r, y.r, pr);
+      pr = mfma(h.i, y.i, pr);
+      pi = mfma(h.r, y.i, pi);
+      pi = mfma(nhi, y.r, pi);
+    };
+    // fused: this lane's taps (UE c16; lanes past n_ue read UE 0's and
+    // discard the result), prefetched one subcarrier ahead
+    constexpr int NQ = NT > 0 ? NT / 2 : 1;
+    int4 tnext[NQ];
+    auto load_taps = [&](int kk) {
+      kk = kk < nsc ? kk : nsc - 1;
+      const int4* tp = reinterpret_cast<const int4*>(taps + ((long long)kk * nue + (c16 < nue ? c16 : 0)) * NT);
+#pragma unroll
+      for (int u = 0; u < NQ; ++u) tnext[u] = tp[u];
+    };
+    if constexpr (FUSED) load_taps(k0);
 #pragma unroll 1
     for (int sc = 0; sc < kSPW; ++sc) {
       const int k = k0 + sc;
       f32x4 gr = {0.f, 0.f, 0.f, 0.f}, gi = gr, pr = gr, pi = gr;
-      if (k < nsc) {
-        cf h[KS], y[KS];
-        if constexpr (FUSED) {
-          // this lane's fragment of H (UE c16, its beams), interpolated from
-          // the LS values the beamforming epilogue left in the pilot symbols;
-          // lanes past n_ue take UE 0's taps with weight 0 (zero rows of H)
+      if constexpr (FUSED) {
+        int off[NT];
+        float w[NT];
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+          off[2 * u] = tnext[u].x;
+          w[2 * u] = __int_as_float(tnext[u].y);
+          off[2 * u + 1] = tnext[u].z;
+          w[2 * u + 1] = __int_as_float(tnext[u].w);
+        }
+        if (sc + 1 < kSPW) load_taps(k + 1);
+        if (k < nsc) {
+          // H interpolated from the LS values the beamforming epilogue left in
+          // the pilot symbols.  The loads of CH beam pairs go out together
+          // (one wait), then their arithmetic.  Even n_beams: one 16-byte load
+          // per pair; y columns of lanes past n_data only feed columns of P
+          // that are never read, beams past n_beams meet zero columns of H.
           const cf* LSb = Y + bi * cg.y_batch;
-          const int4* tp = reinterpret_cast<const int4*>(taps + ((long long)k * nue + (c16 < nue ? c16 : 0)) * NT);
-          int off[NT];
-          float w[NT];
+          const cf* yrow = Y + bi * g.y_batch + ysym + (long long)k * nb;
+          constexpr int CH = NT <= 2 ? 4 : 1;
 #pragma unroll
-          for (int t = 0; t < NT; t += 2) {
-            const int4 e = tp[t / 2];
-            off[t] = e.x;
-            off[t + 1] = e.z;
-            w[t] = c16 < nue ? __int_as_float(e.y) : 0.f;
-            w[t + 1] = c16 < nue ? __int_as_float(e.w) : 0.f;
-          }
+          for (int c0 = 0; c0 < KS / 2; c0 += CH) {
+            float4 lv[CH][NT], yv[CH];
 #pragma unroll
-          for (int s = 0; s < KS; s += 2) {
-            const int b = frag_beam(s, q);
-            float4 a = {0.f, 0.f, 0.f, 0.f};
+            for (int u = 0; u < CH; ++u) {
+              if (c0 + u >= KS / 2) continue;
+              const int b = frag_beam(2 * (c0 + u), q);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-              const float4 v = load_pair_even(LSb + off[t], b, nb);
-              a.x = __builtin_fmaf(w[t], v.x, a.x);
-              a.y = __builtin_fmaf(w[t], v.y, a.y);
-              a.z = __builtin_fmaf(w[t], v.z, a.z);
-              a.w = __builtin_fmaf(w[t], v.w, a.w);
+              for (int t = 0; t < NT; ++t) lv[u][t] = load_pair_even(LSb + off[t], b, nb);
+              yv[u] = load_pair_even(yrow, b, nb);
             }
-            const bool bv = b < nb;  // beams past n_beams: zero columns of H
-            h[s] = cf{bv ? a.x : 0.f, bv ? a.y : 0.f};
-            h[s + 1] = cf{bv ? a.z : 0.f, bv ? a.w : 0.f};
-          }
-        } else {
-          const cf* hrow = H + bi * g.h_batch + ((long long)k * nue + (c16 < nue ? c16 : 0)) * nb;
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int s = 0; s < KS; s += 2) load_pair(h[s], h[s + 1], hrow, frag_beam(s, q), nb, c16 < nue, vec);
+            for (int u = 0; u < CH; ++u) {
+              if (c0 + u >= KS / 2) continue;
+              const int b = frag_beam(2 * (c0 + u), q);
+              float4 a = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+              for (int t = 0; t < NT; ++t) {
+                a.x = __builtin_fmaf(w[t], lv[u][t].x, a.x);
+                a.y = __builtin_fmaf(w[t], lv[u][t].y, a.y);
+                a.z = __builtin_fmaf(w[t], lv[u][t].z, a.z);
+                a.w = __builtin_fmaf(w[t], lv[u][t].w, a.w);
+              }
+              const bool keep = c16 < nue && b < nb;  // zero rows / columns of H
+              kstep(gr, gi, pr, pi, cf{keep ? a.x : 0.f, keep ? a.y : 0.f}, cf{yv[u].x, yv[u].y});
+              kstep(gr, gi, pr, pi, cf{keep ? a.z : 0.f, keep ? a.w : 0.f}, cf{yv[u].z, yv[u].w});
+            }
+          }
         }
+      } else if (k < nsc) {
+        cf h[KS], y[KS];
+        const cf* hrow = H + bi * g.h_batch + ((long long)k * nue + (c16 < nue ? c16 : 0)) * nb;
+#pragma unroll
+        for (int s = 0; s < KS; s += 2) load_pair(h[s], h[s + 1], hrow, frag_beam(s, q), nb, c16 < nue, vec);
         const cf* yrow = Y + bi * g.y_batch + ysym + (long long)k * nb;
-        if constexpr (FUSED) {
-          // even n_beams: one 16-byte load per beam pair; columns of lanes
-          // past n_data only feed columns of P that are never read, and beams
-          // past n_beams meet zero columns of H
 #pragma unroll
-          for (int s = 0; s < KS; s += 2) {
-            const float4 v = load_pair_even(yrow, frag_beam(s, q), nb);
-            y[s] = cf{v.x, v.y};
-            y[s + 1] = cf{v.z, v.w};
-          }
-        } else {
+        for (int s = 0; s < KS; s += 2) load_pair(y[s], y[s + 1], yrow, frag_beam(s, q), nb, c16 < nd, vec);
 #pragma unroll
-          for (int s = 0; s < KS; s += 2) load_pair(y[s], y[s + 1], yrow, frag_beam(s, q), nb, c16 < nd, vec);
-        }
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          const float hr = h[s].r, hi = h[s].i, nhi = -h[s].i;
-          gr = mfma(hr, hr, gr);
-          gr = mfma(hi, hi, gr);
-          gi = mfma(hr, hi, gi);
-          gi = mfma(nhi, hr, gi);
-          pr = mfma(hr, y[s].r, pr);
-          pr = mfma(hi, y[s].i, pr);
-          pi = mfma(hr, y[s].i, pi);
-          pi = mfma(nhi, y[s].r, pi);
-        }
+        for (int s = 0; s < KS; ++s) kstep(gr, gi, pr, pi, h[s], y[s]);
       }
       // lane holds rows 4q..4q+3 of column c16 (G: lower triangle only)
 #pragma unroll
