@@ -261,6 +261,9 @@ constexpr int kRow = 17;             // padded LDS row of a 16x16 matrix (cf)
 constexpr int kMat = 16 * kRow + 1;  // padded matrix stride: the 4 groups' broadcasts hit distinct banks
 constexpr int kTri = 16 * 17 / 2 + 1;  // packed lower triangle (row i at i(i+1)/2), odd stride
 constexpr int kDinv = 17;
+// staged solutions: rows of 16 cf, pair p of row (grp, d) at pair p ^ (d & 7)
+// (spreads the 16-byte accesses of one instruction over the banks)
+static_assert(kSPW * 16 * 16 <= kSPW * kMat, "solution staging must fit in the P buffer");
 
 __device__ __forceinline__ int tri(int i) { return (i * (i + 1)) >> 1; }
 
@@ -361,7 +364,7 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
                                                   const int2* __restrict__ taps, cf* __restrict__ Xh,
                                                   int* __restrict__ st, MmseGeom g, ChestGeom cg, int nblk_batch) {
   __shared__ cf Gs[kSPW * kTri];  // lower triangle of G, then of L in place
-  __shared__ cf Ps[kSPW * kMat];  // P[i][d] = (H^H y_d)_i
+  __shared__ __align__(16) cf Ps[kSPW * kMat];  // P[i][d] = (H^H y_d)_i; then the staged solutions
   __shared__ float Dinv[kSPW * kDinv];
   const int lane = threadIdx.x;
   const int c16 = lane & 15, q = lane >> 4;
@@ -389,6 +392,62 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
       pi = mfma(h.r, y.i, pi);
       pi = mfma(nhi, y.r, pi);
     };
+    // lane holds rows 4q..4q+3 of column c16 (G: lower triangle only)
+    auto store_gp = [&](int sc, const f32x4& gr, const f32x4& gi, const f32x4& pr, const f32x4& pi) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * q + v;
+        if (i >= c16) Gs[sc * kTri + tri(i) + c16] = cf{gr[v], gi[v]};
+        Ps[sc * kMat + i * kRow + c16] = cf{pr[v], pi[v]};
+      }
+    };
+    // Two taps and up to 8 K-steps (the common fused case): all kSPW
+    // subcarriers unrolled, the loads of subcarrier sc + 1 in flight during
+    // the MFMAs of sc (double-buffered registers).
+    constexpr bool PIPE = FUSED && NT == 2 && KS <= 8;
+    if constexpr (PIPE) {
+      const int ue = c16 < nue ? c16 : 0;  // lanes past n_ue: UE 0's taps, result discarded
+      int4 tq[kSPW];
+#pragma unroll
+      for (int sc = 0; sc < kSPW; ++sc) {
+        const int kk = k0 + sc < nsc ? k0 + sc : nsc - 1;
+        tq[sc] = reinterpret_cast<const int4*>(taps)[(long long)kk * nue + ue];
+      }
+      const cf* LSb = Y + bi * cg.y_batch;
+      float4 lv[2][KS / 2][2], yv[2][KS / 2];
+      auto issue = [&](int sc, int buf) {
+        const int kk = k0 + sc < nsc ? k0 + sc : nsc - 1;
+        const cf* yrow = Y + bi * g.y_batch + ysym + (long long)kk * nb;
+#pragma unroll
+        for (int u = 0; u < KS / 2; ++u) {
+          const int b = frag_beam(2 * u, q);
+          lv[buf][u][0] = load_pair_even(LSb + tq[sc].x, b, nb);
+          lv[buf][u][1] = load_pair_even(LSb + tq[sc].z, b, nb);
+          yv[buf][u] = load_pair_even(yrow, b, nb);
+        }
+      };
+      issue(0, 0);
+#pragma unroll
+      for (int sc = 0; sc < kSPW; ++sc) {
+        const int buf = sc & 1;
+        if (sc + 1 < kSPW) issue(sc + 1, buf ^ 1);
+        __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this subcarrier's arithmetic
+        f32x4 gr = {0.f, 0.f, 0.f, 0.f}, gi = gr, pr = gr, pi = gr;
+        const float w0 = __int_as_float(tq[sc].y), w1 = __int_as_float(tq[sc].w);
+        const bool live = c16 < nue && k0 + sc < nsc;  // else zero rows of H (G = 0, P = 0)
+#pragma unroll
+        for (int u = 0; u < KS / 2; ++u) {
+          const int b = frag_beam(2 * u, q);
+          const float4 l0 = lv[buf][u][0], l1 = lv[buf][u][1], yy = yv[buf][u];
+          const bool keep = live && b < nb;
+          const float4 a = {__builtin_fmaf(w1, l1.x, w0 * l0.x), __builtin_fmaf(w1, l1.y, w0 * l0.y),
+                            __builtin_fmaf(w1, l1.z, w0 * l0.z), __builtin_fmaf(w1, l1.w, w0 * l0.w)};
+          kstep(gr, gi, pr, pi, cf{keep ? a.x : 0.f, keep ? a.y : 0.f}, cf{yy.x, yy.y});
+          kstep(gr, gi, pr, pi, cf{keep ? a.z : 0.f, keep ? a.w : 0.f}, cf{yy.z, yy.w});
+        }
+        store_gp(sc, gr, gi, pr, pi);
+      }
+    }
     // fused: this lane's taps (UE c16; lanes past n_ue read UE 0's and
     // discard the result), prefetched one subcarrier ahead
     constexpr int NQ = NT > 0 ? NT / 2 : 1;
@@ -399,9 +458,9 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
 #pragma unroll
       for (int u = 0; u < NQ; ++u) tnext[u] = tp[u];
     };
-    if constexpr (FUSED) load_taps(k0);
+    if constexpr (FUSED && !PIPE) load_taps(k0);
 #pragma unroll 1
-    for (int sc = 0; sc < kSPW; ++sc) {
+    for (int sc = 0; sc < (PIPE ? 0 : kSPW); ++sc) {
       const int k = k0 + sc;
       f32x4 gr = {0.f, 0.f, 0.f, 0.f}, gi = gr, pr = gr, pi = gr;
       if constexpr (FUSED) {
@@ -465,13 +524,7 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
 #pragma unroll
         for (int s = 0; s < KS; ++s) kstep(gr, gi, pr, pi, h[s], y[s]);
       }
-      // lane holds rows 4q..4q+3 of column c16 (G: lower triangle only)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 4 * q + v;
-        if (i >= c16) Gs[sc * kTri + tri(i) + c16] = cf{gr[v], gi[v]};
-        Ps[sc * kMat + i * kRow + c16] = cf{pr[v], pi[v]};
-      }
+      store_gp(sc, gr, gi, pr, pi);
     }
     __syncthreads();
 
@@ -542,15 +595,33 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
       for (int r = 0; r < m; ++r) csub_conj_mul(z[r], Gm[tri(m) + r], z[m]);  // z_r -= conj(L_mr) x_m
     }
     const int k = k0 + grp;
-    if (k < nsc) {
-      if (d < nd) {
-        cf* dst = Xh + bi * g.x_batch + ((long long)d * nsc + k) * nue;
+    if (nue == 16 && k0 + kSPW <= nsc) {
+      // x_hat[d][k0 .. k0+3][0..15] is one contiguous 512-byte run per data
+      // symbol: stage the solutions in LDS (P is consumed) and write each run
+      // with 16-byte stores, consecutive lanes on consecutive bytes.
+      cf* Xs = Ps;  // [grp][d] rows of 16 (swizzled pairs)
+      __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-          if (r < nue) dst[r] = fail ? cf{0.f, 0.f} : z[r];
+      for (int r = 0; r < 16; r += 2)
+        *reinterpret_cast<float4*>(Xs + (grp * 16 + d) * 16 + 2 * ((r >> 1) ^ (d & 7))) =
+            fail ? float4{0.f, 0.f, 0.f, 0.f} : float4{z[r].r, z[r].i, z[r + 1].r, z[r + 1].i};
+      __syncthreads();
+      cf* xb = Xh + bi * g.x_batch + (long long)k0 * 16;
+#pragma unroll
+      for (int it = 0; it < 16 * kSPW * 16 / 2 / 64; ++it) {
+        const int c = it * 64 + lane;  // 16-byte chunk: data symbol, subcarrier, UE pair
+        const int dd = c >> 5, gg = (c >> 3) & 3, rp = c & 7;
+        if (dd < nd)
+          *reinterpret_cast<float4*>(xb + (long long)dd * nsc * 16 + gg * 16 + 2 * rp) =
+              *reinterpret_cast<const float4*>(Xs + (gg * 16 + dd) * 16 + 2 * (rp ^ (dd & 7)));
       }
-      if (d == 0 && st) st[bi * g.st_batch + k] = fail;
+    } else if (k < nsc && d < nd) {
+      cf* dst = Xh + bi * g.x_batch + ((long long)d * nsc + k) * nue;
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if (r < nue) dst[r] = fail ? cf{0.f, 0.f} : z[r];
     }
+    if (k < nsc && d == 0 && st) st[bi * g.st_batch + k] = fail;
   }
 }
 
