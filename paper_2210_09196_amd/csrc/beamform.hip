@@ -189,6 +189,145 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform(const cf* __restrict__
   }
 }
 
+// Up to 64 antennas: a wavefront owns (16*MT beams) x 16 REs and holds the
+// whole antenna axis of its tile in registers (KS K-steps of one 8-byte X
+// value per lane); the next tile's loads are in flight while the current
+// tile's MFMAs run (ping-pong over a tile loop unrolled by two).  Half the
+// accumulators of the 32-RE tile, so two tiles of X fit next to them.
+template <int MT, int KS>
+__global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict__ W, const cf* __restrict__ X,
+                                                            cf* __restrict__ Y, int nb, int na, int nre,
+                                                            long long ldx, long long sx, long long sy, long long ntiles,
+                                                            long long ntn, PilotScale ps) {
+  extern __shared__ float4 wl[];  // [ks][m][lane] = (Wr, Wi, Wr + Wi, 0)
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15;  // A row / B column / D column inside a 16x16 tile
+  const int kq = lane >> 4;   // A column / B row (antenna within the step of 4)
+  for (int e = threadIdx.x; e < KS * MT * 64; e += blockDim.x) {
+    const int l = e & 63, m = (e >> 6) % MT, ks = (e >> 6) / MT;
+    const int b = m * 16 + (l & 15), a = ks * 4 + (l >> 4);
+    const cf w = (a < na && b < nb) ? W[b * na + a] : cf{0.f, 0.f};
+    wl[e] = make_float4(w.r, w.i, w.r + w.i, 0.f);
+  }
+  __syncthreads();
+
+  const long long nwave = (long long)gridDim.x * kWaves;
+  const long long t0 = (long long)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  // X operand of every K-step of a tile: clamped in-bounds loads (a tile
+  // index past the end re-reads the last tile; such a prefetch is dropped)
+  // (a wave-uniform base per batch item, 32-bit per-lane offsets: the host
+  // guarantees n_ant * ldx < 2^28)
+  auto load = [&](cf (&x)[KS], long long tile) {
+    tile = tile < ntiles ? tile : ntiles - 1;
+    const long long bi = tile / ntn;
+    const int n = (int)(tile - bi * ntn) * 16 + col;
+    const cf* base = X + bi * sx;
+    const unsigned nn = (unsigned)(n < nre ? n : nre - 1);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int a = ks * 4 + kq;
+      x[ks] = base[(unsigned)(a < na ? a : na - 1) * (unsigned)ldx + nn];
+    }
+  };
+  auto compute = [&](const cf (&x)[KS], long long tile) {
+    const long long bi = tile / ntn;
+    const int n = (int)(tile - bi * ntn) * 16 + col;
+    f32x4 t1[MT], t2[MT], t3[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) t1[m] = t2[m] = t3[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const bool ok = ks * 4 + kq < na;  // padded antennas: zero operand
+      const float xr = ok ? x[ks].r : 0.f, xi = ok ? x[ks].i : 0.f;
+      const float xs = xr + xi;
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const float4 w = wl[(ks * MT + m) * 64 + lane];
+        t1[m] = mfma(w.x, xr, t1[m]);
+        t2[m] = mfma(w.y, xi, t2[m]);
+        t3[m] = mfma(w.z, xs, t3[m]);
+      }
+    }
+    if (n >= nre) return;
+    // optional LS epilogue for pilot symbols
+    cf sc = cf{1.f, 0.f};
+    bool scaled = false;
+    if (ps.pilots) {
+      const long long slot = bi / ps.n_symb;
+      const int j = ps.pilot_of[bi - slot * ps.n_symb];
+      if (j >= 0) {
+        scaled = true;
+        const cf p = ps.pilots[slot * ps.p_slot + (long long)j * nre + n];
+        const float inv = fast_rcp(p.r * p.r + p.i * p.i);
+        sc = cf{p.r * inv, -p.i * inv};
+      }
+    }
+    cf* dst0 = Y + bi * sy + (long long)n * nb;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int b0 = m * 16 + kq * 4;
+      cf o[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float re = t1[m][v] - t2[m][v];
+        const float im = t3[m][v] - t1[m][v] - t2[m][v];
+        o[v] = scaled ? cf{re * sc.r - im * sc.i, re * sc.i + im * sc.r} : cf{re, im};
+      }
+      cf* dst = dst0 + b0;
+      if (b0 + 3 < nb && (nb & 1) == 0) {
+        reinterpret_cast<float4*>(dst)[0] = make_float4(o[0].r, o[0].i, o[1].r, o[1].i);
+        reinterpret_cast<float4*>(dst)[1] = make_float4(o[2].r, o[2].i, o[3].r, o[3].i);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (b0 + v < nb) dst[v] = o[v];
+      }
+    }
+  };
+  if (t0 >= ntiles) return;
+  cf xa[KS], xb[KS];
+  load(xa, t0);
+  for (long long t = t0; t < ntiles; t += 2 * nwave) {
+    load(xb, t + nwave);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(xa, t);
+    load(xa, t + 2 * nwave);
+    __builtin_amdgcn_sched_barrier(0);
+    if (t + nwave < ntiles) compute(xb, t + nwave);
+  }
+}
+
+template <int MT, int KS>
+hipError_t launch_k(const cf* W, const cf* X, cf* Y, int nb, int na, int nre, long long ldx, long long sx,
+                    long long sy, long long batch, const PilotScale& ps, int n_cu, hipStream_t s) {
+  const long long ntn = (nre + 15) / 16;
+  const long long tiles = batch * ntn;
+  const size_t lds = (size_t)KS * MT * 64 * sizeof(float4);
+  // persistent grid of exactly the resident workgroups: every wave walks its
+  // tiles from the start, no second round of workgroups and its tail
+  static const int per_cu = [&] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_beamform_k<MT, KS>, 64 * kWaves, lds) != hipSuccess ||
+        n < 1)
+      n = 1;
+    return n;
+  }();
+  long long blocks = (tiles + kWaves - 1) / kWaves;
+  const long long cap = (long long)n_cu * per_cu;
+  if (blocks > cap) blocks = cap;
+  hipLaunchKernelGGL((k_beamform_k<MT, KS>), dim3((unsigned)blocks), dim3(64 * kWaves), lds, s, W, X, Y, nb, na,
+                     nre, ldx, sx, sy, tiles, ntn, ps);
+  return hipGetLastError();
+}
+
+template <int MT>
+hipError_t launch_k_mt(const cf* W, const cf* X, cf* Y, int nb, int na, int nre, long long ldx, long long sx,
+                       long long sy, long long batch, const PilotScale& ps, int n_cu, hipStream_t s) {
+  if (na <= 16) return launch_k<MT, 4>(W, X, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+  if (na <= 32) return launch_k<MT, 8>(W, X, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+  return launch_k<MT, 16>(W, X, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+}
+
 constexpr size_t kWLdsMax = 64 * 1024;
 
 template <int MT, bool VEC>
@@ -218,14 +357,23 @@ hipError_t launch_beamform(const cf* W, const cf* X, cf* Y, int n_beams, int n_a
                            long long sx, long long sy, long long batch, int n_cu, hipStream_t s,
                            const PilotScale* pilot_scale) {
   if (batch <= 0 || n_re <= 0) return hipSuccess;
+  PilotScale ps{};
+  if (pilot_scale) ps = *pilot_scale;
+  if (n_ant <= 64 && ldx * n_ant < (1ll << 28)) {
+    switch ((n_beams + 15) / 16) {
+      case 1: return launch_k_mt<1>(W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ps, n_cu, s);
+      case 2: return launch_k_mt<2>(W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ps, n_cu, s);
+      case 3: return launch_k_mt<3>(W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ps, n_cu, s);
+      case 4: return launch_k_mt<4>(W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ps, n_cu, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   const long long ntn = (n_re + kTileN - 1) / kTileN;
   const long long tiles = batch * ntn;
   long long blocks = (tiles + kWaves - 1) / kWaves;
   const long long cap = (long long)n_cu * 8;
   if (blocks > cap) blocks = cap;
   const dim3 grid((unsigned)blocks);
-  PilotScale ps{};
-  if (pilot_scale) ps = *pilot_scale;
   switch ((n_beams + 15) / 16) {
     case 1: return launch_mt<1>(W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ntn, ps, grid, s);
     case 2: return launch_mt<2>(W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ntn, ps, grid, s);

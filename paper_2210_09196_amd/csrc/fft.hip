@@ -265,6 +265,24 @@ void fft_fill_twiddles(cf* host) {
   }
 }
 
+namespace {
+// Persistent grid of exactly the resident workgroups (no second round of
+// workgroups and its tail).
+template <int N>
+hipError_t launch_n(const cf* x, cf* X, const cf* tw, long long batch, int out_len, int shift, long long blocks,
+                    int n_cu, hipStream_t s) {
+  static const int per_cu = [] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fft<N>, kThreads, 0) != hipSuccess || n < 1) n = 1;
+    return n;
+  }();
+  const long long cap = (long long)n_cu * per_cu;
+  if (blocks > cap) blocks = cap;
+  hipLaunchKernelGGL(k_fft<N>, dim3((unsigned)blocks), dim3(kThreads), 0, s, x, X, tw, batch, out_len, shift);
+  return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_len, int shift, const cf* twiddles,
                       int n_cu, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
@@ -272,19 +290,15 @@ hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_le
   const TwiddleLayout lay = fft_twiddle_layout();
   const cf* tw = twiddles + lay.offset[si];
   const long long fpb = kThreads / (n_fft / 16);
-  long long blocks = (batch + fpb - 1) / fpb;
-  const long long cap = (long long)n_cu * 4;  // four 35 KB workgroups fit one CU's LDS
-  if (blocks > cap) blocks = cap;
-  const dim3 grid((unsigned)blocks), block(kThreads);
+  const long long blocks = (batch + fpb - 1) / fpb;
   switch (n_fft) {
-    case 64: hipLaunchKernelGGL(k_fft<64>, grid, block, 0, s, x, X, tw, batch, out_len, shift); break;
-    case 256: hipLaunchKernelGGL(k_fft<256>, grid, block, 0, s, x, X, tw, batch, out_len, shift); break;
-    case 1024: hipLaunchKernelGGL(k_fft<1024>, grid, block, 0, s, x, X, tw, batch, out_len, shift); break;
-    case 2048: hipLaunchKernelGGL(k_fft<2048>, grid, block, 0, s, x, X, tw, batch, out_len, shift); break;
-    case 4096: hipLaunchKernelGGL(k_fft<4096>, grid, block, 0, s, x, X, tw, batch, out_len, shift); break;
+    case 64: return launch_n<64>(x, X, tw, batch, out_len, shift, blocks, n_cu, s);
+    case 256: return launch_n<256>(x, X, tw, batch, out_len, shift, blocks, n_cu, s);
+    case 1024: return launch_n<1024>(x, X, tw, batch, out_len, shift, blocks, n_cu, s);
+    case 2048: return launch_n<2048>(x, X, tw, batch, out_len, shift, blocks, n_cu, s);
+    case 4096: return launch_n<4096>(x, X, tw, batch, out_len, shift, blocks, n_cu, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace pusch
