@@ -189,7 +189,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform(const cf* __restrict__
   }
 }
 
-// Up to 64 antennas: a wavefront owns (16*MT beams) x 16 REs and holds the
+// Up to 64 antennas: a wavefront owns 16 REs x (16*MT beams) and holds the
 // whole antenna axis of its tile in registers (KS K-steps of one 8-byte X
 // value per lane); the next tile's loads are in flight while the current
 // tile's MFMAs run (ping-pong over a tile loop unrolled by two).  Half the
@@ -229,9 +229,13 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict
       x[ks] = base[(unsigned)(a < na ? a : na - 1) * (unsigned)ldx + nn];
     }
   };
+  // X is the A operand and W the B operand, so the result tile is
+  // D[RE][beam]: lane (kq, col) receives REs n0 + 4 kq + v of beam col, and
+  // sixteen consecutive lanes hold one RE's sixteen consecutive beams (each
+  // store instruction writes whole 128-byte lines).
   auto compute = [&](const cf (&x)[KS], long long tile) {
     const long long bi = tile / ntn;
-    const int n = (int)(tile - bi * ntn) * 16 + col;
+    const int n0 = (int)(tile - bi * ntn) * 16;
     f32x4 t1[MT], t2[MT], t3[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) t1[m] = t2[m] = t3[m] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -243,44 +247,40 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
         const float4 w = wl[(ks * MT + m) * 64 + lane];
-        t1[m] = mfma(w.x, xr, t1[m]);
-        t2[m] = mfma(w.y, xi, t2[m]);
-        t3[m] = mfma(w.z, xs, t3[m]);
+        t1[m] = mfma(xr, w.x, t1[m]);
+        t2[m] = mfma(xi, w.y, t2[m]);
+        t3[m] = mfma(xs, w.z, t3[m]);
       }
     }
-    if (n >= nre) return;
-    // optional LS epilogue for pilot symbols
-    cf sc = cf{1.f, 0.f};
+    // optional LS epilogue for pilot symbols: y * conj(p) / |p|^2 per RE
+    cf sc[4] = {cf{1.f, 0.f}, cf{1.f, 0.f}, cf{1.f, 0.f}, cf{1.f, 0.f}};
     bool scaled = false;
     if (ps.pilots) {
       const long long slot = bi / ps.n_symb;
       const int j = ps.pilot_of[bi - slot * ps.n_symb];
       if (j >= 0) {
         scaled = true;
-        const cf p = ps.pilots[slot * ps.p_slot + (long long)j * nre + n];
-        const float inv = fast_rcp(p.r * p.r + p.i * p.i);
-        sc = cf{p.r * inv, -p.i * inv};
+        const cf* pv = ps.pilots + slot * ps.p_slot + (long long)j * nre;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = n0 + 4 * kq + v;
+          const cf p = pv[n < nre ? n : nre - 1];
+          const float inv = fast_rcp(p.r * p.r + p.i * p.i);
+          sc[v] = cf{p.r * inv, -p.i * inv};
+        }
       }
     }
-    cf* dst0 = Y + bi * sy + (long long)n * nb;
+    cf* yb = Y + bi * sy;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
-      const int b0 = m * 16 + kq * 4;
-      cf o[4];
+      const int b = m * 16 + col;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
+        const int n = n0 + 4 * kq + v;
         const float re = t1[m][v] - t2[m][v];
         const float im = t3[m][v] - t1[m][v] - t2[m][v];
-        o[v] = scaled ? cf{re * sc.r - im * sc.i, re * sc.i + im * sc.r} : cf{re, im};
-      }
-      cf* dst = dst0 + b0;
-      if (b0 + 3 < nb && (nb & 1) == 0) {
-        reinterpret_cast<float4*>(dst)[0] = make_float4(o[0].r, o[0].i, o[1].r, o[1].i);
-        reinterpret_cast<float4*>(dst)[1] = make_float4(o[2].r, o[2].i, o[3].r, o[3].i);
-      } else {
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (b0 + v < nb) dst[v] = o[v];
+        const cf o = scaled ? cf{re * sc[v].r - im * sc[v].i, re * sc[v].i + im * sc[v].r} : cf{re, im};
+        if (n < nre && b < nb) yb[(long long)n * nb + b] = o;
       }
     }
   };
