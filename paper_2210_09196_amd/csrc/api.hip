@@ -136,7 +136,7 @@ int pusch_fft(const pusch_c32* x, pusch_c32* X, int n_fft, int n_sc, long long b
   DeviceTables* t = nullptr;
   if (int rc = device_tables(&t)) return rc;
   return hip_status(pusch::launch_fft(reinterpret_cast<const cf*>(x), reinterpret_cast<cf*>(X), n_fft, batch, out_len,
-                                      shift, t->twiddles, t->n_cu, static_cast<hipStream_t>(stream)));
+                                      shift, out_len, t->twiddles, t->n_cu, static_cast<hipStream_t>(stream)));
 }
 
 int pusch_beamform(const pusch_c32* W, const pusch_c32* X, pusch_c32* Y, int n_beams, int n_ant, int n_re,
@@ -256,11 +256,17 @@ int check_desc(const pusch_slot_desc* d) {
   return PUSCH_OK;
 }
 
+// Row pitch of the active-bin grids between the FFT and beamforming: a
+// multiple of 16 subcarriers, so every antenna row starts on a 128-byte line
+// and a beamforming tile of 16 subcarriers reads whole lines that no other
+// tile touches.
+size_t xa_pitch(int n_sc) { return ((size_t)n_sc + 15) & ~(size_t)15; }
+
 SlotLayout slot_layout(const pusch_slot_desc* d, long long n_slot) {
   const size_t S = d->n_symb, R = d->n_ant, K = d->n_sc, B = d->n_beams, L = d->n_ue, n = (size_t)n_slot;
   SlotLayout lay;
   lay.off_xa = 0;
-  lay.off_y = align256(n * S * R * K * 8);
+  lay.off_y = align256(n * S * R * xa_pitch(d->n_sc) * 8);
   lay.off_h = lay.off_y + align256(n * S * K * B * 8);
   // when the detection kernel estimates the channel itself (up to 16 UEs, an
   // even number of beams) no stored estimate is needed
@@ -318,7 +324,8 @@ int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td
 
   // OFDM demodulation (FFT) of every antenna and symbol, active bins only
   if (!mark(0)) return PUSCH_EHIP;
-  if (pusch::launch_fft(reinterpret_cast<const cf*>(x_td), Xa, d->n_fft, n_slot * S * R, K, K / 2, t->twiddles,
+  const long long KP = (long long)xa_pitch(K);
+  if (pusch::launch_fft(reinterpret_cast<const cf*>(x_td), Xa, d->n_fft, n_slot * S * R, K, K / 2, KP, t->twiddles,
                         t->n_cu, s) != hipSuccess)
     return PUSCH_EHIP;
   // beamforming of every symbol, RE-major output; when the detection
@@ -334,7 +341,7 @@ int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td
     for (int j = 0; j < P; ++j) psc.pilot_of[d->pilot_symb[j]] = (signed char)j;
   }
   if (!mark(1)) return PUSCH_EHIP;
-  if (pusch::launch_beamform(w, Xa, Y, B, R, K, K, (long long)R * K, (long long)K * B, n_slot * S, t->n_cu, s,
+  if (pusch::launch_beamform(w, Xa, Y, B, R, K, KP, R * KP, (long long)K * B, n_slot * S, t->n_cu, s,
                              fused ? &psc : nullptr) != hipSuccess)
     return PUSCH_EHIP;
   // LS channel estimate from the pilot symbols

@@ -136,7 +136,7 @@ constexpr int kThreads = 256;
 template <int N>
 __global__ __launch_bounds__(kThreads) void k_fft(const cf* __restrict__ x, cf* __restrict__ X,
                                                   const cf* __restrict__ tw, long long batch, int out_len,
-                                                  int shift) {
+                                                  int shift, long long ldo) {
   constexpr int T = N / 16;         // threads per transform
   constexpr int FPB = kThreads / T;  // transforms per workgroup
   constexpr int R0 = Shape<N>::R0;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kThreads) void k_fft(const cf* __restrict__ x, cf* 
         __syncthreads();
       } else if (act) {
         // last pass: Ns = N/16 = T, so bin f = t + r*T
-        cf* dst = X + fft * out_len;
+        cf* dst = X + fft * ldo;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           int k = t + r * T + shift;
@@ -269,8 +269,8 @@ namespace {
 // Persistent grid of exactly the resident workgroups (no second round of
 // workgroups and its tail).
 template <int N>
-hipError_t launch_n(const cf* x, cf* X, const cf* tw, long long batch, int out_len, int shift, long long blocks,
-                    int n_cu, hipStream_t s) {
+hipError_t launch_n(const cf* x, cf* X, const cf* tw, long long batch, int out_len, int shift, long long ldo,
+                    long long blocks, int n_cu, hipStream_t s) {
   static const int per_cu = [] {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fft<N>, kThreads, 0) != hipSuccess || n < 1) n = 1;
@@ -278,13 +278,13 @@ hipError_t launch_n(const cf* x, cf* X, const cf* tw, long long batch, int out_l
   }();
   const long long cap = (long long)n_cu * per_cu;
   if (blocks > cap) blocks = cap;
-  hipLaunchKernelGGL(k_fft<N>, dim3((unsigned)blocks), dim3(kThreads), 0, s, x, X, tw, batch, out_len, shift);
+  hipLaunchKernelGGL(k_fft<N>, dim3((unsigned)blocks), dim3(kThreads), 0, s, x, X, tw, batch, out_len, shift, ldo);
   return hipGetLastError();
 }
 }  // namespace
 
-hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_len, int shift, const cf* twiddles,
-                      int n_cu, hipStream_t s) {
+hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_len, int shift, long long ldo,
+                      const cf* twiddles, int n_cu, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
   const int si = fft_size_index(n_fft);
   const TwiddleLayout lay = fft_twiddle_layout();
@@ -292,11 +292,11 @@ hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_le
   const long long fpb = kThreads / (n_fft / 16);
   const long long blocks = (batch + fpb - 1) / fpb;
   switch (n_fft) {
-    case 64: return launch_n<64>(x, X, tw, batch, out_len, shift, blocks, n_cu, s);
-    case 256: return launch_n<256>(x, X, tw, batch, out_len, shift, blocks, n_cu, s);
-    case 1024: return launch_n<1024>(x, X, tw, batch, out_len, shift, blocks, n_cu, s);
-    case 2048: return launch_n<2048>(x, X, tw, batch, out_len, shift, blocks, n_cu, s);
-    case 4096: return launch_n<4096>(x, X, tw, batch, out_len, shift, blocks, n_cu, s);
+    case 64: return launch_n<64>(x, X, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
+    case 256: return launch_n<256>(x, X, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
+    case 1024: return launch_n<1024>(x, X, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
+    case 2048: return launch_n<2048>(x, X, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
+    case 4096: return launch_n<4096>(x, X, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -28,9 +28,10 @@ TwiddleLayout fft_twiddle_layout();
 void fft_fill_twiddles(cf* host);
 int fft_size_index(int n_fft);  // 0..4, or -1 if unsupported
 
-// X_i[(f + shift) mod n_fft] = DFT(x_i)[f] for the targets below out_len.
-hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_len, int shift, const cf* twiddles,
-                      int n_cu, hipStream_t s);
+// X_i[(f + shift) mod n_fft] = DFT(x_i)[f] for the targets below out_len;
+// output rows ldo elements apart (>= out_len).
+hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_len, int shift, long long ldo,
+                      const cf* twiddles, int n_cu, hipStream_t s);
 
 // ---------------------------------------------------------------- beamforming
 // Optional beamforming epilogue of the fused slot: the outputs of pilot
@@ -49,6 +50,17 @@ hipError_t launch_beamform(const cf* W, const cf* X, cf* Y, int n_beams, int n_a
                            const PilotScale* pilot_scale = nullptr);
 
 // ---------------------------------------------------------------- LS channel estimation
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
+// id.  xcd_block(b, n) renumbers them so that XCD x gets one contiguous run of
+// the n logical blocks: neighbouring blocks, which share input lines, then
+// share an L2.  A bijection of [0, n) for any n.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  const int per = n / kXcds, rem = n % kXcds;
+  const int x = b % kXcds, local = b / kXcds;
+  return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+}
+
 struct ChestGeom {
   long long y_batch;              // Y elements between batch items
   long long y_sym;                // Y elements between the RE-major symbol grids [n_sc][n_beams]

@@ -376,8 +376,9 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
   {
     // one workgroup = one block of kSPW subcarriers (no enclosing loop, so no
     // lane predicates are hoisted and kept alive across blocks)
-    const int bi = blockIdx.x / nblk_batch;
-    const int k0 = (blockIdx.x - bi * nblk_batch) * kSPW;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);  // neighbouring subcarriers on one XCD (shared pilot rows)
+    const int bi = blk / nblk_batch;
+    const int k0 = (blk - bi * nblk_batch) * kSPW;
 
     // ---- phase A: Gram and matched filter of each subcarrier on MFMA
     // 8 MFMAs of one K-step: G += h^H h, P += h^H y (complex as real parts)

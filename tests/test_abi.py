@@ -95,7 +95,8 @@ def _desc(**kw):
 def test_slot_workspace_bytes(lib):
     d = _desc()
     n = 16
-    xa = n * 14 * 64 * 3300 * 8
+    # active-bin rows padded to a multiple of 16 subcarriers (3300 -> 3312)
+    xa = n * 14 * 64 * 3312 * 8
     y = n * 14 * 3300 * 32 * 8
     h = n * 3300 * 16 * 32 * 8
     a = lambda v: (v + 255) // 256 * 256
@@ -104,17 +105,17 @@ def test_slot_workspace_bytes(lib):
     # subcarrier and UE: no two pilot symbols share a UE's subcarriers)
     assert lib.pusch_slot_workspace_bytes(ctypes.byref(d), n) == a(xa) + a(y) + a(3300 * 16 * 2 * 8)
     d32 = _desc(n_ue=32, n_beams=64)
-    xa, y, h = n * 14 * 64 * 3300 * 8, n * 14 * 3300 * 64 * 8, n * 3300 * 32 * 64 * 8
+    xa, y, h = n * 14 * 64 * 3312 * 8, n * 14 * 3300 * 64 * 8, n * 3300 * 32 * 64 * 8
     assert lib.pusch_slot_workspace_bytes(ctypes.byref(d32), n) == a(xa) + a(y) + a(h)
     # odd number of beams: separate estimation kernel, stored estimate
     d31 = _desc(n_beams=31)
-    xa, y, h = n * 14 * 64 * 3300 * 8, n * 14 * 3300 * 31 * 8, n * 3300 * 16 * 31 * 8
+    xa, y, h = n * 14 * 64 * 3312 * 8, n * 14 * 3300 * 31 * 8, n * 3300 * 16 * 31 * 8
     assert lib.pusch_slot_workspace_bytes(ctypes.byref(d31), n) == a(xa) + a(y) + a(h)
     # one UE, two pilot symbols on the same subcarriers: each bracket end
     # averages them, 8 taps per subcarrier
     d1 = _desc(n_ue=1)
     y = n * 14 * 3300 * 32 * 8
-    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d1), n) == a(n * 14 * 64 * 3300 * 8) + a(y) + a(3300 * 8 * 8)
+    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d1), n) == a(n * 14 * 64 * 3312 * 8) + a(y) + a(3300 * 8 * 8)
     assert lib.pusch_slot_workspace_bytes(ctypes.byref(_desc(n_fft=1000)), n) == 0
     assert lib.pusch_slot_workspace_bytes(ctypes.byref(_desc(pilot_symb=(11, 2))), n) == 0
 
