@@ -10,8 +10,8 @@
 // k_mmse_mfma (n_ue <= 16): one wavefront takes 4 subcarriers per pass.
 //   Phase A runs the two dense products of each subcarrier -- the Gram
 //   matrix H^H H and the matched filter H^H [y_1 .. y_D] -- as 16x16x4 FP32
-//   MFMAs, the complex products split into four real ones; a lane's single
-//   fragment of H feeds both operands of the Gram product.  Phase B does the
+//   MFMAs, each complex product taking three real ones (Gauss/Karatsuba); a
+//   lane's single fragment of H feeds both operands of the Gram product.  Phase B does the
 //   Crout factorisation with one lane per row of L (16 lanes per subcarrier,
 //   row j broadcast by cross-lane shuffles).  Phase C runs both
 //   substitutions with one lane per data symbol, reading L from LDS by
@@ -382,26 +382,33 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
 
     // ---- phase A: Gram and matched filter of each subcarrier on MFMA
     // 8 MFMAs of one K-step: G += h^H h, P += h^H y (complex as real parts)
-    auto kstep = [](f32x4& gr, f32x4& gi, f32x4& pr, f32x4& pi, cf h, cf y) {
-      const float nhi = -h.i;
-      gr = mfma(h.r, h.r, gr);
-      gr = mfma(h.i, h.i, gr);
-      gi = mfma(h.r, h.i, gi);
-      gi = mfma(nhi, h.r, gi);
-      pr = mfma(h.r, y.r, pr);
-      pr = mfma(h.i, y.i, pr);
-      pi = mfma(h.r, y.i, pi);
-      pi = mfma(nhi, y.r, pi);
+    // 6 MFMAs of one K-step.  Both products take three real products
+    // (Gauss/Karatsuba): with T1 = ar br, T2 = ai bi, T3 = (ar - ai)(br + bi),
+    // conj(a) b = (T1 + T2) + i (T3 - T1 + T2).  The lane's fragment of H is
+    // both the A row (UE c16) and the B column (UE c16) of the Gram product.
+    struct Acc {
+      f32x4 g1, g2, g3, p1, p2, p3;
+    };
+    auto kstep = [](Acc& c, cf h, cf y) {
+      const float hm = h.r - h.i, hp = h.r + h.i, ys = y.r + y.i;
+      c.g1 = mfma(h.r, h.r, c.g1);
+      c.g2 = mfma(h.i, h.i, c.g2);
+      c.g3 = mfma(hm, hp, c.g3);
+      c.p1 = mfma(h.r, y.r, c.p1);
+      c.p2 = mfma(h.i, y.i, c.p2);
+      c.p3 = mfma(hm, ys, c.p3);
     };
     // lane holds rows 4q..4q+3 of column c16 (G: lower triangle only)
-    auto store_gp = [&](int sc, const f32x4& gr, const f32x4& gi, const f32x4& pr, const f32x4& pi) {
+    auto store_gp = [&](int sc, const Acc& c) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = 4 * q + v;
-        if (i >= c16) Gs[sc * kTri + tri(i) + c16] = cf{gr[v], gi[v]};
-        Ps[sc * kMat + i * kRow + c16] = cf{pr[v], pi[v]};
+        const float g12 = c.g1[v] + c.g2[v], p12 = c.p1[v] + c.p2[v];
+        if (i >= c16) Gs[sc * kTri + tri(i) + c16] = cf{g12, c.g3[v] - c.g1[v] + c.g2[v]};
+        Ps[sc * kMat + i * kRow + c16] = cf{p12, c.p3[v] - c.p1[v] + c.p2[v]};
       }
     };
+    const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
     // Two taps and up to 8 K-steps (the common fused case): all kSPW
     // subcarriers unrolled, the loads of subcarrier sc + 1 in flight during
     // the MFMAs of sc (double-buffered registers).
@@ -433,7 +440,7 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
         const int buf = sc & 1;
         if (sc + 1 < kSPW) issue(sc + 1, buf ^ 1);
         __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this subcarrier's arithmetic
-        f32x4 gr = {0.f, 0.f, 0.f, 0.f}, gi = gr, pr = gr, pi = gr;
+        Acc ac{z4, z4, z4, z4, z4, z4};
         const float w0 = __int_as_float(tq[sc].y), w1 = __int_as_float(tq[sc].w);
         const bool live = c16 < nue && k0 + sc < nsc;  // else zero rows of H (G = 0, P = 0)
 #pragma unroll
@@ -443,10 +450,10 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
           const bool keep = live && b < nb;
           const float4 a = {__builtin_fmaf(w1, l1.x, w0 * l0.x), __builtin_fmaf(w1, l1.y, w0 * l0.y),
                             __builtin_fmaf(w1, l1.z, w0 * l0.z), __builtin_fmaf(w1, l1.w, w0 * l0.w)};
-          kstep(gr, gi, pr, pi, cf{keep ? a.x : 0.f, keep ? a.y : 0.f}, cf{yy.x, yy.y});
-          kstep(gr, gi, pr, pi, cf{keep ? a.z : 0.f, keep ? a.w : 0.f}, cf{yy.z, yy.w});
+          kstep(ac, cf{keep ? a.x : 0.f, keep ? a.y : 0.f}, cf{yy.x, yy.y});
+          kstep(ac, cf{keep ? a.z : 0.f, keep ? a.w : 0.f}, cf{yy.z, yy.w});
         }
-        store_gp(sc, gr, gi, pr, pi);
+        store_gp(sc, ac);
       }
     }
     // fused: this lane's taps (UE c16; lanes past n_ue read UE 0's and
@@ -463,7 +470,7 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
 #pragma unroll 1
     for (int sc = 0; sc < (PIPE ? 0 : kSPW); ++sc) {
       const int k = k0 + sc;
-      f32x4 gr = {0.f, 0.f, 0.f, 0.f}, gi = gr, pr = gr, pi = gr;
+      Acc ac{z4, z4, z4, z4, z4, z4};
       if constexpr (FUSED) {
         int off[NT];
         float w[NT];
@@ -509,8 +516,8 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
                 a.w = __builtin_fmaf(w[t], lv[u][t].w, a.w);
               }
               const bool keep = c16 < nue && b < nb;  // zero rows / columns of H
-              kstep(gr, gi, pr, pi, cf{keep ? a.x : 0.f, keep ? a.y : 0.f}, cf{yv[u].x, yv[u].y});
-              kstep(gr, gi, pr, pi, cf{keep ? a.z : 0.f, keep ? a.w : 0.f}, cf{yv[u].z, yv[u].w});
+              kstep(ac, cf{keep ? a.x : 0.f, keep ? a.y : 0.f}, cf{yv[u].x, yv[u].y});
+              kstep(ac, cf{keep ? a.z : 0.f, keep ? a.w : 0.f}, cf{yv[u].z, yv[u].w});
             }
           }
         }
@@ -523,9 +530,9 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
 #pragma unroll
         for (int s = 0; s < KS; s += 2) load_pair(y[s], y[s + 1], yrow, frag_beam(s, q), nb, c16 < nd, vec);
 #pragma unroll
-        for (int s = 0; s < KS; ++s) kstep(gr, gi, pr, pi, h[s], y[s]);
+        for (int s = 0; s < KS; ++s) kstep(ac, h[s], y[s]);
       }
-      store_gp(sc, gr, gi, pr, pi);
+      store_gp(sc, ac);
     }
     __syncthreads();
 
