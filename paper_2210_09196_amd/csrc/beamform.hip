@@ -197,9 +197,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform(const cf* __restrict__
 template <int MT, int KS>
 __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict__ W, const cf* __restrict__ X,
                                                             cf* __restrict__ Y, int nb, int na, int nre,
-                                                            long long ldx, long long sx, long long sy, long long ntiles,
-                                                            long long ntn, PilotScale ps) {
-  extern __shared__ float4 wl[];  // [ks][m][lane] = (Wr, Wi, Wr + Wi, 0)
+                                                            long long ldx, long long sx, long long sy, int ntiles,
+                                                            int ntn, PilotScale ps) {
+  extern __shared__ float4 wl[];  // [ks][m][lane] = (Wr, Wi, Wr + Wi, 0); zero for padded antennas / beams
   const int lane = threadIdx.x & 63;
   const int col = lane & 15;  // A row / B column / D column inside a 16x16 tile
   const int kq = lane >> 4;   // A column / B row (antenna within the step of 4)
@@ -211,16 +211,17 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict
   }
   __syncthreads();
 
-  const long long nwave = (long long)gridDim.x * kWaves;
-  const long long t0 = (long long)blockIdx.x * kWaves + (threadIdx.x >> 6);
-  // X operand of every K-step of a tile: clamped in-bounds loads (a tile
-  // index past the end re-reads the last tile; such a prefetch is dropped)
-  // (a wave-uniform base per batch item, 32-bit per-lane offsets: the host
-  // guarantees n_ant * ldx < 2^28)
-  auto load = [&](cf (&x)[KS], long long tile) {
+  const int nwave = gridDim.x * kWaves;
+  const int t0 = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  // X operand of every K-step of a tile, from a wave-uniform base with
+  // 32-bit lane offsets (the host guarantees n_ant * ldx < 2^28).  Loads are
+  // clamped in bounds: padded antennas meet zero W entries, REs past n_re are
+  // not stored, and a tile index past the end re-reads the last tile (such a
+  // prefetch is dropped).
+  auto load = [&](cf (&x)[KS], int tile) {
     tile = tile < ntiles ? tile : ntiles - 1;
-    const long long bi = tile / ntn;
-    const int n = (int)(tile - bi * ntn) * 16 + col;
+    const int bi = tile / ntn;
+    const int n = (tile - bi * ntn) * 16 + col;
     const cf* base = X + bi * sx;
     const unsigned nn = (unsigned)(n < nre ? n : nre - 1);
 #pragma unroll
@@ -233,17 +234,15 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict
   // D[RE][beam]: lane (kq, col) receives REs n0 + 4 kq + v of beam col, and
   // sixteen consecutive lanes hold one RE's sixteen consecutive beams (each
   // store instruction writes whole 128-byte lines).
-  auto compute = [&](const cf (&x)[KS], long long tile) {
-    const long long bi = tile / ntn;
-    const int n0 = (int)(tile - bi * ntn) * 16;
+  auto compute = [&](const cf (&x)[KS], int tile) {
+    const int bi = tile / ntn;
+    const int n0 = (tile - bi * ntn) * 16;
     f32x4 t1[MT], t2[MT], t3[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) t1[m] = t2[m] = t3[m] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const bool ok = ks * 4 + kq < na;  // padded antennas: zero operand
-      const float xr = ok ? x[ks].r : 0.f, xi = ok ? x[ks].i : 0.f;
-      const float xs = xr + xi;
+      const float xr = x[ks].r, xi = x[ks].i, xs = xr + xi;
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
         const float4 w = wl[(ks * MT + m) * 64 + lane];
@@ -270,24 +269,37 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict
         }
       }
     }
-    cf* yb = Y + bi * sy;
+    cf o[MT][4];
 #pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      const int b = m * 16 + col;
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int n = n0 + 4 * kq + v;
         const float re = t1[m][v] - t2[m][v];
         const float im = t3[m][v] - t1[m][v] - t2[m][v];
-        const cf o = scaled ? cf{re * sc[v].r - im * sc[v].i, re * sc[v].i + im * sc[v].r} : cf{re, im};
-        if (n < nre && b < nb) yb[(long long)n * nb + b] = o;
+        o[m][v] = scaled ? cf{re * sc[v].r - im * sc[v].i, re * sc[v].i + im * sc[v].r} : cf{re, im};
       }
+    cf* yb = Y + bi * sy + (long long)n0 * nb;  // wave-uniform
+    if (n0 + 16 <= nre && nb == 16 * MT) {
+      // whole tile: 32-bit lane offsets, no per-store checks
+      const unsigned lo = (unsigned)(4 * kq * nb + col);
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) yb[lo + (unsigned)(v * nb + m * 16)] = o[m][v];
+    } else {
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = n0 + 4 * kq + v, b = m * 16 + col;
+          if (n < nre && b < nb) yb[(long long)(4 * kq + v) * nb + b] = o[m][v];
+        }
     }
   };
   if (t0 >= ntiles) return;
   cf xa[KS], xb[KS];
   load(xa, t0);
-  for (long long t = t0; t < ntiles; t += 2 * nwave) {
+  for (int t = t0; t < ntiles; t += 2 * nwave) {
     load(xb, t + nwave);
     __builtin_amdgcn_sched_barrier(0);
     compute(xa, t);
@@ -300,8 +312,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict
 template <int MT, int KS>
 hipError_t launch_k(const cf* W, const cf* X, cf* Y, int nb, int na, int nre, long long ldx, long long sx,
                     long long sy, long long batch, const PilotScale& ps, int n_cu, hipStream_t s) {
-  const long long ntn = (nre + 15) / 16;
-  const long long tiles = batch * ntn;
+  const int ntn = (nre + 15) / 16;
+  const long long tiles = batch * ntn;  // < 2^30 (checked by the caller)
   const size_t lds = (size_t)KS * MT * 64 * sizeof(float4);
   // persistent grid of exactly the resident workgroups: every wave walks its
   // tiles from the start, no second round of workgroups and its tail
@@ -316,7 +328,7 @@ hipError_t launch_k(const cf* W, const cf* X, cf* Y, int nb, int na, int nre, lo
   const long long cap = (long long)n_cu * per_cu;
   if (blocks > cap) blocks = cap;
   hipLaunchKernelGGL((k_beamform_k<MT, KS>), dim3((unsigned)blocks), dim3(64 * kWaves), lds, s, W, X, Y, nb, na,
-                     nre, ldx, sx, sy, tiles, ntn, ps);
+                     nre, ldx, sx, sy, (int)tiles, ntn, ps);
   return hipGetLastError();
 }
 
@@ -359,7 +371,8 @@ hipError_t launch_beamform(const cf* W, const cf* X, cf* Y, int n_beams, int n_a
   if (batch <= 0 || n_re <= 0) return hipSuccess;
   PilotScale ps{};
   if (pilot_scale) ps = *pilot_scale;
-  if (n_ant <= 64 && ldx * n_ant < (1ll << 28)) {
+  // 32-bit lane offsets and tile indices (with room for the prefetch index)
+  if (n_ant <= 64 && ldx * n_ant < (1ll << 28) && batch * ((n_re + 15) / 16) < (1ll << 30)) {
     switch ((n_beams + 15) / 16) {
       case 1: return launch_k_mt<1>(W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ps, n_cu, s);
       case 2: return launch_k_mt<2>(W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ps, n_cu, s);
