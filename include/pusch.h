@@ -161,8 +161,8 @@ size_t pusch_slot_workspace_bytes(const pusch_slot_desc* d, long long n_slot);
  * independent slots, enqueued on one stream: OFDM demodulation of every
  * antenna and symbol to the n_sc active subcarriers, beamforming, LS channel
  * estimation on the pilot symbols, MMSE detection of every other ("data")
- * symbol in ascending symbol order.  With n_ue <= 16 the channel estimate is
- * computed inside the detection kernel and never stored.
+ * symbol in ascending symbol order.  With n_ue <= 16 and an even n_beams the
+ * channel estimate is computed inside the detection kernel and never stored.
  *   x_td   [n_slot][n_symb][n_ant][n_fft] time-domain samples.
  *   x_hat  [n_slot][n_data][n_sc][n_ue], n_data = n_symb - n_pilot.
  *   status [n_slot][n_sc] int32 or NULL, as pusch_mmse_solve.
@@ -173,9 +173,35 @@ int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td
                void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Many independent cells of different geometries in one call (the paper runs
+ * many independent small problems side by side, each on its own group of
+ * cores between barriers: Sec. V, Sec. VI).  Cell c is a pusch_slot call
+ * with descriptor d[c], n_slot[c] slots and buffers x_td[c], x_hat[c],
+ * status[c] (status may be NULL, or any status[c] may be NULL).  The cells run
+ * on PUSCH_CELL_STREAMS library-owned side streams of default priority, cell
+ * c on side stream c mod PUSCH_CELL_STREAMS in order, forked from and joined
+ * back to `stream` with events, so the whole call is ordered on `stream` and
+ * can be captured into a HIP graph (after one uncaptured call on the device,
+ * or pusch_init, has built the device tables).
+ *   ws   device workspace of at least pusch_cells_workspace_bytes bytes,
+ *        256-byte aligned: one slice per side stream used, each as large as
+ *        the largest cell's pusch_slot workspace.
+ * Every cell's arguments are checked as for pusch_slot, and no cell's output
+ * may overlap any other cell's buffers or the workspace.  1 <= n_cells <=
+ * PUSCH_MAX_CELLS.  Calls on one device are serialised on the host while
+ * they enqueue; a capture that includes a call holds the side streams until
+ * it ends.
+ */
+#define PUSCH_CELL_STREAMS 4
+#define PUSCH_MAX_CELLS 4096
+size_t pusch_cells_workspace_bytes(const pusch_slot_desc* d, int n_cells, const long long* n_slot);
+int pusch_cells(const pusch_slot_desc* d, int n_cells, const long long* n_slot, const pusch_c32* const* x_td,
+                pusch_c32* const* x_hat, int32_t* const* status, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Stage timing for measurement.  pusch_profile_begin(max_calls) creates
  * HIP events (allocation happens here, not in pusch_slot); while active, each
- * pusch_slot call records an event before and after each of its
+ * pusch_slot call (not the cells of pusch_cells) records an event before and after each of its
  * PUSCH_SLOT_STAGES launches on its stream, for up to max_calls calls.
  * pusch_profile_end(stage_ms, n) synchronises on the last event, writes the
  * summed device time of each stage (ms; order: fft, beamform, chest, mmse)

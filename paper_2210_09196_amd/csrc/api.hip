@@ -3,6 +3,7 @@
 // layout and the launch sequence of the fused slot.
 #include <cmath>
 #include <cstdint>
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -19,6 +20,8 @@ namespace {
 constexpr int kMaxDevices = 64;
 constexpr long long kMaxAnt = 1024;
 
+constexpr int kSideStreams = PUSCH_CELL_STREAMS;
+
 struct DeviceTables {
   std::once_flag once;
   int status = PUSCH_EHIP;
@@ -26,6 +29,11 @@ struct DeviceTables {
   int n_cu = 1;
   std::mutex mu;
   std::map<std::pair<int, int>, cf*> dft_w;  // (n_beams, n_ant) -> device table
+  // pusch_cells: side streams (default priority) and the fork / join events
+  // that tie them to the caller's stream; cells_mu serialises the enqueue
+  hipStream_t side[kSideStreams] = {};
+  hipEvent_t fork = nullptr, join[kSideStreams] = {};
+  std::mutex cells_mu;
 };
 DeviceTables g_dev[kMaxDevices];
 
@@ -47,6 +55,11 @@ int device_tables(DeviceTables** out) {
     if (hipMemcpy(d, host.data(), host.size() * sizeof(cf), hipMemcpyHostToDevice) != hipSuccess) return;
     t.twiddles = static_cast<cf*>(d);
     t.n_cu = ncu;
+    if (hipEventCreateWithFlags(&t.fork, hipEventDisableTiming) != hipSuccess) return;
+    for (int i = 0; i < kSideStreams; ++i)
+      if (hipStreamCreateWithFlags(&t.side[i], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&t.join[i], hipEventDisableTiming) != hipSuccess)
+        return;
     t.status = PUSCH_OK;
   });
   *out = &t;
@@ -277,40 +290,37 @@ SlotLayout slot_layout(const pusch_slot_desc* d, long long n_slot) {
   return lay;
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t pusch_slot_workspace_bytes(const pusch_slot_desc* d, long long n_slot) {
-  if (check_geom(d) != PUSCH_OK || n_slot < 0) return 0;
-  return slot_layout(d, n_slot).total;
+size_t out_bytes(const pusch_slot_desc* d, long long n_slot) {
+  return (size_t)n_slot * (size_t)(d->n_symb - d->n_pilot) * d->n_sc * d->n_ue * 8;
 }
 
-int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td, pusch_c32* x_hat, int32_t* status,
-               void* ws, size_t ws_bytes, void* stream) {
+// Arguments of one slot call (descriptor, buffers, workspace, aliasing).
+int check_slot_call(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td, pusch_c32* x_hat,
+                    int32_t* status, void* ws, size_t ws_bytes) {
   if (int rc = check_desc(d)) return rc;
   if (n_slot < 0 || !x_td || !x_hat || !ws) return PUSCH_EINVAL;
   if (reinterpret_cast<uintptr_t>(ws) & 255) return PUSCH_EINVAL;
   const SlotLayout lay = slot_layout(d, n_slot);
   if (ws_bytes < lay.total) return PUSCH_ENOMEM;
-  const int S = d->n_symb, R = d->n_ant, K = d->n_sc, B = d->n_beams, L = d->n_ue, P = d->n_pilot;
-  const int D = S - P;
-  const long long xb = n_slot * (long long)S * R * d->n_fft * 8, ob = n_slot * (long long)D * K * L * 8,
+  const int S = d->n_symb, R = d->n_ant, K = d->n_sc, B = d->n_beams, P = d->n_pilot;
+  const long long xb = n_slot * (long long)S * R * d->n_fft * 8, ob = (long long)out_bytes(d, n_slot),
                   sb = n_slot * (long long)K * 4, wb = (long long)lay.total;
   if (overlap(x_hat, ob, x_td, xb) || overlap(x_hat, ob, ws, wb) || overlap(x_hat, ob, status, sb) ||
       overlap(ws, wb, x_td, xb) || overlap(status, sb, x_td, xb) || overlap(status, sb, ws, wb) ||
       overlap(ws, wb, d->pilots, n_slot * (long long)P * K * 8) || overlap(ws, wb, d->W, (long long)B * R * 8))
     return PUSCH_EINVAL;
-  if (n_slot == 0) return PUSCH_OK;
+  return PUSCH_OK;
+}
 
-  DeviceTables* t = nullptr;
-  if (int rc = device_tables(&t)) return rc;
+// Launch sequence of one fused slot call on stream s (arguments checked).
+int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td, pusch_c32* x_hat,
+             int32_t* status, char* base, hipStream_t s, bool profile) {
+  const SlotLayout lay = slot_layout(d, n_slot);
+  const int S = d->n_symb, R = d->n_ant, K = d->n_sc, B = d->n_beams, L = d->n_ue, P = d->n_pilot;
+  const int D = S - P;
   const cf* w = reinterpret_cast<const cf*>(d->W);
   if (!w)
     if (int rc = dft_beamformer(t, B, R, &w)) return rc;
-  const hipStream_t s = static_cast<hipStream_t>(stream);
-
-  char* base = static_cast<char*>(ws);
   cf* Xa = reinterpret_cast<cf*>(base + lay.off_xa);
   cf* Y = reinterpret_cast<cf*>(base + lay.off_y);
   cf* H = reinterpret_cast<cf*>(base + lay.off_h);
@@ -318,7 +328,7 @@ int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td
   hipEvent_t* ev = nullptr;
   {
     std::lock_guard<std::mutex> lock(g_prof.mu);
-    if (g_prof.active && g_prof.calls < g_prof.max_calls) ev = &g_prof.ev[(size_t)g_prof.calls++ * kEvPerCall];
+    if (profile && g_prof.active && g_prof.calls < g_prof.max_calls) ev = &g_prof.ev[(size_t)g_prof.calls++ * kEvPerCall];
   }
   auto mark = [&](int i) -> bool { return !ev || hipEventRecord(ev[i], s) == hipSuccess; };
 
@@ -384,6 +394,100 @@ int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td
   if (me != hipSuccess) return PUSCH_EHIP;
   if (!mark(4)) return PUSCH_EHIP;
   return PUSCH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pusch_slot_workspace_bytes(const pusch_slot_desc* d, long long n_slot) {
+  if (check_geom(d) != PUSCH_OK || n_slot < 0) return 0;
+  return slot_layout(d, n_slot).total;
+}
+
+int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td, pusch_c32* x_hat, int32_t* status,
+               void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_slot_call(d, n_slot, x_td, x_hat, status, ws, ws_bytes)) return rc;
+  if (n_slot == 0) return PUSCH_OK;
+  DeviceTables* t = nullptr;
+  if (int rc = device_tables(&t)) return rc;
+  return run_slot(t, d, n_slot, x_td, x_hat, status, static_cast<char*>(ws), static_cast<hipStream_t>(stream), true);
+}
+
+size_t pusch_cells_workspace_bytes(const pusch_slot_desc* d, int n_cells, const long long* n_slot) {
+  if (!d || !n_slot || n_cells < 1) return 0;
+  size_t slice = 0;
+  for (int c = 0; c < n_cells; ++c) {
+    if (check_geom(&d[c]) != PUSCH_OK || n_slot[c] < 0) return 0;
+    slice = std::max(slice, slot_layout(&d[c], n_slot[c]).total);
+  }
+  const int used = n_cells < kSideStreams ? n_cells : kSideStreams;
+  return (size_t)used * align256(slice);
+}
+
+int pusch_cells(const pusch_slot_desc* d, int n_cells, const long long* n_slot, const pusch_c32* const* x_td,
+                pusch_c32* const* x_hat, int32_t* const* status, void* ws, size_t ws_bytes, void* stream) {
+  if (!d || !n_slot || !x_td || !x_hat || n_cells < 1 || n_cells > PUSCH_MAX_CELLS) return PUSCH_EINVAL;
+  size_t slice = 0;
+  for (int c = 0; c < n_cells; ++c) {
+    if (int rc = check_geom(&d[c])) return rc;
+    if (n_slot[c] < 0) return PUSCH_EINVAL;
+    slice = std::max(slice, slot_layout(&d[c], n_slot[c]).total);
+  }
+  slice = align256(slice);
+  const int used = n_cells < kSideStreams ? n_cells : kSideStreams;
+  if (!ws) return PUSCH_EINVAL;
+  if (ws_bytes < (size_t)used * slice) return PUSCH_ENOMEM;
+  // every cell as a pusch_slot call on its workspace slice, and no cell's
+  // output may overlap another cell's output or input
+  for (int c = 0; c < n_cells; ++c) {
+    char* wsc = static_cast<char*>(ws) + (size_t)(c % kSideStreams) * slice;
+    if (int rc = check_slot_call(&d[c], n_slot[c], x_td[c], x_hat[c], status ? status[c] : nullptr, wsc, slice))
+      return rc;
+    const long long ob = out_bytes(&d[c], n_slot[c]), sb = n_slot[c] * (long long)d[c].n_sc * 4;
+    const long long xb_c = n_slot[c] * (long long)d[c].n_symb * d[c].n_ant * d[c].n_fft * 8;
+    const long long wall = (long long)used * (long long)slice;  // every slice is in use at once
+    if (overlap(ws, wall, x_hat[c], ob) || overlap(ws, wall, status ? status[c] : nullptr, sb) ||
+        overlap(ws, wall, x_td[c], xb_c) ||
+        overlap(ws, wall, d[c].pilots, n_slot[c] * (long long)d[c].n_pilot * d[c].n_sc * 8) ||
+        overlap(ws, wall, d[c].W, (long long)d[c].n_beams * d[c].n_ant * 8))
+      return PUSCH_EINVAL;
+    for (int e = 0; e < n_cells; ++e) {
+      if (e == c) continue;
+      const long long xb = n_slot[e] * (long long)d[e].n_symb * d[e].n_ant * d[e].n_fft * 8;
+      const long long ob2 = out_bytes(&d[e], n_slot[e]), sb2 = n_slot[e] * (long long)d[e].n_sc * 4;
+      const void* st_c = status ? status[c] : nullptr;
+      const void* st_e = status ? status[e] : nullptr;
+      if (overlap(x_hat[c], ob, x_td[e], xb) || overlap(x_hat[c], ob, x_hat[e], ob2) ||
+          overlap(x_hat[c], ob, st_e, sb2) || overlap(st_c, sb, x_td[e], xb) || overlap(st_c, sb, st_e, sb2) ||
+          overlap(x_hat[c], ob, d[e].pilots, n_slot[e] * (long long)d[e].n_pilot * d[e].n_sc * 8) ||
+          overlap(st_c, sb, d[e].pilots, n_slot[e] * (long long)d[e].n_pilot * d[e].n_sc * 8))
+        return PUSCH_EINVAL;
+    }
+  }
+  DeviceTables* t = nullptr;
+  if (int rc = device_tables(&t)) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lock(t->cells_mu);
+  // fork: every side stream used waits for the caller's stream
+  if (hipEventRecord(t->fork, s) != hipSuccess) return PUSCH_EHIP;
+  for (int i = 0; i < used; ++i)
+    if (hipStreamWaitEvent(t->side[i], t->fork, 0) != hipSuccess) return PUSCH_EHIP;
+  // cell c on side stream c mod kSideStreams, in order on that stream, so
+  // the cells sharing a workspace slice never overlap in time
+  int rc = PUSCH_OK;
+  for (int c = 0; c < n_cells && rc == PUSCH_OK; ++c) {
+    if (n_slot[c] == 0) continue;
+    char* wsc = static_cast<char*>(ws) + (size_t)(c % kSideStreams) * slice;
+    rc = run_slot(t, &d[c], n_slot[c], x_td[c], x_hat[c], status ? status[c] : nullptr, wsc,
+                  t->side[c % kSideStreams], false);
+  }
+  // join (also after a failed launch, so the caller's stream never runs
+  // ahead of work already enqueued on a side stream)
+  for (int i = 0; i < used; ++i)
+    if (hipEventRecord(t->join[i], t->side[i]) != hipSuccess || hipStreamWaitEvent(s, t->join[i], 0) != hipSuccess)
+      rc = PUSCH_EHIP;
+  return rc;
 }
 
 int pusch_profile_begin(int max_calls) {

@@ -20,7 +20,7 @@ __global__ __launch_bounds__(256) void k_chest(const cf* __restrict__ Y, const c
                                                ChestGeom g, long long batch, int per_item) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= per_item) return;
-  const int nb = g.n_beams, nue = g.n_ue, nsc = g.n_sc;
+  const int nb = g.n_beams, nue = g.n_ue;
   const int nbc = nb / NBV;
   const int bc = idx % nbc;
   const int r = idx / nbc;

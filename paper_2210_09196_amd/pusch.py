@@ -55,6 +55,9 @@ _SIG = {
     "pusch_mmse_solve": (_I, [_P, _P, _F, _P, _I, _I, _I, _I, _LL, _P, _P]),
     "pusch_slot_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SlotDesc), _LL]),
     "pusch_slot": (_I, [ctypes.POINTER(SlotDesc), _LL, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "pusch_cells_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SlotDesc), _I, ctypes.POINTER(_LL)]),
+    "pusch_cells": (_I, [ctypes.POINTER(SlotDesc), _I, ctypes.POINTER(_LL), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                         ctypes.POINTER(_P), _P, ctypes.c_size_t, _P]),
     "pusch_profile_begin": (_I, [_I]),
     "pusch_profile_end": (_I, [ctypes.POINTER(_F), _I]),
 }
@@ -241,6 +244,89 @@ class Slot:
         _check(lib().pusch_slot(ctypes.byref(d), self.n_slot, x_td.data_ptr(), x_hat.data_ptr(), _ptr(status),
                                 self.ws.data_ptr(), self.ws_bytes, _stream()), "pusch_slot")
         return x_hat, status
+
+
+def _fill_desc(d: SlotDesc, n_ant, n_fft, n_sc, n_symb, n_beams, n_ue, pilot_symb, sigma2, W) -> None:
+    pilot_symb = list(pilot_symb)
+    if not 1 <= len(pilot_symb) <= MAX_PILOTS:
+        raise PuschError("1..4 pilot symbols")
+    d.n_ant, d.n_fft, d.n_sc, d.n_symb = n_ant, n_fft, n_sc, n_symb
+    d.n_beams, d.n_ue, d.n_pilot = n_beams, n_ue, len(pilot_symb)
+    for j, s in enumerate(pilot_symb):
+        d.pilot_symb[j] = s
+    d.sigma2 = float(sigma2)
+    d.W = _ptr(W)
+
+
+class Cells:
+    """Independent cells of different slot geometries, run by one pusch_cells call.
+
+    Each cell is a dict with the slot geometry (n_ant, n_fft, n_sc, n_symb,
+    n_beams, n_ue, pilot_symb), sigma2, n_slot (>= 1) and optionally W.  The
+    workspace is allocated once here; a call enqueues every cell on the
+    library's side streams, forked from and joined back to the current torch
+    stream, so it can be captured into a CUDA/HIP graph.
+    """
+
+    def __init__(self, cells: list[dict], device="cuda"):
+        n = len(cells)
+        if n < 1:
+            raise PuschError("at least one cell")
+        self.n = n
+        self.descs = (SlotDesc * n)()
+        self.n_slot = (_LL * n)()
+        self.W = []
+        self.geom = []
+        for c, g in enumerate(cells):
+            if int(g["n_slot"]) < 1:
+                raise PuschError("every cell needs n_slot >= 1")
+            W = g.get("W")
+            W = None if W is None else _c64(W, "W")
+            self.W.append(W)
+            _fill_desc(self.descs[c], g["n_ant"], g["n_fft"], g["n_sc"], g["n_symb"], g["n_beams"], g["n_ue"],
+                       g["pilot_symb"], g["sigma2"], W)
+            self.n_slot[c] = int(g["n_slot"])
+            self.geom.append(dict(g))
+        nbytes = lib().pusch_cells_workspace_bytes(self.descs, n, self.n_slot)
+        if nbytes == 0:
+            raise PuschError("pusch_cells_workspace_bytes rejected a cell geometry")
+        self.ws = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+        self.ws_bytes = int(nbytes)
+
+    def outputs(self, device="cuda"):
+        """Fresh (x_hat, status) tensors for every cell."""
+        xs, st = [], []
+        for c in range(self.n):
+            d = self.descs[c]
+            xs.append(torch.empty(self.n_slot[c], d.n_symb - d.n_pilot, d.n_sc, d.n_ue, dtype=torch.complex64,
+                                  device=device))
+            st.append(torch.empty(self.n_slot[c], d.n_sc, dtype=torch.int32, device=device))
+        return xs, st
+
+    def __call__(self, x_tds, pilots, x_hats=None, statuses=None):
+        if len(x_tds) != self.n or len(pilots) != self.n:
+            raise PuschError(f"{self.n} x_td and pilots tensors expected")
+        if x_hats is None:
+            x_hats, statuses = self.outputs(x_tds[0].device)
+        for c in range(self.n):
+            d = self.descs[c]
+            _c64(x_tds[c], "x_td")
+            _c64(pilots[c], "pilots")
+            _c64(x_hats[c], "x_hat")
+            ns = self.n_slot[c]
+            if tuple(x_tds[c].shape) != (ns, d.n_symb, d.n_ant, d.n_fft):
+                raise PuschError(f"cell {c}: x_td must be [{ns}, {d.n_symb}, {d.n_ant}, {d.n_fft}]")
+            if tuple(pilots[c].shape) != (ns, d.n_pilot, d.n_sc):
+                raise PuschError(f"cell {c}: pilots must be [{ns}, {d.n_pilot}, {d.n_sc}]")
+            if tuple(x_hats[c].shape) != (ns, d.n_symb - d.n_pilot, d.n_sc, d.n_ue):
+                raise PuschError(f"cell {c}: x_hat has the wrong shape")
+            d.pilots = pilots[c].data_ptr()
+        xp = (_P * self.n)(*[t.data_ptr() for t in x_tds])
+        op = (_P * self.n)(*[t.data_ptr() for t in x_hats])
+        sp = None if statuses is None else (_P * self.n)(*[_ptr(t) for t in statuses])
+        _check(lib().pusch_cells(self.descs, self.n, self.n_slot, xp, op, sp, self.ws.data_ptr(), self.ws_bytes,
+                                 _stream()), "pusch_cells")
+        return x_hats, statuses
 
 
 def profile_begin(max_calls: int) -> None:

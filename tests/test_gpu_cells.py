@@ -1,0 +1,105 @@
+"""GPU parity of pusch_cells: independent cells of different geometries in one
+call (side streams forked from and joined to the caller's stream).
+
+Each cell must match the FP64 oracle (detected symbols NRMSE <= 1e-4, no
+status flags) and be bit-identical to the same cell run alone by pusch_slot
+(same kernels, same inputs).  A captured graph of the call, replayed several
+times with eager work in between, must reproduce the eager result exactly.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import metrics as M
+from oracle import pusch_oracle as O
+from paper_2210_09196_amd import pusch, synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+TOL_X = 1e-4
+
+# (geometry over the small workload's defaults, slots per cell)
+CELLS = [
+    (dict(), 1),
+    (dict(n_ant=16, n_fft=1024, n_sc=825, n_beams=8, n_ue=4, pilot_symb=(2,), qam_bits=2, channel="tdl"), 2),
+    (dict(n_ant=32, n_fft=2048, n_sc=1650, n_beams=16, n_ue=8, pilot_symb=(2, 11), qam_bits=8, channel="tdl"), 1),
+    (dict(n_ant=8, n_fft=64, n_sc=60, n_beams=8, n_ue=3, pilot_symb=(3, 9), qam_bits=4), 1),
+    # odd beam count: stand-alone estimation kernel and a stored estimate
+    (dict(n_beams=15), 1),
+    (dict(n_ant=64, n_fft=4096, n_sc=3300, n_beams=32, n_ue=16, pilot_symb=(2, 11), qam_bits=6, channel="tdl"), 1),
+]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def make_cells(cells, seed0=700):
+    cfgs, batches, geoms = [], [], []
+    for c, (geom, n_slot) in enumerate(cells):
+        cfg = synth.CFG1.replace(snr_db=25.0, **geom)
+        b = synth.make_batch(cfg, [seed0 + 10 * c + k for k in range(n_slot)])
+        cfgs.append(cfg)
+        batches.append(b)
+        geoms.append(dict(n_ant=cfg.n_ant, n_fft=cfg.n_fft, n_sc=cfg.n_sc, n_symb=cfg.n_symb, n_beams=cfg.n_beams,
+                          n_ue=cfg.n_ue, pilot_symb=cfg.pilot_symb, sigma2=b["sigma2"], n_slot=n_slot))
+    return cfgs, batches, geoms
+
+
+def test_cells_match_oracle_and_single_slot_calls():
+    cfgs, batches, geoms = make_cells(CELLS)
+    print(f"[cells] {len(CELLS)} cells", flush=True)
+    cells = pusch.Cells(geoms)
+    xs = [dev(b["x_td"]) for b in batches]
+    ps = [dev(b["pilots"]) for b in batches]
+    xh, st = cells(xs, ps)
+    for c, (cfg, b, g) in enumerate(zip(cfgs, batches, geoms)):
+        got, flags = host(xh[c]), host(st[c])
+        assert np.all(flags == 0), c
+        slot = pusch.Slot(cfg.n_ant, cfg.n_fft, cfg.n_sc, cfg.n_symb, cfg.n_beams, cfg.n_ue, cfg.pilot_symb,
+                          b["sigma2"], g["n_slot"])
+        alone, alone_st = slot(xs[c], ps[c])
+        assert torch.equal(alone, xh[c]) and torch.equal(alone_st, st[c]), c
+        for k in range(g["n_slot"]):
+            ref = O.receive_slot(b["x_td"][k], b["pilots"][k], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
+                                 n_beams=cfg.n_beams)
+            assert M.nrmse(got[k], ref["x_hat"]) <= TOL_X, (c, k)
+
+
+def test_cells_graph_replay_matches_eager():
+    cfgs, batches, geoms = make_cells(CELLS[:5], seed0=900)
+    cells = pusch.Cells(geoms)
+    xs = [dev(b["x_td"]) for b in batches]
+    ps = [dev(b["pilots"]) for b in batches]
+    ref, ref_st = cells(xs, ps)  # eager call: builds every device table before the capture
+    torch.cuda.synchronize()
+    out, out_st = cells.outputs()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        cells(xs, ps, out, out_st)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        cells(xs, ps, out, out_st)
+    for r in range(3):
+        for t in out:
+            t.zero_()
+        for t in out_st:
+            t.fill_(-1)
+        g.replay()
+        torch.cuda.synchronize()
+        for c in range(len(geoms)):
+            assert torch.equal(out[c], ref[c]) and torch.equal(out_st[c], ref_st[c]), (r, c)
+        # eager work between replays, on the same buffers the graph does not use
+        e, e_st = cells(xs, ps)
+        torch.cuda.synchronize()
+        for c in range(len(geoms)):
+            assert torch.equal(e[c], ref[c]), (r, c)

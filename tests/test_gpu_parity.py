@@ -38,7 +38,7 @@ def assert_grid(got, ref, tol=TOL_GRID):
     assert e <= tol and m <= 10 * tol, f"nrmse {e:.3e} max-rel {m:.3e}"
 
 
-# ----------------------------------------------------------------------------- a1 FFT
+# ----------------------------------------------------------------------------- OFDM demodulation (FFT)
 
 ACTIVE = {64: 63, 256: 256, 1024: 825, 2048: 1650, 4096: 3300}
 
@@ -89,7 +89,7 @@ def test_fft_full_size_sampled():
     assert_grid(host(X[torch.as_tensor(idx, device=DEV)]), O.ofdm_demodulate(xs, 3300))
 
 
-# ----------------------------------------------------------------------------- a2 beamforming
+# ----------------------------------------------------------------------------- beamforming
 
 @pytest.mark.parametrize("nb,na,n_re,ld_x,batch,builtin", [
     (16, 16, 256, 256, 14, True),  # 16x16 DFT beamformer, 256 subcarriers
@@ -124,7 +124,7 @@ def test_beamform_full_size_sampled():
     assert_grid(host(Y[torch.as_tensor(bi, device=DEV), torch.as_tensor(n, device=DEV)]), ref)
 
 
-# ----------------------------------------------------------------------------- a3 LS channel estimate
+# ----------------------------------------------------------------------------- LS channel estimate
 
 @pytest.mark.parametrize("nb,nue,nsc,npil,batch", [
     (16, 4, 256, 1, 1),
@@ -146,7 +146,7 @@ def test_chest(nb, nue, nsc, npil, batch):
         assert_grid(H[b], np.swapaxes(ref, 1, 2))
 
 
-# ----------------------------------------------------------------------------- a4-a6 MMSE
+# ----------------------------------------------------------------------------- MMSE detection
 
 @pytest.mark.parametrize("nb,nue,nsc,nd,batch,s2", [
     (16, 4, 256, 13, 1, 0.01),
@@ -189,7 +189,7 @@ def test_mmse_status_flags():
     assert M.nrmse(x[0][:, keep], ref[:, keep]) <= TOL_X
 
 
-# ----------------------------------------------------------------------------- a7 fused slot
+# ----------------------------------------------------------------------------- fused slot
 
 def run_slot(cfg, data, n_slot=None, W=None):
     xs, ps = data["x_td"], data["pilots"]
