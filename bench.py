@@ -116,6 +116,98 @@ def calibrate_copy() -> int:
     return 0
 
 
+def cells_geometries(n_cells: int, seed: int = 4000) -> list[dict]:
+    """Seeded draw of uneven cells: N in {1024, 2048, 4096} with N*3300/4096
+    active subcarriers, 16/32/64 antennas, beams = antennas / 2, 4..16 UEs,
+    pilots on symbols 2 and 11, one slot each."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_cells):
+        n_fft = int(rng.choice([1024, 2048, 4096]))
+        n_ant = int(rng.choice([16, 32, 64]))
+        n_beams = n_ant // 2
+        n_ue = int(rng.integers(4, min(16, n_beams) + 1))
+        out.append(dict(n_ant=n_ant, n_fft=n_fft, n_sc=n_fft * 3300 // 4096, n_symb=14, n_beams=n_beams, n_ue=n_ue,
+                        pilot_symb=(2, 11), sigma2=0.01, n_slot=1))
+    return out
+
+
+def bench_cells(n_cells: int, steps: int, warmup: int) -> int:
+    """Batched uneven cells: one pusch_cells call over n_cells cells of
+    different geometries, replayed from a captured HIP graph, against the same
+    cells as plain pusch_slot calls one after another on one stream."""
+    import torch
+
+    from paper_2210_09196_amd import pusch
+
+    geoms = cells_geometries(n_cells)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4001)
+    xs, ps = [], []
+    for c in geoms:
+        # seeded complex Gaussian samples of the cell's shape (the chain's
+        # work does not depend on the values) and QPSK pilots
+        xs.append(torch.view_as_complex(torch.randn(1, 14, c["n_ant"], c["n_fft"], 2, generator=g, device="cuda"))
+                  .contiguous() * 0.05)
+        ph = torch.randint(0, 4, (1, 2, c["n_sc"]), generator=g, device="cuda").float() * (np.pi / 2) + np.pi / 4
+        ps.append(torch.polar(torch.ones_like(ph), ph).to(torch.complex64).contiguous())
+    cells = pusch.Cells(geoms)
+    out, out_st = cells.outputs()
+
+    def timed(fn, n):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        return np.array([a.elapsed_time(b) * 1e3 for a, b in ev])  # us per call
+
+    run = lambda: cells(xs, ps, out, out_st)
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    eager = timed(run, steps)
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        run()
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    replay = timed(graph.replay, steps)
+    slots = [pusch.Slot(c["n_ant"], c["n_fft"], c["n_sc"], 14, c["n_beams"], c["n_ue"], c["pilot_symb"], c["sigma2"], 1)
+             for c in geoms]
+
+    def sequential():
+        for k, sl in enumerate(slots):
+            sl(xs[k], ps[k], out[k], out_st[k])
+
+    for _ in range(warmup):
+        sequential()
+    torch.cuda.synchronize()
+    seq = timed(sequential, steps)
+    per = lambda a, q: round(float(np.percentile(a, q)) / n_cells, 3)
+    mix = {f"N{n}": sum(c["n_fft"] == n for c in geoms) for n in (1024, 2048, 4096)}
+    mix.update({f"ant{a}": sum(c["n_ant"] == a for c in geoms) for a in (16, 32, 64)})
+    print(json.dumps({
+        "metric": "batched uneven cells: us/slot", "value": per(replay, 50), "unit": "us/slot",
+        "higher_is_better": False, "cells": n_cells, "steps": steps, "warmup": warmup,
+        "graph_p50_us_per_slot": per(replay, 50), "graph_p99_us_per_slot": per(replay, 99),
+        "eager_p50_us_per_slot": per(eager, 50), "eager_p99_us_per_slot": per(eager, 99),
+        "sequential_slot_calls_p50_us_per_slot": per(seq, 50),
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{n_cells} uneven cells, one slot each: N in 1024/2048/4096 (N*3300/4096 active), "
+                               f"16/32/64 antennas, beams = antennas/2, 4-16 UEs, pilots 2+11", "mix": mix},
+    }), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,9 +220,16 @@ def main() -> int:
                          "(for profiler passes; kernel time and traffic do not depend on the values)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
+    ap.add_argument("--cells", type=int, default=0,
+                    help="instead: time one pusch_cells call over this many uneven cells (graph replay)")
     args = ap.parse_args()
     if args.calibrate_copy:
         return calibrate_copy()
+    if args.cells > 0:
+        if not os.path.exists(os.path.join(ROOT, "paper_2210_09196_amd", "libpusch.so")):
+            from paper_2210_09196_amd.build import build
+            build()
+        return bench_cells(args.cells, min(args.steps, 100), min(args.warmup, 10))
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); slots are independent, so a "
               f"multi-GPU run would split the slot batch with no communication -- see the design notes.",
