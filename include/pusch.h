@@ -173,6 +173,22 @@ int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td
                void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * The same chain with the active-bin grids between OFDM demodulation and
+ * beamforming stored in FP16 instead of FP32 (the paper's chain works on
+ * 32-bit words, Sec. VI; this is a reduced-precision form of it): every
+ * antenna row of every symbol is scaled by a power of two chosen from its
+ * time-domain L1 norm, which bounds every output bin, so nothing overflows;
+ * beamforming widens each value back to FP32 and undoes the scale exactly.
+ * All arithmetic stays FP32, so the only extra error is the FP16 rounding of
+ * the grids (relative 2^-11 per value).  It halves the bytes those grids
+ * move through HBM.  Arguments and results as pusch_slot; n_ant <= 64
+ * (PUSCH_EUNSUPPORTED otherwise).
+ */
+size_t pusch_slot_mixed_workspace_bytes(const pusch_slot_desc* d, long long n_slot);
+int pusch_slot_mixed(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td, pusch_c32* x_hat,
+                     int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Many independent cells of different geometries in one call (the paper runs
  * many independent small problems side by side, each on its own group of
  * cores between barriers: Sec. V, Sec. VI).  Cell c is a pusch_slot call

@@ -239,7 +239,7 @@ int pusch_mmse_solve(const pusch_c32* H, const pusch_c32* Yd, float sigma2, pusc
 namespace {
 
 struct SlotLayout {
-  size_t off_xa, off_y, off_h, off_comb, total;
+  size_t off_xa, off_ex, off_y, off_h, off_comb, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -275,11 +275,22 @@ int check_desc(const pusch_slot_desc* d) {
 // tile touches.
 size_t xa_pitch(int n_sc) { return ((size_t)n_sc + 15) & ~(size_t)15; }
 
-SlotLayout slot_layout(const pusch_slot_desc* d, long long n_slot) {
+// Mixed precision: the active-bin grids as FP16 pairs (4 bytes), rows padded
+// to 32 subcarriers (one 128-byte line), and an int8 exponent table of 64
+// entries per slot symbol.
+size_t xa_pitch_h16(int n_sc) { return ((size_t)n_sc + 31) & ~(size_t)31; }
+
+SlotLayout slot_layout(const pusch_slot_desc* d, long long n_slot, bool mixed = false) {
   const size_t S = d->n_symb, R = d->n_ant, K = d->n_sc, B = d->n_beams, L = d->n_ue, n = (size_t)n_slot;
   SlotLayout lay;
   lay.off_xa = 0;
-  lay.off_y = align256(n * S * R * xa_pitch(d->n_sc) * 8);
+  if (mixed) {
+    lay.off_ex = align256(n * S * R * xa_pitch_h16(d->n_sc) * 4);
+    lay.off_y = lay.off_ex + align256(n * S * 64);
+  } else {
+    lay.off_ex = 0;
+    lay.off_y = align256(n * S * R * xa_pitch(d->n_sc) * 8);
+  }
   lay.off_h = lay.off_y + align256(n * S * K * B * 8);
   // when the detection kernel estimates the channel itself (up to 16 UEs, an
   // even number of beams) no stored estimate is needed
@@ -290,17 +301,24 @@ SlotLayout slot_layout(const pusch_slot_desc* d, long long n_slot) {
   return lay;
 }
 
+// The FP16 path runs on the register-tile beamforming kernel: up to 64
+// antennas, 32-bit tile indices.
+bool mixed_supported(const pusch_slot_desc* d, long long n_slot) {
+  return d->n_ant <= 64 && n_slot * d->n_symb * (((long long)d->n_sc + 15) / 16) < (1ll << 30);
+}
+
 size_t out_bytes(const pusch_slot_desc* d, long long n_slot) {
   return (size_t)n_slot * (size_t)(d->n_symb - d->n_pilot) * d->n_sc * d->n_ue * 8;
 }
 
 // Arguments of one slot call (descriptor, buffers, workspace, aliasing).
 int check_slot_call(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td, pusch_c32* x_hat,
-                    int32_t* status, void* ws, size_t ws_bytes) {
+                    int32_t* status, void* ws, size_t ws_bytes, bool mixed = false) {
   if (int rc = check_desc(d)) return rc;
   if (n_slot < 0 || !x_td || !x_hat || !ws) return PUSCH_EINVAL;
   if (reinterpret_cast<uintptr_t>(ws) & 255) return PUSCH_EINVAL;
-  const SlotLayout lay = slot_layout(d, n_slot);
+  if (mixed && !mixed_supported(d, n_slot)) return PUSCH_EUNSUPPORTED;
+  const SlotLayout lay = slot_layout(d, n_slot, mixed);
   if (ws_bytes < lay.total) return PUSCH_ENOMEM;
   const int S = d->n_symb, R = d->n_ant, K = d->n_sc, B = d->n_beams, P = d->n_pilot;
   const long long xb = n_slot * (long long)S * R * d->n_fft * 8, ob = (long long)out_bytes(d, n_slot),
@@ -314,8 +332,8 @@ int check_slot_call(const pusch_slot_desc* d, long long n_slot, const pusch_c32*
 
 // Launch sequence of one fused slot call on stream s (arguments checked).
 int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td, pusch_c32* x_hat,
-             int32_t* status, char* base, hipStream_t s, bool profile) {
-  const SlotLayout lay = slot_layout(d, n_slot);
+             int32_t* status, char* base, hipStream_t s, bool profile, bool mixed = false) {
+  const SlotLayout lay = slot_layout(d, n_slot, mixed);
   const int S = d->n_symb, R = d->n_ant, K = d->n_sc, B = d->n_beams, L = d->n_ue, P = d->n_pilot;
   const int D = S - P;
   const cf* w = reinterpret_cast<const cf*>(d->W);
@@ -334,9 +352,11 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
 
   // OFDM demodulation (FFT) of every antenna and symbol, active bins only
   if (!mark(0)) return PUSCH_EHIP;
-  const long long KP = (long long)xa_pitch(K);
+  const long long KP = mixed ? (long long)xa_pitch_h16(K) : (long long)xa_pitch(K);
+  unsigned* Xh = mixed ? reinterpret_cast<unsigned*>(base + lay.off_xa) : nullptr;
+  signed char* ex = mixed ? reinterpret_cast<signed char*>(base + lay.off_ex) : nullptr;
   if (pusch::launch_fft(reinterpret_cast<const cf*>(x_td), Xa, d->n_fft, n_slot * S * R, K, K / 2, KP, t->twiddles,
-                        t->n_cu, s) != hipSuccess)
+                        t->n_cu, s, Xh, ex, R) != hipSuccess)
     return PUSCH_EHIP;
   // beamforming of every symbol, RE-major output; when the detection
   // kernel estimates the channel itself, the pilot symbols leave this stage
@@ -352,7 +372,7 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   }
   if (!mark(1)) return PUSCH_EHIP;
   if (pusch::launch_beamform(w, Xa, Y, B, R, K, KP, R * KP, (long long)K * B, n_slot * S, t->n_cu, s,
-                             fused ? &psc : nullptr) != hipSuccess)
+                             fused ? &psc : nullptr, Xh, ex) != hipSuccess)
     return PUSCH_EHIP;
   // LS channel estimate from the pilot symbols
   if (!mark(2)) return PUSCH_EHIP;
@@ -412,6 +432,21 @@ int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td
   DeviceTables* t = nullptr;
   if (int rc = device_tables(&t)) return rc;
   return run_slot(t, d, n_slot, x_td, x_hat, status, static_cast<char*>(ws), static_cast<hipStream_t>(stream), true);
+}
+
+size_t pusch_slot_mixed_workspace_bytes(const pusch_slot_desc* d, long long n_slot) {
+  if (check_geom(d) != PUSCH_OK || n_slot < 0 || !mixed_supported(d, n_slot)) return 0;
+  return slot_layout(d, n_slot, true).total;
+}
+
+int pusch_slot_mixed(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td, pusch_c32* x_hat,
+                     int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_slot_call(d, n_slot, x_td, x_hat, status, ws, ws_bytes, true)) return rc;
+  if (n_slot == 0) return PUSCH_OK;
+  DeviceTables* t = nullptr;
+  if (int rc = device_tables(&t)) return rc;
+  return run_slot(t, d, n_slot, x_td, x_hat, status, static_cast<char*>(ws), static_cast<hipStream_t>(stream), true,
+                  true);
 }
 
 size_t pusch_cells_workspace_bytes(const pusch_slot_desc* d, int n_cells, const long long* n_slot) {

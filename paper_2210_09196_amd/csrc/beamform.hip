@@ -18,6 +18,8 @@
 // Optional epilogue for the fused slot: outputs of pilot symbols are turned
 // into LS channel values y * conj(p) / |p|^2 before they are stored (the
 // element-wise division of the paper's channel-estimation step).
+#include <hip/hip_fp16.h>
+
 #include "comb_ls.h"
 #include "kernels.h"
 
@@ -194,11 +196,27 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform(const cf* __restrict__
 // value per lane); the next tile's loads are in flight while the current
 // tile's MFMAs run (ping-pong over a tile loop unrolled by two).  Half the
 // accumulators of the 32-RE tile, so two tiles of X fit next to them.
-template <int MT, int KS>
+// X operand of one tile: FP32 pairs, or (H16) FP16 pairs (half2 words, re
+// low) plus the 16 exponents of this lane's antennas 4 ks + kq (launch_fft's
+// table: 16 consecutive bytes per lane).
+template <int KS, bool H16>
+struct XBuf {
+  cf x[KS];
+};
+template <int KS>
+struct XBuf<KS, true> {
+  unsigned w[KS];
+  int4 e;
+};
+
+// H16: each FP16 value is widened to FP32 and rescaled by its row's power of
+// two exactly, before the FP32 MFMAs.
+template <int MT, int KS, bool H16>
 __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict__ W, const cf* __restrict__ X,
-                                                            cf* __restrict__ Y, int nb, int na, int nre,
-                                                            long long ldx, long long sx, long long sy, int ntiles,
-                                                            int ntn, PilotScale ps) {
+                                                            const unsigned* __restrict__ Xh,
+                                                            const signed char* __restrict__ ex, cf* __restrict__ Y,
+                                                            int nb, int na, int nre, long long ldx, long long sx,
+                                                            long long sy, int ntiles, int ntn, PilotScale ps) {
   extern __shared__ float4 wl[];  // [ks][m][lane] = (Wr, Wi, Wr + Wi, 0); zero for padded antennas / beams
   const int lane = threadIdx.x & 63;
   const int col = lane & 15;  // A row / B column / D column inside a 16x16 tile
@@ -218,23 +236,33 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict
   // clamped in bounds: padded antennas meet zero W entries, REs past n_re are
   // not stored, and a tile index past the end re-reads the last tile (such a
   // prefetch is dropped).
-  auto load = [&](cf (&x)[KS], int tile) {
+  auto load = [&](XBuf<KS, H16>& xb, int tile) {
     tile = tile < ntiles ? tile : ntiles - 1;
     const int bi = tile / ntn;
     const int n = (tile - bi * ntn) * 16 + col;
-    const cf* base = X + bi * sx;
     const unsigned nn = (unsigned)(n < nre ? n : nre - 1);
+    if constexpr (H16) {
+      const unsigned* base = Xh + bi * sx;
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int a = ks * 4 + kq;
-      x[ks] = base[(unsigned)(a < na ? a : na - 1) * (unsigned)ldx + nn];
+      for (int ks = 0; ks < KS; ++ks) {
+        const int a = ks * 4 + kq;
+        xb.w[ks] = base[(unsigned)(a < na ? a : na - 1) * (unsigned)ldx + nn];
+      }
+      xb.e = *reinterpret_cast<const int4*>(ex + (long long)bi * 64 + kq * 16);
+    } else {
+      const cf* base = X + bi * sx;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int a = ks * 4 + kq;
+        xb.x[ks] = base[(unsigned)(a < na ? a : na - 1) * (unsigned)ldx + nn];
+      }
     }
   };
   // X is the A operand and W the B operand, so the result tile is
   // D[RE][beam]: lane (kq, col) receives REs n0 + 4 kq + v of beam col, and
   // sixteen consecutive lanes hold one RE's sixteen consecutive beams (each
   // store instruction writes whole 128-byte lines).
-  auto compute = [&](const cf (&x)[KS], int tile) {
+  auto compute = [&](const XBuf<KS, H16>& xb, int tile) {
     const int bi = tile / ntn;
     const int n0 = (tile - bi * ntn) * 16;
     f32x4 t1[MT], t2[MT], t3[MT];
@@ -242,7 +270,20 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict
     for (int m = 0; m < MT; ++m) t1[m] = t2[m] = t3[m] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const float xr = x[ks].r, xi = x[ks].i, xs = xr + xi;
+      float xr, xi;
+      if constexpr (H16) {
+        const int ew = (ks >> 2) == 0 ? xb.e.x : ((ks >> 2) == 1 ? xb.e.y : ((ks >> 2) == 2 ? xb.e.z : xb.e.w));
+        // exponents of padded antennas (never written) are taken as 0: the
+        // value only meets a zero W entry, it just has to be finite
+        const int e = ks * 4 + kq < na ? (int)__builtin_amdgcn_sbfe((unsigned)ew, 8 * (ks & 3), 8) : 0;
+        const unsigned u = xb.w[ks];
+        xr = ldexpf(__half2float(__ushort_as_half((unsigned short)(u & 0xffffu))), -e);
+        xi = ldexpf(__half2float(__ushort_as_half((unsigned short)(u >> 16))), -e);
+      } else {
+        xr = xb.x[ks].r;
+        xi = xb.x[ks].i;
+      }
+      const float xs = xr + xi;
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
         const float4 w = wl[(ks * MT + m) * 64 + lane];
@@ -297,7 +338,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict
     }
   };
   if (t0 >= ntiles) return;
-  cf xa[KS], xb[KS];
+  XBuf<KS, H16> xa, xb;
   load(xa, t0);
   for (int t = t0; t < ntiles; t += 2 * nwave) {
     load(xb, t + nwave);
@@ -309,9 +350,11 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict
   }
 }
 
-template <int MT, int KS>
-hipError_t launch_k(const cf* W, const cf* X, cf* Y, int nb, int na, int nre, long long ldx, long long sx,
-                    long long sy, long long batch, const PilotScale& ps, int n_cu, hipStream_t s) {
+template <int MT, int KS, bool H16>
+hipError_t launch_k(const cf* W, const cf* X, const unsigned* Xh, const signed char* ex, cf* Y, int nb, int na,
+                    int nre,
+                    long long ldx, long long sx, long long sy, long long batch, const PilotScale& ps, int n_cu,
+                    hipStream_t s) {
   const int ntn = (nre + 15) / 16;
   const long long tiles = batch * ntn;  // < 2^30 (checked by the caller)
   const size_t lds = (size_t)KS * MT * 64 * sizeof(float4);
@@ -319,7 +362,7 @@ hipError_t launch_k(const cf* W, const cf* X, cf* Y, int nb, int na, int nre, lo
   // tiles from the start, no second round of workgroups and its tail
   static const int per_cu = [&] {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_beamform_k<MT, KS>, 64 * kWaves, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_beamform_k<MT, KS, H16>, 64 * kWaves, lds) != hipSuccess ||
         n < 1)
       n = 1;
     return n;
@@ -327,17 +370,23 @@ hipError_t launch_k(const cf* W, const cf* X, cf* Y, int nb, int na, int nre, lo
   long long blocks = (tiles + kWaves - 1) / kWaves;
   const long long cap = (long long)n_cu * per_cu;
   if (blocks > cap) blocks = cap;
-  hipLaunchKernelGGL((k_beamform_k<MT, KS>), dim3((unsigned)blocks), dim3(64 * kWaves), lds, s, W, X, Y, nb, na,
-                     nre, ldx, sx, sy, (int)tiles, ntn, ps);
+  hipLaunchKernelGGL((k_beamform_k<MT, KS, H16>), dim3((unsigned)blocks), dim3(64 * kWaves), lds, s, W, X, Xh, ex,
+                     Y, nb, na, nre, ldx, sx, sy, (int)tiles, ntn, ps);
   return hipGetLastError();
 }
 
 template <int MT>
-hipError_t launch_k_mt(const cf* W, const cf* X, cf* Y, int nb, int na, int nre, long long ldx, long long sx,
-                       long long sy, long long batch, const PilotScale& ps, int n_cu, hipStream_t s) {
-  if (na <= 16) return launch_k<MT, 4>(W, X, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
-  if (na <= 32) return launch_k<MT, 8>(W, X, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
-  return launch_k<MT, 16>(W, X, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+hipError_t launch_k_mt(const cf* W, const cf* X, const unsigned* Xh, const signed char* ex, cf* Y, int nb, int na,
+                       int nre, long long ldx, long long sx, long long sy, long long batch, const PilotScale& ps,
+                       int n_cu, hipStream_t s) {
+  if (Xh) {
+    if (na <= 16) return launch_k<MT, 4, true>(W, X, Xh, ex, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+    if (na <= 32) return launch_k<MT, 8, true>(W, X, Xh, ex, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+    return launch_k<MT, 16, true>(W, X, Xh, ex, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+  }
+  if (na <= 16) return launch_k<MT, 4, false>(W, X, Xh, ex, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+  if (na <= 32) return launch_k<MT, 8, false>(W, X, Xh, ex, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+  return launch_k<MT, 16, false>(W, X, Xh, ex, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
 }
 
 constexpr size_t kWLdsMax = 64 * 1024;
@@ -367,20 +416,21 @@ hipError_t launch_mt(const cf* W, const cf* X, cf* Y, int nb, int na, int nre, l
 
 hipError_t launch_beamform(const cf* W, const cf* X, cf* Y, int n_beams, int n_ant, int n_re, long long ldx,
                            long long sx, long long sy, long long batch, int n_cu, hipStream_t s,
-                           const PilotScale* pilot_scale) {
+                           const PilotScale* pilot_scale, const unsigned* Xh, const signed char* ex) {
   if (batch <= 0 || n_re <= 0) return hipSuccess;
   PilotScale ps{};
   if (pilot_scale) ps = *pilot_scale;
   // 32-bit lane offsets and tile indices (with room for the prefetch index)
   if (n_ant <= 64 && ldx * n_ant < (1ll << 28) && batch * ((n_re + 15) / 16) < (1ll << 30)) {
     switch ((n_beams + 15) / 16) {
-      case 1: return launch_k_mt<1>(W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ps, n_cu, s);
-      case 2: return launch_k_mt<2>(W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ps, n_cu, s);
-      case 3: return launch_k_mt<3>(W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ps, n_cu, s);
-      case 4: return launch_k_mt<4>(W, X, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ps, n_cu, s);
+      case 1: return launch_k_mt<1>(W, X, Xh, ex, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ps, n_cu, s);
+      case 2: return launch_k_mt<2>(W, X, Xh, ex, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ps, n_cu, s);
+      case 3: return launch_k_mt<3>(W, X, Xh, ex, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ps, n_cu, s);
+      case 4: return launch_k_mt<4>(W, X, Xh, ex, Y, n_beams, n_ant, n_re, ldx, sx, sy, batch, ps, n_cu, s);
       default: return hipErrorInvalidValue;
     }
   }
+  if (Xh) return hipErrorInvalidValue;  // FP16 input: register-tile kernel only (up to 64 antennas)
   const long long ntn = (n_re + kTileN - 1) / kTileN;
   const long long tiles = batch * ntn;
   long long blocks = (tiles + kWaves - 1) / kWaves;

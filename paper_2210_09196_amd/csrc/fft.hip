@@ -15,6 +15,8 @@
 // FP32 table computed in FP64 on the host.  The final pass writes straight
 // from registers to global memory, optionally keeping only the active
 // subcarriers (fused gather).
+#include <hip/hip_fp16.h>
+
 #include <cmath>
 #include <vector>
 
@@ -133,8 +135,21 @@ __host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
 
 constexpr int kThreads = 256;
 
-template <int N>
+// FP16 output (H16): each transform's output row is stored as half2 words
+// (re in the low half) scaled by 2^e, e = 14 - k where the row's input L1
+// norm sum |re| + |im| = m * 2^k, m in [0.5, 1).  Every output bin is bounded
+// by that norm, so |scaled| < 2^14 (no overflow); FP16 keeps 11 significant
+// bits of every value.  The exponents go to an int8 table with 64 entries per
+// group of `rows` transforms (one slot symbol: the antennas): transform
+// i = g * rows + a stores e at g * 64 + (a % 4) * 16 + a / 4, so the 16
+// antennas a = 4 j + q (j = 0..15) of one group are 16 consecutive bytes.
+__device__ __forceinline__ unsigned pack_h2(float re, float im) {
+  return (unsigned)__half_as_ushort(__float2half_rn(re)) | ((unsigned)__half_as_ushort(__float2half_rn(im)) << 16);
+}
+
+template <int N, bool H16>
 __global__ __launch_bounds__(kThreads) void k_fft(const cf* __restrict__ x, cf* __restrict__ X,
+                                                  unsigned* __restrict__ Xh, signed char* __restrict__ ex, int rows,
                                                   const cf* __restrict__ tw, long long batch, int out_len,
                                                   int shift, long long ldo) {
   constexpr int T = N / 16;         // threads per transform
@@ -143,6 +158,7 @@ __global__ __launch_bounds__(kThreads) void k_fft(const cf* __restrict__ x, cf* 
   constexpr int P = Shape<N>::P;
   constexpr int LSTR = lds_pad(N);
   __shared__ cf lds[FPB * LSTR];
+  __shared__ float red[kThreads / 64];  // per-wave partial norms (H16, T > 64)
 
   const int fl = threadIdx.x / T;
   const int t = threadIdx.x % T;
@@ -176,6 +192,33 @@ __global__ __launch_bounds__(kThreads) void k_fft(const cf* __restrict__ x, cf* 
       for (int m = 0; m < 16; ++m) v[m] = cf{0.f, 0.f};
     }
 
+    float scale = 1.f;
+    if constexpr (H16) {
+      float s1 = 0.f;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) s1 += fabsf(v[m].r) + fabsf(v[m].i);
+      constexpr int WL = T < 64 ? T : 64;  // lanes of this transform in one wave
+#pragma unroll
+      for (int o = 1; o < WL; o <<= 1) s1 += __shfl_xor(s1, o);
+      if constexpr (T > 64) {
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s1;
+        __syncthreads();
+        s1 = 0.f;
+#pragma unroll
+        for (int w = 0; w < T / 64; ++w) s1 += red[fl * (T / 64) + w];
+      }
+      int k = 0;
+      (void)frexpf(s1, &k);
+      int e = s1 > 0.f ? 14 - k : 0;
+      e = e < -100 ? -100 : (e > 100 ? 100 : e);
+      scale = ldexpf(1.f, e);
+      if (t == 0 && act) {
+        const long long grp = fft / rows;
+        const int a = (int)(fft - grp * rows);
+        ex[grp * 64 + (a & 3) * 16 + (a >> 2)] = (signed char)e;
+      }
+    }
+
     // Pass 0: radix R0, Ns = 1 (no twiddles).  Butterfly j = t + u*T reads
     // x[j + r*N/R0] = v[u + r*16/R0] and writes element j*R0 + r.
 #pragma unroll
@@ -206,12 +249,22 @@ __global__ __launch_bounds__(kThreads) void k_fft(const cf* __restrict__ x, cf* 
         __syncthreads();
       } else if (act) {
         // last pass: Ns = N/16 = T, so bin f = t + r*T
-        cf* dst = X + fft * ldo;
+        if constexpr (H16) {
+          unsigned* dst = Xh + fft * ldo;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          int k = t + r * T + shift;
-          if (k >= N) k -= N;
-          if (k < out_len) dst[k] = v[r];
+          for (int r = 0; r < 16; ++r) {
+            int k = t + r * T + shift;
+            if (k >= N) k -= N;
+            if (k < out_len) dst[k] = pack_h2(v[r].r * scale, v[r].i * scale);
+          }
+        } else {
+          cf* dst = X + fft * ldo;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            int k = t + r * T + shift;
+            if (k >= N) k -= N;
+            if (k < out_len) dst[k] = v[r];
+          }
         }
       }
     }
@@ -268,23 +321,32 @@ void fft_fill_twiddles(cf* host) {
 namespace {
 // Persistent grid of exactly the resident workgroups (no second round of
 // workgroups and its tail).
-template <int N>
-hipError_t launch_n(const cf* x, cf* X, const cf* tw, long long batch, int out_len, int shift, long long ldo,
-                    long long blocks, int n_cu, hipStream_t s) {
+template <int N, bool H16>
+hipError_t launch_nh(const cf* x, cf* X, unsigned* Xh, signed char* ex, int rows, const cf* tw, long long batch,
+                     int out_len, int shift, long long ldo, long long blocks, int n_cu, hipStream_t s) {
   static const int per_cu = [] {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fft<N>, kThreads, 0) != hipSuccess || n < 1) n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fft<N, H16>, kThreads, 0) != hipSuccess || n < 1) n = 1;
     return n;
   }();
   const long long cap = (long long)n_cu * per_cu;
   if (blocks > cap) blocks = cap;
-  hipLaunchKernelGGL(k_fft<N>, dim3((unsigned)blocks), dim3(kThreads), 0, s, x, X, tw, batch, out_len, shift, ldo);
+  hipLaunchKernelGGL((k_fft<N, H16>), dim3((unsigned)blocks), dim3(kThreads), 0, s, x, X, Xh, ex, rows, tw, batch,
+                     out_len, shift, ldo);
   return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_n(const cf* x, cf* X, unsigned* Xh, signed char* ex, int rows, const cf* tw, long long batch,
+                    int out_len, int shift, long long ldo, long long blocks, int n_cu, hipStream_t s) {
+  return Xh ? launch_nh<N, true>(x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo, blocks, n_cu, s)
+            : launch_nh<N, false>(x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
 }
 }  // namespace
 
 hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_len, int shift, long long ldo,
-                      const cf* twiddles, int n_cu, hipStream_t s) {
+                      const cf* twiddles, int n_cu, hipStream_t s, unsigned* Xh, signed char* ex, int rows) {
+  if (Xh && (rows < 1 || rows > 64 || !ex)) return hipErrorInvalidValue;
   if (batch <= 0) return hipSuccess;
   const int si = fft_size_index(n_fft);
   const TwiddleLayout lay = fft_twiddle_layout();
@@ -292,11 +354,11 @@ hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_le
   const long long fpb = kThreads / (n_fft / 16);
   const long long blocks = (batch + fpb - 1) / fpb;
   switch (n_fft) {
-    case 64: return launch_n<64>(x, X, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
-    case 256: return launch_n<256>(x, X, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
-    case 1024: return launch_n<1024>(x, X, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
-    case 2048: return launch_n<2048>(x, X, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
-    case 4096: return launch_n<4096>(x, X, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
+    case 64: return launch_n<64>(x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
+    case 256: return launch_n<256>(x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
+    case 1024: return launch_n<1024>(x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
+    case 2048: return launch_n<2048>(x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
+    case 4096: return launch_n<4096>(x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
     default: return hipErrorInvalidValue;
   }
 }

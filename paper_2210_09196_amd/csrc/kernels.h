@@ -29,9 +29,13 @@ void fft_fill_twiddles(cf* host);
 int fft_size_index(int n_fft);  // 0..4, or -1 if unsupported
 
 // X_i[(f + shift) mod n_fft] = DFT(x_i)[f] for the targets below out_len;
-// output rows ldo elements apart (>= out_len).
+// output rows ldo elements apart (>= out_len).  With Xh set, the rows are
+// written as FP16 pairs (half2 words, re low) scaled by 2^e per row instead
+// (X unused): transform i = g * rows + a (rows <= 64) stores e in
+// ex[g * 64 + (a % 4) * 16 + a / 4].
 hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_len, int shift, long long ldo,
-                      const cf* twiddles, int n_cu, hipStream_t s);
+                      const cf* twiddles, int n_cu, hipStream_t s, unsigned* Xh = nullptr,
+                      signed char* ex = nullptr, int rows = 0);
 
 // ---------------------------------------------------------------- beamforming
 // Optional beamforming epilogue of the fused slot: the outputs of pilot
@@ -44,10 +48,14 @@ struct PilotScale {
   signed char pilot_of[kMaxSymbols];  // pilot index of each symbol, or -1
 };
 // Y_i[n][b] = sum_a W[b][a] X_i[a][n]; X_i = X + i*sx (row pitch ldx),
-// Y_i = Y + i*sy (RE-major, n_beams values per RE).
+// Y_i = Y + i*sy (RE-major, n_beams values per RE).  With Xh set, X is read
+// instead as FP16 pairs (half2 words, pitches in words) with row a of batch
+// item i scaled by 2^e, e from launch_fft's exponent table (rows = n_ant);
+// up to 64 antennas.
 hipError_t launch_beamform(const cf* W, const cf* X, cf* Y, int n_beams, int n_ant, int n_re, long long ldx,
                            long long sx, long long sy, long long batch, int n_cu, hipStream_t s,
-                           const PilotScale* pilot_scale = nullptr);
+                           const PilotScale* pilot_scale = nullptr, const unsigned* Xh = nullptr,
+                           const signed char* ex = nullptr);
 
 // ---------------------------------------------------------------- LS channel estimation
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by

@@ -55,6 +55,8 @@ _SIG = {
     "pusch_mmse_solve": (_I, [_P, _P, _F, _P, _I, _I, _I, _I, _LL, _P, _P]),
     "pusch_slot_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SlotDesc), _LL]),
     "pusch_slot": (_I, [ctypes.POINTER(SlotDesc), _LL, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "pusch_slot_mixed_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SlotDesc), _LL]),
+    "pusch_slot_mixed": (_I, [ctypes.POINTER(SlotDesc), _LL, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "pusch_cells_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SlotDesc), _I, ctypes.POINTER(_LL)]),
     "pusch_cells": (_I, [ctypes.POINTER(SlotDesc), _I, ctypes.POINTER(_LL), ctypes.POINTER(_P), ctypes.POINTER(_P),
                          ctypes.POINTER(_P), _P, ctypes.c_size_t, _P]),
@@ -198,10 +200,16 @@ def mmse_solve(H: torch.Tensor, Yd: torch.Tensor, sigma2: float, out: torch.Tens
 
 
 class Slot:
-    """A fixed slot geometry with its device workspace, for repeated pusch_slot calls."""
+    """A fixed slot geometry with its device workspace, for repeated pusch_slot calls.
+
+    precision="mixed" uses pusch_slot_mixed (FP16 active-bin grids between
+    OFDM demodulation and beamforming, FP32 arithmetic)."""
 
     def __init__(self, n_ant: int, n_fft: int, n_sc: int, n_symb: int, n_beams: int, n_ue: int, pilot_symb,
-                 sigma2: float, n_slot: int, W: torch.Tensor | None = None, device="cuda"):
+                 sigma2: float, n_slot: int, W: torch.Tensor | None = None, device="cuda", precision: str = "fp32"):
+        if precision not in ("fp32", "mixed"):
+            raise PuschError("precision is 'fp32' or 'mixed'")
+        self.mixed = precision == "mixed"
         pilot_symb = list(pilot_symb)
         if not 1 <= len(pilot_symb) <= MAX_PILOTS:
             raise PuschError("1..4 pilot symbols")
@@ -216,9 +224,10 @@ class Slot:
         d.W = _ptr(self.W)
         self.n_slot = n_slot
         self.n_data = n_symb - len(pilot_symb)
-        nbytes = lib().pusch_slot_workspace_bytes(ctypes.byref(d), n_slot)
+        wsb = lib().pusch_slot_mixed_workspace_bytes if self.mixed else lib().pusch_slot_workspace_bytes
+        nbytes = wsb(ctypes.byref(d), n_slot)
         if nbytes == 0 and n_slot > 0:
-            raise PuschError("pusch_slot_workspace_bytes rejected the slot geometry")
+            raise PuschError("the library rejected the slot geometry (workspace size 0)")
         self.ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
         self.ws_bytes = int(nbytes)
 
@@ -241,8 +250,9 @@ class Slot:
         if self.n_slot == 0:
             return x_hat, status
         d.pilots = pilots.data_ptr()
-        _check(lib().pusch_slot(ctypes.byref(d), self.n_slot, x_td.data_ptr(), x_hat.data_ptr(), _ptr(status),
-                                self.ws.data_ptr(), self.ws_bytes, _stream()), "pusch_slot")
+        fn, name = (lib().pusch_slot_mixed, "pusch_slot_mixed") if self.mixed else (lib().pusch_slot, "pusch_slot")
+        _check(fn(ctypes.byref(d), self.n_slot, x_td.data_ptr(), x_hat.data_ptr(), _ptr(status), self.ws.data_ptr(),
+                  self.ws_bytes, _stream()), name)
         return x_hat, status
 
 

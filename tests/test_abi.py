@@ -23,7 +23,7 @@ def lib():
 
 def test_exports_every_declared_symbol(lib):
     names = pusch.header_symbols()
-    assert len(names) == 12
+    assert len(names) == 14
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(pusch._SIG)
@@ -201,3 +201,23 @@ def test_cells_validation(lib):
     # a cell's output over another cell's input
     over = (P * 2)(0x800000, 0x98000000)
     assert f(descs, 2, ns, x, over, None, ws, need, None) == EINVAL
+
+
+def test_slot_mixed_workspace_and_validation(lib):
+    a = lambda v: (v + 255) // 256 * 256
+    d = _desc()
+    n = 16
+    # FP16 active-bin grids (4 B per value, rows padded to 32: 3300 -> 3328),
+    # 64 exponent bytes per slot symbol, then as pusch_slot
+    xa, ex = n * 14 * 64 * 3328 * 4, n * 14 * 64
+    y = n * 14 * 3300 * 32 * 8
+    assert lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(d), n) == a(xa) + a(ex) + a(y) + a(3300 * 16 * 2 * 8)
+    many = _desc(n_ant=65, n_beams=32)
+    assert lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(many), n) == 0  # FP16 path: up to 64 antennas
+    ws = ctypes.c_void_p(0x4000000000)
+    f = lib.pusch_slot_mixed
+    assert f(ctypes.byref(many), 1, FAKE, FAKE2, None, ws, 1 << 40, None) == EUNSUP
+    assert f(ctypes.byref(_desc(sigma2=-1.0)), 1, FAKE, FAKE2, None, ws, 1 << 40, None) == EINVAL
+    need = lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(d), 2)
+    assert f(ctypes.byref(d), 2, FAKE, FAKE2, None, ws, need - 1, None) == ENOMEM
+    assert f(ctypes.byref(d), 0, FAKE, FAKE2, None, ws, need, None) == 0

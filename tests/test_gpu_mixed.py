@@ -1,0 +1,94 @@
+"""GPU checks of pusch_slot_mixed (FP16 active-bin grids between OFDM
+demodulation and beamforming, FP32 arithmetic) against the FP32 chain and the
+FP64 oracle.
+
+Tolerance: the FP16 grids carry a relative rounding error of at most
+u = 2^-11 per value (RMS about u / sqrt(3) ~ 2.8e-4), which the linear stages
+pass on and the detection amplifies by the conditioning of the Gram matrix;
+detected symbols must stay within NRMSE 2e-3 of the oracle, and the EVM of
+the detected symbols against the transmitted ones within 0.1 dB of the FP32
+chain's at every SNR (the criterion for the reduced-precision form).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import metrics as M
+from oracle import pusch_oracle as O
+from paper_2210_09196_amd import pusch, synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+TOL_MIXED = 2e-3
+EVM_GAP_DB = 0.1
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def run(cfg, b, precision, scale=1.0, sigma2=None):
+    n = b["x_td"].shape[0]
+    s2 = b["sigma2"] if sigma2 is None else sigma2
+    slot = pusch.Slot(cfg.n_ant, cfg.n_fft, cfg.n_sc, cfg.n_symb, cfg.n_beams, cfg.n_ue, cfg.pilot_symb, s2, n,
+                      precision=precision)
+    x = dev(b["x_td"]) * scale if scale != 1.0 else dev(b["x_td"])
+    xh, st = slot(x.contiguous(), dev(b["pilots"]))
+    return host(xh), host(st)
+
+
+@pytest.mark.parametrize("snr_db", [10.0, 15.0, 20.0, 25.0, 30.0])
+def test_mixed_evm_gap_and_oracle(snr_db):
+    cfg = synth.CFG2.replace(snr_db=snr_db)
+    b = synth.make_batch(cfg, [3100, 3101])
+    print(f"[mixed] paper-scale slots at {snr_db} dB", flush=True)
+    x32, st32 = run(cfg, b, "fp32")
+    x16, st16 = run(cfg, b, "mixed")
+    assert np.all(st32 == 0) and np.all(st16 == 0)
+    data = b["data"].transpose(0, 1, 3, 2)  # [slot][D][K][L], the x_hat layout
+    gap = M.evm_db(x16, data) - M.evm_db(x32, data)
+    assert abs(gap) <= EVM_GAP_DB, gap
+    for k in range(2):
+        s = {key: b[key][k] for key in ("x_td", "pilots")}
+        ref = O.receive_slot(s["x_td"], s["pilots"], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
+                             n_beams=cfg.n_beams)
+        assert M.nrmse(x16[k], ref["x_hat"]) <= TOL_MIXED
+        assert M.nrmse(x32[k], ref["x_hat"]) <= 1e-4
+
+
+@pytest.mark.parametrize("log2_scale", [40, -40])
+def test_mixed_power_of_two_row_scaling_covers_any_range(log2_scale):
+    # x_td * 2^s with sigma2 * 2^(2s) gives the same detected symbols; without
+    # the per-row scaling the FP16 grids would overflow (2^40) or flush to
+    # zero (2^-40).
+    cfg = synth.CFG1
+    b = synth.make_batch(cfg, [3200])
+    base, _ = run(cfg, b, "mixed")
+    a = 2.0 ** log2_scale
+    got, st = run(cfg, b, "mixed", scale=a, sigma2=b["sigma2"] * a * a)
+    assert np.all(st == 0) and np.all(np.isfinite(got))
+    assert M.nrmse(got, base) <= 1e-6
+    ref = O.receive_slot(b["x_td"][0], b["pilots"][0], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
+                         n_beams=cfg.n_beams)
+    assert M.nrmse(got[0], ref["x_hat"]) <= TOL_MIXED
+
+
+def test_mixed_small_geometries():
+    for geom in (dict(n_ant=8, n_fft=64, n_sc=60, n_beams=8, n_ue=3, pilot_symb=(3, 9)),
+                 dict(n_ant=32, n_fft=2048, n_sc=1650, n_beams=16, n_ue=8, pilot_symb=(0, 4, 7, 11), qam_bits=8,
+                      channel="tdl"),
+                 dict(n_beams=15)):
+        cfg = synth.CFG1.replace(snr_db=25.0, **geom)
+        b = synth.make_batch(cfg, [3300, 3301])
+        got, st = run(cfg, b, "mixed")
+        assert np.all(st == 0)
+        for k in range(2):
+            ref = O.receive_slot(b["x_td"][k], b["pilots"][k], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
+                                 n_beams=cfg.n_beams)
+            assert M.nrmse(got[k], ref["x_hat"]) <= TOL_MIXED, geom
