@@ -193,9 +193,6 @@ def bench_cells(n_cells: int, steps: int, warmup: int) -> int:
                   .contiguous() * 0.05)
         ph = torch.randint(0, 4, (1, 2, c["n_sc"]), generator=g, device="cuda").float() * (np.pi / 2) + np.pi / 4
         ps.append(torch.polar(torch.ones_like(ph), ph).to(torch.complex64).contiguous())
-    cells = pusch.Cells(geoms)
-    out, out_st = cells.outputs()
-
     def timed(fn, n):
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
         for a, b in ev:
@@ -205,24 +202,30 @@ def bench_cells(n_cells: int, steps: int, warmup: int) -> int:
         torch.cuda.synchronize()
         return np.array([a.elapsed_time(b) * 1e3 for a, b in ev])  # us per call
 
-    run = lambda: cells(xs, ps, out, out_st)
-    for _ in range(warmup):
-        run()
-    torch.cuda.synchronize()
-    eager = timed(run, steps)
-    graph = torch.cuda.CUDAGraph()
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        run()
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    with torch.cuda.graph(graph):
-        run()
-    for _ in range(warmup):
-        graph.replay()
-    torch.cuda.synchronize()
-    replay = timed(graph.replay, steps)
+    def measure(precision):
+        cells = pusch.Cells(geoms, precision=precision)
+        out, out_st = cells.outputs()
+        run = lambda: cells(xs, ps, out, out_st)
+        for _ in range(warmup):
+            run()
+        torch.cuda.synchronize()
+        eager = timed(run, steps)
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            run()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph):
+            run()
+        for _ in range(warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        return eager, timed(graph.replay, steps), out, out_st
+
+    eager, replay, out, out_st = measure("fp32")
+    _, replay_mixed, _, _ = measure("mixed")
     slots = [pusch.Slot(c["n_ant"], c["n_fft"], c["n_sc"], 14, c["n_beams"], c["n_ue"], c["pilot_symb"], c["sigma2"], 1)
              for c in geoms]
 
@@ -243,6 +246,8 @@ def bench_cells(n_cells: int, steps: int, warmup: int) -> int:
         "graph_p50_us_per_slot": per(replay, 50), "graph_p99_us_per_slot": per(replay, 99),
         "eager_p50_us_per_slot": per(eager, 50), "eager_p99_us_per_slot": per(eager, 99),
         "sequential_slot_calls_p50_us_per_slot": per(seq, 50),
+        "mixed_graph_p50_us_per_slot": per(replay_mixed, 50),
+        "mixed_graph_p99_us_per_slot": per(replay_mixed, 99),
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{n_cells} uneven cells, one slot each: N in 1024/2048/4096 (N*3300/4096 active), "
                                f"16/32/64 antennas, beams = antennas/2, 4-16 UEs, pilots 2+11", "mix": mix},

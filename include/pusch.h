@@ -199,9 +199,11 @@ int pusch_slot_mixed(const pusch_slot_desc* d, long long n_slot, const pusch_c32
  * back to `stream` with events, so the whole call is ordered on `stream` and
  * can be captured into a HIP graph (after one uncaptured call on the device,
  * or pusch_init, has built the device tables).
- *   ws   device workspace of at least pusch_cells_workspace_bytes bytes,
- *        256-byte aligned: one slice per side stream used, each as large as
- *        the largest cell's pusch_slot workspace.
+ *   ws     device workspace of at least pusch_cells_workspace_bytes bytes,
+ *          256-byte aligned: one slice per side stream used, each as large
+ *          as the largest cell's pusch_slot (or pusch_slot_mixed) workspace.
+ *   mixed  nonzero: every cell runs as pusch_slot_mixed (each cell n_ant <=
+ *          64, else PUSCH_EUNSUPPORTED; workspace size 0).
  * Every cell's arguments are checked as for pusch_slot, and no cell's output
  * may overlap any other cell's buffers or the workspace.  1 <= n_cells <=
  * PUSCH_MAX_CELLS.  Calls on one device are serialised on the host while
@@ -210,9 +212,10 @@ int pusch_slot_mixed(const pusch_slot_desc* d, long long n_slot, const pusch_c32
  */
 #define PUSCH_CELL_STREAMS 4
 #define PUSCH_MAX_CELLS 4096
-size_t pusch_cells_workspace_bytes(const pusch_slot_desc* d, int n_cells, const long long* n_slot);
+size_t pusch_cells_workspace_bytes(const pusch_slot_desc* d, int n_cells, const long long* n_slot, int mixed);
 int pusch_cells(const pusch_slot_desc* d, int n_cells, const long long* n_slot, const pusch_c32* const* x_td,
-                pusch_c32* const* x_hat, int32_t* const* status, void* ws, size_t ws_bytes, void* stream);
+                pusch_c32* const* x_hat, int32_t* const* status, void* ws, size_t ws_bytes, int mixed,
+                void* stream);
 
 /*
  * Stage timing for measurement.  pusch_profile_begin(max_calls) creates

@@ -449,25 +449,28 @@ int pusch_slot_mixed(const pusch_slot_desc* d, long long n_slot, const pusch_c32
                   true);
 }
 
-size_t pusch_cells_workspace_bytes(const pusch_slot_desc* d, int n_cells, const long long* n_slot) {
+size_t pusch_cells_workspace_bytes(const pusch_slot_desc* d, int n_cells, const long long* n_slot, int mixed) {
   if (!d || !n_slot || n_cells < 1) return 0;
   size_t slice = 0;
   for (int c = 0; c < n_cells; ++c) {
     if (check_geom(&d[c]) != PUSCH_OK || n_slot[c] < 0) return 0;
-    slice = std::max(slice, slot_layout(&d[c], n_slot[c]).total);
+    if (mixed && !mixed_supported(&d[c], n_slot[c])) return 0;
+    slice = std::max(slice, slot_layout(&d[c], n_slot[c], mixed != 0).total);
   }
   const int used = n_cells < kSideStreams ? n_cells : kSideStreams;
   return (size_t)used * align256(slice);
 }
 
 int pusch_cells(const pusch_slot_desc* d, int n_cells, const long long* n_slot, const pusch_c32* const* x_td,
-                pusch_c32* const* x_hat, int32_t* const* status, void* ws, size_t ws_bytes, void* stream) {
+                pusch_c32* const* x_hat, int32_t* const* status, void* ws, size_t ws_bytes, int mixed,
+                void* stream) {
   if (!d || !n_slot || !x_td || !x_hat || n_cells < 1 || n_cells > PUSCH_MAX_CELLS) return PUSCH_EINVAL;
+  const bool mx = mixed != 0;
   size_t slice = 0;
   for (int c = 0; c < n_cells; ++c) {
     if (int rc = check_geom(&d[c])) return rc;
     if (n_slot[c] < 0) return PUSCH_EINVAL;
-    slice = std::max(slice, slot_layout(&d[c], n_slot[c]).total);
+    slice = std::max(slice, slot_layout(&d[c], n_slot[c], mx).total);
   }
   slice = align256(slice);
   const int used = n_cells < kSideStreams ? n_cells : kSideStreams;
@@ -477,7 +480,7 @@ int pusch_cells(const pusch_slot_desc* d, int n_cells, const long long* n_slot, 
   // output may overlap another cell's output or input
   for (int c = 0; c < n_cells; ++c) {
     char* wsc = static_cast<char*>(ws) + (size_t)(c % kSideStreams) * slice;
-    if (int rc = check_slot_call(&d[c], n_slot[c], x_td[c], x_hat[c], status ? status[c] : nullptr, wsc, slice))
+    if (int rc = check_slot_call(&d[c], n_slot[c], x_td[c], x_hat[c], status ? status[c] : nullptr, wsc, slice, mx))
       return rc;
     const long long ob = out_bytes(&d[c], n_slot[c]), sb = n_slot[c] * (long long)d[c].n_sc * 4;
     const long long xb_c = n_slot[c] * (long long)d[c].n_symb * d[c].n_ant * d[c].n_fft * 8;
@@ -515,7 +518,7 @@ int pusch_cells(const pusch_slot_desc* d, int n_cells, const long long* n_slot, 
     if (n_slot[c] == 0) continue;
     char* wsc = static_cast<char*>(ws) + (size_t)(c % kSideStreams) * slice;
     rc = run_slot(t, &d[c], n_slot[c], x_td[c], x_hat[c], status ? status[c] : nullptr, wsc,
-                  t->side[c % kSideStreams], false);
+                  t->side[c % kSideStreams], false, mx);
   }
   // join (also after a failed launch, so the caller's stream never runs
   // ahead of work already enqueued on a side stream)

@@ -179,11 +179,28 @@ __global__ __launch_bounds__(kThreads) void k_fft(const cf* __restrict__ x, cf* 
     }
   }
 
-  for (long long f0 = (long long)blockIdx.x * FPB; f0 < batch; f0 += (long long)gridDim.x * FPB) {
+  // With FP16 output the kernel no longer saturates HBM, so the input of the
+  // workgroup's next transform is loaded during the current one's passes (a
+  // transform past the batch re-reads the last one and is never stored).
+  // With FP32 output the traffic is already at the bandwidth limit and the
+  // registers are kept for occupancy.
+  const long long fstep = (long long)gridDim.x * FPB;
+  cf vn[H16 ? 16 : 1];
+  auto prefetch = [&](long long f) {
+    const cf* src = x + (f < batch ? f : batch - 1) * N;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) vn[m] = src[t + m * T];
+  };
+  if constexpr (H16) prefetch((long long)blockIdx.x * FPB + fl);
+  for (long long f0 = (long long)blockIdx.x * FPB; f0 < batch; f0 += fstep) {
     const long long fft = f0 + fl;
     const bool act = fft < batch;
     cf v[16];
-    if (act) {
+    if constexpr (H16) {
+#pragma unroll
+      for (int m = 0; m < 16; ++m) v[m] = act ? vn[m] : cf{0.f, 0.f};
+      prefetch(fft + fstep);
+    } else if (act) {
       const cf* src = x + fft * N;
 #pragma unroll
       for (int m = 0; m < 16; ++m) v[m] = src[t + m * T];

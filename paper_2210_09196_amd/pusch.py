@@ -57,9 +57,9 @@ _SIG = {
     "pusch_slot": (_I, [ctypes.POINTER(SlotDesc), _LL, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "pusch_slot_mixed_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SlotDesc), _LL]),
     "pusch_slot_mixed": (_I, [ctypes.POINTER(SlotDesc), _LL, _P, _P, _P, _P, ctypes.c_size_t, _P]),
-    "pusch_cells_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SlotDesc), _I, ctypes.POINTER(_LL)]),
+    "pusch_cells_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SlotDesc), _I, ctypes.POINTER(_LL), _I]),
     "pusch_cells": (_I, [ctypes.POINTER(SlotDesc), _I, ctypes.POINTER(_LL), ctypes.POINTER(_P), ctypes.POINTER(_P),
-                         ctypes.POINTER(_P), _P, ctypes.c_size_t, _P]),
+                         ctypes.POINTER(_P), _P, ctypes.c_size_t, _I, _P]),
     "pusch_profile_begin": (_I, [_I]),
     "pusch_profile_end": (_I, [ctypes.POINTER(_F), _I]),
 }
@@ -278,7 +278,10 @@ class Cells:
     stream, so it can be captured into a CUDA/HIP graph.
     """
 
-    def __init__(self, cells: list[dict], device="cuda"):
+    def __init__(self, cells: list[dict], device="cuda", precision: str = "fp32"):
+        if precision not in ("fp32", "mixed"):
+            raise PuschError("precision is 'fp32' or 'mixed'")
+        self.mixed = 1 if precision == "mixed" else 0
         n = len(cells)
         if n < 1:
             raise PuschError("at least one cell")
@@ -297,7 +300,7 @@ class Cells:
                        g["pilot_symb"], g["sigma2"], W)
             self.n_slot[c] = int(g["n_slot"])
             self.geom.append(dict(g))
-        nbytes = lib().pusch_cells_workspace_bytes(self.descs, n, self.n_slot)
+        nbytes = lib().pusch_cells_workspace_bytes(self.descs, n, self.n_slot, self.mixed)
         if nbytes == 0:
             raise PuschError("pusch_cells_workspace_bytes rejected a cell geometry")
         self.ws = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
@@ -335,7 +338,7 @@ class Cells:
         op = (_P * self.n)(*[t.data_ptr() for t in x_hats])
         sp = None if statuses is None else (_P * self.n)(*[_ptr(t) for t in statuses])
         _check(lib().pusch_cells(self.descs, self.n, self.n_slot, xp, op, sp, self.ws.data_ptr(), self.ws_bytes,
-                                 _stream()), "pusch_cells")
+                                 self.mixed, _stream()), "pusch_cells")
         return x_hats, statuses
 
 

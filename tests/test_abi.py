@@ -166,41 +166,47 @@ def test_cells_workspace_bytes(lib):
     descs, ns = _cell_arrays([big, small, small], [2, 1, 3])
     # one slice per side stream used (3 cells -> 3), each the largest cell's workspace
     slice_ = a(max(ws(big, 2), ws(small, 1), ws(small, 3)))
-    assert lib.pusch_cells_workspace_bytes(descs, 3, ns) == 3 * slice_
+    assert lib.pusch_cells_workspace_bytes(descs, 3, ns, 0) == 3 * slice_
     descs6, ns6 = _cell_arrays([small] * 6, [1] * 6)
-    assert lib.pusch_cells_workspace_bytes(descs6, 6, ns6) == 4 * a(ws(small, 1))  # four side streams
+    assert lib.pusch_cells_workspace_bytes(descs6, 6, ns6, 0) == 4 * a(ws(small, 1))  # four side streams
     bad, nsb = _cell_arrays([big, _desc(n_fft=1000)], [1, 1])
-    assert lib.pusch_cells_workspace_bytes(bad, 2, nsb) == 0
-    assert lib.pusch_cells_workspace_bytes(descs, 0, ns) == 0
-    assert lib.pusch_cells_workspace_bytes(None, 1, ns) == 0
+    assert lib.pusch_cells_workspace_bytes(bad, 2, nsb, 0) == 0
+    assert lib.pusch_cells_workspace_bytes(descs, 0, ns, 0) == 0
+    assert lib.pusch_cells_workspace_bytes(None, 1, ns, 0) == 0
+    # mixed precision: the FP16 grids need n_ant <= 64 in every cell
+    many, nsm = _cell_arrays([small, _desc(n_ant=65)], [1, 1])
+    assert lib.pusch_cells_workspace_bytes(many, 2, nsm, 1) == 0
+    assert lib.pusch_cells_workspace_bytes(descs, 3, ns, 1) == 3 * a(max(
+        lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(big), 2),
+        lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(small), 3)))
 
 
 def test_cells_validation(lib):
     small = _desc(n_ant=16, n_fft=1024, n_sc=825, n_beams=8, n_ue=4, pilot_symb=(2,), n_pilot=1)
     descs, ns = _cell_arrays([small, small], [1, 1])
-    need = lib.pusch_cells_workspace_bytes(descs, 2, ns)
+    need = lib.pusch_cells_workspace_bytes(descs, 2, ns, 0)
     ws = ctypes.c_void_p(0x4000000000)
     P = ctypes.c_void_p
     x = (P * 2)(0x10000, 0x800000)
     o = (P * 2)(0x90000000, 0x98000000)
     f = lib.pusch_cells
-    assert f(descs, 0, ns, x, o, None, ws, need, None) == EINVAL
-    assert f(None, 2, ns, x, o, None, ws, need, None) == EINVAL
-    assert f(descs, 2, ns, x, o, None, ws, need - 1, None) == ENOMEM
-    assert f(descs, 2, ns, x, o, None, ctypes.c_void_p(0x4000000010), need, None) == EINVAL  # unaligned
-    assert f(descs, 2, ns, x, o, None, None, need, None) == EINVAL
+    assert f(descs, 0, ns, x, o, None, ws, need, 0, None) == EINVAL
+    assert f(None, 2, ns, x, o, None, ws, need, 0, None) == EINVAL
+    assert f(descs, 2, ns, x, o, None, ws, need - 1, 0, None) == ENOMEM
+    assert f(descs, 2, ns, x, o, None, ctypes.c_void_p(0x4000000010), need, 0, None) == EINVAL  # unaligned
+    assert f(descs, 2, ns, x, o, None, None, need, 0, None) == EINVAL
     # one invalid cell rejects the whole call
     bad, nsb = _cell_arrays([small, _desc(sigma2=-1.0)], [1, 1])
-    assert f(bad, 2, nsb, x, o, None, ws, 1 << 40, None) == EINVAL
+    assert f(bad, 2, nsb, x, o, None, ws, 1 << 40, 0, None) == EINVAL
     # two cells writing the same output
     same = (P * 2)(0x90000000, 0x90000000)
-    assert f(descs, 2, ns, x, same, None, ws, need, None) == EINVAL
+    assert f(descs, 2, ns, x, same, None, ws, need, 0, None) == EINVAL
     # a cell's output inside another cell's workspace slice
     inside = (P * 2)(0x90000000, 0x4000000000 + need - 4096)
-    assert f(descs, 2, ns, x, inside, None, ws, need, None) == EINVAL
+    assert f(descs, 2, ns, x, inside, None, ws, need, 0, None) == EINVAL
     # a cell's output over another cell's input
     over = (P * 2)(0x800000, 0x98000000)
-    assert f(descs, 2, ns, x, over, None, ws, need, None) == EINVAL
+    assert f(descs, 2, ns, x, over, None, ws, need, 0, None) == EINVAL
 
 
 def test_slot_mixed_workspace_and_validation(lib):

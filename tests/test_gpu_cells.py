@@ -103,3 +103,19 @@ def test_cells_graph_replay_matches_eager():
         torch.cuda.synchronize()
         for c in range(len(geoms)):
             assert torch.equal(e[c], ref[c]), (r, c)
+
+
+def test_cells_mixed_precision_match_single_mixed_calls():
+    cfgs, batches, geoms = make_cells(CELLS[:4], seed0=1100)
+    cells = pusch.Cells(geoms, precision="mixed")
+    xs = [dev(b["x_td"]) for b in batches]
+    ps = [dev(b["pilots"]) for b in batches]
+    xh, st = cells(xs, ps)
+    for c, (cfg, b, g) in enumerate(zip(cfgs, batches, geoms)):
+        slot = pusch.Slot(cfg.n_ant, cfg.n_fft, cfg.n_sc, cfg.n_symb, cfg.n_beams, cfg.n_ue, cfg.pilot_symb,
+                          b["sigma2"], g["n_slot"], precision="mixed")
+        alone, alone_st = slot(xs[c], ps[c])
+        assert torch.equal(alone, xh[c]) and torch.equal(alone_st, st[c]), c
+        ref = O.receive_slot(b["x_td"][0], b["pilots"][0], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
+                             n_beams=cfg.n_beams)
+        assert M.nrmse(host(xh[c])[0], ref["x_hat"]) <= 2e-3, c
