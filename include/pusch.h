@@ -178,11 +178,13 @@ int pusch_slot(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td
  * 32-bit words, Sec. VI; this is a reduced-precision form of it): every
  * antenna row of every symbol is scaled by a power of two chosen from its
  * time-domain L1 norm, which bounds every output bin, so nothing overflows;
- * beamforming widens each value back to FP32 and undoes the scale exactly.
- * All arithmetic stays FP32, so the only extra error is the FP16 rounding of
- * the grids (relative 2^-11 per value).  It halves the bytes those grids
- * move through HBM.  Arguments and results as pusch_slot; n_ant <= 64
- * (PUSCH_EUNSUPPORTED otherwise).
+ * beamforming runs on FP16 matrix cores with FP32 accumulation (W rounded
+ * to FP16, the rows rebased to each symbol's smallest exponent, the common
+ * scale undone in FP32).  Channel estimation and detection stay FP32.  The
+ * extra error is the FP16 rounding of the grids and of W (relative 2^-11 per
+ * value).  It halves the bytes those grids move through HBM and takes the
+ * beamforming product off the FP32 pipes.  Arguments and results as
+ * pusch_slot; n_ant <= 64 (PUSCH_EUNSUPPORTED otherwise).
  */
 size_t pusch_slot_mixed_workspace_bytes(const pusch_slot_desc* d, long long n_slot);
 int pusch_slot_mixed(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td, pusch_c32* x_hat,

@@ -196,27 +196,11 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform(const cf* __restrict__
 // value per lane); the next tile's loads are in flight while the current
 // tile's MFMAs run (ping-pong over a tile loop unrolled by two).  Half the
 // accumulators of the 32-RE tile, so two tiles of X fit next to them.
-// X operand of one tile: FP32 pairs, or (H16) FP16 pairs (half2 words, re
-// low) plus the 16 exponents of this lane's antennas 4 ks + kq (launch_fft's
-// table: 16 consecutive bytes per lane).
-template <int KS, bool H16>
-struct XBuf {
-  cf x[KS];
-};
-template <int KS>
-struct XBuf<KS, true> {
-  unsigned w[KS];
-  int4 e;
-};
-
-// H16: each FP16 value is widened to FP32 and rescaled by its row's power of
-// two exactly, before the FP32 MFMAs.
-template <int MT, int KS, bool H16>
+template <int MT, int KS>
 __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict__ W, const cf* __restrict__ X,
-                                                            const unsigned* __restrict__ Xh,
-                                                            const signed char* __restrict__ ex, cf* __restrict__ Y,
-                                                            int nb, int na, int nre, long long ldx, long long sx,
-                                                            long long sy, int ntiles, int ntn, PilotScale ps) {
+                                                            cf* __restrict__ Y, int nb, int na, int nre,
+                                                            long long ldx, long long sx, long long sy, int ntiles,
+                                                            int ntn, PilotScale ps) {
   extern __shared__ float4 wl[];  // [ks][m][lane] = (Wr, Wi, Wr + Wi, 0); zero for padded antennas / beams
   const int lane = threadIdx.x & 63;
   const int col = lane & 15;  // A row / B column / D column inside a 16x16 tile
@@ -236,33 +220,23 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict
   // clamped in bounds: padded antennas meet zero W entries, REs past n_re are
   // not stored, and a tile index past the end re-reads the last tile (such a
   // prefetch is dropped).
-  auto load = [&](XBuf<KS, H16>& xb, int tile) {
+  auto load = [&](cf (&x)[KS], int tile) {
     tile = tile < ntiles ? tile : ntiles - 1;
     const int bi = tile / ntn;
     const int n = (tile - bi * ntn) * 16 + col;
     const unsigned nn = (unsigned)(n < nre ? n : nre - 1);
-    if constexpr (H16) {
-      const unsigned* base = Xh + bi * sx;
+    const cf* base = X + bi * sx;
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int a = ks * 4 + kq;
-        xb.w[ks] = base[(unsigned)(a < na ? a : na - 1) * (unsigned)ldx + nn];
-      }
-      xb.e = *reinterpret_cast<const int4*>(ex + (long long)bi * 64 + kq * 16);
-    } else {
-      const cf* base = X + bi * sx;
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int a = ks * 4 + kq;
-        xb.x[ks] = base[(unsigned)(a < na ? a : na - 1) * (unsigned)ldx + nn];
-      }
+    for (int ks = 0; ks < KS; ++ks) {
+      const int a = ks * 4 + kq;
+      x[ks] = base[(unsigned)(a < na ? a : na - 1) * (unsigned)ldx + nn];
     }
   };
   // X is the A operand and W the B operand, so the result tile is
   // D[RE][beam]: lane (kq, col) receives REs n0 + 4 kq + v of beam col, and
   // sixteen consecutive lanes hold one RE's sixteen consecutive beams (each
   // store instruction writes whole 128-byte lines).
-  auto compute = [&](const XBuf<KS, H16>& xb, int tile) {
+  auto compute = [&](const cf (&x)[KS], int tile) {
     const int bi = tile / ntn;
     const int n0 = (tile - bi * ntn) * 16;
     f32x4 t1[MT], t2[MT], t3[MT];
@@ -270,20 +244,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict
     for (int m = 0; m < MT; ++m) t1[m] = t2[m] = t3[m] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      float xr, xi;
-      if constexpr (H16) {
-        const int ew = (ks >> 2) == 0 ? xb.e.x : ((ks >> 2) == 1 ? xb.e.y : ((ks >> 2) == 2 ? xb.e.z : xb.e.w));
-        // exponents of padded antennas (never written) are taken as 0: the
-        // value only meets a zero W entry, it just has to be finite
-        const int e = ks * 4 + kq < na ? (int)__builtin_amdgcn_sbfe((unsigned)ew, 8 * (ks & 3), 8) : 0;
-        const unsigned u = xb.w[ks];
-        xr = ldexpf(__half2float(__ushort_as_half((unsigned short)(u & 0xffffu))), -e);
-        xi = ldexpf(__half2float(__ushort_as_half((unsigned short)(u >> 16))), -e);
-      } else {
-        xr = xb.x[ks].r;
-        xi = xb.x[ks].i;
-      }
-      const float xs = xr + xi;
+      const float xr = x[ks].r, xi = x[ks].i, xs = xr + xi;
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
         const float4 w = wl[(ks * MT + m) * 64 + lane];
@@ -338,7 +299,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict
     }
   };
   if (t0 >= ntiles) return;
-  XBuf<KS, H16> xa, xb;
+  cf xa[KS], xb[KS];
   load(xa, t0);
   for (int t = t0; t < ntiles; t += 2 * nwave) {
     load(xb, t + nwave);
@@ -350,9 +311,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict
   }
 }
 
-template <int MT, int KS, bool H16>
-hipError_t launch_k(const cf* W, const cf* X, const unsigned* Xh, const signed char* ex, cf* Y, int nb, int na,
-                    int nre,
+template <int MT, int KS>
+hipError_t launch_k(const cf* W, const cf* X, cf* Y, int nb, int na, int nre,
                     long long ldx, long long sx, long long sy, long long batch, const PilotScale& ps, int n_cu,
                     hipStream_t s) {
   const int ntn = (nre + 15) / 16;
@@ -362,7 +322,7 @@ hipError_t launch_k(const cf* W, const cf* X, const unsigned* Xh, const signed c
   // tiles from the start, no second round of workgroups and its tail
   static const int per_cu = [&] {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_beamform_k<MT, KS, H16>, 64 * kWaves, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_beamform_k<MT, KS>, 64 * kWaves, lds) != hipSuccess ||
         n < 1)
       n = 1;
     return n;
@@ -370,8 +330,195 @@ hipError_t launch_k(const cf* W, const cf* X, const unsigned* Xh, const signed c
   long long blocks = (tiles + kWaves - 1) / kWaves;
   const long long cap = (long long)n_cu * per_cu;
   if (blocks > cap) blocks = cap;
-  hipLaunchKernelGGL((k_beamform_k<MT, KS, H16>), dim3((unsigned)blocks), dim3(64 * kWaves), lds, s, W, X, Xh, ex,
-                     Y, nb, na, nre, ldx, sx, sy, (int)tiles, ntn, ps);
+  hipLaunchKernelGGL((k_beamform_k<MT, KS>), dim3((unsigned)blocks), dim3(64 * kWaves), lds, s, W, X, Y, nb, na,
+                     nre, ldx, sx, sy, (int)tiles, ntn, ps);
+  return hipGetLastError();
+}
+
+// FP16 input on FP16 matrix cores (v_mfma_f32_16x16x16_f16, FP32
+// accumulation), up to 64 antennas in J blocks of 16.  Lane (kq, col) loads,
+// for K-step ks, antenna 4 ks + kq of RE col (as k_beamform_k); the four
+// K-steps 4j..4j+3 are the four A-operand halves of block j, i.e. block j
+// slot (kq, i) holds antenna 4 (4j + i) + kq.  The contraction over antennas
+// does not depend on the order, and W is staged in the same order.  Rows
+// carry their own power of two; they are rebased to the symbol's smallest
+// exponent (each value scaled down by 2^(e_a - e_min), exact unless it
+// drops below the FP16 range, where it is negligible next to the row with
+// e_min), and 2^-e_min is applied to the FP32 accumulators.  W is rounded to
+// FP16 (entries of a beamformer are O(1); |W| must lie inside FP16's range).
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma16(h4 a, h4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+
+template <int MT, int J>
+__global__ __launch_bounds__(64 * kWaves) void k_beamform_h16(const cf* __restrict__ W,
+                                                              const unsigned* __restrict__ Xh,
+                                                              const signed char* __restrict__ ex,
+                                                              cf* __restrict__ Y, int nb, int na, int nre,
+                                                              long long ldx, long long sx, long long sy, int ntiles,
+                                                              int ntn, PilotScale ps) {
+  constexpr int KS = 4 * J;
+  // [j][m][lane] = (Wr, Wi, Wr + Wi) as three half4, lane (q, col): beam
+  // m*16 + col, antennas 4 (4j + i) + q, i = 0..3; zero past n_ant / n_beams
+  extern __shared__ h4 wh[];
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15;
+  const int kq = lane >> 4;
+  for (int e = threadIdx.x; e < J * MT * 64; e += blockDim.x) {
+    const int l = e & 63, m = (e >> 6) % MT, j = (e >> 6) / MT;
+    const int b = m * 16 + (l & 15), q = l >> 4;
+    h4 wr, wi, ws;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int a = 4 * (4 * j + i) + q;
+      const cf w = (a < na && b < nb) ? W[b * na + a] : cf{0.f, 0.f};
+      wr[i] = (_Float16)w.r;
+      wi[i] = (_Float16)w.i;
+      ws[i] = (_Float16)(w.r + w.i);
+    }
+    wh[3 * e] = wr;
+    wh[3 * e + 1] = wi;
+    wh[3 * e + 2] = ws;
+  }
+  __syncthreads();
+
+  const int nwave = gridDim.x * kWaves;
+  const int t0 = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  struct Buf {
+    unsigned w[KS];
+    int4 e;
+  };
+  auto load = [&](Buf& xb, int tile) {
+    tile = tile < ntiles ? tile : ntiles - 1;
+    const int bi = tile / ntn;
+    const int n = (tile - bi * ntn) * 16 + col;
+    const unsigned nn = (unsigned)(n < nre ? n : nre - 1);
+    const unsigned* base = Xh + bi * sx;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int a = ks * 4 + kq;
+      xb.w[ks] = base[(unsigned)(a < na ? a : na - 1) * (unsigned)ldx + nn];
+    }
+    xb.e = *reinterpret_cast<const int4*>(ex + (long long)bi * 64 + kq * 16);
+  };
+  auto compute = [&](const Buf& xb, int tile) {
+    const int bi = tile / ntn;
+    const int n0 = (tile - bi * ntn) * 16;
+    // this lane's exponents (antennas past n_ant: never written, ignored)
+    int ev[KS];
+    int emin = 127;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int word = (ks >> 2) == 0 ? xb.e.x : ((ks >> 2) == 1 ? xb.e.y : ((ks >> 2) == 2 ? xb.e.z : xb.e.w));
+      const bool ok = ks * 4 + kq < na;
+      ev[ks] = ok ? (int)__builtin_amdgcn_sbfe((unsigned)word, 8 * (ks & 3), 8) : 127;
+      emin = ev[ks] < emin ? ev[ks] : emin;
+    }
+    // symbol-wide minimum: the four antenna groups kq sit 16 lanes apart
+    emin = min(emin, __shfl_xor(emin, 16));
+    emin = min(emin, __shfl_xor(emin, 32));
+    f32x4 t1[MT], t2[MT], t3[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) t1[m] = t2[m] = t3[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      h4 ar, ai, as;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int ks = 4 * j + i;
+        const unsigned u = xb.w[ks];
+        const int d = ev[ks] == 127 ? 0 : emin - ev[ks];  // <= 0: scale down to the common exponent
+        const float xr = ldexpf(__half2float(__ushort_as_half((unsigned short)(u & 0xffffu))), d);
+        const float xi = ldexpf(__half2float(__ushort_as_half((unsigned short)(u >> 16))), d);
+        ar[i] = (_Float16)xr;
+        ai[i] = (_Float16)xi;
+        as[i] = (_Float16)(xr + xi);
+      }
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const h4* w = wh + 3 * ((j * MT + m) * 64 + lane);
+        t1[m] = mfma16(ar, w[0], t1[m]);
+        t2[m] = mfma16(ai, w[1], t2[m]);
+        t3[m] = mfma16(as, w[2], t3[m]);
+      }
+    }
+    const float escale = ldexpf(1.f, emin == 127 ? 0 : -emin);
+    // optional LS epilogue for pilot symbols: y * conj(p) / |p|^2 per RE
+    cf sc[4] = {cf{escale, 0.f}, cf{escale, 0.f}, cf{escale, 0.f}, cf{escale, 0.f}};
+    if (ps.pilots) {
+      const long long slot = bi / ps.n_symb;
+      const int jp = ps.pilot_of[bi - slot * ps.n_symb];
+      if (jp >= 0) {
+        const cf* pv = ps.pilots + slot * ps.p_slot + (long long)jp * nre;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = n0 + 4 * kq + v;
+          const cf p = pv[n < nre ? n : nre - 1];
+          const float inv = fast_rcp(p.r * p.r + p.i * p.i) * escale;
+          sc[v] = cf{p.r * inv, -p.i * inv};
+        }
+      }
+    }
+    cf o[MT][4];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float re = t1[m][v] - t2[m][v];
+        const float im = t3[m][v] - t1[m][v] - t2[m][v];
+        o[m][v] = cf{re * sc[v].r - im * sc[v].i, re * sc[v].i + im * sc[v].r};
+      }
+    cf* yb = Y + bi * sy + (long long)n0 * nb;
+    if (n0 + 16 <= nre && nb == 16 * MT) {
+      const unsigned lo = (unsigned)(4 * kq * nb + col);
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) yb[lo + (unsigned)(v * nb + m * 16)] = o[m][v];
+    } else {
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = n0 + 4 * kq + v, b = m * 16 + col;
+          if (n < nre && b < nb) yb[(long long)(4 * kq + v) * nb + b] = o[m][v];
+        }
+    }
+  };
+  if (t0 >= ntiles) return;
+  Buf xa, xb;
+  load(xa, t0);
+  for (int t = t0; t < ntiles; t += 2 * nwave) {
+    load(xb, t + nwave);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(xa, t);
+    load(xa, t + 2 * nwave);
+    __builtin_amdgcn_sched_barrier(0);
+    if (t + nwave < ntiles) compute(xb, t + nwave);
+  }
+}
+
+template <int MT, int J>
+hipError_t launch_h16(const cf* W, const unsigned* Xh, const signed char* ex, cf* Y, int nb, int na, int nre,
+                      long long ldx, long long sx, long long sy, long long batch, const PilotScale& ps, int n_cu,
+                      hipStream_t s) {
+  const int ntn = (nre + 15) / 16;
+  const long long tiles = batch * ntn;  // < 2^30 (checked by the caller)
+  const size_t lds = (size_t)J * MT * 64 * 3 * sizeof(h4);
+  static const int per_cu = [&] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_beamform_h16<MT, J>, 64 * kWaves, lds) != hipSuccess ||
+        n < 1)
+      n = 1;
+    return n;
+  }();
+  long long blocks = (tiles + kWaves - 1) / kWaves;
+  const long long cap = (long long)n_cu * per_cu;
+  if (blocks > cap) blocks = cap;
+  hipLaunchKernelGGL((k_beamform_h16<MT, J>), dim3((unsigned)blocks), dim3(64 * kWaves), lds, s, W, Xh, ex, Y, nb, na,
+                     nre, ldx, sx, sy, (int)tiles, ntn, ps);
   return hipGetLastError();
 }
 
@@ -380,13 +527,13 @@ hipError_t launch_k_mt(const cf* W, const cf* X, const unsigned* Xh, const signe
                        int nre, long long ldx, long long sx, long long sy, long long batch, const PilotScale& ps,
                        int n_cu, hipStream_t s) {
   if (Xh) {
-    if (na <= 16) return launch_k<MT, 4, true>(W, X, Xh, ex, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
-    if (na <= 32) return launch_k<MT, 8, true>(W, X, Xh, ex, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
-    return launch_k<MT, 16, true>(W, X, Xh, ex, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+    if (na <= 16) return launch_h16<MT, 1>(W, Xh, ex, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+    if (na <= 32) return launch_h16<MT, 2>(W, Xh, ex, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+    return launch_h16<MT, 4>(W, Xh, ex, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
   }
-  if (na <= 16) return launch_k<MT, 4, false>(W, X, Xh, ex, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
-  if (na <= 32) return launch_k<MT, 8, false>(W, X, Xh, ex, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
-  return launch_k<MT, 16, false>(W, X, Xh, ex, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+  if (na <= 16) return launch_k<MT, 4>(W, X, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+  if (na <= 32) return launch_k<MT, 8>(W, X, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+  return launch_k<MT, 16>(W, X, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
 }
 
 constexpr size_t kWLdsMax = 64 * 1024;

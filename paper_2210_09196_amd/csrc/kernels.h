@@ -50,8 +50,9 @@ struct PilotScale {
 // Y_i[n][b] = sum_a W[b][a] X_i[a][n]; X_i = X + i*sx (row pitch ldx),
 // Y_i = Y + i*sy (RE-major, n_beams values per RE).  With Xh set, X is read
 // instead as FP16 pairs (half2 words, pitches in words) with row a of batch
-// item i scaled by 2^e, e from launch_fft's exponent table (rows = n_ant);
-// up to 64 antennas.
+// item i scaled by 2^e, e from launch_fft's exponent table (rows = n_ant),
+// and the product runs on FP16 matrix cores with FP32 accumulation (W
+// rounded to FP16); up to 64 antennas.
 hipError_t launch_beamform(const cf* W, const cf* X, cf* Y, int n_beams, int n_ant, int n_re, long long ldx,
                            long long sx, long long sy, long long batch, int n_cu, hipStream_t s,
                            const PilotScale* pilot_scale = nullptr, const unsigned* Xh = nullptr,

@@ -203,7 +203,8 @@ class Slot:
     """A fixed slot geometry with its device workspace, for repeated pusch_slot calls.
 
     precision="mixed" uses pusch_slot_mixed (FP16 active-bin grids between
-    OFDM demodulation and beamforming, FP32 arithmetic)."""
+    OFDM demodulation and beamforming, beamforming on FP16 matrix cores with
+    FP32 accumulation, FP32 estimation and detection)."""
 
     def __init__(self, n_ant: int, n_fft: int, n_sc: int, n_symb: int, n_beams: int, n_ue: int, pilot_symb,
                  sigma2: float, n_slot: int, W: torch.Tensor | None = None, device="cuda", precision: str = "fp32"):

@@ -1,8 +1,9 @@
 """GPU checks of pusch_slot_mixed (FP16 active-bin grids between OFDM
-demodulation and beamforming, FP32 arithmetic) against the FP32 chain and the
+demodulation and beamforming, beamforming on FP16 matrix cores with FP32
+accumulation, FP32 estimation and detection) against the FP32 chain and the
 FP64 oracle.
 
-Tolerance: the FP16 grids carry a relative rounding error of at most
+Tolerance: the FP16 grids and W carry a relative rounding error of at most
 u = 2^-11 per value (RMS about u / sqrt(3) ~ 2.8e-4), which the linear stages
 pass on and the detection amplifies by the conditioning of the Gram matrix;
 detected symbols must stay within NRMSE 2e-3 of the oracle, and the EVM of
