@@ -1,19 +1,24 @@
 // Beamforming (Sec. II; Table 1, row "BF"): a complex matrix product with
-// known coefficients, Y_i[n][b] = sum_a W[b][a] X_i[a][n], on gfx950 FP32
-// matrix cores.
+// known coefficients, Y_i[n][b] = sum_a W[b][a] X_i[a][n], on gfx950 matrix
+// cores.
 //
-// The paper computes 4x4 output windows per core in registers (Sec. V-B).
-// Here one wavefront owns an output tile of (16*MT beams) x 32 REs and walks
-// the antenna axis four at a time with v_mfma_f32_16x16x4_f32.  Each complex
-// step takes three real products (Gauss/Karatsuba):
+// The paper computes 4x4 output windows per core in registers (Sec. V-B);
+// here the matrix cores take that role.  Every complex step takes three real
+// products (Gauss/Karatsuba):
 //   T1 = Wr Xr,  T2 = Wi Xi,  T3 = (Wr + Wi)(Xr + Xi),
 //   Yr = T1 - T2,  Yi = T3 - T1 - T2,
-// 25% fewer matrix-core operations than the four-product form.  W is staged
-// once per workgroup in LDS in operand order (Wr, Wi, Wr + Wi per lane).  The
-// two 16-column MFMA tiles of a wavefront take interleaved columns (lane c
-// owns columns 2c and 2c+1), so one 16-byte load of the interleaved complex
-// grid feeds both tiles.  Operand layouts of the 16x16x4 instruction: lane l
-// supplies A[l%16][l/16] and B[l/16][l%16] and receives D[4*(l/16)+v][l%16].
+// 25% fewer matrix-core operations than the four-product form, with W staged
+// once per workgroup in LDS in operand order (Wr, Wi, Wr + Wi per lane).
+// Three kernels:
+//   k_beamform_k (up to 64 antennas): a wavefront owns 16 REs x (16*MT
+//     beams), keeps its tile's whole antenna axis in registers and prefetches
+//     the next tile during the current one's v_mfma_f32_16x16x4_f32s;
+//   k_beamform_h16 (mixed-precision slot): the same tiles from FP16 grids
+//     with per-row power-of-two scales, on v_mfma_f32_16x16x16_f16;
+//   k_beamform (any antenna count): 32-RE tiles walking the antenna axis in
+//     double-buffered chunks of 16.
+// Operand layouts of the 16x16x4 instruction: lane l supplies A[l%16][l/16]
+// and B[l/16][l%16] and receives D[4*(l/16)+v][l%16].
 //
 // Optional epilogue for the fused slot: outputs of pilot symbols are turned
 // into LS channel values y * conj(p) / |p|^2 before they are stored (the
@@ -58,6 +63,11 @@ __device__ __forceinline__ float4 mask_x(int4 v, int ks, int kq, int na, int nc,
                      __int_as_float(v.w & m1));
 }
 
+// Any antenna count: a wavefront owns (16*MT beams) x 32 REs.  Its two
+// 16-column MFMA tiles take interleaved columns (lane c owns columns 2c and
+// 2c+1), so one 16-byte load of the interleaved complex grid feeds both; the
+// antenna axis goes in double-buffered chunks of 4 K-steps; W is read from
+// LDS when it fits (64 KB), else from global memory.
 template <int MT, bool W_LDS, bool VEC>
 __global__ __launch_bounds__(64 * kWaves) void k_beamform(const cf* __restrict__ W, const cf* __restrict__ X,
                                                           cf* __restrict__ Y, int nb, int na, int nre, long long ldx,

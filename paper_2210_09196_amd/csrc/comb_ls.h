@@ -1,6 +1,7 @@
 // Device-side LS channel estimate of one UE at one subcarrier from comb
-// pilots (Sec. II, CHE), shared by the stand-alone estimation kernel and the
-// detection kernel that estimates on the fly inside the fused slot.
+// pilots (Sec. II, CHE): the stand-alone estimation kernel evaluates it
+// directly, and the kernel that builds the interpolation taps of the fused
+// slot uses the same brackets.
 //
 // On pilot symbol j, subcarrier k carries UE (k + j*step) mod n_ue's pilot,
 // step = n_ue / n_pilot, so UE l's pilot subcarriers on symbol j are the
@@ -15,11 +16,6 @@
 #include "kernels.h"
 
 namespace pusch {
-
-__device__ __forceinline__ int pmod(int a, int m) {
-  const int r = a % m;
-  return r < 0 ? r + m : r;
-}
 
 // a mod m in [0, m) for |a| < 2^20, with inv_m = 1/m: a float quotient
 // corrected by one step (avoids the integer division sequence).
@@ -113,35 +109,6 @@ __device__ __forceinline__ void ls_at(cf (&out)[NBV], const cf* __restrict__ Y, 
       const cf v = y[e];
       sr[e] += __builtin_fmaf(v.r, pv.r, v.i * pv.i) * inv;  // y * conj(p) / |p|^2
       si[e] += __builtin_fmaf(v.i, pv.r, -v.r * pv.i) * inv;
-    }
-  }
-  const float ic = inv_count(mask);
-#pragma unroll
-  for (int e = 0; e < NBV; ++e) out[e] = cf{sr[e] * ic, si[e] * ic};
-}
-
-// The same value from grids that already hold y * conj(p) / |p|^2 per RE
-// (the fused slot divides in the beamforming epilogue).
-template <int NBV>
-__device__ __forceinline__ void merged_at(cf (&out)[NBV], const cf* __restrict__ LS, const ChestGeom& g,
-                                          unsigned mask, int p, int b0) {
-  const int nb = g.n_beams;
-  if ((mask & (mask - 1)) == 0) {  // one pilot symbol at p: no averaging
-    const cf* v = LS + pilot_grid(g, __ffs(mask) - 1) + (p * nb + b0);
-#pragma unroll
-    for (int e = 0; e < NBV; ++e) out[e] = v[e];
-    return;
-  }
-  float sr[NBV], si[NBV];
-#pragma unroll
-  for (int e = 0; e < NBV; ++e) sr[e] = si[e] = 0.f;
-  for (unsigned m = mask; m; m &= m - 1) {
-    const int j = __ffs(m) - 1;
-    const cf* v = LS + pilot_grid(g, j) + (p * nb + b0);
-#pragma unroll
-    for (int e = 0; e < NBV; ++e) {
-      sr[e] += v[e].r;
-      si[e] += v[e].i;
     }
   }
   const float ic = inv_count(mask);

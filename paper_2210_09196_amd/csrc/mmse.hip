@@ -15,15 +15,15 @@
 //   Crout factorisation with one lane per row of L (16 lanes per subcarrier,
 //   row j broadcast by cross-lane shuffles).  Phase C runs both
 //   substitutions with one lane per data symbol, reading L from LDS by
-//   broadcast.  With FUSED the kernel interpolates H itself (comb_ls.h) from
-//   the LS values that the beamforming epilogue leaves in the pilot symbols,
-//   so the fused slot never writes or re-reads a channel estimate.
+//   broadcast.  With FUSED the kernel interpolates H itself, from the LS
+//   values that the beamforming epilogue leaves in the pilot symbols and a
+//   table of interpolation taps (launch_comb_taps), so the fused slot never
+//   writes or re-reads a channel estimate.
 //
 // k_mmse_rows (n_ue <= 32): lane i of a group of LPS lanes holds row i of G
 //   and L; Gram and matched filter from LDS-staged H and y on the VALU.
 #include <cmath>
 
-#include "comb_ls.h"
 #include "kernels.h"
 
 namespace pusch {
