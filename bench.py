@@ -49,7 +49,7 @@ STAGE_FLOPS = {
     "mmse": 8 * K * (B * L * L + L ** 3 // 6 + D * (B * L + L * L)),
 }
 SLOT_FLOOR_BYTES = S * R * N * 8 + D * K * L * 8 + K * 4  # time-domain input + detected symbols
-STAGE_KERNEL = {"fft": "k_fft<4096>", "beamform": "k_beamform_k<2, 16>", "mmse": "k_mmse_mfma<8, true, 2>"}
+STAGE_KERNEL = {"fft": "k_fft<4096, false>", "beamform": "k_beamform_k<2, 16>", "mmse": "k_mmse_mfma<8, true, 2>"}
 STAGE_SOURCE = {"fft": "fft.hip", "beamform": "beamform.hip", "mmse": "mmse.hip"}
 TRAFFIC_FILE = "profiles/hbm_traffic_paper_scale.md"
 
