@@ -99,6 +99,13 @@ def test_fft_full_size_sampled():
     (64, 64, 100, 100, 2, False),
     (48, 20, 17, 17, 1, False),
     (1, 1, 1, 1, 1, False),
+    # more than 64 antennas: the chunked kernel, W in LDS (first three) or read
+    # from global memory (last two); 16-byte or 8-byte (odd pitch) X loads
+    (16, 65, 300, 300, 2, False),
+    (32, 128, 3300, 3300, 2, True),
+    (64, 100, 77, 77, 3, False),
+    (64, 200, 129, 131, 2, False),
+    (32, 1024, 40, 40, 1, False),
 ])
 def test_beamform(nb, na, n_re, ld_x, batch, builtin):
     rng = np.random.default_rng(nb * 1000 + na)
@@ -106,6 +113,20 @@ def test_beamform(nb, na, n_re, ld_x, batch, builtin):
     W = O.dft_beamformer(nb, na) if builtin else crandn(rng, nb, na)
     Y = host(pusch.beamform(dev(X), nb, W=None if builtin else dev(W), n_re=n_re))
     ref = np.swapaxes(O.beamform(W, X[:, :, :n_re]), 1, 2)  # RE-major
+    assert_grid(Y, ref)
+
+
+def test_beamform_long_row_pitch():
+    # 16 antennas, rows 2^24 elements apart: offsets past 32 bits take the
+    # chunked kernel with 64-bit addressing
+    na, nb, nre, ld = 16, 16, 300, 1 << 24
+    rng = np.random.default_rng(5)
+    Xs = crandn(rng, 1, na, nre)
+    X = torch.zeros(1, na, ld, dtype=torch.complex64, device=DEV)
+    X[:, :, :nre] = dev(Xs)
+    Y = host(pusch.beamform(X, nb, n_re=nre))
+    del X
+    ref = np.swapaxes(O.beamform(O.dft_beamformer(nb, na), Xs), 1, 2)
     assert_grid(Y, ref)
 
 
@@ -279,6 +300,8 @@ def test_slot_cfg2_full_batch_sampled():
     dict(n_ant=16, n_fft=256, n_sc=200, n_beams=6, n_ue=2, pilot_symb=(0, 4, 7, 11), qam_bits=6, channel="tdl"),
     # odd number of beams: stand-alone estimation kernel and stored estimate
     dict(n_ant=16, n_fft=256, n_sc=256, n_beams=15, n_ue=4, pilot_symb=(2,), qam_bits=4, channel="flat"),
+    # more than 64 antennas: chunked beamforming kernel inside the slot
+    dict(n_ant=128, n_fft=256, n_sc=200, n_beams=32, n_ue=8, pilot_symb=(2, 11), qam_bits=4, channel="tdl"),
 ])
 def test_slot_other_geometries(geom):
     cfg = synth.CFG1.replace(snr_db=25.0, **geom)
