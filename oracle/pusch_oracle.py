@@ -22,7 +22,10 @@ Readings of points the paper leaves open (each also stated where used):
       one estimate and the Cholesky factor is computed once per subcarrier and
       reused for every data symbol;
   R12 a non-positive or non-finite Cholesky pivot flags the subcarrier
-      (status 1) and its detected symbols are set to 0.
+      (status 1) and its detected symbols are set to 0;
+  R17 noise estimation compares each pilot RE with the prediction from the
+      UE's channel interpolated from its other pilot positions (leave one
+      out), normalised by the exact noise gain of that prediction.
 """
 from __future__ import annotations
 
@@ -35,6 +38,7 @@ __all__ = [
     "beamform",
     "pilot_owner",
     "ls_channel_estimate",
+    "noise_variance_estimate",
     "gram",
     "cholesky_crout",
     "forward_substitution",
@@ -130,6 +134,65 @@ def ls_channel_estimate(Yp, pilots, n_ue: int) -> np.ndarray:
     return H
 
 
+def noise_variance_estimate(Yp, pilots, n_ue: int) -> float:
+    """Noise estimation (Sec. II, NE; Table 1, row "NE"): the noise variance
+    from the differences between the received pilot REs and the values that
+    the estimated channel and the known pilots predict there (reading R17).
+
+    Pilot RE (j, k) belongs to UE l (reading R5).  Its prediction is
+    p_j[k] h(k), where h(k) is UE l's channel interpolated as in
+    ls_channel_estimate (merged LS values, linear between the nearest
+    positions, end-value hold) but from UE l's pilot positions other than k:
+    the nearest one below and the nearest one above, or the nearest one on
+    the only side there is.  The interpolation passes through every pilot
+    position, so without leaving k out the difference would be zero.
+    If h(k) = sum_i w_i m_i, with m_i the mean of c_i LS values at position i
+    from pilots p_s, the difference r = Y_j[:, k] - p_j[k] h(k) has noise
+    variance sigma^2 * kappa per beam, with
+        kappa = 1 + |p_j[k]|^2 sum_i (w_i / c_i)^2 sum_{s at i} 1 / |p_s|^2,
+    and the estimate is sum |r|^2 over all pilot REs and beams divided by
+    N_B sum kappa: unbiased whenever the channel is linear in k between the
+    positions used.  Requires K >= 2 N_L (every UE then has at least two
+    pilot positions).
+
+    Yp: [N_p, N_B, K] beam-domain pilot symbols; pilots: [N_p, K].
+    Returns sigma2_hat (float).
+    """
+    Yp = np.asarray(Yp, np.complex128)
+    pilots = np.asarray(pilots, np.complex128)
+    n_pilot, n_beams, K = Yp.shape
+    if K < 2 * n_ue:
+        raise ValueError("noise estimation needs at least two pilot subcarriers per UE")
+    num, den = 0.0, 0.0
+    for l in range(n_ue):
+        # the pilot REs of UE l, grouped by subcarrier
+        at = {}
+        for j in range(n_pilot):
+            for k in np.nonzero(pilot_owner(K, j, n_ue, n_pilot) == l)[0]:
+                at.setdefault(int(k), []).append(j)
+        pos = sorted(at)
+        mean, cnt, inv_pow = {}, {}, {}
+        for k in pos:
+            ls = [Yp[j][:, k] * np.conj(pilots[j, k]) / abs(pilots[j, k]) ** 2 for j in at[k]]
+            mean[k] = sum(ls) / len(ls)
+            cnt[k] = len(ls)
+            inv_pow[k] = sum(1.0 / abs(pilots[j, k]) ** 2 for j in at[k])
+        for i, k in enumerate(pos):
+            below = pos[i - 1] if i > 0 else None
+            above = pos[i + 1] if i + 1 < len(pos) else None
+            if below is not None and above is not None:
+                weights = {below: (above - k) / (above - below), above: (k - below) / (above - below)}
+            else:
+                weights = {below if above is None else above: 1.0}
+            h = sum(w * mean[m] for m, w in weights.items())
+            gain = sum((w / cnt[m]) ** 2 * inv_pow[m] for m, w in weights.items())
+            for j in at[k]:
+                r = Yp[j][:, k] - pilots[j, k] * h
+                num += float(np.sum(r.real ** 2 + r.imag ** 2))
+                den += n_beams * (1.0 + abs(pilots[j, k]) ** 2 * gain)
+    return num / den
+
+
 def gram(H, sigma2: float) -> np.ndarray:
     """Regularised Gram matrix of Eq. 2: G = H^H H + sigma^2 I per subcarrier.
 
@@ -213,13 +276,16 @@ def mmse_detect(H, Yd, sigma2: float) -> tuple[np.ndarray, np.ndarray]:
     return x, ok
 
 
-def receive_slot(x_td, pilots, pilot_symb, n_ue: int, n_sc: int, sigma2: float, W=None, n_beams: int | None = None) -> dict:
+def receive_slot(x_td, pilots, pilot_symb, n_ue: int, n_sc: int, sigma2: float | None, W=None,
+                 n_beams: int | None = None) -> dict:
     """The whole receive chain of one slot (Sec. II), in the paper's order.
 
     x_td: [S, N_R, N] time-domain samples; pilots: [N_p, K]; pilot_symb: the
     0-based pilot symbol indices.  W defaults to the DFT beamformer with
-    n_beams rows.  Returns a dict with the intermediates and the result:
-    X [S, N_R, K], Y [S, N_B, K], H [K, N_B, N_L], x_hat [D, K, N_L], ok [K].
+    n_beams rows.  sigma2 None: the noise variance is estimated from the
+    pilot symbols (noise_variance_estimate) and used in the MIMO stage.
+    Returns a dict with the intermediates and the result: X [S, N_R, K],
+    Y [S, N_B, K], H [K, N_B, N_L], sigma2, x_hat [D, K, N_L], ok [K].
     """
     x_td = np.asarray(x_td)
     S, n_ant, _ = x_td.shape
@@ -230,6 +296,8 @@ def receive_slot(x_td, pilots, pilot_symb, n_ue: int, n_sc: int, sigma2: float, 
     pilot_symb = list(pilot_symb)
     data_symb = [s for s in range(S) if s not in pilot_symb]
     H = ls_channel_estimate(Y[pilot_symb], pilots, n_ue)
+    if sigma2 is None:
+        sigma2 = noise_variance_estimate(Y[pilot_symb], pilots, n_ue)
     Yd = np.swapaxes(Y[data_symb], -1, -2)  # [D, K, N_B]
     x_hat, ok = mmse_detect(H, Yd, sigma2)
-    return {"X": X, "Y": Y, "H": H, "x_hat": x_hat, "ok": ok}
+    return {"X": X, "Y": Y, "H": H, "sigma2": sigma2, "x_hat": x_hat, "ok": ok}

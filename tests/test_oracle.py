@@ -316,6 +316,83 @@ def test_single_ue_qpsk_ber_matches_rayleigh_mrc_closed_form():
     assert abs(ber - pb) < 5 * sd + 1e-4
 
 
+# ----------------------------------------------------------------------------- noise estimation
+
+def _ne_golden(mod, g, e):
+    return mod.noise_variance_estimate(np.array(g[e + "_Y"], complex), np.array(g[e + "_pilots"], complex),
+                                       g[e + "_n_ue"])
+
+
+def test_noise_estimate_golden(golden):
+    g = golden("ne_small.txt")
+    for e in "ABC":
+        assert abs(_ne_golden(O, g, e) - g[e + "_sigma2"]) <= 1e-14 * g[e + "_sigma2"], e
+
+
+def _ne_inputs(rng, K, n_ue, n_pilot, n_beams, sigma2, slope=0.0):
+    """Pilot symbols through a channel h_l(k) = a_l + slope * k b_l per beam, plus CN(0, sigma2) noise;
+    pilots of random phase and magnitude 0.5..2."""
+    a = crandn(n_ue, n_beams, rng=rng)
+    b = crandn(n_ue, n_beams, rng=rng)
+    p = rng.uniform(0.5, 2.0, (n_pilot, K)) * np.exp(2j * np.pi * rng.uniform(size=(n_pilot, K)))
+    Y = np.zeros((n_pilot, n_beams, K), complex)
+    for j in range(n_pilot):
+        for k in range(K):
+            l = (k + j * (n_ue // n_pilot)) % n_ue
+            Y[j, :, k] = (a[l] + slope * k * b[l]) * p[j, k]
+    Y += crandn(n_pilot, n_beams, K, rng=rng) * math.sqrt(sigma2 / 2)
+    return Y, p
+
+
+@pytest.mark.parametrize("n_ue,n_pilot", [(4, 2), (2, 4), (3, 2), (1, 1)])
+def test_noise_estimate_noiseless_flat_channel_is_zero(n_ue, n_pilot):
+    Y, p = _ne_inputs(np.random.default_rng(n_ue * 10 + n_pilot), 40, n_ue, n_pilot, 3, 0.0)
+    assert O.noise_variance_estimate(Y, p, n_ue) <= 1e-28
+
+
+@pytest.mark.parametrize("n_ue,n_pilot", [(4, 2), (2, 4), (3, 2)])
+def test_noise_estimate_is_unbiased(n_ue, n_pilot):
+    # stagger (4, 2), all pilot symbols on the same subcarriers (2, 4: four values averaged per
+    # position) and unequal gaps (3, 2); pilots of unequal power
+    rng = np.random.default_rng(77 + n_ue)
+    sigma2 = 0.3
+    ratios = []
+    for _ in range(40):
+        Y, p = _ne_inputs(rng, 200, n_ue, n_pilot, 4, sigma2)
+        ratios.append(O.noise_variance_estimate(Y, p, n_ue) / sigma2)
+    m, se = np.mean(ratios), np.std(ratios, ddof=1) / math.sqrt(len(ratios))
+    assert abs(m - 1.0) < 5 * se, (m, se)
+    assert se < 0.02
+
+
+def test_noise_estimate_scales_with_power():
+    Y, p = _ne_inputs(np.random.default_rng(5), 60, 4, 2, 3, 0.5, slope=0.1)
+    s = O.noise_variance_estimate(Y, p, 4)
+    assert abs(O.noise_variance_estimate(Y * (3 - 4j), p, 4) - 25 * s) <= 1e-12 * 25 * s
+    # a common unit-modulus factor on the pilots and the received values changes nothing
+    assert abs(O.noise_variance_estimate(Y * 1j, p * 1j, 4) - s) <= 1e-12 * s
+
+
+def test_noise_estimate_needs_two_positions_per_ue():
+    with pytest.raises(ValueError):
+        O.noise_variance_estimate(np.ones((1, 2, 7)), np.ones((1, 7)), 4)
+
+
+def test_noise_estimate_in_the_chain():
+    cfg = synth.CFG1
+    s = synth.make_slot(cfg, 1000)
+    r = O.receive_slot(s["x_td"], s["pilots"], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, None, n_beams=cfg.n_beams)
+    # 256 pilot REs x 16 beams: standard error about 3 %
+    assert abs(r["sigma2"] / s["sigma2"] - 1.0) < 0.15
+    pts, lab = synth.qam_table(cfg.qam_bits)
+    _, bh = M.hard_decide(r["x_hat"], pts, lab)
+    assert np.mean(bh != np.swapaxes(s["bits"], 1, 2)) == 0.0
+    quiet = synth.make_slot(cfg.replace(snr_db=None), 1000)
+    r0 = O.receive_slot(quiet["x_td"], quiet["pilots"], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, None,
+                        n_beams=cfg.n_beams)
+    assert r0["sigma2"] < 1e-10  # flat channel, no noise: only the input's FP32 rounding remains
+
+
 # ----------------------------------------------------------------------------- end to end
 
 def test_chain_noiseless_cfg1_recovers_bits_exactly():
@@ -365,6 +442,9 @@ def _pins_pass(mod, golden) -> bool:
         g = golden("mmse_2x2.txt")
         xm, _ = mod.mmse_detect(np.array(g["H"], complex)[None], np.array(g["y"], complex)[None, None], g["sigma2"])
         assert np.allclose(xm[0, 0], g["x"], atol=1e-12)
+        g = golden("ne_small.txt")
+        for e in "ABC":
+            assert abs(_ne_golden(mod, g, e) - g[e + "_sigma2"]) <= 1e-12
         g = golden("ls_comb_small.txt")
         H = mod.ls_channel_estimate(np.array(g["Y"], complex)[None, None, :], np.array(g["pilots"], complex)[None], 2)
         assert np.allclose(H[:, 0, 0], g["H_ue0"]) and np.allclose(H[:, 0, 1], g["H_ue1"])
@@ -395,6 +475,14 @@ MUTATIONS = [
     ("np.conj(L[..., i + 1:, i]) * x[..., i + 1:]", "L[..., i + 1:, i] * x[..., i + 1:]"),
     ('np.einsum("kbl,dkb->dkl", np.conj(H), Yd)', 'np.einsum("kbl,dkb->dkl", H, Yd)'),
     ("return G + float(sigma2) * np.eye(n)", "return G + float(sigma2)"),
+    # noise estimation: noise gain dropped, no leave-one-out, swapped weights, unsquared weights,
+    # conjugated pilot in the prediction
+    ("den += n_beams * (1.0 + abs(pilots[j, k]) ** 2 * gain)", "den += n_beams * 1.0"),
+    ("h = sum(w * mean[m] for m, w in weights.items())", "h = mean[k]"),
+    ("weights = {below: (above - k) / (above - below), above: (k - below) / (above - below)}",
+     "weights = {below: (k - below) / (above - below), above: (above - k) / (above - below)}"),
+    ("gain = sum((w / cnt[m]) ** 2 * inv_pow[m]", "gain = sum((w / cnt[m]) * inv_pow[m]"),
+    ("r = Yp[j][:, k] - pilots[j, k] * h", "r = Yp[j][:, k] - np.conj(pilots[j, k]) * h"),
 ]
 
 
