@@ -121,6 +121,32 @@ int pusch_chest(const pusch_c32* Yp, const pusch_c32* pilots, pusch_c32* H, int 
                 int n_pilot, long long batch, void* stream);
 
 /*
+ * Noise-variance estimation (Sec. II, NE; Table 1, row "NE"): the variance of
+ * the difference between the received pilot REs and the values that the
+ * estimated channel and the known pilots predict there, per batch item.
+ * The LS estimate of pusch_chest passes through every pilot position, so
+ * the prediction for pilot RE (j, k) of UE l is p_j[k] times UE l's channel
+ * interpolated (as pusch_chest) from its OTHER pilot positions: the nearest
+ * one below k and the nearest one above, or the nearest one on the only side
+ * there is.  With weights w_i on positions holding c_i averaged LS values of
+ * pilots p_s, the difference r = y - p h has noise variance sigma^2 kappa
+ * per beam, kappa = 1 + |p|^2 sum_i (w_i / c_i)^2 sum_{s at i} 1 / |p_s|^2, and
+ *   sigma2[i] = sum |r|^2 / (n_beams * sum kappa)
+ * over all pilot REs of item i: unbiased for white noise of equal variance
+ * on every beam (unitary beamformer rows) when the channel is linear in k
+ * between the positions used; channel variation beyond that adds to it.
+ *   Yp, pilots  as pusch_chest.
+ *   sigma2 [batch] FP32 estimates (device).
+ *   ws     device scratch of at least pusch_noise_est_workspace_bytes(batch)
+ *          bytes, 8-byte aligned; its contents are not needed afterwards.
+ *   n_sc >= 2 n_ue (every UE has two pilot positions), other limits as
+ *   pusch_chest.  sigma2, ws, Yp and pilots must not overlap.
+ */
+size_t pusch_noise_est_workspace_bytes(long long batch);
+int pusch_noise_est(const pusch_c32* Yp, const pusch_c32* pilots, float* sigma2, int n_beams, int n_ue, int n_sc,
+                    int n_pilot, long long batch, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * MMSE MIMO detection (Eq. 2) per subcarrier: G = H^H H + sigma2 I, the
  * Cholesky factor G = L L^H (Crout order, Sec. V-C), then for every data
  * symbol the matched filter b = H^H y, forward substitution L z = b and back
@@ -147,21 +173,26 @@ typedef struct {
   int n_ue;                         /* N_L, 1..min(PUSCH_MAX_UES, n_beams) */
   int n_pilot;                      /* pilot symbols, 1..min(PUSCH_MAX_PILOTS, n_symb - 1) */
   int pilot_symb[PUSCH_MAX_PILOTS]; /* 0-based pilot symbol indices, strictly ascending */
-  float sigma2;                     /* noise variance per RE after beamforming, >= 0 */
+  float sigma2;                     /* noise variance per RE after beamforming, >= 0 (unless noise_est) */
   const pusch_c32* W;               /* device [n_beams][n_ant], or NULL = built-in DFT rows */
   const pusch_c32* pilots;          /* device [n_slot][n_pilot][n_sc] */
+  int noise_est;                    /* nonzero: estimate each slot's noise variance from its pilot
+                                       symbols (as pusch_noise_est) and use it instead of sigma2;
+                                       needs n_sc >= 2 n_ue */
+  float* sigma2_est;                /* device [n_slot]: receives the estimates when noise_est is set,
+                                       or NULL; must not overlap any other buffer of the call */
 } pusch_slot_desc;
 
 /* Bytes of device workspace pusch_slot needs for n_slot slots (0 on bad input). */
 size_t pusch_slot_workspace_bytes(const pusch_slot_desc* d, long long n_slot);
-/* (Depends on the geometry fields only; W, pilots and sigma2 are not read.) */
+/* (Depends on the geometry fields only; W, pilots, sigma2, noise_est and sigma2_est are not read.) */
 
 /*
  * The fused receive chain (Sec. II, Fig. "PUSCH processing chain") for n_slot
  * independent slots, enqueued on one stream: OFDM demodulation of every
  * antenna and symbol to the n_sc active subcarriers, beamforming, LS channel
- * estimation on the pilot symbols, MMSE detection of every other ("data")
- * symbol in ascending symbol order.  With n_ue <= 16 and an even n_beams the
+ * estimation on the pilot symbols, optionally noise estimation (noise_est),
+ * MMSE detection of every other ("data") symbol in ascending symbol order.  With n_ue <= 16 and an even n_beams the
  * channel estimate is computed inside the detection kernel and never stored.
  *   x_td   [n_slot][n_symb][n_ant][n_fft] time-domain samples.
  *   x_hat  [n_slot][n_data][n_sc][n_ue], n_data = n_symb - n_pilot.
@@ -225,9 +256,9 @@ int pusch_cells(const pusch_slot_desc* d, int n_cells, const long long* n_slot, 
  * pusch_slot call (not the cells of pusch_cells) records an event before and after each of its
  * PUSCH_SLOT_STAGES launches on its stream, for up to max_calls calls.
  * pusch_profile_end(stage_ms, n) synchronises on the last event, writes the
- * summed device time of each stage (ms; order: fft, beamform, chest, mmse)
- * into stage_ms[0..n-1], releases the events and returns the number of calls
- * recorded (or a negative code).
+ * summed device time of each stage (ms; order: fft, beamform, chest = channel
+ * and noise estimation, mmse) into stage_ms[0..n-1], releases the events and
+ * returns the number of calls recorded (or a negative code).
  */
 #define PUSCH_SLOT_STAGES 4
 int pusch_profile_begin(int max_calls);

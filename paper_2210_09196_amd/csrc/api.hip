@@ -196,6 +196,38 @@ int pusch_chest(const pusch_c32* Yp, const pusch_c32* pilots, pusch_c32* H, int 
                                         reinterpret_cast<cf*>(H), g, batch, static_cast<hipStream_t>(stream)));
 }
 
+size_t pusch_noise_est_workspace_bytes(long long batch) {
+  return batch < 0 ? 0 : (size_t)batch * pusch::kNeParts * sizeof(float2);
+}
+
+int pusch_noise_est(const pusch_c32* Yp, const pusch_c32* pilots, float* sigma2, int n_beams, int n_ue, int n_sc,
+                    int n_pilot, long long batch, void* ws, size_t ws_bytes, void* stream) {
+  if (!Yp || !pilots || !sigma2 || batch < 0) return PUSCH_EINVAL;
+  if (n_pilot < 1 || n_pilot > PUSCH_MAX_PILOTS) return PUSCH_EINVAL;
+  if (n_beams < 1 || n_beams > PUSCH_MAX_BEAMS) return PUSCH_EINVAL;
+  if (n_ue < 1 || n_ue > PUSCH_MAX_UES || n_ue > n_beams || n_sc < 2 * n_ue) return PUSCH_EINVAL;
+  if (batch == 0) return PUSCH_OK;
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 7)) return PUSCH_EINVAL;
+  const long long need = (long long)pusch_noise_est_workspace_bytes(batch);
+  if (ws_bytes < (size_t)need) return PUSCH_ENOMEM;
+  const long long yb = batch * n_pilot * (long long)n_sc * n_beams * 8, pb = batch * n_pilot * (long long)n_sc * 8;
+  if (overlap(sigma2, batch * 4, Yp, yb) || overlap(sigma2, batch * 4, pilots, pb) ||
+      overlap(sigma2, batch * 4, ws, need) || overlap(ws, need, Yp, yb) || overlap(ws, need, pilots, pb))
+    return PUSCH_EINVAL;
+  pusch::ChestGeom g{};
+  g.n_beams = n_beams;
+  g.n_ue = n_ue;
+  g.n_sc = n_sc;
+  g.n_pilot = n_pilot;
+  g.y_batch = (long long)n_pilot * n_sc * n_beams;
+  g.y_sym = (long long)n_sc * n_beams;
+  for (int j = 0; j < n_pilot; ++j) g.pilot_sym[j] = j;
+  g.p_batch = (long long)n_pilot * n_sc;
+  return hip_status(pusch::launch_noise_est(reinterpret_cast<const cf*>(Yp), reinterpret_cast<const cf*>(pilots),
+                                            false, static_cast<float2*>(ws), sigma2, g, batch,
+                                            static_cast<hipStream_t>(stream)));
+}
+
 int pusch_mmse_solve(const pusch_c32* H, const pusch_c32* Yd, float sigma2, pusch_c32* Xhat, int n_beams, int n_ue,
                      int n_sc, int n_data, long long batch, int32_t* status, void* stream) {
   if (!H || !Yd || !Xhat || batch < 0 || n_sc < 0 || n_data < 1) return PUSCH_EINVAL;
@@ -239,7 +271,7 @@ int pusch_mmse_solve(const pusch_c32* H, const pusch_c32* Yd, float sigma2, pusc
 namespace {
 
 struct SlotLayout {
-  size_t off_xa, off_ex, off_y, off_h, off_comb, total;
+  size_t off_xa, off_ex, off_y, off_h, off_comb, off_ne, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -264,10 +296,19 @@ int check_geom(const pusch_slot_desc* d) {
 
 int check_desc(const pusch_slot_desc* d) {
   if (int rc = check_geom(d)) return rc;
-  if (!(d->sigma2 >= 0.f) || !std::isfinite(d->sigma2)) return PUSCH_EINVAL;
+  if (d->noise_est) {
+    // noise estimation: every UE needs two pilot positions
+    if (d->n_sc < 2 * d->n_ue) return PUSCH_EINVAL;
+  } else if (!(d->sigma2 >= 0.f) || !std::isfinite(d->sigma2)) {
+    return PUSCH_EINVAL;
+  }
   if (!d->pilots) return PUSCH_EINVAL;
   return PUSCH_OK;
 }
+
+// Noise-estimation scratch: kNeParts partial sums per slot, then the
+// per-slot estimates (used when the caller asks for none).
+size_t ne_part_bytes(long long n_slot) { return (size_t)n_slot * pusch::kNeParts * sizeof(float2); }
 
 // Row pitch of the active-bin grids between the FFT and beamforming: a
 // multiple of 16 subcarriers, so every antenna row starts on a 128-byte line
@@ -297,7 +338,8 @@ SlotLayout slot_layout(const pusch_slot_desc* d, long long n_slot, bool mixed = 
   const bool fused = pusch::mmse_fusable(d->n_ue, d->n_beams, (long long)d->n_symb * K * B);
   lay.off_comb = lay.off_h + (fused ? 0 : align256(n * K * L * B * 8));
   // channel interpolation taps (fused path), one table for all slots
-  lay.total = lay.off_comb + (fused ? align256(K * L * pusch::comb_taps(d->n_ue, d->n_pilot) * 8) : 0);
+  lay.off_ne = lay.off_comb + (fused ? align256(K * L * pusch::comb_taps(d->n_ue, d->n_pilot) * 8) : 0);
+  lay.total = lay.off_ne + align256(ne_part_bytes(n_slot) + n * sizeof(float));
   return lay;
 }
 
@@ -327,6 +369,14 @@ int check_slot_call(const pusch_slot_desc* d, long long n_slot, const pusch_c32*
       overlap(ws, wb, x_td, xb) || overlap(status, sb, x_td, xb) || overlap(status, sb, ws, wb) ||
       overlap(ws, wb, d->pilots, n_slot * (long long)P * K * 8) || overlap(ws, wb, d->W, (long long)B * R * 8))
     return PUSCH_EINVAL;
+  if (d->noise_est && d->sigma2_est) {
+    const long long eb = n_slot * 4;
+    if (overlap(d->sigma2_est, eb, x_td, xb) || overlap(d->sigma2_est, eb, x_hat, ob) ||
+        overlap(d->sigma2_est, eb, status, sb) || overlap(d->sigma2_est, eb, ws, wb) ||
+        overlap(d->sigma2_est, eb, d->pilots, n_slot * (long long)P * K * 8) ||
+        overlap(d->sigma2_est, eb, d->W, (long long)B * R * 8))
+      return PUSCH_EINVAL;
+  }
   return PUSCH_OK;
 }
 
@@ -388,6 +438,16 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   cg.h_batch = (long long)K * L * B;
   if (!fused && pusch::launch_chest(Y, reinterpret_cast<const cf*>(d->pilots), H, cg, n_slot, s) != hipSuccess)
     return PUSCH_EHIP;
+  // noise variance of every slot from its pilot symbols (which hold LS
+  // values when fused, received values otherwise)
+  float* s2 = nullptr;
+  if (d->noise_est) {
+    float2* part = reinterpret_cast<float2*>(base + lay.off_ne);
+    s2 = d->sigma2_est ? d->sigma2_est : reinterpret_cast<float*>(base + lay.off_ne + ne_part_bytes(n_slot));
+    if (pusch::launch_noise_est(Y, reinterpret_cast<const cf*>(d->pilots), fused, part, s2, cg, n_slot, s) !=
+        hipSuccess)
+      return PUSCH_EHIP;
+  }
   // MMSE detection: Gram, Cholesky, matched filter and substitutions for the data
   // symbols (with the channel estimate computed inside when fused)
   if (!mark(3)) return PUSCH_EHIP;
@@ -396,7 +456,8 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   mg.n_ue = L;
   mg.n_sc = K;
   mg.n_data = D;
-  mg.sigma2 = d->sigma2;
+  mg.sigma2 = d->noise_est ? 0.f : d->sigma2;
+  mg.sigma2_item = s2;
   mg.h_batch = (long long)K * L * B;
   mg.y_batch = (long long)S * K * B;
   mg.y_sym = (long long)K * B;
@@ -490,6 +551,9 @@ int pusch_cells(const pusch_slot_desc* d, int n_cells, const long long* n_slot, 
         overlap(ws, wall, d[c].pilots, n_slot[c] * (long long)d[c].n_pilot * d[c].n_sc * 8) ||
         overlap(ws, wall, d[c].W, (long long)d[c].n_beams * d[c].n_ant * 8))
       return PUSCH_EINVAL;
+    const float* e_c = d[c].noise_est ? d[c].sigma2_est : nullptr;
+    const long long eb = n_slot[c] * 4;
+    if (overlap(ws, wall, e_c, eb)) return PUSCH_EINVAL;
     for (int e = 0; e < n_cells; ++e) {
       if (e == c) continue;
       const long long xb = n_slot[e] * (long long)d[e].n_symb * d[e].n_ant * d[e].n_fft * 8;
@@ -500,6 +564,12 @@ int pusch_cells(const pusch_slot_desc* d, int n_cells, const long long* n_slot, 
           overlap(x_hat[c], ob, st_e, sb2) || overlap(st_c, sb, x_td[e], xb) || overlap(st_c, sb, st_e, sb2) ||
           overlap(x_hat[c], ob, d[e].pilots, n_slot[e] * (long long)d[e].n_pilot * d[e].n_sc * 8) ||
           overlap(st_c, sb, d[e].pilots, n_slot[e] * (long long)d[e].n_pilot * d[e].n_sc * 8))
+        return PUSCH_EINVAL;
+      // a cell's estimates against every buffer of another cell
+      const float* e_e = d[e].noise_est ? d[e].sigma2_est : nullptr;
+      if (overlap(e_c, eb, x_td[e], xb) || overlap(e_c, eb, x_hat[e], ob2) || overlap(e_c, eb, st_e, sb2) ||
+          overlap(e_c, eb, d[e].pilots, n_slot[e] * (long long)d[e].n_pilot * d[e].n_sc * 8) ||
+          overlap(e_c, eb, e_e, n_slot[e] * 4) || overlap(e_c, eb, d[e].W, (long long)d[e].n_beams * d[e].n_ant * 8))
         return PUSCH_EINVAL;
     }
   }

@@ -89,6 +89,18 @@ hipError_t launch_chest(const cf* Y, const cf* pilots, cf* H, const ChestGeom& g
 int comb_taps(int n_ue, int n_pilot);  // taps per (k, l) the geometry needs: 2 or 8
 hipError_t launch_comb_taps(int2* tab, const ChestGeom& g, int n_tap, hipStream_t s);
 
+// ---------------------------------------------------------------- noise estimation
+// Noise variance of every batch item from its pilot symbols (grids at
+// pilot_sym[j] * y_sym as for launch_chest): each pilot RE against the
+// prediction of its UE's channel interpolated from the UE's other pilot
+// positions, normalised by the noise gain of that prediction.  ls: the pilot
+// grids already hold LS values y*conj(p)/|p|^2 (PilotScale epilogue) instead
+// of received values.  part: kNeParts float2 per batch item (scratch);
+// sigma2: [batch].  Requires n_sc >= 2 * n_ue.
+constexpr int kNeParts = 64;
+hipError_t launch_noise_est(const cf* Y, const cf* pilots, bool ls, float2* part, float* sigma2, const ChestGeom& g,
+                            long long batch, hipStream_t s);
+
 // ---------------------------------------------------------------- MMSE detection
 struct MmseGeom {
   long long h_batch;          // H elements between batch items
@@ -101,6 +113,7 @@ struct MmseGeom {
   int skip[kMaxPilots];       //   counting data symbols)
   int n_beams, n_ue, n_sc, n_data;
   float sigma2;
+  const float* sigma2_item;   // device [batch] noise variance per batch item, or nullptr = sigma2
 };
 hipError_t launch_mmse(const cf* H, const cf* Y, cf* Xhat, int* status, const MmseGeom& g, long long batch,
                        hipStream_t s);

@@ -105,9 +105,10 @@ __global__ __launch_bounds__(64) void k_mmse_rows(const cf* __restrict__ H, cons
         }
       }
     }
+    const float s2 = g.sigma2_item ? g.sigma2_item[bi] : g.sigma2;
 #pragma unroll
     for (int j = 0; j < LPS; ++j)
-      if (j == i) G[j].r += g.sigma2;
+      if (j == i) G[j].r += s2;
 
     // matched filter r_d = H^H y_d for every data symbol
     cf rr[kMaxD];
@@ -544,7 +545,8 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
     cf* Grow = Gm + tri(i);
     // regularise the own diagonal entry (padding rows beyond n_ue get 1 so
     // their part of L is the identity; so do the rows of a subcarrier past n_sc)
-    Grow[i].r += (i < nue && k0 + grp < nsc) ? g.sigma2 : 1.0f;
+    const float s2 = g.sigma2_item ? g.sigma2_item[bi] : g.sigma2;
+    Grow[i].r += (i < nue && k0 + grp < nsc) ? s2 : 1.0f;
     cf L[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) L[j] = j <= i ? Grow[j] : cf{0.f, 0.f};

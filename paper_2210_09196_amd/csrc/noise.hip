@@ -1,0 +1,244 @@
+// Noise-variance estimation (Sec. II, NE; Table 1, row "NE"): the variance
+// of the difference between each received pilot RE and the value that the
+// estimated channel and the known pilot predict for it.
+//
+// The interpolated LS estimate passes through every pilot position, so the
+// prediction at pilot RE (j, k) of UE l uses UE l's merged LS values at its
+// other positions only: the nearest one below k and the nearest one above
+// (weights linear in k), or the nearest one on the only side there is.  With
+// weights w_i on positions holding c_i averaged LS values from pilots p_s,
+// the difference r = y - p h has noise variance sigma^2 kappa per beam,
+//   kappa = 1 + |p|^2 sum_i (w_i / c_i)^2 sum_{s at i} 1 / |p_s|^2,
+// and the estimate is sum |r|^2 / (N_B sum kappa) over the pilot REs of a
+// batch item.  Since y = p * LS(y), |r|^2 = |p|^2 |LS(y) - h|^2.
+//
+// Two launches: k_noise_partial sums |r|^2 and N_B kappa over kNeParts fixed
+// slices of an item's pilot REs; k_noise_final adds an item's slices and
+// divides.  Every sum runs in a fixed order (no atomics), so the result does
+// not depend on timing.
+//
+// Layout: BW lanes (a power of two) share one pilot RE, each taking NBV
+// consecutive beams of its RE-major row, so a group reads whole rows; the
+// neighbour search is closed-form per pilot symbol (the comb of residue
+// classes mod n_ue).
+#include "comb_ls.h"
+#include "kernels.h"
+
+namespace pusch {
+namespace {
+
+constexpr int kNeThreads = 256;
+
+__device__ __forceinline__ int pos_mod(int a, int m) {
+  const int r = a % m;
+  return r < 0 ? r + m : r;
+}
+
+struct NeNeighbours {
+  int lo, hi;          // nearest pilot subcarriers of the UE strictly below / above k (-1 / n_sc: none)
+  unsigned mlo, mhi;   // pilot symbols whose pilot for the UE sits there
+  float wlo, whi;      // prediction weights
+};
+
+__device__ __forceinline__ NeNeighbours ne_neighbours(int k, int l, int nue, int npil, int nsc) {
+  const int step = nue / npil;
+  NeNeighbours n;
+  n.lo = -1;
+  n.hi = nsc;
+  n.mlo = n.mhi = 0;
+  for (int j = 0; j < npil; ++j) {
+    const int rj = pos_mod(l - j * step, nue);            // UE l's residue class on pilot symbol j
+    const int plo = (k - 1) - pos_mod(k - 1 - rj, nue);  // largest position < k in that class
+    const int phi = (k + 1) + pos_mod(rj - k - 1, nue);  // smallest position > k
+    if (plo >= 0) {
+      if (plo > n.lo) {
+        n.lo = plo;
+        n.mlo = 1u << j;
+      } else if (plo == n.lo) {
+        n.mlo |= 1u << j;
+      }
+    }
+    if (phi < nsc) {
+      if (phi < n.hi) {
+        n.hi = phi;
+        n.mhi = 1u << j;
+      } else if (phi == n.hi) {
+        n.mhi |= 1u << j;
+      }
+    }
+  }
+  if (n.lo >= 0 && n.hi < nsc) {
+    const float inv = 1.f / (float)(n.hi - n.lo);
+    n.wlo = (float)(n.hi - k) * inv;
+    n.whi = (float)(k - n.lo) * inv;
+  } else {  // one side only: hold (the host guarantees at least one side)
+    n.wlo = n.lo >= 0 ? 1.f : 0.f;
+    n.whi = n.lo >= 0 ? 0.f : 1.f;
+  }
+  return n;
+}
+
+// LS value of pilot RE (j, p) for NBV consecutive beams: the grid value itself
+// when the pilot symbols already hold LS values, else y conj(p) / |p|^2.
+template <int NBV, bool LS>
+__device__ __forceinline__ void ls_value(float (&vr)[NBV], float (&vi)[NBV], const cf* __restrict__ Yb,
+                                         const ChestGeom& g, cf pv, int j, int p, int b0) {
+  const cf* y = Yb + pilot_grid(g, j) + ((long long)p * g.n_beams + b0);
+  const float inv = LS ? 1.f : 1.f / (pv.r * pv.r + pv.i * pv.i);
+#pragma unroll
+  for (int e = 0; e < NBV; ++e) {
+    const cf v = y[e];
+    vr[e] = LS ? v.r : (v.r * pv.r + v.i * pv.i) * inv;
+    vi[e] = LS ? v.i : (v.i * pv.r - v.r * pv.i) * inv;
+  }
+}
+
+// Mean LS value at position p over the pilot symbols in mask, accumulated
+// with weight w into (hr, hi); returns sum_{s in mask} 1 / |p_s|^2.
+template <int NBV, bool LS>
+__device__ __forceinline__ float add_mean(float (&hr)[NBV], float (&hi)[NBV], const cf* __restrict__ Yb,
+                                          const cf* __restrict__ Pb, const ChestGeom& g, unsigned mask, int p,
+                                          float w, int b0) {
+  const float wc = w / (float)__popc(mask);
+  float q = 0.f;
+  for (unsigned m = mask; m; m &= m - 1) {
+    const int j = __ffs(m) - 1;
+    const cf pv = Pb[(long long)j * g.n_sc + p];
+    q += 1.f / (pv.r * pv.r + pv.i * pv.i);
+    float vr[NBV], vi[NBV];
+    ls_value<NBV, LS>(vr, vi, Yb, g, pv, j, p, b0);
+#pragma unroll
+    for (int e = 0; e < NBV; ++e) {
+      hr[e] += wc * vr[e];
+      hi[e] += wc * vi[e];
+    }
+  }
+  return q;
+}
+
+__device__ __forceinline__ float2 wave_sum(float2 v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    v.x += __shfl_xor(v.x, o);
+    v.y += __shfl_xor(v.y, o);
+  }
+  return v;
+}
+
+// grid: (n_parts, min(batch, 65535)); part[item * kNeParts + blockIdx.x] = (sum |r|^2, sum N_B kappa)
+template <int NBV, bool LS>
+__global__ __launch_bounds__(kNeThreads) void k_noise_partial(const cf* __restrict__ Y, const cf* __restrict__ P,
+                                                              float2* __restrict__ part, ChestGeom g, int bw,
+                                                              long long batch) {
+  __shared__ float2 red[kNeThreads / 64];
+  const int nb = g.n_beams, nsc = g.n_sc, nue = g.n_ue, npil = g.n_pilot;
+  const int gl = threadIdx.x & (bw - 1);          // lane within the RE's group
+  const int b0 = gl * NBV;                         // first beam of this lane
+  const int per_it = kNeThreads / bw;              // pilot REs per block per iteration
+  const int n_re = npil * nsc;
+  const int stride = gridDim.x * per_it;
+  const int step = nue / npil;
+  for (long long bi = blockIdx.y; bi < batch; bi += gridDim.y) {
+    const cf* Yb = Y + bi * g.y_batch;
+    const cf* Pb = P + bi * g.p_batch;
+    float num = 0.f, den = 0.f;
+    for (int s = blockIdx.x * per_it + (int)(threadIdx.x / bw); s < n_re; s += stride) {
+      const int j = s / nsc, k = s - j * nsc;
+      const int l = pos_mod(k + j * step, nue);
+      const NeNeighbours n = ne_neighbours(k, l, nue, npil, nsc);
+      float hr[NBV], hi[NBV];
+#pragma unroll
+      for (int e = 0; e < NBV; ++e) hr[e] = hi[e] = 0.f;
+      const bool mine = b0 < nb;
+      const int bb = mine ? b0 : 0;  // lanes past the last beam read beam 0 and add nothing
+      float gain = 0.f;
+      if (n.mlo) {
+        const float q = add_mean<NBV, LS>(hr, hi, Yb, Pb, g, n.mlo, n.lo, n.wlo, bb);
+        const float c = n.wlo / (float)__popc(n.mlo);
+        gain += c * c * q;
+      }
+      if (n.mhi) {
+        const float q = add_mean<NBV, LS>(hr, hi, Yb, Pb, g, n.mhi, n.hi, n.whi, bb);
+        const float c = n.whi / (float)__popc(n.mhi);
+        gain += c * c * q;
+      }
+      const cf pv = Pb[(long long)j * nsc + k];
+      const float pp = pv.r * pv.r + pv.i * pv.i;
+      float vr[NBV], vi[NBV];
+      ls_value<NBV, LS>(vr, vi, Yb, g, pv, j, k, bb);
+      float e2 = 0.f;
+#pragma unroll
+      for (int e = 0; e < NBV; ++e) {
+        const float dr = vr[e] - hr[e], di = vi[e] - hi[e];
+        e2 += dr * dr + di * di;
+      }
+      num += mine ? pp * e2 : 0.f;
+      den += gl == 0 ? (float)nb * (1.f + pp * gain) : 0.f;
+    }
+    float2 v = wave_sum(make_float2(num, den));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float2 t = red[0];
+#pragma unroll
+      for (int w = 1; w < kNeThreads / 64; ++w) {
+        t.x += red[w].x;
+        t.y += red[w].y;
+      }
+      part[bi * kNeParts + blockIdx.x] = t;
+    }
+    __syncthreads();  // red is reused by the next batch item
+  }
+}
+
+// One wavefront per batch item: sigma2[item] = sum of its parts' |r|^2 / sum of N_B kappa.
+__global__ __launch_bounds__(256) void k_noise_final(const float2* __restrict__ part, float* __restrict__ sigma2,
+                                                      int n_parts, long long batch) {
+  const long long bi = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (bi >= batch) return;
+  const int lane = threadIdx.x & 63;
+  float2 v = lane < n_parts ? part[bi * kNeParts + lane] : make_float2(0.f, 0.f);
+  v = wave_sum(v);
+  if (lane == 0) sigma2[bi] = v.x / v.y;
+}
+
+template <int NBV, bool LS>
+void launch_partial(const cf* Y, const cf* P, float2* part, const ChestGeom& g, int bw, int n_parts, long long batch,
+                    hipStream_t s) {
+  const dim3 grid((unsigned)n_parts, (unsigned)(batch < 65535 ? batch : 65535));
+  hipLaunchKernelGGL((k_noise_partial<NBV, LS>), grid, dim3(kNeThreads), 0, s, Y, P, part, g, bw, batch);
+}
+
+// Slices per batch item: one per block-iteration's worth of pilot REs, at most kNeParts.
+int noise_parts(const ChestGeom& g) {
+  const int nbv = (g.n_beams % 2) == 0 ? 2 : 1;
+  int bw = 1;
+  while (bw * nbv < g.n_beams) bw *= 2;
+  const int per_it = kNeThreads / bw;
+  const int n_re = g.n_pilot * g.n_sc;
+  const int want = (n_re + per_it - 1) / per_it;
+  return want < 1 ? 1 : (want > kNeParts ? kNeParts : want);
+}
+
+}  // namespace
+
+hipError_t launch_noise_est(const cf* Y, const cf* pilots, bool ls, float2* part, float* sigma2, const ChestGeom& g,
+                            long long batch, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  const bool pair = (g.n_beams % 2) == 0;
+  int bw = 1;
+  while (bw * (pair ? 2 : 1) < g.n_beams) bw *= 2;
+  const int n_parts = noise_parts(g);
+  if (pair)
+    ls ? launch_partial<2, true>(Y, pilots, part, g, bw, n_parts, batch, s)
+       : launch_partial<2, false>(Y, pilots, part, g, bw, n_parts, batch, s);
+  else
+    ls ? launch_partial<1, true>(Y, pilots, part, g, bw, n_parts, batch, s)
+       : launch_partial<1, false>(Y, pilots, part, g, bw, n_parts, batch, s);
+  if (hipError_t e = hipGetLastError()) return e;
+  const long long blocks = (batch + 3) / 4;
+  hipLaunchKernelGGL(k_noise_final, dim3((unsigned)blocks), dim3(256), 0, s, part, sigma2, n_parts, batch);
+  return hipGetLastError();
+}
+
+}  // namespace pusch

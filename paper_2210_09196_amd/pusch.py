@@ -38,6 +38,8 @@ class SlotDesc(ctypes.Structure):
         ("sigma2", ctypes.c_float),
         ("W", ctypes.c_void_p),
         ("pilots", ctypes.c_void_p),
+        ("noise_est", ctypes.c_int),
+        ("sigma2_est", ctypes.c_void_p),
     ]
 
 
@@ -52,6 +54,8 @@ _SIG = {
     "pusch_fft": (_I, [_P, _P, _I, _I, _LL, _P]),
     "pusch_beamform": (_I, [_P, _P, _P, _I, _I, _I, _LL, _LL, _P]),
     "pusch_chest": (_I, [_P, _P, _P, _I, _I, _I, _I, _LL, _P]),
+    "pusch_noise_est_workspace_bytes": (ctypes.c_size_t, [_LL]),
+    "pusch_noise_est": (_I, [_P, _P, _P, _I, _I, _I, _I, _LL, _P, ctypes.c_size_t, _P]),
     "pusch_mmse_solve": (_I, [_P, _P, _F, _P, _I, _I, _I, _I, _LL, _P, _P]),
     "pusch_slot_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SlotDesc), _LL]),
     "pusch_slot": (_I, [ctypes.POINTER(SlotDesc), _LL, _P, _P, _P, _P, ctypes.c_size_t, _P]),
@@ -175,6 +179,27 @@ def chest(Yp: torch.Tensor, pilots: torch.Tensor, n_ue: int, out: torch.Tensor |
     return out
 
 
+def noise_est(Yp: torch.Tensor, pilots: torch.Tensor, n_ue: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Noise variance per batch item from the pilot symbols: Yp [batch, n_pilot, n_sc, n_beams],
+    pilots [batch, n_pilot, n_sc] -> sigma2 [batch] float32."""
+    _c64(Yp, "Yp")
+    _c64(pilots, "pilots")
+    batch, n_pilot, n_sc, n_beams = Yp.shape
+    if tuple(pilots.shape) != (batch, n_pilot, n_sc):
+        raise PuschError("noise_est: pilots must be [batch, n_pilot, n_sc]")
+    if out is None:
+        out = torch.empty(batch, dtype=torch.float32, device=Yp.device)
+    if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() < batch:
+        raise PuschError("noise_est: out must be a contiguous float32 tensor of batch elements")
+    if batch == 0:
+        return out
+    nbytes = int(lib().pusch_noise_est_workspace_bytes(batch))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=Yp.device)
+    _check(lib().pusch_noise_est(Yp.data_ptr(), pilots.data_ptr(), out.data_ptr(), n_beams, n_ue, n_sc, n_pilot, batch,
+                                 ws.data_ptr(), nbytes, _stream()), "pusch_noise_est")
+    return out
+
+
 def mmse_solve(H: torch.Tensor, Yd: torch.Tensor, sigma2: float, out: torch.Tensor | None = None,
                status: torch.Tensor | None | bool = True):
     """MMSE detection: H [batch, n_sc, n_ue, n_beams], Yd [batch, n_data, n_sc, n_beams]
@@ -204,10 +229,13 @@ class Slot:
 
     precision="mixed" uses pusch_slot_mixed (FP16 active-bin grids between
     OFDM demodulation and beamforming, beamforming on FP16 matrix cores with
-    FP32 accumulation, FP32 estimation and detection)."""
+    FP32 accumulation, FP32 estimation and detection).  sigma2=None estimates
+    every slot's noise variance from its pilot symbols; each call leaves the
+    estimates in self.sigma2_est ([n_slot] float32)."""
 
     def __init__(self, n_ant: int, n_fft: int, n_sc: int, n_symb: int, n_beams: int, n_ue: int, pilot_symb,
-                 sigma2: float, n_slot: int, W: torch.Tensor | None = None, device="cuda", precision: str = "fp32"):
+                 sigma2: float | None, n_slot: int, W: torch.Tensor | None = None, device="cuda",
+                 precision: str = "fp32"):
         if precision not in ("fp32", "mixed"):
             raise PuschError("precision is 'fp32' or 'mixed'")
         self.mixed = precision == "mixed"
@@ -220,7 +248,7 @@ class Slot:
         d.n_beams, d.n_ue, d.n_pilot = n_beams, n_ue, len(pilot_symb)
         for j, s in enumerate(pilot_symb):
             d.pilot_symb[j] = s
-        d.sigma2 = float(sigma2)
+        self.sigma2_est = _noise_fields(d, sigma2, n_slot, device)
         self.W = None if W is None else _c64(W, "W")
         d.W = _ptr(self.W)
         self.n_slot = n_slot
@@ -257,7 +285,18 @@ class Slot:
         return x_hat, status
 
 
-def _fill_desc(d: SlotDesc, n_ant, n_fft, n_sc, n_symb, n_beams, n_ue, pilot_symb, sigma2, W) -> None:
+def _noise_fields(d: SlotDesc, sigma2, n_slot: int, device) -> torch.Tensor | None:
+    """sigma2 None: estimate it per slot (noise_est) into a new [n_slot] float32 tensor, returned."""
+    if sigma2 is None:
+        est = torch.zeros(max(int(n_slot), 1), dtype=torch.float32, device=device)
+        d.sigma2, d.noise_est, d.sigma2_est = 0.0, 1, est.data_ptr()
+        return est
+    d.sigma2, d.noise_est, d.sigma2_est = float(sigma2), 0, None
+    return None
+
+
+def _fill_desc(d: SlotDesc, n_ant, n_fft, n_sc, n_symb, n_beams, n_ue, pilot_symb, sigma2, W, n_slot=1,
+               device="cuda") -> torch.Tensor | None:
     pilot_symb = list(pilot_symb)
     if not 1 <= len(pilot_symb) <= MAX_PILOTS:
         raise PuschError("1..4 pilot symbols")
@@ -265,15 +304,16 @@ def _fill_desc(d: SlotDesc, n_ant, n_fft, n_sc, n_symb, n_beams, n_ue, pilot_sym
     d.n_beams, d.n_ue, d.n_pilot = n_beams, n_ue, len(pilot_symb)
     for j, s in enumerate(pilot_symb):
         d.pilot_symb[j] = s
-    d.sigma2 = float(sigma2)
     d.W = _ptr(W)
+    return _noise_fields(d, sigma2, n_slot, device)
 
 
 class Cells:
     """Independent cells of different slot geometries, run by one pusch_cells call.
 
     Each cell is a dict with the slot geometry (n_ant, n_fft, n_sc, n_symb,
-    n_beams, n_ue, pilot_symb), sigma2, n_slot (>= 1) and optionally W.  The
+    n_beams, n_ue, pilot_symb), sigma2 (None: estimated per slot, left in
+    self.sigma2_est[c]), n_slot (>= 1) and optionally W.  The
     workspace is allocated once here; a call enqueues every cell on the
     library's side streams, forked from and joined back to the current torch
     stream, so it can be captured into a CUDA/HIP graph.
@@ -291,14 +331,16 @@ class Cells:
         self.n_slot = (_LL * n)()
         self.W = []
         self.geom = []
+        self.sigma2_est = []
         for c, g in enumerate(cells):
             if int(g["n_slot"]) < 1:
                 raise PuschError("every cell needs n_slot >= 1")
             W = g.get("W")
             W = None if W is None else _c64(W, "W")
             self.W.append(W)
-            _fill_desc(self.descs[c], g["n_ant"], g["n_fft"], g["n_sc"], g["n_symb"], g["n_beams"], g["n_ue"],
-                       g["pilot_symb"], g["sigma2"], W)
+            self.sigma2_est.append(
+                _fill_desc(self.descs[c], g["n_ant"], g["n_fft"], g["n_sc"], g["n_symb"], g["n_beams"], g["n_ue"],
+                           g["pilot_symb"], g["sigma2"], W, int(g["n_slot"]), device))
             self.n_slot[c] = int(g["n_slot"])
             self.geom.append(dict(g))
         nbytes = lib().pusch_cells_workspace_bytes(self.descs, n, self.n_slot, self.mixed)

@@ -23,7 +23,7 @@ def lib():
 
 def test_exports_every_declared_symbol(lib):
     names = pusch.header_symbols()
-    assert len(names) == 14
+    assert len(names) == 16
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(pusch._SIG)
@@ -100,22 +100,25 @@ def test_slot_workspace_bytes(lib):
     y = n * 14 * 3300 * 32 * 8
     h = n * 3300 * 16 * 32 * 8
     a = lambda v: (v + 255) // 256 * 256
+    # noise estimation scratch: 64 partial sums (8 B) and one estimate per slot
+    ne = a(n * 64 * 8 + n * 4)
     # 16 UEs: the channel is estimated inside the detection kernel, no stored
     # estimate; a table of interpolation taps instead (two 8-byte taps per
     # subcarrier and UE: no two pilot symbols share a UE's subcarriers)
-    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d), n) == a(xa) + a(y) + a(3300 * 16 * 2 * 8)
+    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d), n) == a(xa) + a(y) + a(3300 * 16 * 2 * 8) + ne
     d32 = _desc(n_ue=32, n_beams=64)
     xa, y, h = n * 14 * 64 * 3312 * 8, n * 14 * 3300 * 64 * 8, n * 3300 * 32 * 64 * 8
-    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d32), n) == a(xa) + a(y) + a(h)
+    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d32), n) == a(xa) + a(y) + a(h) + ne
     # odd number of beams: separate estimation kernel, stored estimate
     d31 = _desc(n_beams=31)
     xa, y, h = n * 14 * 64 * 3312 * 8, n * 14 * 3300 * 31 * 8, n * 3300 * 16 * 31 * 8
-    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d31), n) == a(xa) + a(y) + a(h)
+    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d31), n) == a(xa) + a(y) + a(h) + ne
     # one UE, two pilot symbols on the same subcarriers: each bracket end
     # averages them, 8 taps per subcarrier
     d1 = _desc(n_ue=1)
     y = n * 14 * 3300 * 32 * 8
-    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d1), n) == a(n * 14 * 64 * 3312 * 8) + a(y) + a(3300 * 8 * 8)
+    assert (lib.pusch_slot_workspace_bytes(ctypes.byref(d1), n) ==
+            a(n * 14 * 64 * 3312 * 8) + a(y) + a(3300 * 8 * 8) + ne)
     assert lib.pusch_slot_workspace_bytes(ctypes.byref(_desc(n_fft=1000)), n) == 0
     assert lib.pusch_slot_workspace_bytes(ctypes.byref(_desc(pilot_symb=(11, 2))), n) == 0
 
@@ -145,6 +148,45 @@ def test_slot_workspace_errors(lib):
     ws = ctypes.c_void_p(0x4000000000)
     assert lib.pusch_slot(ctypes.byref(d), 2, FAKE, FAKE2, None, ws, need - 1, None) == ENOMEM
     assert lib.pusch_slot(ctypes.byref(d), 2, FAKE, FAKE2, None, ctypes.c_void_p(0x4000000010), need, None) == EINVAL
+    assert lib.pusch_slot(ctypes.byref(d), 0, FAKE, FAKE2, None, ws, need, None) == 0
+
+
+def test_noise_est_validation(lib):
+    assert lib.pusch_noise_est_workspace_bytes(16) == 16 * 64 * 8  # 64 partial sums per item
+    assert lib.pusch_noise_est_workspace_bytes(-1) == 0
+    f = lib.pusch_noise_est
+    ws = ctypes.c_void_p(0x4000000000)
+    S = ctypes.c_void_p(0x70000000)
+    big = 1 << 30
+    assert f(None, FAKE2, S, 32, 16, 3300, 2, 1, ws, big, None) == EINVAL
+    assert f(FAKE, FAKE2, None, 32, 16, 3300, 2, 1, ws, big, None) == EINVAL
+    assert f(FAKE, FAKE2, S, 32, 16, 31, 2, 1, ws, big, None) == EINVAL  # a UE with one pilot position
+    assert f(FAKE, FAKE2, S, 32, 16, 3300, 5, 1, ws, big, None) == EINVAL  # too many pilot symbols
+    assert f(FAKE, FAKE2, S, 8, 16, 3300, 2, 1, ws, big, None) == EINVAL  # more UEs than beams
+    assert f(FAKE, FAKE2, S, 32, 16, 3300, 2, 2, ws, 2 * 64 * 8 - 1, None) == ENOMEM
+    assert f(FAKE, FAKE2, S, 32, 16, 3300, 2, 1, None, big, None) == EINVAL
+    assert f(FAKE, FAKE2, S, 32, 16, 3300, 2, 1, ctypes.c_void_p(0x4000000004), big, None) == EINVAL
+    assert f(FAKE, FAKE2, ctypes.c_void_p(0x20000), 32, 16, 3300, 2, 1, ws, big, None) == EINVAL  # inside Yp
+    assert f(FAKE, FAKE2, S, 32, 16, 3300, 2, 1, ctypes.c_void_p(0x90000100), big, None) == EINVAL  # ws on pilots
+    assert f(FAKE, FAKE2, S, 32, 16, 3300, 2, 0, None, 0, None) == 0  # empty batch
+
+
+def test_slot_noise_est_validation(lib):
+    ws = ctypes.c_void_p(0x4000000000)
+    # estimation needs two pilot positions per UE (n_sc >= 2 n_ue)
+    d = _desc(n_fft=64, n_sc=31, noise_est=1)
+    assert lib.pusch_slot(ctypes.byref(d), 1, FAKE, FAKE2, None, ws, 1 << 40, None) == EINVAL
+    # the given sigma2 is not used, so not checked, when it is estimated
+    d = _desc(sigma2=-1.0, noise_est=1)
+    need = lib.pusch_slot_workspace_bytes(ctypes.byref(d), 2)
+    assert need == lib.pusch_slot_workspace_bytes(ctypes.byref(_desc()), 2)
+    assert lib.pusch_slot(ctypes.byref(d), 0, FAKE, FAKE2, None, ws, need, None) == 0
+    # the estimates may not overlap the output, the input or the workspace
+    for where in (0x90000040, 0x10040, 0x4000000100):
+        d = _desc(noise_est=1, sigma2_est=where)
+        assert lib.pusch_slot(ctypes.byref(d), 2, FAKE, FAKE2, None, ws, need, None) == EINVAL, hex(where)
+    # ignored without noise_est
+    d = _desc(sigma2_est=0x90000040)
     assert lib.pusch_slot(ctypes.byref(d), 0, FAKE, FAKE2, None, ws, need, None) == 0
 
 
@@ -198,6 +240,11 @@ def test_cells_validation(lib):
     # one invalid cell rejects the whole call
     bad, nsb = _cell_arrays([small, _desc(sigma2=-1.0)], [1, 1])
     assert f(bad, 2, nsb, x, o, None, ws, 1 << 40, 0, None) == EINVAL
+    # a cell's noise estimates over another cell's output
+    est = _desc(n_ant=16, n_fft=1024, n_sc=825, n_beams=8, n_ue=4, pilot_symb=(2,), n_pilot=1, noise_est=1,
+                sigma2_est=0x98000000 + 64)
+    clash, nsc = _cell_arrays([est, small], [1, 1])
+    assert f(clash, 2, nsc, x, o, None, ws, need, 0, None) == EINVAL
     # two cells writing the same output
     same = (P * 2)(0x90000000, 0x90000000)
     assert f(descs, 2, ns, x, same, None, ws, need, 0, None) == EINVAL
@@ -217,7 +264,9 @@ def test_slot_mixed_workspace_and_validation(lib):
     # 64 exponent bytes per slot symbol, then as pusch_slot
     xa, ex = n * 14 * 64 * 3328 * 4, n * 14 * 64
     y = n * 14 * 3300 * 32 * 8
-    assert lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(d), n) == a(xa) + a(ex) + a(y) + a(3300 * 16 * 2 * 8)
+    ne = a(n * 64 * 8 + n * 4)
+    assert (lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(d), n) ==
+            a(xa) + a(ex) + a(y) + a(3300 * 16 * 2 * 8) + ne)
     many = _desc(n_ant=65, n_beams=32)
     assert lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(many), n) == 0  # FP16 path: up to 64 antennas
     ws = ctypes.c_void_p(0x4000000000)
