@@ -7,10 +7,13 @@ subcarriers, 14 OFDM symbols with pilots on symbols 2 and 11, 32 DFT beams,
 every antenna and symbol, beamforming, LS channel estimation and MMSE
 detection.  Inputs sit in HBM before the timed region starts.
 
-Prints ONE JSON line with slots/s, us/slot (p50/p99 over steps), the per-stage
-device time measured with HIP events recorded by the library on the launch
-stream during the timed steps, the roofline of the dominant kernel and the
-serial FP64 CPU oracle timed on a bounded sample of the same slots.
+Prints ONE JSON line with slots/s and us/slot (p50/p99 over steps, one event
+per step and nothing else recorded in the timed region), the per-stage device
+time measured with HIP events that the library records on the launch stream
+around every stage in a second pass over the same steps, the roofline of the
+dominant kernel, the serial FP64 CPU oracle timed on a bounded sample of the
+same slots, and the same batch through the mixed-precision chain and through
+the chain with the noise variance estimated from the pilots.
 """
 from __future__ import annotations
 
@@ -80,7 +83,8 @@ def _traffic(stage: str) -> float | None:
 
 
 def cpu_baseline(batch: dict, seconds: float) -> dict:
-    """The FP64 oracle, serial (one BLAS thread), on as many of the slots as fit in `seconds`."""
+    """The FP64 oracle, serial (one BLAS thread), over the batch's slots in turn (cycling) until
+    `seconds` have passed."""
     from threadpoolctl import threadpool_limits
 
     from oracle import pusch_oracle
@@ -89,15 +93,14 @@ def cpu_baseline(batch: dict, seconds: float) -> dict:
     cfg = synth.CFG2
     done, t0 = 0, time.perf_counter()
     with threadpool_limits(limits=1):
-        while done < N_SLOT:
-            pusch_oracle.receive_slot(batch["x_td"][done], batch["pilots"][done], cfg.pilot_symb, cfg.n_ue, cfg.n_sc,
+        while time.perf_counter() - t0 < seconds:
+            i = done % N_SLOT
+            pusch_oracle.receive_slot(batch["x_td"][i], batch["pilots"][i], cfg.pilot_symb, cfg.n_ue, cfg.n_sc,
                                       batch["sigma2"], n_beams=cfg.n_beams)
             done += 1
-            if time.perf_counter() - t0 >= seconds:
-                break
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "slots/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} slot(s) of the same workload (seeds {SEEDS[0]}..{SEEDS[0] + done - 1}), "
+            "sample": f"{done} slot evaluations of the same workload (the batch's {N_SLOT} slots in turn), "
                       f"FP64 NumPy oracle, one thread, {dt:.1f} s"}
 
 
@@ -116,21 +119,20 @@ def calibrate_copy() -> int:
     return 0
 
 
-def bench_mixed(args, cfg, batch, x, p, x_hat32, nd: int, ms32: float) -> dict:
-    """The same batch through pusch_slot_mixed (FP16 active-bin grids between
-    OFDM demodulation and beamforming, FP16-MFMA beamforming): time per step with the
-    same protocol, and the EVM of both chains' detected symbols against the
-    transmitted ones on the distinct slots."""
+def _evm_db(xh, xt) -> float:  # 10 log10(sum |x_hat - x|^2 / sum |x|^2)
+    return float(10.0 * np.log10(np.sum(np.abs(xh - xt) ** 2) / np.sum(np.abs(xt) ** 2)))
+
+
+def _run_variant(args, cfg, batch, x, p, x_hat32, precision: str, sigma2):
+    """Time the 16-slot launch of one chain variant with the same protocol as
+    the headline run; returns (ms per step, stage us per launch, x_hat, status, slot)."""
     import torch
 
     from paper_2210_09196_amd import pusch
 
-    def evm_db(xh, xt):  # 10 log10(sum |x_hat - x|^2 / sum |x|^2)
-        return float(10.0 * np.log10(np.sum(np.abs(xh - xt) ** 2) / np.sum(np.abs(xt) ** 2)))
-
     dev = x.device
     slot = pusch.Slot(cfg.n_ant, cfg.n_fft, cfg.n_sc, cfg.n_symb, cfg.n_beams, cfg.n_ue, cfg.pilot_symb,
-                      batch["sigma2"], N_SLOT, device=dev, precision="mixed")
+                      sigma2, N_SLOT, device=dev, precision=precision)
     xh = torch.empty_like(x_hat32)
     st = torch.empty(N_SLOT, cfg.n_sc, dtype=torch.int32, device=dev)
     for _ in range(args.warmup):
@@ -138,24 +140,52 @@ def bench_mixed(args, cfg, batch, x, p, x_hat32, nd: int, ms32: float) -> dict:
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    pusch.profile_begin(args.steps)
     e0.record(stream)
     for _ in range(args.steps):
         slot(x, p, xh, st)
     e1.record(stream)
     torch.cuda.synchronize()
-    calls, stage_ms = pusch.profile_end()
     ms = e0.elapsed_time(e1) / args.steps
+    pusch.profile_begin(args.steps)  # stage times in a second pass, as for the headline
+    for _ in range(args.steps):
+        slot(x, p, xh, st)
+    torch.cuda.synchronize()
+    calls, stage_ms = pusch.profile_end()
+    return ms, {k: round(v / calls * 1e3, 2) for k, v in stage_ms.items()}, xh, st, slot
+
+
+def bench_mixed(args, cfg, batch, x, p, x_hat32, nd: int, ms32: float) -> dict:
+    """The same batch through pusch_slot_mixed (FP16 active-bin grids between
+    OFDM demodulation and beamforming, FP16-MFMA beamforming): time per step with the
+    same protocol, and the EVM of both chains' detected symbols against the
+    transmitted ones on the distinct slots."""
+    ms, stage_us, xh, st, _ = _run_variant(args, cfg, batch, x, p, x_hat32, "mixed", batch["sigma2"])
     data = batch["data"][:nd].transpose(0, 1, 3, 2)  # x_hat layout [slot][D][K][L]
-    e32 = evm_db(x_hat32[:nd].cpu().numpy(), data)
-    e16 = evm_db(xh[:nd].cpu().numpy(), data)
+    e32 = _evm_db(x_hat32[:nd].cpu().numpy(), data)
+    e16 = _evm_db(xh[:nd].cpu().numpy(), data)
     return {"precision": "FP16 active-bin grids between FFT and beamforming (power-of-two row scale), "
                          "beamforming on FP16 MFMA with FP32 accumulation, FP32 estimation and detection",
             "value": round(N_SLOT / (ms / 1e3), 1), "unit": "slots/s", "us_per_slot": round(1e3 * ms / N_SLOT, 3),
-            "speedup_vs_fp32": round(ms32 / ms, 3),
-            "stage_us_per_launch": {k: round(v / calls * 1e3, 2) for k, v in stage_ms.items()},
+            "speedup_vs_fp32": round(ms32 / ms, 3), "stage_us_per_launch": stage_us,
             "evm_db_fp32": round(e32, 3), "evm_db_mixed": round(e16, 3), "evm_gap_db": round(e16 - e32, 4),
             "evm_slots": nd, "status_flags": int(st.sum().item())}
+
+
+def bench_noise_est(args, cfg, batch, x, p, x_hat32, nd: int, ms32: float) -> dict:
+    """The FP32 chain with the noise variance estimated from the pilot symbols
+    of every slot (the chain's NE step) instead of given: time per step, the
+    estimation kernels' share (the chest stage, empty otherwise in the fused
+    slot), the estimates and the EVM next to the chain given the true variance."""
+    ms, stage_us, xh, st, slot = _run_variant(args, cfg, batch, x, p, x_hat32, "fp32", None)
+    data = batch["data"][:nd].transpose(0, 1, 3, 2)
+    est = slot.sigma2_est[:nd].cpu().numpy()
+    return {"sigma2": batch["sigma2"], "sigma2_est": [round(float(v), 5) for v in est],
+            "value": round(N_SLOT / (ms / 1e3), 1), "unit": "slots/s", "us_per_slot": round(1e3 * ms / N_SLOT, 3),
+            "time_vs_given_sigma2": round(ms / ms32, 4), "ne_us_per_launch": stage_us["chest"],
+            "stage_us_per_launch": stage_us,
+            "evm_db_given": round(_evm_db(x_hat32[:nd].cpu().numpy(), data), 3),
+            "evm_db_estimated": round(_evm_db(xh[:nd].cpu().numpy(), data), 3),
+            "status_flags": int(st.sum().item())}
 
 
 def cells_geometries(n_cells: int, seed: int = 4000) -> list[dict]:
@@ -310,9 +340,9 @@ def main() -> int:
         slot(x, p, x_hat, status)
     torch.cuda.synchronize()
 
+    # headline: the chain alone, one event per step and nothing recorded in between
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    pusch.profile_begin(args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev[0].record(stream)
@@ -321,13 +351,23 @@ def main() -> int:
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    calls, stage_ms = pusch.profile_end()
     step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
     total_ms = ev[0].elapsed_time(ev[-1])
     ms_per_step = total_ms / args.steps
     bad = int(status.sum().item())
     print(f"[bench] {args.steps} steps in {total_ms:.2f} ms (wall {wall * 1e3:.1f} ms), status flags {bad}",
           file=sys.stderr, flush=True)
+    # stage times: the same steps again with the library's events around every stage launch
+    # (they add a few microseconds per stage boundary, so they stay out of the headline)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pusch.profile_begin(args.steps)
+    e0.record(stream)
+    for _ in range(args.steps):
+        slot(x, p, x_hat, status)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    calls, stage_ms = pusch.profile_end()
+    ms_profiled = e0.elapsed_time(e1) / args.steps
 
     us_slot = 1e3 * step_ms / N_SLOT
     stages = {}
@@ -348,6 +388,7 @@ def main() -> int:
                 "us_per_launch": stages[dom]["us_per_launch"]}
     chain_bytes = sum(STAGE_BYTES.values()) * N_SLOT
     mixed = bench_mixed(args, cfg, batch, x, p, x_hat, nd, ms_per_step)
+    noise = bench_noise_est(args, cfg, batch, x, p, x_hat, nd, ms_per_step)
     out = {
         "metric": "PUSCH slots/s & \u00b5s/slot, 64ant\u00d74096-FFT; FP32 vs mixed+batched, EVM gap \u22640.1dB",
         "value": round(N_SLOT / (ms_per_step / 1e3), 1),
@@ -359,6 +400,7 @@ def main() -> int:
         "us_per_slot": round(1e3 * ms_per_step / N_SLOT, 3),
         "us_per_slot_p50": round(float(np.percentile(us_slot, 50)), 3),
         "us_per_slot_p99": round(float(np.percentile(us_slot, 99)), 3),
+        "ms_per_step_with_stage_events": round(ms_profiled, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -375,6 +417,7 @@ def main() -> int:
         "cpu_baseline": None,
         "status_flags": bad,
         "mixed": mixed,
+        "noise_est": noise,
     }
     if not args.no_cpu_baseline:
         print(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)", file=sys.stderr, flush=True)

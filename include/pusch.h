@@ -21,7 +21,11 @@
  *             and status arrays are valid once the stream has been
  *             synchronised.  No call synchronises the device or allocates in
  *             steady state.  The first call on a device builds small
- *             immutable tables (FFT twiddles, DFT beamformers) once.
+ *             immutable tables (FFT twiddles, DFT beamformers) once, and the
+ *             first call with a slot geometry builds that geometry's
+ *             estimation tables (channel interpolation taps, noise-estimation
+ *             neighbours) once, on a stream of the library's own that it
+ *             waits for (never on the caller's stream).
  * Errors      arguments are checked on the host before any device work; a
  *             rejected call returns a negative code and enqueues nothing.
  *             Launch failures return PUSCH_EHIP.  Numerical failure of one
@@ -139,8 +143,8 @@ int pusch_chest(const pusch_c32* Yp, const pusch_c32* pilots, pusch_c32* H, int 
  *   sigma2 [batch] FP32 estimates (device).
  *   ws     device scratch of at least pusch_noise_est_workspace_bytes(batch)
  *          bytes, 8-byte aligned; its contents are not needed afterwards.
- *   n_sc >= 2 n_ue (every UE has two pilot positions), other limits as
- *   pusch_chest.  sigma2, ws, Yp and pilots must not overlap.
+ *   2 n_ue <= n_sc <= 4096 (every UE has two pilot positions), other limits
+ *   as pusch_chest.  sigma2, ws, Yp and pilots must not overlap.
  */
 size_t pusch_noise_est_workspace_bytes(long long batch);
 int pusch_noise_est(const pusch_c32* Yp, const pusch_c32* pilots, float* sigma2, int n_beams, int n_ue, int n_sc,
@@ -230,8 +234,8 @@ int pusch_slot_mixed(const pusch_slot_desc* d, long long n_slot, const pusch_c32
  * on PUSCH_CELL_STREAMS library-owned side streams of default priority, cell
  * c on side stream c mod PUSCH_CELL_STREAMS in order, forked from and joined
  * back to `stream` with events, so the whole call is ordered on `stream` and
- * can be captured into a HIP graph (after one uncaptured call on the device,
- * or pusch_init, has built the device tables).
+ * can be captured into a HIP graph (after one uncaptured call with the same
+ * cells has built the device tables).
  *   ws     device workspace of at least pusch_cells_workspace_bytes bytes,
  *          256-byte aligned: one slice per side stream used, each as large
  *          as the largest cell's pusch_slot (or pusch_slot_mixed) workspace.

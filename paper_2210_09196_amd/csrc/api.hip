@@ -19,6 +19,9 @@ namespace {
 
 constexpr int kMaxDevices = 64;
 constexpr long long kMaxAnt = 1024;
+constexpr int kMaxNeSc = 4096;  // noise estimation: subcarrier positions packed in 12 bits
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 constexpr int kSideStreams = PUSCH_CELL_STREAMS;
 
@@ -34,6 +37,10 @@ struct DeviceTables {
   hipStream_t side[kSideStreams] = {};
   hipEvent_t fork = nullptr, join[kSideStreams] = {};
   std::mutex cells_mu;
+  // per-geometry tables (interpolation taps of the fused detection,
+  // noise-estimation neighbours), built on the library's own stream
+  hipStream_t build = nullptr;
+  std::map<std::vector<long long>, void*> geom;
 };
 DeviceTables g_dev[kMaxDevices];
 
@@ -60,6 +67,7 @@ int device_tables(DeviceTables** out) {
       if (hipStreamCreateWithFlags(&t.side[i], hipStreamNonBlocking) != hipSuccess ||
           hipEventCreateWithFlags(&t.join[i], hipEventDisableTiming) != hipSuccess)
         return;
+    if (hipStreamCreateWithFlags(&t.build, hipStreamNonBlocking) != hipSuccess) return;
     t.status = PUSCH_OK;
   });
   *out = &t;
@@ -92,6 +100,40 @@ int dft_beamformer(DeviceTables* t, int n_beams, int n_ant, const cf** out) {
   }
   t->dft_w[key] = static_cast<cf*>(d);
   *out = static_cast<cf*>(d);
+  return PUSCH_OK;
+}
+
+// Tables that depend on a slot geometry only, built once per geometry by
+// their kernels on the library's stream (waited for there, so the caller's
+// stream never waits on it) and kept until the process ends.
+enum GeomTable { kCombTaps = 0, kNoiseTable = 1 };
+
+int geometry_table(DeviceTables* t, GeomTable kind, const pusch::ChestGeom& g, int n_tap, const void** out) {
+  std::vector<long long> key = {kind, g.n_sc, g.n_ue, g.n_pilot};
+  if (kind == kCombTaps) {
+    key.push_back(g.n_beams);
+    key.push_back(g.y_sym);
+    key.push_back(n_tap);
+    for (int j = 0; j < g.n_pilot; ++j) key.push_back(g.pilot_sym[j]);
+  }
+  std::lock_guard<std::mutex> lock(t->mu);
+  auto it = t->geom.find(key);
+  if (it != t->geom.end()) {
+    *out = it->second;
+    return PUSCH_OK;
+  }
+  const size_t bytes = kind == kCombTaps ? (size_t)g.n_sc * g.n_ue * n_tap * sizeof(int2)
+                                         : pusch::noise_table_bytes(g.n_pilot, g.n_sc);
+  void* d = nullptr;
+  if (hipMalloc(&d, bytes) != hipSuccess) return PUSCH_ENOMEM;
+  const hipError_t e = kind == kCombTaps ? pusch::launch_comb_taps(static_cast<int2*>(d), g, n_tap, t->build)
+                                         : pusch::launch_noise_table(static_cast<int4*>(d), g, t->build);
+  if (e != hipSuccess || hipStreamSynchronize(t->build) != hipSuccess) {
+    (void)hipFree(d);
+    return PUSCH_EHIP;
+  }
+  t->geom[key] = d;
+  *out = d;
   return PUSCH_OK;
 }
 
@@ -205,7 +247,7 @@ int pusch_noise_est(const pusch_c32* Yp, const pusch_c32* pilots, float* sigma2,
   if (!Yp || !pilots || !sigma2 || batch < 0) return PUSCH_EINVAL;
   if (n_pilot < 1 || n_pilot > PUSCH_MAX_PILOTS) return PUSCH_EINVAL;
   if (n_beams < 1 || n_beams > PUSCH_MAX_BEAMS) return PUSCH_EINVAL;
-  if (n_ue < 1 || n_ue > PUSCH_MAX_UES || n_ue > n_beams || n_sc < 2 * n_ue) return PUSCH_EINVAL;
+  if (n_ue < 1 || n_ue > PUSCH_MAX_UES || n_ue > n_beams || n_sc < 2 * n_ue || n_sc > kMaxNeSc) return PUSCH_EINVAL;
   if (batch == 0) return PUSCH_OK;
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 7)) return PUSCH_EINVAL;
   const long long need = (long long)pusch_noise_est_workspace_bytes(batch);
@@ -223,9 +265,13 @@ int pusch_noise_est(const pusch_c32* Yp, const pusch_c32* pilots, float* sigma2,
   g.y_sym = (long long)n_sc * n_beams;
   for (int j = 0; j < n_pilot; ++j) g.pilot_sym[j] = j;
   g.p_batch = (long long)n_pilot * n_sc;
+  DeviceTables* t = nullptr;
+  if (int rc = device_tables(&t)) return rc;
+  const void* tab = nullptr;
+  if (int rc = geometry_table(t, kNoiseTable, g, 0, &tab)) return rc;
   return hip_status(pusch::launch_noise_est(reinterpret_cast<const cf*>(Yp), reinterpret_cast<const cf*>(pilots),
-                                            false, static_cast<float2*>(ws), sigma2, g, batch,
-                                            static_cast<hipStream_t>(stream)));
+                                            false, static_cast<const int4*>(tab), static_cast<float2*>(ws), sigma2,
+                                            g, batch, static_cast<hipStream_t>(stream)));
 }
 
 int pusch_mmse_solve(const pusch_c32* H, const pusch_c32* Yd, float sigma2, pusch_c32* Xhat, int n_beams, int n_ue,
@@ -271,10 +317,8 @@ int pusch_mmse_solve(const pusch_c32* H, const pusch_c32* Yd, float sigma2, pusc
 namespace {
 
 struct SlotLayout {
-  size_t off_xa, off_ex, off_y, off_h, off_comb, off_ne, total;
+  size_t off_xa, off_ex, off_y, off_h, off_ne, total;
 };
-
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Geometry only (what the workspace size depends on).
 int check_geom(const pusch_slot_desc* d) {
@@ -336,9 +380,7 @@ SlotLayout slot_layout(const pusch_slot_desc* d, long long n_slot, bool mixed = 
   // when the detection kernel estimates the channel itself (up to 16 UEs, an
   // even number of beams) no stored estimate is needed
   const bool fused = pusch::mmse_fusable(d->n_ue, d->n_beams, (long long)d->n_symb * K * B);
-  lay.off_comb = lay.off_h + (fused ? 0 : align256(n * K * L * B * 8));
-  // channel interpolation taps (fused path), one table for all slots
-  lay.off_ne = lay.off_comb + (fused ? align256(K * L * pusch::comb_taps(d->n_ue, d->n_pilot) * 8) : 0);
+  lay.off_ne = lay.off_h + (fused ? 0 : align256(n * K * L * B * 8));
   lay.total = lay.off_ne + align256(ne_part_bytes(n_slot) + n * sizeof(float));
   return lay;
 }
@@ -392,6 +434,26 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   cf* Xa = reinterpret_cast<cf*>(base + lay.off_xa);
   cf* Y = reinterpret_cast<cf*>(base + lay.off_y);
   cf* H = reinterpret_cast<cf*>(base + lay.off_h);
+  // estimation geometry, and the geometry's cached tables (built before
+  // anything is enqueued on s)
+  const bool fused = pusch::mmse_fusable(L, B, (long long)S * K * B);
+  pusch::ChestGeom cg{};
+  cg.n_beams = B;
+  cg.n_ue = L;
+  cg.n_sc = K;
+  cg.n_pilot = P;
+  cg.y_batch = (long long)S * K * B;
+  cg.y_sym = (long long)K * B;
+  for (int j = 0; j < P; ++j) cg.pilot_sym[j] = d->pilot_symb[j];
+  cg.p_batch = (long long)P * K;
+  cg.h_batch = (long long)K * L * B;
+  const int n_tap = pusch::comb_taps(L, P);
+  const void* taps = nullptr;
+  const void* ne_tab = nullptr;
+  if (fused)
+    if (int rc = geometry_table(t, kCombTaps, cg, n_tap, &taps)) return rc;
+  if (d->noise_est)
+    if (int rc = geometry_table(t, kNoiseTable, cg, 0, &ne_tab)) return rc;
 
   hipEvent_t* ev = nullptr;
   {
@@ -411,7 +473,6 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   // beamforming of every symbol, RE-major output; when the detection
   // kernel estimates the channel itself, the pilot symbols leave this stage
   // already divided by their pilots (the LS division of the channel estimate)
-  const bool fused = pusch::mmse_fusable(L, B, (long long)S * K * B);
   pusch::PilotScale psc{};
   if (fused) {
     psc.pilots = reinterpret_cast<const cf*>(d->pilots);
@@ -426,16 +487,6 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
     return PUSCH_EHIP;
   // LS channel estimate from the pilot symbols
   if (!mark(2)) return PUSCH_EHIP;
-  pusch::ChestGeom cg{};
-  cg.n_beams = B;
-  cg.n_ue = L;
-  cg.n_sc = K;
-  cg.n_pilot = P;
-  cg.y_batch = (long long)S * K * B;
-  cg.y_sym = (long long)K * B;
-  for (int j = 0; j < P; ++j) cg.pilot_sym[j] = d->pilot_symb[j];
-  cg.p_batch = (long long)P * K;
-  cg.h_batch = (long long)K * L * B;
   if (!fused && pusch::launch_chest(Y, reinterpret_cast<const cf*>(d->pilots), H, cg, n_slot, s) != hipSuccess)
     return PUSCH_EHIP;
   // noise variance of every slot from its pilot symbols (which hold LS
@@ -444,8 +495,8 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   if (d->noise_est) {
     float2* part = reinterpret_cast<float2*>(base + lay.off_ne);
     s2 = d->sigma2_est ? d->sigma2_est : reinterpret_cast<float*>(base + lay.off_ne + ne_part_bytes(n_slot));
-    if (pusch::launch_noise_est(Y, reinterpret_cast<const cf*>(d->pilots), fused, part, s2, cg, n_slot, s) !=
-        hipSuccess)
+    if (pusch::launch_noise_est(Y, reinterpret_cast<const cf*>(d->pilots), fused, static_cast<const int4*>(ne_tab),
+                                part, s2, cg, n_slot, s) != hipSuccess)
       return PUSCH_EHIP;
   }
   // MMSE detection: Gram, Cholesky, matched filter and substitutions for the data
@@ -466,11 +517,9 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   for (int j = 0; j < P; ++j) mg.skip[j] = d->pilot_symb[j];
   mg.x_batch = (long long)D * K * L;
   mg.st_batch = K;
-  int2* taps = reinterpret_cast<int2*>(base + lay.off_comb);
-  const int n_tap = pusch::comb_taps(L, P);
-  if (fused && pusch::launch_comb_taps(taps, cg, n_tap, s) != hipSuccess) return PUSCH_EHIP;
   const hipError_t me =
-      fused ? pusch::launch_mmse_fused(Y, taps, n_tap, cg, reinterpret_cast<cf*>(x_hat), status, mg, n_slot, s)
+      fused ? pusch::launch_mmse_fused(Y, static_cast<const int2*>(taps), n_tap, cg, reinterpret_cast<cf*>(x_hat),
+                                       status, mg, n_slot, s)
             : pusch::launch_mmse(H, Y, reinterpret_cast<cf*>(x_hat), status, mg, n_slot, s);
   if (me != hipSuccess) return PUSCH_EHIP;
   if (!mark(4)) return PUSCH_EHIP;

@@ -84,8 +84,8 @@ hipError_t launch_chest(const cf* Y, const cf* pilots, cf* H, const ChestGeom& g
 // of (k, l), LS being one batch item of the RE-major grids that hold per-RE
 // LS values, off_t an element offset into it (pilot grid of the pilot symbol
 // plus position * n_beams).  tab[(k * n_ue + l) * n_tap + t] = {off_t, bits
-// of w_t}; unused taps repeat the first offset with weight 0.  The same for
-// every slot of a geometry.
+// of w_t}; unused taps repeat the first offset with weight 0.  Depends on the
+// geometry only (n_sc, n_ue, n_pilot, n_beams, the pilot grid offsets).
 int comb_taps(int n_ue, int n_pilot);  // taps per (k, l) the geometry needs: 2 or 8
 hipError_t launch_comb_taps(int2* tab, const ChestGeom& g, int n_tap, hipStream_t s);
 
@@ -95,11 +95,16 @@ hipError_t launch_comb_taps(int2* tab, const ChestGeom& g, int n_tap, hipStream_
 // prediction of its UE's channel interpolated from the UE's other pilot
 // positions, normalised by the noise gain of that prediction.  ls: the pilot
 // grids already hold LS values y*conj(p)/|p|^2 (PilotScale epilogue) instead
-// of received values.  part: kNeParts float2 per batch item (scratch);
-// sigma2: [batch].  Requires n_sc >= 2 * n_ue.
-constexpr int kNeParts = 64;
-hipError_t launch_noise_est(const cf* Y, const cf* pilots, bool ls, float2* part, float* sigma2, const ChestGeom& g,
-                            long long batch, hipStream_t s);
+// of received values.  tab: the geometry's neighbour table from
+// launch_noise_table (noise_table_bytes(n_pilot, n_sc) bytes, 16-byte
+// aligned; depends on n_sc, n_ue and n_pilot only); part: kNeParts float2 per
+// batch item (scratch); sigma2: [batch].  Requires n_sc >= 2 * n_ue and
+// n_sc <= 4096.
+constexpr int kNeParts = 256;
+size_t noise_table_bytes(int n_pilot, int n_sc);
+hipError_t launch_noise_table(int4* tab, const ChestGeom& g, hipStream_t s);
+hipError_t launch_noise_est(const cf* Y, const cf* pilots, bool ls, const int4* tab, float2* part, float* sigma2,
+                            const ChestGeom& g, long long batch, hipStream_t s);
 
 // ---------------------------------------------------------------- MMSE detection
 struct MmseGeom {

@@ -12,15 +12,15 @@
 // and the estimate is sum |r|^2 / (N_B sum kappa) over the pilot REs of a
 // batch item.  Since y = p * LS(y), |r|^2 = |p|^2 |LS(y) - h|^2.
 //
-// Two launches: k_noise_partial sums |r|^2 and N_B kappa over kNeParts fixed
-// slices of an item's pilot REs; k_noise_final adds an item's slices and
-// divides.  Every sum runs in a fixed order (no atomics), so the result does
-// not depend on timing.
+// k_noise_table finds every pilot RE's neighbours and weights (they depend
+// on the geometry only: closed form per pilot symbol, the comb of residue
+// classes mod n_ue), once per geometry.  Per call, k_noise_partial sums
+// |r|^2 and N_B kappa over kNeParts fixed slices of an item's pilot REs and
+// k_noise_final adds an item's slices and divides.  Every sum runs in a
+// fixed order (no atomics), so the result does not depend on timing.
 //
 // Layout: BW lanes (a power of two) share one pilot RE, each taking NBV
-// consecutive beams of its RE-major row, so a group reads whole rows; the
-// neighbour search is closed-form per pilot symbol (the comb of residue
-// classes mod n_ue).
+// consecutive beams of its RE-major row, so a group reads whole rows.
 #include "comb_ls.h"
 #include "kernels.h"
 
@@ -125,41 +125,58 @@ __device__ __forceinline__ float2 wave_sum(float2 v) {
   return v;
 }
 
+// One table entry per pilot RE s = j * n_sc + k: {lo | hi << 12 | mlo << 24 |
+// mhi << 28, bits of wlo, bits of whi, k | j << 16}; a mask of 0 marks a
+// missing side (positions < 4096).
+__global__ __launch_bounds__(256) void k_noise_table(int4* __restrict__ tab, ChestGeom g) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.n_pilot * g.n_sc) return;
+  const int j = s / g.n_sc, k = s - j * g.n_sc;
+  const int l = pos_mod(k + j * (g.n_ue / g.n_pilot), g.n_ue);
+  const NeNeighbours n = ne_neighbours(k, l, g.n_ue, g.n_pilot, g.n_sc);
+  const int lo = n.mlo ? n.lo : 0, hi = n.mhi ? n.hi : 0;
+  tab[s] = make_int4(lo | hi << 12 | (int)(n.mlo << 24) | (int)(n.mhi << 28), __float_as_int(n.wlo),
+                     __float_as_int(n.whi), k | j << 16);
+}
+
 // grid: (n_parts, min(batch, 65535)); part[item * kNeParts + blockIdx.x] = (sum |r|^2, sum N_B kappa)
 template <int NBV, bool LS>
 __global__ __launch_bounds__(kNeThreads) void k_noise_partial(const cf* __restrict__ Y, const cf* __restrict__ P,
+                                                              const int4* __restrict__ tab,
                                                               float2* __restrict__ part, ChestGeom g, int bw,
                                                               long long batch) {
   __shared__ float2 red[kNeThreads / 64];
-  const int nb = g.n_beams, nsc = g.n_sc, nue = g.n_ue, npil = g.n_pilot;
+  const int nb = g.n_beams, nsc = g.n_sc;
   const int gl = threadIdx.x & (bw - 1);          // lane within the RE's group
   const int b0 = gl * NBV;                         // first beam of this lane
+  const bool mine = b0 < nb;
+  const int bb = mine ? b0 : 0;                    // lanes past the last beam read beam 0 and add nothing
   const int per_it = kNeThreads / bw;              // pilot REs per block per iteration
-  const int n_re = npil * nsc;
+  const int n_re = g.n_pilot * nsc;
   const int stride = gridDim.x * per_it;
-  const int step = nue / npil;
   for (long long bi = blockIdx.y; bi < batch; bi += gridDim.y) {
     const cf* Yb = Y + bi * g.y_batch;
     const cf* Pb = P + bi * g.p_batch;
     float num = 0.f, den = 0.f;
     for (int s = blockIdx.x * per_it + (int)(threadIdx.x / bw); s < n_re; s += stride) {
-      const int j = s / nsc, k = s - j * nsc;
-      const int l = pos_mod(k + j * step, nue);
-      const NeNeighbours n = ne_neighbours(k, l, nue, npil, nsc);
-      float hr[NBV], hi[NBV];
+      const int4 t = tab[s];
+      const unsigned mlo = ((unsigned)t.x >> 24) & 15u, mhi = (unsigned)t.x >> 28;
+      const int lo = t.x & 4095, hi = (t.x >> 12) & 4095;
+      const int k = t.w & 0xffff, j = t.w >> 16;
+      float hr[NBV], hi_[NBV];
 #pragma unroll
-      for (int e = 0; e < NBV; ++e) hr[e] = hi[e] = 0.f;
-      const bool mine = b0 < nb;
-      const int bb = mine ? b0 : 0;  // lanes past the last beam read beam 0 and add nothing
+      for (int e = 0; e < NBV; ++e) hr[e] = hi_[e] = 0.f;
       float gain = 0.f;
-      if (n.mlo) {
-        const float q = add_mean<NBV, LS>(hr, hi, Yb, Pb, g, n.mlo, n.lo, n.wlo, bb);
-        const float c = n.wlo / (float)__popc(n.mlo);
+      if (mlo) {
+        const float wlo = __int_as_float(t.y);
+        const float q = add_mean<NBV, LS>(hr, hi_, Yb, Pb, g, mlo, lo, wlo, bb);
+        const float c = wlo / (float)__popc(mlo);
         gain += c * c * q;
       }
-      if (n.mhi) {
-        const float q = add_mean<NBV, LS>(hr, hi, Yb, Pb, g, n.mhi, n.hi, n.whi, bb);
-        const float c = n.whi / (float)__popc(n.mhi);
+      if (mhi) {
+        const float whi = __int_as_float(t.z);
+        const float q = add_mean<NBV, LS>(hr, hi_, Yb, Pb, g, mhi, hi, whi, bb);
+        const float c = whi / (float)__popc(mhi);
         gain += c * c * q;
       }
       const cf pv = Pb[(long long)j * nsc + k];
@@ -169,7 +186,7 @@ __global__ __launch_bounds__(kNeThreads) void k_noise_partial(const cf* __restri
       float e2 = 0.f;
 #pragma unroll
       for (int e = 0; e < NBV; ++e) {
-        const float dr = vr[e] - hr[e], di = vi[e] - hi[e];
+        const float dr = vr[e] - hr[e], di = vi[e] - hi_[e];
         e2 += dr * dr + di * di;
       }
       num += mine ? pp * e2 : 0.f;
@@ -191,50 +208,78 @@ __global__ __launch_bounds__(kNeThreads) void k_noise_partial(const cf* __restri
   }
 }
 
-// One wavefront per batch item: sigma2[item] = sum of its parts' |r|^2 / sum of N_B kappa.
+// One wavefront per batch item: sigma2[item] = sum of its parts' |r|^2 / sum of N_B kappa
+// (lane i adds parts i, i + 64, ... in order, then a fixed butterfly).
 __global__ __launch_bounds__(256) void k_noise_final(const float2* __restrict__ part, float* __restrict__ sigma2,
                                                       int n_parts, long long batch) {
   const long long bi = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (bi >= batch) return;
   const int lane = threadIdx.x & 63;
-  float2 v = lane < n_parts ? part[bi * kNeParts + lane] : make_float2(0.f, 0.f);
+  float2 v = make_float2(0.f, 0.f);
+  for (int i = lane; i < n_parts; i += 64) {
+    const float2 w = part[bi * kNeParts + i];
+    v.x += w.x;
+    v.y += w.y;
+  }
   v = wave_sum(v);
   if (lane == 0) sigma2[bi] = v.x / v.y;
 }
 
+// Beams per lane and lanes per pilot RE (a power of two).
+void ne_shape(int n_beams, int* nbv, int* bw) {
+  *nbv = n_beams % 4 == 0 ? 4 : (n_beams % 2 == 0 ? 2 : 1);
+  *bw = 1;
+  while (*bw * *nbv < n_beams) *bw *= 2;
+}
+
 template <int NBV, bool LS>
-void launch_partial(const cf* Y, const cf* P, float2* part, const ChestGeom& g, int bw, int n_parts, long long batch,
-                    hipStream_t s) {
+void launch_partial(const cf* Y, const cf* P, const int4* tab, float2* part, const ChestGeom& g, int bw, int n_parts,
+                    long long batch, hipStream_t s) {
   const dim3 grid((unsigned)n_parts, (unsigned)(batch < 65535 ? batch : 65535));
-  hipLaunchKernelGGL((k_noise_partial<NBV, LS>), grid, dim3(kNeThreads), 0, s, Y, P, part, g, bw, batch);
+  hipLaunchKernelGGL((k_noise_partial<NBV, LS>), grid, dim3(kNeThreads), 0, s, Y, P, tab, part, g, bw, batch);
+}
+
+template <bool LS>
+void launch_partial_ls(int nbv, const cf* Y, const cf* P, const int4* tab, float2* part, const ChestGeom& g, int bw,
+                       int n_parts, long long batch, hipStream_t s) {
+  if (nbv == 4)
+    launch_partial<4, LS>(Y, P, tab, part, g, bw, n_parts, batch, s);
+  else if (nbv == 2)
+    launch_partial<2, LS>(Y, P, tab, part, g, bw, n_parts, batch, s);
+  else
+    launch_partial<1, LS>(Y, P, tab, part, g, bw, n_parts, batch, s);
 }
 
 // Slices per batch item: one per block-iteration's worth of pilot REs, at most kNeParts.
 int noise_parts(const ChestGeom& g) {
-  const int nbv = (g.n_beams % 2) == 0 ? 2 : 1;
-  int bw = 1;
-  while (bw * nbv < g.n_beams) bw *= 2;
+  int nbv, bw;
+  ne_shape(g.n_beams, &nbv, &bw);
   const int per_it = kNeThreads / bw;
-  const int n_re = g.n_pilot * g.n_sc;
-  const int want = (n_re + per_it - 1) / per_it;
+  const int want = (g.n_pilot * g.n_sc + per_it - 1) / per_it;
   return want < 1 ? 1 : (want > kNeParts ? kNeParts : want);
 }
 
 }  // namespace
 
-hipError_t launch_noise_est(const cf* Y, const cf* pilots, bool ls, float2* part, float* sigma2, const ChestGeom& g,
-                            long long batch, hipStream_t s) {
+size_t noise_table_bytes(int n_pilot, int n_sc) { return (size_t)n_pilot * n_sc * sizeof(int4); }
+
+hipError_t launch_noise_table(int4* tab, const ChestGeom& g, hipStream_t s) {
+  const int n_re = g.n_pilot * g.n_sc;
+  if (n_re <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_noise_table, dim3((unsigned)((n_re + 255) / 256)), dim3(256), 0, s, tab, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_noise_est(const cf* Y, const cf* pilots, bool ls, const int4* tab, float2* part, float* sigma2,
+                            const ChestGeom& g, long long batch, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
-  const bool pair = (g.n_beams % 2) == 0;
-  int bw = 1;
-  while (bw * (pair ? 2 : 1) < g.n_beams) bw *= 2;
+  int nbv, bw;
+  ne_shape(g.n_beams, &nbv, &bw);
   const int n_parts = noise_parts(g);
-  if (pair)
-    ls ? launch_partial<2, true>(Y, pilots, part, g, bw, n_parts, batch, s)
-       : launch_partial<2, false>(Y, pilots, part, g, bw, n_parts, batch, s);
+  if (ls)
+    launch_partial_ls<true>(nbv, Y, pilots, tab, part, g, bw, n_parts, batch, s);
   else
-    ls ? launch_partial<1, true>(Y, pilots, part, g, bw, n_parts, batch, s)
-       : launch_partial<1, false>(Y, pilots, part, g, bw, n_parts, batch, s);
+    launch_partial_ls<false>(nbv, Y, pilots, tab, part, g, bw, n_parts, batch, s);
   if (hipError_t e = hipGetLastError()) return e;
   const long long blocks = (batch + 3) / 4;
   hipLaunchKernelGGL(k_noise_final, dim3((unsigned)blocks), dim3(256), 0, s, part, sigma2, n_parts, batch);

@@ -100,12 +100,11 @@ def test_slot_workspace_bytes(lib):
     y = n * 14 * 3300 * 32 * 8
     h = n * 3300 * 16 * 32 * 8
     a = lambda v: (v + 255) // 256 * 256
-    # noise estimation scratch: 64 partial sums (8 B) and one estimate per slot
-    ne = a(n * 64 * 8 + n * 4)
+    # noise estimation scratch: 256 partial sums (8 B) and one estimate per slot
+    ne = a(n * 256 * 8 + n * 4)
     # 16 UEs: the channel is estimated inside the detection kernel, no stored
-    # estimate; a table of interpolation taps instead (two 8-byte taps per
-    # subcarrier and UE: no two pilot symbols share a UE's subcarriers)
-    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d), n) == a(xa) + a(y) + a(3300 * 16 * 2 * 8) + ne
+    # estimate (its interpolation taps are a per-geometry table of the library)
+    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d), n) == a(xa) + a(y) + ne
     d32 = _desc(n_ue=32, n_beams=64)
     xa, y, h = n * 14 * 64 * 3312 * 8, n * 14 * 3300 * 64 * 8, n * 3300 * 32 * 64 * 8
     assert lib.pusch_slot_workspace_bytes(ctypes.byref(d32), n) == a(xa) + a(y) + a(h) + ne
@@ -113,12 +112,10 @@ def test_slot_workspace_bytes(lib):
     d31 = _desc(n_beams=31)
     xa, y, h = n * 14 * 64 * 3312 * 8, n * 14 * 3300 * 31 * 8, n * 3300 * 16 * 31 * 8
     assert lib.pusch_slot_workspace_bytes(ctypes.byref(d31), n) == a(xa) + a(y) + a(h) + ne
-    # one UE, two pilot symbols on the same subcarriers: each bracket end
-    # averages them, 8 taps per subcarrier
+    # one UE: fused detection as well
     d1 = _desc(n_ue=1)
     y = n * 14 * 3300 * 32 * 8
-    assert (lib.pusch_slot_workspace_bytes(ctypes.byref(d1), n) ==
-            a(n * 14 * 64 * 3312 * 8) + a(y) + a(3300 * 8 * 8) + ne)
+    assert lib.pusch_slot_workspace_bytes(ctypes.byref(d1), n) == a(n * 14 * 64 * 3312 * 8) + a(y) + ne
     assert lib.pusch_slot_workspace_bytes(ctypes.byref(_desc(n_fft=1000)), n) == 0
     assert lib.pusch_slot_workspace_bytes(ctypes.byref(_desc(pilot_symb=(11, 2))), n) == 0
 
@@ -152,8 +149,10 @@ def test_slot_workspace_errors(lib):
 
 
 def test_noise_est_validation(lib):
-    assert lib.pusch_noise_est_workspace_bytes(16) == 16 * 64 * 8  # 64 partial sums per item
+    # 256 partial sums (8 B) per item; the neighbour table is the library's, per geometry
+    assert lib.pusch_noise_est_workspace_bytes(16) == 16 * 256 * 8
     assert lib.pusch_noise_est_workspace_bytes(-1) == 0
+    need = lib.pusch_noise_est_workspace_bytes(2)
     f = lib.pusch_noise_est
     ws = ctypes.c_void_p(0x4000000000)
     S = ctypes.c_void_p(0x70000000)
@@ -163,9 +162,10 @@ def test_noise_est_validation(lib):
     assert f(FAKE, FAKE2, S, 32, 16, 31, 2, 1, ws, big, None) == EINVAL  # a UE with one pilot position
     assert f(FAKE, FAKE2, S, 32, 16, 3300, 5, 1, ws, big, None) == EINVAL  # too many pilot symbols
     assert f(FAKE, FAKE2, S, 8, 16, 3300, 2, 1, ws, big, None) == EINVAL  # more UEs than beams
-    assert f(FAKE, FAKE2, S, 32, 16, 3300, 2, 2, ws, 2 * 64 * 8 - 1, None) == ENOMEM
+    assert f(FAKE, FAKE2, S, 32, 16, 3300, 2, 2, ws, need - 1, None) == ENOMEM
     assert f(FAKE, FAKE2, S, 32, 16, 3300, 2, 1, None, big, None) == EINVAL
     assert f(FAKE, FAKE2, S, 32, 16, 3300, 2, 1, ctypes.c_void_p(0x4000000004), big, None) == EINVAL
+    assert f(FAKE, FAKE2, S, 32, 16, 5000, 2, 1, ws, big, None) == EINVAL  # beyond 4096 subcarriers
     assert f(FAKE, FAKE2, ctypes.c_void_p(0x20000), 32, 16, 3300, 2, 1, ws, big, None) == EINVAL  # inside Yp
     assert f(FAKE, FAKE2, S, 32, 16, 3300, 2, 1, ctypes.c_void_p(0x90000100), big, None) == EINVAL  # ws on pilots
     assert f(FAKE, FAKE2, S, 32, 16, 3300, 2, 0, None, 0, None) == 0  # empty batch
@@ -264,9 +264,8 @@ def test_slot_mixed_workspace_and_validation(lib):
     # 64 exponent bytes per slot symbol, then as pusch_slot
     xa, ex = n * 14 * 64 * 3328 * 4, n * 14 * 64
     y = n * 14 * 3300 * 32 * 8
-    ne = a(n * 64 * 8 + n * 4)
-    assert (lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(d), n) ==
-            a(xa) + a(ex) + a(y) + a(3300 * 16 * 2 * 8) + ne)
+    ne = a(n * 256 * 8 + n * 4)
+    assert lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(d), n) == a(xa) + a(ex) + a(y) + ne
     many = _desc(n_ant=65, n_beams=32)
     assert lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(many), n) == 0  # FP16 path: up to 64 antennas
     ws = ctypes.c_void_p(0x4000000000)
