@@ -20,7 +20,11 @@
 // fixed order (no atomics), so the result does not depend on timing.
 //
 // Layout: BW lanes (a power of two) share one pilot RE, each taking NBV
-// consecutive beams of its RE-major row, so a group reads whole rows.
+// consecutive beams of its RE-major row, so a group reads whole rows.  Pilot
+// REs are ordered subcarrier-major (s = k * n_pilot + j), so an RE's
+// neighbours on other pilot symbols are a few REs away, and consecutive
+// slices of an item run on one XCD (xcd_block): they share its L2 instead of
+// fetching the same rows from HBM again.
 #include "comb_ls.h"
 #include "kernels.h"
 
@@ -125,13 +129,13 @@ __device__ __forceinline__ float2 wave_sum(float2 v) {
   return v;
 }
 
-// One table entry per pilot RE s = j * n_sc + k: {lo | hi << 12 | mlo << 24 |
+// One table entry per pilot RE s = k * n_pilot + j: {lo | hi << 12 | mlo << 24 |
 // mhi << 28, bits of wlo, bits of whi, k | j << 16}; a mask of 0 marks a
 // missing side (positions < 4096).
 __global__ __launch_bounds__(256) void k_noise_table(int4* __restrict__ tab, ChestGeom g) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.n_pilot * g.n_sc) return;
-  const int j = s / g.n_sc, k = s - j * g.n_sc;
+  const int k = s / g.n_pilot, j = s - k * g.n_pilot;
   const int l = pos_mod(k + j * (g.n_ue / g.n_pilot), g.n_ue);
   const NeNeighbours n = ne_neighbours(k, l, g.n_ue, g.n_pilot, g.n_sc);
   const int lo = n.mlo ? n.lo : 0, hi = n.mhi ? n.hi : 0;
@@ -139,13 +143,18 @@ __global__ __launch_bounds__(256) void k_noise_table(int4* __restrict__ tab, Che
                      __float_as_int(n.whi), k | j << 16);
 }
 
-// grid: (n_parts, min(batch, 65535)); part[item * kNeParts + blockIdx.x] = (sum |r|^2, sum N_B kappa)
+// One workgroup per (item, slice): logical block id = (item - item0) * n_parts +
+// slice, renumbered by xcd_block; part[item * kNeParts + slice] = (sum |r|^2,
+// sum N_B kappa).
 template <int NBV, bool LS>
 __global__ __launch_bounds__(kNeThreads) void k_noise_partial(const cf* __restrict__ Y, const cf* __restrict__ P,
                                                               const int4* __restrict__ tab,
                                                               float2* __restrict__ part, ChestGeom g, int bw,
-                                                              long long batch) {
+                                                              int n_parts, long long item0) {
   __shared__ float2 red[kNeThreads / 64];
+  const int logical = xcd_block(blockIdx.x, gridDim.x);
+  const int slice = logical % n_parts;
+  const long long bi = item0 + logical / n_parts;
   const int nb = g.n_beams, nsc = g.n_sc;
   const int gl = threadIdx.x & (bw - 1);          // lane within the RE's group
   const int b0 = gl * NBV;                         // first beam of this lane
@@ -153,58 +162,55 @@ __global__ __launch_bounds__(kNeThreads) void k_noise_partial(const cf* __restri
   const int bb = mine ? b0 : 0;                    // lanes past the last beam read beam 0 and add nothing
   const int per_it = kNeThreads / bw;              // pilot REs per block per iteration
   const int n_re = g.n_pilot * nsc;
-  const int stride = gridDim.x * per_it;
-  for (long long bi = blockIdx.y; bi < batch; bi += gridDim.y) {
-    const cf* Yb = Y + bi * g.y_batch;
-    const cf* Pb = P + bi * g.p_batch;
-    float num = 0.f, den = 0.f;
-    for (int s = blockIdx.x * per_it + (int)(threadIdx.x / bw); s < n_re; s += stride) {
-      const int4 t = tab[s];
-      const unsigned mlo = ((unsigned)t.x >> 24) & 15u, mhi = (unsigned)t.x >> 28;
-      const int lo = t.x & 4095, hi = (t.x >> 12) & 4095;
-      const int k = t.w & 0xffff, j = t.w >> 16;
-      float hr[NBV], hi_[NBV];
+  const int stride = n_parts * per_it;
+  const cf* Yb = Y + bi * g.y_batch;
+  const cf* Pb = P + bi * g.p_batch;
+  float num = 0.f, den = 0.f;
+  for (int s = slice * per_it + (int)(threadIdx.x / bw); s < n_re; s += stride) {
+    const int4 t = tab[s];
+    const unsigned mlo = ((unsigned)t.x >> 24) & 15u, mhi = (unsigned)t.x >> 28;
+    const int lo = t.x & 4095, hi = (t.x >> 12) & 4095;
+    const int k = t.w & 0xffff, j = t.w >> 16;
+    float hr[NBV], hi_[NBV];
 #pragma unroll
-      for (int e = 0; e < NBV; ++e) hr[e] = hi_[e] = 0.f;
-      float gain = 0.f;
-      if (mlo) {
-        const float wlo = __int_as_float(t.y);
-        const float q = add_mean<NBV, LS>(hr, hi_, Yb, Pb, g, mlo, lo, wlo, bb);
-        const float c = wlo / (float)__popc(mlo);
-        gain += c * c * q;
-      }
-      if (mhi) {
-        const float whi = __int_as_float(t.z);
-        const float q = add_mean<NBV, LS>(hr, hi_, Yb, Pb, g, mhi, hi, whi, bb);
-        const float c = whi / (float)__popc(mhi);
-        gain += c * c * q;
-      }
-      const cf pv = Pb[(long long)j * nsc + k];
-      const float pp = pv.r * pv.r + pv.i * pv.i;
-      float vr[NBV], vi[NBV];
-      ls_value<NBV, LS>(vr, vi, Yb, g, pv, j, k, bb);
-      float e2 = 0.f;
-#pragma unroll
-      for (int e = 0; e < NBV; ++e) {
-        const float dr = vr[e] - hr[e], di = vi[e] - hi_[e];
-        e2 += dr * dr + di * di;
-      }
-      num += mine ? pp * e2 : 0.f;
-      den += gl == 0 ? (float)nb * (1.f + pp * gain) : 0.f;
+    for (int e = 0; e < NBV; ++e) hr[e] = hi_[e] = 0.f;
+    float gain = 0.f;
+    if (mlo) {
+      const float wlo = __int_as_float(t.y);
+      const float q = add_mean<NBV, LS>(hr, hi_, Yb, Pb, g, mlo, lo, wlo, bb);
+      const float c = wlo / (float)__popc(mlo);
+      gain += c * c * q;
     }
-    float2 v = wave_sum(make_float2(num, den));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      float2 t = red[0];
-#pragma unroll
-      for (int w = 1; w < kNeThreads / 64; ++w) {
-        t.x += red[w].x;
-        t.y += red[w].y;
-      }
-      part[bi * kNeParts + blockIdx.x] = t;
+    if (mhi) {
+      const float whi = __int_as_float(t.z);
+      const float q = add_mean<NBV, LS>(hr, hi_, Yb, Pb, g, mhi, hi, whi, bb);
+      const float c = whi / (float)__popc(mhi);
+      gain += c * c * q;
     }
-    __syncthreads();  // red is reused by the next batch item
+    const cf pv = Pb[(long long)j * nsc + k];
+    const float pp = pv.r * pv.r + pv.i * pv.i;
+    float vr[NBV], vi[NBV];
+    ls_value<NBV, LS>(vr, vi, Yb, g, pv, j, k, bb);
+    float e2 = 0.f;
+#pragma unroll
+    for (int e = 0; e < NBV; ++e) {
+      const float dr = vr[e] - hr[e], di = vi[e] - hi_[e];
+      e2 += dr * dr + di * di;
+    }
+    num += mine ? pp * e2 : 0.f;
+    den += gl == 0 ? (float)nb * (1.f + pp * gain) : 0.f;
+  }
+  float2 v = wave_sum(make_float2(num, den));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float2 t = red[0];
+#pragma unroll
+    for (int w = 1; w < kNeThreads / 64; ++w) {
+      t.x += red[w].x;
+      t.y += red[w].y;
+    }
+    part[bi * kNeParts + slice] = t;
   }
 }
 
@@ -232,11 +238,16 @@ void ne_shape(int n_beams, int* nbv, int* bw) {
   while (*bw * *nbv < n_beams) *bw *= 2;
 }
 
+// One launch per run of at most 2^22 items (n_parts * items < 2^31 blocks).
 template <int NBV, bool LS>
 void launch_partial(const cf* Y, const cf* P, const int4* tab, float2* part, const ChestGeom& g, int bw, int n_parts,
                     long long batch, hipStream_t s) {
-  const dim3 grid((unsigned)n_parts, (unsigned)(batch < 65535 ? batch : 65535));
-  hipLaunchKernelGGL((k_noise_partial<NBV, LS>), grid, dim3(kNeThreads), 0, s, Y, P, tab, part, g, bw, batch);
+  constexpr long long kChunk = 1ll << 22;
+  for (long long b0 = 0; b0 < batch; b0 += kChunk) {
+    const long long items = batch - b0 < kChunk ? batch - b0 : kChunk;
+    hipLaunchKernelGGL((k_noise_partial<NBV, LS>), dim3((unsigned)(items * n_parts)), dim3(kNeThreads), 0, s, Y, P,
+                       tab, part, g, bw, n_parts, b0);
+  }
 }
 
 template <bool LS>
