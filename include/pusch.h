@@ -185,11 +185,16 @@ typedef struct {
                                        needs n_sc >= 2 n_ue */
   float* sigma2_est;                /* device [n_slot]: receives the estimates when noise_est is set,
                                        or NULL; must not overlap any other buffer of the call */
+  int refine;                       /* nonzero: one step of iterative refinement of the MIMO solve
+                                       (residual H^H (y - H x) - sigma2 x from the channel estimate
+                                       and the data symbols, solved with the same Cholesky factor);
+                                       for ill-conditioned Gram matrices (n_ue close to n_beams).
+                                       Uses a stored channel estimate (larger workspace) */
 } pusch_slot_desc;
 
 /* Bytes of device workspace pusch_slot needs for n_slot slots (0 on bad input). */
 size_t pusch_slot_workspace_bytes(const pusch_slot_desc* d, long long n_slot);
-/* (Depends on the geometry fields only; W, pilots, sigma2, noise_est and sigma2_est are not read.) */
+/* (Depends on the geometry fields and refine; W, pilots, sigma2, noise_est and sigma2_est are not read.) */
 
 /*
  * The fused receive chain (Sec. II, Fig. "PUSCH processing chain") for n_slot

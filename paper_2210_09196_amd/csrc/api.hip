@@ -354,6 +354,13 @@ int check_desc(const pusch_slot_desc* d) {
 // per-slot estimates (used when the caller asks for none).
 size_t ne_part_bytes(long long n_slot) { return (size_t)n_slot * pusch::kNeParts * sizeof(float2); }
 
+// The detection kernel estimates the channel itself (no stored estimate)
+// for up to 16 UEs and an even number of beams, unless refinement is asked
+// for (the refining kernel reads a stored estimate).
+bool slot_fused(const pusch_slot_desc* d) {
+  return !d->refine && pusch::mmse_fusable(d->n_ue, d->n_beams, (long long)d->n_symb * d->n_sc * d->n_beams);
+}
+
 // Row pitch of the active-bin grids between the FFT and beamforming: a
 // multiple of 16 subcarriers, so every antenna row starts on a 128-byte line
 // and a beamforming tile of 16 subcarriers reads whole lines that no other
@@ -379,7 +386,7 @@ SlotLayout slot_layout(const pusch_slot_desc* d, long long n_slot, bool mixed = 
   lay.off_h = lay.off_y + align256(n * S * K * B * 8);
   // when the detection kernel estimates the channel itself (up to 16 UEs, an
   // even number of beams) no stored estimate is needed
-  const bool fused = pusch::mmse_fusable(d->n_ue, d->n_beams, (long long)d->n_symb * K * B);
+  const bool fused = slot_fused(d);
   lay.off_ne = lay.off_h + (fused ? 0 : align256(n * K * L * B * 8));
   lay.total = lay.off_ne + align256(ne_part_bytes(n_slot) + n * sizeof(float));
   return lay;
@@ -436,7 +443,7 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   cf* H = reinterpret_cast<cf*>(base + lay.off_h);
   // estimation geometry, and the geometry's cached tables (built before
   // anything is enqueued on s)
-  const bool fused = pusch::mmse_fusable(L, B, (long long)S * K * B);
+  const bool fused = slot_fused(d);
   pusch::ChestGeom cg{};
   cg.n_beams = B;
   cg.n_ue = L;
@@ -509,6 +516,7 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   mg.n_data = D;
   mg.sigma2 = d->noise_est ? 0.f : d->sigma2;
   mg.sigma2_item = s2;
+  mg.refine = d->refine ? 1 : 0;
   mg.h_batch = (long long)K * L * B;
   mg.y_batch = (long long)S * K * B;
   mg.y_sym = (long long)K * B;

@@ -119,6 +119,7 @@ struct MmseGeom {
   int n_beams, n_ue, n_sc, n_data;
   float sigma2;
   const float* sigma2_item;   // device [batch] noise variance per batch item, or nullptr = sigma2
+  int refine;                 // nonzero: one step of iterative refinement (stored-estimate path only)
 };
 hipError_t launch_mmse(const cf* H, const cf* Y, cf* Xhat, int* status, const MmseGeom& g, long long batch,
                        hipStream_t s);

@@ -52,10 +52,64 @@ struct LdsGeom {
   int lrow, lgrp;  // L rows / per-subcarrier stride (aliases the H region)
   int region;      // cf size of the H / L region
   int yg, ydd;     // Y per-subcarrier stride and per-symbol stride
+  int xoff, xd, xg;  // refinement: first solution [grp][d][i] (offset, symbol and subcarrier strides)
+  int eoff, ed, eg;  // refinement: residual of the data symbols [grp][d][b]
   int total;       // cf size of the whole LDS buffer
 };
 
+// acc -= a * b
+__device__ __forceinline__ void csub_mul_rows(cf& acc, cf a, cf b) {
+  acc.r = __builtin_fmaf(-a.r, b.r, __builtin_fmaf(a.i, b.i, acc.r));
+  acc.i = __builtin_fmaf(-a.r, b.i, __builtin_fmaf(-a.i, b.r, acc.i));
+}
+
+// L L^H v = v for every data symbol (v[d], lane i of the group holding
+// component i): lane i holds row i of L in registers (L[m] = L_im) and 1/L_ii
+// in invd; Lg holds the rows of the group's L (row stride lrow) for the
+// transposed reads of the back substitution.
 template <int LPS>
+__device__ __forceinline__ void row_solve(cf (&v)[kMaxD], const cf (&L)[LPS], float invd, const cf* Lg, int lrow, int i,
+                                          int gbase, int nue, int nd) {
+  // forward substitution L z = v, column-oriented
+#pragma unroll
+  for (int m = 0; m < LPS; ++m) {
+    if (m >= nue) continue;
+#pragma unroll
+    for (int d = 0; d < kMaxD; ++d) {
+      if (d >= nd) continue;
+      const float zr = lane_bcast(v[d].r * invd, (gbase + m) << 2);
+      const float zi = lane_bcast(v[d].i * invd, (gbase + m) << 2);
+      if (i == m) {
+        v[d] = cf{zr, zi};
+      } else if (i > m) {
+        v[d].r -= L[m].r * zr - L[m].i * zi;
+        v[d].i -= L[m].r * zi + L[m].i * zr;
+      }
+    }
+  }
+  // back substitution L^H x = z: x_m = (z_m - sum_{n>m} conj(L_nm) x_n) / L_mm
+#pragma unroll
+  for (int m = LPS - 1; m >= 0; --m) {
+    if (m >= nue) continue;
+    const cf lmi = Lg[m * lrow + i];
+#pragma unroll
+    for (int d = 0; d < kMaxD; ++d) {
+      if (d >= nd) continue;
+      const float xr = lane_bcast(v[d].r * invd, (gbase + m) << 2);
+      const float xi = lane_bcast(v[d].i * invd, (gbase + m) << 2);
+      if (i == m) {
+        v[d] = cf{xr, xi};
+      } else if (i < m) {
+        v[d].r -= lmi.r * xr + lmi.i * xi;  // conj(L_mi) * x_m
+        v[d].i -= lmi.r * xi - lmi.i * xr;
+      }
+    }
+  }
+}
+
+// REFINE: one step of iterative refinement (g.refine), a separate instance so
+// the plain path keeps its registers.
+template <int LPS, bool REFINE>
 __global__ __launch_bounds__(64) void k_mmse_rows(const cf* __restrict__ H, const cf* __restrict__ Y, cf* __restrict__ Xh,
                                              int* __restrict__ st, MmseGeom g, LdsGeom lg, long long nblk,
                                              int nblk_batch) {
@@ -173,40 +227,49 @@ __global__ __launch_bounds__(64) void k_mmse_rows(const cf* __restrict__ H, cons
     for (int m = 0; m < LPS; ++m) Ls[grp * lg.lgrp + i * lg.lrow + m] = L[m];
     __syncthreads();
 
-    // forward substitution L z = r, column-oriented
+    row_solve<LPS>(rr, L, invd, Ls + grp * lg.lgrp, lg.lrow, i, gbase, nue, nd);
+
+    if constexpr (REFINE) {
+      // One step of iterative refinement.  The residual of the normal
+      // equations, r = H^H (y - H x0) - sigma^2 x0, is formed from the stored
+      // estimate and the data symbols themselves (not from the rounded G);
+      // L L^H dx = r with the same factor; x1 = x0 + dx.
+      cf* Xs = sm + lg.xoff + grp * lg.xg;
+      cf* Es = sm + lg.eoff + grp * lg.eg;
+      __syncthreads();
 #pragma unroll
-    for (int m = 0; m < LPS; ++m) {
-      if (m >= nue) continue;
+      for (int d = 0; d < kMaxD; ++d)
+        if (d < nd) Xs[d * lg.xd + i] = (i < nue) ? rr[d] : cf{0.f, 0.f};
+      __syncthreads();
+      const cf* Hk = H + bi * g.h_batch + (long long)(valid ? k : k0) * nue * nb;
+      // e_b = y_b - sum_j H_bj x0_j: lane t takes beams t, t + LPS, ...
+      for (int b = i; b < nb; b += LPS)
+        for (int d = 0; d < nd; ++d) {
+          cf e = valid ? Y[bi * g.y_batch + data_grid(g, d) + (long long)k * nb + b] : cf{0.f, 0.f};
+          for (int j = 0; j < nue; ++j) csub_mul_rows(e, Hk[j * nb + b], Xs[d * lg.xd + j]);
+          Es[d * lg.ed + b] = e;
+        }
+      __syncthreads();
+      // r_i = sum_b conj(H_bi) e_b - sigma^2 x0_i
+      cf r[kMaxD];
 #pragma unroll
       for (int d = 0; d < kMaxD; ++d) {
-        if (d >= nd) continue;
-        const float zr = lane_bcast(rr[d].r * invd, (gbase + m) << 2);
-        const float zi = lane_bcast(rr[d].i * invd, (gbase + m) << 2);
-        if (i == m) {
-          rr[d] = cf{zr, zi};
-        } else if (i > m) {
-          rr[d].r -= L[m].r * zr - L[m].i * zi;
-          rr[d].i -= L[m].r * zi + L[m].i * zr;
+        const cf x0 = d < nd ? Xs[d * lg.xd + i] : cf{0.f, 0.f};
+        r[d] = cf{-s2 * x0.r, -s2 * x0.i};
+      }
+      for (int b = 0; b < nb; ++b) {
+        const cf h = Hk[irow * nb + b];
+#pragma unroll
+        for (int d = 0; d < kMaxD; ++d) {
+          if (d >= nd) continue;
+          const cf e = Es[d * lg.ed + b];
+          r[d].r += h.r * e.r + h.i * e.i;
+          r[d].i += h.r * e.i - h.i * e.r;
         }
       }
-    }
-    // back substitution L^H x = z: x_m = (z_m - sum_{n>m} conj(L_nm) x_n) / L_mm
+      row_solve<LPS>(r, L, invd, Ls + grp * lg.lgrp, lg.lrow, i, gbase, nue, nd);
 #pragma unroll
-    for (int m = LPS - 1; m >= 0; --m) {
-      if (m >= nue) continue;
-      const cf lmi = Ls[grp * lg.lgrp + m * lg.lrow + i];
-#pragma unroll
-      for (int d = 0; d < kMaxD; ++d) {
-        if (d >= nd) continue;
-        const float xr = lane_bcast(rr[d].r * invd, (gbase + m) << 2);
-        const float xi = lane_bcast(rr[d].i * invd, (gbase + m) << 2);
-        if (i == m) {
-          rr[d] = cf{xr, xi};
-        } else if (i < m) {
-          rr[d].r -= lmi.r * xr + lmi.i * xi;  // conj(L_mi) * x_m
-          rr[d].i -= lmi.r * xi - lmi.i * xr;
-        }
-      }
+      for (int d = 0; d < kMaxD; ++d) rr[d] = cf{rr[d].r + r[d].r, rr[d].i + r[d].i};
     }
 
     if (valid && i < nue) {
@@ -221,7 +284,7 @@ __global__ __launch_bounds__(64) void k_mmse_rows(const cf* __restrict__ H, cons
   }
 }
 
-LdsGeom lds_geom(int lps, int nb, int nue) {
+LdsGeom lds_geom(int lps, int nb, int nue, bool refine) {
   const int spw = 64 / lps;
   LdsGeom lg;
   lg.hrow = nb | 1;
@@ -232,20 +295,34 @@ LdsGeom lds_geom(int lps, int nb, int nue) {
   lg.yg = nb | 1;
   lg.ydd = spw * lg.yg + 1;
   lg.total = lg.region + kDCh * lg.ydd;
+  lg.xd = lps + 1;
+  lg.xg = kMaxD * lg.xd + 1;
+  lg.ed = nb | 1;
+  lg.eg = kMaxD * lg.ed + 1;
+  lg.xoff = lg.eoff = 0;
+  if (refine) {
+    lg.xoff = lg.total;
+    lg.eoff = lg.xoff + spw * lg.xg;
+    lg.total = lg.eoff + spw * lg.eg;
+  }
   return lg;
 }
 
 template <int LPS>
 hipError_t launch_lps(const cf* H, const cf* Y, cf* Xh, int* st, const MmseGeom& g, long long batch, hipStream_t s) {
   constexpr int SPW = 64 / LPS;
-  const LdsGeom lg = lds_geom(LPS, g.n_beams, g.n_ue);
+  const LdsGeom lg = lds_geom(LPS, g.n_beams, g.n_ue, g.refine != 0);
   const int nblk_batch = (g.n_sc + SPW - 1) / SPW;
   const long long nblk = batch * nblk_batch;
   if (nblk <= 0) return hipSuccess;
   long long blocks = nblk;
   if (blocks > (1LL << 30)) blocks = 1LL << 30;
-  hipLaunchKernelGGL(k_mmse_rows<LPS>, dim3((unsigned)blocks), dim3(64), (size_t)lg.total * sizeof(cf), s, H, Y, Xh, st, g,
-                     lg, nblk, nblk_batch);
+  if (g.refine)
+    hipLaunchKernelGGL((k_mmse_rows<LPS, true>), dim3((unsigned)blocks), dim3(64), (size_t)lg.total * sizeof(cf), s, H,
+                       Y, Xh, st, g, lg, nblk, nblk_batch);
+  else
+    hipLaunchKernelGGL((k_mmse_rows<LPS, false>), dim3((unsigned)blocks), dim3(64), (size_t)lg.total * sizeof(cf), s,
+                       H, Y, Xh, st, g, lg, nblk, nblk_batch);
   return hipGetLastError();
 }
 
@@ -668,7 +745,8 @@ bool mmse_fusable(int n_ue, int n_beams, long long y_batch) {
 hipError_t launch_mmse(const cf* H, const cf* Y, cf* Xhat, int* status, const MmseGeom& g, long long batch,
                        hipStream_t s) {
   if (g.n_data > kMaxD || g.n_data < 1) return hipErrorInvalidValue;
-  if (g.n_ue <= 16) return dispatch_mfma<false, 0>(H, Y, nullptr, ChestGeom{}, Xhat, status, g, batch, s);
+  // refinement: the row kernel (any n_ue up to 32)
+  if (g.n_ue <= 16 && !g.refine) return dispatch_mfma<false, 0>(H, Y, nullptr, ChestGeom{}, Xhat, status, g, batch, s);
   if (g.n_ue <= 32) return launch_lps<32>(H, Y, Xhat, status, g, batch, s);
   return hipErrorInvalidValue;
 }

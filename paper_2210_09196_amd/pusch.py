@@ -40,6 +40,7 @@ class SlotDesc(ctypes.Structure):
         ("pilots", ctypes.c_void_p),
         ("noise_est", ctypes.c_int),
         ("sigma2_est", ctypes.c_void_p),
+        ("refine", ctypes.c_int),
     ]
 
 
@@ -231,11 +232,12 @@ class Slot:
     OFDM demodulation and beamforming, beamforming on FP16 matrix cores with
     FP32 accumulation, FP32 estimation and detection).  sigma2=None estimates
     every slot's noise variance from its pilot symbols; each call leaves the
-    estimates in self.sigma2_est ([n_slot] float32)."""
+    estimates in self.sigma2_est ([n_slot] float32).  refine=True adds one
+    iterative-refinement step to the MIMO solve."""
 
     def __init__(self, n_ant: int, n_fft: int, n_sc: int, n_symb: int, n_beams: int, n_ue: int, pilot_symb,
                  sigma2: float | None, n_slot: int, W: torch.Tensor | None = None, device="cuda",
-                 precision: str = "fp32"):
+                 precision: str = "fp32", refine: bool = False):
         if precision not in ("fp32", "mixed"):
             raise PuschError("precision is 'fp32' or 'mixed'")
         self.mixed = precision == "mixed"
@@ -249,6 +251,7 @@ class Slot:
         for j, s in enumerate(pilot_symb):
             d.pilot_symb[j] = s
         self.sigma2_est = _noise_fields(d, sigma2, n_slot, device)
+        d.refine = 1 if refine else 0
         self.W = None if W is None else _c64(W, "W")
         d.W = _ptr(self.W)
         self.n_slot = n_slot
@@ -313,7 +316,7 @@ class Cells:
 
     Each cell is a dict with the slot geometry (n_ant, n_fft, n_sc, n_symb,
     n_beams, n_ue, pilot_symb), sigma2 (None: estimated per slot, left in
-    self.sigma2_est[c]), n_slot (>= 1) and optionally W.  The
+    self.sigma2_est[c]), n_slot (>= 1) and optionally W and refine.  The
     workspace is allocated once here; a call enqueues every cell on the
     library's side streams, forked from and joined back to the current torch
     stream, so it can be captured into a CUDA/HIP graph.
@@ -341,6 +344,7 @@ class Cells:
             self.sigma2_est.append(
                 _fill_desc(self.descs[c], g["n_ant"], g["n_fft"], g["n_sc"], g["n_symb"], g["n_beams"], g["n_ue"],
                            g["pilot_symb"], g["sigma2"], W, int(g["n_slot"]), device))
+            self.descs[c].refine = 1 if g.get("refine") else 0
             self.n_slot[c] = int(g["n_slot"])
             self.geom.append(dict(g))
         nbytes = lib().pusch_cells_workspace_bytes(self.descs, n, self.n_slot, self.mixed)

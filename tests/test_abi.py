@@ -105,6 +105,9 @@ def test_slot_workspace_bytes(lib):
     # 16 UEs: the channel is estimated inside the detection kernel, no stored
     # estimate (its interpolation taps are a per-geometry table of the library)
     assert lib.pusch_slot_workspace_bytes(ctypes.byref(d), n) == a(xa) + a(y) + ne
+    # refinement reads a stored estimate: the fused geometry gains the H region
+    dr = _desc(refine=1)
+    assert lib.pusch_slot_workspace_bytes(ctypes.byref(dr), n) == a(xa) + a(y) + a(h) + ne
     d32 = _desc(n_ue=32, n_beams=64)
     xa, y, h = n * 14 * 64 * 3312 * 8, n * 14 * 3300 * 64 * 8, n * 3300 * 32 * 64 * 8
     assert lib.pusch_slot_workspace_bytes(ctypes.byref(d32), n) == a(xa) + a(y) + a(h) + ne
