@@ -110,7 +110,7 @@ __device__ __forceinline__ void row_solve(cf (&v)[kMaxD], const cf (&L)[LPS], fl
 // REFINE: one step of iterative refinement (g.refine), a separate instance so
 // the plain path keeps its registers.
 template <int LPS, bool REFINE>
-__global__ __launch_bounds__(64) void k_mmse_rows(const cf* __restrict__ H, const cf* __restrict__ Y, cf* __restrict__ Xh,
+__global__ __launch_bounds__(64, 2) void k_mmse_rows(const cf* __restrict__ H, const cf* __restrict__ Y, cf* __restrict__ Xh,
                                              int* __restrict__ st, MmseGeom g, LdsGeom lg, long long nblk,
                                              int nblk_batch) {
   extern __shared__ cf sm[];
@@ -242,12 +242,23 @@ __global__ __launch_bounds__(64) void k_mmse_rows(const cf* __restrict__ H, cons
         if (d < nd) Xs[d * lg.xd + i] = (i < nue) ? rr[d] : cf{0.f, 0.f};
       __syncthreads();
       const cf* Hk = H + bi * g.h_batch + (long long)(valid ? k : k0) * nue * nb;
-      // e_b = y_b - sum_j H_bj x0_j: lane t takes beams t, t + LPS, ...
+      // e_b = y_b - sum_j H_bj x0_j: lane t takes beams t, t + LPS, ...; kDCh
+      // symbols at a time, so each H_bj is loaded once per chunk
       for (int b = i; b < nb; b += LPS)
-        for (int d = 0; d < nd; ++d) {
-          cf e = valid ? Y[bi * g.y_batch + data_grid(g, d) + (long long)k * nb + b] : cf{0.f, 0.f};
-          for (int j = 0; j < nue; ++j) csub_mul_rows(e, Hk[j * nb + b], Xs[d * lg.xd + j]);
-          Es[d * lg.ed + b] = e;
+        for (int d0 = 0; d0 < nd; d0 += kDCh) {
+          cf e[kDCh];
+#pragma unroll
+          for (int dd = 0; dd < kDCh; ++dd)
+            e[dd] = (valid && d0 + dd < nd) ? Y[bi * g.y_batch + data_grid(g, d0 + dd) + (long long)k * nb + b]
+                                            : cf{0.f, 0.f};
+          for (int j = 0; j < nue; ++j) {
+            const cf h = Hk[j * nb + b];
+#pragma unroll
+            for (int dd = 0; dd < kDCh; ++dd) csub_mul_rows(e[dd], h, Xs[(d0 + dd) * lg.xd + j]);
+          }
+#pragma unroll
+          for (int dd = 0; dd < kDCh; ++dd)
+            if (d0 + dd < nd) Es[(d0 + dd) * lg.ed + b] = e[dd];
         }
       __syncthreads();
       // r_i = sum_b conj(H_bi) e_b - sigma^2 x0_i
