@@ -119,3 +119,40 @@ def test_cells_mixed_precision_match_single_mixed_calls():
         ref = O.receive_slot(b["x_td"][0], b["pilots"][0], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
                              n_beams=cfg.n_beams)
         assert M.nrmse(host(xh[c])[0], ref["x_hat"]) <= 2e-3, c
+
+
+def test_cells_graph_replay_with_noise_estimation_and_mixed_precision():
+    # the noise-estimation kernels and the FP16 path inside a captured graph:
+    # every replay must reproduce the eager call's symbols and estimates exactly
+    cfgs, batches, geoms = make_cells(CELLS[:4], seed0=1300)
+    for g in geoms:
+        g["sigma2"] = None
+    for precision in ("fp32", "mixed"):
+        cells = pusch.Cells(geoms, precision=precision)
+        xs = [dev(b["x_td"]) for b in batches]
+        ps = [dev(b["pilots"]) for b in batches]
+        ref, ref_st = cells(xs, ps)
+        torch.cuda.synchronize()
+        ref_est = [t.clone() for t in cells.sigma2_est]
+        out, out_st = cells.outputs()
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            cells(xs, ps, out, out_st)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            cells(xs, ps, out, out_st)
+        for r in range(3):
+            for t in out:
+                t.zero_()
+            for t in cells.sigma2_est:
+                t.fill_(-1.0)
+            g.replay()
+            torch.cuda.synchronize()
+            for c in range(len(geoms)):
+                assert torch.equal(out[c], ref[c]) and torch.equal(out_st[c], ref_st[c]), (precision, r, c)
+                assert torch.equal(cells.sigma2_est[c], ref_est[c]), (precision, r, c)
+            cells(xs, ps)  # eager work between replays
+            torch.cuda.synchronize()
