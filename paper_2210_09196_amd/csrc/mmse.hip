@@ -20,8 +20,11 @@
 //   table of interpolation taps (launch_comb_taps), so the fused slot never
 //   writes or re-reads a channel estimate.
 //
-// k_mmse_rows (n_ue <= 32): lane i of a group of LPS lanes holds row i of G
-//   and L; Gram and matched filter from LDS-staged H and y on the VALU.
+// k_mmse_rows (n_ue <= 32, and iterative refinement): two subcarriers per
+//   wavefront.  The Gram matrix (three 16x16 blocks of its lower triangle)
+//   and the matched filter run on 16x16x4 FP32 MFMAs as above, through LDS;
+//   then lane i of a group of 32 holds row i of G and L for the Crout
+//   factorisation and the substitutions (rows broadcast by lane permutes).
 #include <cmath>
 
 #include "kernels.h"
@@ -32,316 +35,7 @@ namespace {
 constexpr int kMaxD = 16;  // data symbols per kernel call (host splits larger requests)
 constexpr int kDCh = 4;    // data symbols staged in LDS at a time
 
-// Value of v in the lane whose byte address (4 * lane) is src_byte.
-__device__ __forceinline__ float lane_bcast(float v, int src_byte) {
-  return __int_as_float(__builtin_amdgcn_ds_bpermute(src_byte, __float_as_int(v)));
-}
-
-// Element offset of data symbol d's grid: the d-th grid from d_first that
-// is not one of the (ascending) skipped pilot grids.
-__device__ __forceinline__ long long data_grid(const MmseGeom& g, int d) {
-  int s = g.d_first + d;
-#pragma unroll
-  for (int j = 0; j < kMaxPilots; ++j)
-    if (j < g.n_skip && g.skip[j] <= s) ++s;
-  return (long long)s * g.y_sym;
-}
-
-struct LdsGeom {
-  int hrow, hgrp;  // H rows (beams) and per-subcarrier stride, in cf
-  int lrow, lgrp;  // L rows / per-subcarrier stride (aliases the H region)
-  int region;      // cf size of the H / L region
-  int yg, ydd;     // Y per-subcarrier stride and per-symbol stride
-  int xoff, xd, xg;  // refinement: first solution [grp][d][i] (offset, symbol and subcarrier strides)
-  int eoff, ed, eg;  // refinement: residual of the data symbols [grp][d][b]
-  int total;       // cf size of the whole LDS buffer
-};
-
-// acc -= a * b
-__device__ __forceinline__ void csub_mul_rows(cf& acc, cf a, cf b) {
-  acc.r = __builtin_fmaf(-a.r, b.r, __builtin_fmaf(a.i, b.i, acc.r));
-  acc.i = __builtin_fmaf(-a.r, b.i, __builtin_fmaf(-a.i, b.r, acc.i));
-}
-
-// L L^H v = v for every data symbol (v[d], lane i of the group holding
-// component i): lane i holds row i of L in registers (L[m] = L_im) and 1/L_ii
-// in invd; Lg holds the rows of the group's L (row stride lrow) for the
-// transposed reads of the back substitution.
-template <int LPS>
-__device__ __forceinline__ void row_solve(cf (&v)[kMaxD], const cf (&L)[LPS], float invd, const cf* Lg, int lrow, int i,
-                                          int gbase, int nue, int nd) {
-  // forward substitution L z = v, column-oriented
-#pragma unroll
-  for (int m = 0; m < LPS; ++m) {
-    if (m >= nue) continue;
-#pragma unroll
-    for (int d = 0; d < kMaxD; ++d) {
-      if (d >= nd) continue;
-      const float zr = lane_bcast(v[d].r * invd, (gbase + m) << 2);
-      const float zi = lane_bcast(v[d].i * invd, (gbase + m) << 2);
-      if (i == m) {
-        v[d] = cf{zr, zi};
-      } else if (i > m) {
-        v[d].r -= L[m].r * zr - L[m].i * zi;
-        v[d].i -= L[m].r * zi + L[m].i * zr;
-      }
-    }
-  }
-  // back substitution L^H x = z: x_m = (z_m - sum_{n>m} conj(L_nm) x_n) / L_mm
-#pragma unroll
-  for (int m = LPS - 1; m >= 0; --m) {
-    if (m >= nue) continue;
-    const cf lmi = Lg[m * lrow + i];
-#pragma unroll
-    for (int d = 0; d < kMaxD; ++d) {
-      if (d >= nd) continue;
-      const float xr = lane_bcast(v[d].r * invd, (gbase + m) << 2);
-      const float xi = lane_bcast(v[d].i * invd, (gbase + m) << 2);
-      if (i == m) {
-        v[d] = cf{xr, xi};
-      } else if (i < m) {
-        v[d].r -= lmi.r * xr + lmi.i * xi;  // conj(L_mi) * x_m
-        v[d].i -= lmi.r * xi - lmi.i * xr;
-      }
-    }
-  }
-}
-
-// REFINE: one step of iterative refinement (g.refine), a separate instance so
-// the plain path keeps its registers.
-template <int LPS, bool REFINE>
-__global__ __launch_bounds__(64, 2) void k_mmse_rows(const cf* __restrict__ H, const cf* __restrict__ Y, cf* __restrict__ Xh,
-                                             int* __restrict__ st, MmseGeom g, LdsGeom lg, long long nblk,
-                                             int nblk_batch) {
-  extern __shared__ cf sm[];
-  constexpr int SPW = 64 / LPS;
-  const int lane = threadIdx.x;
-  const int grp = lane / LPS, i = lane % LPS, gbase = grp * LPS;
-  const int nb = g.n_beams, nue = g.n_ue, nsc = g.n_sc, nd = g.n_data;
-  cf* Hs = sm;
-  cf* Ls = sm;
-  cf* Ys = sm + lg.region;
-  const int irow = i < nue ? i : nue - 1;
-
-  for (long long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const long long bi = blk / nblk_batch;
-    const int k0 = (int)(blk - bi * nblk_batch) * SPW;
-    const int cnt = min(SPW, nsc - k0);
-    const int k = k0 + grp;
-    const bool valid = grp < cnt;
-
-    __syncthreads();
-    {
-      const cf* src = H + bi * g.h_batch + (long long)k0 * nue * nb;
-      const int n = cnt * nue * nb;
-      for (int e = lane; e < n; e += 64) {
-        const int b = e % nb, r = e / nb;
-        Hs[(r / nue) * lg.hgrp + (r % nue) * lg.hrow + b] = src[e];
-      }
-    }
-    __syncthreads();
-
-    const cf* hi_row = Hs + grp * lg.hgrp + irow * lg.hrow;
-    const cf* hg = Hs + grp * lg.hgrp;
-
-    // Gram row i: G_ij = sum_b conj(H_bi) H_bj (+ sigma^2 on the diagonal)
-    cf G[LPS];
-#pragma unroll
-    for (int j = 0; j < LPS; ++j) G[j] = cf{0.f, 0.f};
-    for (int b = 0; b < nb; ++b) {
-      const cf a = hi_row[b];
-#pragma unroll
-      for (int j = 0; j < LPS; ++j) {
-        if (j < nue) {
-          const cf c = hg[j * lg.hrow + b];
-          G[j].r += a.r * c.r + a.i * c.i;
-          G[j].i += a.r * c.i - a.i * c.r;
-        }
-      }
-    }
-    const float s2 = g.sigma2_item ? g.sigma2_item[bi] : g.sigma2;
-#pragma unroll
-    for (int j = 0; j < LPS; ++j)
-      if (j == i) G[j].r += s2;
-
-    // matched filter r_d = H^H y_d for every data symbol
-    cf rr[kMaxD];
-#pragma unroll
-    for (int d = 0; d < kMaxD; ++d) rr[d] = cf{0.f, 0.f};
-#pragma unroll
-    for (int c = 0; c < kMaxD / kDCh; ++c) {
-      if (c * kDCh >= nd) continue;
-      __syncthreads();
-      for (int dd = 0; dd < kDCh; ++dd) {
-        const int d = c * kDCh + dd;
-        if (d >= nd) break;
-        const cf* src = Y + bi * g.y_batch + data_grid(g, d) + (long long)k0 * nb;
-        const int n = cnt * nb;
-        for (int e = lane; e < n; e += 64) Ys[dd * lg.ydd + (e / nb) * lg.yg + (e % nb)] = src[e];
-      }
-      __syncthreads();
-      const cf* yg = Ys + grp * lg.yg;
-      for (int b = 0; b < nb; ++b) {
-        const cf a = hi_row[b];
-#pragma unroll
-        for (int dd = 0; dd < kDCh; ++dd) {
-          const cf y = yg[dd * lg.ydd + b];
-          cf& o = rr[c * kDCh + dd];
-          o.r += a.r * y.r + a.i * y.i;
-          o.i += a.r * y.i - a.i * y.r;
-        }
-      }
-    }
-
-    // Cholesky-Crout: column j uses row j of L (lane j of the group)
-    int fail = 0;
-    float invd = 0.f;
-    cf L[LPS];
-#pragma unroll
-    for (int j = 0; j < LPS; ++j) L[j] = G[j];
-#pragma unroll
-    for (int j = 0; j < LPS; ++j) {
-      if (j >= nue) continue;
-      const int src = (gbase + j) << 2;
-      cf t = L[j];
-#pragma unroll
-      for (int m = 0; m < j; ++m) {
-        const float cr = lane_bcast(L[m].r, src);
-        const float ci = lane_bcast(L[m].i, src);
-        t.r -= L[m].r * cr + L[m].i * ci;  // L_im * conj(L_jm)
-        t.i -= L[m].i * cr - L[m].r * ci;
-      }
-      const float dpiv = lane_bcast(t.r, src);
-      fail |= (dpiv > 0.f && dpiv <= 3.402823466e38f) ? 0 : 1;
-      const float ljj = sqrtf(dpiv);
-      const float inv = 1.0f / ljj;
-      const cf lij = cf{t.r * inv, t.i * inv};
-      L[j] = i == j ? cf{ljj, 0.f} : (i > j ? lij : cf{0.f, 0.f});
-      invd = i == j ? inv : invd;
-    }
-
-    // rows of L to LDS (reusing the H region) for the transposed reads of
-    // the back substitution
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < LPS; ++m) Ls[grp * lg.lgrp + i * lg.lrow + m] = L[m];
-    __syncthreads();
-
-    row_solve<LPS>(rr, L, invd, Ls + grp * lg.lgrp, lg.lrow, i, gbase, nue, nd);
-
-    if constexpr (REFINE) {
-      // One step of iterative refinement.  The residual of the normal
-      // equations, r = H^H (y - H x0) - sigma^2 x0, is formed from the stored
-      // estimate and the data symbols themselves (not from the rounded G);
-      // L L^H dx = r with the same factor; x1 = x0 + dx.
-      cf* Xs = sm + lg.xoff + grp * lg.xg;
-      cf* Es = sm + lg.eoff + grp * lg.eg;
-      __syncthreads();
-#pragma unroll
-      for (int d = 0; d < kMaxD; ++d)
-        if (d < nd) Xs[d * lg.xd + i] = (i < nue) ? rr[d] : cf{0.f, 0.f};
-      __syncthreads();
-      const cf* Hk = H + bi * g.h_batch + (long long)(valid ? k : k0) * nue * nb;
-      // e_b = y_b - sum_j H_bj x0_j: lane t takes beams t, t + LPS, ...; kDCh
-      // symbols at a time, so each H_bj is loaded once per chunk
-      for (int b = i; b < nb; b += LPS)
-        for (int d0 = 0; d0 < nd; d0 += kDCh) {
-          cf e[kDCh];
-#pragma unroll
-          for (int dd = 0; dd < kDCh; ++dd)
-            e[dd] = (valid && d0 + dd < nd) ? Y[bi * g.y_batch + data_grid(g, d0 + dd) + (long long)k * nb + b]
-                                            : cf{0.f, 0.f};
-          for (int j = 0; j < nue; ++j) {
-            const cf h = Hk[j * nb + b];
-#pragma unroll
-            for (int dd = 0; dd < kDCh; ++dd) csub_mul_rows(e[dd], h, Xs[(d0 + dd) * lg.xd + j]);
-          }
-#pragma unroll
-          for (int dd = 0; dd < kDCh; ++dd)
-            if (d0 + dd < nd) Es[(d0 + dd) * lg.ed + b] = e[dd];
-        }
-      __syncthreads();
-      // r_i = sum_b conj(H_bi) e_b - sigma^2 x0_i
-      cf r[kMaxD];
-#pragma unroll
-      for (int d = 0; d < kMaxD; ++d) {
-        const cf x0 = d < nd ? Xs[d * lg.xd + i] : cf{0.f, 0.f};
-        r[d] = cf{-s2 * x0.r, -s2 * x0.i};
-      }
-      for (int b = 0; b < nb; ++b) {
-        const cf h = Hk[irow * nb + b];
-#pragma unroll
-        for (int d = 0; d < kMaxD; ++d) {
-          if (d >= nd) continue;
-          const cf e = Es[d * lg.ed + b];
-          r[d].r += h.r * e.r + h.i * e.i;
-          r[d].i += h.r * e.i - h.i * e.r;
-        }
-      }
-      row_solve<LPS>(r, L, invd, Ls + grp * lg.lgrp, lg.lrow, i, gbase, nue, nd);
-#pragma unroll
-      for (int d = 0; d < kMaxD; ++d) rr[d] = cf{rr[d].r + r[d].r, rr[d].i + r[d].i};
-    }
-
-    if (valid && i < nue) {
-      cf* dst = Xh + bi * g.x_batch + (long long)k * nue + i;
-#pragma unroll
-      for (int d = 0; d < kMaxD; ++d) {
-        if (d >= nd) continue;
-        dst[(long long)d * nsc * nue] = fail ? cf{0.f, 0.f} : rr[d];
-      }
-    }
-    if (valid && i == 0 && st) st[bi * g.st_batch + k] = fail ? 1 : 0;
-  }
-}
-
-LdsGeom lds_geom(int lps, int nb, int nue, bool refine) {
-  const int spw = 64 / lps;
-  LdsGeom lg;
-  lg.hrow = nb | 1;
-  lg.hgrp = nue * lg.hrow + 1;
-  lg.lrow = lps + 1;
-  lg.lgrp = lps * lg.lrow + 1;
-  lg.region = spw * (lg.hgrp > lg.lgrp ? lg.hgrp : lg.lgrp);
-  lg.yg = nb | 1;
-  lg.ydd = spw * lg.yg + 1;
-  lg.total = lg.region + kDCh * lg.ydd;
-  lg.xd = lps + 1;
-  lg.xg = kMaxD * lg.xd + 1;
-  lg.ed = nb | 1;
-  lg.eg = kMaxD * lg.ed + 1;
-  lg.xoff = lg.eoff = 0;
-  if (refine) {
-    lg.xoff = lg.total;
-    lg.eoff = lg.xoff + spw * lg.xg;
-    lg.total = lg.eoff + spw * lg.eg;
-  }
-  return lg;
-}
-
-template <int LPS>
-hipError_t launch_lps(const cf* H, const cf* Y, cf* Xh, int* st, const MmseGeom& g, long long batch, hipStream_t s) {
-  constexpr int SPW = 64 / LPS;
-  const LdsGeom lg = lds_geom(LPS, g.n_beams, g.n_ue, g.refine != 0);
-  const int nblk_batch = (g.n_sc + SPW - 1) / SPW;
-  const long long nblk = batch * nblk_batch;
-  if (nblk <= 0) return hipSuccess;
-  long long blocks = nblk;
-  if (blocks > (1LL << 30)) blocks = 1LL << 30;
-  if (g.refine)
-    hipLaunchKernelGGL((k_mmse_rows<LPS, true>), dim3((unsigned)blocks), dim3(64), (size_t)lg.total * sizeof(cf), s, H,
-                       Y, Xh, st, g, lg, nblk, nblk_batch);
-  else
-    hipLaunchKernelGGL((k_mmse_rows<LPS, false>), dim3((unsigned)blocks), dim3(64), (size_t)lg.total * sizeof(cf), s,
-                       H, Y, Xh, st, g, lg, nblk, nblk_batch);
-  return hipGetLastError();
-}
-
-}  // namespace
-
-
-// ---------------------------------------------------------------- MFMA path (n_ue <= 16)
-namespace {
+// ---- shared by both detection kernels: MFMA operands and cross-lane moves
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -446,6 +140,326 @@ __device__ __forceinline__ void load_pair(cf& v0, cf& v1, const cf* __restrict__
 __device__ __forceinline__ float4 load_pair_even(const cf* __restrict__ row, int b, int nb) {
   return *reinterpret_cast<const float4*>(row + (b < nb ? b : 0));
 }
+
+
+
+// Value of v in the lane whose byte address (4 * lane) is src_byte.
+__device__ __forceinline__ float lane_bcast(float v, int src_byte) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src_byte, __float_as_int(v)));
+}
+
+// Element offset of data symbol d's grid: the d-th grid from d_first that
+// is not one of the (ascending) skipped pilot grids.
+__device__ __forceinline__ long long data_grid(const MmseGeom& g, int d) {
+  int s = g.d_first + d;
+#pragma unroll
+  for (int j = 0; j < kMaxPilots; ++j)
+    if (j < g.n_skip && g.skip[j] <= s) ++s;
+  return (long long)s * g.y_sym;
+}
+
+struct LdsGeom {
+  int gt;            // packed lower triangle of G per subcarrier (row i at i(i+1)/2), cf
+  int poff, prow, pg;  // matched filter [grp][UE][symbol]: offset, row and subcarrier strides
+  int lrow, lgrp;    // rows of L [grp][row][col] (reuse the G and P space once both are read)
+  int xoff, xd, xg;  // refinement: first solution [grp][d][i] (offset, symbol and subcarrier strides)
+  int eoff, ed, eg;  // refinement: residual of the data symbols [grp][d][b]
+  int total;         // cf size of the whole LDS buffer
+};
+
+// acc -= a * b
+__device__ __forceinline__ void csub_mul_rows(cf& acc, cf a, cf b) {
+  acc.r = __builtin_fmaf(-a.r, b.r, __builtin_fmaf(a.i, b.i, acc.r));
+  acc.i = __builtin_fmaf(-a.r, b.i, __builtin_fmaf(-a.i, b.r, acc.i));
+}
+
+// L L^H v = v for every data symbol (v[d], lane i of the group holding
+// component i): lane i holds row i of L in registers (L[m] = L_im) and
+// 1/L_ii in invd; Lg holds the rows of the group's L (row stride lrow) for
+// the transposed reads of the back substitution.
+template <int LPS>
+__device__ __forceinline__ void row_solve(cf (&v)[kMaxD], const cf (&L)[LPS], float invd, const cf* Lg, int lrow, int i,
+                                          int gbase, int nue, int nd) {
+  // forward substitution L z = v, column-oriented
+#pragma unroll
+  for (int m = 0; m < LPS; ++m) {
+    if (m >= nue) continue;
+#pragma unroll
+    for (int d = 0; d < kMaxD; ++d) {
+      if (d >= nd) continue;
+      const float zr = lane_bcast(v[d].r * invd, (gbase + m) << 2);
+      const float zi = lane_bcast(v[d].i * invd, (gbase + m) << 2);
+      if (i == m) {
+        v[d] = cf{zr, zi};
+      } else if (i > m) {
+        v[d].r -= L[m].r * zr - L[m].i * zi;
+        v[d].i -= L[m].r * zi + L[m].i * zr;
+      }
+    }
+  }
+  // back substitution L^H x = z: x_m = (z_m - sum_{n>m} conj(L_nm) x_n) / L_mm
+#pragma unroll
+  for (int m = LPS - 1; m >= 0; --m) {
+    if (m >= nue) continue;
+    const cf lmi = Lg[m * lrow + i];
+#pragma unroll
+    for (int d = 0; d < kMaxD; ++d) {
+      if (d >= nd) continue;
+      const float xr = lane_bcast(v[d].r * invd, (gbase + m) << 2);
+      const float xi = lane_bcast(v[d].i * invd, (gbase + m) << 2);
+      if (i == m) {
+        v[d] = cf{xr, xi};
+      } else if (i < m) {
+        v[d].r -= lmi.r * xr + lmi.i * xi;  // conj(L_mi) * x_m
+        v[d].i -= lmi.r * xi - lmi.i * xr;
+      }
+    }
+  }
+}
+
+// REFINE: one step of iterative refinement (g.refine), a separate instance so
+// the plain path keeps its registers.
+template <int LPS, bool REFINE>
+__global__ __launch_bounds__(64, 2) void k_mmse_rows(const cf* __restrict__ H, const cf* __restrict__ Y, cf* __restrict__ Xh,
+                                             int* __restrict__ st, MmseGeom g, LdsGeom lg, long long nblk,
+                                             int nblk_batch) {
+  extern __shared__ cf sm[];
+  constexpr int SPW = 64 / LPS;
+  static_assert(LPS == 32, "two UE blocks of 16 per subcarrier");
+  const int lane = threadIdx.x;
+  const int grp = lane / LPS, i = lane % LPS, gbase = grp * LPS;
+  const int q = lane >> 4, c16 = lane & 15;  // MFMA operand row / column inside a 16x16 block
+  const int nb = g.n_beams, nue = g.n_ue, nsc = g.n_sc, nd = g.n_data;
+  const bool vec = (nb & 1) == 0;
+  const int ksteps = ((nb + 7) >> 3) << 1;  // k-steps of 4 beams, in pairs (a lane loads two adjacent beams)
+  cf* Ls = sm;
+  const int irow = i < nue ? i : nue - 1;
+
+  for (long long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const long long bi = blk / nblk_batch;
+    const int k0 = (int)(blk - bi * nblk_batch) * SPW;
+    const int cnt = min(SPW, nsc - k0);
+    const int k = k0 + grp;
+    const bool valid = grp < cnt;
+
+    // ---- Gram matrix and matched filter of each subcarrier on MFMA
+    // (16x16x4 FP32, three real products per complex step as in the <= 16-UE
+    // kernel): blocks G00, G10, G11 of the lower triangle (UE blocks of 16)
+    // and P0, P1 (UE block x data symbol), then to LDS.
+    __syncthreads();
+    for (int sc = 0; sc < cnt; ++sc) {
+      const cf* Hb = H + bi * g.h_batch + (long long)(k0 + sc) * nue * nb;
+      const cf* hrow0 = Hb + (long long)(c16 < nue ? c16 : 0) * nb;
+      const cf* hrow1 = Hb + (long long)(16 + c16 < nue ? 16 + c16 : 0) * nb;
+      const cf* yrow = Y + bi * g.y_batch + data_grid(g, c16 < nd ? c16 : 0) + (long long)(k0 + sc) * nb;
+      f32x4 acc[15];
+#pragma unroll
+      for (int t = 0; t < 15; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+      // conj(a) b as T1 = ar br, T2 = ai bi, T3 = (ar - ai)(br + bi)
+      auto prod = [&](int t, cf a, cf b) {
+        acc[t] = mfma(a.r, b.r, acc[t]);
+        acc[t + 1] = mfma(a.i, b.i, acc[t + 1]);
+        acc[t + 2] = mfma(a.r - a.i, b.r + b.i, acc[t + 2]);
+      };
+      for (int s = 0; s < ksteps; s += 2) {
+        cf h0[2], h1[2], y[2];
+        load_pair(h0[0], h0[1], hrow0, frag_beam(s, q), nb, c16 < nue, vec);
+        load_pair(h1[0], h1[1], hrow1, frag_beam(s, q), nb, 16 + c16 < nue, vec);
+        load_pair(y[0], y[1], yrow, frag_beam(s, q), nb, c16 < nd, vec);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          prod(0, h0[u], h0[u]);   // G00
+          prod(3, h1[u], h0[u]);   // G10
+          prod(6, h1[u], h1[u]);   // G11
+          prod(9, h0[u], y[u]);    // P0
+          prod(12, h1[u], y[u]);   // P1
+        }
+      }
+      // lane holds rows 4q..4q+3 of column c16 of every block
+      cf* Gp = sm + sc * lg.gt;
+      cf* Pp = sm + lg.poff + sc * lg.pg;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 4 * q + v;
+        auto val = [&](int t) {
+          return cf{acc[t][v] + acc[t + 1][v], acc[t + 2][v] - acc[t][v] + acc[t + 1][v]};
+        };
+        if (c16 <= r) Gp[tri(r) + c16] = val(0);
+        Gp[tri(16 + r) + c16] = val(3);
+        if (c16 <= r) Gp[tri(16 + r) + 16 + c16] = val(6);
+        Pp[r * lg.prow + c16] = val(9);
+        Pp[(16 + r) * lg.prow + c16] = val(12);
+      }
+    }
+    __syncthreads();
+
+    // Gram row i (lower part; sigma^2 on the diagonal) and matched filter
+    // outputs of this lane's subcarrier
+    const float s2 = g.sigma2_item ? g.sigma2_item[bi] : g.sigma2;
+    cf G[LPS];
+    {
+      const cf* Gr = sm + grp * lg.gt + tri(i);
+#pragma unroll
+      for (int j = 0; j < LPS; ++j) G[j] = j <= i ? Gr[j] : cf{0.f, 0.f};
+    }
+#pragma unroll
+    for (int j = 0; j < LPS; ++j)
+      if (j == i) G[j].r += s2;
+    cf rr[kMaxD];
+    {
+      const cf* Pr = sm + lg.poff + grp * lg.pg + i * lg.prow;
+#pragma unroll
+      for (int d = 0; d < kMaxD; ++d) rr[d] = (d < nd && i < nue) ? Pr[d] : cf{0.f, 0.f};
+    }
+
+    // Cholesky-Crout: column j uses row j of L (lane j of the group)
+    int fail = 0;
+    float invd = 0.f;
+    cf L[LPS];
+#pragma unroll
+    for (int j = 0; j < LPS; ++j) L[j] = G[j];
+#pragma unroll
+    for (int j = 0; j < LPS; ++j) {
+      if (j >= nue) continue;
+      cf t = L[j];
+#pragma unroll
+      for (int m = 0; m < j; ++m) {
+        const float cr = lane_bcast(L[m].r, (gbase + j) << 2);
+        const float ci = lane_bcast(L[m].i, (gbase + j) << 2);
+        t.r -= L[m].r * cr + L[m].i * ci;  // L_im * conj(L_jm)
+        t.i -= L[m].i * cr - L[m].r * ci;
+      }
+      const float dpiv = lane_bcast(t.r, (gbase + j) << 2);
+      fail |= (dpiv > 0.f && dpiv <= 3.402823466e38f) ? 0 : 1;
+      const float ljj = sqrtf(dpiv);
+      const float inv = 1.0f / ljj;
+      const cf lij = cf{t.r * inv, t.i * inv};
+      L[j] = i == j ? cf{ljj, 0.f} : (i > j ? lij : cf{0.f, 0.f});
+      invd = i == j ? inv : invd;
+    }
+
+    // rows of L to LDS (reusing the G and P space) for the transposed reads
+    // of the back substitution
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < LPS; ++m) Ls[grp * lg.lgrp + i * lg.lrow + m] = L[m];
+    __syncthreads();
+
+    row_solve<LPS>(rr, L, invd, Ls + grp * lg.lgrp, lg.lrow, i, gbase, nue, nd);
+
+    if constexpr (REFINE) {
+      // One step of iterative refinement.  The residual of the normal
+      // equations, r = H^H (y - H x0) - sigma^2 x0, is formed from the stored
+      // estimate and the data symbols themselves (not from the rounded G);
+      // L L^H dx = r with the same factor; x1 = x0 + dx.
+      cf* Xs = sm + lg.xoff + grp * lg.xg;
+      cf* Es = sm + lg.eoff + grp * lg.eg;
+      __syncthreads();
+#pragma unroll
+      for (int d = 0; d < kMaxD; ++d)
+        if (d < nd) Xs[d * lg.xd + i] = (i < nue) ? rr[d] : cf{0.f, 0.f};
+      __syncthreads();
+      const cf* Hk = H + bi * g.h_batch + (long long)(valid ? k : k0) * nue * nb;
+      // e_b = y_b - sum_j H_bj x0_j: lane t takes beams t, t + LPS, ...; kDCh
+      // symbols at a time, so each H_bj is loaded once per chunk
+      for (int b = i; b < nb; b += LPS)
+        for (int d0 = 0; d0 < nd; d0 += kDCh) {
+          cf e[kDCh];
+#pragma unroll
+          for (int dd = 0; dd < kDCh; ++dd)
+            e[dd] = (valid && d0 + dd < nd) ? Y[bi * g.y_batch + data_grid(g, d0 + dd) + (long long)k * nb + b]
+                                            : cf{0.f, 0.f};
+          for (int j = 0; j < nue; ++j) {
+            const cf h = Hk[j * nb + b];
+#pragma unroll
+            for (int dd = 0; dd < kDCh; ++dd) csub_mul_rows(e[dd], h, Xs[(d0 + dd) * lg.xd + j]);
+          }
+#pragma unroll
+          for (int dd = 0; dd < kDCh; ++dd)
+            if (d0 + dd < nd) Es[(d0 + dd) * lg.ed + b] = e[dd];
+        }
+      __syncthreads();
+      // r_i = sum_b conj(H_bi) e_b - sigma^2 x0_i
+      cf r[kMaxD];
+#pragma unroll
+      for (int d = 0; d < kMaxD; ++d) {
+        const cf x0 = d < nd ? Xs[d * lg.xd + i] : cf{0.f, 0.f};
+        r[d] = cf{-s2 * x0.r, -s2 * x0.i};
+      }
+      for (int b = 0; b < nb; ++b) {
+        const cf h = Hk[irow * nb + b];
+#pragma unroll
+        for (int d = 0; d < kMaxD; ++d) {
+          if (d >= nd) continue;
+          const cf e = Es[d * lg.ed + b];
+          r[d].r += h.r * e.r + h.i * e.i;
+          r[d].i += h.r * e.i - h.i * e.r;
+        }
+      }
+      row_solve<LPS>(r, L, invd, Ls + grp * lg.lgrp, lg.lrow, i, gbase, nue, nd);
+#pragma unroll
+      for (int d = 0; d < kMaxD; ++d) rr[d] = cf{rr[d].r + r[d].r, rr[d].i + r[d].i};
+    }
+
+    if (valid && i < nue) {
+      cf* dst = Xh + bi * g.x_batch + (long long)k * nue + i;
+#pragma unroll
+      for (int d = 0; d < kMaxD; ++d) {
+        if (d >= nd) continue;
+        dst[(long long)d * nsc * nue] = fail ? cf{0.f, 0.f} : rr[d];
+      }
+    }
+    if (valid && i == 0 && st) st[bi * g.st_batch + k] = fail ? 1 : 0;
+  }
+}
+
+LdsGeom lds_geom(int lps, int nb, bool refine) {
+  const int spw = 64 / lps;
+  LdsGeom lg;
+  lg.gt = lps * (lps + 1) / 2 + 1;
+  lg.prow = kMaxD + 1;
+  lg.pg = lps * lg.prow + 1;
+  lg.poff = spw * lg.gt;
+  lg.lrow = lps + 1;
+  lg.lgrp = lps * lg.lrow + 1;
+  const int gp = lg.poff + spw * lg.pg, l = spw * lg.lgrp;
+  lg.total = gp > l ? gp : l;
+  lg.xd = lps + 1;
+  lg.xg = kMaxD * lg.xd + 1;
+  lg.ed = nb | 1;
+  lg.eg = kMaxD * lg.ed + 1;
+  lg.xoff = lg.eoff = 0;
+  if (refine) {
+    lg.xoff = lg.total;
+    lg.eoff = lg.xoff + spw * lg.xg;
+    lg.total = lg.eoff + spw * lg.eg;
+  }
+  return lg;
+}
+
+template <int LPS>
+hipError_t launch_lps(const cf* H, const cf* Y, cf* Xh, int* st, const MmseGeom& g, long long batch, hipStream_t s) {
+  constexpr int SPW = 64 / LPS;
+  const LdsGeom lg = lds_geom(LPS, g.n_beams, g.refine != 0);
+  const int nblk_batch = (g.n_sc + SPW - 1) / SPW;
+  const long long nblk = batch * nblk_batch;
+  if (nblk <= 0) return hipSuccess;
+  long long blocks = nblk;
+  if (blocks > (1LL << 30)) blocks = 1LL << 30;
+  if (g.refine)
+    hipLaunchKernelGGL((k_mmse_rows<LPS, true>), dim3((unsigned)blocks), dim3(64), (size_t)lg.total * sizeof(cf), s, H,
+                       Y, Xh, st, g, lg, nblk, nblk_batch);
+  else
+    hipLaunchKernelGGL((k_mmse_rows<LPS, false>), dim3((unsigned)blocks), dim3(64), (size_t)lg.total * sizeof(cf), s,
+                       H, Y, Xh, st, g, lg, nblk, nblk_batch);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+
+// ---------------------------------------------------------------- MFMA path (n_ue <= 16)
+namespace {
 
 // FUSED: NT interpolation taps per (subcarrier, UE), 0 when H is read.
 template <int KS, bool FUSED, int NT>
