@@ -167,12 +167,6 @@ struct LdsGeom {
   int total;         // cf size of the whole LDS buffer
 };
 
-// acc -= a * b
-__device__ __forceinline__ void csub_mul_rows(cf& acc, cf a, cf b) {
-  acc.r = __builtin_fmaf(-a.r, b.r, __builtin_fmaf(a.i, b.i, acc.r));
-  acc.i = __builtin_fmaf(-a.r, b.i, __builtin_fmaf(-a.i, b.r, acc.i));
-}
-
 // L L^H v = v for every data symbol (v[d], lane i of the group holding
 // component i): lane i holds row i of L in registers (L[m] = L_im) and
 // 1/L_ii in invd; Lg holds the rows of the group's L (row stride lrow) for
@@ -351,49 +345,89 @@ __global__ __launch_bounds__(64, 2) void k_mmse_rows(const cf* __restrict__ H, c
       // One step of iterative refinement.  The residual of the normal
       // equations, r = H^H (y - H x0) - sigma^2 x0, is formed from the stored
       // estimate and the data symbols themselves (not from the rounded G);
-      // L L^H dx = r with the same factor; x1 = x0 + dx.
-      cf* Xs = sm + lg.xoff + grp * lg.xg;
-      cf* Es = sm + lg.eoff + grp * lg.eg;
+      // L L^H dx = r with the same factor; x1 = x0 + dx.  Both products run
+      // on MFMA per subcarrier: e = y - H x0 (beam blocks of 16 x the data
+      // symbols, UEs as K) and H^H e (as the matched filter, e for y).
       __syncthreads();
+      {
+        cf* Xg = sm + lg.xoff + grp * lg.xg;
 #pragma unroll
-      for (int d = 0; d < kMaxD; ++d)
-        if (d < nd) Xs[d * lg.xd + i] = (i < nue) ? rr[d] : cf{0.f, 0.f};
-      __syncthreads();
-      const cf* Hk = H + bi * g.h_batch + (long long)(valid ? k : k0) * nue * nb;
-      // e_b = y_b - sum_j H_bj x0_j: lane t takes beams t, t + LPS, ...; kDCh
-      // symbols at a time, so each H_bj is loaded once per chunk
-      for (int b = i; b < nb; b += LPS)
-        for (int d0 = 0; d0 < nd; d0 += kDCh) {
-          cf e[kDCh];
-#pragma unroll
-          for (int dd = 0; dd < kDCh; ++dd)
-            e[dd] = (valid && d0 + dd < nd) ? Y[bi * g.y_batch + data_grid(g, d0 + dd) + (long long)k * nb + b]
-                                            : cf{0.f, 0.f};
-          for (int j = 0; j < nue; ++j) {
-            const cf h = Hk[j * nb + b];
-#pragma unroll
-            for (int dd = 0; dd < kDCh; ++dd) csub_mul_rows(e[dd], h, Xs[(d0 + dd) * lg.xd + j]);
-          }
-#pragma unroll
-          for (int dd = 0; dd < kDCh; ++dd)
-            if (d0 + dd < nd) Es[(d0 + dd) * lg.ed + b] = e[dd];
-        }
-      __syncthreads();
-      // r_i = sum_b conj(H_bi) e_b - sigma^2 x0_i
-      cf r[kMaxD];
-#pragma unroll
-      for (int d = 0; d < kMaxD; ++d) {
-        const cf x0 = d < nd ? Xs[d * lg.xd + i] : cf{0.f, 0.f};
-        r[d] = cf{-s2 * x0.r, -s2 * x0.i};
+        for (int d = 0; d < kMaxD; ++d)
+          if (d < nd) Xg[d * lg.xd + i] = (i < nue) ? rr[d] : cf{0.f, 0.f};
       }
-      for (int b = 0; b < nb; ++b) {
-        const cf h = Hk[irow * nb + b];
+      __syncthreads();
+      for (int sc = 0; sc < cnt; ++sc) {
+        cf* Xsc = sm + lg.xoff + sc * lg.xg;  // x0 [d][UE]; then H^H e in its place
+        cf* Esc = sm + lg.eoff + sc * lg.eg;  // e [d][beam]
+        const cf* Hb = H + bi * g.h_batch + (long long)(k0 + sc) * nue * nb;
+        const cf* ysrc = Y + bi * g.y_batch + data_grid(g, c16 < nd ? c16 : 0) + (long long)(k0 + sc) * nb;
+        // e = y - H x0: A[m][k] = H[beam 16 bb + m][UE k], B[k][n] = x0[UE k][symbol n];
+        // a b as T1 = ar br, T2 = ai bi, T3 = (ar + ai)(br + bi)
+        for (int bb = 0; bb * 16 < nb; ++bb) {
+          f32x4 t1 = {0.f, 0.f, 0.f, 0.f}, t2 = t1, t3 = t1;
+          const int beam = 16 * bb + c16;
+          for (int s = 0; s < LPS / 4; ++s) {
+            const int ue = 4 * s + q;
+            const cf a = (ue < nue && beam < nb) ? Hb[(long long)ue * nb + beam] : cf{0.f, 0.f};
+            const cf x = Xsc[c16 * lg.xd + ue];
+            t1 = mfma(a.r, x.r, t1);
+            t2 = mfma(a.i, x.i, t2);
+            t3 = mfma(a.r + a.i, x.r + x.i, t3);
+          }
+          // lane holds rows (beams) 16 bb + 4q + v of column (symbol) c16
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int b = 16 * bb + 4 * q + v;
+            if (b < nb && c16 < nd) {
+              const cf y = ysrc[b];
+              Esc[c16 * lg.ed + b] = cf{y.r - (t1[v] - t2[v]), y.i - (t3[v] - t1[v] - t2[v])};
+            }
+          }
+        }
+        __syncthreads();
+        // H^H e: the matched filter's products with e from LDS
+        f32x4 acc[6];
+#pragma unroll
+        for (int t = 0; t < 6; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        auto prod = [&](int t, cf a, cf b) {
+          acc[t] = mfma(a.r, b.r, acc[t]);
+          acc[t + 1] = mfma(a.i, b.i, acc[t + 1]);
+          acc[t + 2] = mfma(a.r - a.i, b.r + b.i, acc[t + 2]);
+        };
+        const cf* hrow0 = Hb + (long long)(c16 < nue ? c16 : 0) * nb;
+        const cf* hrow1 = Hb + (long long)(16 + c16 < nue ? 16 + c16 : 0) * nb;
+        for (int s = 0; s < ksteps; s += 2) {
+          cf h0[2], h1[2], e[2];
+          const int fb = frag_beam(s, q);
+          load_pair(h0[0], h0[1], hrow0, fb, nb, c16 < nue, vec);
+          load_pair(h1[0], h1[1], hrow1, fb, nb, 16 + c16 < nue, vec);
+          e[0] = (c16 < nd && fb < nb) ? Esc[c16 * lg.ed + fb] : cf{0.f, 0.f};
+          e[1] = (c16 < nd && fb + 1 < nb) ? Esc[c16 * lg.ed + fb + 1] : cf{0.f, 0.f};
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            prod(0, h0[u], e[u]);
+            prod(3, h1[u], e[u]);
+          }
+        }
+        __syncthreads();  // H^H e goes into x0's space (read above)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 4 * q + v;
+          if (c16 < nd) {
+            Xsc[c16 * lg.xd + r] = cf{acc[0][v] + acc[1][v], acc[2][v] - acc[0][v] + acc[1][v]};
+            Xsc[c16 * lg.xd + 16 + r] = cf{acc[3][v] + acc[4][v], acc[5][v] - acc[3][v] + acc[4][v]};
+          }
+        }
+      }
+      __syncthreads();
+      // r_i = (H^H e)_i - sigma^2 x0_i (x0 is still in rr)
+      cf r[kMaxD];
+      {
+        const cf* Rg = sm + lg.xoff + grp * lg.xg;
 #pragma unroll
         for (int d = 0; d < kMaxD; ++d) {
-          if (d >= nd) continue;
-          const cf e = Es[d * lg.ed + b];
-          r[d].r += h.r * e.r + h.i * e.i;
-          r[d].i += h.r * e.i - h.i * e.r;
+          const cf he = (d < nd && i < nue) ? Rg[d * lg.xd + i] : cf{0.f, 0.f};
+          r[d] = cf{he.r - s2 * rr[d].r, he.i - s2 * rr[d].i};
         }
       }
       row_solve<LPS>(r, L, invd, Ls + grp * lg.lgrp, lg.lrow, i, gbase, nue, nd);
