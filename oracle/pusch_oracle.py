@@ -25,7 +25,12 @@ Readings of points the paper leaves open (each also stated where used):
       (status 1) and its detected symbols are set to 0;
   R17 noise estimation compares each pilot RE with the prediction from the
       UE's channel interpolated from its other pilot positions (leave one
-      out), normalised by the exact noise gain of that prediction.
+      out), normalised by the exact noise gain of that prediction;
+  R18 for a channel that varies over the slot, each pilot symbol gives its own
+      estimate (its own comb positions only), and data symbol s uses the
+      linear interpolation in s between the two pilot symbols around it
+      (held before the first and after the last); the MIMO stage then
+      factors one Gram matrix per data symbol, as the paper counts it.
 """
 from __future__ import annotations
 
@@ -38,6 +43,7 @@ __all__ = [
     "beamform",
     "pilot_owner",
     "ls_channel_estimate",
+    "time_interpolated_estimate",
     "noise_variance_estimate",
     "gram",
     "cholesky_crout",
@@ -91,7 +97,7 @@ def pilot_owner(n_sc: int, j: int, n_ue: int, n_pilot: int) -> np.ndarray:
     return (np.arange(n_sc) + j * (n_ue // n_pilot)) % n_ue
 
 
-def ls_channel_estimate(Yp, pilots, n_ue: int) -> np.ndarray:
+def ls_channel_estimate(Yp, pilots, n_ue: int, use=None) -> np.ndarray:
     """Least-squares channel estimation on block-type pilot symbols (Sec. II,
     CHE; Table 1, row "CHE": an element-wise division per beam and UE).
 
@@ -102,19 +108,21 @@ def ls_channel_estimate(Yp, pilots, n_ue: int) -> np.ndarray:
     interpolated along the subcarriers, holding the end values beyond the
     first and last pilot position.
 
-    Yp: [N_p, N_B, K] beam-domain pilot symbols; pilots: [N_p, K].
+    Yp: [N_p, N_B, K] beam-domain pilot symbols; pilots: [N_p, K]; use: the
+    pilot symbols (indices j) to take, all by default.
     Returns H_hat [K, N_B, N_L] (one N_B x N_L matrix per subcarrier, Eq. 1).
     """
     Yp = np.asarray(Yp, np.complex128)
     pilots = np.asarray(pilots, np.complex128)
     n_pilot, n_beams, K = Yp.shape
+    use = range(n_pilot) if use is None else list(use)
     if K < n_ue:
         raise ValueError("every UE needs at least one pilot subcarrier")
     H = np.zeros((K, n_beams, n_ue), dtype=np.complex128)
     grid = np.arange(K, dtype=np.float64)
     for l in range(n_ue):
         pos_list, val_list = [], []
-        for j in range(n_pilot):
+        for j in use:
             ks = np.nonzero(pilot_owner(K, j, n_ue, n_pilot) == l)[0]
             p = pilots[j, ks]
             pos_list.append(ks)
@@ -132,6 +140,28 @@ def ls_channel_estimate(Yp, pilots, n_ue: int) -> np.ndarray:
         for b in range(n_beams):
             H[:, b, l] = np.interp(grid, x, acc[b].real) + 1j * np.interp(grid, x, acc[b].imag)
     return H
+
+
+def time_interpolated_estimate(Yp, pilots, n_ue: int, pilot_symb, symb) -> np.ndarray:
+    """Channel estimate of OFDM symbol `symb` for a channel that changes over
+    the slot (reading R18): pilot symbol j alone gives H_j (ls_channel_estimate
+    with use=[j]); between the pilot symbols p_a < symb < p_b next to it the
+    estimate is ((p_b - symb) H_a + (symb - p_a) H_b) / (p_b - p_a), before the
+    first pilot symbol it is H_0 and after the last it is H_{N_p - 1}.
+
+    Yp: [N_p, N_B, K]; pilots: [N_p, K]; pilot_symb: the N_p ascending symbol
+    indices.  Returns [K, N_B, N_L].
+    """
+    ps = list(pilot_symb)
+    if symb <= ps[0]:
+        return ls_channel_estimate(Yp, pilots, n_ue, use=[0])
+    if symb >= ps[-1]:
+        return ls_channel_estimate(Yp, pilots, n_ue, use=[len(ps) - 1])
+    b = next(j for j, p in enumerate(ps) if p > symb)
+    a = b - 1
+    Ha = ls_channel_estimate(Yp, pilots, n_ue, use=[a])
+    Hb = ls_channel_estimate(Yp, pilots, n_ue, use=[b])
+    return ((ps[b] - symb) * Ha + (symb - ps[a]) * Hb) / (ps[b] - ps[a])
 
 
 def noise_variance_estimate(Yp, pilots, n_ue: int) -> float:
@@ -277,15 +307,18 @@ def mmse_detect(H, Yd, sigma2: float) -> tuple[np.ndarray, np.ndarray]:
 
 
 def receive_slot(x_td, pilots, pilot_symb, n_ue: int, n_sc: int, sigma2: float | None, W=None,
-                 n_beams: int | None = None) -> dict:
+                 n_beams: int | None = None, time_varying: bool = False) -> dict:
     """The whole receive chain of one slot (Sec. II), in the paper's order.
 
     x_td: [S, N_R, N] time-domain samples; pilots: [N_p, K]; pilot_symb: the
     0-based pilot symbol indices.  W defaults to the DFT beamformer with
     n_beams rows.  sigma2 None: the noise variance is estimated from the
     pilot symbols (noise_variance_estimate) and used in the MIMO stage.
+    time_varying: every data symbol gets its own estimate
+    (time_interpolated_estimate) and its own factorisation (reading R18).
     Returns a dict with the intermediates and the result: X [S, N_R, K],
-    Y [S, N_B, K], H [K, N_B, N_L], sigma2, x_hat [D, K, N_L], ok [K].
+    Y [S, N_B, K], H [K, N_B, N_L] (the merged static estimate), sigma2,
+    x_hat [D, K, N_L], ok [K] (with time_varying: ok for every data symbol).
     """
     x_td = np.asarray(x_td)
     S, n_ant, _ = x_td.shape
@@ -299,5 +332,14 @@ def receive_slot(x_td, pilots, pilot_symb, n_ue: int, n_sc: int, sigma2: float |
     if sigma2 is None:
         sigma2 = noise_variance_estimate(Y[pilot_symb], pilots, n_ue)
     Yd = np.swapaxes(Y[data_symb], -1, -2)  # [D, K, N_B]
-    x_hat, ok = mmse_detect(H, Yd, sigma2)
+    if not time_varying:
+        x_hat, ok = mmse_detect(H, Yd, sigma2)
+    else:
+        x_hat = np.zeros((len(data_symb), n_sc, n_ue), dtype=np.complex128)
+        ok = np.ones(n_sc, dtype=bool)
+        for d, s in enumerate(data_symb):
+            Hs = time_interpolated_estimate(Y[pilot_symb], pilots, n_ue, pilot_symb, s)
+            xs, oks = mmse_detect(Hs, Yd[d:d + 1], sigma2)
+            x_hat[d] = xs[0]
+            ok &= oks
     return {"X": X, "Y": Y, "H": H, "sigma2": sigma2, "x_hat": x_hat, "ok": ok}

@@ -64,6 +64,7 @@ class SlotConfig:
     tdl_rms_ns: float = 300.0
     tdl_taps: int = 8
     scs_hz: float = 30e3
+    doppler_hz: float = 0.0  # > 0: every tap of every (antenna, UE) pair turns at f_D cos(theta) over the slot
 
     @property
     def n_pilot(self) -> int:
@@ -161,7 +162,8 @@ def make_slot(cfg: SlotConfig, seed: int, sigma2: float | None = None) -> dict:
       pilots complex64 [n_pilot][n_sc]          pilot value on each pilot RE
       data   complex128 [n_data][n_ue][n_sc]    transmitted data symbols
       bits   uint8 [n_data][n_ue][n_sc][qam_bits]
-      h_ant  complex128 [n_sc][n_ant][n_ue]     antenna-domain channel
+      h_ant  complex128 [n_sc][n_ant][n_ue]     antenna-domain channel (at symbol 0 with Doppler;
+                                                [n_symb][n_sc][n_ant][n_ue] as h_ant_t)
       grid   complex128 [n_symb][n_ant][n_sc]   noiseless received frequency grid
       sigma2 float                              noise variance per RE
     """
@@ -177,15 +179,16 @@ def make_slot(cfg: SlotConfig, seed: int, sigma2: float | None = None) -> dict:
     pilots = qam_modulate(pbits, 2)
 
     if cfg.channel == "flat":
-        h_ant = np.broadcast_to(_cn(rng, (R, L), 1.0), (K, R, L)).copy()
+        taps = _cn(rng, (1, R, L), 1.0)
+        phase = np.ones((K, 1))
     elif cfg.channel == "tdl":
         p, tau = tdl_profile(cfg.tdl_taps, cfg.tdl_rms_ns * 1e-9)
         taps = _cn(rng, (cfg.tdl_taps, R, L), 1.0) * np.sqrt(p)[:, None, None]
         kappa = np.arange(K) - K // 2
         phase = np.exp(-2j * np.pi * np.outer(kappa * cfg.scs_hz, tau))  # [K][taps]
-        h_ant = np.tensordot(phase, taps, axes=(1, 0))  # [K][R][L]
     else:
         raise ValueError(f"unknown channel model {cfg.channel!r}")
+    h_ant = np.tensordot(phase, taps, axes=(1, 0))  # [K][R][L]
 
     # Transmitted frequency grid per UE: [n_symb][n_ue][n_sc]
     tx = np.zeros((cfg.n_symb, L, K), dtype=np.complex128)
@@ -195,8 +198,19 @@ def make_slot(cfg: SlotConfig, seed: int, sigma2: float | None = None) -> dict:
         owner = pilot_owner(K, j, L, cfg.n_pilot)
         tx[s, owner, np.arange(K)] = pilots[j]
 
-    # Received noiseless grid R[s][r][k] = sum_l H[k][r][l] X[s][l][k]
-    grid = np.einsum("krl,slk->srk", h_ant, tx, optimize=True)
+    # Time variation (drawn last, so slots without it keep their values): tap t
+    # of pair (r, l) turns by 2 pi f_D cos(theta) per second, one symbol lasting
+    # 1 / scs (no cyclic prefix)
+    if cfg.doppler_hz > 0:
+        theta = rng.uniform(0.0, 2.0 * np.pi, size=taps.shape)
+        sym = np.arange(cfg.n_symb)[:, None, None, None] / cfg.scs_hz
+        rot = np.exp(2j * np.pi * cfg.doppler_hz * np.cos(theta)[None] * sym)  # [S][taps][R][L]
+        h_t = np.einsum("kt,strl->skrl", phase, taps[None] * rot, optimize=True)
+    else:
+        h_t = np.broadcast_to(h_ant, (cfg.n_symb,) + h_ant.shape)
+
+    # Received noiseless grid R[s][r][k] = sum_l H_s[k][r][l] X[s][l][k]
+    grid = np.einsum("skrl,slk->srk", h_t, tx, optimize=True)
     full = np.zeros((cfg.n_symb, R, N), dtype=np.complex128)
     bins = (np.arange(K) - K // 2) % N
     full[:, :, bins] = grid
@@ -209,6 +223,7 @@ def make_slot(cfg: SlotConfig, seed: int, sigma2: float | None = None) -> dict:
         "data": data,
         "bits": bits,
         "h_ant": h_ant,
+        "h_ant_t": np.asarray(h_t),
         "grid": grid,
         "sigma2": s2,
     }

@@ -393,6 +393,61 @@ def test_noise_estimate_in_the_chain():
     assert r0["sigma2"] < 1e-10  # flat channel, no noise: only the input's FP32 rounding remains
 
 
+# ----------------------------------------------------------------------------- time-varying channel estimate
+
+def _linear_in_time(rng, K, n_ue, n_beams, pilot_symb):
+    """Pilot symbols through a channel flat in frequency and linear in time, h_l(s) = a_l + s b_l."""
+    n_pilot = len(pilot_symb)
+    a = crandn(n_beams, n_ue, rng=rng)
+    b = crandn(n_beams, n_ue, rng=rng)
+    p = np.exp(2j * np.pi * rng.uniform(size=(n_pilot, K))) * rng.uniform(0.5, 2.0, (n_pilot, K))
+    Y = np.zeros((n_pilot, n_beams, K), complex)
+    for j, s in enumerate(pilot_symb):
+        own = (np.arange(K) + j * (n_ue // n_pilot)) % n_ue
+        Y[j] = (a + s * b)[:, own] * p[j][None, :]
+    return Y, p, a, b
+
+
+@pytest.mark.parametrize("pilot_symb,n_ue", [((2, 11), 4), ((0, 4, 7, 11), 8), ((3, 9), 3)])
+def test_time_interpolation_is_exact_for_a_channel_linear_in_time(pilot_symb, n_ue):
+    Y, p, a, b = _linear_in_time(np.random.default_rng(len(pilot_symb)), 40, n_ue, 3, pilot_symb)
+    for s in range(14):
+        t = min(max(s, pilot_symb[0]), pilot_symb[-1])  # held outside the pilot symbols
+        H = O.time_interpolated_estimate(Y, p, n_ue, pilot_symb, s)
+        assert np.allclose(H, (a + t * b)[None], atol=1e-12), s
+
+
+def test_single_pilot_symbol_estimate_ignores_the_others():
+    Y, p, _, _ = _linear_in_time(np.random.default_rng(3), 32, 4, 2, (2, 11))
+    H0 = O.ls_channel_estimate(Y, p, 4, use=[0])
+    Y2 = Y.copy()
+    Y2[1] *= -7.0
+    assert np.array_equal(O.ls_channel_estimate(Y2, p, 4, use=[0]), H0)
+    assert not np.allclose(O.ls_channel_estimate(Y2, p, 4), O.ls_channel_estimate(Y, p, 4))
+
+
+def test_time_varying_chain_equals_static_chain_with_one_pilot_symbol():
+    cfg = synth.CFG1
+    s = synth.make_slot(cfg, 1000)
+    a = O.receive_slot(s["x_td"], s["pilots"], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, s["sigma2"], n_beams=cfg.n_beams)
+    b = O.receive_slot(s["x_td"], s["pilots"], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, s["sigma2"], n_beams=cfg.n_beams,
+                       time_varying=True)
+    assert np.allclose(a["x_hat"], b["x_hat"], atol=1e-12)
+
+
+def test_time_varying_receiver_tracks_doppler():
+    # 300 Hz over a slot of 14 symbols at 30 kHz: the per-symbol estimate must
+    # beat the static one that averages the two pilot symbols
+    cfg = synth.CFG1.replace(n_ant=16, n_fft=256, n_sc=240, n_beams=16, n_ue=4, pilot_symb=(2, 11), channel="flat",
+                             doppler_hz=300.0, snr_db=30.0)
+    s = synth.make_slot(cfg, 21)
+    data = np.swapaxes(s["data"], 1, 2)
+    st = O.receive_slot(s["x_td"], s["pilots"], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, s["sigma2"], n_beams=cfg.n_beams)
+    tv = O.receive_slot(s["x_td"], s["pilots"], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, s["sigma2"], n_beams=cfg.n_beams,
+                        time_varying=True)
+    assert M.evm_db(tv["x_hat"], data) < M.evm_db(st["x_hat"], data) - 3.0
+
+
 # ----------------------------------------------------------------------------- end to end
 
 def test_chain_noiseless_cfg1_recovers_bits_exactly():
@@ -442,6 +497,10 @@ def _pins_pass(mod, golden) -> bool:
         g = golden("mmse_2x2.txt")
         xm, _ = mod.mmse_detect(np.array(g["H"], complex)[None], np.array(g["y"], complex)[None, None], g["sigma2"])
         assert np.allclose(xm[0, 0], g["x"], atol=1e-12)
+        Yt, pt, at, bt = _linear_in_time(np.random.default_rng(9), 24, 3, 2, (2, 11))
+        for s_ in (0, 5, 13):
+            tt = min(max(s_, 2), 11)
+            assert np.allclose(mod.time_interpolated_estimate(Yt, pt, 3, (2, 11), s_), (at + tt * bt)[None], atol=1e-12)
         g = golden("ne_small.txt")
         for e in "ABC":
             assert abs(_ne_golden(mod, g, e) - g[e + "_sigma2"]) <= 1e-12
@@ -483,6 +542,11 @@ MUTATIONS = [
      "weights = {below: (k - below) / (above - below), above: (above - k) / (above - below)}"),
     ("gain = sum((w / cnt[m]) ** 2 * inv_pow[m]", "gain = sum((w / cnt[m]) * inv_pow[m]"),
     ("r = Yp[j][:, k] - pilots[j, k] * h", "r = Yp[j][:, k] - np.conj(pilots[j, k]) * h"),
+    # time-varying estimate: swapped time weights, the wrong end held after the last pilot symbol
+    ("return ((ps[b] - symb) * Ha + (symb - ps[a]) * Hb) / (ps[b] - ps[a])",
+     "return ((symb - ps[a]) * Ha + (ps[b] - symb) * Hb) / (ps[b] - ps[a])"),
+    ("return ls_channel_estimate(Yp, pilots, n_ue, use=[len(ps) - 1])",
+     "return ls_channel_estimate(Yp, pilots, n_ue, use=[0])"),
 ]
 
 
