@@ -12,8 +12,9 @@ per step and nothing else recorded in the timed region), the per-stage device
 time measured with HIP events that the library records on the launch stream
 around every stage in a second pass over the same steps, the roofline of the
 dominant kernel, the serial FP64 CPU oracle timed on a bounded sample of the
-same slots, and the same batch through the mixed-precision chain and through
-the chain with the noise variance estimated from the pilots.
+same slots, and the same batch through the mixed-precision chain, through
+the chain with the noise variance estimated from the pilots, and through the
+chain with a channel estimate per data symbol.
 """
 from __future__ import annotations
 
@@ -123,7 +124,7 @@ def _evm_db(xh, xt) -> float:  # 10 log10(sum |x_hat - x|^2 / sum |x|^2)
     return float(10.0 * np.log10(np.sum(np.abs(xh - xt) ** 2) / np.sum(np.abs(xt) ** 2)))
 
 
-def _run_variant(args, cfg, batch, x, p, x_hat32, precision: str, sigma2):
+def _run_variant(args, cfg, batch, x, p, x_hat32, precision: str, sigma2, time_varying: bool = False):
     """Time the 16-slot launch of one chain variant with the same protocol as
     the headline run; returns (ms per step, stage us per launch, x_hat, status, slot)."""
     import torch
@@ -132,7 +133,7 @@ def _run_variant(args, cfg, batch, x, p, x_hat32, precision: str, sigma2):
 
     dev = x.device
     slot = pusch.Slot(cfg.n_ant, cfg.n_fft, cfg.n_sc, cfg.n_symb, cfg.n_beams, cfg.n_ue, cfg.pilot_symb,
-                      sigma2, N_SLOT, device=dev, precision=precision)
+                      sigma2, N_SLOT, device=dev, precision=precision, time_varying=time_varying)
     xh = torch.empty_like(x_hat32)
     st = torch.empty(N_SLOT, cfg.n_sc, dtype=torch.int32, device=dev)
     for _ in range(args.warmup):
@@ -185,6 +186,31 @@ def bench_noise_est(args, cfg, batch, x, p, x_hat32, nd: int, ms32: float) -> di
             "stage_us_per_launch": stage_us,
             "evm_db_given": round(_evm_db(x_hat32[:nd].cpu().numpy(), data), 3),
             "evm_db_estimated": round(_evm_db(xh[:nd].cpu().numpy(), data), 3),
+            "status_flags": int(st.sum().item())}
+
+
+def bench_time_varying(args, cfg, batch, x, p, x_hat32, ms32: float) -> dict:
+    """The FP32 chain with a channel estimate and a factorisation per data
+    symbol (time_varying): time per step on the same batch, and the EVM of it
+    and of the static chain on two slots whose channel turns at 300 Hz."""
+    import torch
+
+    from paper_2210_09196_amd import pusch, synth
+
+    ms, stage_us, _, st, _ = _run_variant(args, cfg, batch, x, p, x_hat32, "fp32", batch["sigma2"], time_varying=True)
+    dcfg = cfg.replace(doppler_hz=300.0)
+    db = synth.make_batch(dcfg, [2100, 2101])
+    dx, dp = torch.from_numpy(db["x_td"]).to(x.device), torch.from_numpy(db["pilots"]).to(x.device)
+    data = db["data"].transpose(0, 1, 3, 2)
+    evm = {}
+    for tv in (False, True):
+        slot = pusch.Slot(cfg.n_ant, cfg.n_fft, cfg.n_sc, cfg.n_symb, cfg.n_beams, cfg.n_ue, cfg.pilot_symb,
+                          db["sigma2"], 2, device=x.device, time_varying=tv)
+        xh, _ = slot(dx, dp)
+        evm[tv] = _evm_db(xh.cpu().numpy(), data)
+    return {"value": round(N_SLOT / (ms / 1e3), 1), "unit": "slots/s", "us_per_slot": round(1e3 * ms / N_SLOT, 3),
+            "time_vs_static": round(ms / ms32, 3), "stage_us_per_launch": stage_us,
+            "doppler_hz": 300.0, "evm_db_static": round(evm[False], 3), "evm_db_time_varying": round(evm[True], 3),
             "status_flags": int(st.sum().item())}
 
 
@@ -389,6 +415,7 @@ def main() -> int:
     chain_bytes = sum(STAGE_BYTES.values()) * N_SLOT
     mixed = bench_mixed(args, cfg, batch, x, p, x_hat, nd, ms_per_step)
     noise = bench_noise_est(args, cfg, batch, x, p, x_hat, nd, ms_per_step)
+    timevar = bench_time_varying(args, cfg, batch, x, p, x_hat, ms_per_step)
     out = {
         "metric": "PUSCH slots/s & \u00b5s/slot, 64ant\u00d74096-FFT; FP32 vs mixed+batched, EVM gap \u22640.1dB",
         "value": round(N_SLOT / (ms_per_step / 1e3), 1),
@@ -418,6 +445,7 @@ def main() -> int:
         "status_flags": bad,
         "mixed": mixed,
         "noise_est": noise,
+        "time_varying": timevar,
     }
     if not args.no_cpu_baseline:
         print(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)", file=sys.stderr, flush=True)

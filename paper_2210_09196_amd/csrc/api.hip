@@ -106,28 +106,33 @@ int dft_beamformer(DeviceTables* t, int n_beams, int n_ant, const cf** out) {
 // Tables that depend on a slot geometry only, built once per geometry by
 // their kernels on the library's stream (waited for there, so the caller's
 // stream never waits on it) and kept until the process ends.
-enum GeomTable { kCombTaps = 0, kNoiseTable = 1 };
+enum GeomTable { kCombTaps = 0, kNoiseTable = 1, kTimeTaps = 2 };
 
-int geometry_table(DeviceTables* t, GeomTable kind, const pusch::ChestGeom& g, int n_tap, const void** out) {
+int geometry_table(DeviceTables* t, GeomTable kind, const pusch::ChestGeom& g, int n_tap, const void** out,
+                   const pusch::TimeTapGeom* tt = nullptr) {
   std::vector<long long> key = {kind, g.n_sc, g.n_ue, g.n_pilot};
-  if (kind == kCombTaps) {
+  if (kind != kNoiseTable) {
     key.push_back(g.n_beams);
     key.push_back(g.y_sym);
     key.push_back(n_tap);
     for (int j = 0; j < g.n_pilot; ++j) key.push_back(g.pilot_sym[j]);
   }
+  if (kind == kTimeTaps)
+    for (int d = 0; d < tt->n_data; ++d) key.push_back(tt->data_sym[d]);
   std::lock_guard<std::mutex> lock(t->mu);
   auto it = t->geom.find(key);
   if (it != t->geom.end()) {
     *out = it->second;
     return PUSCH_OK;
   }
-  const size_t bytes = kind == kCombTaps ? (size_t)g.n_sc * g.n_ue * n_tap * sizeof(int2)
-                                         : pusch::noise_table_bytes(g.n_pilot, g.n_sc);
+  const size_t bytes = kind == kCombTaps   ? (size_t)g.n_sc * g.n_ue * n_tap * sizeof(int2)
+                       : kind == kTimeTaps ? (size_t)tt->n_data * g.n_sc * g.n_ue * pusch::kTimeTaps * sizeof(int2)
+                                           : pusch::noise_table_bytes(g.n_pilot, g.n_sc);
   void* d = nullptr;
   if (hipMalloc(&d, bytes) != hipSuccess) return PUSCH_ENOMEM;
-  const hipError_t e = kind == kCombTaps ? pusch::launch_comb_taps(static_cast<int2*>(d), g, n_tap, t->build)
-                                         : pusch::launch_noise_table(static_cast<int4*>(d), g, t->build);
+  const hipError_t e = kind == kCombTaps   ? pusch::launch_comb_taps(static_cast<int2*>(d), g, n_tap, t->build)
+                       : kind == kTimeTaps ? pusch::launch_time_taps(static_cast<int2*>(d), g, *tt, t->build)
+                                           : pusch::launch_noise_table(static_cast<int4*>(d), g, t->build);
   if (e != hipSuccess || hipStreamSynchronize(t->build) != hipSuccess) {
     (void)hipFree(d);
     return PUSCH_EHIP;
@@ -409,6 +414,9 @@ int check_slot_call(const pusch_slot_desc* d, long long n_slot, const pusch_c32*
   if (n_slot < 0 || !x_td || !x_hat || !ws) return PUSCH_EINVAL;
   if (reinterpret_cast<uintptr_t>(ws) & 255) return PUSCH_EINVAL;
   if (mixed && !mixed_supported(d, n_slot)) return PUSCH_EUNSUPPORTED;
+  // per-symbol estimates: the detection kernel that interpolates the channel
+  // itself (up to 16 UEs, an even number of beams), without refinement
+  if (d->time_varying && !slot_fused(d)) return PUSCH_EUNSUPPORTED;
   const SlotLayout lay = slot_layout(d, n_slot, mixed);
   if (ws_bytes < lay.total) return PUSCH_ENOMEM;
   const int S = d->n_symb, R = d->n_ant, K = d->n_sc, B = d->n_beams, P = d->n_pilot;
@@ -457,8 +465,17 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   const int n_tap = pusch::comb_taps(L, P);
   const void* taps = nullptr;
   const void* ne_tab = nullptr;
-  if (fused)
+  pusch::TimeTapGeom tt{};
+  if (d->time_varying) {
+    for (int s_ = 0; s_ < S; ++s_) {
+      bool pilot = false;
+      for (int j = 0; j < P; ++j) pilot |= d->pilot_symb[j] == s_;
+      if (!pilot) tt.data_sym[tt.n_data++] = s_;
+    }
+    if (int rc = geometry_table(t, kTimeTaps, cg, pusch::kTimeTaps, &taps, &tt)) return rc;
+  } else if (fused) {
     if (int rc = geometry_table(t, kCombTaps, cg, n_tap, &taps)) return rc;
+  }
   if (d->noise_est)
     if (int rc = geometry_table(t, kNoiseTable, cg, 0, &ne_tab)) return rc;
 
@@ -525,11 +542,26 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   for (int j = 0; j < P; ++j) mg.skip[j] = d->pilot_symb[j];
   mg.x_batch = (long long)D * K * L;
   mg.st_batch = K;
-  const hipError_t me =
-      fused ? pusch::launch_mmse_fused(Y, static_cast<const int2*>(taps), n_tap, cg, reinterpret_cast<cf*>(x_hat),
-                                       status, mg, n_slot, s)
-            : pusch::launch_mmse(H, Y, reinterpret_cast<cf*>(x_hat), status, mg, n_slot, s);
-  if (me != hipSuccess) return PUSCH_EHIP;
+  if (d->time_varying) {
+    // one factorisation per data symbol (its own channel estimate); status
+    // flags ORed over the symbols
+    for (int dd = 0; dd < D; ++dd) {
+      pusch::MmseGeom md = mg;
+      md.n_data = 1;
+      md.d_first = dd;
+      md.st_or = dd > 0;
+      const int2* td = static_cast<const int2*>(taps) + (long long)dd * K * L * pusch::kTimeTaps;
+      if (pusch::launch_mmse_fused(Y, td, pusch::kTimeTaps, cg, reinterpret_cast<cf*>(x_hat) + (long long)dd * K * L,
+                                   status, md, n_slot, s) != hipSuccess)
+        return PUSCH_EHIP;
+    }
+  } else {
+    const hipError_t me =
+        fused ? pusch::launch_mmse_fused(Y, static_cast<const int2*>(taps), n_tap, cg, reinterpret_cast<cf*>(x_hat),
+                                         status, mg, n_slot, s)
+              : pusch::launch_mmse(H, Y, reinterpret_cast<cf*>(x_hat), status, mg, n_slot, s);
+    if (me != hipSuccess) return PUSCH_EHIP;
+  }
   if (!mark(4)) return PUSCH_EHIP;
   return PUSCH_OK;
 }

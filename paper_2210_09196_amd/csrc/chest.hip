@@ -58,7 +58,67 @@ __global__ __launch_bounds__(256) void k_comb_taps(int2* __restrict__ tab, Chest
   for (; t < ntap; ++t) dst[t] = make_int2(first, 0);
 }
 
+// Time-varying channel: taps of data symbol d (symbol index t.data_sym[d])
+// for (k, l), laid out tab[((d * n_sc + k) * n_ue + l) * 8 + t].  Between the
+// pilot symbols a < s < b around it the estimate is ((b - s) H_a + (s - a) H_b)
+// / (b - a), before the first pilot symbol H_0, after the last H_{n_pilot-1};
+// H_j is UE l's estimate from pilot symbol j alone: linear between the
+// nearest positions of its residue class on that symbol, held at the ends.
+__global__ __launch_bounds__(256) void k_time_taps(int2* __restrict__ tab, ChestGeom g, TimeTapGeom t) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= t.n_data * g.n_sc * g.n_ue) return;
+  const int l = idx % g.n_ue, k = (idx / g.n_ue) % g.n_sc, d = idx / (g.n_ue * g.n_sc);
+  const int s = t.data_sym[d];
+  // pilot symbols used and their time weights
+  // (pilot symbol indices taken by selects: no dynamically indexed argument)
+  auto psym = [&](int j) {
+    return j == 0 ? g.pilot_sym[0] : (j == 1 ? g.pilot_sym[1] : (j == 2 ? g.pilot_sym[2] : g.pilot_sym[3]));
+  };
+  int jb = g.n_pilot - 1;  // the first pilot symbol after s, or the last one
+#pragma unroll
+  for (int j = kMaxPilots - 1; j >= 0; --j)
+    if (j < g.n_pilot && psym(j) > s) jb = j;
+  int ja = jb;
+  float wb = 0.f;
+  if (s > psym(g.n_pilot - 1)) {
+    ja = jb = g.n_pilot - 1;  // after the last: hold
+  } else if (jb > 0) {
+    ja = jb - 1;  // between ja and jb
+    wb = (float)(s - psym(ja)) / (float)(psym(jb) - psym(ja));
+  }
+  const int step = g.n_ue / g.n_pilot;
+  const float inv = fast_rcp((float)g.n_ue);
+  int2* dst = tab + (long long)idx * 8;
+  int n = 0;
+  auto add = [&](int j, float wt) {
+    const int rj = fmod_pos(l - j * step, g.n_ue, inv);  // UE l's residue class on pilot symbol j
+    int lo = k - fmod_pos(k - rj, g.n_ue, inv);
+    int hi = k + fmod_pos(rj - k, g.n_ue, inv);
+    if (lo < 0) lo = hi;
+    if (hi >= g.n_sc) hi = lo;
+    const long long base = pilot_grid(g, j);
+    if (hi == lo) {
+      dst[n++] = make_int2((int)(base + (long long)lo * g.n_beams), __float_as_int(wt));
+    } else {
+      const float w = (float)(k - lo) / (float)(hi - lo);
+      dst[n++] = make_int2((int)(base + (long long)lo * g.n_beams), __float_as_int(wt * (1.f - w)));
+      dst[n++] = make_int2((int)(base + (long long)hi * g.n_beams), __float_as_int(wt * w));
+    }
+  };
+  add(ja, 1.f - wb);
+  if (jb != ja) add(jb, wb);
+  const int first = dst[0].x;
+  for (; n < 8; ++n) dst[n] = make_int2(first, 0);
+}
+
 }  // namespace
+
+hipError_t launch_time_taps(int2* tab, const ChestGeom& g, const TimeTapGeom& t, hipStream_t s) {
+  const long long n = (long long)t.n_data * g.n_sc * g.n_ue;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_time_taps, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, g, t);
+  return hipGetLastError();
+}
 
 int comb_taps(int n_ue, int n_pilot) {
   // pilot symbols j, j' put UE l's pilot on the same subcarriers when

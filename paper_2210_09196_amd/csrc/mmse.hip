@@ -33,7 +33,6 @@ namespace pusch {
 namespace {
 
 constexpr int kMaxD = 16;  // data symbols per kernel call (host splits larger requests)
-constexpr int kDCh = 4;    // data symbols staged in LDS at a time
 
 // ---- shared by both detection kernels: MFMA operands and cross-lane moves
 
@@ -227,7 +226,6 @@ __global__ __launch_bounds__(64, 2) void k_mmse_rows(const cf* __restrict__ H, c
   const bool vec = (nb & 1) == 0;
   const int ksteps = ((nb + 7) >> 3) << 1;  // k-steps of 4 beams, in pairs (a lane loads two adjacent beams)
   cf* Ls = sm;
-  const int irow = i < nue ? i : nue - 1;
 
   for (long long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
     const long long bi = blk / nblk_batch;
@@ -767,7 +765,10 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
       for (int r = 0; r < 16; ++r)
         if (r < nue) dst[r] = fail ? cf{0.f, 0.f} : z[r];
     }
-    if (k < nsc && d == 0 && st) st[bi * g.st_batch + k] = fail;
+    if (k < nsc && d == 0 && st) {
+      int* sp = st + bi * g.st_batch + k;
+      *sp = g.st_or ? (*sp | fail) : fail;
+    }
   }
 }
 

@@ -41,6 +41,7 @@ class SlotDesc(ctypes.Structure):
         ("noise_est", ctypes.c_int),
         ("sigma2_est", ctypes.c_void_p),
         ("refine", ctypes.c_int),
+        ("time_varying", ctypes.c_int),
     ]
 
 
@@ -233,11 +234,13 @@ class Slot:
     FP32 accumulation, FP32 estimation and detection).  sigma2=None estimates
     every slot's noise variance from its pilot symbols; each call leaves the
     estimates in self.sigma2_est ([n_slot] float32).  refine=True adds one
-    iterative-refinement step to the MIMO solve."""
+    iterative-refinement step to the MIMO solve.  time_varying=True gives
+    every data symbol its own channel estimate (interpolated in time between
+    the pilot symbols) and its own factorisation."""
 
     def __init__(self, n_ant: int, n_fft: int, n_sc: int, n_symb: int, n_beams: int, n_ue: int, pilot_symb,
                  sigma2: float | None, n_slot: int, W: torch.Tensor | None = None, device="cuda",
-                 precision: str = "fp32", refine: bool = False):
+                 precision: str = "fp32", refine: bool = False, time_varying: bool = False):
         if precision not in ("fp32", "mixed"):
             raise PuschError("precision is 'fp32' or 'mixed'")
         self.mixed = precision == "mixed"
@@ -252,6 +255,7 @@ class Slot:
             d.pilot_symb[j] = s
         self.sigma2_est = _noise_fields(d, sigma2, n_slot, device)
         d.refine = 1 if refine else 0
+        d.time_varying = 1 if time_varying else 0
         self.W = None if W is None else _c64(W, "W")
         d.W = _ptr(self.W)
         self.n_slot = n_slot
@@ -345,6 +349,7 @@ class Cells:
                 _fill_desc(self.descs[c], g["n_ant"], g["n_fft"], g["n_sc"], g["n_symb"], g["n_beams"], g["n_ue"],
                            g["pilot_symb"], g["sigma2"], W, int(g["n_slot"]), device))
             self.descs[c].refine = 1 if g.get("refine") else 0
+            self.descs[c].time_varying = 1 if g.get("time_varying") else 0
             self.n_slot[c] = int(g["n_slot"])
             self.geom.append(dict(g))
         nbytes = lib().pusch_cells_workspace_bytes(self.descs, n, self.n_slot, self.mixed)

@@ -193,6 +193,17 @@ def test_slot_noise_est_validation(lib):
     assert lib.pusch_slot(ctypes.byref(d), 0, FAKE, FAKE2, None, ws, need, None) == 0
 
 
+def test_slot_time_varying_needs_the_fused_detection(lib):
+    ws = ctypes.c_void_p(0x4000000000)
+    ok = _desc(time_varying=1)
+    need = lib.pusch_slot_workspace_bytes(ctypes.byref(ok), 2)
+    assert need == lib.pusch_slot_workspace_bytes(ctypes.byref(_desc()), 2)
+    assert lib.pusch_slot(ctypes.byref(ok), 0, FAKE, FAKE2, None, ws, need, None) == 0
+    for kw in (dict(n_beams=31), dict(n_ue=32, n_beams=64), dict(refine=1)):
+        d = _desc(time_varying=1, **kw)
+        assert lib.pusch_slot(ctypes.byref(d), 0, FAKE, FAKE2, None, ws, 1 << 40, None) == EUNSUP, kw
+
+
 def test_profile_arguments(lib):
     assert lib.pusch_profile_begin(0) == EINVAL
     assert lib.pusch_profile_end(None, 0) == EINVAL  # not active
