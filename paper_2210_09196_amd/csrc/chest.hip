@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_comb_taps(int2* __restrict__ tab, Chest
 }
 
 // Time-varying channel: taps of data symbol d (symbol index t.data_sym[d])
-// for (k, l), laid out tab[((d * n_sc + k) * n_ue + l) * 8 + t].  Between the
+// for (k, l), laid out tab[((d * n_sc + k) * n_ue + l) * kTimeTaps + t].  Between the
 // pilot symbols a < s < b around it the estimate is ((b - s) H_a + (s - a) H_b)
 // / (b - a), before the first pilot symbol H_0, after the last H_{n_pilot-1};
 // H_j is UE l's estimate from pilot symbol j alone: linear between the
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_time_taps(int2* __restrict__ tab, Chest
   }
   const int step = g.n_ue / g.n_pilot;
   const float inv = fast_rcp((float)g.n_ue);
-  int2* dst = tab + (long long)idx * 8;
+  int2* dst = tab + (long long)idx * kTimeTaps;
   int n = 0;
   auto add = [&](int j, float wt) {
     const int rj = fmod_pos(l - j * step, g.n_ue, inv);  // UE l's residue class on pilot symbol j
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void k_time_taps(int2* __restrict__ tab, Chest
   add(ja, 1.f - wb);
   if (jb != ja) add(jb, wb);
   const int first = dst[0].x;
-  for (; n < 8; ++n) dst[n] = make_int2(first, 0);
+  for (; n < kTimeTaps; ++n) dst[n] = make_int2(first, 0);
 }
 
 }  // namespace

@@ -88,8 +88,9 @@ hipError_t launch_chest(const cf* Y, const cf* pilots, cf* H, const ChestGeom& g
 // geometry only (n_sc, n_ue, n_pilot, n_beams, the pilot grid offsets).
 int comb_taps(int n_ue, int n_pilot);  // taps per (k, l) the geometry needs: 2 or 8
 hipError_t launch_comb_taps(int2* tab, const ChestGeom& g, int n_tap, hipStream_t s);
-// Time-varying channel: 8 taps per (data symbol, k, l) (up to four used),
-// tab[((d * n_sc + k) * n_ue + l) * 8 + t]: UE l's estimate from each of the
+// Time-varying channel: 4 taps per (data symbol, k, l) (two frequency
+// neighbours on each of two pilot symbols; unused taps weight 0),
+// tab[((d * n_sc + k) * n_ue + l) * kTimeTaps + t]: UE l's estimate from each of the
 // two pilot symbols around data symbol d (from that symbol's own positions),
 // weighted linearly in time; held before the first and after the last pilot
 // symbol.  data_sym: the symbol index of each data symbol.
@@ -97,7 +98,7 @@ struct TimeTapGeom {
   int data_sym[kMaxSymbols];
   int n_data;
 };
-constexpr int kTimeTaps = 8;
+constexpr int kTimeTaps = 4;
 hipError_t launch_time_taps(int2* tab, const ChestGeom& g, const TimeTapGeom& t, hipStream_t s);
 
 // ---------------------------------------------------------------- noise estimation

@@ -625,7 +625,7 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
           // that are never read, beams past n_beams meet zero columns of H.
           const cf* LSb = Y + bi * cg.y_batch;
           const cf* yrow = Y + bi * g.y_batch + ysym + (long long)k * nb;
-          constexpr int CH = NT <= 2 ? 4 : 1;
+          constexpr int CH = NT <= 2 ? 4 : (NT <= 4 ? 2 : 1);
 #pragma unroll
           for (int c0 = 0; c0 < KS / 2; c0 += CH) {
             float4 lv[CH][NT], yv[CH];
@@ -815,6 +815,7 @@ hipError_t launch_mmse_fused(const cf* Y, const int2* taps, int n_tap, const Che
                              const MmseGeom& g, long long batch, hipStream_t s) {
   if (g.n_data > kMaxD || g.n_data < 1 || !mmse_fusable(g.n_ue, g.n_beams, cg.y_batch)) return hipErrorInvalidValue;
   if (n_tap == 2) return dispatch_mfma<true, 2>(nullptr, Y, taps, cg, Xhat, status, g, batch, s);
+  if (n_tap == 4) return dispatch_mfma<true, 4>(nullptr, Y, taps, cg, Xhat, status, g, batch, s);
   if (n_tap == 2 * kMaxPilots) return dispatch_mfma<true, 2 * kMaxPilots>(nullptr, Y, taps, cg, Xhat, status, g, batch, s);
   return hipErrorInvalidValue;
 }
