@@ -290,6 +290,24 @@ def test_slot_cfg2_full_batch_sampled():
     assert np.array_equal(xh[0], xh[2]) and np.array_equal(xh[1], xh[15])
 
 
+def test_slot_cfg2_64_slots_sampled():
+    # four times the throughput launch (1.9 GB of time-domain input): every
+    # slot against the oracle's result for the distinct slot it repeats, and
+    # the status of every subcarrier
+    cfg = synth.CFG2
+    s0, s1 = synth.make_slot(cfg, 2004), synth.make_slot(cfg, 2005)
+    xs = np.stack([s0["x_td"], s1["x_td"]] * 32)
+    ps = np.stack([s0["pilots"], s1["pilots"]] * 32)
+    print("[parity] 64 paper-scale slots in one call", flush=True)
+    xh, st = run_slot(cfg, {"x_td": xs, "pilots": ps, "sigma2": s0["sigma2"]})
+    del xs
+    assert np.all(st == 0)
+    refs = [oracle_slot(cfg, s0)["x_hat"], oracle_slot(cfg, s1)["x_hat"]]
+    for i in (0, 1, 31, 32, 62, 63):
+        assert M.nrmse(xh[i], refs[i % 2]) <= TOL_X, i
+    assert all(np.array_equal(xh[i], xh[i % 2]) for i in range(64))
+
+
 @pytest.mark.parametrize("geom", [
     dict(n_ant=16, n_fft=1024, n_sc=825, n_beams=8, n_ue=4, pilot_symb=(0,), qam_bits=2, channel="tdl"),
     dict(n_ant=32, n_fft=2048, n_sc=1650, n_beams=16, n_ue=8, pilot_symb=(0, 4, 7, 11), qam_bits=8, channel="tdl"),
