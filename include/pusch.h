@@ -188,15 +188,17 @@ typedef struct {
   int refine;                       /* nonzero: one step of iterative refinement of the MIMO solve
                                        (residual H^H (y - H x) - sigma2 x from the channel estimate
                                        and the data symbols, solved with the same Cholesky factor);
-                                       for ill-conditioned Gram matrices (n_ue close to n_beams).
+                                       for ill-conditioned Gram matrices (n_ue close to n_beams), where
+                                       the 32-bit arithmetic of Sec. VI alone loses accuracy.
                                        Uses a stored channel estimate (larger workspace) */
   int time_varying;                 /* nonzero: a channel that changes over the slot -- each pilot
                                        symbol gives its own estimate (from its own comb positions),
                                        data symbol s uses their linear interpolation in s between the
                                        pilot symbols around it (held before the first and after the
                                        last), and the MIMO stage factors one Gram matrix per data
-                                       symbol.  Needs n_ue <= 16, an even n_beams and no refine
-                                       (PUSCH_EUNSUPPORTED otherwise) */
+                                       symbol (the paper counts the Cholesky decomposition per data
+                                       symbol, Sec. II).  Needs n_ue <= 16, an even n_beams and no
+                                       refine (PUSCH_EUNSUPPORTED otherwise) */
 } pusch_slot_desc;
 
 /* Bytes of device workspace pusch_slot needs for n_slot slots (0 on bad input). */
