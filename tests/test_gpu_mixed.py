@@ -93,3 +93,22 @@ def test_mixed_small_geometries():
             ref = O.receive_slot(b["x_td"][k], b["pilots"][k], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
                                  n_beams=cfg.n_beams)
             assert M.nrmse(got[k], ref["x_hat"]) <= TOL_MIXED, geom
+
+
+@pytest.mark.parametrize("snr_db", [10.0, 20.0, 30.0])
+def test_mixed_square_beamformer_64x64(snr_db):
+    # the precision form's main point: as many beams as antennas (the square
+    # 64-point DFT), 16 UEs, paper-scale grid; EVM gap and parity as above
+    cfg = synth.CFG2.replace(n_beams=64, snr_db=snr_db)
+    b = synth.make_batch(cfg, [3400, 3401])
+    x32, st32 = run(cfg, b, "fp32")
+    x16, st16 = run(cfg, b, "mixed")
+    assert np.all(st32 == 0) and np.all(st16 == 0)
+    data = b["data"].transpose(0, 1, 3, 2)
+    gap = M.evm_db(x16, data) - M.evm_db(x32, data)
+    print(f"[mixed] 64x64 at {snr_db} dB: EVM FP32 {M.evm_db(x32, data):.3f} dB, gap {gap:.4f} dB", flush=True)
+    assert abs(gap) <= EVM_GAP_DB
+    ref = O.receive_slot(b["x_td"][0], b["pilots"][0], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
+                         n_beams=cfg.n_beams)
+    assert M.nrmse(x32[0], ref["x_hat"]) <= 1e-4
+    assert M.nrmse(x16[0], ref["x_hat"]) <= TOL_MIXED
