@@ -156,3 +156,45 @@ def test_cells_graph_replay_with_noise_estimation_and_mixed_precision():
                 assert torch.equal(cells.sigma2_est[c], ref_est[c]), (precision, r, c)
             cells(xs, ps)  # eager work between replays
             torch.cuda.synchronize()
+
+
+def test_cells_graph_replay_with_refinement_and_time_varying_cells():
+    # a plain cell, a refined cell (row kernel, stored estimate) and a
+    # time-varying cell (one detection launch per data symbol, flags ORed)
+    # with estimated noise, captured into one graph and replayed
+    cfgs, batches, geoms = make_cells([CELLS[0], CELLS[2], CELLS[1]], seed0=1500)
+    geoms[1]["refine"] = True
+    geoms[2]["time_varying"] = True
+    geoms[2]["sigma2"] = None
+    cells = pusch.Cells(geoms)
+    xs = [dev(b["x_td"]) for b in batches]
+    ps = [dev(b["pilots"]) for b in batches]
+    ref, ref_st = cells(xs, ps)
+    torch.cuda.synchronize()
+    for c, (cfg, b, g) in enumerate(zip(cfgs, batches, geoms)):
+        s2 = b["sigma2"] if g["sigma2"] is not None else None
+        for k in range(g["n_slot"]):
+            o = O.receive_slot(b["x_td"][k], b["pilots"][k], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, s2,
+                               n_beams=cfg.n_beams, time_varying=bool(g.get("time_varying")))
+            assert M.nrmse(host(ref[c])[k], o["x_hat"]) <= TOL_X, (c, k)
+    out, out_st = cells.outputs()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        cells(xs, ps, out, out_st)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        cells(xs, ps, out, out_st)
+    for r in range(3):
+        for t in out:
+            t.zero_()
+        for t in out_st:
+            t.fill_(-1)
+        g.replay()
+        torch.cuda.synchronize()
+        for c in range(len(geoms)):
+            assert torch.equal(out[c], ref[c]) and torch.equal(out_st[c], ref_st[c]), (r, c)
+        cells(xs, ps)
+        torch.cuda.synchronize()
