@@ -543,17 +543,26 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   mg.x_batch = (long long)D * K * L;
   mg.st_batch = K;
   if (d->time_varying) {
-    // one factorisation per data symbol (its own channel estimate); status
-    // flags ORed over the symbols
-    for (int dd = 0; dd < D; ++dd) {
+    // one factorisation per data symbol (its own channel estimate); the data
+    // symbols before the first pilot symbol share one estimate, and so do
+    // those after the last, so each such run is one launch; status flags
+    // ORed over the launches
+    const int first = d->pilot_symb[0], last = d->pilot_symb[P - 1];
+    auto side = [&](int sym) { return sym < first ? -1 : (sym > last ? 1 : 0); };
+    for (int dd = 0; dd < D;) {
+      int n = 1;
+      const int sd = side(tt.data_sym[dd]);
+      if (sd != 0)
+        while (dd + n < D && side(tt.data_sym[dd + n]) == sd) ++n;
       pusch::MmseGeom md = mg;
-      md.n_data = 1;
+      md.n_data = n;
       md.d_first = dd;
       md.st_or = dd > 0;
       const int2* td = static_cast<const int2*>(taps) + (long long)dd * K * L * pusch::kTimeTaps;
       if (pusch::launch_mmse_fused(Y, td, pusch::kTimeTaps, cg, reinterpret_cast<cf*>(x_hat) + (long long)dd * K * L,
                                    status, md, n_slot, s) != hipSuccess)
         return PUSCH_EHIP;
+      dd += n;
     }
   } else {
     const hipError_t me =
