@@ -60,12 +60,12 @@ typedef struct {
 enum {
   PUSCH_OK = 0,
   PUSCH_EINVAL = -1,       /* bad argument (null pointer, size out of range, overlap) */
-  PUSCH_EUNSUPPORTED = -2, /* valid request outside what this build implements */
+  PUSCH_EUNSUPPORTED = -2, /* valid request outside what this library implements */
   PUSCH_EHIP = -3,         /* HIP runtime / launch failure */
   PUSCH_ENOMEM = -4        /* workspace too small, or device table allocation failed */
 };
 
-/* Limits of this build. */
+/* Limits of this library. */
 #define PUSCH_MAX_BEAMS 64
 #define PUSCH_MAX_UES 32
 #define PUSCH_MAX_PILOTS 4
