@@ -133,6 +133,8 @@ struct Shape<4096> {
 
 __host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
 
+typedef float v2f __attribute__((ext_vector_type(2)));  // one complex value, for the non-temporal builtins
+
 constexpr int kThreads = 256;
 
 // FP16 output (H16): each transform's output row is stored as half2 words
@@ -183,7 +185,10 @@ __global__ __launch_bounds__(kThreads) void k_fft(const cf* __restrict__ x, cf* 
   // workgroup's next transform is loaded during the current one's passes (a
   // transform past the batch re-reads the last one and is never stored).
   // With FP32 output the traffic is already at the bandwidth limit and the
-  // registers are kept for occupancy.
+  // registers are kept for occupancy.  Its time samples (read once) and its
+  // output rows go through the caches as non-temporal accesses: measured on
+  // the paper-scale slot, the FFT then takes ~4 us longer and the
+  // beamforming that reads its output ~10 us less.
   const long long fstep = (long long)gridDim.x * FPB;
   cf vn[H16 ? 16 : 1];
   auto prefetch = [&](long long f) {
@@ -201,9 +206,12 @@ __global__ __launch_bounds__(kThreads) void k_fft(const cf* __restrict__ x, cf* 
       for (int m = 0; m < 16; ++m) v[m] = act ? vn[m] : cf{0.f, 0.f};
       prefetch(fft + fstep);
     } else if (act) {
-      const cf* src = x + fft * N;
+      const v2f* src = reinterpret_cast<const v2f*>(x + fft * N);
 #pragma unroll
-      for (int m = 0; m < 16; ++m) v[m] = src[t + m * T];
+      for (int m = 0; m < 16; ++m) {
+        const v2f q = __builtin_nontemporal_load(src + t + m * T);
+        v[m] = cf{q.x, q.y};
+      }
     } else {
 #pragma unroll
       for (int m = 0; m < 16; ++m) v[m] = cf{0.f, 0.f};
@@ -280,7 +288,7 @@ __global__ __launch_bounds__(kThreads) void k_fft(const cf* __restrict__ x, cf* 
           for (int r = 0; r < 16; ++r) {
             int k = t + r * T + shift;
             if (k >= N) k -= N;
-            if (k < out_len) dst[k] = v[r];
+            if (k < out_len) __builtin_nontemporal_store(v2f{v[r].r, v[r].i}, reinterpret_cast<v2f*>(dst + k));
           }
         }
       }
