@@ -116,6 +116,28 @@ def _c64(t: torch.Tensor, name: str) -> torch.Tensor:
     return t
 
 
+def _sized(t, n: int, dtype, name: str) -> torch.Tensor:
+    """An output buffer the library writes n elements of dtype into: a contiguous device tensor of exactly n."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise PuschError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise PuschError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise PuschError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise PuschError(f"{name} must hold {n} elements, got {t.numel()}")
+    return t
+
+
+def _status(status, n_items: int, n_sc: int, device, name: str = "status"):
+    """status=True: a new [n_items, n_sc] int32 tensor; False/None: no flags; else a caller tensor of that size."""
+    if status is True:
+        return torch.empty(n_items, n_sc, dtype=torch.int32, device=device)
+    if status is False or status is None:
+        return None
+    return _sized(status, n_items * n_sc, torch.int32, name)
+
+
 def _ptr(t) -> int | None:
     return None if t is None else t.data_ptr()
 
@@ -155,7 +177,7 @@ def beamform(X: torch.Tensor, n_beams: int, W: torch.Tensor | None = None, n_re:
             raise PuschError("beamform: W must be [n_beams, n_ant]")
     if out is None:
         out = torch.empty(batch, n_re, n_beams, dtype=torch.complex64, device=X.device)
-    _c64(out, "out")
+    _sized(out, batch * n_re * n_beams, torch.complex64, "out")
     if batch == 0 or n_re == 0:
         return out
     _check(lib().pusch_beamform(_ptr(W), X.data_ptr(), out.data_ptr(), n_beams, n_ant, n_re, ld_x, batch, _stream()),
@@ -173,7 +195,7 @@ def chest(Yp: torch.Tensor, pilots: torch.Tensor, n_ue: int, out: torch.Tensor |
         raise PuschError("chest: pilots must be [batch, n_pilot, n_sc]")
     if out is None:
         out = torch.empty(batch, n_sc, n_ue, n_beams, dtype=torch.complex64, device=Yp.device)
-    _c64(out, "out")
+    _sized(out, batch * n_sc * n_ue * n_beams, torch.complex64, "out")
     if batch == 0:
         return out
     _check(lib().pusch_chest(Yp.data_ptr(), pilots.data_ptr(), out.data_ptr(), n_beams, n_ue, n_sc, n_pilot, batch,
@@ -191,8 +213,7 @@ def noise_est(Yp: torch.Tensor, pilots: torch.Tensor, n_ue: int, out: torch.Tens
         raise PuschError("noise_est: pilots must be [batch, n_pilot, n_sc]")
     if out is None:
         out = torch.empty(batch, dtype=torch.float32, device=Yp.device)
-    if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() < batch:
-        raise PuschError("noise_est: out must be a contiguous float32 tensor of batch elements")
+    _sized(out, batch, torch.float32, "out")
     if batch == 0:
         return out
     nbytes = int(lib().pusch_noise_est_workspace_bytes(batch))
@@ -214,11 +235,8 @@ def mmse_solve(H: torch.Tensor, Yd: torch.Tensor, sigma2: float, out: torch.Tens
     n_data = Yd.shape[1]
     if out is None:
         out = torch.empty(batch, n_data, n_sc, n_ue, dtype=torch.complex64, device=H.device)
-    _c64(out, "out")
-    if status is True:
-        status = torch.empty(batch, n_sc, dtype=torch.int32, device=H.device)
-    elif status is False:
-        status = None
+    _sized(out, batch * n_data * n_sc * n_ue, torch.complex64, "out")
+    status = _status(status, batch, n_sc, H.device)
     if batch == 0 or n_sc == 0:
         return out, status
     _check(lib().pusch_mmse_solve(H.data_ptr(), Yd.data_ptr(), float(sigma2), out.data_ptr(), n_beams, n_ue, n_sc,
@@ -278,11 +296,8 @@ class Slot:
             raise PuschError(f"pilots must be [{self.n_slot}, {d.n_pilot}, {d.n_sc}]")
         if x_hat is None:
             x_hat = torch.empty(self.n_slot, self.n_data, d.n_sc, d.n_ue, dtype=torch.complex64, device=x_td.device)
-        _c64(x_hat, "x_hat")
-        if status is True:
-            status = torch.empty(self.n_slot, d.n_sc, dtype=torch.int32, device=x_td.device)
-        elif status is False:
-            status = None
+        _sized(x_hat, self.n_slot * self.n_data * d.n_sc * d.n_ue, torch.complex64, "x_hat")
+        status = _status(status, self.n_slot, d.n_sc, x_td.device)
         if self.n_slot == 0:
             return x_hat, status
         d.pilots = pilots.data_ptr()
@@ -373,6 +388,8 @@ class Cells:
             raise PuschError(f"{self.n} x_td and pilots tensors expected")
         if x_hats is None:
             x_hats, statuses = self.outputs(x_tds[0].device)
+        if len(x_hats) != self.n or (statuses is not None and len(statuses) != self.n):
+            raise PuschError(f"{self.n} x_hat (and status) tensors expected")
         for c in range(self.n):
             d = self.descs[c]
             _c64(x_tds[c], "x_td")
@@ -385,6 +402,8 @@ class Cells:
                 raise PuschError(f"cell {c}: pilots must be [{ns}, {d.n_pilot}, {d.n_sc}]")
             if tuple(x_hats[c].shape) != (ns, d.n_symb - d.n_pilot, d.n_sc, d.n_ue):
                 raise PuschError(f"cell {c}: x_hat has the wrong shape")
+            if statuses is not None and statuses[c] is not None:
+                _sized(statuses[c], ns * d.n_sc, torch.int32, f"cell {c}: status")
             d.pilots = pilots[c].data_ptr()
         xp = (_P * self.n)(*[t.data_ptr() for t in x_tds])
         op = (_P * self.n)(*[t.data_ptr() for t in x_hats])
