@@ -557,3 +557,118 @@ def test_pins_pass_on_the_oracle(golden):
 @pytest.mark.parametrize("old,new", MUTATIONS)
 def test_planted_mistake_is_caught(old, new, golden):
     assert not _pins_pass(_mutant(old, new), golden)
+
+
+# ----------------------------------------------------------------------------- scoring metrics (O7)
+#
+# The metrics decide pass or fail for every GPU parity test, so they are pinned
+# to values worked out by hand, not to their own formulas.
+
+QPSK_PTS = np.array([1 + 1j, 1 - 1j, -1 + 1j, -1 - 1j]) / math.sqrt(2.0)
+QPSK_LAB = np.array([[0, 0], [0, 1], [1, 0], [1, 1]], np.uint8)
+QAM16_ROW = np.array([-3, -1, 1, 3]) / math.sqrt(10.0)  # one rail of unit-energy 16-QAM
+QAM16_PTS = (QAM16_ROW[:, None] + 1j * QAM16_ROW[None, :]).ravel()
+
+
+def _metric_pins_pass(mm) -> bool:
+    """Hand-worked values of every metric; False if a module's metrics miss any."""
+    try:
+        # nrmse: ||a - ref|| / ||ref||
+        assert abs(mm.nrmse([1 + 1j], [1]) - 1.0) < 1e-15  # |i| / |1|
+        assert abs(mm.nrmse([1, 0], [0, 1]) - math.sqrt(2.0)) < 1e-15  # sqrt(1 + 1) / 1
+        assert abs(mm.nrmse([2, 0], [1, 0]) - 1.0) < 1e-15  # normalised by ||ref|| = 1, not ||a|| = 2
+        assert abs(mm.nrmse([3, 4j], [3, 4j]) - 0.0) < 1e-15
+        assert abs(mm.nrmse([3.3, 4.4j], [3, 4j]) - 0.1) < 1e-14  # a 10 % scale error
+        # max_rel_err: ref [3, 4i, 0, 0] has RMS sqrt(25 / 4) = 2.5; one error of 1 -> 0.4
+        assert abs(mm.max_rel_err([3, 4j, 0, 1], [3, 4j, 0, 0]) - 0.4) < 1e-15
+        assert abs(mm.max_rel_err([3, 4j, 0.5, 1j], [3, 4j, 0, 0]) - 0.4) < 1e-15  # the largest, not the sum
+        # worst_slice_err: rows [[1, 1], [1, 1]] (RMS 1); errors (0, 0.3) in row 0, (0.4, 0) in row 1
+        ref = np.ones((2, 2))
+        got = ref + np.array([[0.0, 0.3], [0.4j, 0.0]])
+        assert abs(mm.worst_slice_err(got, ref, 0) - math.sqrt(0.16 / 2)) < 1e-15  # row 1
+        assert abs(mm.worst_slice_err(got, ref, 1) - math.sqrt(0.16 / 2)) < 1e-15  # column 0
+        got = ref + np.array([[0.0, 0.3], [0.0, 0.0]])
+        assert abs(mm.worst_slice_err(got, ref, 0) - math.sqrt(0.09 / 2)) < 1e-15
+        assert abs(mm.worst_slice_err(got, 2 * ref, 0) - 0.5) < 1e-15  # row 1 misses by (1, 1): RMS 1 over RMS 2
+        # evm_db: a 10 % amplitude error is -20 dB (power ratio 0.01); an error as large as x is 0 dB
+        x = QPSK_PTS[[0, 1, 2, 3, 0, 2]]
+        assert abs(mm.evm_db(1.1 * x, x) - (-20.0)) < 1e-12
+        assert abs(mm.evm_db(0.9 * x, x) - (-20.0)) < 1e-12
+        assert abs(mm.evm_db(x + x * 1j, x) - 0.0) < 1e-12
+        assert abs(mm.evm_db(x[:2] + np.array([0.1, 0.0]), x[:2]) - 10 * math.log10(0.01 / 2)) < 1e-12
+        # hard_decide: nearest point; a tie at the origin goes to the lowest index
+        idx, bits = mm.hard_decide(np.array([0.6 + 0.8j, 0.6 - 0.1j, -0.2 + 0.05j, -1 - 3j, 0j]), QPSK_PTS, QPSK_LAB)
+        assert idx.tolist() == [0, 1, 2, 3, 0]
+        assert bits.tolist() == [[0, 0], [0, 1], [1, 0], [1, 1], [0, 0]]
+        # decision_margin (squared distances): on a point of unit-energy QPSK the second-nearest
+        # neighbour is sqrt(2) away -> 2; on a decision boundary -> 0
+        m = mm.decision_margin(np.array([QPSK_PTS[0], 0j, 0.5 + 0j, 0.3j]), QPSK_PTS)
+        assert np.allclose(m, [2.0, 0.0, 0.0, 0.0], atol=1e-15)
+        # 16-QAM with sqrt(10) normalisation: at (1 + i)/sqrt(10) the neighbours are 2/sqrt(10) away -> 0.4;
+        # moved 0.1/sqrt(10) towards (3 + i)/sqrt(10): 1.9^2 / 10 - 0.1^2 / 10 = 0.36
+        s10 = math.sqrt(10.0)
+        m = mm.decision_margin(np.array([(1 + 1j) / s10, (1.1 + 1j) / s10]), QAM16_PTS)
+        assert np.allclose(m, [0.4, 0.36], atol=1e-14)
+        # xhat_errors bundles the three parity figures over the subcarrier axis (-2)
+        ref = np.ones((3, 4, 2), complex)
+        got = ref.copy()
+        got[1, 2, 0] += 0.5
+        e = mm.xhat_errors(got, ref)
+        assert abs(e["nrmse"] - 0.5 / math.sqrt(24)) < 1e-15
+        assert abs(e["max_rel"] - 0.5) < 1e-15
+        assert abs(e["worst_sc"] - math.sqrt(0.25 / 6)) < 1e-15
+        return True
+    except AssertionError:
+        return False
+
+
+def test_metric_pins_pass():
+    assert _metric_pins_pass(M)
+
+
+def _metric_mutant(old: str, new: str) -> types.ModuleType:
+    src = open(M.__file__).read()
+    assert src.count(old) >= 1, old
+    mod = types.ModuleType("metrics_mutant")
+    exec(compile(src.replace(old, new, 1), "metrics_mutant", "exec"), mod.__dict__)
+    return mod
+
+
+METRIC_MUTATIONS = [
+    # nrmse: squared ratio; normalised by ||a||; mean instead of RMS over elements
+    ("return float(np.linalg.norm((a - ref).ravel()) / (den if den > 0 else 1.0))",
+     "return float((np.linalg.norm((a - ref).ravel()) / (den if den > 0 else 1.0)) ** 2)"),
+    ("den = np.linalg.norm(ref.ravel())", "den = np.linalg.norm(a.ravel())"),
+    ("return float(np.linalg.norm((a - ref).ravel()) / (den if den > 0 else 1.0))",
+     "return float(np.sum(np.abs(a - ref)) / (den if den > 0 else 1.0))"),
+    # max_rel_err: normalised by the largest reference magnitude, or by the norm
+    ("rms = np.sqrt(np.mean(np.abs(ref) ** 2)) if ref.size else 1.0",
+     "rms = np.max(np.abs(ref)) if ref.size else 1.0"),
+    ("rms = np.sqrt(np.mean(np.abs(ref) ** 2)) if ref.size else 1.0",
+     "rms = np.linalg.norm(ref.ravel()) if ref.size else 1.0"),
+    # worst_slice_err: pooled over the wrong axis; mean over slices instead of the worst
+    ("other = tuple(i for i in range(ref.ndim) if i != axis % ref.ndim)",
+     "other = tuple(i for i in range(ref.ndim) if i == axis % ref.ndim)"),
+    ("return float(np.max(per) / (rms if rms > 0 else 1.0))",
+     "return float(np.mean(per) / (rms if rms > 0 else 1.0))"),
+    # evm_db: 20 log10 of a power ratio; normalised by the estimate's power
+    ("return float(10.0 * np.log10(np.sum(np.abs(x_hat - x) ** 2) / np.sum(np.abs(x) ** 2)))",
+     "return float(20.0 * np.log10(np.sum(np.abs(x_hat - x) ** 2) / np.sum(np.abs(x) ** 2)))"),
+    ("return float(10.0 * np.log10(np.sum(np.abs(x_hat - x) ** 2) / np.sum(np.abs(x) ** 2)))",
+     "return float(10.0 * np.log10(np.sum(np.abs(x_hat - x) ** 2) / np.sum(np.abs(x_hat) ** 2)))"),
+    # hard_decide: farthest point; highest index wins a tie
+    ("idx = np.argmin(d, axis=-1)", "idx = np.argmax(d, axis=-1)"),
+    ("idx = np.argmin(d, axis=-1)", "idx = d.shape[-1] - 1 - np.argmin(d[..., ::-1], axis=-1)"),
+    # decision_margin: reversed order; plain distances; gap to the farthest point
+    ("return d[..., 1] - d[..., 0]", "return d[..., 0] - d[..., 1]"),
+    ("d = np.sort(np.abs(x_hat[..., None] - np.asarray(points)[None, :]) ** 2, axis=-1)",
+     "d = np.sort(np.abs(x_hat[..., None] - np.asarray(points)[None, :]), axis=-1)"),
+    ("return d[..., 1] - d[..., 0]", "return d[..., -1] - d[..., 0]"),
+    # xhat_errors: the subcarrier figure taken over the UE axis
+    ('"worst_sc": worst_slice_err(a, ref, sc_axis)}', '"worst_sc": worst_slice_err(a, ref, -1)}'),
+]
+
+
+@pytest.mark.parametrize("old,new", METRIC_MUTATIONS)
+def test_planted_metric_mistake_is_caught(old, new):
+    assert not _metric_pins_pass(_metric_mutant(old, new))
