@@ -11,8 +11,9 @@ Prints ONE JSON line with slots/s and us/slot (p50/p99 over steps, one event
 per step and nothing else recorded in the timed region), the per-stage device
 time measured with HIP events that the library records on the launch stream
 around every stage in a second pass over the same steps, the roofline of the
-dominant kernel, the serial FP64 CPU oracle timed on a bounded sample of the
-same slots, and the same batch through the mixed-precision chain, through
+dominant kernel (the HBM or the FP32 roof, whichever binds at the kernel's
+algorithmic intensity), the FP64 CPU oracle timed on a bounded sample of the
+same slots (serial, and on every host core of the GPU's share), and the same batch through the mixed-precision chain, through
 the chain with the noise variance estimated from the pilots, and through the
 chain with a channel estimate per data symbol.
 """
@@ -47,11 +48,18 @@ STAGE_BYTES = {
     "mmse": NP * K * B * 8 + D * K * B * 8 + D * K * L * 8 + K * 4,
 }
 # Nominal arithmetic per slot (8 flops per complex MAC, 5 N log2 N per FFT).
+# Detection counts the Hermitian half of the Gram matrix (B L (L + 1) / 2
+# complex MACs), N_L^3 / 3 for the Cholesky factor, the matched filter and the
+# two substitutions per data symbol; the fused stage also interpolates the
+# channel estimate (about 27 MFLOP per slot at this geometry).
+CHEST_FLOPS = 27_000_000
 STAGE_FLOPS = {
     "fft": S * R * 5 * N * 12,
     "beamform": 8 * S * K * R * B,
-    "mmse": 8 * K * (B * L * L + L ** 3 // 6 + D * (B * L + L * L)),
+    "mmse": 8 * K * (B * L * (L + 1) // 2 + L ** 3 // 3 + D * (B * L + L * L)) + CHEST_FLOPS,
 }
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 (vector and MFMA, dense)
+RIDGE = FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)  # flop/B where the two roofs meet
 SLOT_FLOOR_BYTES = S * R * N * 8 + D * K * L * 8 + K * 4  # time-domain input + detected symbols
 STAGE_KERNEL = {"fft": "k_fft<4096, false>", "beamform": "k_beamform_k<2, 16>", "mmse": "k_mmse_mfma<8, true, 2>"}
 STAGE_SOURCE = {"fft": "fft.hip", "beamform": "beamform.hip", "mmse": "mmse.hip"}
@@ -83,26 +91,75 @@ def _traffic(stage: str) -> float | None:
         return None
 
 
-def cpu_baseline(batch: dict, seconds: float) -> dict:
-    """The FP64 oracle, serial (one BLAS thread), over the batch's slots in turn (cycling) until
-    `seconds` have passed."""
+_CPU_BATCH = None  # the slot batch, inherited by the forked oracle workers
+
+
+def _oracle_worker(args) -> tuple[int, float]:
+    """One host core: the FP64 oracle with one BLAS thread over slots first, first + stride, ...
+    (cycling over the batch) until `seconds` have passed; returns (slots done, seconds)."""
+    first, stride, seconds = args
     from threadpoolctl import threadpool_limits
 
     from oracle import pusch_oracle
     from paper_2210_09196_amd import synth
 
-    cfg = synth.CFG2
+    cfg, batch = synth.CFG2, _CPU_BATCH
     done, t0 = 0, time.perf_counter()
     with threadpool_limits(limits=1):
         while time.perf_counter() - t0 < seconds:
-            i = done % N_SLOT
+            i = (first + stride * done) % N_SLOT
             pusch_oracle.receive_slot(batch["x_td"][i], batch["pilots"][i], cfg.pilot_symb, cfg.n_ue, cfg.n_sc,
                                       batch["sigma2"], n_beams=cfg.n_beams)
             done += 1
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "slots/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} slot evaluations of the same workload (the batch's {N_SLOT} slots in turn), "
-                      f"FP64 NumPy oracle, one thread, {dt:.1f} s"}
+    return done, time.perf_counter() - t0
+
+
+def _host_description() -> dict:
+    import platform
+
+    import numpy
+
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = "unknown"
+    try:
+        from threadpoolctl import threadpool_info
+
+        libs = [f"{i.get('internal_api')} {i.get('version')}" for i in threadpool_info() if i.get("user_api") == "blas"]
+        blas = ", ".join(libs) or blas
+    except Exception:
+        pass
+    return {"cpu_model": model, "numpy": numpy.__version__, "blas": blas}
+
+
+def cpu_baseline(batch: dict, seconds: float, max_cores: int) -> dict:
+    """The FP64 oracle on the host, as it stands, in two modes over the batch's slots (cycling):
+    serial (one process, one BLAS thread; the paper's single-core baseline) and all cores (one
+    forked process per core, one BLAS thread each, independent slots).  Must run before the
+    process touches the GPU (the workers are forked)."""
+    import multiprocessing as mp
+
+    global _CPU_BATCH
+    _CPU_BATCH = batch
+    done, dt = _oracle_worker((0, 1, seconds))
+    cores = max(1, min(max_cores, len(os.sched_getaffinity(0))))
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(c, cores, seconds) for c in range(cores)])
+    all_done = sum(r[0] for r in res)
+    all_dt = max(r[1] for r in res)
+    host = _host_description()
+    return {"value": all_done / all_dt, "unit": "slots/s", "cores": cores, "kind": "oracle",
+            "sample": f"{all_done} slot evaluations of the same workload (the batch's {N_SLOT} slots in turn) by "
+                      f"{cores} forked processes, one per core, one BLAS thread each, {all_dt:.1f} s",
+            "serial": {"value": done / dt, "unit": "slots/s", "cores": 1,
+                       "sample": f"{done} slot evaluations, one process, one BLAS thread, {dt:.1f} s"},
+            **host}
 
 
 def calibrate_copy() -> int:
@@ -116,7 +173,17 @@ def calibrate_copy() -> int:
     for _ in range(5):
         dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"calibrate_copy_bytes": n, "copies": 5}), flush=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    ev[0].record()
+    for i in range(5):
+        dst.copy_(src)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(5)]
+    gbs = [2 * n / (m / 1e3) / 1e9 for m in ms]  # read + write
+    print(json.dumps({"calibrate_copy_bytes": n, "copies": 10, "timed_copies_ms": [round(m, 4) for m in ms],
+                      "copy_GBs_read_plus_write": [round(g, 1) for g in gbs],
+                      "copy_hbm_frac": round(max(gbs) / HBM_PEAK_GBS, 4)}), flush=True)
     return 0
 
 
@@ -214,22 +281,6 @@ def bench_time_varying(args, cfg, batch, x, p, x_hat32, ms32: float) -> dict:
             "status_flags": int(st.sum().item())}
 
 
-def cells_geometries(n_cells: int, seed: int = 4000) -> list[dict]:
-    """Seeded draw of uneven cells: N in {1024, 2048, 4096} with N*3300/4096
-    active subcarriers, 16/32/64 antennas, beams = antennas / 2, 4..16 UEs,
-    pilots on symbols 2 and 11, one slot each."""
-    rng = np.random.default_rng(seed)
-    out = []
-    for _ in range(n_cells):
-        n_fft = int(rng.choice([1024, 2048, 4096]))
-        n_ant = int(rng.choice([16, 32, 64]))
-        n_beams = n_ant // 2
-        n_ue = int(rng.integers(4, min(16, n_beams) + 1))
-        out.append(dict(n_ant=n_ant, n_fft=n_fft, n_sc=n_fft * 3300 // 4096, n_symb=14, n_beams=n_beams, n_ue=n_ue,
-                        pilot_symb=(2, 11), sigma2=0.01, n_slot=1))
-    return out
-
-
 def bench_cells(n_cells: int, steps: int, warmup: int) -> int:
     """Batched uneven cells: one pusch_cells call over n_cells cells of
     different geometries, replayed from a captured HIP graph, against the same
@@ -238,7 +289,9 @@ def bench_cells(n_cells: int, steps: int, warmup: int) -> int:
 
     from paper_2210_09196_amd import pusch
 
-    geoms = cells_geometries(n_cells)
+    from paper_2210_09196_amd import synth
+
+    geoms = synth.uneven_cells(n_cells)
     g = torch.Generator(device="cuda")
     g.manual_seed(4001)
     xs, ps = [], []
@@ -316,7 +369,11 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--settle-s", type=float, default=2.0,
+                    help="warm-up lasts at least this many seconds of back-to-back steps")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="per CPU-baseline mode")
+    ap.add_argument("--cpu-cores", type=int, default=16,
+                    help="most host cores the all-cores CPU baseline uses (the GPU's share of the host)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--distinct-slots", type=int, default=N_SLOT,
                     help="generate this many distinct slots and repeat them to fill the 16-slot launch "
@@ -353,6 +410,13 @@ def main() -> int:
     if nd < N_SLOT:
         for key in ("x_td", "pilots"):
             batch[key] = np.ascontiguousarray(np.resize(batch[key], (N_SLOT,) + batch[key].shape[1:]))
+    cpu = None
+    if not args.no_cpu_baseline:  # before the GPU is touched: the all-cores mode forks workers
+        print(f"[bench] CPU oracle baseline (~{2 * args.cpu_seconds:.0f} s: serial, then all cores)",
+              file=sys.stderr, flush=True)
+        cpu = cpu_baseline(batch, args.cpu_seconds, args.cpu_cores)
+        print(f"[bench] CPU oracle: {cpu['serial']['value']:.2f} slots/s serial, {cpu['value']:.2f} slots/s on "
+              f"{cpu['cores']} cores", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     x = torch.from_numpy(batch["x_td"]).to(dev)
     p = torch.from_numpy(batch["pilots"]).to(dev)
@@ -361,10 +425,16 @@ def main() -> int:
     x_hat = torch.empty(N_SLOT, cfg.n_data, cfg.n_sc, cfg.n_ue, dtype=torch.complex64, device=dev)
     status = torch.empty(N_SLOT, cfg.n_sc, dtype=torch.int32, device=dev)
 
-    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        slot(x, p, x_hat, status)
-    torch.cuda.synchronize()
+    # warm-up: at least --warmup steps and at least --settle-s seconds of back-to-back steps, so
+    # that clocks and caches have settled before the timed region
+    print(f"[bench] warmup {args.warmup} steps / {args.settle_s} s", file=sys.stderr, flush=True)
+    t_settle, warm_steps = time.perf_counter(), 0
+    while warm_steps < args.warmup or time.perf_counter() - t_settle < args.settle_s:
+        for _ in range(4):
+            slot(x, p, x_hat, status)
+        warm_steps += 4
+        torch.cuda.synchronize()
+    settle_s = time.perf_counter() - t_settle
 
     # headline: the chain alone, one event per step and nothing recorded in between
     stream = torch.cuda.current_stream()
@@ -406,12 +476,25 @@ def main() -> int:
                         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                         "nominal_TFLOPs": round(STAGE_FLOPS[name] * N_SLOT / per_launch_s / 1e12, 2)}
     stages["chest"] = {"fused_into": "mmse", "us_per_launch": round(stage_ms["chest"] / calls * 1e3, 2)}
+    for name in STAGE_KERNEL:  # which roof binds at the kernel's algorithmic intensity
+        inten = STAGE_FLOPS[name] / STAGE_BYTES[name]
+        stages[name]["flop_per_byte"] = round(inten, 2)
+        stages[name]["bound"] = "mfma" if inten > RIDGE else "hbm"
+        stages[name]["fp32_frac"] = round(stages[name]["nominal_TFLOPs"] / FP32_PEAK_TFLOPS, 4)
     dom = max(STAGE_KERNEL, key=lambda k: stages[k]["us_per_launch"])
     traffic = _traffic(dom)
-    roofline = {"bound": "hbm", "achieved": stages[dom]["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": stages[dom]["hbm_frac"], "traffic": traffic, "kernel": stages[dom]["kernel"],
-                "alg_bytes_per_launch": stages[dom]["alg_bytes_per_launch"],
-                "us_per_launch": stages[dom]["us_per_launch"]}
+    st_dom = stages[dom]
+    if st_dom["bound"] == "mfma":
+        roofline = {"bound": "mfma", "achieved": st_dom["nominal_TFLOPs"], "peak": FP32_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": st_dom["fp32_frac"]}
+    else:
+        roofline = {"bound": "hbm", "achieved": st_dom["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": st_dom["hbm_frac"]}
+    roofline.update({"traffic": traffic, "kernel": st_dom["kernel"], "flop_per_byte": st_dom["flop_per_byte"],
+                     "ridge_flop_per_byte": round(RIDGE, 2),
+                     "alg_bytes_per_launch": st_dom["alg_bytes_per_launch"],
+                     "alg_flops_per_launch": STAGE_FLOPS[dom] * N_SLOT, "hbm_frac": st_dom["hbm_frac"],
+                     "us_per_launch": st_dom["us_per_launch"]})
     chain_bytes = sum(STAGE_BYTES.values()) * N_SLOT
     mixed = bench_mixed(args, cfg, batch, x, p, x_hat, nd, ms_per_step)
     noise = bench_noise_est(args, cfg, batch, x, p, x_hat, nd, ms_per_step)
@@ -423,6 +506,8 @@ def main() -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "warmup_steps_run": warm_steps,
+        "settle_s": round(settle_s, 2),
         "ms_per_step": round(ms_per_step, 4),
         "us_per_slot": round(1e3 * ms_per_step / N_SLOT, 3),
         "us_per_slot_p50": round(float(np.percentile(us_slot, 50)), 3),
@@ -441,15 +526,12 @@ def main() -> int:
         "slot_floor_frac": round(SLOT_FLOOR_BYTES * N_SLOT / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "stages": stages,
         "roofline": roofline,
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
         "status_flags": bad,
         "mixed": mixed,
         "noise_est": noise,
         "time_varying": timevar,
     }
-    if not args.no_cpu_baseline:
-        print(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
 

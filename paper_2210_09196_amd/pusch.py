@@ -138,6 +138,15 @@ def _status(status, n_items: int, n_sc: int, device, name: str = "status"):
     return _sized(status, n_items * n_sc, torch.int32, name)
 
 
+def _beamformer(W, n_beams: int, n_ant: int, name: str) -> torch.Tensor:
+    """A caller-supplied beamformer: the library reads n_beams * n_ant values from it, so its shape
+    must be exactly [n_beams, n_ant]."""
+    _c64(W, name)
+    if tuple(W.shape) != (n_beams, n_ant):
+        raise PuschError(f"{name} must be [{n_beams}, {n_ant}], got {list(W.shape)}")
+    return W
+
+
 def _ptr(t) -> int | None:
     return None if t is None else t.data_ptr()
 
@@ -274,7 +283,7 @@ class Slot:
         self.sigma2_est = _noise_fields(d, sigma2, n_slot, device)
         d.refine = 1 if refine else 0
         d.time_varying = 1 if time_varying else 0
-        self.W = None if W is None else _c64(W, "W")
+        self.W = None if W is None else _beamformer(W, n_beams, n_ant, "W")
         d.W = _ptr(self.W)
         self.n_slot = n_slot
         self.n_data = n_symb - len(pilot_symb)
@@ -358,7 +367,7 @@ class Cells:
             if int(g["n_slot"]) < 1:
                 raise PuschError("every cell needs n_slot >= 1")
             W = g.get("W")
-            W = None if W is None else _c64(W, "W")
+            W = None if W is None else _beamformer(W, g["n_beams"], g["n_ant"], f"cell {c}: W")
             self.W.append(W)
             self.sigma2_est.append(
                 _fill_desc(self.descs[c], g["n_ant"], g["n_fft"], g["n_sc"], g["n_symb"], g["n_beams"], g["n_ue"],

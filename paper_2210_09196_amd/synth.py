@@ -44,6 +44,7 @@ __all__ = [
     "tdl_profile",
     "make_slot",
     "make_batch",
+    "uneven_cells",
 ]
 
 
@@ -234,4 +235,20 @@ def make_batch(cfg: SlotConfig, seeds, sigma2: float | None = None, keep=("x_td"
     slots = [make_slot(cfg, int(s), sigma2) for s in seeds]
     out = {k: np.stack([sl[k] for sl in slots]) for k in keep}
     out["sigma2"] = slots[0]["sigma2"]
+    return out
+
+
+def uneven_cells(n_cells: int, seed: int = 4000) -> list[dict]:
+    """Seeded draw of uneven cells: FFT size in {1024, 2048, 4096} with
+    N * 3300 / 4096 active subcarriers, 16/32/64 antennas, beams = antennas / 2,
+    4..16 UEs, pilots on symbols 2 and 11, one slot each, sigma^2 = 0.01."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_cells):
+        n_fft = int(rng.choice([1024, 2048, 4096]))
+        n_ant = int(rng.choice([16, 32, 64]))
+        n_beams = n_ant // 2
+        n_ue = int(rng.integers(4, min(16, n_beams) + 1))
+        out.append(dict(n_ant=n_ant, n_fft=n_fft, n_sc=n_fft * 3300 // 4096, n_symb=14, n_beams=n_beams, n_ue=n_ue,
+                        pilot_symb=(2, 11), sigma2=0.01, n_slot=1))
     return out

@@ -63,3 +63,20 @@ def test_slot_and_cells_outputs_are_checked():
     with pytest.raises(pusch.PuschError, match="expected"):
         cells(xs, ps, outs[:1], sts[:1])
     torch.cuda.synchronize()
+
+
+def test_slot_and_cells_reject_a_beamformer_of_the_wrong_shape():
+    # the chain reads n_beams * n_ant values of W: a short one would be read past its end
+    cfg = synth.CFG1
+    for bad in (z(cfg.n_beams, cfg.n_ant - 1), z(cfg.n_beams - 1, cfg.n_ant), z(cfg.n_beams * cfg.n_ant)):
+        with pytest.raises(pusch.PuschError, match="W must be"):
+            pusch.Slot(cfg.n_ant, cfg.n_fft, cfg.n_sc, cfg.n_symb, cfg.n_beams, cfg.n_ue, cfg.pilot_symb, 0.01, 1,
+                       W=bad)
+        geom = dict(n_ant=cfg.n_ant, n_fft=cfg.n_fft, n_sc=cfg.n_sc, n_symb=cfg.n_symb, n_beams=cfg.n_beams,
+                    n_ue=cfg.n_ue, pilot_symb=cfg.pilot_symb, sigma2=0.01, n_slot=1)
+        with pytest.raises(pusch.PuschError, match="cell 1: W must be"):
+            pusch.Cells([geom, dict(geom, W=bad)])
+    ok = pusch.Slot(cfg.n_ant, cfg.n_fft, cfg.n_sc, cfg.n_symb, cfg.n_beams, cfg.n_ue, cfg.pilot_symb, 0.01, 1,
+                    W=z(cfg.n_beams, cfg.n_ant))
+    assert ok.W.shape == (cfg.n_beams, cfg.n_ant)
+    torch.cuda.synchronize()

@@ -15,6 +15,7 @@ import pytest
 import torch
 
 from oracle import metrics as M
+from checks import assert_xhat
 from oracle import pusch_oracle as O
 from paper_2210_09196_amd import pusch, synth
 
@@ -59,8 +60,8 @@ def test_mixed_evm_gap_and_oracle(snr_db):
         s = {key: b[key][k] for key in ("x_td", "pilots")}
         ref = O.receive_slot(s["x_td"], s["pilots"], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
                              n_beams=cfg.n_beams)
-        assert M.nrmse(x16[k], ref["x_hat"]) <= TOL_MIXED
-        assert M.nrmse(x32[k], ref["x_hat"]) <= 1e-4
+        assert_xhat(x16[k], ref["x_hat"], TOL_MIXED)
+        assert_xhat(x32[k], ref["x_hat"], 1e-4)
 
 
 @pytest.mark.parametrize("log2_scale", [40, -40])
@@ -77,7 +78,7 @@ def test_mixed_power_of_two_row_scaling_covers_any_range(log2_scale):
     assert M.nrmse(got, base) <= 1e-6
     ref = O.receive_slot(b["x_td"][0], b["pilots"][0], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
                          n_beams=cfg.n_beams)
-    assert M.nrmse(got[0], ref["x_hat"]) <= TOL_MIXED
+    assert_xhat(got[0], ref["x_hat"], TOL_MIXED)
 
 
 def test_mixed_small_geometries():
@@ -92,7 +93,7 @@ def test_mixed_small_geometries():
         for k in range(2):
             ref = O.receive_slot(b["x_td"][k], b["pilots"][k], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
                                  n_beams=cfg.n_beams)
-            assert M.nrmse(got[k], ref["x_hat"]) <= TOL_MIXED, geom
+            assert_xhat(got[k], ref["x_hat"], TOL_MIXED, geom)
 
 
 @pytest.mark.parametrize("snr_db", [10.0, 20.0, 30.0])
@@ -110,5 +111,5 @@ def test_mixed_square_beamformer_64x64(snr_db):
     assert abs(gap) <= EVM_GAP_DB
     ref = O.receive_slot(b["x_td"][0], b["pilots"][0], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
                          n_beams=cfg.n_beams)
-    assert M.nrmse(x32[0], ref["x_hat"]) <= 1e-4
-    assert M.nrmse(x16[0], ref["x_hat"]) <= TOL_MIXED
+    assert_xhat(x32[0], ref["x_hat"], 1e-4)
+    assert_xhat(x16[0], ref["x_hat"], TOL_MIXED)

@@ -16,6 +16,7 @@ import pytest
 import torch
 
 from oracle import metrics as M
+from checks import assert_xhat
 from oracle import pusch_oracle as O
 from paper_2210_09196_amd import pusch, synth
 
@@ -112,7 +113,7 @@ def test_slot_with_estimated_noise_matches_oracle(geom):
         s = synth.make_slot(cfg, seed)
         ref = O.receive_slot(s["x_td"], s["pilots"], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, None, n_beams=cfg.n_beams)
         assert abs(est[i] - ref["sigma2"]) <= TOL_NE_CHAIN * ref["sigma2"], (i, est[i], ref["sigma2"])
-        assert M.nrmse(xh[i], ref["x_hat"]) <= TOL_X
+        assert_xhat(xh[i], ref["x_hat"], TOL_X)
 
 
 def test_slot_paper_scale_estimated_noise_sampled():
@@ -127,7 +128,7 @@ def test_slot_paper_scale_estimated_noise_sampled():
     for i in range(16):
         r = refs[i % 2]
         assert abs(est[i] - r["sigma2"]) <= TOL_NE_CHAIN * r["sigma2"], (i, est[i], r["sigma2"])
-        assert M.nrmse(xh[i], r["x_hat"]) <= TOL_X, i
+        assert_xhat(xh[i], r["x_hat"], TOL_X, i)
     assert np.array_equal(est[0::2], np.full(8, est[0])) and np.array_equal(xh[1], xh[15])
     print(f"[ne] paper scale at 20 dB: sigma2 {s0['sigma2']:.4g}, estimates {est[0]:.4g} {est[1]:.4g}", flush=True)
 
