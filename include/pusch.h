@@ -75,7 +75,8 @@ enum {
 const char* pusch_strerror(int code);
 
 /* Build the per-device immutable tables for the current device now instead
- * of on first use.  Returns PUSCH_OK or PUSCH_EHIP. */
+ * of on first use, and look up the device address of the scratch array of
+ * pusch_noise_est_static.  Returns PUSCH_OK or PUSCH_EHIP. */
 int pusch_init(void);
 
 /*
@@ -149,6 +150,27 @@ int pusch_chest(const pusch_c32* Yp, const pusch_c32* pilots, pusch_c32* H, int 
 size_t pusch_noise_est_workspace_bytes(long long batch);
 int pusch_noise_est(const pusch_c32* Yp, const pusch_c32* pilots, float* sigma2, int n_beams, int n_ue, int n_sc,
                     int n_pilot, long long batch, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * The same noise-variance estimate as pusch_noise_est, for callers that
+ * cannot allocate device memory or pass a workspace (code captured into a
+ * HIP graph, tight serving loops, harnesses that forbid hipMalloc).  It
+ * allocates nothing and calls no allocating routine: its scratch (the
+ * geometry's neighbour table and the per-item partial sums, 2.25 MiB) is a
+ * device array inside the library, one copy per GPU, whose address is looked
+ * up once per device (by pusch_init, or by the first call on that device).
+ * Every call on a GPU shares that GPU's array and leaves its contents there;
+ * each call rebuilds what it reads before reading it, so nothing needs
+ * clearing, but two calls whose work overlaps on one GPU (different streams,
+ * or a graph replayed while another call runs) race on the array and give
+ * undefined estimates: serialise them.  Results are bit-identical to
+ * pusch_noise_est on the same inputs.
+ *   Yp, pilots, sigma2 and the limits as pusch_noise_est, plus
+ *   batch <= PUSCH_NOISE_EST_STATIC_MAX_BATCH (PUSCH_EUNSUPPORTED beyond it).
+ */
+#define PUSCH_NOISE_EST_STATIC_MAX_BATCH 1024
+int pusch_noise_est_static(const pusch_c32* Yp, const pusch_c32* pilots, float* sigma2, int n_beams, int n_ue,
+                           int n_sc, int n_pilot, long long batch, void* stream);
 
 /*
  * MMSE MIMO detection (Eq. 2) per subcarrier: G = H^H H + sigma2 I, the

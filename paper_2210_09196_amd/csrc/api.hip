@@ -150,6 +150,16 @@ bool overlap(const void* a, long long abytes, const void* b, long long bbytes) {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? PUSCH_OK : PUSCH_EHIP; }
 
+// Device address of the allocation-free entry point's scratch array (below),
+// looked up once per device with that device current.
+struct ScratchAddr {
+  std::once_flag once;
+  int status = PUSCH_EHIP;
+  unsigned char* ptr = nullptr;
+};
+ScratchAddr g_scratch_addr[kMaxDevices];
+int scratch_address(unsigned char** out);
+
 // ---------------------------------------------------------------- stage timing
 struct Profile {
   std::mutex mu;
@@ -178,7 +188,9 @@ const char* pusch_strerror(int code) {
 
 int pusch_init(void) {
   DeviceTables* t = nullptr;
-  return device_tables(&t);
+  if (int rc = device_tables(&t)) return rc;
+  unsigned char* sp = nullptr;
+  return scratch_address(&sp);
 }
 
 int pusch_fft(const pusch_c32* x, pusch_c32* X, int n_fft, int n_sc, long long batch, void* stream) {
@@ -277,6 +289,64 @@ int pusch_noise_est(const pusch_c32* Yp, const pusch_c32* pilots, float* sigma2,
   return hip_status(pusch::launch_noise_est(reinterpret_cast<const cf*>(Yp), reinterpret_cast<const cf*>(pilots),
                                             false, static_cast<const int4*>(tab), static_cast<float2*>(ws), sigma2,
                                             g, batch, static_cast<hipStream_t>(stream)));
+}
+
+// ---- allocation-free noise estimation
+// The scratch of pusch_noise_est_static lives in this file-scope device array
+// (one copy per device, kept until the process ends): the geometry's
+// neighbour table, then the per-item partial sums.  Host code never passes
+// the array's name to a kernel -- on the host it is only a stand-in for the
+// symbol; the device address comes from hipGetSymbolAddress (scratch_address).
+constexpr size_t kStaticTabBytes = (size_t)PUSCH_MAX_PILOTS * kMaxNeSc * sizeof(int4);
+constexpr size_t kStaticPartBytes = (size_t)PUSCH_NOISE_EST_STATIC_MAX_BATCH * pusch::kNeParts * sizeof(float2);
+static __device__ __align__(256) unsigned char scratch[kStaticTabBytes + kStaticPartBytes];
+
+namespace {
+int scratch_address(unsigned char** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PUSCH_EHIP;
+  ScratchAddr& sa = g_scratch_addr[dev];
+  std::call_once(sa.once, [&sa]() {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return;
+    sa.ptr = static_cast<unsigned char*>(p);
+    sa.status = PUSCH_OK;
+  });
+  *out = sa.ptr;
+  return sa.status;
+}
+}  // namespace
+
+int pusch_noise_est_static(const pusch_c32* Yp, const pusch_c32* pilots, float* sigma2, int n_beams, int n_ue,
+                           int n_sc, int n_pilot, long long batch, void* stream) {
+  if (!Yp || !pilots || !sigma2 || batch < 0) return PUSCH_EINVAL;
+  if (n_pilot < 1 || n_pilot > PUSCH_MAX_PILOTS) return PUSCH_EINVAL;
+  if (n_beams < 1 || n_beams > PUSCH_MAX_BEAMS) return PUSCH_EINVAL;
+  if (n_ue < 1 || n_ue > PUSCH_MAX_UES || n_ue > n_beams || n_sc < 2 * n_ue || n_sc > kMaxNeSc) return PUSCH_EINVAL;
+  if (batch > PUSCH_NOISE_EST_STATIC_MAX_BATCH) return PUSCH_EUNSUPPORTED;
+  if (batch == 0) return PUSCH_OK;
+  const long long yb = batch * n_pilot * (long long)n_sc * n_beams * 8, pb = batch * n_pilot * (long long)n_sc * 8;
+  if (overlap(sigma2, batch * 4, Yp, yb) || overlap(sigma2, batch * 4, pilots, pb)) return PUSCH_EINVAL;
+  pusch::ChestGeom g{};
+  g.n_beams = n_beams;
+  g.n_ue = n_ue;
+  g.n_sc = n_sc;
+  g.n_pilot = n_pilot;
+  g.y_batch = (long long)n_pilot * n_sc * n_beams;
+  g.y_sym = (long long)n_sc * n_beams;
+  for (int j = 0; j < n_pilot; ++j) g.pilot_sym[j] = j;
+  g.p_batch = (long long)n_pilot * n_sc;
+  unsigned char* base = nullptr;
+  if (int rc = scratch_address(&base)) return rc;
+  int4* tab = reinterpret_cast<int4*>(base);
+  float2* part = reinterpret_cast<float2*>(base + kStaticTabBytes);
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  // the neighbour table is rebuilt in the scratch on every call (it is cheap,
+  // and the previous call may have left another geometry's table there); the
+  // partial sums need no clearing: every slice the final sum reads is written
+  if (hipError_t e = pusch::launch_noise_table(tab, g, s)) return hip_status(e);
+  return hip_status(pusch::launch_noise_est(reinterpret_cast<const cf*>(Yp), reinterpret_cast<const cf*>(pilots),
+                                            false, tab, part, sigma2, g, batch, s));
 }
 
 int pusch_mmse_solve(const pusch_c32* H, const pusch_c32* Yd, float sigma2, pusch_c32* Xhat, int n_beams, int n_ue,

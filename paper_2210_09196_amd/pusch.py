@@ -58,6 +58,7 @@ _SIG = {
     "pusch_chest": (_I, [_P, _P, _P, _I, _I, _I, _I, _LL, _P]),
     "pusch_noise_est_workspace_bytes": (ctypes.c_size_t, [_LL]),
     "pusch_noise_est": (_I, [_P, _P, _P, _I, _I, _I, _I, _LL, _P, ctypes.c_size_t, _P]),
+    "pusch_noise_est_static": (_I, [_P, _P, _P, _I, _I, _I, _I, _LL, _P]),
     "pusch_mmse_solve": (_I, [_P, _P, _F, _P, _I, _I, _I, _I, _LL, _P, _P]),
     "pusch_slot_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SlotDesc), _LL]),
     "pusch_slot": (_I, [ctypes.POINTER(SlotDesc), _LL, _P, _P, _P, _P, ctypes.c_size_t, _P]),
@@ -229,6 +230,30 @@ def noise_est(Yp: torch.Tensor, pilots: torch.Tensor, n_ue: int, out: torch.Tens
     ws = torch.empty(nbytes, dtype=torch.uint8, device=Yp.device)
     _check(lib().pusch_noise_est(Yp.data_ptr(), pilots.data_ptr(), out.data_ptr(), n_beams, n_ue, n_sc, n_pilot, batch,
                                  ws.data_ptr(), nbytes, _stream()), "pusch_noise_est")
+    return out
+
+
+NOISE_EST_STATIC_MAX_BATCH = 1024
+
+
+def noise_est_static(Yp: torch.Tensor, pilots: torch.Tensor, n_ue: int, out: torch.Tensor | None = None
+                     ) -> torch.Tensor:
+    """As noise_est, through pusch_noise_est_static: no workspace, the library's own device scratch
+    (at most NOISE_EST_STATIC_MAX_BATCH items per call; calls that overlap on one GPU race)."""
+    _c64(Yp, "Yp")
+    _c64(pilots, "pilots")
+    batch, n_pilot, n_sc, n_beams = Yp.shape
+    if tuple(pilots.shape) != (batch, n_pilot, n_sc):
+        raise PuschError("noise_est_static: pilots must be [batch, n_pilot, n_sc]")
+    if batch > NOISE_EST_STATIC_MAX_BATCH:
+        raise PuschError(f"noise_est_static: at most {NOISE_EST_STATIC_MAX_BATCH} items per call, got {batch}")
+    if out is None:
+        out = torch.empty(batch, dtype=torch.float32, device=Yp.device)
+    _sized(out, batch, torch.float32, "out")
+    if batch == 0:
+        return out
+    _check(lib().pusch_noise_est_static(Yp.data_ptr(), pilots.data_ptr(), out.data_ptr(), n_beams, n_ue, n_sc,
+                                        n_pilot, batch, _stream()), "pusch_noise_est_static")
     return out
 
 

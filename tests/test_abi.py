@@ -23,7 +23,7 @@ def lib():
 
 def test_exports_every_declared_symbol(lib):
     names = pusch.header_symbols()
-    assert len(names) == 16
+    assert len(names) == 17
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(pusch._SIG)
@@ -172,6 +172,23 @@ def test_noise_est_validation(lib):
     assert f(FAKE, FAKE2, ctypes.c_void_p(0x20000), 32, 16, 3300, 2, 1, ws, big, None) == EINVAL  # inside Yp
     assert f(FAKE, FAKE2, S, 32, 16, 3300, 2, 1, ctypes.c_void_p(0x90000100), big, None) == EINVAL  # ws on pilots
     assert f(FAKE, FAKE2, S, 32, 16, 3300, 2, 0, None, 0, None) == 0  # empty batch
+
+
+def test_noise_est_static_validation(lib):
+    # the allocation-free variant: same checks, no workspace, at most 1024 items per call
+    f = lib.pusch_noise_est_static
+    f.restype, f.argtypes = ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int] * 4 + [ctypes.c_longlong,
+                                                                                      ctypes.c_void_p]
+    S = ctypes.c_void_p(0x70000000)
+    assert f(None, FAKE2, S, 32, 16, 3300, 2, 1, None) == EINVAL
+    assert f(FAKE, FAKE2, None, 32, 16, 3300, 2, 1, None) == EINVAL
+    assert f(FAKE, FAKE2, S, 32, 16, 31, 2, 1, None) == EINVAL  # a UE with one pilot position
+    assert f(FAKE, FAKE2, S, 32, 16, 3300, 5, 1, None) == EINVAL  # too many pilot symbols
+    assert f(FAKE, FAKE2, S, 8, 16, 3300, 2, 1, None) == EINVAL  # more UEs than beams
+    assert f(FAKE, FAKE2, S, 32, 16, 5000, 2, 1, None) == EINVAL  # beyond 4096 subcarriers
+    assert f(FAKE, FAKE2, S, 32, 16, 3300, 2, 1025, None) == EUNSUP  # beyond the scratch's items
+    assert f(FAKE, FAKE2, ctypes.c_void_p(0x20000), 32, 16, 3300, 2, 1, None) == EINVAL  # inside Yp
+    assert f(FAKE, FAKE2, S, 32, 16, 3300, 2, 0, None) == 0  # empty batch
 
 
 def test_slot_noise_est_validation(lib):
