@@ -27,16 +27,15 @@ Readings (where the paper gives no denoiser at all):
   R19 LS grid over all symbols: each symbol's estimate is the time
       interpolation of R18 between the per-pilot-symbol LS estimates (held
       outside), so with one pilot symbol it is the same on every symbol.
-  R20 fallback: the "post-MMSE pilot residual" of an estimator is measured on
-      held-out pilots.  Each UE's pilot positions on each pilot symbol are
-      split by their order along k into an even and an odd half; the
-      estimator sees one half, and at every pilot RE of the other half the
-      MMSE-equalised received vector (Eq. 2 with that estimate) is compared
-      with the known transmitted vector (the UE's pilot, zero for the other
-      UEs).  Both halves take a turn; the residual is the summed squared
-      error.  The chain keeps the denoised estimate unless its residual
-      exceeds the LS one.  (On the full comb the LS estimate passes through
-      every pilot RE, so a residual on seen pilots would always favour LS.)
+  R20 fallback: the "post-MMSE residual" of an estimate is measured on the
+      data REs: each data symbol is equalised with Eq. 2 using the estimate,
+      and |y - H_hat x_hat|^2 is summed over the slot's data REs and beams.
+      Neither estimate has seen those REs, so the sum grows with the
+      estimation error.  The chain keeps the denoised estimate unless its
+      residual exceeds the LS one.  (The LS estimate passes through every
+      pilot RE of its comb, so a residual on the pilot REs would always favour
+      it; held-out pilots of a regular comb sit where linear interpolation is
+      at its best, at the midpoints between the seen ones.)
 """
 from __future__ import annotations
 
@@ -133,14 +132,16 @@ def conv3x3_weight_grad(g, x) -> tuple[np.ndarray, np.ndarray]:
     return dW, g.sum(axis=(0, 1))
 
 
-def forward(grid, params, bf16: bool = False):
-    """Denoised estimate of one LS grid [S, K] (complex): grid + net(grid).
+def forward(grid, params, bf16: bool = False, sigma: float = 1.0):
+    """Denoised estimate of one LS grid [S, K] (complex): grid + sigma net(grid / sigma),
+    the network run in units of sigma (sigma = 1: the plain network).
 
-    Returns (out [S, K] complex128, cache for backward)."""
+    Returns (out [S, K] complex128, cache for backward, valid for sigma = 1)."""
     grid = np.asarray(grid, np.complex128)
     rnd = to_bf16 if bf16 else (lambda v: np.asarray(v, np.float64))
     layers = unpack(params)
-    a = rnd(np.stack([grid.real, grid.imag], axis=-1))
+    x = grid / sigma
+    a = rnd(np.stack([x.real, x.imag], axis=-1))
     acts = [a]  # the input of every layer, as the layer reads it
     for n, ((W, b), (_, _, relu)) in enumerate(zip(layers, LAYERS)):
         z = conv3x3(a, rnd(W), b)
@@ -149,7 +150,7 @@ def forward(grid, params, bf16: bool = False):
             acts.append(a)
         else:
             a = z
-    out = grid + (a[..., 0] + 1j * a[..., 1])
+    out = grid + sigma * (a[..., 0] + 1j * a[..., 1])
     return out, {"acts": acts, "bf16": bf16, "layers": layers}
 
 
@@ -173,34 +174,30 @@ def backward(cache, dout) -> np.ndarray:
     return pack(grads)
 
 
-def mse_loss(out, target) -> tuple[float, np.ndarray]:
-    """Mean over all complex entries of |out - target|^2, and its gradient as a
-    complex grid (d/d re + i d/d im): 2 (out - target) / N."""
+def mse_loss(out, target, weights=None) -> tuple[float, np.ndarray]:
+    """Mean over all complex entries of w_g |out - target|^2 (grids g along the
+    first axis, w_g = 1 without weights), and its gradient as a complex grid
+    (d/d re + i d/d im): 2 w_g (out - target) / N."""
     out = np.asarray(out, np.complex128)
     target = np.asarray(target, np.complex128)
     e = out - target
     n = e.size
-    return float(np.sum(e.real ** 2 + e.imag ** 2) / n), 2.0 * e / n
+    w = np.ones(e.shape[0]) if weights is None else np.asarray(weights, np.float64)
+    w = w.reshape((-1,) + (1,) * (e.ndim - 1))
+    return float(np.sum(w * (e.real ** 2 + e.imag ** 2)) / n), 2.0 * w * e / n
 
 
 # ----------------------------------------------------------------------------- LS grid and fallback
 
-def _fold_positions(ks: np.ndarray, fold: int) -> np.ndarray:
-    """A UE's pilot subcarriers on one pilot symbol (ascending): all (fold 0), the
-    even-indexed half (fold 1) or the odd-indexed half (fold 2)."""
-    return ks if fold == 0 else ks[fold - 1::2]
-
-
-def ls_symbol_estimate(Yp_j, p_j, n_ue: int, j: int, n_pilot: int, fold: int = 0) -> np.ndarray:
+def ls_symbol_estimate(Yp_j, p_j, n_ue: int, j: int, n_pilot: int) -> np.ndarray:
     """LS estimate from pilot symbol j alone (as pusch_oracle.ls_channel_estimate
-    with use=[j]), from the fold's positions only.  Yp_j: [N_B, K]; p_j: [K].
-    Returns [K, N_B, N_L]."""
+    with use=[j]).  Yp_j: [N_B, K]; p_j: [K].  Returns [K, N_B, N_L]."""
     n_beams, K = Yp_j.shape
     H = np.zeros((K, n_beams, n_ue), complex)
     grid = np.arange(K, dtype=np.float64)
     owner = O.pilot_owner(K, j, n_ue, n_pilot)
     for l in range(n_ue):
-        ks = _fold_positions(np.nonzero(owner == l)[0], fold)
+        ks = np.nonzero(owner == l)[0]
         p = p_j[ks]
         val = Yp_j[:, ks] * (np.conj(p) / np.abs(p) ** 2)
         for b in range(n_beams):
@@ -208,16 +205,16 @@ def ls_symbol_estimate(Yp_j, p_j, n_ue: int, j: int, n_pilot: int, fold: int = 0
     return H
 
 
-def ls_grid(Yp, pilots, n_ue: int, pilot_symb, n_symb: int, fold: int = 0) -> np.ndarray:
+def ls_grid(Yp, pilots, n_ue: int, pilot_symb, n_symb: int) -> np.ndarray:
     """LS estimate on every symbol (reading R19): per pilot symbol from its own
-    positions (of the fold), interpolated linearly in time between the pilot
-    symbols around each symbol and held outside them.
+    comb positions, interpolated linearly in time between the pilot symbols
+    around each symbol and held outside them.
 
     Yp: [N_p, N_B, K]; pilots: [N_p, K].  Returns [S, K, N_B, N_L]."""
     Yp = np.asarray(Yp, np.complex128)
     pilots = np.asarray(pilots, np.complex128)
     n_pilot = Yp.shape[0]
-    per = [ls_symbol_estimate(Yp[j], pilots[j], n_ue, j, n_pilot, fold) for j in range(n_pilot)]
+    per = [ls_symbol_estimate(Yp[j], pilots[j], n_ue, j, n_pilot) for j in range(n_pilot)]
     ps = list(pilot_symb)
     out = []
     for s in range(n_symb):
@@ -232,36 +229,69 @@ def ls_grid(Yp, pilots, n_ue: int, pilot_symb, n_symb: int, fold: int = 0) -> np
     return np.stack(out)
 
 
-def denoise_estimate(H_grid, params, bf16: bool = False) -> np.ndarray:
-    """The network on every (beam, UE) pair of an estimate [S, K, N_B, N_L]."""
+def denoise_estimate(H_grid, params, bf16: bool = False, sigma: float = 1.0) -> np.ndarray:
+    """The network (in units of sigma) on every (beam, UE) pair of an estimate [S, K, N_B, N_L]."""
     S, K, NB, NL = H_grid.shape
     out = np.zeros_like(H_grid)
     for b in range(NB):
         for l in range(NL):
-            out[:, :, b, l] = forward(H_grid[:, :, b, l], params, bf16)[0]
+            out[:, :, b, l] = forward(H_grid[:, :, b, l], params, bf16, sigma)[0]
     return out
 
 
-def pilot_holdout_residual(Yp, pilots, n_ue: int, pilot_symb, n_symb: int, sigma2: float, estimator) -> float:
-    """Post-MMSE pilot residual of an estimator (reading R20).
+def detect_and_residual(Y, H_grid, pilot_symb, sigma2: float):
+    """Eq. 2 on every data symbol with the estimate of that symbol, and the
+    post-MMSE residual of reading R20: sum over data REs and beams of
+    |y - H_hat x_hat|^2.
 
-    estimator(fold) -> [S, K, N_B, N_L] estimate from that fold's pilots.  For
-    fold 1 the held-out REs are fold 2's and vice versa.  At each held-out
-    pilot RE (j, k) of UE l the received vector is equalised with Eq. 2 using
-    the estimate of symbol pilot_symb[j] at k, and |x_hat - p e_l|^2 is summed."""
-    Yp = np.asarray(Yp, np.complex128)
-    pilots = np.asarray(pilots, np.complex128)
-    n_pilot, _, K = Yp.shape
-    total = 0.0
-    for fold, held in ((1, 2), (2, 1)):
-        H = estimator(fold)
-        for j in range(n_pilot):
-            owner = O.pilot_owner(K, j, n_ue, n_pilot)
-            ks = np.concatenate([_fold_positions(np.nonzero(owner == l)[0], held) for l in range(n_ue)])
-            ks.sort()
-            Hk = H[pilot_symb[j]][ks]  # [n, N_B, N_L]
-            x_hat, _ = O.mmse_detect(Hk, Yp[j][:, ks].T[None], sigma2)
-            x = np.zeros((len(ks), n_ue), complex)
-            x[np.arange(len(ks)), owner[ks]] = pilots[j, ks]
-            total += float(np.sum(np.abs(x_hat[0] - x) ** 2))
-    return total
+    Y: [S, N_B, K] beam-domain grids; H_grid: [S, K, N_B, N_L].
+    Returns (x_hat [D, K, N_L], ok [D, K], residual)."""
+    Y = np.asarray(Y, np.complex128)
+    S, _, K = Y.shape
+    n_ue = H_grid.shape[3]
+    data = [s for s in range(S) if s not in list(pilot_symb)]
+    x_hat = np.zeros((len(data), K, n_ue), complex)
+    ok = np.zeros((len(data), K), bool)
+    res = 0.0
+    for d, s in enumerate(data):
+        xs, ok[d] = O.mmse_detect(H_grid[s], Y[s].T[None], sigma2)
+        x_hat[d] = xs[0]
+        r = Y[s].T - np.einsum("kbl,kl->kb", H_grid[s], xs[0])
+        res += float(np.sum(r.real ** 2 + r.imag ** 2))
+    return x_hat, ok, res
+
+
+def adam_step(p, g, m, v, step: int, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+    """One Adam step (Kingma and Ba, "Adam: a method for stochastic optimization",
+    Algorithm 1): moments m, v of the gradient, bias-corrected by 1 - beta^step.
+    Returns (p, m, v)."""
+    p, g, m, v = (np.asarray(a, np.float64) for a in (p, g, m, v))
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** step)
+    vh = v / (1.0 - b2 ** step)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def receive_slot_denoised(x_td, pilots, pilot_symb, n_ue: int, n_sc: int, sigma2: float, params, n_beams: int,
+                          W=None, bf16: bool = True) -> dict:
+    """The chain with the denoised estimate and the LS fallback (reading R20):
+    OFDM demodulation and beamforming as pusch_oracle.receive_slot; the LS grid
+    and the network on it, in units of sqrt(sigma2); Eq. 2 for every data symbol with each estimate of
+    that symbol; the denoised result unless its post-MMSE residual exceeds the
+    LS one.
+
+    Returns {"x_hat" [D, K, N_L], "used_dn" bool, "res_ls", "res_dn", "ok" [D, K]}."""
+    x_td = np.asarray(x_td, np.complex128)
+    n_symb, n_ant, _ = x_td.shape
+    W = O.dft_beamformer(n_beams, n_ant) if W is None else np.asarray(W, np.complex128)
+    Y = O.beamform(W, O.ofdm_demodulate(x_td, n_sc))  # [S, N_B, K]
+    ps = list(pilot_symb)
+    G = ls_grid(Y[ps], pilots, n_ue, ps, n_symb)
+    # the network in units of the LS values' noise standard deviation (unit-power pilots, unitary beams)
+    Dn = denoise_estimate(G, params, bf16, float(np.sqrt(sigma2)))
+    x_ls, ok_ls, res_ls = detect_and_residual(Y, G, ps, sigma2)
+    x_dn, ok_dn, res_dn = detect_and_residual(Y, Dn, ps, sigma2)
+    use = res_dn <= res_ls
+    return {"x_hat": x_dn if use else x_ls, "used_dn": bool(use), "res_ls": res_ls, "res_dn": res_dn,
+            "ok": ok_dn if use else ok_ls}

@@ -1,9 +1,9 @@
 """Pins of the denoiser oracle (oracle/denoiser_oracle.py) against what the
-mathematics fixes: a hand-worked convolution and holdout residual
+mathematics fixes: a hand-worked convolution and post-MMSE residual
 (tests/golden/conv3x3_small.txt), delta responses, an independent library
 correlation (scipy.signal.correlate2d), finite differences of the loss for the
 backward pass, bfloat16 rounding of known values, exact LS interpolation of a
-channel linear in frequency from either half of the comb.  Planted mistakes
+channel linear in frequency.  Planted mistakes
 in a copy of the oracle must fail these pins.
 """
 import math
@@ -82,28 +82,33 @@ def _pins_pass(mod, golden) -> bool:
         assert abs(np.sum(mod.conv3x3(xs, Ws) * ys) - np.sum(xs * mod.conv3x3_transposed(ys, Ws))) < 1e-10
         # backward against finite differences of the MSE loss (FP64)
         assert _fd_check(mod, np.random.default_rng(11), _sample_idx(np.random.default_rng(12))) < 1e-5
+        # in units of sigma: sigma * DN(grid / sigma)
+        pr = _params(np.random.default_rng(21))
+        gr = rng.standard_normal((3, 5)) + 1j * rng.standard_normal((3, 5))
+        assert np.allclose(mod.forward(gr, pr, sigma=0.25)[0], 0.25 * mod.forward(gr / 0.25, pr)[0], atol=1e-12)
+        assert not np.allclose(mod.forward(gr, pr, sigma=0.25)[0], mod.forward(gr, pr)[0])
         # zero network: the output is the LS grid, and the first three layers get no gradient
         z = np.zeros(mod.n_params())
         grid = rng.standard_normal((3, 4)) + 1j * rng.standard_normal((3, 4))
         out, cache = mod.forward(grid, z)
         assert np.array_equal(out, grid)
-        # holdout residual worked by hand
-        y = np.array(g["res_y"], complex)
-        est = lambda fold: mod.ls_grid(y[None, None], np.ones((1, 4)), 1, (0,), 1, fold)
-        r = mod.pilot_holdout_residual(y[None, None], np.ones((1, 4)), 1, (0,), 1, 0.0, est)
+        # post-MMSE residual worked by hand: pilot symbol 0, data symbol 1
+        H = np.zeros((2, 2, 1, 1), complex)
+        H[1, :, 0, 0] = g["res_h"]
+        Y = np.zeros((2, 1, 2), complex)
+        Y[1, 0] = g["res_y"]
+        _, _, r = mod.detect_and_residual(Y, H, (0,), 1.0)
         assert abs(r - g["res_total"]) < 1e-12
-        # two pilot symbols, a channel that is constant in frequency but different on each: the
-        # held-out REs of pilot symbol j must be equalised with symbol pilot_symb[j]'s estimate
-        K2, nb2 = 16, 2
-        A = np.array([[1.0 + 0.5j, -0.3j], [0.2, 1.1 - 0.4j]])  # [N_B, N_L] on pilot symbol 2
-        B = np.array([[0.4 - 1.0j, 0.9], [1.3j, -0.6 + 0.2j]])  # on pilot symbol 11
-        p2 = np.exp(0.5j * np.pi * np.random.default_rng(4).integers(0, 4, (2, K2)))
-        Y2 = np.zeros((2, nb2, K2), complex)
-        for j, Hj in enumerate((A, B)):
-            own = O.pilot_owner(K2, j, 2, 2)
-            Y2[j] = Hj[:, own] * p2[j]
-        est2 = lambda fold: mod.ls_grid(Y2, p2, 2, (2, 11), 14, fold)
-        assert mod.pilot_holdout_residual(Y2, p2, 2, (2, 11), 14, 0.0, est2) < 1e-18
+        # each data symbol is equalised with its own estimate: a different channel on symbol 2
+        H3 = np.concatenate([H, H[1:] * 0.5j], axis=0)
+        Y3 = np.concatenate([Y, Y[1:] * 0.5j], axis=1 - 1)
+        x3, _, r3 = mod.detect_and_residual(Y3, H3, (0,), 0.0)
+        assert np.allclose(x3[1], x3[0]) and r3 < 1e-24
+        # the weighted loss: weight 2 on the first grid, 0 on the second
+        o = np.array([[[1 + 1j]], [[5.0]]])
+        t = np.array([[[0.0]], [[0.0]]])
+        lv, dv = mod.mse_loss(o, t, [2.0, 0.0])
+        assert abs(lv - 2.0 * 2.0 / 2) < 1e-15 and np.allclose(dv, [[[2 * 2 * (1 + 1j) / 2]], [[0.0]]])
         return True
     except Exception:  # a wrong result, or a mutant that no longer runs
         return False
@@ -151,9 +156,8 @@ def test_bf16_forward_backward_are_close_to_fp64():
     assert np.linalg.norm(g16 - g64) / np.linalg.norm(g64) < 0.2
 
 
-@pytest.mark.parametrize("fold", [0, 1, 2])
-def test_fold_ls_is_exact_for_a_channel_linear_in_frequency(fold):
-    rng = np.random.default_rng(fold)
+def test_ls_grid_is_exact_for_a_channel_linear_in_frequency():
+    rng = np.random.default_rng(0)
     K, n_ue, n_beams = 40, 4, 3
     a = rng.standard_normal((n_beams, n_ue)) + 1j * rng.standard_normal((n_beams, n_ue))
     c = rng.standard_normal((n_beams, n_ue)) + 1j * rng.standard_normal((n_beams, n_ue))
@@ -161,45 +165,69 @@ def test_fold_ls_is_exact_for_a_channel_linear_in_frequency(fold):
     p = np.exp(0.5j * np.pi * rng.integers(0, 4, (1, K)))
     own = O.pilot_owner(K, 0, n_ue, 1)
     Yp = (Hk[np.arange(K), :, own] * p[0][:, None]).T[None]  # [1, N_B, K]
-    H = DN.ls_grid(Yp, p, n_ue, (2,), 5, fold)
+    H = DN.ls_grid(Yp, p, n_ue, (2,), 5)
     assert H.shape == (5, K, n_beams, n_ue)
     for l in range(n_ue):
         ks = np.nonzero(own == l)[0]
-        ks = ks if fold == 0 else ks[fold - 1::2]
         inside = np.arange(ks[0], ks[-1] + 1)
         for s in range(5):  # one pilot symbol: the same estimate on every symbol
             assert np.allclose(H[s, inside, :, l], Hk[inside, :, l], atol=1e-12)
         assert np.allclose(H[0, :ks[0], :, l], Hk[ks[0], :, l], atol=1e-12)  # held below the first position
 
 
-def test_fold_zero_matches_the_chain_estimator():
+def test_ls_grid_matches_the_chain_estimator():
     rng = np.random.default_rng(8)
     K, n_ue, n_beams = 30, 3, 2
     Yp = rng.standard_normal((2, n_beams, K)) + 1j * rng.standard_normal((2, n_beams, K))
     p = np.exp(0.5j * np.pi * rng.integers(0, 4, (2, K)))
-    H = DN.ls_grid(Yp, p, n_ue, (2, 11), 14, 0)
+    H = DN.ls_grid(Yp, p, n_ue, (2, 11), 14)
     for s in (0, 5, 13):
         assert np.allclose(H[s], O.time_interpolated_estimate(Yp, p, n_ue, (2, 11), s), atol=1e-12)
 
 
-def test_holdout_residual_noiseless_linear_channel_is_zero():
+def test_residual_is_the_noise_for_the_true_channel_and_grows_with_the_error():
+    # with the true channel and noiseless data the residual is the regularisation's share only
     rng = np.random.default_rng(9)
-    K, n_ue, n_beams = 64, 4, 8
-    a = rng.standard_normal((n_beams, n_ue)) + 1j * rng.standard_normal((n_beams, n_ue))
-    c = rng.standard_normal((n_beams, n_ue)) + 1j * rng.standard_normal((n_beams, n_ue))
-    Hk = a[None] + np.arange(K)[:, None, None] * c[None] * 0.02
-    p = np.exp(0.5j * np.pi * rng.integers(0, 4, (1, K)))
-    own = O.pilot_owner(K, 0, n_ue, 1)
-    Yp = (Hk[np.arange(K), :, own] * p[0][:, None]).T[None]
-    est = lambda fold: DN.ls_grid(Yp, p, n_ue, (2,), 14, fold)
-    # held-out positions past a fold's last position see a held (not linear) value: keep the
-    # comparison inside, by making the channel constant there
-    r = DN.pilot_holdout_residual(Yp, p, n_ue, (2,), 14, 1e-12, est)
-    assert r < 0.5  # only the end holds miss
-    Hc = np.repeat(a[None], K, axis=0)
-    Yc = (Hc[np.arange(K), :, own] * p[0][:, None]).T[None]
-    estc = lambda fold: DN.ls_grid(Yc, p, n_ue, (2,), 14, fold)
-    assert DN.pilot_holdout_residual(Yc, p, n_ue, (2,), 14, 0.0, estc) < 1e-18
+    S, K, nb, nl = 4, 50, 8, 3
+    H = rng.standard_normal((S, K, nb, nl)) + 1j * rng.standard_normal((S, K, nb, nl))
+    x = np.exp(0.5j * np.pi * rng.integers(0, 4, (S, K, nl)))
+    Y = np.einsum("skbl,skl->sbk", H, x)
+    _, _, r0 = DN.detect_and_residual(Y, H, (0,), 0.0)
+    assert r0 < 1e-18
+    noisy = H + 0.1 * (rng.standard_normal(H.shape) + 1j * rng.standard_normal(H.shape))
+    _, _, r1 = DN.detect_and_residual(Y, noisy, (0,), 0.0)
+    worse = H + 0.3 * (rng.standard_normal(H.shape) + 1j * rng.standard_normal(H.shape))
+    _, _, r2 = DN.detect_and_residual(Y, worse, (0,), 0.0)
+    assert 0 < r1 < r2
+
+
+def test_adam_first_steps_closed_form():
+    # with m = v = 0 the first bias-corrected step is lr g / (|g| + eps); a constant gradient keeps
+    # the bias-corrected moments at g and g^2, so every later step is the same
+    p = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    m = v = np.zeros(3)
+    for step in (1, 2, 3):
+        p2, m, v = DN.adam_step(p, g, m, v, step, 0.01)
+        assert np.allclose(p2 - p, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+        p = p2
+    # a sign flip after one step: m2 = 0.9 (0.1 g) - 0.1 g = -0.01 g over 1 - 0.81 = 0.19
+    p0 = np.zeros(1)
+    p1, m1, v1 = DN.adam_step(p0, np.array([1.0]), np.zeros(1), np.zeros(1), 1, 1.0, eps=0.0)
+    p2, _, _ = DN.adam_step(p1, np.array([-1.0]), m1, v1, 2, 1.0, eps=0.0)
+    assert np.allclose(p2 - p1, -(-0.01 / 0.19) / np.sqrt((0.999 * 0.001 + 0.001) / (1 - 0.999 ** 2)), rtol=1e-12)
+
+
+def test_denoised_chain_with_a_zero_network_is_the_ls_chain():
+    from paper_2210_09196_amd import synth
+    cfg = synth.CFG1.replace(n_fft=64, n_sc=64, n_ant=8, n_beams=8)
+    b = synth.make_batch(cfg, [3])
+    r = DN.receive_slot_denoised(b["x_td"][0], b["pilots"][0], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
+                                 np.zeros(DN.n_params()), cfg.n_beams)
+    ref = O.receive_slot(b["x_td"][0], b["pilots"][0], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
+                         n_beams=cfg.n_beams)
+    assert r["used_dn"] and r["res_dn"] == r["res_ls"]
+    assert np.allclose(r["x_hat"], ref["x_hat"], atol=1e-12)
 
 
 def _mutant(old: str, new: str) -> types.ModuleType:
@@ -228,16 +256,21 @@ MUTATIONS = [
     # bias gradient lost
     ("return dW, g.sum(axis=(0, 1))", "return dW, 0.0 * g.sum(axis=(0, 1))"),
     # loss gradient without the factor 2
-    ("return float(np.sum(e.real ** 2 + e.imag ** 2) / n), 2.0 * e / n", "return float(np.sum(e.real ** 2 + e.imag ** 2) / n), e / n"),
+    ("return float(np.sum(w * (e.real ** 2 + e.imag ** 2)) / n), 2.0 * w * e / n",
+     "return float(np.sum(w * (e.real ** 2 + e.imag ** 2)) / n), w * e / n"),
     # no residual connection
-    ("out = grid + (a[..., 0] + 1j * a[..., 1])", "out = a[..., 0] + 1j * a[..., 1]"),
+    ("out = grid + sigma * (a[..., 0] + 1j * a[..., 1])", "out = sigma * (a[..., 0] + 1j * a[..., 1])"),
+    # the correction not scaled back to the grid's units
+    ("out = grid + sigma * (a[..., 0] + 1j * a[..., 1])", "out = grid + (a[..., 0] + 1j * a[..., 1])"),
     # weight-gradient offsets transposed
     ('dW[:, dy, dx, :] = np.einsum("sko,ski->oi", g, xp[dy:dy + S, dx:dx + K])',
      'dW[:, dx % 3, dy, :] = np.einsum("sko,ski->oi", g, xp[dy:dy + S, dx:dx + K])'),
-    # folds: the same half twice
-    ("return ks if fold == 0 else ks[fold - 1::2]", "return ks if fold == 0 else ks[0::2]"),
-    # residual: held-out REs equalised with the estimate of the wrong symbol
-    ("Hk = H[pilot_symb[j]][ks]", "Hk = H[0][ks]"),
+    # residual: plus instead of minus; the estimate of the wrong symbol
+    ('r = Y[s].T - np.einsum("kbl,kl->kb", H_grid[s], xs[0])', 'r = Y[s].T + np.einsum("kbl,kl->kb", H_grid[s], xs[0])'),
+    ("xs, ok[d] = O.mmse_detect(H_grid[s], Y[s].T[None], sigma2)",
+     "xs, ok[d] = O.mmse_detect(H_grid[data[0]], Y[s].T[None], sigma2)"),
+    # loss weights ignored
+    ("w = w.reshape((-1,) + (1,) * (e.ndim - 1))", "w = np.ones_like(w).reshape((-1,) + (1,) * (e.ndim - 1))"),
 ]
 
 
