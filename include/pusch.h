@@ -291,6 +291,88 @@ int pusch_cells(const pusch_slot_desc* d, int n_cells, const long long* n_slot, 
                 void* stream);
 
 /*
+ * Learned refinement of the LS channel estimate (the paper's estimator is LS
+ * on the pilot symbols, Sec. II, CHE; Table 1, row "CHE").  For every (UE,
+ * beam) pair the LS estimate over the n_symb x n_sc grid (a complex grid: real
+ * and imaginary parts are two channels) passes four 3x3 convolution layers,
+ * 2 -> 32 -> 32 -> 32 -> 2 channels with ReLU after the first three, and the
+ * result is added to the LS estimate.  Convolutions are cross-correlations
+ * over (symbol, subcarrier) with zero padding.  The kernels run on bfloat16
+ * matrix cores with FP32 accumulation: weights, the network input, the hidden
+ * activations and the gradients entering the transposed convolutions are
+ * rounded to bfloat16 (nearest, ties to even); biases, the residual addition,
+ * weight gradients and the optimiser are FP32.
+ *
+ * Parameters: PUSCH_DN_PARAMS FP32 values (device), layer by layer
+ * W[c_out][3][3][c_in] (c_in fastest) then b[c_out].
+ * Grids: complex [n_grid][n_symb][n_sc] (subcarrier fastest).
+ *   1 <= n_symb <= PUSCH_MAX_SYMBOLS, 1 <= n_sc <= 4096, n_grid >= 0.
+ * ws: device workspace of at least pusch_dn_workspace_bytes(n_symb, n_sc,
+ * n_grid) bytes, 256-byte aligned; pusch_dn_forward needs only its first part
+ * (the hidden activations) but a smaller buffer is accepted only when it is
+ * at least that part; pusch_dn_backward reads the activations the last
+ * forward pass over the same grids left there.
+ */
+#define PUSCH_DN_PARAMS 19682
+size_t pusch_dn_workspace_bytes(int n_symb, int n_sc, long long n_grid);
+/* LS estimate on every symbol of every (UE, beam) pair: per pilot symbol from
+ * that symbol's comb positions of the UE, linear along the subcarriers with
+ * the end values held, then linear in time between the pilot symbols around
+ * each symbol (held before the first and after the last).
+ *   Yp [batch][n_pilot][n_sc][n_beams] RE-major received pilot symbols,
+ *   pilots [batch][n_pilot][n_sc], pilot_symb: n_pilot host ints (the pilot
+ *   symbols' indices among the n_symb, ascending),
+ *   grid [batch][n_ue][n_beams][n_symb][n_sc]. */
+int pusch_dn_ls_grid(const pusch_c32* Yp, const pusch_c32* pilots, pusch_c32* grid, int n_beams, int n_ue, int n_sc,
+                     int n_symb, int n_pilot, const int* pilot_symb, long long batch, void* stream);
+/* out = grid + sigma net(grid / sigma): the network on the grid in units of
+ * sigma > 0 (the noise standard deviation of the LS values, as the network is
+ * trained), its correction scaled back; sigma = 1 is the plain network.  out
+ * must not overlap grid. */
+int pusch_dn_forward(const float* params, const pusch_c32* grid, pusch_c32* out, float sigma, int n_symb, int n_sc,
+                     long long n_grid, void* ws, size_t ws_bytes, void* stream);
+/* grads[PUSCH_DN_PARAMS] = dL/dparams from dout = dL/d(out) (real part: the
+ * derivative with respect to the output's real part, imaginary: imaginary),
+ * after pusch_dn_forward(params, grid, ...) on the same ws.  Weight gradients
+ * are summed in a fixed order (bit-reproducible).  The gradients are those of
+ * the plain network (sigma = 1 in the forward pass).  n_grid >= 1. */
+int pusch_dn_backward(const float* params, const pusch_c32* grid, const pusch_c32* dout, float* grads, int n_symb,
+                      int n_sc, long long n_grid, void* ws, size_t ws_bytes, void* stream);
+/* loss[0] = mean over all complex entries of w_g |out - target|^2, and
+ * dout = 2 w_g (out - target) / (n_grid n_symb n_sc), with w_g = weights[g]
+ * for the entries of grid g (weights: n_grid FP32 on the device, or NULL for
+ * all 1).  n_grid >= 1. */
+int pusch_dn_loss(const pusch_c32* out, const pusch_c32* target, const float* weights, pusch_c32* dout, float* loss,
+                  int n_symb, int n_sc, long long n_grid, void* ws, size_t ws_bytes, void* stream);
+/* One Adam step (Kingma and Ba) on the FP32 parameters, in place: m and v
+ * (PUSCH_DN_PARAMS each, zero before step 1) are the moment estimates, step
+ * >= 1 the step number (for the bias correction 1 - beta^step). */
+int pusch_dn_adam(float* params, const float* grads, float* m, float* v, int step, float lr, float beta1, float beta2,
+                  float eps, void* stream);
+
+/*
+ * The receive chain with the denoised channel estimate and the LS fallback.
+ * OFDM demodulation and beamforming as pusch_slot; the LS estimate on every
+ * symbol (as pusch_dn_ls_grid) and its denoised form (params, run as
+ * pusch_dn_forward with sigma = sqrt(sigma2): the LS values' noise standard
+ * deviation after a unitary beamformer and unit-power pilots); every data
+ * symbol detected (Eq. 2) with each estimate of that symbol; then, per slot,
+ * the fallback test: the post-MMSE residual sum |y - H_hat x_hat|^2 over the
+ * slot's data REs and beams is formed for both estimates (neither has seen
+ * those REs, so it grows with the estimation error), and the denoised
+ * result is kept unless its residual exceeds the LS one, in which case the
+ * slot falls back to plain LS.
+ *   Arguments as pusch_slot; dn_params: PUSCH_DN_PARAMS FP32 (device);
+ *   used_dn [n_slot] int32 (device) or NULL: 1 where the denoised estimate was
+ *   used, 0 where the slot fell back to LS; status: the flags of the result
+ *   kept.  sigma2 > 0 given (noise_est 0; PUSCH_EINVAL for sigma2 = 0),
+ *   refine 0 and time_varying 0, else PUSCH_EUNSUPPORTED.
+ */
+size_t pusch_slot_denoised_workspace_bytes(const pusch_slot_desc* d, long long n_slot);
+int pusch_slot_denoised(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td, const float* dn_params,
+                        pusch_c32* x_hat, int32_t* status, int32_t* used_dn, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Stage timing for measurement.  pusch_profile_begin(max_calls) creates
  * HIP events (allocation happens here, not in pusch_slot); while active, each
  * pusch_slot call (not the cells of pusch_cells) records an event before and after each of its

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libpusch.so")
-SOURCES = ["fft.hip", "beamform.hip", "chest.hip", "noise.hip", "mmse.hip", "api.hip"]
+SOURCES = ["fft.hip", "beamform.hip", "chest.hip", "noise.hip", "mmse.hip", "denoise.hip", "api.hip"]
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

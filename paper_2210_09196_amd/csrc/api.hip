@@ -815,3 +815,286 @@ int pusch_profile_end(float* stage_ms, int n) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- LS-estimate denoiser
+namespace {
+
+constexpr int kDnMaxSc = 4096;
+
+int check_dn_grid(int n_symb, int n_sc, long long n_grid) {
+  if (n_symb < 1 || n_symb > PUSCH_MAX_SYMBOLS || n_sc < 1 || n_sc > kDnMaxSc || n_grid < 0) return PUSCH_EINVAL;
+  // positions and wave tiles fit the kernels' index arithmetic
+  if (n_grid * n_symb * (long long)n_sc > (1ll << 40)) return PUSCH_EUNSUPPORTED;
+  return PUSCH_OK;
+}
+
+// Workspace of pusch_slot_denoised (byte offsets).
+struct DnSlotLayout {
+  size_t off_xa, off_y, off_g, off_d, off_dn, off_h[2], off_x[2], off_st[2], off_res, total;
+};
+
+DnSlotLayout dn_slot_layout(const pusch_slot_desc* d, long long n_slot) {
+  const size_t S = d->n_symb, R = d->n_ant, K = d->n_sc, B = d->n_beams, L = d->n_ue, P = d->n_pilot;
+  const size_t D = S - P, n = (size_t)n_slot;
+  DnSlotLayout lay;
+  lay.off_xa = 0;
+  lay.off_y = align256(n * S * R * xa_pitch(d->n_sc) * 8);
+  size_t o = lay.off_y + align256(n * S * K * B * 8);
+  const size_t grid = align256(n * L * B * S * K * 8);
+  lay.off_g = o;
+  o += grid;
+  lay.off_d = o;
+  o += grid;
+  lay.off_dn = o;
+  o += align256((size_t)pusch::dn_layout(d->n_symb, d->n_sc, n_slot * L * B, 0).fwd_total);
+  for (int e = 0; e < 2; ++e) {
+    lay.off_h[e] = o;
+    o += align256(D * n * K * L * B * 8);
+    lay.off_x[e] = o;
+    o += align256(n * D * K * L * 8);
+    lay.off_st[e] = o;
+    o += align256(n * K * 4);
+  }
+  lay.off_res = o;
+  o += align256(n * 2 * 4);
+  lay.total = o;
+  return lay;
+}
+
+int check_dn_slot_geom(const pusch_slot_desc* d) {
+  if (int rc = check_geom(d)) return rc;
+  if (d->refine || d->time_varying || d->noise_est) return PUSCH_EUNSUPPORTED;
+  if (!(d->sigma2 > 0.f) || !std::isfinite(d->sigma2)) return PUSCH_EINVAL;  // the network's unit
+  if (d->n_ant > 1024) return PUSCH_EUNSUPPORTED;
+  return PUSCH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pusch_dn_workspace_bytes(int n_symb, int n_sc, long long n_grid) {
+  if (check_dn_grid(n_symb, n_sc, n_grid) != PUSCH_OK) return 0;
+  return (size_t)pusch::dn_layout(n_symb, n_sc, n_grid, 0).total;
+}
+
+int pusch_dn_ls_grid(const pusch_c32* Yp, const pusch_c32* pilots, pusch_c32* grid, int n_beams, int n_ue, int n_sc,
+                     int n_symb, int n_pilot, const int* pilot_symb, long long batch, void* stream) {
+  if (!Yp || !pilots || !grid || !pilot_symb || batch < 0) return PUSCH_EINVAL;
+  if (n_beams < 1 || n_beams > PUSCH_MAX_BEAMS || n_ue < 1 || n_ue > PUSCH_MAX_UES || n_ue > n_beams) return PUSCH_EINVAL;
+  if (n_pilot < 1 || n_pilot > PUSCH_MAX_PILOTS || n_symb < 1 || n_symb > PUSCH_MAX_SYMBOLS) return PUSCH_EINVAL;
+  if (n_sc < n_ue || n_sc > kDnMaxSc) return PUSCH_EINVAL;
+  for (int j = 0; j < n_pilot; ++j)
+    if (pilot_symb[j] < 0 || pilot_symb[j] >= n_symb || (j > 0 && pilot_symb[j] <= pilot_symb[j - 1]))
+      return PUSCH_EINVAL;
+  const long long yb = batch * n_pilot * (long long)n_sc * n_beams * 8, pb = batch * n_pilot * (long long)n_sc * 8;
+  const long long gb = batch * n_ue * (long long)n_beams * n_symb * n_sc * 8;
+  if (overlap(grid, gb, Yp, yb) || overlap(grid, gb, pilots, pb)) return PUSCH_EINVAL;
+  if (batch == 0) return PUSCH_OK;
+  pusch::DnGridGeom g{};
+  g.n_beams = n_beams;
+  g.n_ue = n_ue;
+  g.n_sc = n_sc;
+  g.n_symb = n_symb;
+  g.n_pilot = n_pilot;
+  for (int j = 0; j < n_pilot; ++j) {
+    g.pilot_sym[j] = pilot_symb[j];
+    g.y_off[j] = (long long)j * n_sc * n_beams;
+  }
+  g.y_batch = (long long)n_pilot * n_sc * n_beams;
+  g.p_batch = (long long)n_pilot * n_sc;
+  return hip_status(pusch::launch_dn_ls_grid(reinterpret_cast<const cf*>(Yp), reinterpret_cast<const cf*>(pilots),
+                                             reinterpret_cast<cf*>(grid), g, batch, static_cast<hipStream_t>(stream)));
+}
+
+int pusch_dn_forward(const float* params, const pusch_c32* grid, pusch_c32* out, float sigma, int n_symb, int n_sc,
+                     long long n_grid, void* ws, size_t ws_bytes, void* stream) {
+  if (!params || !grid || !out || !ws) return PUSCH_EINVAL;
+  if (!(sigma > 0.f) || !std::isfinite(sigma) || !std::isfinite(1.f / sigma)) return PUSCH_EINVAL;
+  if (int rc = check_dn_grid(n_symb, n_sc, n_grid)) return rc;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return PUSCH_EINVAL;
+  const pusch::DnLayout lay = pusch::dn_layout(n_symb, n_sc, n_grid, 0);
+  if (ws_bytes < (size_t)lay.fwd_total) return PUSCH_ENOMEM;
+  const long long gb = n_grid * n_symb * (long long)n_sc * 8;
+  if (overlap(out, gb, grid, gb) || overlap(out, gb, ws, lay.fwd_total) || overlap(ws, lay.fwd_total, grid, gb) ||
+      overlap(params, pusch::kDnParams * 4, ws, lay.fwd_total) || overlap(params, pusch::kDnParams * 4, out, gb))
+    return PUSCH_EINVAL;
+  if (n_grid == 0) return PUSCH_OK;
+  DeviceTables* t = nullptr;
+  if (int rc = device_tables(&t)) return rc;
+  return hip_status(pusch::launch_dn_forward(params, reinterpret_cast<const cf*>(grid), reinterpret_cast<cf*>(out),
+                                             n_symb, n_sc, n_grid, static_cast<char*>(ws), lay, t->n_cu,
+                                             static_cast<hipStream_t>(stream), sigma));
+}
+
+int pusch_dn_backward(const float* params, const pusch_c32* grid, const pusch_c32* dout, float* grads, int n_symb,
+                      int n_sc, long long n_grid, void* ws, size_t ws_bytes, void* stream) {
+  if (!params || !grid || !dout || !grads || !ws) return PUSCH_EINVAL;
+  if (int rc = check_dn_grid(n_symb, n_sc, n_grid)) return rc;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return PUSCH_EINVAL;
+  const pusch::DnLayout lay = pusch::dn_layout(n_symb, n_sc, n_grid, 0);
+  if (ws_bytes < (size_t)lay.total) return PUSCH_ENOMEM;
+  const long long gb = n_grid * n_symb * (long long)n_sc * 8, pn = pusch::kDnParams * 4;
+  if (overlap(grads, pn, ws, lay.total) || overlap(grads, pn, params, pn) || overlap(grads, pn, grid, gb) ||
+      overlap(grads, pn, dout, gb) || overlap(ws, lay.total, grid, gb) || overlap(ws, lay.total, dout, gb) ||
+      overlap(ws, lay.total, params, pn))
+    return PUSCH_EINVAL;
+  if (n_grid == 0) return PUSCH_EINVAL;  // a gradient needs at least one grid
+  DeviceTables* t = nullptr;
+  if (int rc = device_tables(&t)) return rc;
+  return hip_status(pusch::launch_dn_backward(params, reinterpret_cast<const cf*>(grid), reinterpret_cast<const cf*>(dout),
+                                              grads, n_symb, n_sc, n_grid, static_cast<char*>(ws), lay, t->n_cu,
+                                              static_cast<hipStream_t>(stream)));
+}
+
+int pusch_dn_loss(const pusch_c32* out, const pusch_c32* target, const float* weights, pusch_c32* dout, float* loss,
+                  int n_symb, int n_sc, long long n_grid, void* ws, size_t ws_bytes, void* stream) {
+  if (!out || !target || !dout || !loss || !ws) return PUSCH_EINVAL;
+  if (int rc = check_dn_grid(n_symb, n_sc, n_grid)) return rc;
+  if (n_grid == 0) return PUSCH_EINVAL;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return PUSCH_EINVAL;
+  const pusch::DnLayout lay = pusch::dn_layout(n_symb, n_sc, n_grid, 0);
+  if (ws_bytes < (size_t)lay.total) return PUSCH_ENOMEM;
+  const long long n = n_grid * n_symb * (long long)n_sc, gb = n * 8;
+  if (overlap(dout, gb, out, gb) || overlap(dout, gb, target, gb) || overlap(dout, gb, ws, lay.total) ||
+      overlap(loss, 4, dout, gb) || overlap(loss, 4, ws, lay.total) || overlap(loss, 4, out, gb) ||
+      overlap(loss, 4, target, gb))
+    return PUSCH_EINVAL;
+  if (weights && (overlap(weights, n_grid * 4, dout, gb) || overlap(weights, n_grid * 4, loss, 4)))
+    return PUSCH_EINVAL;
+  return hip_status(pusch::launch_dn_loss(reinterpret_cast<const cf*>(out), reinterpret_cast<const cf*>(target),
+                                          weights, (long long)n_symb * n_sc, reinterpret_cast<cf*>(dout), loss, n,
+                                          static_cast<char*>(ws), lay, static_cast<hipStream_t>(stream)));
+}
+
+int pusch_dn_adam(float* params, const float* grads, float* m, float* v, int step, float lr, float beta1, float beta2,
+                  float eps, void* stream) {
+  if (!params || !grads || !m || !v || step < 1) return PUSCH_EINVAL;
+  if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return PUSCH_EINVAL;
+  const long long pn = pusch::kDnParams * 4;
+  if (overlap(params, pn, grads, pn) || overlap(params, pn, m, pn) || overlap(params, pn, v, pn) ||
+      overlap(m, pn, v, pn) || overlap(m, pn, grads, pn) || overlap(v, pn, grads, pn))
+    return PUSCH_EINVAL;
+  const float c1 = (float)(1.0 - std::pow((double)beta1, step)), c2 = (float)(1.0 - std::pow((double)beta2, step));
+  return hip_status(pusch::launch_dn_adam(params, grads, m, v, pusch::kDnParams, lr, beta1, beta2, eps, c1, c2,
+                                          static_cast<hipStream_t>(stream)));
+}
+
+size_t pusch_slot_denoised_workspace_bytes(const pusch_slot_desc* d, long long n_slot) {
+  if (check_dn_slot_geom(d) != PUSCH_OK || n_slot < 0) return 0;
+  return dn_slot_layout(d, n_slot).total;
+}
+
+int pusch_slot_denoised(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td, const float* dn_params,
+                        pusch_c32* x_hat, int32_t* status, int32_t* used_dn, void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_dn_slot_geom(d)) return rc;
+  if (int rc = check_desc(d)) return rc;
+  if (!dn_params || n_slot < 0 || !x_td || !x_hat || !ws) return PUSCH_EINVAL;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return PUSCH_EINVAL;
+  const DnSlotLayout lay = dn_slot_layout(d, n_slot);
+  if (ws_bytes < lay.total) return PUSCH_ENOMEM;
+  const int S = d->n_symb, R = d->n_ant, K = d->n_sc, B = d->n_beams, L = d->n_ue, P = d->n_pilot, D = S - P;
+  {
+    const long long xb = n_slot * (long long)S * R * d->n_fft * 8, ob = (long long)out_bytes(d, n_slot),
+                    sb = n_slot * (long long)K * 4, ub = n_slot * 4, wb = (long long)lay.total,
+                    pb = n_slot * (long long)P * K * 8, pn = pusch::kDnParams * 4;
+    if (overlap(x_hat, ob, x_td, xb) || overlap(x_hat, ob, ws, wb) || overlap(x_hat, ob, status, sb) ||
+        overlap(ws, wb, x_td, xb) || overlap(status, sb, x_td, xb) || overlap(status, sb, ws, wb) ||
+        overlap(ws, wb, d->pilots, pb) || overlap(ws, wb, d->W, (long long)B * R * 8) || overlap(ws, wb, dn_params, pn) ||
+        overlap(used_dn, ub, ws, wb) || overlap(used_dn, ub, x_hat, ob) || overlap(used_dn, ub, status, sb) ||
+        overlap(used_dn, ub, x_td, xb) || overlap(x_hat, ob, dn_params, pn) || overlap(status, sb, dn_params, pn))
+      return PUSCH_EINVAL;
+  }
+  if (n_slot == 0) return PUSCH_OK;
+  DeviceTables* t = nullptr;
+  if (int rc = device_tables(&t)) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  const cf* w = reinterpret_cast<const cf*>(d->W);
+  if (!w)
+    if (int rc = dft_beamformer(t, B, R, &w)) return rc;
+  const cf* pil = reinterpret_cast<const cf*>(d->pilots);
+  cf* Xa = reinterpret_cast<cf*>(base + lay.off_xa);
+  cf* Y = reinterpret_cast<cf*>(base + lay.off_y);
+  cf* G = reinterpret_cast<cf*>(base + lay.off_g);
+  cf* Dn = reinterpret_cast<cf*>(base + lay.off_d);
+  float* res = reinterpret_cast<float*>(base + lay.off_res);
+  const long long n_grid = n_slot * L * B;
+  const pusch::DnLayout dl = pusch::dn_layout(S, K, n_grid, t->n_cu);
+
+  // OFDM demodulation and beamforming (RE-major, received values)
+  const long long KP = (long long)xa_pitch(K);
+  if (pusch::launch_fft(reinterpret_cast<const cf*>(x_td), Xa, d->n_fft, n_slot * S * R, K, K / 2, KP, t->twiddles,
+                        t->n_cu, s) != hipSuccess)
+    return PUSCH_EHIP;
+  if (pusch::launch_beamform(w, Xa, Y, B, R, K, KP, R * KP, (long long)K * B, n_slot * S, t->n_cu, s) != hipSuccess)
+    return PUSCH_EHIP;
+  // the LS estimate on every symbol, and the network on it
+  pusch::DnGridGeom gg{};
+  gg.n_beams = B;
+  gg.n_ue = L;
+  gg.n_sc = K;
+  gg.n_symb = S;
+  gg.n_pilot = P;
+  for (int j = 0; j < P; ++j) {
+    gg.pilot_sym[j] = d->pilot_symb[j];
+    gg.y_off[j] = (long long)d->pilot_symb[j] * K * B;
+  }
+  gg.y_batch = (long long)S * K * B;
+  gg.p_batch = (long long)P * K;
+  if (pusch::launch_dn_ls_grid(Y, pil, G, gg, n_slot, s) != hipSuccess) return PUSCH_EHIP;
+  // the network runs on the estimate in units of the noise standard deviation
+  const float sig = std::sqrt(d->sigma2);
+  if (pusch::launch_dn_forward(dn_params, G, Dn, S, K, n_grid, base + lay.off_dn, dl, t->n_cu, s, sig) != hipSuccess)
+    return PUSCH_EHIP;
+  // Eq. 2 for every data symbol with each estimate of that symbol
+  pusch::MmseGeom mg{};
+  mg.n_beams = B;
+  mg.n_ue = L;
+  mg.n_sc = K;
+  mg.n_data = 1;
+  mg.sigma2 = d->sigma2;
+  mg.h_batch = (long long)K * L * B;
+  mg.y_batch = (long long)S * K * B;
+  mg.y_sym = (long long)K * B;
+  mg.n_skip = P;
+  for (int j = 0; j < P; ++j) mg.skip[j] = d->pilot_symb[j];
+  mg.x_batch = (long long)D * K * L;
+  mg.st_batch = K;
+  pusch::DnSymbols ds{};
+  for (int sym = 0; sym < S; ++sym) {
+    bool pilot = false;
+    for (int j = 0; j < P; ++j) pilot |= d->pilot_symb[j] == sym;
+    if (!pilot) ds.sym[ds.n_data++] = sym;
+  }
+  cf* He[2];
+  cf* Xe[2];
+  int* Se[2];
+  for (int e = 0; e < 2; ++e) {
+    He[e] = reinterpret_cast<cf*>(base + lay.off_h[e]);
+    Xe[e] = reinterpret_cast<cf*>(base + lay.off_x[e]);
+    Se[e] = reinterpret_cast<int*>(base + lay.off_st[e]);
+    for (int dd = 0; dd < D; ++dd) {
+      cf* H = He[e] + (long long)dd * n_slot * K * L * B;
+      if (pusch::launch_dn_grid_to_h(e ? Dn : G, nullptr, nullptr, 1, H, ds.sym[dd], L, B, S, K, n_slot, s) !=
+          hipSuccess)
+        return PUSCH_EHIP;
+      pusch::MmseGeom m1 = mg;
+      m1.d_first = dd;
+      m1.st_or = dd > 0;
+      if (pusch::launch_mmse(H, Y, Xe[e] + (long long)dd * K * L, Se[e], m1, n_slot, s) != hipSuccess)
+        return PUSCH_EHIP;
+    }
+  }
+  // fallback test: the post-MMSE residual of each over the data REs, and the pick
+  if (pusch::launch_dn_residual(He[0], He[1], Xe[0], Xe[1], Y, res, ds, L, B, K, n_slot, (long long)S * K * B, s) !=
+      hipSuccess)
+    return PUSCH_EHIP;
+  if (pusch::launch_dn_select(res, Xe[0], Xe[1], Se[0], Se[1], reinterpret_cast<cf*>(x_hat), status, used_dn,
+                              (long long)D * K * L, K, n_slot, s) != hipSuccess)
+    return PUSCH_EHIP;
+  return PUSCH_OK;
+}
+
+}  // extern "C"

@@ -145,4 +145,64 @@ bool mmse_fusable(int n_ue, int n_beams, long long y_batch);
 hipError_t launch_mmse_fused(const cf* Y, const int2* taps, int n_tap, const ChestGeom& cg, cf* Xhat, int* status,
                              const MmseGeom& g, long long batch, hipStream_t s);
 
+// ---------------------------------------------------------------- LS-estimate denoiser
+// Four 3x3 convolution layers 2 -> 32 -> 32 -> 32 -> 2 over every [S][K] grid
+// (complex values = two channels), ReLU after the first three, output added
+// to the input.  Parameters: one FP32 vector, per layer W[c_out][3][3][c_in]
+// then b[c_out].  Hidden activations are bfloat16 [position][32].
+constexpr int kDnW1 = 32 * 9 * 2, kDnW2 = 32 * 9 * 32, kDnW4 = 2 * 9 * 32;
+constexpr int kDnParams = (kDnW1 + 32) + 2 * (kDnW2 + 32) + (kDnW4 + 2);
+constexpr int kDnWgradBlocks = 1024;  // workgroups (and partial sums) of one weight-gradient pass
+int dn_wgrad_blocks(int n_cu);
+// Workspace of n_grid grids: the three hidden activations (written by the
+// forward pass, read by the backward pass), two FP32 gradient buffers, the
+// weight-gradient partial sums and the loss partial sums (byte offsets).
+struct DnLayout {
+  long long off_act[3], off_dz[2], off_part, off_loss, total, fwd_total;
+};
+DnLayout dn_layout(int n_symb, int n_sc, long long n_grid, int n_cu);
+// out = grid + sigma f(grid / sigma): the network on the grid in units of sigma
+// (the noise standard deviation when the network was trained so), its
+// correction scaled back; sigma = 1 is the plain network.
+hipError_t launch_dn_forward(const float* params, const cf* grid, cf* out, int S, int K, long long n_grid, char* ws,
+                             const DnLayout& lay, int n_cu, hipStream_t s, float sigma = 1.f);
+// Gradients of a loss with respect to the parameters, from dL/d(out) and the
+// activations the last forward pass (with sigma = 1) over the same grids left in ws.
+hipError_t launch_dn_backward(const float* params, const cf* grid, const cf* dout, float* grads, int S, int K,
+                              long long n_grid, char* ws, const DnLayout& lay, int n_cu, hipStream_t s);
+// weights: one per grid of per_grid entries (nullptr: all 1).
+hipError_t launch_dn_loss(const cf* out, const cf* target, const float* weights, long long per_grid, cf* dout,
+                          float* loss, long long n, char* ws, const DnLayout& lay, hipStream_t s);
+hipError_t launch_dn_adam(float* params, const float* grads, float* m, float* v, int n, float lr, float b1, float b2,
+                          float eps, float c1, float c2, hipStream_t s);
+// LS estimate on every symbol of every (UE, beam) pair: grid [item][n_ue][n_beams][n_symb][n_sc].
+// Pilot symbol j of item i is RE-major at Y + i * y_batch + y_off[j]; pilots at
+// P + i * p_batch + j * n_sc.
+struct DnGridGeom {
+  int n_beams, n_ue, n_sc, n_symb, n_pilot;
+  int pilot_sym[kMaxPilots];
+  long long y_off[kMaxPilots];
+  long long y_batch, p_batch;
+};
+hipError_t launch_dn_ls_grid(const cf* Y, const cf* pilots, cf* grid, const DnGridGeom& g, long long batch,
+                             hipStream_t s);
+// Detection input from grids: H[item][n_sc][n_ue][n_beams] = symbol s of
+// (use_b && use_b[item / per_use] ? b : a) [item][n_ue][n_beams][n_symb][n_sc].
+hipError_t launch_dn_grid_to_h(const cf* a, const cf* b, const int* use_b, long long per_use, cf* H, int s_idx,
+                               int n_ue, int n_beams, int n_symb, int n_sc, long long n_item, hipStream_t s);
+// Fallback test: res[slot][e] = post-MMSE residual of estimate e (0: LS, 1:
+// denoised) over the slot's data REs; H_e: [data symbol][slot][n_sc][n_ue][n_beams],
+// X_e: [slot][data symbol][n_sc][n_ue], Y: [slot][n_symb][n_sc][n_beams] (y_slot apart).
+struct DnSymbols {
+  int n_data;
+  int sym[kMaxSymbols];
+};
+hipError_t launch_dn_residual(const cf* H0, const cf* H1, const cf* X0, const cf* X1, const cf* Y, float* res,
+                              const DnSymbols& ds, int n_ue, int n_beams, int n_sc, long long n_slot,
+                              long long y_slot, hipStream_t s);
+// X[slot] = res DN <= res LS ? X1 : X0 (per_slot entries each), the same for the
+// status flags (st: [slot][n_sc], or nullptr), used[slot] (or nullptr) = the choice.
+hipError_t launch_dn_select(const float* res, const cf* X0, const cf* X1, const int* st0, const int* st1, cf* X,
+                            int* st, int* used, long long per_slot, int n_sc, long long n_slot, hipStream_t s);
+
 }  // namespace pusch

@@ -67,6 +67,14 @@ _SIG = {
     "pusch_cells_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SlotDesc), _I, ctypes.POINTER(_LL), _I]),
     "pusch_cells": (_I, [ctypes.POINTER(SlotDesc), _I, ctypes.POINTER(_LL), ctypes.POINTER(_P), ctypes.POINTER(_P),
                          ctypes.POINTER(_P), _P, ctypes.c_size_t, _I, _P]),
+    "pusch_dn_workspace_bytes": (ctypes.c_size_t, [_I, _I, _LL]),
+    "pusch_dn_ls_grid": (_I, [_P, _P, _P, _I, _I, _I, _I, _I, ctypes.POINTER(_I), _LL, _P]),
+    "pusch_dn_forward": (_I, [_P, _P, _P, _F, _I, _I, _LL, _P, ctypes.c_size_t, _P]),
+    "pusch_dn_backward": (_I, [_P, _P, _P, _P, _I, _I, _LL, _P, ctypes.c_size_t, _P]),
+    "pusch_dn_loss": (_I, [_P, _P, _P, _P, _P, _I, _I, _LL, _P, ctypes.c_size_t, _P]),
+    "pusch_dn_adam": (_I, [_P, _P, _P, _P, _I, _F, _F, _F, _F, _P]),
+    "pusch_slot_denoised_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SlotDesc), _LL]),
+    "pusch_slot_denoised": (_I, [ctypes.POINTER(SlotDesc), _LL, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "pusch_profile_begin": (_I, [_I]),
     "pusch_profile_end": (_I, [ctypes.POINTER(_F), _I]),
 }
@@ -456,3 +464,146 @@ def profile_end() -> tuple[int, dict]:
     buf = (ctypes.c_float * len(SLOT_STAGES))()
     calls = _check(lib().pusch_profile_end(buf, len(SLOT_STAGES)), "pusch_profile_end")
     return calls, {name: float(buf[i]) for i, name in enumerate(SLOT_STAGES)}
+
+
+# ----------------------------------------------------------------------------- LS-estimate denoiser
+
+DN_PARAMS = 19682
+
+
+def _f32(t, n, name):
+    return _sized(t, n, torch.float32, name)
+
+
+def dn_ls_grid(Yp: torch.Tensor, pilots: torch.Tensor, n_ue: int, n_symb: int, pilot_symb,
+               out: torch.Tensor | None = None) -> torch.Tensor:
+    """LS estimate on every symbol: Yp [batch, n_pilot, n_sc, n_beams], pilots [batch, n_pilot, n_sc]
+    -> grid [batch, n_ue, n_beams, n_symb, n_sc]."""
+    _c64(Yp, "Yp")
+    _c64(pilots, "pilots")
+    batch, n_pilot, n_sc, n_beams = Yp.shape
+    if tuple(pilots.shape) != (batch, n_pilot, n_sc):
+        raise PuschError("dn_ls_grid: pilots must be [batch, n_pilot, n_sc]")
+    ps = list(pilot_symb)
+    if len(ps) != n_pilot:
+        raise PuschError("dn_ls_grid: one symbol index per pilot symbol")
+    if out is None:
+        out = torch.empty(batch, n_ue, n_beams, n_symb, n_sc, dtype=torch.complex64, device=Yp.device)
+    _sized(out, batch * n_ue * n_beams * n_symb * n_sc, torch.complex64, "out")
+    if batch == 0:
+        return out
+    arr = (_I * n_pilot)(*ps)
+    _check(lib().pusch_dn_ls_grid(Yp.data_ptr(), pilots.data_ptr(), out.data_ptr(), n_beams, n_ue, n_sc, n_symb,
+                                  n_pilot, arr, batch, _stream()), "pusch_dn_ls_grid")
+    return out
+
+
+class Denoiser:
+    """Workspace for running and training the LS-estimate denoiser on n_grid grids of n_symb x n_sc
+    (complex [n_grid, n_symb, n_sc]).  Parameters are a float32 tensor of DN_PARAMS values."""
+
+    def __init__(self, n_symb: int, n_sc: int, n_grid: int, device="cuda"):
+        nbytes = int(lib().pusch_dn_workspace_bytes(n_symb, n_sc, n_grid))
+        if nbytes == 0:
+            raise PuschError("pusch_dn_workspace_bytes rejected the grid shape")
+        self.n_symb, self.n_sc, self.n_grid = n_symb, n_sc, n_grid
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.ws_bytes = nbytes
+        self.loss_buf = torch.zeros(1, dtype=torch.float32, device=device)
+
+    def _grid(self, t, name):
+        return _sized(t, self.n_grid * self.n_symb * self.n_sc, torch.complex64, name)
+
+    def forward(self, params: torch.Tensor, grid: torch.Tensor, out: torch.Tensor | None = None,
+                sigma: float = 1.0) -> torch.Tensor:
+        """out = grid + sigma net(grid / sigma); sigma = 1 (the default) is the plain network."""
+        _f32(params, DN_PARAMS, "params")
+        self._grid(grid, "grid")
+        if out is None:
+            out = torch.empty_like(grid)
+        self._grid(out, "out")
+        if self.n_grid == 0:
+            return out
+        _check(lib().pusch_dn_forward(params.data_ptr(), grid.data_ptr(), out.data_ptr(), float(sigma), self.n_symb,
+                                      self.n_sc, self.n_grid, self.ws.data_ptr(), self.ws_bytes, _stream()),
+               "pusch_dn_forward")
+        return out
+
+    def loss(self, out: torch.Tensor, target: torch.Tensor, dout: torch.Tensor | None = None,
+             weights: torch.Tensor | None = None):
+        """(loss [1] float32 on the device, dout = dL/d(out)); weights: one float32 per grid, or None."""
+        self._grid(out, "out")
+        self._grid(target, "target")
+        if dout is None:
+            dout = torch.empty_like(out)
+        self._grid(dout, "dout")
+        if weights is not None:
+            _f32(weights, self.n_grid, "weights")
+        _check(lib().pusch_dn_loss(out.data_ptr(), target.data_ptr(), _ptr(weights), dout.data_ptr(),
+                                   self.loss_buf.data_ptr(), self.n_symb, self.n_sc, self.n_grid, self.ws.data_ptr(),
+                                   self.ws_bytes, _stream()), "pusch_dn_loss")
+        return self.loss_buf, dout
+
+    def backward(self, params: torch.Tensor, grid: torch.Tensor, dout: torch.Tensor,
+                 grads: torch.Tensor | None = None) -> torch.Tensor:
+        _f32(params, DN_PARAMS, "params")
+        self._grid(grid, "grid")
+        self._grid(dout, "dout")
+        if grads is None:
+            grads = torch.empty(DN_PARAMS, dtype=torch.float32, device=params.device)
+        _f32(grads, DN_PARAMS, "grads")
+        _check(lib().pusch_dn_backward(params.data_ptr(), grid.data_ptr(), dout.data_ptr(), grads.data_ptr(),
+                                       self.n_symb, self.n_sc, self.n_grid, self.ws.data_ptr(), self.ws_bytes,
+                                       _stream()), "pusch_dn_backward")
+        return grads
+
+
+def dn_adam(params: torch.Tensor, grads: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float,
+            beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+    for t, name in ((params, "params"), (grads, "grads"), (m, "m"), (v, "v")):
+        _f32(t, DN_PARAMS, name)
+    _check(lib().pusch_dn_adam(params.data_ptr(), grads.data_ptr(), m.data_ptr(), v.data_ptr(), int(step), float(lr),
+                               float(beta1), float(beta2), float(eps), _stream()), "pusch_dn_adam")
+
+
+class DenoisedSlot:
+    """The receive chain with the denoised LS estimate and the LS fallback (pusch_slot_denoised) for a
+    fixed slot geometry; each call returns (x_hat, status, used_dn [n_slot] int32)."""
+
+    def __init__(self, n_ant: int, n_fft: int, n_sc: int, n_symb: int, n_beams: int, n_ue: int, pilot_symb,
+                 sigma2: float, n_slot: int, W: torch.Tensor | None = None, device="cuda"):
+        pilot_symb = list(pilot_symb)
+        self.desc = SlotDesc()
+        d = self.desc
+        _fill_desc(d, n_ant, n_fft, n_sc, n_symb, n_beams, n_ue, pilot_symb, sigma2, W, n_slot, device)
+        if sigma2 is None:
+            raise PuschError("the denoised chain takes sigma2 as given")
+        self.W = None if W is None else _beamformer(W, n_beams, n_ant, "W")
+        d.W = _ptr(self.W)
+        self.n_slot = n_slot
+        self.n_data = n_symb - len(pilot_symb)
+        nbytes = lib().pusch_slot_denoised_workspace_bytes(ctypes.byref(d), n_slot)
+        if nbytes == 0 and n_slot > 0:
+            raise PuschError("the library rejected the slot geometry (workspace size 0)")
+        self.ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        self.ws_bytes = int(nbytes)
+
+    def __call__(self, x_td: torch.Tensor, pilots: torch.Tensor, params: torch.Tensor):
+        d = self.desc
+        _c64(x_td, "x_td")
+        _c64(pilots, "pilots")
+        _f32(params, DN_PARAMS, "params")
+        if tuple(x_td.shape) != (self.n_slot, d.n_symb, d.n_ant, d.n_fft):
+            raise PuschError(f"x_td must be [{self.n_slot}, {d.n_symb}, {d.n_ant}, {d.n_fft}]")
+        if tuple(pilots.shape) != (self.n_slot, d.n_pilot, d.n_sc):
+            raise PuschError(f"pilots must be [{self.n_slot}, {d.n_pilot}, {d.n_sc}]")
+        x_hat = torch.empty(self.n_slot, self.n_data, d.n_sc, d.n_ue, dtype=torch.complex64, device=x_td.device)
+        status = torch.empty(self.n_slot, d.n_sc, dtype=torch.int32, device=x_td.device)
+        used = torch.empty(self.n_slot, dtype=torch.int32, device=x_td.device)
+        if self.n_slot == 0:
+            return x_hat, status, used
+        d.pilots = pilots.data_ptr()
+        _check(lib().pusch_slot_denoised(ctypes.byref(d), self.n_slot, x_td.data_ptr(), params.data_ptr(),
+                                         x_hat.data_ptr(), status.data_ptr(), used.data_ptr(), self.ws.data_ptr(),
+                                         self.ws_bytes, _stream()), "pusch_slot_denoised")
+        return x_hat, status, used

@@ -23,7 +23,7 @@ def lib():
 
 def test_exports_every_declared_symbol(lib):
     names = pusch.header_symbols()
-    assert len(names) == 17
+    assert len(names) == 25
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(pusch._SIG)
@@ -306,3 +306,62 @@ def test_slot_mixed_workspace_and_validation(lib):
     need = lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(d), 2)
     assert f(ctypes.byref(d), 2, FAKE, FAKE2, None, ws, need - 1, None) == ENOMEM
     assert f(ctypes.byref(d), 0, FAKE, FAKE2, None, ws, need, None) == 0
+
+
+def test_denoiser_workspace_and_validation(lib):
+    a = lambda v: (v + 255) // 256 * 256
+    n, S, K = 64, 14, 256
+    P = n * S * K
+    # three bfloat16 activations of 32 channels, two FP32 gradient buffers, 1024 x 9248 partial sums, loss parts
+    assert lib.pusch_dn_workspace_bytes(S, K, n) == 3 * a(P * 64) + 2 * a(P * 128) + a(1024 * 9248 * 4) + a(1024)
+    assert lib.pusch_dn_workspace_bytes(0, K, n) == 0 and lib.pusch_dn_workspace_bytes(17, K, n) == 0
+    assert lib.pusch_dn_workspace_bytes(S, 4097, n) == 0 and lib.pusch_dn_workspace_bytes(S, K, -1) == 0
+    ws = ctypes.c_void_p(0x4000000000)
+    big = 1 << 40
+    Pm = ctypes.c_void_p(0x300000)
+    fw = lib.pusch_dn_forward
+    assert fw(None, FAKE, FAKE2, 1.0, S, K, n, ws, big, None) == EINVAL
+    assert fw(Pm, FAKE, FAKE2, 1.0, S, K, n, ctypes.c_void_p(0x4000000010), big, None) == EINVAL
+    assert fw(Pm, FAKE, FAKE2, 1.0, S, K, n, ws, 1024, None) == ENOMEM
+    assert fw(Pm, FAKE, ctypes.c_void_p(0x10008), 1.0, S, K, n, ws, big, None) == EINVAL  # out on grid
+    assert fw(Pm, FAKE, FAKE2, 0.0, S, K, n, ws, big, None) == EINVAL  # the noise unit must be positive
+    assert fw(Pm, FAKE, FAKE2, float("nan"), S, K, n, ws, big, None) == EINVAL
+    assert fw(Pm, FAKE, FAKE2, 1.0, S, K, 0, ws, big, None) == 0  # no grids
+    assert lib.pusch_dn_backward(Pm, FAKE, FAKE2, ctypes.c_void_p(0x500000), S, K, 0, ws, big, None) == EINVAL
+    assert lib.pusch_dn_backward(Pm, FAKE, FAKE2, Pm, S, K, n, ws, big, None) == EINVAL  # grads on params
+    assert lib.pusch_dn_loss(FAKE, FAKE2, None, ctypes.c_void_p(0x90000008), ctypes.c_void_p(0x700000), S, K, n, ws,
+                             big, None) == EINVAL  # dout on the target
+    assert lib.pusch_dn_loss(FAKE, FAKE2, ctypes.c_void_p(0x800008), ctypes.c_void_p(0x800000), ctypes.c_void_p(0x700000),
+                             S, K, n, ws, big, None) == EINVAL  # weights on dout
+    g = ctypes.c_void_p(0x500000)
+    m = ctypes.c_void_p(0x600000)
+    v = ctypes.c_void_p(0x700000)
+    f = lib.pusch_dn_adam
+    assert f(Pm, g, m, v, 0, 1e-3, 0.9, 0.999, 1e-8, None) == EINVAL  # steps count from 1
+    assert f(Pm, g, m, v, 1, 0.0, 0.9, 0.999, 1e-8, None) == EINVAL
+    assert f(Pm, g, m, v, 1, 1e-3, 1.0, 0.999, 1e-8, None) == EINVAL
+    assert f(Pm, g, m, m, 1, 1e-3, 0.9, 0.999, 1e-8, None) == EINVAL  # m and v overlap
+    ps = (ctypes.c_int * 1)(2)
+    lg = lib.pusch_dn_ls_grid
+    assert lg(FAKE, FAKE2, ws, 16, 4, 3, 14, 1, ps, 2, None) == EINVAL  # a UE without a pilot position
+    assert lg(FAKE, FAKE2, ws, 16, 4, 256, 2, 1, ps, 2, None) == EINVAL  # pilot symbol outside the slot
+    assert lg(FAKE, FAKE2, ws, 16, 4, 256, 14, 1, None, 2, None) == EINVAL
+    assert lg(FAKE, FAKE2, ws, 16, 4, 256, 14, 1, ps, 0, None) == 0  # empty batch
+
+
+def test_slot_denoised_workspace_and_validation(lib):
+    d = _desc(n_ant=16, n_fft=256, n_sc=256, n_beams=16, n_ue=4, n_pilot=1, pilot_symb=(2,))
+    need = lib.pusch_slot_denoised_workspace_bytes(ctypes.byref(d), 2)
+    assert need > 0
+    assert lib.pusch_slot_denoised_workspace_bytes(ctypes.byref(_desc(refine=1)), 2) == 0
+    assert lib.pusch_slot_denoised_workspace_bytes(ctypes.byref(_desc(time_varying=1)), 2) == 0
+    assert lib.pusch_slot_denoised_workspace_bytes(ctypes.byref(_desc(noise_est=1)), 2) == 0
+    assert lib.pusch_slot_denoised_workspace_bytes(ctypes.byref(_desc(sigma2=0.0)), 2) == 0  # the network's unit
+    ws = ctypes.c_void_p(0x4000000000)
+    Pm = ctypes.c_void_p(0x300000)
+    f = lib.pusch_slot_denoised
+    assert f(ctypes.byref(d), 2, FAKE, None, FAKE2, None, None, ws, need, None) == EINVAL  # no parameters
+    assert f(ctypes.byref(d), 2, FAKE, Pm, FAKE2, None, None, ws, need - 1, None) == ENOMEM
+    assert f(ctypes.byref(d), 2, FAKE, Pm, FAKE2, None, None, ctypes.c_void_p(0x4000000010), need, None) == EINVAL
+    assert f(ctypes.byref(d), 2, FAKE, Pm, FAKE2, None, ctypes.c_void_p(0x90000004), ws, need, None) == EINVAL
+    assert f(ctypes.byref(d), 0, FAKE, Pm, FAKE2, None, None, ws, need, None) == 0
