@@ -6,8 +6,10 @@
 // a radix-4 decimation-in-frequency FFT whose operands are folded into each
 // core's local banks (Sec. V-A); here each 16-point butterfly is done in a
 // thread's registers (a 4x4 split), and the data exchange between passes goes
-// through LDS with one padding slot per 16 elements, which keeps every
-// 8-byte LDS access of a wavefront conflict-free for all supported sizes.
+// through LDS with one padding slot per 16 elements, which spreads the
+// strided accesses of a pass over the banks.  It does not remove every
+// conflict: the hardware counter (SQ_LDS_BANK_CONFLICT) still reports about
+// 1,800 conflict cycles per wave at N = 4096, about 2 % of the wave's time.
 //
 // One workgroup of 256 threads owns 4096/N transforms at a time (N/16 threads
 // per transform, 16 values per thread) and loops over the batch, so each
