@@ -177,7 +177,9 @@ int pusch_noise_est_static(const pusch_c32* Yp, const pusch_c32* pilots, float* 
  * Cholesky factor G = L L^H (Crout order, Sec. V-C), then for every data
  * symbol the matched filter b = H^H y, forward substitution L z = b and back
  * substitution L^H x = z.  One factorisation per subcarrier serves all data
- * symbols of the call.
+ * symbols of the call.  With more than 16 UEs and n_ue > n_beams / 2 (Gram
+ * matrices of condition numbers 1e3..1e5 at high SNR) one step of iterative
+ * refinement follows, as the slot option refine describes.
  *   H      [batch][n_sc][n_ue][n_beams] as written by pusch_chest.
  *   Yd     [batch][n_data][n_sc][n_beams] RE-major data symbols.
  *   Xhat   [batch][n_data][n_sc][n_ue] detected symbols (0 where status = 1).
@@ -209,10 +211,15 @@ typedef struct {
                                        or NULL; must not overlap any other buffer of the call */
   int refine;                       /* nonzero: one step of iterative refinement of the MIMO solve
                                        (residual H^H (y - H x) - sigma2 x from the channel estimate
-                                       and the data symbols, solved with the same Cholesky factor);
+                                       and the data symbols, solved with the same Cholesky factor;
+                                       the residual in FP64 for a subcarrier whose condition
+                                       estimate ||G||_F ||G^-1||_F (the latter from +-1 probe
+                                       vectors) exceeds 1e4, FP32 otherwise);
                                        for ill-conditioned Gram matrices (n_ue close to n_beams), where
                                        the 32-bit arithmetic of Sec. VI alone loses accuracy.
-                                       Uses a stored channel estimate (larger workspace) */
+                                       Uses a stored channel estimate (larger workspace).  With more
+                                       than 16 UEs and n_ue > n_beams / 2 the detection refines even
+                                       when this is 0 */
   int time_varying;                 /* nonzero: a channel that changes over the slot -- each pilot
                                        symbol gives its own estimate (from its own comb positions),
                                        data symbol s uses their linear interpolation in s between the

@@ -131,7 +131,8 @@ struct MmseGeom {
   int n_beams, n_ue, n_sc, n_data;
   float sigma2;
   const float* sigma2_item;   // device [batch] noise variance per batch item, or nullptr = sigma2
-  int refine;                 // nonzero: one step of iterative refinement (stored-estimate path only)
+  int refine;                 // nonzero: one step of iterative refinement (stored-estimate path only;
+                              //   launch_mmse also refines when mmse_auto_refine)
   int st_or;                  // nonzero: OR the status flags into st instead of writing them
 };
 hipError_t launch_mmse(const cf* H, const cf* Y, cf* Xhat, int* status, const MmseGeom& g, long long batch,
@@ -142,6 +143,9 @@ hipError_t launch_mmse(const cf* H, const cf* Y, cf* Xhat, int* status, const Mm
 // launch_comb_taps, instead of read from a stored estimate.  Requires
 // mmse_fusable(n_ue, n_beams, y_batch).
 bool mmse_fusable(int n_ue, int n_beams, long long y_batch);
+// Beyond 16 UEs with more than half as many UEs as beams the detection
+// refines its solve without being asked (the Gram matrices are ill-conditioned).
+bool mmse_auto_refine(int n_ue, int n_beams);
 hipError_t launch_mmse_fused(const cf* Y, const int2* taps, int n_tap, const ChestGeom& cg, cf* Xhat, int* status,
                              const MmseGeom& g, long long batch, hipStream_t s);
 

@@ -25,6 +25,12 @@
 //   and the matched filter run on 16x16x4 FP32 MFMAs as above, through LDS;
 //   then lane i of a group of 32 holds row i of G and L for the Crout
 //   factorisation and the substitutions (rows broadcast by lane permutes).
+//   With refinement (asked for, or beyond 16 UEs with N_L > N_B / 2), one step
+//   of iterative refinement: the residual H^H (y - H x0) - sigma^2 x0 from the
+//   stored estimate and the data symbols, on FP32 MFMA, or in FP64 for a
+//   subcarrier whose condition estimate exceeds 1e4 (||G||_F times a
+//   Hutchinson estimate of ||G^-1||_F from +-1 probe vectors solved in the
+//   spare right-hand-side slots), solved with the same factor.
 #include <cmath>
 
 #include "kernels.h"
@@ -33,6 +39,10 @@ namespace pusch {
 namespace {
 
 constexpr int kMaxD = 16;  // data symbols per kernel call (host splits larger requests)
+// Subcarriers whose condition estimate exceeds this get their refinement
+// residual in FP64.
+constexpr float kFp64Cond = 1e4f;
+constexpr int kProbes = 4;  // probe vectors of the condition estimate
 
 // ---- shared by both detection kernels: MFMA operands and cross-lane moves
 
@@ -210,8 +220,10 @@ __device__ __forceinline__ void row_solve(cf (&v)[kMaxD], const cf (&L)[LPS], fl
   }
 }
 
-// REFINE: one step of iterative refinement (g.refine), a separate instance so
-// the plain path keeps its registers.
+// REFINE: after the first solve, one step of iterative refinement (a separate
+// instance, so the plain path keeps its registers and LDS); the residual is
+// FP32 on MFMA, or FP64 for a subcarrier whose condition estimate exceeds
+// kFp64Cond.
 template <int LPS, bool REFINE>
 __global__ __launch_bounds__(64, 2) void k_mmse_rows(const cf* __restrict__ H, const cf* __restrict__ Y, cf* __restrict__ Xh,
                                              int* __restrict__ st, MmseGeom g, LdsGeom lg, long long nblk,
@@ -294,15 +306,29 @@ __global__ __launch_bounds__(64, 2) void k_mmse_rows(const cf* __restrict__ H, c
 #pragma unroll
       for (int j = 0; j < LPS; ++j) G[j] = j <= i ? Gr[j] : cf{0.f, 0.f};
     }
+    float gii = 0.f;  // this row's regularised diagonal entry
 #pragma unroll
     for (int j = 0; j < LPS; ++j)
-      if (j == i) G[j].r += s2;
+      if (j == i) {
+        G[j].r += s2;
+        gii = G[j].r;
+      }
     cf rr[kMaxD];
     {
       const cf* Pr = sm + lg.poff + grp * lg.pg + i * lg.prow;
 #pragma unroll
       for (int d = 0; d < kMaxD; ++d) rr[d] = (d < nd && i < nue) ? Pr[d] : cf{0.f, 0.f};
     }
+    // With refinement, the right-hand sides past the data symbols carry probe
+    // vectors of +-1 entries (a fixed sign pattern per slot), so the same
+    // substitutions give z = G^-1 v for the condition estimate below.
+    const int nprobe = REFINE ? min(kProbes, kMaxD - nd) : 0;
+#pragma unroll
+    for (int d = 0; d < kMaxD; ++d)
+      if (d >= nd && d < nd + nprobe && i < nue) rr[d] = cf{(((i * (2 * d + 3) + d) >> 1) & 1) ? -1.f : 1.f, 0.f};
+    float gfro = 0.f;  // sum of |G_ij|^2 over this row's lower triangle
+#pragma unroll
+    for (int j = 0; j < LPS; ++j) gfro += G[j].r * G[j].r + G[j].i * G[j].i;
 
     // Cholesky-Crout: column j uses row j of L (lane j of the group)
     int fail = 0;
@@ -337,9 +363,32 @@ __global__ __launch_bounds__(64, 2) void k_mmse_rows(const cf* __restrict__ H, c
     for (int m = 0; m < LPS; ++m) Ls[grp * lg.lgrp + i * lg.lrow + m] = L[m];
     __syncthreads();
 
-    row_solve<LPS>(rr, L, invd, Ls + grp * lg.lgrp, lg.lrow, i, gbase, nue, nd);
+    row_solve<LPS>(rr, L, invd, Ls + grp * lg.lgrp, lg.lrow, i, gbase, nue, nd + nprobe);
 
     if constexpr (REFINE) {
+      // Condition estimate of each subcarrier's G: ||G||_F ||G^-1||_F, with
+      // ||G^-1||_F^2 the mean of |G^-1 v|^2 over the probes (E[v v^H] = I for
+      // independent +-1 entries); ||G||_F^2 from the lower triangles.  It is
+      // at least the 2-norm condition number up to the probes' sampling error.
+      // Without a spare right-hand side (16 data symbols): max_i G_ii /
+      // min_i L_ii^2, a lower bound.
+      float zsq = 0.f;
+#pragma unroll
+      for (int d = 0; d < kMaxD; ++d)
+        if (d >= nd && d < nd + nprobe) zsq += rr[d].r * rr[d].r + rr[d].i * rr[d].i;
+      float fro = (i < nue) ? 2.f * gfro - gii * gii : 0.f;  // off-diagonal entries count twice
+      float gmax = (i < nue) ? gii : 0.f, dmax = (i < nue) ? invd : 0.f;  // invd = 1 / L_ii
+#pragma unroll
+      for (int o = 16; o >= 1; o >>= 1) {
+        zsq += __shfl_xor(zsq, o);
+        fro += __shfl_xor(fro, o);
+        gmax = fmaxf(gmax, __shfl_xor(gmax, o));
+        dmax = fmaxf(dmax, __shfl_xor(dmax, o));
+      }
+      const float kap_own = nprobe > 0 ? sqrtf(fro * zsq / (float)nprobe) : gmax * dmax * dmax;
+      float kap[SPW];
+#pragma unroll
+      for (int sc = 0; sc < SPW; ++sc) kap[sc] = __shfl(kap_own, sc * LPS);
       // One step of iterative refinement.  The residual of the normal
       // equations, r = H^H (y - H x0) - sigma^2 x0, is formed from the stored
       // estimate and the data symbols themselves (not from the rounded G);
@@ -358,6 +407,43 @@ __global__ __launch_bounds__(64, 2) void k_mmse_rows(const cf* __restrict__ H, c
         cf* Xsc = sm + lg.xoff + sc * lg.xg;  // x0 [d][UE]; then H^H e in its place
         cf* Esc = sm + lg.eoff + sc * lg.eg;  // e [d][beam]
         const cf* Hb = H + bi * g.h_batch + (long long)(k0 + sc) * nue * nb;
+        if (kap[sc] > kFp64Cond) {
+          // Ill-conditioned: the whole residual r = H^H (y - H x0) - sigma^2 x0 in
+          // FP64 (products of FP32 values are exact there), rounded once to FP32
+          // into x0's place.  e [d][beam] in FP64 spans the E region of both
+          // subcarriers (used one subcarrier at a time).
+          double* E = reinterpret_cast<double*>(sm + lg.eoff);
+          const cf* yb = Y + bi * g.y_batch + (long long)(k0 + sc) * nb;
+          for (int t = lane; t < nd * nb; t += 64) {
+            const int d = t / nb, b = t - d * nb;
+            const cf y = yb[data_grid(g, d) + b];
+            double er = y.r, ei = y.i;
+            for (int l = 0; l < nue; ++l) {
+              const cf h = Hb[(long long)l * nb + b], x = Xsc[d * lg.xd + l];
+              er -= (double)h.r * x.r - (double)h.i * x.i;
+              ei -= (double)h.r * x.i + (double)h.i * x.r;
+            }
+            E[2 * t] = er;
+            E[2 * t + 1] = ei;
+          }
+          __syncthreads();
+          // r[d][l]: each entry reads only its own x0[d][l] (and E), so it can
+          // replace it at once
+          for (int t = lane; t < nd * nue; t += 64) {
+            const int d = t / nue, l = t - d * nue;
+            const cf x = Xsc[d * lg.xd + l];
+            double ar = -(double)s2 * x.r, ai = -(double)s2 * x.i;
+            for (int b = 0; b < nb; ++b) {
+              const cf h = Hb[(long long)l * nb + b];
+              const double er = E[2 * (d * nb + b)], ei = E[2 * (d * nb + b) + 1];
+              ar += (double)h.r * er + (double)h.i * ei;  // conj(h) e
+              ai += (double)h.r * ei - (double)h.i * er;
+            }
+            Xsc[d * lg.xd + l] = cf{(float)ar, (float)ai};
+          }
+          __syncthreads();
+          continue;
+        }
         const cf* ysrc = Y + bi * g.y_batch + data_grid(g, c16 < nd ? c16 : 0) + (long long)(k0 + sc) * nb;
         // e = y - H x0: A[m][k] = H[beam 16 bb + m][UE k], B[k][n] = x0[UE k][symbol n];
         // a b as T1 = ar br, T2 = ai bi, T3 = (ar + ai)(br + bi)
@@ -418,14 +504,16 @@ __global__ __launch_bounds__(64, 2) void k_mmse_rows(const cf* __restrict__ H, c
         }
       }
       __syncthreads();
-      // r_i = (H^H e)_i - sigma^2 x0_i (x0 is still in rr)
+      // r_i = (H^H e)_i - sigma^2 x0_i (x0 is still in rr); an FP64 subcarrier's
+      // slot already holds the whole residual
       cf r[kMaxD];
       {
         const cf* Rg = sm + lg.xoff + grp * lg.xg;
+        const float s2r = kap_own > kFp64Cond ? 0.f : s2;
 #pragma unroll
         for (int d = 0; d < kMaxD; ++d) {
           const cf he = (d < nd && i < nue) ? Rg[d * lg.xd + i] : cf{0.f, 0.f};
-          r[d] = cf{he.r - s2 * rr[d].r, he.i - s2 * rr[d].i};
+          r[d] = cf{he.r - s2r * rr[d].r, he.i - s2r * rr[d].i};
         }
       }
       row_solve<LPS>(r, L, invd, Ls + grp * lg.lgrp, lg.lrow, i, gbase, nue, nd);
@@ -797,6 +885,8 @@ hipError_t dispatch_mfma(const cf* H, const cf* Y, const int2* taps, const Chest
 
 }  // namespace
 
+bool mmse_auto_refine(int n_ue, int n_beams) { return n_ue > 16 && 2 * n_ue > n_beams; }
+
 bool mmse_fusable(int n_ue, int n_beams, long long y_batch) {
   // MFMA tile of 16 UEs; paired 16-byte beam loads; 32-bit tap offsets
   return n_ue >= 1 && n_ue <= 16 && n_beams >= 2 && n_beams <= 64 && n_beams % 2 == 0 && y_batch < (1ll << 31);
@@ -805,9 +895,19 @@ bool mmse_fusable(int n_ue, int n_beams, long long y_batch) {
 hipError_t launch_mmse(const cf* H, const cf* Y, cf* Xhat, int* status, const MmseGeom& g, long long batch,
                        hipStream_t s) {
   if (g.n_data > kMaxD || g.n_data < 1) return hipErrorInvalidValue;
-  // refinement: the row kernel (any n_ue up to 32)
+  // refinement: the row kernel (any n_ue up to 32).  Beyond 16 UEs with more
+  // than half as many UEs as beams it refines without being asked: the
+  // smallest eigenvalue of H^H H shrinks like (1 - sqrt(N_L / N_B))^2 relative
+  // to the largest (for channels with independent entries), so the
+  // regularised Gram matrices reach condition numbers of 1e3..1e5 at high SNR,
+  // where the FP32 solve alone misses 1e-4; at N_B >= 2 N_L they stay near
+  // 1e1..1e2.
   if (g.n_ue <= 16 && !g.refine) return dispatch_mfma<false, 0>(H, Y, nullptr, ChestGeom{}, Xhat, status, g, batch, s);
-  if (g.n_ue <= 32) return launch_lps<32>(H, Y, Xhat, status, g, batch, s);
+  if (g.n_ue <= 32) {
+    MmseGeom gr = g;
+    gr.refine = g.refine || mmse_auto_refine(g.n_ue, g.n_beams);
+    return launch_lps<32>(H, Y, Xhat, status, gr, batch, s);
+  }
   return hipErrorInvalidValue;
 }
 

@@ -7,8 +7,11 @@ condition numbers of 1e4..1e5 and the FP32 Cholesky solve alone leaves
 errors of a few 1e-4 against the oracle, while an exact solve from the FP32
 beam-domain grids would be within ~3e-7 of it (the floor set by the
 grids' rounding).  One refinement step, with the residual formed from the
-channel estimate and the data symbols instead of the rounded Gram matrix,
-must bring the detected symbols within the chain's tolerance (NRMSE 1e-4).
+channel estimate and the data symbols instead of the rounded Gram matrix
+(in FP64 where the subcarrier's condition estimate exceeds 1e4), must bring
+the detected symbols within the chain's tolerance (NRMSE 1e-4, every element
+and subcarrier within 1e-3).  Beyond 16 UEs the chain refines on its own the
+subcarriers whose estimate exceeds 1e3.
 """
 import numpy as np
 import pytest
@@ -54,13 +57,13 @@ def test_refinement_at_the_stress_point(snr_db):
                          n_beams=cfg.n_beams)
     e0, e1 = M.nrmse(x0[0], ref["x_hat"]), M.nrmse(x1[0], ref["x_hat"])
     cond = np.linalg.cond(O.gram(ref["H"], b["sigma2"]))
-    print(f"[refine] {snr_db} dB: cond median {np.median(cond):.3g} max {cond.max():.3g}; "
-          f"NRMSE plain {e0:.2e} refined {e1:.2e}", flush=True)
+    print(f"[refine] {snr_db} dB: cond median {np.median(cond):.3g} max {cond.max():.3g} "
+          f"(> 1e4: {np.mean(cond > 1e4):.1%}); NRMSE automatic {e0:.2e} all {e1:.2e}", flush=True)
     assert np.all(st1 == 0) and np.all(st0 == 0)
-    assert e1 <= TOL_X and e1 <= e0 / 3
-    assert_xhat(x1[0], ref["x_hat"], TOL_X)
-    if snr_db == 30.0:
-        assert e0 > TOL_X  # the case refinement is for
+    # beyond 16 UEs the chain refines on its own the subcarriers whose condition estimate exceeds
+    # 1e3 (refine unset), and every subcarrier with refine set; FP64 residual beyond 1e4
+    assert_xhat(x0[0], ref["x_hat"], TOL_X, "refined where ill-conditioned")
+    assert_xhat(x1[0], ref["x_hat"], TOL_X, "refined everywhere")
 
 
 def test_refinement_paper_scale_well_conditioned():
