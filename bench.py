@@ -281,27 +281,63 @@ def bench_time_varying(args, cfg, batch, x, p, x_hat32, ms32: float) -> dict:
             "status_flags": int(st.sum().item())}
 
 
+def _cell_chain_bytes(c: dict) -> int:
+    """Algorithmic HBM bytes of one slot of a cell through the fused chain (as STAGE_BYTES)."""
+    s_, r_, n_, k_, b_, l_, np_ = c["n_symb"], c["n_ant"], c["n_fft"], c["n_sc"], c["n_beams"], c["n_ue"], \
+        len(c["pilot_symb"])
+    d_ = s_ - np_
+    return (s_ * r_ * n_ * 8 + s_ * r_ * k_ * 8                                        # FFT
+            + s_ * r_ * k_ * 8 + b_ * r_ * 8 + np_ * k_ * 8 + s_ * k_ * b_ * 8           # beamforming
+            + np_ * k_ * b_ * 8 + d_ * k_ * b_ * 8 + d_ * k_ * l_ * 8 + k_ * 4)          # detection
+
+
+def cells_cpu_baseline(cfgs, batches, got) -> tuple[dict, dict]:
+    """The oracle over every cell's slot, single-threaded, timed; and the GPU's detected symbols of
+    each cell against it (NRMSE, worst over the cells)."""
+    from oracle import metrics as M
+    from oracle import pusch_oracle as O
+
+    t0 = time.perf_counter()
+    worst, flagged = 0.0, 0
+    for c, (cfg, b) in enumerate(zip(cfgs, batches)):
+        ref = O.receive_slot(b["x_td"][0], b["pilots"][0], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
+                             n_beams=cfg.n_beams)
+        e = M.xhat_errors(got[c][0], ref["x_hat"])
+        worst = max(worst, e["nrmse"])
+        flagged += int(e["nrmse"] > 1e-4 or e["max_rel"] > 1e-3 or e["worst_sc"] > 1e-3)
+    dt = time.perf_counter() - t0
+    base = {"value": round(len(cfgs) / dt, 3), "unit": "slots/s", "cores": 1, "kind": "oracle",
+            "sample": f"all {len(cfgs)} cells, one slot each, FP64, one thread"}
+    check = {"cells": len(cfgs), "max_nrmse": float(f"{worst:.3g}"), "cells_out_of_tolerance": flagged,
+             "tolerance": "NRMSE 1e-4, max-rel and worst-subcarrier 1e-3", "pass": flagged == 0}
+    return base, check
+
+
 def bench_cells(n_cells: int, steps: int, warmup: int) -> int:
     """Batched uneven cells: one pusch_cells call over n_cells cells of
-    different geometries, replayed from a captured HIP graph, against the same
-    cells as plain pusch_slot calls one after another on one stream."""
+    different geometries, replayed from a captured HIP graph, grouped (one
+    launch per stage and kernel shape) and on side streams, against the same
+    cells as plain pusch_slot calls one after another on one stream; then the
+    oracle over every cell (the CPU baseline) and the grouped result against it."""
     import torch
 
-    from paper_2210_09196_amd import pusch
-
-    from paper_2210_09196_amd import synth
+    from paper_2210_09196_amd import pusch, synth
 
     geoms = synth.uneven_cells(n_cells)
-    g = torch.Generator(device="cuda")
-    g.manual_seed(4001)
-    xs, ps = [], []
-    for c in geoms:
-        # seeded complex Gaussian samples of the cell's shape (the chain's
-        # work does not depend on the values) and QPSK pilots
-        xs.append(torch.view_as_complex(torch.randn(1, 14, c["n_ant"], c["n_fft"], 2, generator=g, device="cuda"))
-                  .contiguous() * 0.05)
-        ph = torch.randint(0, 4, (1, 2, c["n_sc"]), generator=g, device="cuda").float() * (np.pi / 2) + np.pi / 4
-        ps.append(torch.polar(torch.ones_like(ph), ph).to(torch.complex64).contiguous())
+    cfgs, batches = [], []
+    for c, g in enumerate(geoms):
+        # a seeded TDL slot per cell at 20 dB, QPSK..256-QAM by cell
+        cfg = synth.CFG1.replace(n_ant=g["n_ant"], n_fft=g["n_fft"], n_sc=g["n_sc"], n_beams=g["n_beams"],
+                                 n_ue=g["n_ue"], pilot_symb=g["pilot_symb"], qam_bits=(2, 4, 6, 8)[c % 4],
+                                 channel="tdl", snr_db=20.0)
+        b = synth.make_batch(cfg, [5000 + c])
+        g["sigma2"] = b["sigma2"]
+        cfgs.append(cfg)
+        batches.append(b)
+    xs = [torch.from_numpy(b["x_td"]).cuda() for b in batches]
+    ps = [torch.from_numpy(b["pilots"]).cuda() for b in batches]
+    print(f"[bench] {n_cells} cells generated", file=sys.stderr, flush=True)
+
     def timed(fn, n):
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
         for a, b in ev:
@@ -311,8 +347,8 @@ def bench_cells(n_cells: int, steps: int, warmup: int) -> int:
         torch.cuda.synchronize()
         return np.array([a.elapsed_time(b) * 1e3 for a, b in ev])  # us per call
 
-    def measure(precision):
-        cells = pusch.Cells(geoms, precision=precision)
+    def measure(precision, grouped):
+        cells = pusch.Cells(geoms, precision=precision, grouped=grouped)
         out, out_st = cells.outputs()
         run = lambda: cells(xs, ps, out, out_st)
         for _ in range(warmup):
@@ -331,22 +367,35 @@ def bench_cells(n_cells: int, steps: int, warmup: int) -> int:
         for _ in range(warmup):
             graph.replay()
         torch.cuda.synchronize()
-        return eager, timed(graph.replay, steps), out, out_st
+        replay = timed(graph.replay, steps)
+        print(f"[bench] cells {precision} {'grouped' if grouped else 'streams'}: graph p50 "
+              f"{np.percentile(replay, 50) / n_cells:.3f} us/slot", file=sys.stderr, flush=True)
+        return eager, replay, [o.cpu().numpy() for o in out], [o.cpu().numpy() for o in out_st]
 
-    eager, replay, out, out_st = measure("fp32")
-    _, replay_mixed, _, _ = measure("mixed")
+    eager, replay, out, out_st = measure("fp32", True)
+    eager_s, replay_s, out_s, _ = measure("fp32", False)
+    _, replay_mixed, _, _ = measure("mixed", True)
+    _, replay_mixed_s, _, _ = measure("mixed", False)
+    same = all(np.array_equal(a, b) for a, b in zip(out, out_s))
     slots = [pusch.Slot(c["n_ant"], c["n_fft"], c["n_sc"], 14, c["n_beams"], c["n_ue"], c["pilot_symb"], c["sigma2"], 1)
              for c in geoms]
+    seq_out = [(torch.empty(1, 12, c["n_sc"], c["n_ue"], dtype=torch.complex64, device="cuda"),
+                torch.empty(1, c["n_sc"], dtype=torch.int32, device="cuda")) for c in geoms]
 
     def sequential():
         for k, sl in enumerate(slots):
-            sl(xs[k], ps[k], out[k], out_st[k])
+            sl(xs[k], ps[k], *seq_out[k])
 
     for _ in range(warmup):
         sequential()
     torch.cuda.synchronize()
     seq = timed(sequential, steps)
+    base, check = cells_cpu_baseline(cfgs, batches, out)
+    check["grouped_equals_streams"] = same
+    check["status_flags"] = int(sum(int(np.count_nonzero(st)) for st in out_st))
     per = lambda a, q: round(float(np.percentile(a, q)) / n_cells, 3)
+    chain_bytes = sum(_cell_chain_bytes(dict(g, n_symb=14)) for g in geoms)
+    floor_us = chain_bytes / (HBM_PEAK_GBS * 1e9) * 1e6 / n_cells
     mix = {f"N{n}": sum(c["n_fft"] == n for c in geoms) for n in (1024, 2048, 4096)}
     mix.update({f"ant{a}": sum(c["n_ant"] == a for c in geoms) for a in (16, 32, 64)})
     print(json.dumps({
@@ -354,14 +403,21 @@ def bench_cells(n_cells: int, steps: int, warmup: int) -> int:
         "higher_is_better": False, "cells": n_cells, "steps": steps, "warmup": warmup,
         "graph_p50_us_per_slot": per(replay, 50), "graph_p99_us_per_slot": per(replay, 99),
         "eager_p50_us_per_slot": per(eager, 50), "eager_p99_us_per_slot": per(eager, 99),
+        "streams_graph_p50_us_per_slot": per(replay_s, 50), "streams_graph_p99_us_per_slot": per(replay_s, 99),
+        "streams_eager_p50_us_per_slot": per(eager_s, 50),
         "sequential_slot_calls_p50_us_per_slot": per(seq, 50),
         "mixed_graph_p50_us_per_slot": per(replay_mixed, 50),
         "mixed_graph_p99_us_per_slot": per(replay_mixed, 99),
+        "mixed_streams_graph_p50_us_per_slot": per(replay_mixed_s, 50),
+        "chain_bytes_MB": round(chain_bytes / 1e6, 1), "byte_floor_us_per_slot": round(floor_us, 3),
+        "floor_frac": round(floor_us / per(replay, 50), 4),
+        "oracle_check": check, "cpu_baseline": base,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{n_cells} uneven cells, one slot each: N in 1024/2048/4096 (N*3300/4096 active), "
-                               f"16/32/64 antennas, beams = antennas/2, 4-16 UEs, pilots 2+11", "mix": mix},
+                               f"16/32/64 antennas, beams = antennas/2, 4-16 UEs, pilots 2+11, TDL at 20 dB, "
+                               f"QPSK..256-QAM", "mix": mix},
     }), flush=True)
-    return 0
+    return 0 if check["pass"] and same else 1
 
 
 def main() -> int:

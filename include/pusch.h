@@ -272,18 +272,28 @@ int pusch_slot_mixed(const pusch_slot_desc* d, long long n_slot, const pusch_c32
  * Many independent cells of different geometries in one call (the paper runs
  * many independent small problems side by side, each on its own group of
  * cores between barriers: Sec. V, Sec. VI).  Cell c is a pusch_slot call
- * with descriptor d[c], n_slot[c] slots and buffers x_td[c], x_hat[c],
- * status[c] (status may be NULL, or any status[c] may be NULL).  The cells run
- * on PUSCH_CELL_STREAMS library-owned side streams of default priority, cell
- * c on side stream c mod PUSCH_CELL_STREAMS in order, forked from and joined
- * back to `stream` with events, so the whole call is ordered on `stream` and
- * can be captured into a HIP graph (after one uncaptured call with the same
- * cells has built the device tables).
+ * (pusch_slot_mixed with PUSCH_CELLS_MIXED) with descriptor d[c], n_slot[c]
+ * slots and buffers x_td[c], x_hat[c], status[c] (status may be NULL, or any
+ * status[c] may be NULL); results are those of that call, bit for bit.
+ *
+ * Launches.  The cells that detect with the channel interpolated inside the
+ * detection kernel (up to 16 UEs, an even number of beams, no refinement, one
+ * estimate per slot) and have up to 64 antennas run grouped: one launch per
+ * stage for all such cells of one kernel shape (transform size; beamforming
+ * tile class; detection class), on `stream`.  Every other cell (and every
+ * cell with PUSCH_CELLS_STREAMS) runs as its own launches on
+ * PUSCH_CELL_STREAMS library-owned side streams of default priority, the i-th
+ * such cell on side stream i mod PUSCH_CELL_STREAMS, forked from and joined
+ * back to `stream` with events.  The whole call is ordered on `stream` and can
+ * be captured into a HIP graph (after one uncaptured call with the same cells
+ * has built the device tables).
  *   ws     device workspace of at least pusch_cells_workspace_bytes bytes,
- *          256-byte aligned: one slice per side stream used, each as large
- *          as the largest cell's pusch_slot (or pusch_slot_mixed) workspace.
- *   mixed  nonzero: every cell runs as pusch_slot_mixed (each cell n_ant <=
- *          64, else PUSCH_EUNSUPPORTED; workspace size 0).
+ *          256-byte aligned: one slice per cell, in cell order, each that
+ *          cell's pusch_slot (or pusch_slot_mixed) workspace rounded up to
+ *          256 bytes.
+ *   flags  PUSCH_CELLS_MIXED: every cell runs as pusch_slot_mixed (each cell
+ *          n_ant <= 64, else PUSCH_EUNSUPPORTED; workspace size 0);
+ *          PUSCH_CELLS_STREAMS: no grouped launches.  Other bits: PUSCH_EINVAL.
  * Every cell's arguments are checked as for pusch_slot, and no cell's output
  * may overlap any other cell's buffers or the workspace.  1 <= n_cells <=
  * PUSCH_MAX_CELLS.  Calls on one device are serialised on the host while
@@ -292,9 +302,11 @@ int pusch_slot_mixed(const pusch_slot_desc* d, long long n_slot, const pusch_c32
  */
 #define PUSCH_CELL_STREAMS 4
 #define PUSCH_MAX_CELLS 4096
-size_t pusch_cells_workspace_bytes(const pusch_slot_desc* d, int n_cells, const long long* n_slot, int mixed);
+#define PUSCH_CELLS_MIXED 1
+#define PUSCH_CELLS_STREAMS 2
+size_t pusch_cells_workspace_bytes(const pusch_slot_desc* d, int n_cells, const long long* n_slot, int flags);
 int pusch_cells(const pusch_slot_desc* d, int n_cells, const long long* n_slot, const pusch_c32* const* x_td,
-                pusch_c32* const* x_hat, int32_t* const* status, void* ws, size_t ws_bytes, int mixed,
+                pusch_c32* const* x_hat, int32_t* const* status, void* ws, size_t ws_bytes, int flags,
                 void* stream);
 
 /*

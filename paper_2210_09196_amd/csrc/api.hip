@@ -507,6 +507,57 @@ int check_slot_call(const pusch_slot_desc* d, long long n_slot, const pusch_c32*
   return PUSCH_OK;
 }
 
+// Estimation geometry of a slot call (grids of one batch item: [n_symb][n_sc][n_beams]).
+pusch::ChestGeom chest_geom(const pusch_slot_desc* d) {
+  const int S = d->n_symb, K = d->n_sc, B = d->n_beams, L = d->n_ue, P = d->n_pilot;
+  pusch::ChestGeom cg{};
+  cg.n_beams = B;
+  cg.n_ue = L;
+  cg.n_sc = K;
+  cg.n_pilot = P;
+  cg.y_batch = (long long)S * K * B;
+  cg.y_sym = (long long)K * B;
+  for (int j = 0; j < P; ++j) cg.pilot_sym[j] = d->pilot_symb[j];
+  cg.p_batch = (long long)P * K;
+  cg.h_batch = (long long)K * L * B;
+  return cg;
+}
+
+// Beamforming epilogue of the fused detection: the pilot symbols leave the
+// stage divided by their pilots.
+pusch::PilotScale pilot_scale(const pusch_slot_desc* d) {
+  pusch::PilotScale psc{};
+  psc.pilots = reinterpret_cast<const cf*>(d->pilots);
+  psc.p_slot = (long long)d->n_pilot * d->n_sc;
+  psc.n_symb = d->n_symb;
+  for (int s_ = 0; s_ < pusch::kMaxSymbols; ++s_) psc.pilot_of[s_] = -1;
+  for (int j = 0; j < d->n_pilot; ++j) psc.pilot_of[d->pilot_symb[j]] = (signed char)j;
+  return psc;
+}
+
+// Detection geometry of a slot call; s2: per-slot noise variances (device) or nullptr.
+pusch::MmseGeom mmse_geom(const pusch_slot_desc* d, const float* s2) {
+  const int S = d->n_symb, K = d->n_sc, B = d->n_beams, L = d->n_ue, P = d->n_pilot;
+  const int D = S - P;
+  pusch::MmseGeom mg{};
+  mg.n_beams = B;
+  mg.n_ue = L;
+  mg.n_sc = K;
+  mg.n_data = D;
+  mg.sigma2 = d->noise_est ? 0.f : d->sigma2;
+  mg.sigma2_item = s2;
+  mg.refine = d->refine ? 1 : 0;
+  mg.h_batch = (long long)K * L * B;
+  mg.y_batch = (long long)S * K * B;
+  mg.y_sym = (long long)K * B;
+  mg.d_first = 0;
+  mg.n_skip = P;
+  for (int j = 0; j < P; ++j) mg.skip[j] = d->pilot_symb[j];
+  mg.x_batch = (long long)D * K * L;
+  mg.st_batch = K;
+  return mg;
+}
+
 // Launch sequence of one fused slot call on stream s (arguments checked).
 int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td, pusch_c32* x_hat,
              int32_t* status, char* base, hipStream_t s, bool profile, bool mixed = false) {
@@ -522,16 +573,7 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   // estimation geometry, and the geometry's cached tables (built before
   // anything is enqueued on s)
   const bool fused = slot_fused(d);
-  pusch::ChestGeom cg{};
-  cg.n_beams = B;
-  cg.n_ue = L;
-  cg.n_sc = K;
-  cg.n_pilot = P;
-  cg.y_batch = (long long)S * K * B;
-  cg.y_sym = (long long)K * B;
-  for (int j = 0; j < P; ++j) cg.pilot_sym[j] = d->pilot_symb[j];
-  cg.p_batch = (long long)P * K;
-  cg.h_batch = (long long)K * L * B;
+  const pusch::ChestGeom cg = chest_geom(d);
   const int n_tap = pusch::comb_taps(L, P);
   const void* taps = nullptr;
   const void* ne_tab = nullptr;
@@ -568,13 +610,7 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   // kernel estimates the channel itself, the pilot symbols leave this stage
   // already divided by their pilots (the LS division of the channel estimate)
   pusch::PilotScale psc{};
-  if (fused) {
-    psc.pilots = reinterpret_cast<const cf*>(d->pilots);
-    psc.p_slot = (long long)P * K;
-    psc.n_symb = S;
-    for (int s_ = 0; s_ < pusch::kMaxSymbols; ++s_) psc.pilot_of[s_] = -1;
-    for (int j = 0; j < P; ++j) psc.pilot_of[d->pilot_symb[j]] = (signed char)j;
-  }
+  if (fused) psc = pilot_scale(d);
   if (!mark(1)) return PUSCH_EHIP;
   if (pusch::launch_beamform(w, Xa, Y, B, R, K, KP, R * KP, (long long)K * B, n_slot * S, t->n_cu, s,
                              fused ? &psc : nullptr, Xh, ex) != hipSuccess)
@@ -596,22 +632,7 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   // MMSE detection: Gram, Cholesky, matched filter and substitutions for the data
   // symbols (with the channel estimate computed inside when fused)
   if (!mark(3)) return PUSCH_EHIP;
-  pusch::MmseGeom mg{};
-  mg.n_beams = B;
-  mg.n_ue = L;
-  mg.n_sc = K;
-  mg.n_data = D;
-  mg.sigma2 = d->noise_est ? 0.f : d->sigma2;
-  mg.sigma2_item = s2;
-  mg.refine = d->refine ? 1 : 0;
-  mg.h_batch = (long long)K * L * B;
-  mg.y_batch = (long long)S * K * B;
-  mg.y_sym = (long long)K * B;
-  mg.d_first = 0;
-  mg.n_skip = P;
-  for (int j = 0; j < P; ++j) mg.skip[j] = d->pilot_symb[j];
-  mg.x_batch = (long long)D * K * L;
-  mg.st_batch = K;
+  const pusch::MmseGeom mg = mmse_geom(d, s2);
   if (d->time_varying) {
     // one factorisation per data symbol (its own channel estimate); the data
     // symbols before the first pilot symbol share one estimate, and so do
@@ -643,6 +664,158 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   }
   if (!mark(4)) return PUSCH_EHIP;
   return PUSCH_OK;
+}
+
+// ---------------------------------------------------------------- grouped cells
+// pusch_cells runs the cells that the grouped kernels take as one launch per
+// stage and kernel shape (transform size; beamforming tile class; detection
+// class), each launch covering up to its table's worth of cells, all on the
+// caller's stream; a cell's workgroups find their cell through a prefix table
+// of workgroup counts passed with the launch.  Other cells (refinement,
+// per-symbol estimates, more than 64 antennas, odd beam counts, more than 16
+// UEs) run as pusch_slot calls on the side streams meanwhile.
+
+// Cells that the grouped kernels take: the detection that interpolates the
+// channel itself with one estimate per slot, on the register-tile
+// beamforming kernels (up to 64 antennas, 32-bit tile indices).
+bool cell_grouped(const pusch_slot_desc* d, long long n_slot, bool mixed) {
+  if (n_slot < 1 || !slot_fused(d) || d->time_varying) return false;
+  if (pusch::bf_cell_class(d->n_beams, d->n_ant) < 0) return false;
+  if (pusch::mmse_cell_class(d->n_beams, pusch::comb_taps(d->n_ue, d->n_pilot)) < 0) return false;
+  const long long KP = mixed ? (long long)xa_pitch_h16(d->n_sc) : (long long)xa_pitch(d->n_sc);
+  // (the detection's workgroups, one per 4 subcarriers of a slot, are far fewer than the tiles)
+  return KP * d->n_ant < (1ll << 28) && n_slot * d->n_symb * (((long long)d->n_sc + 15) / 16) < (1ll << 30);
+}
+
+// Calls f(key, cells) for the cells of every distinct key, at most per_launch at a time,
+// in order of first appearance.
+template <class Key, class Launch>
+int for_groups(const std::vector<int>& idx, Key key, int per_launch, Launch f) {
+  std::vector<char> done(idx.size(), 0);
+  std::vector<int> grp;
+  for (size_t i = 0; i < idx.size(); ++i) {
+    if (done[i]) continue;
+    const int k = key(idx[i]);
+    grp.clear();
+    for (size_t j = i; j < idx.size(); ++j) {
+      if (done[j] || key(idx[j]) != k) continue;
+      done[j] = 1;
+      grp.push_back(idx[j]);
+      if ((int)grp.size() == per_launch) {
+        if (int rc = f(k, grp)) return rc;
+        grp.clear();
+      }
+    }
+    if (!grp.empty())
+      if (int rc = f(k, grp)) return rc;
+  }
+  return PUSCH_OK;
+}
+
+// The grouped stages of pusch_cells on stream s for the cells in idx (arguments
+// checked); cell c's intermediates in its own workspace slice base[c].
+int run_cells_grouped(DeviceTables* t, const pusch_slot_desc* d, const long long* n_slot, const pusch_c32* const* x_td,
+                      pusch_c32* const* x_hat, int32_t* const* status, const std::vector<char*>& base,
+                      const std::vector<int>& idx, bool mixed, hipStream_t s) {
+  if (idx.empty()) return PUSCH_OK;
+  const int n = (int)base.size();
+  // the geometries' tables, before anything is enqueued
+  std::vector<const cf*> W(n, nullptr);
+  std::vector<const void*> taps(n, nullptr), ne_tab(n, nullptr);
+  for (int c : idx) {
+    W[c] = reinterpret_cast<const cf*>(d[c].W);
+    if (!W[c])
+      if (int rc = dft_beamformer(t, d[c].n_beams, d[c].n_ant, &W[c])) return rc;
+    const pusch::ChestGeom cg = chest_geom(&d[c]);
+    if (int rc = geometry_table(t, kCombTaps, cg, pusch::comb_taps(d[c].n_ue, d[c].n_pilot), &taps[c])) return rc;
+    if (d[c].noise_est)
+      if (int rc = geometry_table(t, kNoiseTable, cg, 0, &ne_tab[c])) return rc;
+  }
+  auto pitch = [&](int c) {
+    return mixed ? (long long)xa_pitch_h16(d[c].n_sc) : (long long)xa_pitch(d[c].n_sc);
+  };
+  // OFDM demodulation, one launch per transform size
+  int rc = for_groups(idx, [&](int c) { return d[c].n_fft; }, pusch::kFftCellsPerLaunch,
+                      [&](int n_fft, const std::vector<int>& grp) {
+                        pusch::FftCells ft{};
+                        ft.n = (int)grp.size();
+                        for (int i = 0; i < ft.n; ++i) {
+                          const int c = grp[i];
+                          const SlotLayout lay = slot_layout(&d[c], n_slot[c], mixed);
+                          pusch::FftCell& e = ft.cell[i];
+                          e.x = reinterpret_cast<const cf*>(x_td[c]);
+                          e.X = reinterpret_cast<cf*>(base[c] + lay.off_xa);
+                          e.Xh = mixed ? reinterpret_cast<unsigned*>(base[c] + lay.off_xa) : nullptr;
+                          e.ex = mixed ? reinterpret_cast<signed char*>(base[c] + lay.off_ex) : nullptr;
+                          e.rows = d[c].n_ant;
+                          e.batch = n_slot[c] * d[c].n_symb * d[c].n_ant;
+                          e.out_len = d[c].n_sc;
+                          e.shift = d[c].n_sc / 2;
+                          e.ldo = pitch(c);
+                        }
+                        return hip_status(pusch::launch_fft_cells(ft, n_fft, mixed, t->twiddles, t->n_cu, s));
+                      });
+  if (rc) return rc;
+  // beamforming with the pilot epilogue, one launch per tile class
+  rc = for_groups(idx, [&](int c) { return pusch::bf_cell_class(d[c].n_beams, d[c].n_ant); },
+                  pusch::kBfCellsPerLaunch, [&](int cls, const std::vector<int>& grp) {
+                    pusch::BfCells bt{};
+                    bt.n = (int)grp.size();
+                    for (int i = 0; i < bt.n; ++i) {
+                      const int c = grp[i];
+                      const SlotLayout lay = slot_layout(&d[c], n_slot[c], mixed);
+                      pusch::BfCell& e = bt.cell[i];
+                      const long long KP = pitch(c);
+                      e.W = W[c];
+                      e.X = reinterpret_cast<const cf*>(base[c] + lay.off_xa);
+                      e.Xh = mixed ? reinterpret_cast<const unsigned*>(base[c] + lay.off_xa) : nullptr;
+                      e.ex = mixed ? reinterpret_cast<const signed char*>(base[c] + lay.off_ex) : nullptr;
+                      e.Y = reinterpret_cast<cf*>(base[c] + lay.off_y);
+                      e.ldx = KP;
+                      e.sx = d[c].n_ant * KP;
+                      e.sy = (long long)d[c].n_sc * d[c].n_beams;
+                      e.batch = n_slot[c] * d[c].n_symb;
+                      e.nb = d[c].n_beams;
+                      e.na = d[c].n_ant;
+                      e.nre = d[c].n_sc;
+                      e.ps = pilot_scale(&d[c]);
+                    }
+                    return hip_status(pusch::launch_beamform_cells(bt, cls, mixed, t->n_cu, s));
+                  });
+  if (rc) return rc;
+  // noise variance per slot, one launch per cell that estimates it
+  std::vector<float*> s2(n, nullptr);
+  for (int c : idx) {
+    if (!d[c].noise_est) continue;
+    const SlotLayout lay = slot_layout(&d[c], n_slot[c], mixed);
+    float2* part = reinterpret_cast<float2*>(base[c] + lay.off_ne);
+    s2[c] = d[c].sigma2_est ? d[c].sigma2_est
+                            : reinterpret_cast<float*>(base[c] + lay.off_ne + ne_part_bytes(n_slot[c]));
+    if (pusch::launch_noise_est(reinterpret_cast<const cf*>(base[c] + lay.off_y),
+                                reinterpret_cast<const cf*>(d[c].pilots), true, static_cast<const int4*>(ne_tab[c]),
+                                part, s2[c], chest_geom(&d[c]), n_slot[c], s) != hipSuccess)
+      return PUSCH_EHIP;
+  }
+  // detection, one launch per detection class
+  return for_groups(
+      idx, [&](int c) { return pusch::mmse_cell_class(d[c].n_beams, pusch::comb_taps(d[c].n_ue, d[c].n_pilot)); },
+      pusch::kMmseCellsPerLaunch, [&](int cls, const std::vector<int>& grp) {
+        pusch::MmseCells mt{};
+        mt.n = (int)grp.size();
+        for (int i = 0; i < mt.n; ++i) {
+          const int c = grp[i];
+          const SlotLayout lay = slot_layout(&d[c], n_slot[c], mixed);
+          pusch::MmseCell& e = mt.cell[i];
+          e.Y = reinterpret_cast<const cf*>(base[c] + lay.off_y);
+          e.taps = static_cast<const int2*>(taps[c]);
+          e.Xh = reinterpret_cast<cf*>(x_hat[c]);
+          e.st = status ? status[c] : nullptr;
+          e.batch = n_slot[c];
+          e.g = mmse_geom(&d[c], s2[c]);
+          e.cg = chest_geom(&d[c]);
+        }
+        return hip_status(pusch::launch_mmse_cells(mt, cls, s));
+      });
 }
 
 }  // namespace
@@ -678,50 +851,54 @@ int pusch_slot_mixed(const pusch_slot_desc* d, long long n_slot, const pusch_c32
                   true);
 }
 
-size_t pusch_cells_workspace_bytes(const pusch_slot_desc* d, int n_cells, const long long* n_slot, int mixed) {
-  if (!d || !n_slot || n_cells < 1) return 0;
-  size_t slice = 0;
+size_t pusch_cells_workspace_bytes(const pusch_slot_desc* d, int n_cells, const long long* n_slot, int flags) {
+  if (!d || !n_slot || n_cells < 1 || n_cells > PUSCH_MAX_CELLS) return 0;
+  const bool mixed = (flags & PUSCH_CELLS_MIXED) != 0;
+  size_t total = 0;
   for (int c = 0; c < n_cells; ++c) {
     if (check_geom(&d[c]) != PUSCH_OK || n_slot[c] < 0) return 0;
     if (mixed && !mixed_supported(&d[c], n_slot[c])) return 0;
-    slice = std::max(slice, slot_layout(&d[c], n_slot[c], mixed != 0).total);
+    total += align256(slot_layout(&d[c], n_slot[c], mixed).total);
   }
-  const int used = n_cells < kSideStreams ? n_cells : kSideStreams;
-  return (size_t)used * align256(slice);
+  return total;
 }
 
 int pusch_cells(const pusch_slot_desc* d, int n_cells, const long long* n_slot, const pusch_c32* const* x_td,
-                pusch_c32* const* x_hat, int32_t* const* status, void* ws, size_t ws_bytes, int mixed,
+                pusch_c32* const* x_hat, int32_t* const* status, void* ws, size_t ws_bytes, int flags,
                 void* stream) {
   if (!d || !n_slot || !x_td || !x_hat || n_cells < 1 || n_cells > PUSCH_MAX_CELLS) return PUSCH_EINVAL;
-  const bool mx = mixed != 0;
-  size_t slice = 0;
+  if (flags & ~(PUSCH_CELLS_MIXED | PUSCH_CELLS_STREAMS)) return PUSCH_EINVAL;
+  const bool mx = (flags & PUSCH_CELLS_MIXED) != 0;
+  // one workspace slice per cell, in order
+  std::vector<char*> base(n_cells);
+  std::vector<size_t> slice(n_cells);
+  size_t wall = 0;
   for (int c = 0; c < n_cells; ++c) {
     if (int rc = check_geom(&d[c])) return rc;
     if (n_slot[c] < 0) return PUSCH_EINVAL;
-    slice = std::max(slice, slot_layout(&d[c], n_slot[c], mx).total);
+    slice[c] = align256(slot_layout(&d[c], n_slot[c], mx).total);
+    base[c] = static_cast<char*>(ws) + wall;
+    wall += slice[c];
   }
-  slice = align256(slice);
-  const int used = n_cells < kSideStreams ? n_cells : kSideStreams;
   if (!ws) return PUSCH_EINVAL;
-  if (ws_bytes < (size_t)used * slice) return PUSCH_ENOMEM;
+  if (ws_bytes < wall) return PUSCH_ENOMEM;
   // every cell as a pusch_slot call on its workspace slice, and no cell's
   // output may overlap another cell's output or input
   for (int c = 0; c < n_cells; ++c) {
-    char* wsc = static_cast<char*>(ws) + (size_t)(c % kSideStreams) * slice;
-    if (int rc = check_slot_call(&d[c], n_slot[c], x_td[c], x_hat[c], status ? status[c] : nullptr, wsc, slice, mx))
+    if (int rc = check_slot_call(&d[c], n_slot[c], x_td[c], x_hat[c], status ? status[c] : nullptr, base[c],
+                                 slice[c], mx))
       return rc;
     const long long ob = out_bytes(&d[c], n_slot[c]), sb = n_slot[c] * (long long)d[c].n_sc * 4;
     const long long xb_c = n_slot[c] * (long long)d[c].n_symb * d[c].n_ant * d[c].n_fft * 8;
-    const long long wall = (long long)used * (long long)slice;  // every slice is in use at once
-    if (overlap(ws, wall, x_hat[c], ob) || overlap(ws, wall, status ? status[c] : nullptr, sb) ||
-        overlap(ws, wall, x_td[c], xb_c) ||
-        overlap(ws, wall, d[c].pilots, n_slot[c] * (long long)d[c].n_pilot * d[c].n_sc * 8) ||
-        overlap(ws, wall, d[c].W, (long long)d[c].n_beams * d[c].n_ant * 8))
+    const long long wb = (long long)wall;  // every slice is in use at once
+    if (overlap(ws, wb, x_hat[c], ob) || overlap(ws, wb, status ? status[c] : nullptr, sb) ||
+        overlap(ws, wb, x_td[c], xb_c) ||
+        overlap(ws, wb, d[c].pilots, n_slot[c] * (long long)d[c].n_pilot * d[c].n_sc * 8) ||
+        overlap(ws, wb, d[c].W, (long long)d[c].n_beams * d[c].n_ant * 8))
       return PUSCH_EINVAL;
     const float* e_c = d[c].noise_est ? d[c].sigma2_est : nullptr;
     const long long eb = n_slot[c] * 4;
-    if (overlap(ws, wall, e_c, eb)) return PUSCH_EINVAL;
+    if (overlap(ws, wb, e_c, eb)) return PUSCH_EINVAL;
     for (int e = 0; e < n_cells; ++e) {
       if (e == c) continue;
       const long long xb = n_slot[e] * (long long)d[e].n_symb * d[e].n_ant * d[e].n_fft * 8;
@@ -741,23 +918,34 @@ int pusch_cells(const pusch_slot_desc* d, int n_cells, const long long* n_slot, 
         return PUSCH_EINVAL;
     }
   }
+  // which cells the grouped launches take; the rest run on the side streams
+  std::vector<int> grouped, streamed;
+  for (int c = 0; c < n_cells; ++c) {
+    if (n_slot[c] == 0) continue;
+    if (!(flags & PUSCH_CELLS_STREAMS) && cell_grouped(&d[c], n_slot[c], mx))
+      grouped.push_back(c);
+    else
+      streamed.push_back(c);
+  }
   DeviceTables* t = nullptr;
   if (int rc = device_tables(&t)) return rc;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lock(t->cells_mu);
+  const int used = (int)std::min<size_t>(streamed.size(), kSideStreams);
   // fork: every side stream used waits for the caller's stream
-  if (hipEventRecord(t->fork, s) != hipSuccess) return PUSCH_EHIP;
-  for (int i = 0; i < used; ++i)
-    if (hipStreamWaitEvent(t->side[i], t->fork, 0) != hipSuccess) return PUSCH_EHIP;
-  // cell c on side stream c mod kSideStreams, in order on that stream, so
-  // the cells sharing a workspace slice never overlap in time
-  int rc = PUSCH_OK;
-  for (int c = 0; c < n_cells && rc == PUSCH_OK; ++c) {
-    if (n_slot[c] == 0) continue;
-    char* wsc = static_cast<char*>(ws) + (size_t)(c % kSideStreams) * slice;
-    rc = run_slot(t, &d[c], n_slot[c], x_td[c], x_hat[c], status ? status[c] : nullptr, wsc,
-                  t->side[c % kSideStreams], false, mx);
+  if (used > 0) {
+    if (hipEventRecord(t->fork, s) != hipSuccess) return PUSCH_EHIP;
+    for (int i = 0; i < used; ++i)
+      if (hipStreamWaitEvent(t->side[i], t->fork, 0) != hipSuccess) return PUSCH_EHIP;
   }
+  // the i-th streamed cell on side stream i mod PUSCH_CELL_STREAMS
+  int rc = PUSCH_OK;
+  for (size_t i = 0; i < streamed.size() && rc == PUSCH_OK; ++i) {
+    const int c = streamed[i];
+    rc = run_slot(t, &d[c], n_slot[c], x_td[c], x_hat[c], status ? status[c] : nullptr, base[c],
+                  t->side[i % kSideStreams], false, mx);
+  }
+  if (rc == PUSCH_OK) rc = run_cells_grouped(t, d, n_slot, x_td, x_hat, status, base, grouped, mx, s);
   // join (also after a failed launch, so the caller's stream never runs
   // ahead of work already enqueued on a side stream)
   for (int i = 0; i < used; ++i)

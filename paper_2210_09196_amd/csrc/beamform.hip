@@ -207,10 +207,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform(const cf* __restrict__
 // tile's MFMAs run (ping-pong over a tile loop unrolled by two).  Half the
 // accumulators of the 32-RE tile, so two tiles of X fit next to them.
 template <int MT, int KS>
-__global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict__ W, const cf* __restrict__ X,
-                                                            cf* __restrict__ Y, int nb, int na, int nre,
-                                                            long long ldx, long long sx, long long sy, int ntiles,
-                                                            int ntn, PilotScale ps) {
+__device__ __forceinline__ void bf_k_body(int vb, int vg, const cf* __restrict__ W, const cf* __restrict__ X,
+                                          cf* __restrict__ Y, int nb, int na, int nre, long long ldx, long long sx,
+                                          long long sy, int ntiles, int ntn, const PilotScale& ps) {
   extern __shared__ float4 wl[];  // [ks][m][lane] = (Wr, Wi, Wr + Wi, 0); zero for padded antennas / beams
   const int lane = threadIdx.x & 63;
   const int col = lane & 15;  // A row / B column / D column inside a 16x16 tile
@@ -223,8 +222,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict
   }
   __syncthreads();
 
-  const int nwave = gridDim.x * kWaves;
-  const int t0 = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int nwave = vg * kWaves;
+  const int t0 = vb * kWaves + (threadIdx.x >> 6);
   // X operand of every K-step of a tile, from a wave-uniform base with
   // 32-bit lane offsets (the host guarantees n_ant * ldx < 2^28).  Loads are
   // clamped in bounds: padded antennas meet zero W entries, REs past n_re are
@@ -322,6 +321,25 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict
 }
 
 template <int MT, int KS>
+__global__ __launch_bounds__(64 * kWaves) void k_beamform_k(const cf* __restrict__ W, const cf* __restrict__ X,
+                                                            cf* __restrict__ Y, int nb, int na, int nre,
+                                                            long long ldx, long long sx, long long sy, int ntiles,
+                                                            int ntn, PilotScale ps) {
+  bf_k_body<MT, KS>(blockIdx.x, gridDim.x, W, X, Y, nb, na, nre, ldx, sx, sy, ntiles, ntn, ps);
+}
+
+// Many cells of one tile shape in one launch: cell c owns workgroups
+// [start[c], start[c + 1]) (its W staged once in each) and walks its tiles.
+template <int MT, int KS>
+__global__ __launch_bounds__(64 * kWaves) void k_beamform_k_cells(BfCells t) {
+  int c = 0;
+  while (c + 1 < t.n && (int)blockIdx.x >= t.start[c + 1]) ++c;
+  const BfCell& e = t.cell[c];
+  bf_k_body<MT, KS>(blockIdx.x - t.start[c], t.start[c + 1] - t.start[c], e.W, e.X, e.Y, e.nb, e.na, e.nre, e.ldx,
+                    e.sx, e.sy, e.ntiles, e.ntn, e.ps);
+}
+
+template <int MT, int KS>
 hipError_t launch_k(const cf* W, const cf* X, cf* Y, int nb, int na, int nre,
                     long long ldx, long long sx, long long sy, long long batch, const PilotScale& ps, int n_cu,
                     hipStream_t s) {
@@ -363,12 +381,10 @@ __device__ __forceinline__ f32x4 mfma16(h4 a, h4 b, f32x4 c) {
 }
 
 template <int MT, int J>
-__global__ __launch_bounds__(64 * kWaves) void k_beamform_h16(const cf* __restrict__ W,
-                                                              const unsigned* __restrict__ Xh,
-                                                              const signed char* __restrict__ ex,
-                                                              cf* __restrict__ Y, int nb, int na, int nre,
-                                                              long long ldx, long long sx, long long sy, int ntiles,
-                                                              int ntn, PilotScale ps) {
+__device__ __forceinline__ void bf_h16_body(int vb, int vg, const cf* __restrict__ W, const unsigned* __restrict__ Xh,
+                                            const signed char* __restrict__ ex, cf* __restrict__ Y, int nb, int na,
+                                            int nre, long long ldx, long long sx, long long sy, int ntiles, int ntn,
+                                            const PilotScale& ps) {
   constexpr int KS = 4 * J;
   // [j][m][lane] = (Wr, Wi, Wr + Wi) as three half4, lane (q, col): beam
   // m*16 + col, antennas 4 (4j + i) + q, i = 0..3; zero past n_ant / n_beams
@@ -394,8 +410,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_h16(const cf* __restri
   }
   __syncthreads();
 
-  const int nwave = gridDim.x * kWaves;
-  const int t0 = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int nwave = vg * kWaves;
+  const int t0 = vb * kWaves + (threadIdx.x >> 6);
   struct Buf {
     unsigned w[KS];
     int4 e;
@@ -511,6 +527,25 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_h16(const cf* __restri
 }
 
 template <int MT, int J>
+__global__ __launch_bounds__(64 * kWaves) void k_beamform_h16(const cf* __restrict__ W,
+                                                              const unsigned* __restrict__ Xh,
+                                                              const signed char* __restrict__ ex,
+                                                              cf* __restrict__ Y, int nb, int na, int nre,
+                                                              long long ldx, long long sx, long long sy, int ntiles,
+                                                              int ntn, PilotScale ps) {
+  bf_h16_body<MT, J>(blockIdx.x, gridDim.x, W, Xh, ex, Y, nb, na, nre, ldx, sx, sy, ntiles, ntn, ps);
+}
+
+template <int MT, int J>
+__global__ __launch_bounds__(64 * kWaves) void k_beamform_h16_cells(BfCells t) {
+  int c = 0;
+  while (c + 1 < t.n && (int)blockIdx.x >= t.start[c + 1]) ++c;
+  const BfCell& e = t.cell[c];
+  bf_h16_body<MT, J>(blockIdx.x - t.start[c], t.start[c + 1] - t.start[c], e.W, e.Xh, e.ex, e.Y, e.nb, e.na, e.nre,
+                     e.ldx, e.sx, e.sy, e.ntiles, e.ntn, e.ps);
+}
+
+template <int MT, int J>
 hipError_t launch_h16(const cf* W, const unsigned* Xh, const signed char* ex, cf* Y, int nb, int na, int nre,
                       long long ldx, long long sx, long long sy, long long batch, const PilotScale& ps, int n_cu,
                       hipStream_t s) {
@@ -546,6 +581,54 @@ hipError_t launch_k_mt(const cf* W, const cf* X, const unsigned* Xh, const signe
   return launch_k<MT, 16>(W, X, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
 }
 
+int share_blocks(BfCells& t, long long cap) {
+  return share_rounds(t.n, [&](int c) { return (long long)t.cell[c].ntiles; }, kWaves, cap, t.start);
+}
+
+template <int MT, int KS>
+hipError_t launch_k_cells(BfCells& t, int n_cu, hipStream_t s) {
+  const size_t lds = (size_t)KS * MT * 64 * sizeof(float4);
+  static const int per_cu = [&] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_beamform_k_cells<MT, KS>, 64 * kWaves, lds) !=
+            hipSuccess ||
+        n < 1)
+      n = 1;
+    return n;
+  }();
+  const int blocks = share_blocks(t, (long long)n_cu * per_cu);
+  hipLaunchKernelGGL((k_beamform_k_cells<MT, KS>), dim3((unsigned)blocks), dim3(64 * kWaves), lds, s, t);
+  return hipGetLastError();
+}
+
+template <int MT, int J>
+hipError_t launch_h16_cells(BfCells& t, int n_cu, hipStream_t s) {
+  const size_t lds = (size_t)J * MT * 64 * 3 * sizeof(h4);
+  static const int per_cu = [&] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_beamform_h16_cells<MT, J>, 64 * kWaves, lds) !=
+            hipSuccess ||
+        n < 1)
+      n = 1;
+    return n;
+  }();
+  const int blocks = share_blocks(t, (long long)n_cu * per_cu);
+  hipLaunchKernelGGL((k_beamform_h16_cells<MT, J>), dim3((unsigned)blocks), dim3(64 * kWaves), lds, s, t);
+  return hipGetLastError();
+}
+
+template <int MT>
+hipError_t launch_cells_mt(BfCells& t, int ks_class, bool h16, int n_cu, hipStream_t s) {
+  if (h16) {
+    if (ks_class == 0) return launch_h16_cells<MT, 1>(t, n_cu, s);
+    if (ks_class == 1) return launch_h16_cells<MT, 2>(t, n_cu, s);
+    return launch_h16_cells<MT, 4>(t, n_cu, s);
+  }
+  if (ks_class == 0) return launch_k_cells<MT, 4>(t, n_cu, s);
+  if (ks_class == 1) return launch_k_cells<MT, 8>(t, n_cu, s);
+  return launch_k_cells<MT, 16>(t, n_cu, s);
+}
+
 constexpr size_t kWLdsMax = 64 * 1024;
 
 template <int MT, bool VEC>
@@ -570,6 +653,29 @@ hipError_t launch_mt(const cf* W, const cf* X, cf* Y, int nb, int na, int nre, l
 }
 
 }  // namespace
+
+int bf_cell_class(int n_beams, int n_ant) {
+  if (n_beams < 1 || n_beams > 64 || n_ant < 1 || n_ant > 64) return -1;
+  const int mt = (n_beams + 15) / 16, ks = n_ant <= 16 ? 0 : (n_ant <= 32 ? 1 : 2);
+  return (mt - 1) * 3 + ks;
+}
+
+hipError_t launch_beamform_cells(BfCells& t, int cls, bool h16, int n_cu, hipStream_t s) {
+  if (t.n < 1 || t.n > kBfCellsPerLaunch || cls < 0 || cls >= 12) return hipErrorInvalidValue;
+  for (int c = 0; c < t.n; ++c) {
+    BfCell& e = t.cell[c];
+    if (bf_cell_class(e.nb, e.na) != cls || e.nre <= 0 || e.batch <= 0) return hipErrorInvalidValue;
+    if (e.ldx * e.na >= (1ll << 28) || e.batch * ((e.nre + 15) / 16) >= (1ll << 30)) return hipErrorInvalidValue;
+    e.ntn = (e.nre + 15) / 16;
+    e.ntiles = (int)(e.batch * e.ntn);
+  }
+  switch (cls / 3) {
+    case 0: return launch_cells_mt<1>(t, cls % 3, h16, n_cu, s);
+    case 1: return launch_cells_mt<2>(t, cls % 3, h16, n_cu, s);
+    case 2: return launch_cells_mt<3>(t, cls % 3, h16, n_cu, s);
+    default: return launch_cells_mt<4>(t, cls % 3, h16, n_cu, s);
+  }
+}
 
 hipError_t launch_beamform(const cf* W, const cf* X, cf* Y, int n_beams, int n_ant, int n_re, long long ldx,
                            long long sx, long long sy, long long batch, int n_cu, hipStream_t s,

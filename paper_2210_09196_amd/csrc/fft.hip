@@ -151,11 +151,13 @@ __device__ __forceinline__ unsigned pack_h2(float re, float im) {
   return (unsigned)__half_as_ushort(__float2half_rn(re)) | ((unsigned)__half_as_ushort(__float2half_rn(im)) << 16);
 }
 
+// The transform loop of one launch (or of one cell's share of a grouped
+// launch): workgroup vb of vg walks transforms vb*FPB, (vb + vg)*FPB, ...
 template <int N, bool H16>
-__global__ __launch_bounds__(kThreads) void k_fft(const cf* __restrict__ x, cf* __restrict__ X,
-                                                  unsigned* __restrict__ Xh, signed char* __restrict__ ex, int rows,
-                                                  const cf* __restrict__ tw, long long batch, int out_len,
-                                                  int shift, long long ldo) {
+__device__ __forceinline__ void fft_body(int vb, int vg, const cf* __restrict__ x, cf* __restrict__ X,
+                                         unsigned* __restrict__ Xh, signed char* __restrict__ ex, int rows,
+                                         const cf* __restrict__ tw, long long batch, int out_len, int shift,
+                                         long long ldo) {
   constexpr int T = N / 16;         // threads per transform
   constexpr int FPB = kThreads / T;  // transforms per workgroup
   constexpr int R0 = Shape<N>::R0;
@@ -191,15 +193,15 @@ __global__ __launch_bounds__(kThreads) void k_fft(const cf* __restrict__ x, cf* 
   // output rows go through the caches as non-temporal accesses: measured on
   // the paper-scale slot, the FFT then takes ~4 us longer and the
   // beamforming that reads its output ~10 us less.
-  const long long fstep = (long long)gridDim.x * FPB;
+  const long long fstep = (long long)vg * FPB;
   cf vn[H16 ? 16 : 1];
   auto prefetch = [&](long long f) {
     const cf* src = x + (f < batch ? f : batch - 1) * N;
 #pragma unroll
     for (int m = 0; m < 16; ++m) vn[m] = src[t + m * T];
   };
-  if constexpr (H16) prefetch((long long)blockIdx.x * FPB + fl);
-  for (long long f0 = (long long)blockIdx.x * FPB; f0 < batch; f0 += fstep) {
+  if constexpr (H16) prefetch((long long)vb * FPB + fl);
+  for (long long f0 = (long long)vb * FPB; f0 < batch; f0 += fstep) {
     const long long fft = f0 + fl;
     const bool act = fft < batch;
     cf v[16];
@@ -298,6 +300,25 @@ __global__ __launch_bounds__(kThreads) void k_fft(const cf* __restrict__ x, cf* 
   }
 }
 
+template <int N, bool H16>
+__global__ __launch_bounds__(kThreads) void k_fft(const cf* __restrict__ x, cf* __restrict__ X,
+                                                  unsigned* __restrict__ Xh, signed char* __restrict__ ex, int rows,
+                                                  const cf* __restrict__ tw, long long batch, int out_len,
+                                                  int shift, long long ldo) {
+  fft_body<N, H16>(blockIdx.x, gridDim.x, x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo);
+}
+
+// Many cells of one FFT size in one launch: cell c owns workgroups
+// [start[c], start[c + 1]) and runs the single-call loop on its share.
+template <int N, bool H16>
+__global__ __launch_bounds__(kThreads) void k_fft_cells(FftCells t, const cf* __restrict__ tw) {
+  int c = 0;
+  while (c + 1 < t.n && (int)blockIdx.x >= t.start[c + 1]) ++c;
+  const FftCell& e = t.cell[c];
+  fft_body<N, H16>(blockIdx.x - t.start[c], t.start[c + 1] - t.start[c], e.x, e.X, e.Xh, e.ex, e.rows, tw, e.batch,
+                   e.out_len, e.shift, e.ldo);
+}
+
 constexpr int kSizes[5] = {64, 256, 1024, 2048, 4096};
 constexpr int kR0[5] = {4, 16, 4, 8, 16};
 constexpr int kP[5] = {1, 1, 2, 2, 2};
@@ -370,6 +391,36 @@ hipError_t launch_n(const cf* x, cf* X, unsigned* Xh, signed char* ex, int rows,
             : launch_nh<N, false>(x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
 }
 }  // namespace
+
+namespace {
+template <int N, bool H16>
+hipError_t launch_cells_nh(FftCells& t, const cf* tw, int n_cu, hipStream_t s) {
+  static const int per_cu = [] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fft_cells<N, H16>, kThreads, 0) != hipSuccess || n < 1) n = 1;
+    return n;
+  }();
+  constexpr long long fpb = kThreads / (N / 16);  // transforms per workgroup and round
+  const int start = share_rounds(t.n, [&](int c) { return t.cell[c].batch; }, fpb, (long long)n_cu * per_cu, t.start);
+  hipLaunchKernelGGL((k_fft_cells<N, H16>), dim3((unsigned)start), dim3(kThreads), 0, s, t, tw);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_fft_cells(FftCells& t, int n_fft, bool h16, const cf* twiddles, int n_cu, hipStream_t s) {
+  if (t.n < 1 || t.n > kFftCellsPerLaunch) return hipErrorInvalidValue;
+  const int si = fft_size_index(n_fft);
+  if (si < 0) return hipErrorInvalidValue;
+  const cf* tw = twiddles + fft_twiddle_layout().offset[si];
+  switch (n_fft) {
+    case 64: return h16 ? launch_cells_nh<64, true>(t, tw, n_cu, s) : launch_cells_nh<64, false>(t, tw, n_cu, s);
+    case 256: return h16 ? launch_cells_nh<256, true>(t, tw, n_cu, s) : launch_cells_nh<256, false>(t, tw, n_cu, s);
+    case 1024: return h16 ? launch_cells_nh<1024, true>(t, tw, n_cu, s) : launch_cells_nh<1024, false>(t, tw, n_cu, s);
+    case 2048: return h16 ? launch_cells_nh<2048, true>(t, tw, n_cu, s) : launch_cells_nh<2048, false>(t, tw, n_cu, s);
+    case 4096: return h16 ? launch_cells_nh<4096, true>(t, tw, n_cu, s) : launch_cells_nh<4096, false>(t, tw, n_cu, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_len, int shift, long long ldo,
                       const cf* twiddles, int n_cu, hipStream_t s, unsigned* Xh, signed char* ex, int rows) {

@@ -37,6 +37,66 @@ hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_le
                       const cf* twiddles, int n_cu, hipStream_t s, unsigned* Xh = nullptr,
                       signed char* ex = nullptr, int rows = 0);
 
+// Many cells of one FFT size in one launch (the grouped form of pusch_cells):
+// the per-cell arguments of launch_fft (with X or Xh/ex/rows), up to
+// kFftCellsPerLaunch cells; start[] is filled by the launcher.
+// Workgroups of a grouped persistent launch.  Cell c has need(c) work items
+// and a workgroup takes per_round of them per round; the launch finishes
+// after the largest round count of any cell, so the counts are chosen for
+// the smallest R with sum_c ceil(need(c) / (per_round R)) <= cap (the
+// resident workgroups): no workgroup waits for a second wave, and no cell
+// takes more than R rounds.  (Shares rounded up from a proportional split can
+// exceed cap by a few workgroups, which then run after everything else and
+// double the launch time.)  Fills start[0..n] and returns start[n].
+template <class Need>
+inline int share_rounds(int n, Need need, long long per_round, long long cap, int* start) {
+  long long total = 0, hi = 1;
+  for (int c = 0; c < n; ++c) {
+    total += need(c);
+    const long long r = (need(c) + per_round - 1) / per_round;
+    hi = r > hi ? r : hi;
+  }
+  auto blocks = [&](long long R) {
+    long long b = 0;
+    for (int c = 0; c < n; ++c) {
+      const long long k = (need(c) + per_round * R - 1) / (per_round * R);
+      b += k < 1 ? 1 : k;
+    }
+    return b;
+  };
+  long long lo = (total + per_round * cap - 1) / (per_round * cap);
+  lo = lo < 1 ? 1 : (lo > hi ? hi : lo);
+  while (lo < hi) {  // smallest R in [lo, hi] that fits (R = hi: one workgroup per cell)
+    const long long mid = (lo + hi) / 2;
+    if (blocks(mid) <= cap) hi = mid;
+    else lo = mid + 1;
+  }
+  int at = 0;
+  for (int c = 0; c < n; ++c) {
+    start[c] = at;
+    const long long k = (need(c) + per_round * lo - 1) / (per_round * lo);
+    at += (int)(k < 1 ? 1 : k);
+  }
+  start[n] = at;
+  return at;
+}
+
+constexpr int kFftCellsPerLaunch = 32;
+struct FftCell {
+  const cf* x;
+  cf* X;
+  unsigned* Xh;
+  signed char* ex;
+  long long batch, ldo;
+  int rows, out_len, shift;
+};
+struct FftCells {
+  FftCell cell[kFftCellsPerLaunch];
+  int start[kFftCellsPerLaunch + 1];
+  int n;
+};
+hipError_t launch_fft_cells(FftCells& t, int n_fft, bool h16, const cf* twiddles, int n_cu, hipStream_t s);
+
 // ---------------------------------------------------------------- beamforming
 // Optional beamforming epilogue of the fused slot: the outputs of pilot
 // symbols are multiplied by conj(p)/|p|^2 (the LS division), batch item
@@ -57,6 +117,30 @@ hipError_t launch_beamform(const cf* W, const cf* X, cf* Y, int n_beams, int n_a
                            long long sx, long long sy, long long batch, int n_cu, hipStream_t s,
                            const PilotScale* pilot_scale = nullptr, const unsigned* Xh = nullptr,
                            const signed char* ex = nullptr);
+// Many cells of one beamforming tile shape in one launch (the grouped form of
+// pusch_cells): per cell the arguments of launch_beamform with up to 64
+// antennas (the register-tile kernels); W must be a device table; the FP16
+// form reads Xh/ex.  Cells of one launch share bf_cell_class(n_beams, n_ant).
+// ntn, ntiles and start[] are filled by the launcher.
+constexpr int kBfCellsPerLaunch = 24;
+struct BfCell {
+  const cf* W;
+  const cf* X;
+  const unsigned* Xh;
+  const signed char* ex;
+  cf* Y;
+  long long ldx, sx, sy, batch;
+  int nb, na, nre, ntiles, ntn;
+  PilotScale ps;
+};
+struct BfCells {
+  BfCell cell[kBfCellsPerLaunch];
+  int start[kBfCellsPerLaunch + 1];
+  int n;
+};
+int bf_cell_class(int n_beams, int n_ant);  // -1 when the register-tile kernels do not apply
+hipError_t launch_beamform_cells(BfCells& t, int cls, bool h16, int n_cu, hipStream_t s);
+
 
 // ---------------------------------------------------------------- LS channel estimation
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
@@ -148,6 +232,32 @@ bool mmse_fusable(int n_ue, int n_beams, long long y_batch);
 bool mmse_auto_refine(int n_ue, int n_beams);
 hipError_t launch_mmse_fused(const cf* Y, const int2* taps, int n_tap, const ChestGeom& cg, cf* Xhat, int* status,
                              const MmseGeom& g, long long batch, hipStream_t s);
+// Many cells' fused detections in one launch (the grouped form of
+// pusch_cells): per cell the arguments of launch_mmse_fused (a batch of
+// `batch` items); cells of one launch share mmse_cell_class(n_beams, n_tap)
+// (-1: no grouped kernel); nblk_batch and start[] are filled by the launcher.
+constexpr int kMmseCellsPerLaunch = 16;
+struct MmseCell {
+  const cf* Y;
+  const int2* taps;
+  cf* Xh;
+  int* st;
+  long long batch;
+  MmseGeom g;
+  ChestGeom cg;
+  int nblk_batch;
+};
+struct MmseCells {
+  MmseCell cell[kMmseCellsPerLaunch];
+  int start[kMmseCellsPerLaunch + 1];
+  int n;
+};
+int mmse_cell_class(int n_beams, int n_tap);
+hipError_t launch_mmse_cells(MmseCells& t, int cls, hipStream_t s);
+// kernel arguments stay within 4 KB
+static_assert(sizeof(MmseCells) <= 4096, "grouped detection arguments");
+static_assert(sizeof(BfCells) <= 4096, "grouped beamforming arguments");
+static_assert(sizeof(FftCells) <= 4096, "grouped FFT arguments");
 
 // ---------------------------------------------------------------- LS-estimate denoiser
 // Four 3x3 convolution layers 2 -> 32 -> 32 -> 32 -> 2 over every [S][K] grid

@@ -582,10 +582,12 @@ hipError_t launch_lps(const cf* H, const cf* Y, cf* Xh, int* st, const MmseGeom&
 namespace {
 
 // FUSED: NT interpolation taps per (subcarrier, UE), 0 when H is read.
+// blk: the workgroup's logical block (kSPW subcarriers of one batch item).
 template <int KS, bool FUSED, int NT>
-__global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, const cf* __restrict__ Y,
-                                                  const int2* __restrict__ taps, cf* __restrict__ Xh,
-                                                  int* __restrict__ st, MmseGeom g, ChestGeom cg, int nblk_batch) {
+__device__ __forceinline__ void mmse_mfma_body(const int blk, const cf* __restrict__ H, const cf* __restrict__ Y,
+                                               const int2* __restrict__ taps, cf* __restrict__ Xh,
+                                               int* __restrict__ st, const MmseGeom& g, const ChestGeom& cg,
+                                               int nblk_batch) {
   __shared__ cf Gs[kSPW * kTri];  // lower triangle of G, then of L in place
   __shared__ __align__(16) cf Ps[kSPW * kMat];  // P[i][d] = (H^H y_d)_i; then the staged solutions
   __shared__ float Dinv[kSPW * kDinv];
@@ -599,7 +601,6 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
   {
     // one workgroup = one block of kSPW subcarriers (no enclosing loop, so no
     // lane predicates are hoisted and kept alive across blocks)
-    const int blk = xcd_block(blockIdx.x, gridDim.x);  // neighbouring subcarriers on one XCD (shared pilot rows)
     const int bi = blk / nblk_batch;
     const int k0 = (blk - bi * nblk_batch) * kSPW;
 
@@ -861,6 +862,26 @@ __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, cons
 }
 
 template <int KS, bool FUSED, int NT>
+__global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, const cf* __restrict__ Y,
+                                                  const int2* __restrict__ taps, cf* __restrict__ Xh,
+                                                  int* __restrict__ st, MmseGeom g, ChestGeom cg, int nblk_batch) {
+  // neighbouring subcarriers on one XCD (shared pilot rows)
+  mmse_mfma_body<KS, FUSED, NT>(xcd_block(blockIdx.x, gridDim.x), H, Y, taps, Xh, st, g, cg, nblk_batch);
+}
+
+// Many cells in one launch: logical block b (after the XCD renumbering, so a
+// cell's neighbouring subcarriers still share an L2) belongs to the cell c
+// with start[c] <= b < start[c + 1].
+template <int KS, int NT>
+__global__ __launch_bounds__(64) void k_mmse_mfma_cells(MmseCells t) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  int c = 0;
+  while (c + 1 < t.n && blk >= t.start[c + 1]) ++c;
+  const MmseCell& e = t.cell[c];
+  mmse_mfma_body<KS, true, NT>(blk - t.start[c], nullptr, e.Y, e.taps, e.Xh, e.st, e.g, e.cg, e.nblk_batch);
+}
+
+template <int KS, bool FUSED, int NT>
 hipError_t launch_mfma(const cf* H, const cf* Y, const int2* taps, const ChestGeom& cg, cf* Xh, int* st,
                        const MmseGeom& g, long long batch, hipStream_t s) {
   const int nblk_batch = (g.n_sc + kSPW - 1) / kSPW;
@@ -883,7 +904,43 @@ hipError_t dispatch_mfma(const cf* H, const cf* Y, const int2* taps, const Chest
   return hipErrorInvalidValue;
 }
 
+template <int KS>
+hipError_t launch_cells_ks(MmseCells& t, int n_tap, unsigned blocks, hipStream_t s) {
+  if (n_tap == 2) hipLaunchKernelGGL((k_mmse_mfma_cells<KS, 2>), dim3(blocks), dim3(64), 0, s, t);
+  else hipLaunchKernelGGL((k_mmse_mfma_cells<KS, 2 * kMaxPilots>), dim3(blocks), dim3(64), 0, s, t);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+int mmse_cell_class(int n_beams, int n_tap) {
+  if (n_tap != 2 && n_tap != 2 * kMaxPilots) return -1;
+  const int ks = n_beams <= 8 ? 0 : (n_beams <= 16 ? 1 : (n_beams <= 32 ? 2 : (n_beams <= 64 ? 3 : -1)));
+  return ks < 0 ? -1 : ks * 2 + (n_tap == 2 ? 0 : 1);
+}
+
+hipError_t launch_mmse_cells(MmseCells& t, int cls, hipStream_t s) {
+  if (t.n < 1 || t.n > kMmseCellsPerLaunch || cls < 0 || cls >= 8) return hipErrorInvalidValue;
+  const int n_tap = cls % 2 ? 2 * kMaxPilots : 2;
+  long long start = 0;
+  for (int c = 0; c < t.n; ++c) {
+    MmseCell& e = t.cell[c];
+    if (e.batch <= 0 || e.g.n_data > kMaxD || e.g.n_data < 1 || e.g.n_beams != e.cg.n_beams ||
+        !mmse_fusable(e.g.n_ue, e.g.n_beams, e.cg.y_batch) || mmse_cell_class(e.g.n_beams, n_tap) != cls)
+      return hipErrorInvalidValue;
+    e.nblk_batch = (e.g.n_sc + kSPW - 1) / kSPW;
+    t.start[c] = (int)start;
+    start += e.batch * e.nblk_batch;
+    if (start > 0x7fffffffLL) return hipErrorInvalidValue;
+  }
+  t.start[t.n] = (int)start;
+  switch (cls / 2) {
+    case 0: return launch_cells_ks<2>(t, n_tap, (unsigned)start, s);
+    case 1: return launch_cells_ks<4>(t, n_tap, (unsigned)start, s);
+    case 2: return launch_cells_ks<8>(t, n_tap, (unsigned)start, s);
+    default: return launch_cells_ks<16>(t, n_tap, (unsigned)start, s);
+  }
+}
 
 bool mmse_auto_refine(int n_ue, int n_beams) { return n_ue > 16 && 2 * n_ue > n_beams; }
 

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpusch.so
 HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "pusch.h")
 
 MAX_PILOTS = 4
+CELLS_MIXED, CELLS_STREAMS = 1, 2  # pusch_cells flags
 SLOT_STAGES = ("fft", "beamform", "chest", "mmse")
 
 
@@ -377,16 +378,18 @@ class Cells:
 
     Each cell is a dict with the slot geometry (n_ant, n_fft, n_sc, n_symb,
     n_beams, n_ue, pilot_symb), sigma2 (None: estimated per slot, left in
-    self.sigma2_est[c]), n_slot (>= 1) and optionally W and refine.  The
-    workspace is allocated once here; a call enqueues every cell on the
-    library's side streams, forked from and joined back to the current torch
-    stream, so it can be captured into a CUDA/HIP graph.
+    self.sigma2_est[c]), n_slot (>= 1) and optionally W, refine and
+    time_varying.  The workspace is allocated once here.  A call runs the
+    cells the grouped kernels take as one launch per stage and kernel shape on
+    the current torch stream, and the others on the library's side streams,
+    forked from and joined back to that stream, so it can be captured into a
+    HIP graph; grouped=False runs every cell on the side streams.
     """
 
-    def __init__(self, cells: list[dict], device="cuda", precision: str = "fp32"):
+    def __init__(self, cells: list[dict], device="cuda", precision: str = "fp32", grouped: bool = True):
         if precision not in ("fp32", "mixed"):
             raise PuschError("precision is 'fp32' or 'mixed'")
-        self.mixed = 1 if precision == "mixed" else 0
+        self.flags = (CELLS_MIXED if precision == "mixed" else 0) | (0 if grouped else CELLS_STREAMS)
         n = len(cells)
         if n < 1:
             raise PuschError("at least one cell")
@@ -409,7 +412,7 @@ class Cells:
             self.descs[c].time_varying = 1 if g.get("time_varying") else 0
             self.n_slot[c] = int(g["n_slot"])
             self.geom.append(dict(g))
-        nbytes = lib().pusch_cells_workspace_bytes(self.descs, n, self.n_slot, self.mixed)
+        nbytes = lib().pusch_cells_workspace_bytes(self.descs, n, self.n_slot, self.flags)
         if nbytes == 0:
             raise PuschError("pusch_cells_workspace_bytes rejected a cell geometry")
         self.ws = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
@@ -451,7 +454,7 @@ class Cells:
         op = (_P * self.n)(*[t.data_ptr() for t in x_hats])
         sp = None if statuses is None else (_P * self.n)(*[_ptr(t) for t in statuses])
         _check(lib().pusch_cells(self.descs, self.n, self.n_slot, xp, op, sp, self.ws.data_ptr(), self.ws_bytes,
-                                 self.mixed, _stream()), "pusch_cells")
+                                 self.flags, _stream()), "pusch_cells")
         return x_hats, statuses
 
 

@@ -237,11 +237,12 @@ def test_cells_workspace_bytes(lib):
     small = _desc(n_ant=16, n_fft=1024, n_sc=825, n_beams=8, n_ue=4, pilot_symb=(2,), n_pilot=1)
     ws = lambda d, n: lib.pusch_slot_workspace_bytes(ctypes.byref(d), n)
     descs, ns = _cell_arrays([big, small, small], [2, 1, 3])
-    # one slice per side stream used (3 cells -> 3), each the largest cell's workspace
-    slice_ = a(max(ws(big, 2), ws(small, 1), ws(small, 3)))
-    assert lib.pusch_cells_workspace_bytes(descs, 3, ns, 0) == 3 * slice_
+    # one slice per cell, each that cell's pusch_slot workspace rounded up to 256 bytes
+    assert lib.pusch_cells_workspace_bytes(descs, 3, ns, 0) == a(ws(big, 2)) + a(ws(small, 1)) + a(ws(small, 3))
     descs6, ns6 = _cell_arrays([small] * 6, [1] * 6)
-    assert lib.pusch_cells_workspace_bytes(descs6, 6, ns6, 0) == 4 * a(ws(small, 1))  # four side streams
+    assert lib.pusch_cells_workspace_bytes(descs6, 6, ns6, 0) == 6 * a(ws(small, 1))
+    # the streams-only flag does not change the layout
+    assert lib.pusch_cells_workspace_bytes(descs6, 6, ns6, 2) == 6 * a(ws(small, 1))
     bad, nsb = _cell_arrays([big, _desc(n_fft=1000)], [1, 1])
     assert lib.pusch_cells_workspace_bytes(bad, 2, nsb, 0) == 0
     assert lib.pusch_cells_workspace_bytes(descs, 0, ns, 0) == 0
@@ -249,9 +250,8 @@ def test_cells_workspace_bytes(lib):
     # mixed precision: the FP16 grids need n_ant <= 64 in every cell
     many, nsm = _cell_arrays([small, _desc(n_ant=65)], [1, 1])
     assert lib.pusch_cells_workspace_bytes(many, 2, nsm, 1) == 0
-    assert lib.pusch_cells_workspace_bytes(descs, 3, ns, 1) == 3 * a(max(
-        lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(big), 2),
-        lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(small), 3)))
+    mws = lambda d, n: lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(d), n)
+    assert lib.pusch_cells_workspace_bytes(descs, 3, ns, 1) == a(mws(big, 2)) + a(mws(small, 1)) + a(mws(small, 3))
 
 
 def test_cells_validation(lib):
@@ -268,6 +268,7 @@ def test_cells_validation(lib):
     assert f(descs, 2, ns, x, o, None, ws, need - 1, 0, None) == ENOMEM
     assert f(descs, 2, ns, x, o, None, ctypes.c_void_p(0x4000000010), need, 0, None) == EINVAL  # unaligned
     assert f(descs, 2, ns, x, o, None, None, need, 0, None) == EINVAL
+    assert f(descs, 2, ns, x, o, None, ws, need, 4, None) == EINVAL  # unknown flag
     # one invalid cell rejects the whole call
     bad, nsb = _cell_arrays([small, _desc(sigma2=-1.0)], [1, 1])
     assert f(bad, 2, nsb, x, o, None, ws, 1 << 40, 0, None) == EINVAL

@@ -1,5 +1,6 @@
 """GPU parity of pusch_cells: independent cells of different geometries in one
-call (side streams forked from and joined to the caller's stream).
+call (grouped launches on the caller's stream, the other cells on side streams
+forked from and joined to it).
 
 Each cell must match the FP64 oracle (detected symbols NRMSE <= 1e-4, no
 status flags) and be bit-identical to the same cell run alone by pusch_slot
@@ -216,17 +217,58 @@ def uneven48():
         cfgs.append(cfg)
         batches.append(b)
     print(f"[cells] 48 uneven cells generated", flush=True)
-    xh, st = pusch.Cells(geoms)([dev(b["x_td"]) for b in batches], [dev(b["pilots"]) for b in batches])
+    xs, ps = [dev(b["x_td"]) for b in batches], [dev(b["pilots"]) for b in batches]
+    xh, st = pusch.Cells(geoms)(xs, ps)
     torch.cuda.synchronize()
-    return cfgs, batches, [host(t) for t in xh], [host(t) for t in st]
+    return cfgs, batches, [host(t) for t in xh], [host(t) for t in st], geoms, xs, ps
 
 
 @pytest.mark.parametrize("part", range(4))
 def test_uneven_48_cell_mix_matches_oracle(uneven48, part):
-    cfgs, batches, xh, st = uneven48
+    cfgs, batches, xh, st = uneven48[:4]
     for c in range(part * 12, part * 12 + 12):
         cfg, b = cfgs[c], batches[c]
         assert np.all(st[c] == 0), c
         ref = O.receive_slot(b["x_td"][0], b["pilots"][0], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
                              n_beams=cfg.n_beams)
         assert_xhat(xh[c][0], ref["x_hat"], TOL_X, (c, cfg.n_fft, cfg.n_ant, cfg.n_ue))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_uneven_48_grouped_launches_equal_side_streams(uneven48, precision):
+    # the grouped launches (one per stage and kernel shape over all 48 cells) and the per-cell
+    # launches on side streams run the same arithmetic per tile: identical bits
+    geoms, xs, ps = uneven48[4:]
+    g_out, g_st = pusch.Cells(geoms, precision=precision)(xs, ps)
+    s_out, s_st = pusch.Cells(geoms, precision=precision, grouped=False)(xs, ps)
+    torch.cuda.synchronize()
+    for c in range(len(geoms)):
+        assert torch.equal(g_out[c], s_out[c]) and torch.equal(g_st[c], s_st[c]), (precision, c)
+    if precision == "fp32":
+        for c in range(len(geoms)):
+            assert np.array_equal(host(g_out[c]), uneven48[2][c]), c
+
+
+def test_more_cells_of_one_shape_than_one_launch_holds():
+    # 40 cells of one geometry: more than one grouped launch per stage (32 FFT, 24 beamforming and
+    # 16 detection cells per launch), plus two cells the grouped kernels do not take (odd beam count,
+    # refinement) on the side streams; each equals its cell run alone
+    base = dict(n_ant=8, n_fft=64, n_sc=60, n_beams=8, n_ue=3, pilot_symb=(3, 9), qam_bits=4)
+    spec = [(base, 1 + (c % 3 == 0)) for c in range(40)] + [(dict(base, n_beams=7), 1), (base, 1)]
+    cfgs, batches, geoms = make_cells(spec, seed0=3000)
+    geoms[-1]["refine"] = True
+    cells = pusch.Cells(geoms)
+    xs = [dev(b["x_td"]) for b in batches]
+    ps = [dev(b["pilots"]) for b in batches]
+    xh, st = cells(xs, ps)
+    for c, (cfg, b, g) in enumerate(zip(cfgs, batches, geoms)):
+        slot = pusch.Slot(cfg.n_ant, cfg.n_fft, cfg.n_sc, cfg.n_symb, cfg.n_beams, cfg.n_ue, cfg.pilot_symb,
+                          b["sigma2"], g["n_slot"], refine=bool(g.get("refine")))
+        alone, alone_st = slot(xs[c], ps[c])
+        assert torch.equal(alone, xh[c]) and torch.equal(alone_st, st[c]), c
+    for c in (0, 17, 39, 40, 41):
+        cfg, b = cfgs[c], batches[c]
+        for k in range(geoms[c]["n_slot"]):
+            ref = O.receive_slot(b["x_td"][k], b["pilots"][k], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
+                                 n_beams=cfg.n_beams)
+            assert_xhat(host(xh[c])[k], ref["x_hat"], TOL_X, (c, k))
