@@ -347,9 +347,15 @@ def bench_cells(n_cells: int, steps: int, warmup: int) -> int:
         torch.cuda.synchronize()
         return np.array([a.elapsed_time(b) * 1e3 for a, b in ev])  # us per call
 
+    tuned = {}
+
     def measure(precision, grouped):
         cells = pusch.Cells(geoms, precision=precision, grouped=grouped)
         out, out_st = cells.outputs()
+        if grouped:
+            # the autotuner times every launch plan on this cell set and records the fastest
+            plan, us = cells.tune(xs, ps, reps=5, x_hats=out, statuses=out_st)
+            tuned[precision] = {"plan": plan, "us_per_plan": [round(u, 1) for u in us]}
         run = lambda: cells(xs, ps, out, out_st)
         for _ in range(warmup):
             run()
@@ -411,7 +417,7 @@ def bench_cells(n_cells: int, steps: int, warmup: int) -> int:
         "mixed_streams_graph_p50_us_per_slot": per(replay_mixed_s, 50),
         "chain_bytes_MB": round(chain_bytes / 1e6, 1), "byte_floor_us_per_slot": round(floor_us, 3),
         "floor_frac": round(floor_us / per(replay, 50), 4),
-        "oracle_check": check, "cpu_baseline": base,
+        "tuned_plans": tuned, "oracle_check": check, "cpu_baseline": base,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{n_cells} uneven cells, one slot each: N in 1024/2048/4096 (N*3300/4096 active), "
                                f"16/32/64 antennas, beams = antennas/2, 4-16 UEs, pilots 2+11, TDL at 20 dB, "

@@ -293,7 +293,10 @@ int pusch_slot_mixed(const pusch_slot_desc* d, long long n_slot, const pusch_c32
  *          256 bytes.
  *   flags  PUSCH_CELLS_MIXED: every cell runs as pusch_slot_mixed (each cell
  *          n_ant <= 64, else PUSCH_EUNSUPPORTED; workspace size 0);
- *          PUSCH_CELLS_STREAMS: no grouped launches.  Other bits: PUSCH_EINVAL.
+ *          PUSCH_CELLS_STREAMS: no grouped launches;
+ *          PUSCH_CELLS_WITH_PLAN(p): the grouped cells run launch plan p
+ *          (below) instead of the one recorded for the cell set.
+ *          Other bits: PUSCH_EINVAL.
  * Every cell's arguments are checked as for pusch_slot, and no cell's output
  * may overlap any other cell's buffers or the workspace.  1 <= n_cells <=
  * PUSCH_MAX_CELLS.  Calls on one device are serialised on the host while
@@ -304,10 +307,47 @@ int pusch_slot_mixed(const pusch_slot_desc* d, long long n_slot, const pusch_c32
 #define PUSCH_MAX_CELLS 4096
 #define PUSCH_CELLS_MIXED 1
 #define PUSCH_CELLS_STREAMS 2
+#define PUSCH_CELLS_WITH_PLAN(p) (4 | ((p) << 3)) /* 0 <= p < PUSCH_CELLS_PLANS */
 size_t pusch_cells_workspace_bytes(const pusch_slot_desc* d, int n_cells, const long long* n_slot, int flags);
 int pusch_cells(const pusch_slot_desc* d, int n_cells, const long long* n_slot, const pusch_c32* const* x_td,
                 pusch_c32* const* x_hat, int32_t* const* status, void* ws, size_t ws_bytes, int flags,
                 void* stream);
+
+/*
+ * Launch plan of the grouped cells: per stage, one launch for all kernel
+ * shapes of the call (a kernel that runs each workgroup's shape: one ramp
+ * and one tail, but the largest shape's registers and LDS for every
+ * workgroup) or one launch per shape (each shape's own kernel, launched one
+ * after another).  Plan p of PUSCH_CELLS_PLANS has fft_merged = p & 1,
+ * bf_merged = (p >> 1) & 1, mmse_merged = (p >> 2) & 1.  Results do not
+ * depend on the plan (every tile runs the same arithmetic).  A cell set that
+ * pusch_cells_tune has not timed runs {1, 0, 1}.
+ */
+typedef struct pusch_cells_plan {
+  int fft_merged;   /* one FFT launch for every transform size */
+  int bf_merged;    /* one beamforming launch for every tile class (n_beams, n_ant) */
+  int mmse_merged;  /* one detection launch for every class (n_beams, taps) */
+} pusch_cells_plan;
+#define PUSCH_CELLS_PLANS 8
+
+/*
+ * Autotuner of pusch_cells: runs the call (same arguments) once and then
+ * `reps` times under every plan, timing each call with events on `stream`
+ * (the host waits for each), and records the plan with the smallest median
+ * time for this cell set (the geometries, slot counts, options and flags of
+ * every cell) on the current device; later pusch_cells calls with the same
+ * cell set use it.  Writes the plan to *chosen (if not NULL) and the median
+ * time of plan p in microseconds to us[p] for p < n_us.  x_hat and status
+ * hold the results of the last call.  1 <= reps <= 1000.  Not for capture
+ * into a graph (it synchronises); creates and destroys two events.
+ */
+int pusch_cells_tune(const pusch_slot_desc* d, int n_cells, const long long* n_slot, const pusch_c32* const* x_td,
+                     pusch_c32* const* x_hat, int32_t* const* status, void* ws, size_t ws_bytes, int flags, int reps,
+                     pusch_cells_plan* chosen, float* us, int n_us, void* stream);
+/* The plan pusch_cells would use for this cell set: returns 1 if tuned, 0 for
+ * the default plan, or a negative code. */
+int pusch_cells_plan_get(const pusch_slot_desc* d, int n_cells, const long long* n_slot, int flags,
+                         pusch_cells_plan* plan);
 
 /*
  * Learned refinement of the LS channel estimate (the paper's estimator is LS

@@ -41,6 +41,8 @@ struct DeviceTables {
   // noise-estimation neighbours), built on the library's own stream
   hipStream_t build = nullptr;
   std::map<std::vector<long long>, void*> geom;
+  // pusch_cells: launch plans chosen by pusch_cells_tune, by cell set
+  std::map<std::vector<long long>, pusch_cells_plan> plans;
 };
 DeviceTables g_dev[kMaxDevices];
 
@@ -716,7 +718,7 @@ int for_groups(const std::vector<int>& idx, Key key, int per_launch, Launch f) {
 // checked); cell c's intermediates in its own workspace slice base[c].
 int run_cells_grouped(DeviceTables* t, const pusch_slot_desc* d, const long long* n_slot, const pusch_c32* const* x_td,
                       pusch_c32* const* x_hat, int32_t* const* status, const std::vector<char*>& base,
-                      const std::vector<int>& idx, bool mixed, hipStream_t s) {
+                      const std::vector<int>& idx, bool mixed, const pusch_cells_plan& plan, hipStream_t s) {
   if (idx.empty()) return PUSCH_OK;
   const int n = (int)base.size();
   // the geometries' tables, before anything is enqueued
@@ -734,9 +736,9 @@ int run_cells_grouped(DeviceTables* t, const pusch_slot_desc* d, const long long
   auto pitch = [&](int c) {
     return mixed ? (long long)xa_pitch_h16(d[c].n_sc) : (long long)xa_pitch(d[c].n_sc);
   };
-  // OFDM demodulation, one launch per transform size
-  int rc = for_groups(idx, [&](int c) { return d[c].n_fft; }, pusch::kFftCellsPerLaunch,
-                      [&](int n_fft, const std::vector<int>& grp) {
+  // OFDM demodulation: one launch for every transform size, or one per size
+  int rc = for_groups(idx, [&](int c) { return plan.fft_merged ? 0 : d[c].n_fft; }, pusch::kFftCellsPerLaunch,
+                      [&](int, const std::vector<int>& grp) {
                         pusch::FftCells ft{};
                         ft.n = (int)grp.size();
                         for (int i = 0; i < ft.n; ++i) {
@@ -747,17 +749,18 @@ int run_cells_grouped(DeviceTables* t, const pusch_slot_desc* d, const long long
                           e.X = reinterpret_cast<cf*>(base[c] + lay.off_xa);
                           e.Xh = mixed ? reinterpret_cast<unsigned*>(base[c] + lay.off_xa) : nullptr;
                           e.ex = mixed ? reinterpret_cast<signed char*>(base[c] + lay.off_ex) : nullptr;
+                          e.n_fft = d[c].n_fft;
                           e.rows = d[c].n_ant;
                           e.batch = n_slot[c] * d[c].n_symb * d[c].n_ant;
                           e.out_len = d[c].n_sc;
                           e.shift = d[c].n_sc / 2;
                           e.ldo = pitch(c);
                         }
-                        return hip_status(pusch::launch_fft_cells(ft, n_fft, mixed, t->twiddles, t->n_cu, s));
+                        return hip_status(pusch::launch_fft_cells(ft, mixed, t->twiddles, t->n_cu, s));
                       });
   if (rc) return rc;
-  // beamforming with the pilot epilogue, one launch per tile class
-  rc = for_groups(idx, [&](int c) { return pusch::bf_cell_class(d[c].n_beams, d[c].n_ant); },
+  // beamforming with the pilot epilogue: one launch for every tile class, or one per class
+  rc = for_groups(idx, [&](int c) { return plan.bf_merged ? -1 : pusch::bf_cell_class(d[c].n_beams, d[c].n_ant); },
                   pusch::kBfCellsPerLaunch, [&](int cls, const std::vector<int>& grp) {
                     pusch::BfCells bt{};
                     bt.n = (int)grp.size();
@@ -796,9 +799,12 @@ int run_cells_grouped(DeviceTables* t, const pusch_slot_desc* d, const long long
                                 part, s2[c], chest_geom(&d[c]), n_slot[c], s) != hipSuccess)
       return PUSCH_EHIP;
   }
-  // detection, one launch per detection class
+  // detection: one launch for every detection class, or one per class
   return for_groups(
-      idx, [&](int c) { return pusch::mmse_cell_class(d[c].n_beams, pusch::comb_taps(d[c].n_ue, d[c].n_pilot)); },
+      idx,
+      [&](int c) {
+        return plan.mmse_merged ? -1 : pusch::mmse_cell_class(d[c].n_beams, pusch::comb_taps(d[c].n_ue, d[c].n_pilot));
+      },
       pusch::kMmseCellsPerLaunch, [&](int cls, const std::vector<int>& grp) {
         pusch::MmseCells mt{};
         mt.n = (int)grp.size();
@@ -813,10 +819,38 @@ int run_cells_grouped(DeviceTables* t, const pusch_slot_desc* d, const long long
           e.batch = n_slot[c];
           e.g = mmse_geom(&d[c], s2[c]);
           e.cg = chest_geom(&d[c]);
+          e.n_tap = pusch::comb_taps(d[c].n_ue, d[c].n_pilot);
         }
         return hip_status(pusch::launch_mmse_cells(mt, cls, s));
       });
 }
+
+// Launch plan of a call that pusch_cells_tune has not timed.
+constexpr pusch_cells_plan kDefaultPlan = {1, 0, 1};
+
+// What a cell set's timing depends on: every cell's geometry, slots and
+// options, and the flags.
+std::vector<long long> cells_signature(const pusch_slot_desc* d, int n_cells, const long long* n_slot, int flags) {
+  std::vector<long long> key = {flags & (PUSCH_CELLS_MIXED | PUSCH_CELLS_STREAMS), n_cells};
+  for (int c = 0; c < n_cells; ++c) {
+    key.insert(key.end(), {d[c].n_ant, d[c].n_fft, d[c].n_sc, d[c].n_symb, d[c].n_beams, d[c].n_ue, d[c].n_pilot,
+                           n_slot[c], d[c].noise_est, d[c].refine, d[c].time_varying});
+    for (int j = 0; j < d[c].n_pilot; ++j) key.push_back(d[c].pilot_symb[j]);
+  }
+  return key;
+}
+
+pusch_cells_plan cells_plan(DeviceTables* t, const std::vector<long long>& key, int* tuned = nullptr) {
+  std::lock_guard<std::mutex> lock(t->mu);
+  auto it = t->plans.find(key);
+  if (tuned) *tuned = it != t->plans.end();
+  return it != t->plans.end() ? it->second : kDefaultPlan;
+}
+
+// pusch_cells with the plan given (nullptr: the recorded one for the cell set, else the default).
+int cells_call(const pusch_slot_desc* d, int n_cells, const long long* n_slot, const pusch_c32* const* x_td,
+               pusch_c32* const* x_hat, int32_t* const* status, void* ws, size_t ws_bytes, int flags,
+               const pusch_cells_plan* force, void* stream);
 
 }  // namespace
 
@@ -866,8 +900,86 @@ size_t pusch_cells_workspace_bytes(const pusch_slot_desc* d, int n_cells, const 
 int pusch_cells(const pusch_slot_desc* d, int n_cells, const long long* n_slot, const pusch_c32* const* x_td,
                 pusch_c32* const* x_hat, int32_t* const* status, void* ws, size_t ws_bytes, int flags,
                 void* stream) {
+  return cells_call(d, n_cells, n_slot, x_td, x_hat, status, ws, ws_bytes, flags, nullptr, stream);
+}
+
+int pusch_cells_plan_get(const pusch_slot_desc* d, int n_cells, const long long* n_slot, int flags,
+                         pusch_cells_plan* plan) {
+  if (!d || !n_slot || !plan || n_cells < 1 || n_cells > PUSCH_MAX_CELLS) return PUSCH_EINVAL;
+  DeviceTables* t = nullptr;
+  if (int rc = device_tables(&t)) return rc;
+  int tuned = 0;
+  *plan = cells_plan(t, cells_signature(d, n_cells, n_slot, flags), &tuned);
+  return tuned;
+}
+
+int pusch_cells_tune(const pusch_slot_desc* d, int n_cells, const long long* n_slot, const pusch_c32* const* x_td,
+                     pusch_c32* const* x_hat, int32_t* const* status, void* ws, size_t ws_bytes, int flags, int reps,
+                     pusch_cells_plan* chosen, float* us, int n_us, void* stream) {
+  if (reps < 1 || reps > 1000 || (n_us > 0 && !us) || n_us < 0) return PUSCH_EINVAL;
+  if (!d || !n_slot || n_cells < 1 || n_cells > PUSCH_MAX_CELLS) return PUSCH_EINVAL;
+  DeviceTables* t = nullptr;
+  if (int rc = device_tables(&t)) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t ev[2] = {};
+  if (hipEventCreate(&ev[0]) != hipSuccess) return PUSCH_EHIP;
+  if (hipEventCreate(&ev[1]) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return PUSCH_EHIP;
+  }
+  int rc = PUSCH_OK;
+  float best = 0.f;
+  pusch_cells_plan pick = kDefaultPlan;
+  std::vector<float> t_us(PUSCH_CELLS_PLANS, 0.f), one(reps);
+  for (int p = 0; p < PUSCH_CELLS_PLANS && rc == PUSCH_OK; ++p) {
+    const pusch_cells_plan plan = {p & 1, (p >> 1) & 1, (p >> 2) & 1};
+    // one call to warm up (tables, code objects), then reps timed calls; the median
+    rc = cells_call(d, n_cells, n_slot, x_td, x_hat, status, ws, ws_bytes, flags, &plan, stream);
+    for (int r = 0; r < reps && rc == PUSCH_OK; ++r) {
+      float ms = 0.f;
+      if (hipEventRecord(ev[0], s) != hipSuccess) rc = PUSCH_EHIP;
+      if (rc == PUSCH_OK) rc = cells_call(d, n_cells, n_slot, x_td, x_hat, status, ws, ws_bytes, flags, &plan, stream);
+      if (rc == PUSCH_OK && (hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+                             hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
+        rc = PUSCH_EHIP;
+      one[r] = ms * 1e3f;
+    }
+    if (rc != PUSCH_OK) break;
+    std::sort(one.begin(), one.end());
+    t_us[p] = one[reps / 2];
+    if (p == 0 || t_us[p] < best) {
+      best = t_us[p];
+      pick = plan;
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (rc != PUSCH_OK) return rc;
+  {
+    std::lock_guard<std::mutex> lock(t->mu);
+    t->plans[cells_signature(d, n_cells, n_slot, flags)] = pick;
+  }
+  if (chosen) *chosen = pick;
+  for (int p = 0; p < n_us && p < PUSCH_CELLS_PLANS; ++p) us[p] = t_us[p];
+  return PUSCH_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int cells_call(const pusch_slot_desc* d, int n_cells, const long long* n_slot, const pusch_c32* const* x_td,
+               pusch_c32* const* x_hat, int32_t* const* status, void* ws, size_t ws_bytes, int flags,
+               const pusch_cells_plan* force, void* stream) {
   if (!d || !n_slot || !x_td || !x_hat || n_cells < 1 || n_cells > PUSCH_MAX_CELLS) return PUSCH_EINVAL;
-  if (flags & ~(PUSCH_CELLS_MIXED | PUSCH_CELLS_STREAMS)) return PUSCH_EINVAL;
+  if (flags & ~(PUSCH_CELLS_MIXED | PUSCH_CELLS_STREAMS | PUSCH_CELLS_WITH_PLAN(PUSCH_CELLS_PLANS - 1)))
+    return PUSCH_EINVAL;
+  pusch_cells_plan given{};
+  if (flags & PUSCH_CELLS_WITH_PLAN(0)) {
+    const int p = (flags >> 3) & 7;
+    given = pusch_cells_plan{p & 1, (p >> 1) & 1, (p >> 2) & 1};
+    if (!force) force = &given;
+  }
   const bool mx = (flags & PUSCH_CELLS_MIXED) != 0;
   // one workspace slice per cell, in order
   std::vector<char*> base(n_cells);
@@ -945,7 +1057,10 @@ int pusch_cells(const pusch_slot_desc* d, int n_cells, const long long* n_slot, 
     rc = run_slot(t, &d[c], n_slot[c], x_td[c], x_hat[c], status ? status[c] : nullptr, base[c],
                   t->side[i % kSideStreams], false, mx);
   }
-  if (rc == PUSCH_OK) rc = run_cells_grouped(t, d, n_slot, x_td, x_hat, status, base, grouped, mx, s);
+  if (rc == PUSCH_OK && !grouped.empty()) {
+    const pusch_cells_plan plan = force ? *force : cells_plan(t, cells_signature(d, n_cells, n_slot, flags));
+    rc = run_cells_grouped(t, d, n_slot, x_td, x_hat, status, base, grouped, mx, plan, s);
+  }
   // join (also after a failed launch, so the caller's stream never runs
   // ahead of work already enqueued on a side stream)
   for (int i = 0; i < used; ++i)
@@ -953,6 +1068,10 @@ int pusch_cells(const pusch_slot_desc* d, int n_cells, const long long* n_slot, 
       rc = PUSCH_EHIP;
   return rc;
 }
+
+}  // namespace
+
+extern "C" {
 
 int pusch_profile_begin(int max_calls) {
   if (max_calls < 1 || max_calls > (1 << 20)) return PUSCH_EINVAL;

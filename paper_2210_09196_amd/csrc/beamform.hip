@@ -581,8 +581,95 @@ hipError_t launch_k_mt(const cf* W, const cf* X, const unsigned* Xh, const signe
   return launch_k<MT, 16>(W, X, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
 }
 
+// Relative time of one workgroup round (kWaves tiles of 16 REs): the tile's
+// padded antennas read plus beams written.
+long long bf_round_cost(int cls) { return (long long)(4 << (cls % 3)) * 4 + (cls / 3 + 1) * 16; }
+
 int share_blocks(BfCells& t, long long cap) {
-  return share_rounds(t.n, [&](int c) { return (long long)t.cell[c].ntiles; }, kWaves, cap, t.start);
+  return share_work(
+      t.n, [&](int c) { return (long long)(t.cell[c].ntiles + kWaves - 1) / kWaves; },
+      [&](int c) { return bf_round_cost(t.cell[c].cls); }, cap, t.start);
+}
+
+// Any tile classes in one launch: each workgroup runs its cell's class (the
+// W stage in dynamic LDS is sized for the launch's largest class).
+__global__ __launch_bounds__(64 * kWaves) void k_beamform_k_any(BfCells t) {
+  int c = 0;
+  while (c + 1 < t.n && (int)blockIdx.x >= t.start[c + 1]) ++c;
+  const BfCell& e = t.cell[c];
+  const int vb = blockIdx.x - t.start[c], vg = t.start[c + 1] - t.start[c];
+#define BF_K_CASE(CLS, MT, KS)                                                                                    \
+  case CLS:                                                                                                      \
+    bf_k_body<MT, KS>(vb, vg, e.W, e.X, e.Y, e.nb, e.na, e.nre, e.ldx, e.sx, e.sy, e.ntiles, e.ntn, e.ps); \
+    break;
+  switch (e.cls) {
+    BF_K_CASE(0, 1, 4)
+    BF_K_CASE(1, 1, 8)
+    BF_K_CASE(2, 1, 16)
+    BF_K_CASE(3, 2, 4)
+    BF_K_CASE(4, 2, 8)
+    BF_K_CASE(5, 2, 16)
+    BF_K_CASE(6, 3, 4)
+    BF_K_CASE(7, 3, 8)
+    BF_K_CASE(8, 3, 16)
+    BF_K_CASE(9, 4, 4)
+    BF_K_CASE(10, 4, 8)
+    default: BF_K_CASE(11, 4, 16)
+  }
+#undef BF_K_CASE
+}
+
+__global__ __launch_bounds__(64 * kWaves) void k_beamform_h16_any(BfCells t) {
+  int c = 0;
+  while (c + 1 < t.n && (int)blockIdx.x >= t.start[c + 1]) ++c;
+  const BfCell& e = t.cell[c];
+  const int vb = blockIdx.x - t.start[c], vg = t.start[c + 1] - t.start[c];
+#define BF_H_CASE(CLS, MT, J)                                                                                     \
+  case CLS:                                                                                                      \
+    bf_h16_body<MT, J>(vb, vg, e.W, e.Xh, e.ex, e.Y, e.nb, e.na, e.nre, e.ldx, e.sx, e.sy, e.ntiles, e.ntn, e.ps); \
+    break;
+  switch (e.cls) {
+    BF_H_CASE(0, 1, 1)
+    BF_H_CASE(1, 1, 2)
+    BF_H_CASE(2, 1, 4)
+    BF_H_CASE(3, 2, 1)
+    BF_H_CASE(4, 2, 2)
+    BF_H_CASE(5, 2, 4)
+    BF_H_CASE(6, 3, 1)
+    BF_H_CASE(7, 3, 2)
+    BF_H_CASE(8, 3, 4)
+    BF_H_CASE(9, 4, 1)
+    BF_H_CASE(10, 4, 2)
+    default: BF_H_CASE(11, 4, 4)
+  }
+#undef BF_H_CASE
+}
+
+// W stage of a class (bytes of dynamic LDS).
+size_t bf_class_lds(int cls, bool h16) {
+  const int mt = cls / 3 + 1, k = cls % 3;
+  return h16 ? (size_t)(1 << k) * mt * 64 * 3 * sizeof(h4) : (size_t)(4 << k) * mt * 64 * sizeof(float4);
+}
+
+hipError_t launch_any_cells(BfCells& t, bool h16, int n_cu, hipStream_t s) {
+  int top = 0;  // the class with the largest W stage
+  for (int c = 0; c < t.n; ++c)
+    if (bf_class_lds(t.cell[c].cls, h16) > bf_class_lds(top, h16)) top = t.cell[c].cls;
+  const size_t lds = bf_class_lds(top, h16);
+  static int per_cu[2][12] = {};  // occupancy by W stage size, looked up once
+  int& pc = per_cu[h16][top];
+  if (pc == 0) {
+    int n = 0;
+    const hipError_t e = h16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_beamform_h16_any, 64 * kWaves, lds)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_beamform_k_any, 64 * kWaves, lds);
+    pc = (e != hipSuccess || n < 1) ? 1 : n;
+  }
+  const int blocks = share_blocks(t, (long long)n_cu * pc);
+  if (h16)
+    hipLaunchKernelGGL(k_beamform_h16_any, dim3((unsigned)blocks), dim3(64 * kWaves), lds, s, t);
+  else
+    hipLaunchKernelGGL(k_beamform_k_any, dim3((unsigned)blocks), dim3(64 * kWaves), lds, s, t);
+  return hipGetLastError();
 }
 
 template <int MT, int KS>
@@ -661,14 +748,16 @@ int bf_cell_class(int n_beams, int n_ant) {
 }
 
 hipError_t launch_beamform_cells(BfCells& t, int cls, bool h16, int n_cu, hipStream_t s) {
-  if (t.n < 1 || t.n > kBfCellsPerLaunch || cls < 0 || cls >= 12) return hipErrorInvalidValue;
+  if (t.n < 1 || t.n > kBfCellsPerLaunch || cls < -1 || cls >= 12) return hipErrorInvalidValue;
   for (int c = 0; c < t.n; ++c) {
     BfCell& e = t.cell[c];
-    if (bf_cell_class(e.nb, e.na) != cls || e.nre <= 0 || e.batch <= 0) return hipErrorInvalidValue;
+    e.cls = bf_cell_class(e.nb, e.na);
+    if (e.cls < 0 || (cls >= 0 && e.cls != cls) || e.nre <= 0 || e.batch <= 0) return hipErrorInvalidValue;
     if (e.ldx * e.na >= (1ll << 28) || e.batch * ((e.nre + 15) / 16) >= (1ll << 30)) return hipErrorInvalidValue;
     e.ntn = (e.nre + 15) / 16;
     e.ntiles = (int)(e.batch * e.ntn);
   }
+  if (cls < 0) return launch_any_cells(t, h16, n_cu, s);
   switch (cls / 3) {
     case 0: return launch_cells_mt<1>(t, cls % 3, h16, n_cu, s);
     case 1: return launch_cells_mt<2>(t, cls % 3, h16, n_cu, s);

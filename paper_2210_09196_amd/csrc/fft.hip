@@ -151,20 +151,25 @@ __device__ __forceinline__ unsigned pack_h2(float re, float im) {
   return (unsigned)__half_as_ushort(__float2half_rn(re)) | ((unsigned)__half_as_ushort(__float2half_rn(im)) << 16);
 }
 
+// LDS of a workgroup: FPB = kThreads / (N / 16) padded transforms, the same
+// 4352 complex values at every size (so one buffer serves every size of a
+// grouped launch).
+constexpr int kLdsCf = 4352;
+
 // The transform loop of one launch (or of one cell's share of a grouped
 // launch): workgroup vb of vg walks transforms vb*FPB, (vb + vg)*FPB, ...
+// lds: kLdsCf values; red: kThreads / 64 floats (per-wave partial norms, H16).
 template <int N, bool H16>
-__device__ __forceinline__ void fft_body(int vb, int vg, const cf* __restrict__ x, cf* __restrict__ X,
-                                         unsigned* __restrict__ Xh, signed char* __restrict__ ex, int rows,
-                                         const cf* __restrict__ tw, long long batch, int out_len, int shift,
-                                         long long ldo) {
+__device__ __forceinline__ void fft_body(cf* __restrict__ lds, float* __restrict__ red, int vb, int vg,
+                                         const cf* __restrict__ x, cf* __restrict__ X, unsigned* __restrict__ Xh,
+                                         signed char* __restrict__ ex, int rows, const cf* __restrict__ tw,
+                                         long long batch, int out_len, int shift, long long ldo) {
   constexpr int T = N / 16;         // threads per transform
   constexpr int FPB = kThreads / T;  // transforms per workgroup
   constexpr int R0 = Shape<N>::R0;
   constexpr int P = Shape<N>::P;
   constexpr int LSTR = lds_pad(N);
-  __shared__ cf lds[FPB * LSTR];
-  __shared__ float red[kThreads / 64];  // per-wave partial norms (H16, T > 64)
+  static_assert(FPB * LSTR == kLdsCf, "one LDS size for every transform size");
 
   const int fl = threadIdx.x / T;
   const int t = threadIdx.x % T;
@@ -305,18 +310,39 @@ __global__ __launch_bounds__(kThreads) void k_fft(const cf* __restrict__ x, cf* 
                                                   unsigned* __restrict__ Xh, signed char* __restrict__ ex, int rows,
                                                   const cf* __restrict__ tw, long long batch, int out_len,
                                                   int shift, long long ldo) {
-  fft_body<N, H16>(blockIdx.x, gridDim.x, x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo);
+  __shared__ cf lds[kLdsCf];
+  __shared__ float red[kThreads / 64];
+  fft_body<N, H16>(lds, red, blockIdx.x, gridDim.x, x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo);
 }
 
-// Many cells of one FFT size in one launch: cell c owns workgroups
-// [start[c], start[c + 1]) and runs the single-call loop on its share.
-template <int N, bool H16>
-__global__ __launch_bounds__(kThreads) void k_fft_cells(FftCells t, const cf* __restrict__ tw) {
+// Many cells of any transform sizes in one launch: cell c owns workgroups
+// [start[c], start[c + 1]) and runs the single-call loop of its size on its
+// share (the size is uniform over a workgroup).
+template <bool H16>
+__global__ __launch_bounds__(kThreads) void k_fft_cells(FftCells t) {
+  __shared__ cf lds[kLdsCf];
+  __shared__ float red[kThreads / 64];
   int c = 0;
   while (c + 1 < t.n && (int)blockIdx.x >= t.start[c + 1]) ++c;
   const FftCell& e = t.cell[c];
-  fft_body<N, H16>(blockIdx.x - t.start[c], t.start[c + 1] - t.start[c], e.x, e.X, e.Xh, e.ex, e.rows, tw, e.batch,
-                   e.out_len, e.shift, e.ldo);
+  const int vb = blockIdx.x - t.start[c], vg = t.start[c + 1] - t.start[c];
+  switch (e.n_fft) {
+    case 64:
+      fft_body<64, H16>(lds, red, vb, vg, e.x, e.X, e.Xh, e.ex, e.rows, e.tw, e.batch, e.out_len, e.shift, e.ldo);
+      break;
+    case 256:
+      fft_body<256, H16>(lds, red, vb, vg, e.x, e.X, e.Xh, e.ex, e.rows, e.tw, e.batch, e.out_len, e.shift, e.ldo);
+      break;
+    case 1024:
+      fft_body<1024, H16>(lds, red, vb, vg, e.x, e.X, e.Xh, e.ex, e.rows, e.tw, e.batch, e.out_len, e.shift, e.ldo);
+      break;
+    case 2048:
+      fft_body<2048, H16>(lds, red, vb, vg, e.x, e.X, e.Xh, e.ex, e.rows, e.tw, e.batch, e.out_len, e.shift, e.ldo);
+      break;
+    default:
+      fft_body<4096, H16>(lds, red, vb, vg, e.x, e.X, e.Xh, e.ex, e.rows, e.tw, e.batch, e.out_len, e.shift, e.ldo);
+      break;
+  }
 }
 
 constexpr int kSizes[5] = {64, 256, 1024, 2048, 4096};
@@ -393,33 +419,34 @@ hipError_t launch_n(const cf* x, cf* X, unsigned* Xh, signed char* ex, int rows,
 }  // namespace
 
 namespace {
-template <int N, bool H16>
-hipError_t launch_cells_nh(FftCells& t, const cf* tw, int n_cu, hipStream_t s) {
+template <bool H16>
+hipError_t launch_cells_h(FftCells& t, int n_cu, hipStream_t s) {
   static const int per_cu = [] {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fft_cells<N, H16>, kThreads, 0) != hipSuccess || n < 1) n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fft_cells<H16>, kThreads, 0) != hipSuccess || n < 1) n = 1;
     return n;
   }();
-  constexpr long long fpb = kThreads / (N / 16);  // transforms per workgroup and round
-  const int start = share_rounds(t.n, [&](int c) { return t.cell[c].batch; }, fpb, (long long)n_cu * per_cu, t.start);
-  hipLaunchKernelGGL((k_fft_cells<N, H16>), dim3((unsigned)start), dim3(kThreads), 0, s, t, tw);
+  // work in workgroup rounds: a workgroup takes kThreads / (N / 16) transforms of
+  // its cell per round (the same bytes and about the same time at every size)
+  const int start = share_work(
+      t.n, [&](int c) { const long long f = kThreads / (t.cell[c].n_fft / 16); return (t.cell[c].batch + f - 1) / f; },
+      [](int) { return 1ll; }, (long long)n_cu * per_cu, t.start);
+  hipLaunchKernelGGL((k_fft_cells<H16>), dim3((unsigned)start), dim3(kThreads), 0, s, t);
   return hipGetLastError();
 }
 }  // namespace
 
-hipError_t launch_fft_cells(FftCells& t, int n_fft, bool h16, const cf* twiddles, int n_cu, hipStream_t s) {
+hipError_t launch_fft_cells(FftCells& t, bool h16, const cf* twiddles, int n_cu, hipStream_t s) {
   if (t.n < 1 || t.n > kFftCellsPerLaunch) return hipErrorInvalidValue;
-  const int si = fft_size_index(n_fft);
-  if (si < 0) return hipErrorInvalidValue;
-  const cf* tw = twiddles + fft_twiddle_layout().offset[si];
-  switch (n_fft) {
-    case 64: return h16 ? launch_cells_nh<64, true>(t, tw, n_cu, s) : launch_cells_nh<64, false>(t, tw, n_cu, s);
-    case 256: return h16 ? launch_cells_nh<256, true>(t, tw, n_cu, s) : launch_cells_nh<256, false>(t, tw, n_cu, s);
-    case 1024: return h16 ? launch_cells_nh<1024, true>(t, tw, n_cu, s) : launch_cells_nh<1024, false>(t, tw, n_cu, s);
-    case 2048: return h16 ? launch_cells_nh<2048, true>(t, tw, n_cu, s) : launch_cells_nh<2048, false>(t, tw, n_cu, s);
-    case 4096: return h16 ? launch_cells_nh<4096, true>(t, tw, n_cu, s) : launch_cells_nh<4096, false>(t, tw, n_cu, s);
-    default: return hipErrorInvalidValue;
+  const TwiddleLayout lay = fft_twiddle_layout();
+  for (int c = 0; c < t.n; ++c) {
+    FftCell& e = t.cell[c];
+    const int si = fft_size_index(e.n_fft);
+    if (si < 0 || e.batch <= 0) return hipErrorInvalidValue;
+    if (h16 && (e.rows < 1 || e.rows > 64 || !e.Xh || !e.ex)) return hipErrorInvalidValue;
+    e.tw = twiddles + lay.offset[si];
   }
+  return h16 ? launch_cells_h<true>(t, n_cu, s) : launch_cells_h<false>(t, n_cu, s);
 }
 
 hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_len, int shift, long long ldo,

@@ -37,65 +37,70 @@ hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_le
                       const cf* twiddles, int n_cu, hipStream_t s, unsigned* Xh = nullptr,
                       signed char* ex = nullptr, int rows = 0);
 
-// Many cells of one FFT size in one launch (the grouped form of pusch_cells):
-// the per-cell arguments of launch_fft (with X or Xh/ex/rows), up to
-// kFftCellsPerLaunch cells; start[] is filled by the launcher.
-// Workgroups of a grouped persistent launch.  Cell c has need(c) work items
-// and a workgroup takes per_round of them per round; the launch finishes
-// after the largest round count of any cell, so the counts are chosen for
-// the smallest R with sum_c ceil(need(c) / (per_round R)) <= cap (the
-// resident workgroups): no workgroup waits for a second wave, and no cell
-// takes more than R rounds.  (Shares rounded up from a proportional split can
-// exceed cap by a few workgroups, which then run after everything else and
-// double the launch time.)  Fills start[0..n] and returns start[n].
-template <class Need>
-inline int share_rounds(int n, Need need, long long per_round, long long cap, int* start) {
-  long long total = 0, hi = 1;
-  for (int c = 0; c < n; ++c) {
-    total += need(c);
-    const long long r = (need(c) + per_round - 1) / per_round;
-    hi = r > hi ? r : hi;
-  }
-  auto blocks = [&](long long R) {
+// Workgroups of a grouped persistent launch.  Cell c needs rounds(c)
+// workgroup-rounds of work (its items over what one workgroup takes per
+// round), each lasting about cost(c).  The launch lasts as long as its slowest
+// cell, so the counts are chosen for the smallest time T with
+// sum_c ceil(rounds(c) / floor(T / cost(c))) <= cap (the resident
+// workgroups): no workgroup waits for a second wave, and every cell finishes
+// within T.  (Shares rounded up from a proportional split can exceed cap by a
+// few workgroups, which then run after everything else and double the launch
+// time.)  Fills start[0..n] and returns start[n] (n when n > cap).
+template <class Rounds, class Cost>
+inline int share_work(int n, Rounds rounds, Cost cost, long long cap, int* start) {
+  auto blocks_at = [&](long long T, int c) {
+    const long long per = T / cost(c);  // rounds one workgroup of cell c fits in T
+    if (per < 1) return rounds(c) + cap + 1;  // does not fit
+    const long long k = (rounds(c) + per - 1) / per;
+    return k < 1 ? 1ll : k;
+  };
+  auto total_at = [&](long long T) {
     long long b = 0;
-    for (int c = 0; c < n; ++c) {
-      const long long k = (need(c) + per_round * R - 1) / (per_round * R);
-      b += k < 1 ? 1 : k;
-    }
+    for (int c = 0; c < n; ++c) b += blocks_at(T, c);
     return b;
   };
-  long long lo = (total + per_round * cap - 1) / (per_round * cap);
+  long long hi = 1, work = 0;
+  for (int c = 0; c < n; ++c) {
+    const long long w = rounds(c) * cost(c);
+    hi = w > hi ? w : hi;  // one workgroup per cell
+    work += w;
+  }
+  long long lo = work / (cap > 0 ? cap : 1);
   lo = lo < 1 ? 1 : (lo > hi ? hi : lo);
-  while (lo < hi) {  // smallest R in [lo, hi] that fits (R = hi: one workgroup per cell)
-    const long long mid = (lo + hi) / 2;
-    if (blocks(mid) <= cap) hi = mid;
+  while (lo < hi) {  // smallest T in [lo, hi] that fits (T = hi: one workgroup per cell)
+    const long long mid = lo + (hi - lo) / 2;
+    if (total_at(mid) <= cap) hi = mid;
     else lo = mid + 1;
   }
   int at = 0;
   for (int c = 0; c < n; ++c) {
     start[c] = at;
-    const long long k = (need(c) + per_round * lo - 1) / (per_round * lo);
-    at += (int)(k < 1 ? 1 : k);
+    const long long k = blocks_at(lo, c);
+    at += (int)(k > rounds(c) ? (rounds(c) < 1 ? 1 : rounds(c)) : k);
   }
   start[n] = at;
   return at;
 }
 
+// Many cells of any FFT sizes in one launch (the grouped form of
+// pusch_cells): the per-cell arguments of launch_fft (with X or Xh/ex/rows),
+// up to kFftCellsPerLaunch cells; tw and start[] are filled by the launcher.
 constexpr int kFftCellsPerLaunch = 32;
 struct FftCell {
   const cf* x;
   cf* X;
   unsigned* Xh;
   signed char* ex;
+  const cf* tw;  // filled by the launcher
   long long batch, ldo;
-  int rows, out_len, shift;
+  int n_fft, rows, out_len, shift;
 };
 struct FftCells {
   FftCell cell[kFftCellsPerLaunch];
   int start[kFftCellsPerLaunch + 1];
   int n;
 };
-hipError_t launch_fft_cells(FftCells& t, int n_fft, bool h16, const cf* twiddles, int n_cu, hipStream_t s);
+hipError_t launch_fft_cells(FftCells& t, bool h16, const cf* twiddles, int n_cu, hipStream_t s);
 
 // ---------------------------------------------------------------- beamforming
 // Optional beamforming epilogue of the fused slot: the outputs of pilot
@@ -120,8 +125,10 @@ hipError_t launch_beamform(const cf* W, const cf* X, cf* Y, int n_beams, int n_a
 // Many cells of one beamforming tile shape in one launch (the grouped form of
 // pusch_cells): per cell the arguments of launch_beamform with up to 64
 // antennas (the register-tile kernels); W must be a device table; the FP16
-// form reads Xh/ex.  Cells of one launch share bf_cell_class(n_beams, n_ant).
-// ntn, ntiles and start[] are filled by the launcher.
+// form reads Xh/ex.  cls >= 0: every cell of the launch has that
+// bf_cell_class(n_beams, n_ant) (the class's own kernel); cls = -1: any
+// classes, one kernel that runs each workgroup's class.  ntn, ntiles, cls
+// and start[] are filled by the launcher.
 constexpr int kBfCellsPerLaunch = 24;
 struct BfCell {
   const cf* W;
@@ -130,7 +137,7 @@ struct BfCell {
   const signed char* ex;
   cf* Y;
   long long ldx, sx, sy, batch;
-  int nb, na, nre, ntiles, ntn;
+  int nb, na, nre, ntiles, ntn, cls;
   PilotScale ps;
 };
 struct BfCells {
@@ -234,8 +241,10 @@ hipError_t launch_mmse_fused(const cf* Y, const int2* taps, int n_tap, const Che
                              const MmseGeom& g, long long batch, hipStream_t s);
 // Many cells' fused detections in one launch (the grouped form of
 // pusch_cells): per cell the arguments of launch_mmse_fused (a batch of
-// `batch` items); cells of one launch share mmse_cell_class(n_beams, n_tap)
-// (-1: no grouped kernel); nblk_batch and start[] are filled by the launcher.
+// `batch` items, n_tap interpolation taps).  cls >= 0: every cell has that
+// mmse_cell_class(n_beams, n_tap) (the class's own kernel; -1 from
+// mmse_cell_class: no grouped kernel); cls = -1: any classes, one kernel.
+// nblk_batch, cls and start[] are filled by the launcher.
 constexpr int kMmseCellsPerLaunch = 16;
 struct MmseCell {
   const cf* Y;
@@ -245,7 +254,7 @@ struct MmseCell {
   long long batch;
   MmseGeom g;
   ChestGeom cg;
-  int nblk_batch;
+  int n_tap, nblk_batch, cls;
 };
 struct MmseCells {
   MmseCell cell[kMmseCellsPerLaunch];

@@ -582,15 +582,24 @@ hipError_t launch_lps(const cf* H, const cf* Y, cf* Xh, int* st, const MmseGeom&
 namespace {
 
 // FUSED: NT interpolation taps per (subcarrier, UE), 0 when H is read.
+// LDS of a workgroup: the lower triangles of G (then of L in place), the
+// matched filters P[i][d] = (H^H y_d)_i (then the staged solutions; 16-byte
+// aligned) and the reciprocal diagonals of L.
+struct MfmaLds {
+  cf G[kSPW * kTri];
+  cf P[kSPW * kMat];
+  float Dinv[kSPW * kDinv];
+};
+
 // blk: the workgroup's logical block (kSPW subcarriers of one batch item).
 template <int KS, bool FUSED, int NT>
-__device__ __forceinline__ void mmse_mfma_body(const int blk, const cf* __restrict__ H, const cf* __restrict__ Y,
-                                               const int2* __restrict__ taps, cf* __restrict__ Xh,
-                                               int* __restrict__ st, const MmseGeom& g, const ChestGeom& cg,
-                                               int nblk_batch) {
-  __shared__ cf Gs[kSPW * kTri];  // lower triangle of G, then of L in place
-  __shared__ __align__(16) cf Ps[kSPW * kMat];  // P[i][d] = (H^H y_d)_i; then the staged solutions
-  __shared__ float Dinv[kSPW * kDinv];
+__device__ __forceinline__ void mmse_mfma_body(MfmaLds& lds, const int blk, const cf* __restrict__ H,
+                                               const cf* __restrict__ Y, const int2* __restrict__ taps,
+                                               cf* __restrict__ Xh, int* __restrict__ st, const MmseGeom& g,
+                                               const ChestGeom& cg, int nblk_batch) {
+  cf* __restrict__ Gs = lds.G;
+  cf* __restrict__ Ps = lds.P;
+  float* __restrict__ Dinv = lds.Dinv;
   const int lane = threadIdx.x;
   const int c16 = lane & 15, q = lane >> 4;
   const int nb = g.n_beams, nue = g.n_ue, nsc = g.n_sc, nd = g.n_data;
@@ -780,25 +789,30 @@ __device__ __forceinline__ void mmse_mfma_body(const int blk, const cf* __restri
     int fail = 0;
     float* dinv = Dinv + grp * kDinv;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {  // padded rows / columns beyond n_ue stay the identity
-      // sum_m L_im conj(L_jm) as positive multiply-adds of broadcast values
-      // (each one can take the broadcast as its DPP operand), then t
-      float sr = 0.f, sp = 0.f, sm = 0.f;
+    for (int j = 0; j < 16; ++j) {
+      // padded rows / columns beyond n_ue stay the identity: G is zero off
+      // the diagonal there (zero rows of H) and 1 on it, so is L, and the
+      // substitutions never read that part (a uniform branch)
+      if (j < nue) {
+        // sum_m L_im conj(L_jm) as positive multiply-adds of broadcast values
+        // (each one can take the broadcast as its DPP operand), then t
+        float sr = 0.f, sp = 0.f, sm = 0.f;
 #pragma unroll
-      for (int m = 0; m < j; ++m) {
-        const cf c = row_bcast_c(L[m], j);
-        const float cr = c.r, ci = c.i;
-        sr = __builtin_fmaf(cr, L[m].r, sr);
-        sr = __builtin_fmaf(ci, L[m].i, sr);
-        sp = __builtin_fmaf(cr, L[m].i, sp);
-        sm = __builtin_fmaf(ci, L[m].r, sm);
+        for (int m = 0; m < j; ++m) {
+          const cf c = row_bcast_c(L[m], j);
+          const float cr = c.r, ci = c.i;
+          sr = __builtin_fmaf(cr, L[m].r, sr);
+          sr = __builtin_fmaf(ci, L[m].i, sr);
+          sp = __builtin_fmaf(cr, L[m].i, sp);
+          sm = __builtin_fmaf(ci, L[m].r, sm);
+        }
+        const cf t = cf{L[j].r - sr, L[j].i - (sp - sm)};
+        const float dpiv = row_bcast(t.r, j);
+        fail |= (dpiv > 0.f && dpiv <= 3.402823466e38f) ? 0 : 1;
+        const float inv = rsqrtf(dpiv);  // 1 / L_jj
+        L[j] = cf{t.r * inv, t.i * inv};
+        dinv[j] = inv;
       }
-      const cf t = cf{L[j].r - sr, L[j].i - (sp - sm)};
-      const float dpiv = row_bcast(t.r, j);
-      fail |= (dpiv > 0.f && dpiv <= 3.402823466e38f) ? 0 : 1;
-      const float inv = rsqrtf(dpiv);  // 1 / L_jj
-      L[j] = cf{t.r * inv, t.i * inv};
-      dinv[j] = inv;
     }
 #pragma unroll
     for (int j = 0; j < 16; ++j)
@@ -865,8 +879,9 @@ template <int KS, bool FUSED, int NT>
 __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, const cf* __restrict__ Y,
                                                   const int2* __restrict__ taps, cf* __restrict__ Xh,
                                                   int* __restrict__ st, MmseGeom g, ChestGeom cg, int nblk_batch) {
+  __shared__ __align__(16) MfmaLds lds;
   // neighbouring subcarriers on one XCD (shared pilot rows)
-  mmse_mfma_body<KS, FUSED, NT>(xcd_block(blockIdx.x, gridDim.x), H, Y, taps, Xh, st, g, cg, nblk_batch);
+  mmse_mfma_body<KS, FUSED, NT>(lds, xcd_block(blockIdx.x, gridDim.x), H, Y, taps, Xh, st, g, cg, nblk_batch);
 }
 
 // Many cells in one launch: logical block b (after the XCD renumbering, so a
@@ -878,7 +893,8 @@ __global__ __launch_bounds__(64) void k_mmse_mfma_cells(MmseCells t) {
   int c = 0;
   while (c + 1 < t.n && blk >= t.start[c + 1]) ++c;
   const MmseCell& e = t.cell[c];
-  mmse_mfma_body<KS, true, NT>(blk - t.start[c], nullptr, e.Y, e.taps, e.Xh, e.st, e.g, e.cg, e.nblk_batch);
+  __shared__ __align__(16) MfmaLds lds;
+  mmse_mfma_body<KS, true, NT>(lds, blk - t.start[c], nullptr, e.Y, e.taps, e.Xh, e.st, e.g, e.cg, e.nblk_batch);
 }
 
 template <int KS, bool FUSED, int NT>
@@ -904,6 +920,31 @@ hipError_t dispatch_mfma(const cf* H, const cf* Y, const int2* taps, const Chest
   return hipErrorInvalidValue;
 }
 
+// Any detection classes in one launch: each workgroup runs its cell's class.
+__global__ __launch_bounds__(64) void k_mmse_mfma_any(MmseCells t) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  int c = 0;
+  while (c + 1 < t.n && blk >= t.start[c + 1]) ++c;
+  const MmseCell& e = t.cell[c];
+  const int b = blk - t.start[c];
+  __shared__ __align__(16) MfmaLds lds;
+#define MM_CASE(CLS, KS, NT)                                                                       \
+  case CLS:                                                                                       \
+    mmse_mfma_body<KS, true, NT>(lds, b, nullptr, e.Y, e.taps, e.Xh, e.st, e.g, e.cg, e.nblk_batch); \
+    break;
+  switch (e.cls) {
+    MM_CASE(0, 2, 2)
+    MM_CASE(1, 2, 2 * kMaxPilots)
+    MM_CASE(2, 4, 2)
+    MM_CASE(3, 4, 2 * kMaxPilots)
+    MM_CASE(4, 8, 2)
+    MM_CASE(5, 8, 2 * kMaxPilots)
+    MM_CASE(6, 16, 2)
+    default: MM_CASE(7, 16, 2 * kMaxPilots)
+  }
+#undef MM_CASE
+}
+
 template <int KS>
 hipError_t launch_cells_ks(MmseCells& t, int n_tap, unsigned blocks, hipStream_t s) {
   if (n_tap == 2) hipLaunchKernelGGL((k_mmse_mfma_cells<KS, 2>), dim3(blocks), dim3(64), 0, s, t);
@@ -920,13 +961,13 @@ int mmse_cell_class(int n_beams, int n_tap) {
 }
 
 hipError_t launch_mmse_cells(MmseCells& t, int cls, hipStream_t s) {
-  if (t.n < 1 || t.n > kMmseCellsPerLaunch || cls < 0 || cls >= 8) return hipErrorInvalidValue;
-  const int n_tap = cls % 2 ? 2 * kMaxPilots : 2;
+  if (t.n < 1 || t.n > kMmseCellsPerLaunch || cls < -1 || cls >= 8) return hipErrorInvalidValue;
   long long start = 0;
   for (int c = 0; c < t.n; ++c) {
     MmseCell& e = t.cell[c];
+    e.cls = mmse_cell_class(e.g.n_beams, e.n_tap);
     if (e.batch <= 0 || e.g.n_data > kMaxD || e.g.n_data < 1 || e.g.n_beams != e.cg.n_beams ||
-        !mmse_fusable(e.g.n_ue, e.g.n_beams, e.cg.y_batch) || mmse_cell_class(e.g.n_beams, n_tap) != cls)
+        !mmse_fusable(e.g.n_ue, e.g.n_beams, e.cg.y_batch) || e.cls < 0 || (cls >= 0 && e.cls != cls))
       return hipErrorInvalidValue;
     e.nblk_batch = (e.g.n_sc + kSPW - 1) / kSPW;
     t.start[c] = (int)start;
@@ -934,6 +975,11 @@ hipError_t launch_mmse_cells(MmseCells& t, int cls, hipStream_t s) {
     if (start > 0x7fffffffLL) return hipErrorInvalidValue;
   }
   t.start[t.n] = (int)start;
+  if (cls < 0) {
+    hipLaunchKernelGGL(k_mmse_mfma_any, dim3((unsigned)start), dim3(64), 0, s, t);
+    return hipGetLastError();
+  }
+  const int n_tap = cls % 2 ? 2 * kMaxPilots : 2;
   switch (cls / 2) {
     case 0: return launch_cells_ks<2>(t, n_tap, (unsigned)start, s);
     case 1: return launch_cells_ks<4>(t, n_tap, (unsigned)start, s);

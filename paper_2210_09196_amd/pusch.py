@@ -19,6 +19,11 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 
 MAX_PILOTS = 4
 CELLS_MIXED, CELLS_STREAMS = 1, 2  # pusch_cells flags
+
+
+def cells_with_plan(p: int) -> int:
+    """pusch_cells flag that runs launch plan p (PUSCH_CELLS_WITH_PLAN)."""
+    return 4 | (p << 3)
 SLOT_STAGES = ("fft", "beamform", "chest", "mmse")
 
 
@@ -47,6 +52,12 @@ class SlotDesc(ctypes.Structure):
 
 
 _lib = None
+class CellsPlan(ctypes.Structure):
+    _fields_ = [("fft_merged", ctypes.c_int), ("bf_merged", ctypes.c_int), ("mmse_merged", ctypes.c_int)]
+
+
+CELLS_PLANS = 8
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _LL = ctypes.c_longlong
@@ -68,6 +79,10 @@ _SIG = {
     "pusch_cells_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SlotDesc), _I, ctypes.POINTER(_LL), _I]),
     "pusch_cells": (_I, [ctypes.POINTER(SlotDesc), _I, ctypes.POINTER(_LL), ctypes.POINTER(_P), ctypes.POINTER(_P),
                          ctypes.POINTER(_P), _P, ctypes.c_size_t, _I, _P]),
+    "pusch_cells_tune": (_I, [ctypes.POINTER(SlotDesc), _I, ctypes.POINTER(_LL), ctypes.POINTER(_P),
+                              ctypes.POINTER(_P), ctypes.POINTER(_P), _P, ctypes.c_size_t, _I, _I,
+                              ctypes.POINTER(CellsPlan), ctypes.POINTER(_F), _I, _P]),
+    "pusch_cells_plan_get": (_I, [ctypes.POINTER(SlotDesc), _I, ctypes.POINTER(_LL), _I, ctypes.POINTER(CellsPlan)]),
     "pusch_dn_workspace_bytes": (ctypes.c_size_t, [_I, _I, _LL]),
     "pusch_dn_ls_grid": (_I, [_P, _P, _P, _I, _I, _I, _I, _I, ctypes.POINTER(_I), _LL, _P]),
     "pusch_dn_forward": (_I, [_P, _P, _P, _F, _I, _I, _LL, _P, ctypes.c_size_t, _P]),
@@ -383,13 +398,19 @@ class Cells:
     cells the grouped kernels take as one launch per stage and kernel shape on
     the current torch stream, and the others on the library's side streams,
     forked from and joined back to that stream, so it can be captured into a
-    HIP graph; grouped=False runs every cell on the side streams.
+    HIP graph; grouped=False runs every cell on the side streams, and plan=p
+    fixes the grouped cells' launch plan (else the one pusch_cells_tune
+    recorded for the cell set, or the default).
     """
 
-    def __init__(self, cells: list[dict], device="cuda", precision: str = "fp32", grouped: bool = True):
+    def __init__(self, cells: list[dict], device="cuda", precision: str = "fp32", grouped: bool = True,
+                 plan: int | None = None):
         if precision not in ("fp32", "mixed"):
             raise PuschError("precision is 'fp32' or 'mixed'")
-        self.flags = (CELLS_MIXED if precision == "mixed" else 0) | (0 if grouped else CELLS_STREAMS)
+        if plan is not None and not 0 <= plan < CELLS_PLANS:
+            raise PuschError(f"plan is 0..{CELLS_PLANS - 1}")
+        self.flags = (CELLS_MIXED if precision == "mixed" else 0) | (0 if grouped else CELLS_STREAMS) | \
+            (0 if plan is None else cells_with_plan(plan))
         n = len(cells)
         if n < 1:
             raise PuschError("at least one cell")
@@ -429,6 +450,29 @@ class Cells:
         return xs, st
 
     def __call__(self, x_tds, pilots, x_hats=None, statuses=None):
+        args, x_hats, statuses = self._args(x_tds, pilots, x_hats, statuses)
+        _check(lib().pusch_cells(*args, _stream()), "pusch_cells")
+        return x_hats, statuses
+
+    def tune(self, x_tds, pilots, reps: int = 5, x_hats=None, statuses=None):
+        """pusch_cells_tune: times every launch plan on these inputs and records the fastest for
+        this cell set; returns (plan dict, median us of plan p for p in 0..7)."""
+        args, x_hats, statuses = self._args(x_tds, pilots, x_hats, statuses)
+        plan = CellsPlan()
+        us = (_F * CELLS_PLANS)()
+        _check(lib().pusch_cells_tune(*args, int(reps), ctypes.byref(plan), us, CELLS_PLANS, _stream()),
+               "pusch_cells_tune")
+        return _plan_dict(plan), [float(v) for v in us]
+
+    def plan(self):
+        """(plan dict, tuned) that pusch_cells uses for this cell set."""
+        plan = CellsPlan()
+        rc = lib().pusch_cells_plan_get(self.descs, self.n, self.n_slot, self.flags, ctypes.byref(plan))
+        if rc < 0:
+            _check(rc, "pusch_cells_plan_get")
+        return _plan_dict(plan), bool(rc)
+
+    def _args(self, x_tds, pilots, x_hats, statuses):
         if len(x_tds) != self.n or len(pilots) != self.n:
             raise PuschError(f"{self.n} x_td and pilots tensors expected")
         if x_hats is None:
@@ -453,9 +497,14 @@ class Cells:
         xp = (_P * self.n)(*[t.data_ptr() for t in x_tds])
         op = (_P * self.n)(*[t.data_ptr() for t in x_hats])
         sp = None if statuses is None else (_P * self.n)(*[_ptr(t) for t in statuses])
-        _check(lib().pusch_cells(self.descs, self.n, self.n_slot, xp, op, sp, self.ws.data_ptr(), self.ws_bytes,
-                                 self.flags, _stream()), "pusch_cells")
-        return x_hats, statuses
+        self._keep = (xp, op, sp)
+        return (self.descs, self.n, self.n_slot, xp, op, sp, self.ws.data_ptr(), self.ws_bytes, self.flags), \
+            x_hats, statuses
+
+
+def _plan_dict(plan: CellsPlan) -> dict:
+    return {"fft_merged": bool(plan.fft_merged), "bf_merged": bool(plan.bf_merged),
+            "mmse_merged": bool(plan.mmse_merged)}
 
 
 def profile_begin(max_calls: int) -> None:

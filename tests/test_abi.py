@@ -23,7 +23,7 @@ def lib():
 
 def test_exports_every_declared_symbol(lib):
     names = pusch.header_symbols()
-    assert len(names) == 25
+    assert len(names) == 27
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(pusch._SIG)
@@ -268,7 +268,17 @@ def test_cells_validation(lib):
     assert f(descs, 2, ns, x, o, None, ws, need - 1, 0, None) == ENOMEM
     assert f(descs, 2, ns, x, o, None, ctypes.c_void_p(0x4000000010), need, 0, None) == EINVAL  # unaligned
     assert f(descs, 2, ns, x, o, None, None, need, 0, None) == EINVAL
-    assert f(descs, 2, ns, x, o, None, ws, need, 4, None) == EINVAL  # unknown flag
+    assert f(descs, 2, ns, x, o, None, ws, need, 1 << 6, None) == EINVAL  # unknown flag
+    # the tuner: repetitions and the times array checked before anything runs
+    plan = pusch.CellsPlan()
+    us = (ctypes.c_float * 8)()
+    tune = lib.pusch_cells_tune
+    assert tune(descs, 2, ns, x, o, None, ws, need, 0, 0, ctypes.byref(plan), us, 8, None) == EINVAL
+    assert tune(descs, 2, ns, x, o, None, ws, need, 0, 1001, ctypes.byref(plan), us, 8, None) == EINVAL
+    assert tune(descs, 2, ns, x, o, None, ws, need, 0, 3, ctypes.byref(plan), None, 8, None) == EINVAL
+    assert tune(None, 2, ns, x, o, None, ws, need, 0, 3, ctypes.byref(plan), us, 8, None) == EINVAL
+    assert lib.pusch_cells_plan_get(descs, 2, ns, 0, None) == EINVAL
+    assert lib.pusch_cells_plan_get(descs, 0, ns, 0, ctypes.byref(plan)) == EINVAL
     # one invalid cell rejects the whole call
     bad, nsb = _cell_arrays([small, _desc(sigma2=-1.0)], [1, 1])
     assert f(bad, 2, nsb, x, o, None, ws, 1 << 40, 0, None) == EINVAL

@@ -272,3 +272,37 @@ def test_more_cells_of_one_shape_than_one_launch_holds():
             ref = O.receive_slot(b["x_td"][k], b["pilots"][k], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
                                  n_beams=cfg.n_beams)
             assert_xhat(host(xh[c])[k], ref["x_hat"], TOL_X, (c, k))
+
+
+def test_every_launch_plan_gives_the_same_bits(uneven48):
+    # one launch per stage for every kernel shape, or one per shape: the same arithmetic per tile
+    geoms, xs, ps = uneven48[4:]
+    for precision in ("fp32", "mixed"):
+        ref, ref_st = pusch.Cells(geoms, precision=precision, grouped=False)(xs, ps)
+        for p in range(pusch.CELLS_PLANS):
+            out, st = pusch.Cells(geoms, precision=precision, plan=p)(xs, ps)
+            torch.cuda.synchronize()
+            for c in range(len(geoms)):
+                assert torch.equal(out[c], ref[c]) and torch.equal(st[c], ref_st[c]), (precision, p, c)
+
+
+def test_tuner_records_the_fastest_plan_for_the_cell_set():
+    cfgs, batches, geoms = make_cells(CELLS[:4], seed0=3300)
+    cells = pusch.Cells(geoms)
+    xs = [dev(b["x_td"]) for b in batches]
+    ps = [dev(b["pilots"]) for b in batches]
+    ref, ref_st = pusch.Cells(geoms, grouped=False)(xs, ps)
+    plan0, tuned0 = cells.plan()
+    assert not tuned0 and plan0 == {"fft_merged": True, "bf_merged": False, "mmse_merged": True}
+    plan, us = cells.tune(xs, ps, reps=3)
+    print(f"[cells] tuned plan {plan}; us per plan {[round(u, 1) for u in us]}", flush=True)
+    assert all(u > 0 for u in us)
+    best = min(range(len(us)), key=lambda p: us[p])
+    assert plan == {"fft_merged": bool(best & 1), "bf_merged": bool(best & 2), "mmse_merged": bool(best & 4)}
+    assert cells.plan() == (plan, True)
+    out, st = cells(xs, ps)
+    for c in range(len(geoms)):
+        assert torch.equal(out[c], ref[c]) and torch.equal(st[c], ref_st[c]), c
+    # another cell set keeps the default
+    other = pusch.Cells(geoms[:3])
+    assert other.plan() == (plan0, False)
