@@ -17,7 +17,9 @@ Readings of points the paper leaves open (each also stated where used):
   R3  active subcarrier k <-> FFT bin (k - N_act//2) mod N;
   R4  default beamformer = first N_B rows of the unitary N_R-point DFT;
   R5  pilots of the N_L UEs form a comb: pilot symbol j, subcarrier k belongs
-      to UE (k + o_j) mod N_L with o_j = j * (N_L // N_pilot);
+      to UE (k + o_j) mod N_L with o_j = j * (N_L // N_pilot) (staggered), or
+      o_j = 0 for every j when the call asks for an aligned comb (every pilot
+      symbol then puts each UE's pilots on the same subcarriers);
   R6  the channel is static over the slot: all pilot symbols are merged into
       one estimate and the Cholesky factor is computed once per subcarrier and
       reused for every data symbol;
@@ -26,6 +28,12 @@ Readings of points the paper leaves open (each also stated where used):
   R17 noise estimation compares each pilot RE with the prediction from the
       UE's channel interpolated from its other pilot positions (leave one
       out), normalised by the exact noise gain of that prediction;
+  R21 ... except at a position where c >= 2 pilot symbols carry the UE's
+      pilot: there each of those REs is compared with its pilot times the
+      mean of the c LS values at that same subcarrier, with noise gain
+      1 - 2/c + |p_j|^2 / c^2 sum_s 1/|p_s|^2.  The channel is the same in
+      every term, so this residual holds noise only, whatever the channel's
+      frequency selectivity (for a channel static over the slot, R6);
   R18 for a channel that varies over the slot, each pilot symbol gives its own
       estimate (its own comb positions only), and data symbol s uses the
       linear interpolation in s between the two pilot symbols around it
@@ -92,12 +100,12 @@ def beamform(W, Xa) -> np.ndarray:
     return np.matmul(np.asarray(W, np.complex128), np.asarray(Xa, np.complex128))
 
 
-def pilot_owner(n_sc: int, j: int, n_ue: int, n_pilot: int) -> np.ndarray:
-    """UE owning each subcarrier of pilot symbol j (reading R5)."""
-    return (np.arange(n_sc) + j * (n_ue // n_pilot)) % n_ue
+def pilot_owner(n_sc: int, j: int, n_ue: int, n_pilot: int, aligned: bool = False) -> np.ndarray:
+    """UE owning each subcarrier of pilot symbol j (reading R5; aligned: o_j = 0)."""
+    return (np.arange(n_sc) + (0 if aligned else j * (n_ue // n_pilot))) % n_ue
 
 
-def ls_channel_estimate(Yp, pilots, n_ue: int, use=None) -> np.ndarray:
+def ls_channel_estimate(Yp, pilots, n_ue: int, use=None, aligned: bool = False) -> np.ndarray:
     """Least-squares channel estimation on block-type pilot symbols (Sec. II,
     CHE; Table 1, row "CHE": an element-wise division per beam and UE).
 
@@ -109,7 +117,8 @@ def ls_channel_estimate(Yp, pilots, n_ue: int, use=None) -> np.ndarray:
     first and last pilot position.
 
     Yp: [N_p, N_B, K] beam-domain pilot symbols; pilots: [N_p, K]; use: the
-    pilot symbols (indices j) to take, all by default.
+    pilot symbols (indices j) to take, all by default; aligned: the comb of R5
+    without stagger.
     Returns H_hat [K, N_B, N_L] (one N_B x N_L matrix per subcarrier, Eq. 1).
     """
     Yp = np.asarray(Yp, np.complex128)
@@ -123,7 +132,7 @@ def ls_channel_estimate(Yp, pilots, n_ue: int, use=None) -> np.ndarray:
     for l in range(n_ue):
         pos_list, val_list = [], []
         for j in use:
-            ks = np.nonzero(pilot_owner(K, j, n_ue, n_pilot) == l)[0]
+            ks = np.nonzero(pilot_owner(K, j, n_ue, n_pilot, aligned) == l)[0]
             p = pilots[j, ks]
             pos_list.append(ks)
             val_list.append(Yp[j][:, ks] * (np.conj(p) / (p.real ** 2 + p.imag ** 2)))
@@ -142,7 +151,7 @@ def ls_channel_estimate(Yp, pilots, n_ue: int, use=None) -> np.ndarray:
     return H
 
 
-def time_interpolated_estimate(Yp, pilots, n_ue: int, pilot_symb, symb) -> np.ndarray:
+def time_interpolated_estimate(Yp, pilots, n_ue: int, pilot_symb, symb, aligned: bool = False) -> np.ndarray:
     """Channel estimate of OFDM symbol `symb` for a channel that changes over
     the slot (reading R18): pilot symbol j alone gives H_j (ls_channel_estimate
     with use=[j]); between the pilot symbols p_a < symb < p_b next to it the
@@ -154,17 +163,17 @@ def time_interpolated_estimate(Yp, pilots, n_ue: int, pilot_symb, symb) -> np.nd
     """
     ps = list(pilot_symb)
     if symb <= ps[0]:
-        return ls_channel_estimate(Yp, pilots, n_ue, use=[0])
+        return ls_channel_estimate(Yp, pilots, n_ue, use=[0], aligned=aligned)
     if symb >= ps[-1]:
-        return ls_channel_estimate(Yp, pilots, n_ue, use=[len(ps) - 1])
+        return ls_channel_estimate(Yp, pilots, n_ue, use=[len(ps) - 1], aligned=aligned)
     b = next(j for j, p in enumerate(ps) if p > symb)
     a = b - 1
-    Ha = ls_channel_estimate(Yp, pilots, n_ue, use=[a])
-    Hb = ls_channel_estimate(Yp, pilots, n_ue, use=[b])
+    Ha = ls_channel_estimate(Yp, pilots, n_ue, use=[a], aligned=aligned)
+    Hb = ls_channel_estimate(Yp, pilots, n_ue, use=[b], aligned=aligned)
     return ((ps[b] - symb) * Ha + (symb - ps[a]) * Hb) / (ps[b] - ps[a])
 
 
-def noise_variance_estimate(Yp, pilots, n_ue: int) -> float:
+def noise_variance_estimate(Yp, pilots, n_ue: int, aligned: bool = False) -> float:
     """Noise estimation (Sec. II, NE; Table 1, row "NE"): the noise variance
     from the differences between the received pilot REs and the values that
     the estimated channel and the known pilots predict there (reading R17).
@@ -185,7 +194,15 @@ def noise_variance_estimate(Yp, pilots, n_ue: int) -> float:
     positions used.  Requires K >= 2 N_L (every UE then has at least two
     pilot positions).
 
-    Yp: [N_p, N_B, K] beam-domain pilot symbols; pilots: [N_p, K].
+    Where c >= 2 pilot symbols put UE l's pilot at k (reading R21), those REs
+    are compared at k itself instead: h(k) is the mean m of their c LS values,
+    r = Y_j[:, k] - p_j[k] m, and since m holds 1/c of this RE's own noise,
+        kappa = 1 - 2/c + |p_j[k]|^2 / c^2 sum_{s at k} 1 / |p_s|^2
+    (the c REs of a position add up to c - 1 for equal pilot powers).  This
+    is unbiased for any frequency selectivity.
+
+    Yp: [N_p, N_B, K] beam-domain pilot symbols; pilots: [N_p, K]; aligned:
+    the comb of R5 without stagger.
     Returns sigma2_hat (float).
     """
     Yp = np.asarray(Yp, np.complex128)
@@ -198,7 +215,7 @@ def noise_variance_estimate(Yp, pilots, n_ue: int) -> float:
         # the pilot REs of UE l, grouped by subcarrier
         at = {}
         for j in range(n_pilot):
-            for k in np.nonzero(pilot_owner(K, j, n_ue, n_pilot) == l)[0]:
+            for k in np.nonzero(pilot_owner(K, j, n_ue, n_pilot, aligned) == l)[0]:
                 at.setdefault(int(k), []).append(j)
         pos = sorted(at)
         mean, cnt, inv_pow = {}, {}, {}
@@ -208,6 +225,13 @@ def noise_variance_estimate(Yp, pilots, n_ue: int) -> float:
             cnt[k] = len(ls)
             inv_pow[k] = sum(1.0 / abs(pilots[j, k]) ** 2 for j in at[k])
         for i, k in enumerate(pos):
+            c = cnt[k]
+            if c >= 2:  # the same subcarrier on several pilot symbols (R21)
+                for j in at[k]:
+                    r = Yp[j][:, k] - pilots[j, k] * mean[k]
+                    num += float(np.sum(r.real ** 2 + r.imag ** 2))
+                    den += n_beams * (1.0 - 2.0 / c + abs(pilots[j, k]) ** 2 / c ** 2 * inv_pow[k])
+                continue
             below = pos[i - 1] if i > 0 else None
             above = pos[i + 1] if i + 1 < len(pos) else None
             if below is not None and above is not None:
@@ -307,7 +331,7 @@ def mmse_detect(H, Yd, sigma2: float) -> tuple[np.ndarray, np.ndarray]:
 
 
 def receive_slot(x_td, pilots, pilot_symb, n_ue: int, n_sc: int, sigma2: float | None, W=None,
-                 n_beams: int | None = None, time_varying: bool = False) -> dict:
+                 n_beams: int | None = None, time_varying: bool = False, aligned: bool = False) -> dict:
     """The whole receive chain of one slot (Sec. II), in the paper's order.
 
     x_td: [S, N_R, N] time-domain samples; pilots: [N_p, K]; pilot_symb: the
@@ -316,6 +340,7 @@ def receive_slot(x_td, pilots, pilot_symb, n_ue: int, n_sc: int, sigma2: float |
     pilot symbols (noise_variance_estimate) and used in the MIMO stage.
     time_varying: every data symbol gets its own estimate
     (time_interpolated_estimate) and its own factorisation (reading R18).
+    aligned: the pilot comb without stagger (reading R5).
     Returns a dict with the intermediates and the result: X [S, N_R, K],
     Y [S, N_B, K], H [K, N_B, N_L] (the merged static estimate), sigma2,
     x_hat [D, K, N_L], ok [K] (with time_varying: ok for every data symbol).
@@ -328,9 +353,9 @@ def receive_slot(x_td, pilots, pilot_symb, n_ue: int, n_sc: int, sigma2: float |
     Y = beamform(W, X)
     pilot_symb = list(pilot_symb)
     data_symb = [s for s in range(S) if s not in pilot_symb]
-    H = ls_channel_estimate(Y[pilot_symb], pilots, n_ue)
+    H = ls_channel_estimate(Y[pilot_symb], pilots, n_ue, aligned=aligned)
     if sigma2 is None:
-        sigma2 = noise_variance_estimate(Y[pilot_symb], pilots, n_ue)
+        sigma2 = noise_variance_estimate(Y[pilot_symb], pilots, n_ue, aligned=aligned)
     Yd = np.swapaxes(Y[data_symb], -1, -2)  # [D, K, N_B]
     if not time_varying:
         x_hat, ok = mmse_detect(H, Yd, sigma2)
@@ -338,7 +363,7 @@ def receive_slot(x_td, pilots, pilot_symb, n_ue: int, n_sc: int, sigma2: float |
         x_hat = np.zeros((len(data_symb), n_sc, n_ue), dtype=np.complex128)
         ok = np.ones(n_sc, dtype=bool)
         for d, s in enumerate(data_symb):
-            Hs = time_interpolated_estimate(Y[pilot_symb], pilots, n_ue, pilot_symb, s)
+            Hs = time_interpolated_estimate(Y[pilot_symb], pilots, n_ue, pilot_symb, s, aligned)
             xs, oks = mmse_detect(Hs, Yd[d:d + 1], sigma2)
             x_hat[d] = xs[0]
             ok &= oks

@@ -66,6 +66,7 @@ class SlotConfig:
     tdl_taps: int = 8
     scs_hz: float = 30e3
     doppler_hz: float = 0.0  # > 0: every tap of every (antenna, UE) pair turns at f_D cos(theta) over the slot
+    comb_aligned: bool = False  # True: every pilot symbol puts each UE's pilots on the same subcarriers
 
     @property
     def n_pilot(self) -> int:
@@ -129,9 +130,10 @@ def qam_modulate(bit_array: np.ndarray, bits: int) -> np.ndarray:
     return pts[(bit_array.astype(np.int64) * weights).sum(-1)]
 
 
-def pilot_owner(n_sc: int, j: int, n_ue: int, n_pilot: int) -> np.ndarray:
-    """UE index whose pilot sits on each subcarrier of pilot symbol j (comb with stagger)."""
-    o_j = j * (n_ue // n_pilot)
+def pilot_owner(n_sc: int, j: int, n_ue: int, n_pilot: int, aligned: bool = False) -> np.ndarray:
+    """UE index whose pilot sits on each subcarrier of pilot symbol j (comb with stagger, or without
+    when aligned)."""
+    o_j = 0 if aligned else j * (n_ue // n_pilot)
     return (np.arange(n_sc) + o_j) % n_ue
 
 
@@ -196,7 +198,7 @@ def make_slot(cfg: SlotConfig, seed: int, sigma2: float | None = None) -> dict:
     for d, s in enumerate(cfg.data_symb):
         tx[s] = data[d]
     for j, s in enumerate(cfg.pilot_symb):
-        owner = pilot_owner(K, j, L, cfg.n_pilot)
+        owner = pilot_owner(K, j, L, cfg.n_pilot, cfg.comb_aligned)
         tx[s, owner, np.arange(K)] = pilots[j]
 
     # Time variation (drawn last, so slots without it keep their values): tap t

@@ -365,6 +365,44 @@ def test_noise_estimate_is_unbiased(n_ue, n_pilot):
     assert se < 0.02
 
 
+def _selective_inputs(rng, K, n_ue, n_pilot, n_beams, sigma2, aligned):
+    """Pilot symbols through a channel drawn independently on every subcarrier (no frequency
+    correlation at all), static over the slot, plus CN(0, sigma2) noise; unit pilots of random phase."""
+    h = crandn(n_ue, n_beams, K, rng=rng)
+    p = np.exp(2j * np.pi * rng.uniform(size=(n_pilot, K)))
+    Y = np.zeros((n_pilot, n_beams, K), complex)
+    for j in range(n_pilot):
+        own = O.pilot_owner(K, j, n_ue, n_pilot, aligned)
+        for k in range(K):
+            Y[j, :, k] = h[own[k], :, k] * p[j, k]
+    return Y + crandn(n_pilot, n_beams, K, rng=rng) * math.sqrt(sigma2 / 2), p
+
+
+@pytest.mark.parametrize("n_pilot", [2, 3])
+def test_noise_estimate_aligned_comb_is_unbiased_on_any_channel(n_pilot):
+    # R21: with the aligned comb every pilot RE is compared at its own subcarrier, so even a channel
+    # with no correlation between subcarriers leaves noise only; the staggered comb's leave-one-out
+    # prediction cannot follow such a channel and counts the channel's own variation as noise
+    rng = np.random.default_rng(300 + n_pilot)
+    sigma2 = 0.01
+    ratios = []
+    for _ in range(30):
+        Y, p = _selective_inputs(rng, 160, 4, n_pilot, 4, sigma2, aligned=True)
+        ratios.append(O.noise_variance_estimate(Y, p, 4, aligned=True) / sigma2)
+    m, se = np.mean(ratios), np.std(ratios, ddof=1) / math.sqrt(len(ratios))
+    assert abs(m - 1.0) < 5 * se and se < 0.03, (m, se)
+    Y, p = _selective_inputs(rng, 160, 4, n_pilot, 4, sigma2, aligned=False)
+    assert O.noise_variance_estimate(Y, p, 4) > 20 * sigma2
+
+
+def test_aligned_comb_places_every_ue_on_the_same_subcarriers():
+    for j in range(3):
+        assert np.array_equal(O.pilot_owner(12, j, 4, 3, aligned=True), np.arange(12) % 4)
+    # a staggered comb of 16 UEs on two pilot symbols shifts by 8
+    assert np.array_equal(O.pilot_owner(16, 1, 16, 2), (np.arange(16) + 8) % 16)
+    assert np.array_equal(synth.pilot_owner(16, 1, 16, 2, aligned=True), O.pilot_owner(16, 1, 16, 2, aligned=True))
+
+
 def test_noise_estimate_scales_with_power():
     Y, p = _ne_inputs(np.random.default_rng(5), 60, 4, 2, 3, 0.5, slope=0.1)
     s = O.noise_variance_estimate(Y, p, 4)
@@ -526,7 +564,7 @@ MUTATIONS = [
     ("return (np.arange(n_sc) - n_sc // 2) % n_fft", "return (np.arange(n_sc) + n_sc // 2) % n_fft"),
     ("np.exp(-2j * np.pi * ((b * r) % n_ant) / n_ant)", "np.exp(2j * np.pi * ((b * r) % n_ant) / n_ant)"),
     ("(np.conj(p) / (p.real ** 2 + p.imag ** 2))", "(p / (p.real ** 2 + p.imag ** 2))"),  # LS without conjugate
-    ("j * (n_ue // n_pilot)) % n_ue", "j * (n_ue // n_pilot) + 1) % n_ue"),  # wrong pilot owner
+    ("(0 if aligned else j * (n_ue // n_pilot))) % n_ue", "(0 if aligned else j * (n_ue // n_pilot) + 1)) % n_ue"),
     ("G = np.matmul(np.conj(np.swapaxes(H, -1, -2)), H)", "G = np.matmul(np.swapaxes(H, -1, -2), H)"),
     ("L[..., i, :j] * np.conj(row_j)", "L[..., i, :j] * row_j"),  # Crout without conjugate
     ("np.sum(row_j.real ** 2 + row_j.imag ** 2, axis=-1)", "0.0"),  # dropped term in the pivot
@@ -542,11 +580,16 @@ MUTATIONS = [
      "weights = {below: (k - below) / (above - below), above: (above - k) / (above - below)}"),
     ("gain = sum((w / cnt[m]) ** 2 * inv_pow[m]", "gain = sum((w / cnt[m]) * inv_pow[m]"),
     ("r = Yp[j][:, k] - pilots[j, k] * h", "r = Yp[j][:, k] - np.conj(pilots[j, k]) * h"),
+    # same-position residual (R21): its own share of the mean ignored, 1/c instead of 1/c^2, not used
+    ("den += n_beams * (1.0 - 2.0 / c + abs(pilots[j, k]) ** 2 / c ** 2 * inv_pow[k])",
+     "den += n_beams * (1.0 + abs(pilots[j, k]) ** 2 / c ** 2 * inv_pow[k])"),
+    ("/ c ** 2 * inv_pow[k]", "/ c * inv_pow[k]"),
+    ("if c >= 2:  # the same subcarrier", "if c >= 3:  # the same subcarrier"),
     # time-varying estimate: swapped time weights, the wrong end held after the last pilot symbol
     ("return ((ps[b] - symb) * Ha + (symb - ps[a]) * Hb) / (ps[b] - ps[a])",
      "return ((symb - ps[a]) * Ha + (ps[b] - symb) * Hb) / (ps[b] - ps[a])"),
-    ("return ls_channel_estimate(Yp, pilots, n_ue, use=[len(ps) - 1])",
-     "return ls_channel_estimate(Yp, pilots, n_ue, use=[0])"),
+    ("return ls_channel_estimate(Yp, pilots, n_ue, use=[len(ps) - 1], aligned=aligned)",
+     "return ls_channel_estimate(Yp, pilots, n_ue, use=[0], aligned=aligned)"),
 ]
 
 
