@@ -40,8 +40,9 @@
  * Pilots      block-type pilot symbols (whole OFDM symbols).  The n_ue UEs
  *             share each pilot symbol as a frequency comb: on pilot symbol j
  *             (0-based among the pilot symbols) subcarrier k carries the pilot
- *             of UE (k + j * (n_ue / n_pilot)) mod n_ue.  Pilot values must be
- *             non-zero.
+ *             of UE (k + j * (n_ue / n_pilot)) mod n_ue (staggered), or of UE
+ *             k mod n_ue on every pilot symbol when a slot descriptor asks for
+ *             the aligned comb.  Pilot values must be non-zero.
  */
 #ifndef PUSCH_H_
 #define PUSCH_H_
@@ -228,6 +229,17 @@ typedef struct {
                                        symbol (the paper counts the Cholesky decomposition per data
                                        symbol, Sec. II).  Needs n_ue <= 16, an even n_beams and no
                                        refine (PUSCH_EUNSUPPORTED otherwise) */
+  int comb_aligned;                 /* nonzero: the pilot comb without stagger -- every pilot symbol
+                                       puts UE l's pilots on the subcarriers k = l mod n_ue (instead
+                                       of k + j * (n_ue / n_pilot) = l mod n_ue).  The channel
+                                       estimate then averages the pilot symbols at each position
+                                       (half the positions of the staggered comb for two pilot
+                                       symbols), and the noise estimate compares each pilot RE with
+                                       the mean at its own subcarrier, so it holds noise only on any
+                                       channel that is static over the slot; with the staggered comb
+                                       the noise estimate predicts from neighbouring positions and
+                                       counts the channel's variation between them as noise.
+                                       pusch_slot_denoised: 0 only (PUSCH_EUNSUPPORTED otherwise) */
 } pusch_slot_desc;
 
 /* Bytes of device workspace pusch_slot needs for n_slot slots (0 on bad input). */

@@ -112,7 +112,7 @@ enum GeomTable { kCombTaps = 0, kNoiseTable = 1, kTimeTaps = 2 };
 
 int geometry_table(DeviceTables* t, GeomTable kind, const pusch::ChestGeom& g, int n_tap, const void** out,
                    const pusch::TimeTapGeom* tt = nullptr) {
-  std::vector<long long> key = {kind, g.n_sc, g.n_ue, g.n_pilot};
+  std::vector<long long> key = {kind, g.n_sc, g.n_ue, g.n_pilot, g.comb_aligned};
   if (kind != kNoiseTable) {
     key.push_back(g.n_beams);
     key.push_back(g.y_sym);
@@ -522,6 +522,7 @@ pusch::ChestGeom chest_geom(const pusch_slot_desc* d) {
   for (int j = 0; j < P; ++j) cg.pilot_sym[j] = d->pilot_symb[j];
   cg.p_batch = (long long)P * K;
   cg.h_batch = (long long)K * L * B;
+  cg.comb_aligned = d->comb_aligned ? 1 : 0;
   return cg;
 }
 
@@ -576,7 +577,7 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   // anything is enqueued on s)
   const bool fused = slot_fused(d);
   const pusch::ChestGeom cg = chest_geom(d);
-  const int n_tap = pusch::comb_taps(L, P);
+  const int n_tap = pusch::comb_taps(L, P, d->comb_aligned != 0);
   const void* taps = nullptr;
   const void* ne_tab = nullptr;
   pusch::TimeTapGeom tt{};
@@ -683,7 +684,8 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
 bool cell_grouped(const pusch_slot_desc* d, long long n_slot, bool mixed) {
   if (n_slot < 1 || !slot_fused(d) || d->time_varying) return false;
   if (pusch::bf_cell_class(d->n_beams, d->n_ant) < 0) return false;
-  if (pusch::mmse_cell_class(d->n_beams, pusch::comb_taps(d->n_ue, d->n_pilot)) < 0) return false;
+  if (pusch::mmse_cell_class(d->n_beams, pusch::comb_taps(d->n_ue, d->n_pilot, d->comb_aligned != 0)) < 0)
+    return false;
   const long long KP = mixed ? (long long)xa_pitch_h16(d->n_sc) : (long long)xa_pitch(d->n_sc);
   // (the detection's workgroups, one per 4 subcarriers of a slot, are far fewer than the tiles)
   return KP * d->n_ant < (1ll << 28) && n_slot * d->n_symb * (((long long)d->n_sc + 15) / 16) < (1ll << 30);
@@ -729,7 +731,9 @@ int run_cells_grouped(DeviceTables* t, const pusch_slot_desc* d, const long long
     if (!W[c])
       if (int rc = dft_beamformer(t, d[c].n_beams, d[c].n_ant, &W[c])) return rc;
     const pusch::ChestGeom cg = chest_geom(&d[c]);
-    if (int rc = geometry_table(t, kCombTaps, cg, pusch::comb_taps(d[c].n_ue, d[c].n_pilot), &taps[c])) return rc;
+    if (int rc = geometry_table(t, kCombTaps, cg, pusch::comb_taps(d[c].n_ue, d[c].n_pilot, cg.comb_aligned != 0),
+                                &taps[c]))
+      return rc;
     if (d[c].noise_est)
       if (int rc = geometry_table(t, kNoiseTable, cg, 0, &ne_tab[c])) return rc;
   }
@@ -803,7 +807,10 @@ int run_cells_grouped(DeviceTables* t, const pusch_slot_desc* d, const long long
   return for_groups(
       idx,
       [&](int c) {
-        return plan.mmse_merged ? -1 : pusch::mmse_cell_class(d[c].n_beams, pusch::comb_taps(d[c].n_ue, d[c].n_pilot));
+        return plan.mmse_merged
+                   ? -1
+                   : pusch::mmse_cell_class(d[c].n_beams,
+                                            pusch::comb_taps(d[c].n_ue, d[c].n_pilot, d[c].comb_aligned != 0));
       },
       pusch::kMmseCellsPerLaunch, [&](int cls, const std::vector<int>& grp) {
         pusch::MmseCells mt{};
@@ -819,7 +826,7 @@ int run_cells_grouped(DeviceTables* t, const pusch_slot_desc* d, const long long
           e.batch = n_slot[c];
           e.g = mmse_geom(&d[c], s2[c]);
           e.cg = chest_geom(&d[c]);
-          e.n_tap = pusch::comb_taps(d[c].n_ue, d[c].n_pilot);
+          e.n_tap = pusch::comb_taps(d[c].n_ue, d[c].n_pilot, d[c].comb_aligned != 0);
         }
         return hip_status(pusch::launch_mmse_cells(mt, cls, s));
       });
@@ -834,7 +841,7 @@ std::vector<long long> cells_signature(const pusch_slot_desc* d, int n_cells, co
   std::vector<long long> key = {flags & (PUSCH_CELLS_MIXED | PUSCH_CELLS_STREAMS), n_cells};
   for (int c = 0; c < n_cells; ++c) {
     key.insert(key.end(), {d[c].n_ant, d[c].n_fft, d[c].n_sc, d[c].n_symb, d[c].n_beams, d[c].n_ue, d[c].n_pilot,
-                           n_slot[c], d[c].noise_est, d[c].refine, d[c].time_varying});
+                           n_slot[c], d[c].noise_est, d[c].refine, d[c].time_varying, d[c].comb_aligned});
     for (int j = 0; j < d[c].n_pilot; ++j) key.push_back(d[c].pilot_symb[j]);
   }
   return key;
@@ -1170,7 +1177,7 @@ DnSlotLayout dn_slot_layout(const pusch_slot_desc* d, long long n_slot) {
 
 int check_dn_slot_geom(const pusch_slot_desc* d) {
   if (int rc = check_geom(d)) return rc;
-  if (d->refine || d->time_varying || d->noise_est) return PUSCH_EUNSUPPORTED;
+  if (d->refine || d->time_varying || d->noise_est || d->comb_aligned) return PUSCH_EUNSUPPORTED;
   if (!(d->sigma2 > 0.f) || !std::isfinite(d->sigma2)) return PUSCH_EINVAL;  // the network's unit
   if (d->n_ant > 1024) return PUSCH_EUNSUPPORTED;
   return PUSCH_OK;

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_comb_taps(int2* __restrict__ tab, Chest
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= g.n_sc * g.n_ue) return;
   const int l = idx % g.n_ue, k = idx / g.n_ue;
-  const CombBracket c = comb_bracket(k, l, g.n_ue, g.n_pilot, g.n_sc);
+  const CombBracket c = comb_bracket(k, l, g.n_ue, g.n_pilot, g.n_sc, comb_step(g));
   // lo end: average over the pilot symbols in mlo, times (1 - w); hi end
   // likewise with w (absent when the estimate is held, lo == hi)
   const bool two = c.hi != c.lo;
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_time_taps(int2* __restrict__ tab, Chest
     ja = jb - 1;  // between ja and jb
     wb = (float)(s - psym(ja)) / (float)(psym(jb) - psym(ja));
   }
-  const int step = g.n_ue / g.n_pilot;
+  const int step = comb_step(g);
   const float inv = fast_rcp((float)g.n_ue);
   int2* dst = tab + (long long)idx * kTimeTaps;
   int n = 0;
@@ -120,11 +120,11 @@ hipError_t launch_time_taps(int2* tab, const ChestGeom& g, const TimeTapGeom& t,
   return hipGetLastError();
 }
 
-int comb_taps(int n_ue, int n_pilot) {
+int comb_taps(int n_ue, int n_pilot, bool aligned) {
   // pilot symbols j, j' put UE l's pilot on the same subcarriers when
-  // (j - j') * step = 0 mod n_ue, step = n_ue / n_pilot: then a bracket end
-  // averages several of them
-  const int step = n_ue / n_pilot;
+  // (j - j') * step = 0 mod n_ue (step = n_ue / n_pilot, or 0 when aligned):
+  // then a bracket end averages several of them
+  const int step = aligned ? 0 : n_ue / n_pilot;
   for (int j = 1; j < n_pilot; ++j)
     if ((j * step) % n_ue == 0) return 2 * kMaxPilots;
   return 2;

@@ -4,7 +4,8 @@
 // slot uses the same brackets.
 //
 // On pilot symbol j, subcarrier k carries UE (k + j*step) mod n_ue's pilot,
-// step = n_ue / n_pilot, so UE l's pilot subcarriers on symbol j are the
+// step = comb_step(g) (n_ue / n_pilot, or 0 for the aligned comb), so UE l's
+// pilot subcarriers on symbol j are the
 // residue class r_j = (l - j*step) mod n_ue.  The nearest pilot positions
 // around k follow in closed form, together with the set of pilot symbols
 // that put UE l's pilot there.  The LS value at a position is
@@ -34,8 +35,7 @@ struct CombBracket {
   float w;             // interpolation weight of hi: (k - lo) / (hi - lo), 0 when lo == hi
 };
 
-__device__ __forceinline__ CombBracket comb_bracket(int k, int l, int nue, int npil, int nsc) {
-  const int step = nue / npil;
+__device__ __forceinline__ CombBracket comb_bracket(int k, int l, int nue, int npil, int nsc, int step) {
   const float inv = fast_rcp((float)nue);
   int lo = -1, hi = 0x7fffffff;
   unsigned mlo = 0, mhi = 0;
@@ -127,7 +127,7 @@ __device__ __forceinline__ void lerp(cf (&lo)[NBV], const cf (&hi)[NBV], float w
 template <int NBV>
 __device__ __forceinline__ void ls_estimate(cf (&out)[NBV], const cf* __restrict__ Y, const ChestGeom& g,
                                             const cf* __restrict__ P, int k, int l, int b0) {
-  const CombBracket c = comb_bracket(k, l, g.n_ue, g.n_pilot, g.n_sc);
+  const CombBracket c = comb_bracket(k, l, g.n_ue, g.n_pilot, g.n_sc, comb_step(g));
   ls_at<NBV>(out, Y, g, P, c.mlo, c.lo, b0);
   if (c.hi != c.lo) {
     cf vhi[NBV];

@@ -168,7 +168,11 @@ struct ChestGeom {
   long long h_batch;              // H elements between batch items ([n_sc][n_ue][n_beams] each)
   int pilot_sym[kMaxPilots];      // grid index of pilot symbol j (grid at pilot_sym[j] * y_sym)
   int n_beams, n_ue, n_sc, n_pilot;
+  int comb_aligned;               // nonzero: the comb without stagger (comb_step 0)
 };
+// Pilot comb: on pilot symbol j, subcarrier k carries UE (k + j * step) mod
+// n_ue's pilot, step = n_ue / n_pilot (staggered) or 0 (aligned).
+__host__ __device__ inline int comb_step(const ChestGeom& g) { return g.comb_aligned ? 0 : g.n_ue / g.n_pilot; }
 hipError_t launch_chest(const cf* Y, const cf* pilots, cf* H, const ChestGeom& g, long long batch, hipStream_t s);
 // Channel interpolation of the fused detection as taps: the estimate of UE l
 // at subcarrier k, beam b, is sum_t w_t * LS[off_t + b] over the n_tap taps
@@ -177,7 +181,7 @@ hipError_t launch_chest(const cf* Y, const cf* pilots, cf* H, const ChestGeom& g
 // plus position * n_beams).  tab[(k * n_ue + l) * n_tap + t] = {off_t, bits
 // of w_t}; unused taps repeat the first offset with weight 0.  Depends on the
 // geometry only (n_sc, n_ue, n_pilot, n_beams, the pilot grid offsets).
-int comb_taps(int n_ue, int n_pilot);  // taps per (k, l) the geometry needs: 2 or 8
+int comb_taps(int n_ue, int n_pilot, bool aligned = false);  // taps per (k, l) the geometry needs: 2 or 8
 hipError_t launch_comb_taps(int2* tab, const ChestGeom& g, int n_tap, hipStream_t s);
 // Time-varying channel: 4 taps per (data symbol, k, l) (two frequency
 // neighbours on each of two pilot symbols; unused taps weight 0),

@@ -11,6 +11,10 @@
 //   kappa = 1 + |p|^2 sum_i (w_i / c_i)^2 sum_{s at i} 1 / |p_s|^2,
 // and the estimate is sum |r|^2 / (N_B sum kappa) over the pilot REs of a
 // batch item.  Since y = p * LS(y), |r|^2 = |p|^2 |LS(y) - h|^2.
+// Where c >= 2 pilot symbols carry UE l's pilot at k itself, the prediction
+// is the mean of those c LS values at k (the same channel in every term, so
+// the residual holds noise only, however selective the channel is); the RE's
+// own noise is 1/c of that mean, so kappa = 1 - 2/c + |p|^2 / c^2 sum_s 1/|p_s|^2.
 //
 // k_noise_table finds every pilot RE's neighbours and weights (they depend
 // on the geometry only: closed form per pilot symbol, the comb of residue
@@ -44,8 +48,7 @@ struct NeNeighbours {
   float wlo, whi;      // prediction weights
 };
 
-__device__ __forceinline__ NeNeighbours ne_neighbours(int k, int l, int nue, int npil, int nsc) {
-  const int step = nue / npil;
+__device__ __forceinline__ NeNeighbours ne_neighbours(int k, int l, int nue, int npil, int nsc, int step) {
   NeNeighbours n;
   n.lo = -1;
   n.hi = nsc;
@@ -130,14 +133,23 @@ __device__ __forceinline__ float2 wave_sum(float2 v) {
 }
 
 // One table entry per pilot RE s = k * n_pilot + j: {lo | hi << 12 | mlo << 24 |
-// mhi << 28, bits of wlo, bits of whi, k | j << 16}; a mask of 0 marks a
-// missing side (positions < 4096).
+// mhi << 28, bits of wlo, bits of whi, k | j << 16 | self << 20}; a mask of 0
+// marks a missing side (positions < 4096); self: the prediction is the mean
+// at k itself (lo = k, mlo its pilot symbols, wlo = 1, no hi side).
 __global__ __launch_bounds__(256) void k_noise_table(int4* __restrict__ tab, ChestGeom g) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.n_pilot * g.n_sc) return;
   const int k = s / g.n_pilot, j = s - k * g.n_pilot;
-  const int l = pos_mod(k + j * (g.n_ue / g.n_pilot), g.n_ue);
-  const NeNeighbours n = ne_neighbours(k, l, g.n_ue, g.n_pilot, g.n_sc);
+  const int step = comb_step(g);
+  const int l = pos_mod(k + j * step, g.n_ue);
+  unsigned here = 0;  // pilot symbols that put UE l's pilot at k
+  for (int jj = 0; jj < g.n_pilot; ++jj)
+    if (pos_mod(k + jj * step, g.n_ue) == l) here |= 1u << jj;
+  if (__popc(here) >= 2) {
+    tab[s] = make_int4(k | (int)(here << 24), __float_as_int(1.f), __float_as_int(0.f), k | j << 16 | 1 << 20);
+    return;
+  }
+  const NeNeighbours n = ne_neighbours(k, l, g.n_ue, g.n_pilot, g.n_sc, step);
   const int lo = n.mlo ? n.lo : 0, hi = n.mhi ? n.hi : 0;
   tab[s] = make_int4(lo | hi << 12 | (int)(n.mlo << 24) | (int)(n.mhi << 28), __float_as_int(n.wlo),
                      __float_as_int(n.whi), k | j << 16);
@@ -170,11 +182,13 @@ __global__ __launch_bounds__(kNeThreads) void k_noise_partial(const cf* __restri
     const int4 t = tab[s];
     const unsigned mlo = ((unsigned)t.x >> 24) & 15u, mhi = (unsigned)t.x >> 28;
     const int lo = t.x & 4095, hi = (t.x >> 12) & 4095;
-    const int k = t.w & 0xffff, j = t.w >> 16;
+    const int k = t.w & 0xffff, j = (t.w >> 16) & 15;
+    const bool self = (t.w >> 20) & 1;
     float hr[NBV], hi_[NBV];
 #pragma unroll
     for (int e = 0; e < NBV; ++e) hr[e] = hi_[e] = 0.f;
-    float gain = 0.f;
+    float gain = 0.f, base = 1.f;  // kappa = base + |p|^2 gain
+    if (self) base = 1.f - 2.f / (float)__popc(mlo);
     if (mlo) {
       const float wlo = __int_as_float(t.y);
       const float q = add_mean<NBV, LS>(hr, hi_, Yb, Pb, g, mlo, lo, wlo, bb);
@@ -198,7 +212,7 @@ __global__ __launch_bounds__(kNeThreads) void k_noise_partial(const cf* __restri
       e2 += dr * dr + di * di;
     }
     num += mine ? pp * e2 : 0.f;
-    den += gl == 0 ? (float)nb * (1.f + pp * gain) : 0.f;
+    den += gl == 0 ? (float)nb * (base + pp * gain) : 0.f;
   }
   float2 v = wave_sum(make_float2(num, den));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;

@@ -48,6 +48,7 @@ class SlotDesc(ctypes.Structure):
         ("sigma2_est", ctypes.c_void_p),
         ("refine", ctypes.c_int),
         ("time_varying", ctypes.c_int),
+        ("comb_aligned", ctypes.c_int),
     ]
 
 
@@ -312,11 +313,14 @@ class Slot:
     estimates in self.sigma2_est ([n_slot] float32).  refine=True adds one
     iterative-refinement step to the MIMO solve.  time_varying=True gives
     every data symbol its own channel estimate (interpolated in time between
-    the pilot symbols) and its own factorisation."""
+    the pilot symbols) and its own factorisation.  comb_aligned=True: the
+    pilot comb without stagger (each UE on the same subcarriers in every pilot
+    symbol)."""
 
     def __init__(self, n_ant: int, n_fft: int, n_sc: int, n_symb: int, n_beams: int, n_ue: int, pilot_symb,
                  sigma2: float | None, n_slot: int, W: torch.Tensor | None = None, device="cuda",
-                 precision: str = "fp32", refine: bool = False, time_varying: bool = False):
+                 precision: str = "fp32", refine: bool = False, time_varying: bool = False,
+                 comb_aligned: bool = False):
         if precision not in ("fp32", "mixed"):
             raise PuschError("precision is 'fp32' or 'mixed'")
         self.mixed = precision == "mixed"
@@ -332,6 +336,7 @@ class Slot:
         self.sigma2_est = _noise_fields(d, sigma2, n_slot, device)
         d.refine = 1 if refine else 0
         d.time_varying = 1 if time_varying else 0
+        d.comb_aligned = 1 if comb_aligned else 0
         self.W = None if W is None else _beamformer(W, n_beams, n_ant, "W")
         d.W = _ptr(self.W)
         self.n_slot = n_slot
@@ -393,8 +398,8 @@ class Cells:
 
     Each cell is a dict with the slot geometry (n_ant, n_fft, n_sc, n_symb,
     n_beams, n_ue, pilot_symb), sigma2 (None: estimated per slot, left in
-    self.sigma2_est[c]), n_slot (>= 1) and optionally W, refine and
-    time_varying.  The workspace is allocated once here.  A call runs the
+    self.sigma2_est[c]), n_slot (>= 1) and optionally W, refine,
+    time_varying and comb_aligned.  The workspace is allocated once here.  A call runs the
     cells the grouped kernels take as one launch per stage and kernel shape on
     the current torch stream, and the others on the library's side streams,
     forked from and joined back to that stream, so it can be captured into a
@@ -431,6 +436,7 @@ class Cells:
                            g["pilot_symb"], g["sigma2"], W, int(g["n_slot"]), device))
             self.descs[c].refine = 1 if g.get("refine") else 0
             self.descs[c].time_varying = 1 if g.get("time_varying") else 0
+            self.descs[c].comb_aligned = 1 if g.get("comb_aligned") else 0
             self.n_slot[c] = int(g["n_slot"])
             self.geom.append(dict(g))
         nbytes = lib().pusch_cells_workspace_bytes(self.descs, n, self.n_slot, self.flags)
