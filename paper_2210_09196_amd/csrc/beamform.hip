@@ -533,16 +533,20 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_h16(const cf* __restri
                                                               cf* __restrict__ Y, int nb, int na, int nre,
                                                               long long ldx, long long sx, long long sy, int ntiles,
                                                               int ntn, PilotScale ps) {
-  bf_h16_body<MT, J>(blockIdx.x, gridDim.x, W, Xh, ex, Y, nb, na, nre, ldx, sx, sy, ntiles, ntn, ps);
+  // neighbouring workgroups take neighbouring 16-RE tiles, whose 64-byte row
+  // segments share 128-byte lines: keep them on one XCD's L2
+  bf_h16_body<MT, J>(xcd_block(blockIdx.x, gridDim.x), gridDim.x, W, Xh, ex, Y, nb, na, nre, ldx, sx, sy, ntiles,
+                     ntn, ps);
 }
 
 template <int MT, int J>
 __global__ __launch_bounds__(64 * kWaves) void k_beamform_h16_cells(BfCells t) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);  // as k_beamform_h16
   int c = 0;
-  while (c + 1 < t.n && (int)blockIdx.x >= t.start[c + 1]) ++c;
+  while (c + 1 < t.n && blk >= t.start[c + 1]) ++c;
   const BfCell& e = t.cell[c];
-  bf_h16_body<MT, J>(blockIdx.x - t.start[c], t.start[c + 1] - t.start[c], e.W, e.Xh, e.ex, e.Y, e.nb, e.na, e.nre,
-                     e.ldx, e.sx, e.sy, e.ntiles, e.ntn, e.ps);
+  bf_h16_body<MT, J>(blk - t.start[c], t.start[c + 1] - t.start[c], e.W, e.Xh, e.ex, e.Y, e.nb, e.na, e.nre, e.ldx,
+                     e.sx, e.sy, e.ntiles, e.ntn, e.ps);
 }
 
 template <int MT, int J>
@@ -620,10 +624,11 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_k_any(BfCells t) {
 }
 
 __global__ __launch_bounds__(64 * kWaves) void k_beamform_h16_any(BfCells t) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);  // as k_beamform_h16
   int c = 0;
-  while (c + 1 < t.n && (int)blockIdx.x >= t.start[c + 1]) ++c;
+  while (c + 1 < t.n && blk >= t.start[c + 1]) ++c;
   const BfCell& e = t.cell[c];
-  const int vb = blockIdx.x - t.start[c], vg = t.start[c + 1] - t.start[c];
+  const int vb = blk - t.start[c], vg = t.start[c + 1] - t.start[c];
 #define BF_H_CASE(CLS, MT, J)                                                                                     \
   case CLS:                                                                                                      \
     bf_h16_body<MT, J>(vb, vg, e.W, e.Xh, e.ex, e.Y, e.nb, e.na, e.nre, e.ldx, e.sx, e.sy, e.ntiles, e.ntn, e.ps); \
