@@ -591,15 +591,161 @@ struct MfmaLds {
   float Dinv[kSPW * kDinv];
 };
 
+// Phases B and C of one block (G and P of its kSPW subcarriers in LDS):
+// Crout factorisation, then the substitutions and the stores of x_hat and
+// the status flags.
+__device__ __forceinline__ void mmse_factor_solve(MfmaLds& lds, const int bi, const int k0, cf* __restrict__ Xh,
+                                                  int* __restrict__ st, const MmseGeom& g) {
+  cf* __restrict__ Gs = lds.G;
+  cf* __restrict__ Ps = lds.P;
+  float* __restrict__ Dinv = lds.Dinv;
+  const int lane = threadIdx.x;
+  const int c16 = lane & 15, q = lane >> 4;
+  const int nue = g.n_ue, nsc = g.n_sc, nd = g.n_data;
+  {
+    // ---- phase B: Crout factorisation, lane (q, c16) holds row c16 of
+    // subcarrier q; the 16 lanes of a subcarrier are one DPP row, so row j of
+    // L reaches every lane by a row broadcast
+    const int grp = q, i = c16;
+    cf* Gm = Gs + grp * kTri;
+    cf* Grow = Gm + tri(i);
+    // regularise the own diagonal entry (padding rows beyond n_ue get 1 so
+    // their part of L is the identity; so do the rows of a subcarrier past n_sc)
+    const float s2 = g.sigma2_item ? g.sigma2_item[bi] : g.sigma2;
+    Grow[i].r += (i < nue && k0 + grp < nsc) ? s2 : 1.0f;
+    cf L[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) L[j] = j <= i ? Grow[j] : cf{0.f, 0.f};
+    // Only the strictly lower triangle of L and the reciprocals of its
+    // diagonal are used later, so every lane keeps t / L_jj in column j
+    // (entries at or above the diagonal are never read) and every lane of
+    // the group stores the same 1 / L_jj: no per-lane selects.
+    int fail = 0;
+    float* dinv = Dinv + grp * kDinv;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      // padded rows / columns beyond n_ue stay the identity: G is zero off
+      // the diagonal there (zero rows of H) and 1 on it, so is L, and the
+      // substitutions never read that part (a uniform branch)
+      if (j < nue) {
+        // sum_m L_im conj(L_jm) as positive multiply-adds of broadcast values
+        // (each one can take the broadcast as its DPP operand), then t
+        float sr = 0.f, sp = 0.f, sm = 0.f;
+#pragma unroll
+        for (int m = 0; m < j; ++m) {
+          const cf c = row_bcast_c(L[m], j);
+          const float cr = c.r, ci = c.i;
+          sr = __builtin_fmaf(cr, L[m].r, sr);
+          sr = __builtin_fmaf(ci, L[m].i, sr);
+          sp = __builtin_fmaf(cr, L[m].i, sp);
+          sm = __builtin_fmaf(ci, L[m].r, sm);
+        }
+        const cf t = cf{L[j].r - sr, L[j].i - (sp - sm)};
+        const float dpiv = row_bcast(t.r, j);
+        fail |= (dpiv > 0.f && dpiv <= 3.402823466e38f) ? 0 : 1;
+        const float inv = rsqrtf(dpiv);  // 1 / L_jj
+        L[j] = cf{t.r * inv, t.i * inv};
+        dinv[j] = inv;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (j <= i) Grow[j] = L[j];
+    __syncthreads();
+
+    // ---- phase C: forward and back substitution, lane (q, c16) solves data symbol c16
+    const int d = c16;
+    const float* dv = Dinv + grp * kDinv;
+    cf z[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) z[r] = Ps[grp * kMat + r * kRow + d];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {  // L z = b, row by row
+      if (r >= nue) continue;
+#pragma unroll
+      for (int m = 0; m < r; ++m) csub_mul(z[r], Gm[tri(r) + m], z[m]);
+      const float s = dv[r];
+      z[r] = cf{z[r].r * s, z[r].i * s};
+    }
+#pragma unroll
+    for (int m = 15; m >= 0; --m) {  // L^H x = z, column by column: x_m is final, remove it from rows r < m
+      if (m >= nue) continue;
+      const float s = dv[m];
+      z[m] = cf{z[m].r * s, z[m].i * s};
+#pragma unroll
+      for (int r = 0; r < m; ++r) csub_conj_mul(z[r], Gm[tri(m) + r], z[m]);  // z_r -= conj(L_mr) x_m
+    }
+    const int k = k0 + grp;
+    if (nue == 16 && k0 + kSPW <= nsc) {
+      // x_hat[d][k0 .. k0+3][0..15] is one contiguous 512-byte run per data
+      // symbol: stage the solutions in LDS (P is consumed) and write each run
+      // with 16-byte stores, consecutive lanes on consecutive bytes.
+      cf* Xs = Ps;  // [grp][d] rows of 16 (swizzled pairs)
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 16; r += 2)
+        *reinterpret_cast<float4*>(Xs + (grp * 16 + d) * 16 + 2 * ((r >> 1) ^ (d & 7))) =
+            fail ? float4{0.f, 0.f, 0.f, 0.f} : float4{z[r].r, z[r].i, z[r + 1].r, z[r + 1].i};
+      __syncthreads();
+      cf* xb = Xh + bi * g.x_batch + (long long)k0 * 16;
+#pragma unroll
+      for (int it = 0; it < 16 * kSPW * 16 / 2 / 64; ++it) {
+        const int c = it * 64 + lane;  // 16-byte chunk: data symbol, subcarrier, UE pair
+        const int dd = c >> 5, gg = (c >> 3) & 3, rp = c & 7;
+        if (dd < nd)
+          *reinterpret_cast<float4*>(xb + (long long)dd * nsc * 16 + gg * 16 + 2 * rp) =
+              *reinterpret_cast<const float4*>(Xs + (gg * 16 + dd) * 16 + 2 * (rp ^ (dd & 7)));
+      }
+    } else if (k < nsc && d < nd) {
+      cf* dst = Xh + bi * g.x_batch + ((long long)d * nsc + k) * nue;
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if (r < nue) dst[r] = fail ? cf{0.f, 0.f} : z[r];
+    }
+    if (k < nsc && d == 0 && st) {
+      int* sp = st + bi * g.st_batch + k;
+      *sp = g.st_or ? (*sp | fail) : fail;
+    }
+  }
+}
+
+// Phase A accumulators of one subcarrier: the Gram matrix and the matched
+// filter, each as three real products (Gauss/Karatsuba): with T1 = ar br,
+// T2 = ai bi, T3 = (ar - ai)(br + bi), conj(a) b = (T1 + T2) + i (T3 - T1 + T2).
+struct GpAcc {
+  f32x4 g1, g2, g3, p1, p2, p3;
+};
+
+// One K-step (4 beams): 6 MFMAs.  The lane's fragment of H is both the A row
+// (UE c16) and the B column (UE c16) of the Gram product.
+__device__ __forceinline__ void gp_kstep(GpAcc& c, cf h, cf y) {
+  const float hm = h.r - h.i, hp = h.r + h.i, ys = y.r + y.i;
+  c.g1 = mfma(h.r, h.r, c.g1);
+  c.g2 = mfma(h.i, h.i, c.g2);
+  c.g3 = mfma(hm, hp, c.g3);
+  c.p1 = mfma(h.r, y.r, c.p1);
+  c.p2 = mfma(h.i, y.i, c.p2);
+  c.p3 = mfma(hm, ys, c.p3);
+}
+
+// Subcarrier sc's G (lower triangle) and P to LDS: the lane holds rows
+// 4q..4q+3 of column c16.
+__device__ __forceinline__ void gp_store(MfmaLds& lds, int sc, const GpAcc& c, int q, int c16) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 4 * q + v;
+    const float g12 = c.g1[v] + c.g2[v], p12 = c.p1[v] + c.p2[v];
+    if (i >= c16) lds.G[sc * kTri + tri(i) + c16] = cf{g12, c.g3[v] - c.g1[v] + c.g2[v]};
+    lds.P[sc * kMat + i * kRow + c16] = cf{p12, c.p3[v] - c.p1[v] + c.p2[v]};
+  }
+}
+
 // blk: the workgroup's logical block (kSPW subcarriers of one batch item).
 template <int KS, bool FUSED, int NT>
 __device__ __forceinline__ void mmse_mfma_body(MfmaLds& lds, const int blk, const cf* __restrict__ H,
                                                const cf* __restrict__ Y, const int2* __restrict__ taps,
                                                cf* __restrict__ Xh, int* __restrict__ st, const MmseGeom& g,
                                                const ChestGeom& cg, int nblk_batch) {
-  cf* __restrict__ Gs = lds.G;
-  cf* __restrict__ Ps = lds.P;
-  float* __restrict__ Dinv = lds.Dinv;
   const int lane = threadIdx.x;
   const int c16 = lane & 15, q = lane >> 4;
   const int nb = g.n_beams, nue = g.n_ue, nsc = g.n_sc, nd = g.n_data;
@@ -619,28 +765,9 @@ __device__ __forceinline__ void mmse_mfma_body(MfmaLds& lds, const int blk, cons
     // (Gauss/Karatsuba): with T1 = ar br, T2 = ai bi, T3 = (ar - ai)(br + bi),
     // conj(a) b = (T1 + T2) + i (T3 - T1 + T2).  The lane's fragment of H is
     // both the A row (UE c16) and the B column (UE c16) of the Gram product.
-    struct Acc {
-      f32x4 g1, g2, g3, p1, p2, p3;
-    };
-    auto kstep = [](Acc& c, cf h, cf y) {
-      const float hm = h.r - h.i, hp = h.r + h.i, ys = y.r + y.i;
-      c.g1 = mfma(h.r, h.r, c.g1);
-      c.g2 = mfma(h.i, h.i, c.g2);
-      c.g3 = mfma(hm, hp, c.g3);
-      c.p1 = mfma(h.r, y.r, c.p1);
-      c.p2 = mfma(h.i, y.i, c.p2);
-      c.p3 = mfma(hm, ys, c.p3);
-    };
-    // lane holds rows 4q..4q+3 of column c16 (G: lower triangle only)
-    auto store_gp = [&](int sc, const Acc& c) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 4 * q + v;
-        const float g12 = c.g1[v] + c.g2[v], p12 = c.p1[v] + c.p2[v];
-        if (i >= c16) Gs[sc * kTri + tri(i) + c16] = cf{g12, c.g3[v] - c.g1[v] + c.g2[v]};
-        Ps[sc * kMat + i * kRow + c16] = cf{p12, c.p3[v] - c.p1[v] + c.p2[v]};
-      }
-    };
+    using Acc = GpAcc;
+    auto kstep = [](Acc& c, cf h, cf y) { gp_kstep(c, h, y); };
+    auto store_gp = [&](int sc, const Acc& c) { gp_store(lds, sc, c, q, c16); };
     const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
     // Two taps and up to 8 K-steps (the common fused case): all kSPW
     // subcarriers unrolled, the loads of subcarrier sc + 1 in flight during
@@ -768,110 +895,7 @@ __device__ __forceinline__ void mmse_mfma_body(MfmaLds& lds, const int blk, cons
       store_gp(sc, ac);
     }
     __syncthreads();
-
-    // ---- phase B: Crout factorisation, lane (q, c16) holds row c16 of
-    // subcarrier q; the 16 lanes of a subcarrier are one DPP row, so row j of
-    // L reaches every lane by a row broadcast
-    const int grp = q, i = c16;
-    cf* Gm = Gs + grp * kTri;
-    cf* Grow = Gm + tri(i);
-    // regularise the own diagonal entry (padding rows beyond n_ue get 1 so
-    // their part of L is the identity; so do the rows of a subcarrier past n_sc)
-    const float s2 = g.sigma2_item ? g.sigma2_item[bi] : g.sigma2;
-    Grow[i].r += (i < nue && k0 + grp < nsc) ? s2 : 1.0f;
-    cf L[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) L[j] = j <= i ? Grow[j] : cf{0.f, 0.f};
-    // Only the strictly lower triangle of L and the reciprocals of its
-    // diagonal are used later, so every lane keeps t / L_jj in column j
-    // (entries at or above the diagonal are never read) and every lane of
-    // the group stores the same 1 / L_jj: no per-lane selects.
-    int fail = 0;
-    float* dinv = Dinv + grp * kDinv;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      // padded rows / columns beyond n_ue stay the identity: G is zero off
-      // the diagonal there (zero rows of H) and 1 on it, so is L, and the
-      // substitutions never read that part (a uniform branch)
-      if (j < nue) {
-        // sum_m L_im conj(L_jm) as positive multiply-adds of broadcast values
-        // (each one can take the broadcast as its DPP operand), then t
-        float sr = 0.f, sp = 0.f, sm = 0.f;
-#pragma unroll
-        for (int m = 0; m < j; ++m) {
-          const cf c = row_bcast_c(L[m], j);
-          const float cr = c.r, ci = c.i;
-          sr = __builtin_fmaf(cr, L[m].r, sr);
-          sr = __builtin_fmaf(ci, L[m].i, sr);
-          sp = __builtin_fmaf(cr, L[m].i, sp);
-          sm = __builtin_fmaf(ci, L[m].r, sm);
-        }
-        const cf t = cf{L[j].r - sr, L[j].i - (sp - sm)};
-        const float dpiv = row_bcast(t.r, j);
-        fail |= (dpiv > 0.f && dpiv <= 3.402823466e38f) ? 0 : 1;
-        const float inv = rsqrtf(dpiv);  // 1 / L_jj
-        L[j] = cf{t.r * inv, t.i * inv};
-        dinv[j] = inv;
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 16; ++j)
-      if (j <= i) Grow[j] = L[j];
-    __syncthreads();
-
-    // ---- phase C: forward and back substitution, lane (q, c16) solves data symbol c16
-    const int d = c16;
-    const float* dv = Dinv + grp * kDinv;
-    cf z[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) z[r] = Ps[grp * kMat + r * kRow + d];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {  // L z = b, row by row
-      if (r >= nue) continue;
-#pragma unroll
-      for (int m = 0; m < r; ++m) csub_mul(z[r], Gm[tri(r) + m], z[m]);
-      const float s = dv[r];
-      z[r] = cf{z[r].r * s, z[r].i * s};
-    }
-#pragma unroll
-    for (int m = 15; m >= 0; --m) {  // L^H x = z, column by column: x_m is final, remove it from rows r < m
-      if (m >= nue) continue;
-      const float s = dv[m];
-      z[m] = cf{z[m].r * s, z[m].i * s};
-#pragma unroll
-      for (int r = 0; r < m; ++r) csub_conj_mul(z[r], Gm[tri(m) + r], z[m]);  // z_r -= conj(L_mr) x_m
-    }
-    const int k = k0 + grp;
-    if (nue == 16 && k0 + kSPW <= nsc) {
-      // x_hat[d][k0 .. k0+3][0..15] is one contiguous 512-byte run per data
-      // symbol: stage the solutions in LDS (P is consumed) and write each run
-      // with 16-byte stores, consecutive lanes on consecutive bytes.
-      cf* Xs = Ps;  // [grp][d] rows of 16 (swizzled pairs)
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < 16; r += 2)
-        *reinterpret_cast<float4*>(Xs + (grp * 16 + d) * 16 + 2 * ((r >> 1) ^ (d & 7))) =
-            fail ? float4{0.f, 0.f, 0.f, 0.f} : float4{z[r].r, z[r].i, z[r + 1].r, z[r + 1].i};
-      __syncthreads();
-      cf* xb = Xh + bi * g.x_batch + (long long)k0 * 16;
-#pragma unroll
-      for (int it = 0; it < 16 * kSPW * 16 / 2 / 64; ++it) {
-        const int c = it * 64 + lane;  // 16-byte chunk: data symbol, subcarrier, UE pair
-        const int dd = c >> 5, gg = (c >> 3) & 3, rp = c & 7;
-        if (dd < nd)
-          *reinterpret_cast<float4*>(xb + (long long)dd * nsc * 16 + gg * 16 + 2 * rp) =
-              *reinterpret_cast<const float4*>(Xs + (gg * 16 + dd) * 16 + 2 * (rp ^ (dd & 7)));
-      }
-    } else if (k < nsc && d < nd) {
-      cf* dst = Xh + bi * g.x_batch + ((long long)d * nsc + k) * nue;
-#pragma unroll
-      for (int r = 0; r < 16; ++r)
-        if (r < nue) dst[r] = fail ? cf{0.f, 0.f} : z[r];
-    }
-    if (k < nsc && d == 0 && st) {
-      int* sp = st + bi * g.st_batch + k;
-      *sp = g.st_or ? (*sp | fail) : fail;
-    }
+    mmse_factor_solve(lds, bi, k0, Xh, st, g);
   }
 }
 
