@@ -49,13 +49,19 @@ constexpr int kProbes = 4;  // probe vectors of the condition estimate
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kSPW = 4;              // subcarriers per wavefront pass
-constexpr int kRow = 17;             // padded LDS row of a 16x16 matrix (cf)
-constexpr int kMat = 16 * kRow + 1;  // padded matrix stride: the 4 groups' broadcasts hit distinct banks
+// P of one subcarrier in LDS: 16 UE rows of NDP data symbols (NDP = 12 or
+// 16, the call's count rounded up), padded to an odd row length so the 4
+// groups' broadcasts hit distinct banks.
+template <int NDP>
+constexpr int kRowP = NDP + 1;
+template <int NDP>
+constexpr int kMatP = 16 * kRowP<NDP> + 1;
 constexpr int kTri = 16 * 17 / 2 + 1;  // packed lower triangle (row i at i(i+1)/2), odd stride
 constexpr int kDinv = 17;
 // staged solutions: rows of 16 cf, pair p of row (grp, d) at pair p ^ (d & 7)
 // (spreads the 16-byte accesses of one instruction over the banks)
-static_assert(kSPW * 16 * 16 <= kSPW * kMat, "solution staging must fit in the P buffer");
+static_assert(kSPW * 12 * 16 <= kSPW * kMatP<12> && kSPW * 16 * 16 <= kSPW * kMatP<16>,
+              "solution staging must fit in the P buffer");
 
 __device__ __forceinline__ int tri(int i) { return (i * (i + 1)) >> 1; }
 
@@ -585,16 +591,18 @@ namespace {
 // LDS of a workgroup: the lower triangles of G (then of L in place), the
 // matched filters P[i][d] = (H^H y_d)_i (then the staged solutions; 16-byte
 // aligned) and the reciprocal diagonals of L.
+template <int NDP>
 struct MfmaLds {
   cf G[kSPW * kTri];
-  cf P[kSPW * kMat];
+  cf P[kSPW * kMatP<NDP>];
   float Dinv[kSPW * kDinv];
 };
 
 // Phases B and C of one block (G and P of its kSPW subcarriers in LDS):
 // Crout factorisation, then the substitutions and the stores of x_hat and
 // the status flags.
-__device__ __forceinline__ void mmse_factor_solve(MfmaLds& lds, const int bi, const int k0, cf* __restrict__ Xh,
+template <int NDP>
+__device__ __forceinline__ void mmse_factor_solve(MfmaLds<NDP>& lds, const int bi, const int k0, cf* __restrict__ Xh,
                                                   int* __restrict__ st, const MmseGeom& g) {
   cf* __restrict__ Gs = lds.G;
   cf* __restrict__ Ps = lds.P;
@@ -658,7 +666,7 @@ __device__ __forceinline__ void mmse_factor_solve(MfmaLds& lds, const int bi, co
     const float* dv = Dinv + grp * kDinv;
     cf z[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) z[r] = Ps[grp * kMat + r * kRow + d];
+    for (int r = 0; r < 16; ++r) z[r] = Ps[grp * kMatP<NDP> + r * kRowP<NDP> + (d < NDP ? d : NDP - 1)];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {  // L z = b, row by row
       if (r >= nue) continue;
@@ -684,17 +692,18 @@ __device__ __forceinline__ void mmse_factor_solve(MfmaLds& lds, const int bi, co
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < 16; r += 2)
-        *reinterpret_cast<float4*>(Xs + (grp * 16 + d) * 16 + 2 * ((r >> 1) ^ (d & 7))) =
-            fail ? float4{0.f, 0.f, 0.f, 0.f} : float4{z[r].r, z[r].i, z[r + 1].r, z[r + 1].i};
+        if (d < NDP)
+          *reinterpret_cast<float4*>(Xs + (grp * NDP + d) * 16 + 2 * ((r >> 1) ^ (d & 7))) =
+              fail ? float4{0.f, 0.f, 0.f, 0.f} : float4{z[r].r, z[r].i, z[r + 1].r, z[r + 1].i};
       __syncthreads();
       cf* xb = Xh + bi * g.x_batch + (long long)k0 * 16;
 #pragma unroll
-      for (int it = 0; it < 16 * kSPW * 16 / 2 / 64; ++it) {
+      for (int it = 0; it < NDP * kSPW * 16 / 2 / 64; ++it) {
         const int c = it * 64 + lane;  // 16-byte chunk: data symbol, subcarrier, UE pair
         const int dd = c >> 5, gg = (c >> 3) & 3, rp = c & 7;
         if (dd < nd)
           *reinterpret_cast<float4*>(xb + (long long)dd * nsc * 16 + gg * 16 + 2 * rp) =
-              *reinterpret_cast<const float4*>(Xs + (gg * 16 + dd) * 16 + 2 * (rp ^ (dd & 7)));
+              *reinterpret_cast<const float4*>(Xs + (gg * NDP + dd) * 16 + 2 * (rp ^ (dd & 7)));
       }
     } else if (k < nsc && d < nd) {
       cf* dst = Xh + bi * g.x_batch + ((long long)d * nsc + k) * nue;
@@ -730,19 +739,20 @@ __device__ __forceinline__ void gp_kstep(GpAcc& c, cf h, cf y) {
 
 // Subcarrier sc's G (lower triangle) and P to LDS: the lane holds rows
 // 4q..4q+3 of column c16.
-__device__ __forceinline__ void gp_store(MfmaLds& lds, int sc, const GpAcc& c, int q, int c16) {
+template <int NDP>
+__device__ __forceinline__ void gp_store(MfmaLds<NDP>& lds, int sc, const GpAcc& c, int q, int c16) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int i = 4 * q + v;
     const float g12 = c.g1[v] + c.g2[v], p12 = c.p1[v] + c.p2[v];
     if (i >= c16) lds.G[sc * kTri + tri(i) + c16] = cf{g12, c.g3[v] - c.g1[v] + c.g2[v]};
-    lds.P[sc * kMat + i * kRow + c16] = cf{p12, c.p3[v] - c.p1[v] + c.p2[v]};
+    if (c16 < kRowP<NDP>) lds.P[sc * kMatP<NDP> + i * kRowP<NDP> + c16] = cf{p12, c.p3[v] - c.p1[v] + c.p2[v]};
   }
 }
 
 // blk: the workgroup's logical block (kSPW subcarriers of one batch item).
-template <int KS, bool FUSED, int NT>
-__device__ __forceinline__ void mmse_mfma_body(MfmaLds& lds, const int blk, const cf* __restrict__ H,
+template <int KS, bool FUSED, int NT, int NDP>
+__device__ __forceinline__ void mmse_mfma_body(MfmaLds<NDP>& lds, const int blk, const cf* __restrict__ H,
                                                const cf* __restrict__ Y, const int2* __restrict__ taps,
                                                cf* __restrict__ Xh, int* __restrict__ st, const MmseGeom& g,
                                                const ChestGeom& cg, int nblk_batch) {
@@ -899,13 +909,13 @@ __device__ __forceinline__ void mmse_mfma_body(MfmaLds& lds, const int blk, cons
   }
 }
 
-template <int KS, bool FUSED, int NT>
+template <int KS, bool FUSED, int NT, int NDP>
 __global__ __launch_bounds__(64) void k_mmse_mfma(const cf* __restrict__ H, const cf* __restrict__ Y,
                                                   const int2* __restrict__ taps, cf* __restrict__ Xh,
                                                   int* __restrict__ st, MmseGeom g, ChestGeom cg, int nblk_batch) {
-  __shared__ __align__(16) MfmaLds lds;
+  __shared__ __align__(16) MfmaLds<NDP> lds;
   // neighbouring subcarriers on one XCD (shared pilot rows)
-  mmse_mfma_body<KS, FUSED, NT>(lds, xcd_block(blockIdx.x, gridDim.x), H, Y, taps, Xh, st, g, cg, nblk_batch);
+  mmse_mfma_body<KS, FUSED, NT, NDP>(lds, xcd_block(blockIdx.x, gridDim.x), H, Y, taps, Xh, st, g, cg, nblk_batch);
 }
 
 // Many cells in one launch: logical block b (after the XCD renumbering, so a
@@ -917,8 +927,9 @@ __global__ __launch_bounds__(64) void k_mmse_mfma_cells(MmseCells t) {
   int c = 0;
   while (c + 1 < t.n && blk >= t.start[c + 1]) ++c;
   const MmseCell& e = t.cell[c];
-  __shared__ __align__(16) MfmaLds lds;
-  mmse_mfma_body<KS, true, NT>(lds, blk - t.start[c], nullptr, e.Y, e.taps, e.Xh, e.st, e.g, e.cg, e.nblk_batch);
+  __shared__ __align__(16) MfmaLds<kMaxD> lds;
+  mmse_mfma_body<KS, true, NT, kMaxD>(lds, blk - t.start[c], nullptr, e.Y, e.taps, e.Xh, e.st, e.g, e.cg,
+                                      e.nblk_batch);
 }
 
 template <int KS, bool FUSED, int NT>
@@ -928,8 +939,13 @@ hipError_t launch_mfma(const cf* H, const cf* Y, const int2* taps, const ChestGe
   const long long nblk = batch * nblk_batch;
   if (nblk <= 0) return hipSuccess;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_mmse_mfma<KS, FUSED, NT>), dim3((unsigned)nblk), dim3(64), 0, s, H, Y, taps, Xh, st, g, cg,
-                     nblk_batch);
+  // P for 12 data symbols when the call has at most 12 (less LDS per wave)
+  if (g.n_data <= 12)
+    hipLaunchKernelGGL((k_mmse_mfma<KS, FUSED, NT, 12>), dim3((unsigned)nblk), dim3(64), 0, s, H, Y, taps, Xh, st, g,
+                       cg, nblk_batch);
+  else
+    hipLaunchKernelGGL((k_mmse_mfma<KS, FUSED, NT, kMaxD>), dim3((unsigned)nblk), dim3(64), 0, s, H, Y, taps, Xh, st,
+                       g, cg, nblk_batch);
   return hipGetLastError();
 }
 
@@ -951,10 +967,10 @@ __global__ __launch_bounds__(64) void k_mmse_mfma_any(MmseCells t) {
   while (c + 1 < t.n && blk >= t.start[c + 1]) ++c;
   const MmseCell& e = t.cell[c];
   const int b = blk - t.start[c];
-  __shared__ __align__(16) MfmaLds lds;
-#define MM_CASE(CLS, KS, NT)                                                                       \
-  case CLS:                                                                                       \
-    mmse_mfma_body<KS, true, NT>(lds, b, nullptr, e.Y, e.taps, e.Xh, e.st, e.g, e.cg, e.nblk_batch); \
+  __shared__ __align__(16) MfmaLds<kMaxD> lds;
+#define MM_CASE(CLS, KS, NT)                                                                              \
+  case CLS:                                                                                              \
+    mmse_mfma_body<KS, true, NT, kMaxD>(lds, b, nullptr, e.Y, e.taps, e.Xh, e.st, e.g, e.cg, e.nblk_batch); \
     break;
   switch (e.cls) {
     MM_CASE(0, 2, 2)
