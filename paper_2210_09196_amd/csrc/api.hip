@@ -35,7 +35,7 @@ struct DeviceTables {
   // pusch_cells: side streams (default priority) and the fork / join events
   // that tie them to the caller's stream; cells_mu serialises the enqueue
   hipStream_t side[kSideStreams] = {};
-  hipEvent_t fork = nullptr, join[kSideStreams] = {};
+  hipEvent_t fork = nullptr, fork_mmse = nullptr, join[kSideStreams] = {};
   std::mutex cells_mu;
   // per-geometry tables (interpolation taps of the fused detection,
   // noise-estimation neighbours), built on the library's own stream
@@ -64,7 +64,9 @@ int device_tables(DeviceTables** out) {
     if (hipMemcpy(d, host.data(), host.size() * sizeof(cf), hipMemcpyHostToDevice) != hipSuccess) return;
     t.twiddles = static_cast<cf*>(d);
     t.n_cu = ncu;
-    if (hipEventCreateWithFlags(&t.fork, hipEventDisableTiming) != hipSuccess) return;
+    if (hipEventCreateWithFlags(&t.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&t.fork_mmse, hipEventDisableTiming) != hipSuccess)
+      return;
     for (int i = 0; i < kSideStreams; ++i)
       if (hipStreamCreateWithFlags(&t.side[i], hipStreamNonBlocking) != hipSuccess ||
           hipEventCreateWithFlags(&t.join[i], hipEventDisableTiming) != hipSuccess)
@@ -718,9 +720,13 @@ int for_groups(const std::vector<int>& idx, Key key, int per_launch, Launch f) {
 
 // The grouped stages of pusch_cells on stream s for the cells in idx (arguments
 // checked); cell c's intermediates in its own workspace slice base[c].
+// *side_used: side streams the call enqueued detection launches on (the
+// caller joins them back to s).
 int run_cells_grouped(DeviceTables* t, const pusch_slot_desc* d, const long long* n_slot, const pusch_c32* const* x_td,
                       pusch_c32* const* x_hat, int32_t* const* status, const std::vector<char*>& base,
-                      const std::vector<int>& idx, bool mixed, const pusch_cells_plan& plan, hipStream_t s) {
+                      const std::vector<int>& idx, bool mixed, const pusch_cells_plan& plan, hipStream_t s,
+                      int* side_used) {
+  *side_used = 0;
   if (idx.empty()) return PUSCH_OK;
   const int n = (int)base.size();
   // the geometries' tables, before anything is enqueued
@@ -803,8 +809,13 @@ int run_cells_grouped(DeviceTables* t, const pusch_slot_desc* d, const long long
                                 part, s2[c], chest_geom(&d[c]), n_slot[c], s) != hipSuccess)
       return PUSCH_EHIP;
   }
-  // detection: one launch for every detection class, or one per class
-  return for_groups(
+  // detection: one launch for every detection class, or one per class.  Its
+  // workgroups are not persistent, so when the cells need several launches
+  // they run side by side: the first on s, the others on the side streams
+  // (forked from s here), and their tails overlap.
+  int n_launch = 0;
+  if (hipEventRecord(t->fork_mmse, s) != hipSuccess) return PUSCH_EHIP;
+  rc = for_groups(
       idx,
       [&](int c) {
         return plan.mmse_merged
@@ -812,7 +823,7 @@ int run_cells_grouped(DeviceTables* t, const pusch_slot_desc* d, const long long
                    : pusch::mmse_cell_class(d[c].n_beams,
                                             pusch::comb_taps(d[c].n_ue, d[c].n_pilot, d[c].comb_aligned != 0));
       },
-      pusch::kMmseCellsPerLaunch, [&](int cls, const std::vector<int>& grp) {
+      pusch::kMmseCellsPerLaunch, [&](int cls, const std::vector<int>& grp) -> int {
         pusch::MmseCells mt{};
         mt.n = (int)grp.size();
         for (int i = 0; i < mt.n; ++i) {
@@ -828,8 +839,18 @@ int run_cells_grouped(DeviceTables* t, const pusch_slot_desc* d, const long long
           e.cg = chest_geom(&d[c]);
           e.n_tap = pusch::comb_taps(d[c].n_ue, d[c].n_pilot, d[c].comb_aligned != 0);
         }
-        return hip_status(pusch::launch_mmse_cells(mt, cls, s));
+        hipStream_t ls = s;
+        if (n_launch > 0) {
+          const int j = (n_launch - 1) % kSideStreams;
+          if (n_launch <= kSideStreams && hipStreamWaitEvent(t->side[j], t->fork_mmse, 0) != hipSuccess)
+            return PUSCH_EHIP;
+          ls = t->side[j];
+          *side_used = std::max(*side_used, j + 1);
+        }
+        ++n_launch;
+        return hip_status(pusch::launch_mmse_cells(mt, cls, ls));
       });
+  return rc;
 }
 
 // Launch plan of a call that pusch_cells_tune has not timed.
@@ -1064,13 +1085,14 @@ int cells_call(const pusch_slot_desc* d, int n_cells, const long long* n_slot, c
     rc = run_slot(t, &d[c], n_slot[c], x_td[c], x_hat[c], status ? status[c] : nullptr, base[c],
                   t->side[i % kSideStreams], false, mx);
   }
+  int side_grouped = 0;
   if (rc == PUSCH_OK && !grouped.empty()) {
     const pusch_cells_plan plan = force ? *force : cells_plan(t, cells_signature(d, n_cells, n_slot, flags));
-    rc = run_cells_grouped(t, d, n_slot, x_td, x_hat, status, base, grouped, mx, plan, s);
+    rc = run_cells_grouped(t, d, n_slot, x_td, x_hat, status, base, grouped, mx, plan, s, &side_grouped);
   }
   // join (also after a failed launch, so the caller's stream never runs
   // ahead of work already enqueued on a side stream)
-  for (int i = 0; i < used; ++i)
+  for (int i = 0; i < std::max(used, side_grouped); ++i)
     if (hipEventRecord(t->join[i], t->side[i]) != hipSuccess || hipStreamWaitEvent(s, t->join[i], 0) != hipSuccess)
       rc = PUSCH_EHIP;
   return rc;

@@ -85,7 +85,7 @@ inline int share_work(int n, Rounds rounds, Cost cost, long long cap, int* start
 // Many cells of any FFT sizes in one launch (the grouped form of
 // pusch_cells): the per-cell arguments of launch_fft (with X or Xh/ex/rows),
 // up to kFftCellsPerLaunch cells; tw and start[] are filled by the launcher.
-constexpr int kFftCellsPerLaunch = 32;
+constexpr int kFftCellsPerLaunch = 48;
 struct FftCell {
   const cf* x;
   cf* X;
