@@ -110,7 +110,7 @@ int dft_beamformer(DeviceTables* t, int n_beams, int n_ant, const cf** out) {
 // Tables that depend on a slot geometry only, built once per geometry by
 // their kernels on the library's stream (waited for there, so the caller's
 // stream never waits on it) and kept until the process ends.
-enum GeomTable { kCombTaps = 0, kNoiseTable = 1, kTimeTaps = 2 };
+enum GeomTable { kCombTaps = 0, kNoiseTable = 1, kTimeTaps = 2, kPairTaps = 3 };
 
 int geometry_table(DeviceTables* t, GeomTable kind, const pusch::ChestGeom& g, int n_tap, const void** out,
                    const pusch::TimeTapGeom* tt = nullptr) {
@@ -131,11 +131,13 @@ int geometry_table(DeviceTables* t, GeomTable kind, const pusch::ChestGeom& g, i
   }
   const size_t bytes = kind == kCombTaps   ? (size_t)g.n_sc * g.n_ue * n_tap * sizeof(int2)
                        : kind == kTimeTaps ? (size_t)tt->n_data * g.n_sc * g.n_ue * pusch::kTimeTaps * sizeof(int2)
+                       : kind == kPairTaps ? (size_t)g.n_sc * g.n_ue * 4 * sizeof(int2)
                                            : pusch::noise_table_bytes(g.n_pilot, g.n_sc);
   void* d = nullptr;
   if (hipMalloc(&d, bytes) != hipSuccess) return PUSCH_ENOMEM;
   const hipError_t e = kind == kCombTaps   ? pusch::launch_comb_taps(static_cast<int2*>(d), g, n_tap, t->build)
                        : kind == kTimeTaps ? pusch::launch_time_taps(static_cast<int2*>(d), g, *tt, t->build)
+                       : kind == kPairTaps ? pusch::launch_pair_taps(static_cast<int2*>(d), g, t->build)
                                            : pusch::launch_noise_table(static_cast<int4*>(d), g, t->build);
   if (e != hipSuccess || hipStreamSynchronize(t->build) != hipSuccess) {
     (void)hipFree(d);
@@ -589,7 +591,13 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
       for (int j = 0; j < P; ++j) pilot |= d->pilot_symb[j] == s_;
       if (!pilot) tt.data_sym[tt.n_data++] = s_;
     }
-    if (int rc = geometry_table(t, kTimeTaps, cg, pusch::kTimeTaps, &taps, &tt)) return rc;
+    // two pilot symbols: every data symbol in one launch from each pilot
+    // symbol's own taps; more: one launch per run of data symbols
+    if (P == 2) {
+      if (int rc = geometry_table(t, kPairTaps, cg, 4, &taps)) return rc;
+    } else if (int rc = geometry_table(t, kTimeTaps, cg, pusch::kTimeTaps, &taps, &tt)) {
+      return rc;
+    }
   } else if (fused) {
     if (int rc = geometry_table(t, kCombTaps, cg, n_tap, &taps)) return rc;
   }
@@ -638,7 +646,12 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   // symbols (with the channel estimate computed inside when fused)
   if (!mark(3)) return PUSCH_EHIP;
   const pusch::MmseGeom mg = mmse_geom(d, s2);
-  if (d->time_varying) {
+  if (d->time_varying && P == 2) {
+    // one factorisation per data symbol (its own channel estimate), all in one launch
+    if (pusch::launch_mmse_tv(Y, static_cast<const int2*>(taps), cg, reinterpret_cast<cf*>(x_hat), status, mg,
+                              n_slot, s) != hipSuccess)
+      return PUSCH_EHIP;
+  } else if (d->time_varying) {
     // one factorisation per data symbol (its own channel estimate); the data
     // symbols before the first pilot symbol share one estimate, and so do
     // those after the last, so each such run is one launch; status flags

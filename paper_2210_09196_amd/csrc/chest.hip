@@ -120,6 +120,41 @@ hipError_t launch_time_taps(int2* tab, const ChestGeom& g, const TimeTapGeom& t,
   return hipGetLastError();
 }
 
+namespace {
+// Two pilot symbols, each UE's estimate from each alone (as for k_time_taps):
+// tab[(k * n_ue + l) * 4 + 2 j + {0, 1}] = the (offset, weight) taps of pilot
+// symbol j (the nearest positions below and above k of UE l's residue class
+// on symbol j, linear in k; a hold gives (offset, 1) and (offset, 0)).
+__global__ __launch_bounds__(256) void k_pair_taps(int2* __restrict__ tab, ChestGeom g) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= g.n_sc * g.n_ue) return;
+  const int l = idx % g.n_ue, k = idx / g.n_ue;
+  const int step = comb_step(g);
+  const float inv = fast_rcp((float)g.n_ue);
+  int2* dst = tab + (long long)idx * 4;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int rj = fmod_pos(l - j * step, g.n_ue, inv);  // UE l's residue class on pilot symbol j
+    int lo = k - fmod_pos(k - rj, g.n_ue, inv);
+    int hi = k + fmod_pos(rj - k, g.n_ue, inv);
+    if (lo < 0) lo = hi;
+    if (hi >= g.n_sc) hi = lo;
+    const long long base = pilot_grid(g, j);
+    const float w = hi == lo ? 0.f : (float)(k - lo) / (float)(hi - lo);
+    dst[2 * j] = make_int2((int)(base + (long long)lo * g.n_beams), __float_as_int(1.f - w));
+    dst[2 * j + 1] = make_int2((int)(base + (long long)hi * g.n_beams), __float_as_int(w));
+  }
+}
+}  // namespace
+
+hipError_t launch_pair_taps(int2* tab, const ChestGeom& g, hipStream_t s) {
+  const long long n = (long long)g.n_sc * g.n_ue;
+  if (n <= 0) return hipSuccess;
+  if (g.n_pilot != 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pair_taps, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, g);
+  return hipGetLastError();
+}
+
 int comb_taps(int n_ue, int n_pilot, bool aligned) {
   // pilot symbols j, j' put UE l's pilot on the same subcarriers when
   // (j - j') * step = 0 mod n_ue (step = n_ue / n_pilot, or 0 when aligned):

@@ -195,6 +195,10 @@ struct TimeTapGeom {
 };
 constexpr int kTimeTaps = 4;
 hipError_t launch_time_taps(int2* tab, const ChestGeom& g, const TimeTapGeom& t, hipStream_t s);
+// Two pilot symbols: per (k, l) the 2 + 2 frequency taps of each pilot
+// symbol's own estimate, tab[(k * n_ue + l) * 4 + 2 j + {0, 1}] (offset as
+// for launch_comb_taps, weight), for launch_mmse_tv.
+hipError_t launch_pair_taps(int2* tab, const ChestGeom& g, hipStream_t s);
 
 // ---------------------------------------------------------------- noise estimation
 // Noise variance of every batch item from its pilot symbols (grids at
@@ -249,6 +253,17 @@ hipError_t launch_mmse_fused(const cf* Y, const int2* taps, int n_tap, const Che
 // mmse_cell_class(n_beams, n_tap) (the class's own kernel; -1 from
 // mmse_cell_class: no grouped kernel); cls = -1: any classes, one kernel.
 // nblk_batch, cls and start[] are filled by the launcher.
+// Time-varying channel with two pilot symbols in one launch: data symbol d's
+// estimate is (1 - a_d) H_0 + a_d H_1, a_d = (s_d - p_0) / (p_1 - p_0)
+// clamped to [0, 1] (s_d its symbol index, p_j the pilot symbols' indices;
+// H_j from pilot symbol j alone, taps of launch_pair_taps), its Gram matrix is formed from H_0^H H_0,
+// H_1^H H_1 and (H_0 + H_1)^H (H_0 + H_1), and each data symbol is factored
+// and solved on its own; status flags OR over the data symbols (st_or as for
+// launch_mmse).  Needs two pilot symbols, 1 <= g.n_data <= 16 and
+// mmse_fusable(n_ue, n_beams, cg.y_batch); grids as for launch_mmse_fused.
+hipError_t launch_mmse_tv(const cf* Y, const int2* taps, const ChestGeom& cg, cf* Xhat, int* status,
+                          const MmseGeom& g, long long batch, hipStream_t s);
+
 constexpr int kMmseCellsPerLaunch = 16;
 struct MmseCell {
   const cf* Y;

@@ -598,6 +598,48 @@ struct MfmaLds {
   float Dinv[kSPW * kDinv];
 };
 
+// Crout factorisation of a 16 x 16 block per group of 16 lanes (Sec. V-C):
+// on entry lane i holds row i of the regularised Gram matrix in L[0..i]
+// (zeros beyond); rows and columns from nue on must be the identity.  On exit
+// L[j] = L_ij for j < i and L[i] = L_ii (the lane keeps t / L_jj in the
+// columns above its diagonal, which are never read), 1 / L_jj goes to
+// dinv[j] (LDS, if given) and the lane's own 1 / L_ii to dvi.  Row j of L
+// reaches every lane of the group by a DPP row broadcast.  Returns 1 when a
+// pivot is not positive and finite (the same value in all 16 lanes).
+__device__ __forceinline__ int crout_rows(cf (&L)[16], const int i, const int nue, float* __restrict__ dinv,
+                                          float& dvi) {
+  int fail = 0;
+  dvi = 1.f;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    // padded rows / columns beyond n_ue stay the identity: G is zero off
+    // the diagonal there (zero rows of H) and 1 on it, so is L, and the
+    // substitutions never read that part (a uniform branch)
+    if (j < nue) {
+      // sum_m L_im conj(L_jm) as positive multiply-adds of broadcast values
+      // (each one can take the broadcast as its DPP operand), then t
+      float sr = 0.f, sp = 0.f, sm = 0.f;
+#pragma unroll
+      for (int m = 0; m < j; ++m) {
+        const cf c = row_bcast_c(L[m], j);
+        const float cr = c.r, ci = c.i;
+        sr = __builtin_fmaf(cr, L[m].r, sr);
+        sr = __builtin_fmaf(ci, L[m].i, sr);
+        sp = __builtin_fmaf(cr, L[m].i, sp);
+        sm = __builtin_fmaf(ci, L[m].r, sm);
+      }
+      const cf t = cf{L[j].r - sr, L[j].i - (sp - sm)};
+      const float dpiv = row_bcast(t.r, j);
+      fail |= (dpiv > 0.f && dpiv <= 3.402823466e38f) ? 0 : 1;
+      const float inv = rsqrtf(dpiv);  // 1 / L_jj
+      L[j] = cf{t.r * inv, t.i * inv};
+      if (dinv) dinv[j] = inv;
+      if (j == i) dvi = inv;
+    }
+  }
+  return fail;
+}
+
 // Phases B and C of one block (G and P of its kSPW subcarriers in LDS):
 // Crout factorisation, then the substitutions and the stores of x_hat and
 // the status flags.
@@ -624,38 +666,8 @@ __device__ __forceinline__ void mmse_factor_solve(MfmaLds<NDP>& lds, const int b
     cf L[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) L[j] = j <= i ? Grow[j] : cf{0.f, 0.f};
-    // Only the strictly lower triangle of L and the reciprocals of its
-    // diagonal are used later, so every lane keeps t / L_jj in column j
-    // (entries at or above the diagonal are never read) and every lane of
-    // the group stores the same 1 / L_jj: no per-lane selects.
-    int fail = 0;
-    float* dinv = Dinv + grp * kDinv;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      // padded rows / columns beyond n_ue stay the identity: G is zero off
-      // the diagonal there (zero rows of H) and 1 on it, so is L, and the
-      // substitutions never read that part (a uniform branch)
-      if (j < nue) {
-        // sum_m L_im conj(L_jm) as positive multiply-adds of broadcast values
-        // (each one can take the broadcast as its DPP operand), then t
-        float sr = 0.f, sp = 0.f, sm = 0.f;
-#pragma unroll
-        for (int m = 0; m < j; ++m) {
-          const cf c = row_bcast_c(L[m], j);
-          const float cr = c.r, ci = c.i;
-          sr = __builtin_fmaf(cr, L[m].r, sr);
-          sr = __builtin_fmaf(ci, L[m].i, sr);
-          sp = __builtin_fmaf(cr, L[m].i, sp);
-          sm = __builtin_fmaf(ci, L[m].r, sm);
-        }
-        const cf t = cf{L[j].r - sr, L[j].i - (sp - sm)};
-        const float dpiv = row_bcast(t.r, j);
-        fail |= (dpiv > 0.f && dpiv <= 3.402823466e38f) ? 0 : 1;
-        const float inv = rsqrtf(dpiv);  // 1 / L_jj
-        L[j] = cf{t.r * inv, t.i * inv};
-        dinv[j] = inv;
-      }
-    }
+    float dvi;
+    const int fail = crout_rows(L, i, nue, Dinv + grp * kDinv, dvi);
 #pragma unroll
     for (int j = 0; j < 16; ++j)
       if (j <= i) Grow[j] = L[j];
@@ -985,6 +997,210 @@ __global__ __launch_bounds__(64) void k_mmse_mfma_any(MmseCells t) {
 #undef MM_CASE
 }
 
+// ---------------------------------------------------------------- time-varying channel, two pilot symbols
+// Data symbol d's estimate is H_d = (1 - a) H_0 + a H_1, so
+//   H_d^H H_d = (1 - a)(1 - 2a) H_0^H H_0 + a(2a - 1) H_1^H H_1 + a(1 - a) H_u^H H_u,  H_u = H_0 + H_1,
+//   H_d^H y_d = (1 - a) H_0^H y_d + a H_1^H y_d:
+// one pass of MFMAs per subcarrier (9 + 6 per K-step) gives every data
+// symbol's Gram matrix and matched filter, and each data symbol is then
+// factored (Crout, as the static kernel) and solved with one lane per row:
+// forward and back substitution step through the rows, each final
+// component reaching the other rows by a DPP row broadcast.
+
+// Grid index of data symbol d: the d-th from d_first that is not a pilot grid.
+__device__ __forceinline__ int data_symbol(const MmseGeom& g, int d) {
+  int s = g.d_first + d;
+#pragma unroll
+  for (int j = 0; j < kMaxPilots; ++j)
+    if (j < g.n_skip && g.skip[j] <= s) ++s;
+  return s;
+}
+
+// LDS of a workgroup: the lower triangles of H_0^H H_0, H_1^H H_1 and
+// H_u^H H_u, the matched filters H_d^H y_d = (1 - a_d) H_0^H y_d + a_d H_1^H y_d
+// (rows of NDP data symbols, as MfmaLds), and the factor of the data symbol
+// in work (full 16 x 16 rows, read by columns in the back substitution).
+template <int NDP>
+struct TvLds {
+  cf G0[kSPW * kTri];
+  cf G1[kSPW * kTri];
+  cf Gu[kSPW * kTri];
+  cf P[kSPW * kMatP<NDP>];
+  cf Lt[kSPW * 256];  // [row][column], zero at and above the diagonal
+};
+
+template <int NDP>
+__device__ __forceinline__ void tv_store(TvLds<NDP>& lds, int sc, const GpAcc& c0, const GpAcc& c1, f32x4 u1,
+                                         f32x4 u2, f32x4 u3, float al, int q, int c16) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 4 * q + v;
+    if (i >= c16) {
+      const int e = sc * kTri + tri(i) + c16;
+      lds.G0[e] = cf{c0.g1[v] + c0.g2[v], c0.g3[v] - c0.g1[v] + c0.g2[v]};
+      lds.G1[e] = cf{c1.g1[v] + c1.g2[v], c1.g3[v] - c1.g1[v] + c1.g2[v]};
+      lds.Gu[e] = cf{u1[v] + u2[v], u3[v] - u1[v] + u2[v]};
+    }
+    if (c16 < kRowP<NDP>) {  // column c16: data symbol c16, time weight al
+      const cf p0 = cf{c0.p1[v] + c0.p2[v], c0.p3[v] - c0.p1[v] + c0.p2[v]};
+      const cf p1 = cf{c1.p1[v] + c1.p2[v], c1.p3[v] - c1.p1[v] + c1.p2[v]};
+      lds.P[sc * kMatP<NDP> + i * kRowP<NDP> + c16] =
+          cf{(1.f - al) * p0.r + al * p1.r, (1.f - al) * p0.i + al * p1.i};
+    }
+  }
+}
+
+template <int KS, int NDP>
+__global__ __launch_bounds__(64) void k_mmse_tv(const cf* __restrict__ Y, const int2* __restrict__ taps,
+                                                cf* __restrict__ Xh, int* __restrict__ st, MmseGeom g, ChestGeom cg,
+                                                int nblk_batch) {
+  __shared__ __align__(16) TvLds<NDP> lds;
+  const int lane = threadIdx.x;
+  const int c16 = lane & 15, q = lane >> 4;
+  const int nb = g.n_beams, nue = g.n_ue, nsc = g.n_sc, nd = g.n_data;
+  const long long ysym = data_grid(g, c16 < nd ? c16 : 0);  // this lane's data symbol (B operand)
+  const int blk = xcd_block(blockIdx.x, gridDim.x);  // neighbouring subcarriers on one XCD
+  const int bi = blk / nblk_batch;
+  const int k0 = (blk - bi * nblk_batch) * kSPW;
+  const int ue = c16 < nue ? c16 : 0;  // lanes past n_ue: UE 0's taps, result discarded
+  const cf* LSb = Y + bi * cg.y_batch;
+  const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
+  const float pa = (float)cg.pilot_sym[0], pspan = (float)(cg.pilot_sym[1] - cg.pilot_sym[0]);
+  auto weight = [&](int d) {  // time weight of pilot symbol 1 for data symbol d
+    const float a = ((float)data_symbol(g, d) - pa) / pspan;
+    return a < 0.f ? 0.f : (a > 1.f ? 1.f : a);
+  };
+  const float al_lane = weight(c16 < nd ? c16 : 0);  // this lane's matched-filter column
+
+  // ---- phase A: both pilot symbols' estimates of this lane's UE and beams,
+  // then the three Gram matrices and the two matched filters
+#pragma unroll 1
+  for (int sc = 0; sc < kSPW; ++sc) {
+    const int kk = k0 + sc < nsc ? k0 + sc : nsc - 1;
+    const int4* tp = reinterpret_cast<const int4*>(taps + ((long long)kk * nue + ue) * 4);
+    const int4 ta = tp[0], tb = tp[1];  // pilot symbol 0: two (offset, weight) taps; pilot symbol 1
+    const float wa0 = __int_as_float(ta.y), wa1 = __int_as_float(ta.w);
+    const float wb0 = __int_as_float(tb.y), wb1 = __int_as_float(tb.w);
+    const cf* yrow = Y + bi * g.y_batch + ysym + (long long)kk * nb;
+    const bool live = c16 < nue && k0 + sc < nsc;  // else zero rows of H
+    float4 la0[KS / 2], la1[KS / 2], lb0[KS / 2], lb1[KS / 2], yv[KS / 2];
+#pragma unroll
+    for (int u = 0; u < KS / 2; ++u) {
+      const int b = frag_beam(2 * u, q);
+      la0[u] = load_pair_even(LSb + ta.x, b, nb);
+      la1[u] = load_pair_even(LSb + ta.z, b, nb);
+      lb0[u] = load_pair_even(LSb + tb.x, b, nb);
+      lb1[u] = load_pair_even(LSb + tb.z, b, nb);
+      yv[u] = load_pair_even(yrow, b, nb);
+    }
+    GpAcc a0{z4, z4, z4, z4, z4, z4}, a1{z4, z4, z4, z4, z4, z4};
+    f32x4 u1 = z4, u2 = z4, u3 = z4;
+#pragma unroll
+    for (int u = 0; u < KS / 2; ++u) {
+      const int b = frag_beam(2 * u, q);
+      const bool keep = live && b < nb;
+      const float4 p = la0[u], r = la1[u], s_ = lb0[u], t = lb1[u], yy = yv[u];
+      const float4 h0 = {__builtin_fmaf(wa1, r.x, wa0 * p.x), __builtin_fmaf(wa1, r.y, wa0 * p.y),
+                         __builtin_fmaf(wa1, r.z, wa0 * p.z), __builtin_fmaf(wa1, r.w, wa0 * p.w)};
+      const float4 h1 = {__builtin_fmaf(wb1, t.x, wb0 * s_.x), __builtin_fmaf(wb1, t.y, wb0 * s_.y),
+                         __builtin_fmaf(wb1, t.z, wb0 * s_.z), __builtin_fmaf(wb1, t.w, wb0 * s_.w)};
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const cf x0 = keep ? (e ? cf{h0.z, h0.w} : cf{h0.x, h0.y}) : cf{0.f, 0.f};
+        const cf x1 = keep ? (e ? cf{h1.z, h1.w} : cf{h1.x, h1.y}) : cf{0.f, 0.f};
+        const cf y = e ? cf{yy.z, yy.w} : cf{yy.x, yy.y};
+        gp_kstep(a0, x0, y);
+        gp_kstep(a1, x1, y);
+        const cf xu = cf{x0.r + x1.r, x0.i + x1.i};
+        u1 = mfma(xu.r, xu.r, u1);
+        u2 = mfma(xu.i, xu.i, u2);
+        u3 = mfma(xu.r - xu.i, xu.r + xu.i, u3);
+      }
+    }
+    tv_store(lds, sc, a0, a1, u1, u2, u3, al_lane, q, c16);
+  }
+  __syncthreads();
+
+  // ---- per data symbol: Gram matrix, Crout factorisation and both
+  // substitutions, lane (q, c16) holding row c16 of subcarrier q
+  const int grp = q, i = c16;
+  const int k = k0 + grp;
+  const float s2 = g.sigma2_item ? g.sigma2_item[bi] : g.sigma2;
+  // padding rows beyond n_ue (and a subcarrier past n_sc) stay the identity
+  const float dreg = (i < nue && k < nsc) ? s2 : 1.0f;
+  const cf* G0r = lds.G0 + grp * kTri + tri(i);
+  const cf* G1r = lds.G1 + grp * kTri + tri(i);
+  const cf* Gur = lds.Gu + grp * kTri + tri(i);
+  cf* Ltg = lds.Lt + grp * 256;
+  int fail_any = 0;
+#pragma unroll 1
+  for (int d = 0; d < nd; ++d) {
+    const float al = weight(d);
+    const float c00 = (1.f - al) * (1.f - 2.f * al), c11 = al * (2.f * al - 1.f), cu = al * (1.f - al);
+    // row i of the Gram matrix (every lane reads 16 entries, in bounds of the
+    // triangle, and keeps those at or below its diagonal: no divergent loads)
+    cf L[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const cf a = G0r[j], b = G1r[j], c = Gur[j];
+      const cf v = cf{c00 * a.r + c11 * b.r + cu * c.r + (j == i ? dreg : 0.f), c00 * a.i + c11 * b.i + cu * c.i};
+      L[j] = j <= i ? v : cf{0.f, 0.f};
+    }
+    float dvi;
+    const int fail = crout_rows(L, i, nue, nullptr, dvi);
+    // the strictly lower part of L, zero elsewhere (the forward substitution
+    // then needs no per-lane branch), and the rows to LDS for the column reads
+#pragma unroll
+    for (int j = 0; j < 16; ++j) L[j] = j < i ? L[j] : cf{0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < 16; ++j) Ltg[i * 16 + j] = L[j];
+    __syncthreads();
+    // right-hand side H_d^H y_d, component i
+    cf zi = lds.P[grp * kMatP<NDP> + i * kRowP<NDP> + d];
+    // L z = b: z_m is final on lane m, broadcast, and removed from the rows
+    // below (L[m] is zero on the lanes at or above row m)
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      if (m < nue) {
+        const cf zm = row_bcast_c(cf{zi.r * dvi, zi.i * dvi}, m);
+        csub_mul(zi, L[m], zm);
+        zi = i == m ? zm : zi;
+      }
+    }
+    // L^H x = z: column i of L from LDS (zero at and above the diagonal); x_m
+    // final on lane m, broadcast, and removed from the rows above
+    cf Lc[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) Lc[m] = Ltg[m * 16 + i];
+#pragma unroll
+    for (int m = 15; m >= 0; --m) {
+      if (m < nue) {
+        const cf xm = row_bcast_c(cf{zi.r * dvi, zi.i * dvi}, m);
+        csub_conj_mul(zi, Lc[m], xm);
+        zi = i == m ? xm : zi;
+      }
+    }
+    if (k < nsc && i < nue) Xh[bi * g.x_batch + ((long long)d * nsc + k) * nue + i] = fail ? cf{0.f, 0.f} : zi;
+    fail_any |= fail;
+    __syncthreads();  // the next data symbol writes its factor over this one
+  }
+  if (k < nsc && i == 0 && st) {
+    int* sp = st + bi * g.st_batch + k;
+    *sp = g.st_or ? (*sp | fail_any) : fail_any;
+  }
+}
+
+template <int KS>
+hipError_t launch_tv_ks(const cf* Y, const int2* taps, const ChestGeom& cg, cf* Xh, int* st, const MmseGeom& g,
+                        long long nblk, int nblk_batch, hipStream_t s) {
+  if (g.n_data <= 12)
+    hipLaunchKernelGGL((k_mmse_tv<KS, 12>), dim3((unsigned)nblk), dim3(64), 0, s, Y, taps, Xh, st, g, cg, nblk_batch);
+  else
+    hipLaunchKernelGGL((k_mmse_tv<KS, kMaxD>), dim3((unsigned)nblk), dim3(64), 0, s, Y, taps, Xh, st, g, cg,
+                       nblk_batch);
+  return hipGetLastError();
+}
+
 template <int KS>
 hipError_t launch_cells_ks(MmseCells& t, int n_tap, unsigned blocks, hipStream_t s) {
   if (n_tap == 2) hipLaunchKernelGGL((k_mmse_mfma_cells<KS, 2>), dim3(blocks), dim3(64), 0, s, t);
@@ -1026,6 +1242,22 @@ hipError_t launch_mmse_cells(MmseCells& t, int cls, hipStream_t s) {
     case 2: return launch_cells_ks<8>(t, n_tap, (unsigned)start, s);
     default: return launch_cells_ks<16>(t, n_tap, (unsigned)start, s);
   }
+}
+
+hipError_t launch_mmse_tv(const cf* Y, const int2* taps, const ChestGeom& cg, cf* Xhat, int* status,
+                          const MmseGeom& g, long long batch, hipStream_t s) {
+  if (g.n_data > kMaxD || g.n_data < 1 || cg.n_pilot != 2 || cg.pilot_sym[1] <= cg.pilot_sym[0] ||
+      !mmse_fusable(g.n_ue, g.n_beams, cg.y_batch))
+    return hipErrorInvalidValue;
+  const int nblk_batch = (g.n_sc + kSPW - 1) / kSPW;
+  const long long nblk = batch * nblk_batch;
+  if (nblk <= 0) return hipSuccess;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  const int nb = g.n_beams;
+  if (nb <= 8) return launch_tv_ks<2>(Y, taps, cg, Xhat, status, g, nblk, nblk_batch, s);
+  if (nb <= 16) return launch_tv_ks<4>(Y, taps, cg, Xhat, status, g, nblk, nblk_batch, s);
+  if (nb <= 32) return launch_tv_ks<8>(Y, taps, cg, Xhat, status, g, nblk, nblk_batch, s);
+  return launch_tv_ks<16>(Y, taps, cg, Xhat, status, g, nblk, nblk_batch, s);
 }
 
 bool mmse_auto_refine(int n_ue, int n_beams) { return n_ue > 16 && 2 * n_ue > n_beams; }
