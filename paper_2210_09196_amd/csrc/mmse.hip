@@ -1017,47 +1017,62 @@ __device__ __forceinline__ int data_symbol(const MmseGeom& g, int d) {
 }
 
 // LDS of a workgroup: the lower triangles of H_0^H H_0, H_1^H H_1 and
-// H_u^H H_u, the matched filters H_d^H y_d = (1 - a_d) H_0^H y_d + a_d H_1^H y_d
-// (rows of NDP data symbols, as MfmaLds), and the factor of the data symbol
-// in work (full 16 x 16 rows, read by columns in the back substitution).
+// H_u^H H_u of the subcarrier in work, its matched filters
+// H_d^H y_d = (1 - a_d) H_0^H y_d + a_d H_1^H y_d (rows of NDP data symbols,
+// as MfmaLds), and per lane group the factor of the data symbol it is
+// solving (strictly lower part, packed by rows as the triangles: row i at
+// tri(i), so a row written by 16 lanes and a column read by them each spread
+// over the banks).
 template <int NDP>
 struct TvLds {
-  cf G0[kSPW * kTri];
-  cf G1[kSPW * kTri];
-  cf Gu[kSPW * kTri];
-  cf P[kSPW * kMatP<NDP>];
-  cf Lt[kSPW * 256];  // [row][column], zero at and above the diagonal
+  cf G0[kTri];
+  cf G1[kTri];
+  cf Gu[kTri];
+  cf P[kMatP<NDP>];
+  cf Lt[kSPW * kTri];
 };
 
+// dreg: the regularisation of row c16.  It goes onto the diagonals of the
+// three products with weights 1, 1 and 4: for every time weight a,
+// (1 - a)(1 - 2a) + a(2a - 1) + 4a(1 - a) = 1, so each data symbol's Gram
+// matrix carries exactly dreg on its diagonal.
 template <int NDP>
-__device__ __forceinline__ void tv_store(TvLds<NDP>& lds, int sc, const GpAcc& c0, const GpAcc& c1, f32x4 u1,
-                                         f32x4 u2, f32x4 u3, float al, int q, int c16) {
+__device__ __forceinline__ void tv_store(TvLds<NDP>& lds, const GpAcc& c0, const GpAcc& c1, f32x4 u1, f32x4 u2,
+                                         f32x4 u3, float al, float dreg, int q, int c16) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int i = 4 * q + v;
     if (i >= c16) {
-      const int e = sc * kTri + tri(i) + c16;
-      lds.G0[e] = cf{c0.g1[v] + c0.g2[v], c0.g3[v] - c0.g1[v] + c0.g2[v]};
-      lds.G1[e] = cf{c1.g1[v] + c1.g2[v], c1.g3[v] - c1.g1[v] + c1.g2[v]};
-      lds.Gu[e] = cf{u1[v] + u2[v], u3[v] - u1[v] + u2[v]};
+      const int e = tri(i) + c16;
+      const float dg = i == c16 ? dreg : 0.f;
+      lds.G0[e] = cf{c0.g1[v] + c0.g2[v] + dg, c0.g3[v] - c0.g1[v] + c0.g2[v]};
+      lds.G1[e] = cf{c1.g1[v] + c1.g2[v] + dg, c1.g3[v] - c1.g1[v] + c1.g2[v]};
+      lds.Gu[e] = cf{u1[v] + u2[v] + 4.f * dg, u3[v] - u1[v] + u2[v]};
     }
     if (c16 < kRowP<NDP>) {  // column c16: data symbol c16, time weight al
       const cf p0 = cf{c0.p1[v] + c0.p2[v], c0.p3[v] - c0.p1[v] + c0.p2[v]};
       const cf p1 = cf{c1.p1[v] + c1.p2[v], c1.p3[v] - c1.p1[v] + c1.p2[v]};
-      lds.P[sc * kMatP<NDP> + i * kRowP<NDP> + c16] =
-          cf{(1.f - al) * p0.r + al * p1.r, (1.f - al) * p0.i + al * p1.i};
+      lds.P[i * kRowP<NDP> + c16] = cf{(1.f - al) * p0.r + al * p1.r, (1.f - al) * p0.i + al * p1.i};
     }
   }
 }
 
-template <int KS, int NDP>
-__global__ __launch_bounds__(64) void k_mmse_tv(const cf* __restrict__ Y, const int2* __restrict__ taps,
-                                                cf* __restrict__ Xh, int* __restrict__ st, MmseGeom g, ChestGeom cg,
-                                                int nblk_batch) {
+// One workgroup takes kSPW subcarriers, one at a time: phase A puts the
+// subcarrier's three Gram products and its matched filters in LDS, then the
+// four lane groups take four of its data symbols at a time (group q the
+// data symbols q, q + 4, ...), each lane holding row c16 of that data
+// symbol's Gram matrix.  Holding one subcarrier's products, not four, keeps
+// the workgroup's LDS small enough for several waves per SIMD.
+// FULL (16 UEs): the row and column guards fold away, so the scalar unit
+// holds no per-row conditions.
+template <int KS, int NDP, bool FULL>
+__global__ __launch_bounds__(64, 3) void k_mmse_tv(const cf* __restrict__ Y, const int2* __restrict__ taps,
+                                                   cf* __restrict__ Xh, int* __restrict__ st, MmseGeom g, ChestGeom cg,
+                                                   int nblk_batch) {
   __shared__ __align__(16) TvLds<NDP> lds;
   const int lane = threadIdx.x;
   const int c16 = lane & 15, q = lane >> 4;
-  const int nb = g.n_beams, nue = g.n_ue, nsc = g.n_sc, nd = g.n_data;
+  const int nb = g.n_beams, nue = FULL ? 16 : g.n_ue, nsc = g.n_sc, nd = g.n_data;
   const long long ysym = data_grid(g, c16 < nd ? c16 : 0);  // this lane's data symbol (B operand)
   const int blk = xcd_block(blockIdx.x, gridDim.x);  // neighbouring subcarriers on one XCD
   const int bi = blk / nblk_batch;
@@ -1071,132 +1086,158 @@ __global__ __launch_bounds__(64) void k_mmse_tv(const cf* __restrict__ Y, const 
     return a < 0.f ? 0.f : (a > 1.f ? 1.f : a);
   };
   const float al_lane = weight(c16 < nd ? c16 : 0);  // this lane's matched-filter column
+  const float s2 = g.sigma2_item ? g.sigma2_item[bi] : g.sigma2;
+  const int grp = q, i = c16;
+  const cf* G0r = lds.G0 + tri(i);
+  const cf* G1r = lds.G1 + tri(i);
+  const cf* Gur = lds.Gu + tri(i);
+  cf* Ltg = lds.Lt + grp * kTri;
 
-  // ---- phase A: both pilot symbols' estimates of this lane's UE and beams,
-  // then the three Gram matrices and the two matched filters
 #pragma unroll 1
   for (int sc = 0; sc < kSPW; ++sc) {
-    const int kk = k0 + sc < nsc ? k0 + sc : nsc - 1;
-    const int4* tp = reinterpret_cast<const int4*>(taps + ((long long)kk * nue + ue) * 4);
-    const int4 ta = tp[0], tb = tp[1];  // pilot symbol 0: two (offset, weight) taps; pilot symbol 1
-    const float wa0 = __int_as_float(ta.y), wa1 = __int_as_float(ta.w);
-    const float wb0 = __int_as_float(tb.y), wb1 = __int_as_float(tb.w);
-    const cf* yrow = Y + bi * g.y_batch + ysym + (long long)kk * nb;
-    const bool live = c16 < nue && k0 + sc < nsc;  // else zero rows of H
-    float4 la0[KS / 2], la1[KS / 2], lb0[KS / 2], lb1[KS / 2], yv[KS / 2];
+    // ---- phase A: both pilot symbols' estimates of this lane's UE and
+    // beams, then the three Gram matrices and the two matched filters
+    const int k = k0 + sc;
+    {
+      const int kk = k < nsc ? k : nsc - 1;
+      const int4* tp = reinterpret_cast<const int4*>(taps + ((long long)kk * nue + ue) * 4);
+      const int4 ta = tp[0], tb = tp[1];  // pilot symbol 0: two (offset, weight) taps; pilot symbol 1
+      const float wa0 = __int_as_float(ta.y), wa1 = __int_as_float(ta.w);
+      const float wb0 = __int_as_float(tb.y), wb1 = __int_as_float(tb.w);
+      const cf* yrow = Y + bi * g.y_batch + ysym + (long long)kk * nb;
+      const bool live = c16 < nue && k < nsc;  // else zero rows of H
+      float4 la0[KS / 2], la1[KS / 2], lb0[KS / 2], lb1[KS / 2], yv[KS / 2];
 #pragma unroll
-    for (int u = 0; u < KS / 2; ++u) {
-      const int b = frag_beam(2 * u, q);
-      la0[u] = load_pair_even(LSb + ta.x, b, nb);
-      la1[u] = load_pair_even(LSb + ta.z, b, nb);
-      lb0[u] = load_pair_even(LSb + tb.x, b, nb);
-      lb1[u] = load_pair_even(LSb + tb.z, b, nb);
-      yv[u] = load_pair_even(yrow, b, nb);
-    }
-    GpAcc a0{z4, z4, z4, z4, z4, z4}, a1{z4, z4, z4, z4, z4, z4};
-    f32x4 u1 = z4, u2 = z4, u3 = z4;
-#pragma unroll
-    for (int u = 0; u < KS / 2; ++u) {
-      const int b = frag_beam(2 * u, q);
-      const bool keep = live && b < nb;
-      const float4 p = la0[u], r = la1[u], s_ = lb0[u], t = lb1[u], yy = yv[u];
-      const float4 h0 = {__builtin_fmaf(wa1, r.x, wa0 * p.x), __builtin_fmaf(wa1, r.y, wa0 * p.y),
-                         __builtin_fmaf(wa1, r.z, wa0 * p.z), __builtin_fmaf(wa1, r.w, wa0 * p.w)};
-      const float4 h1 = {__builtin_fmaf(wb1, t.x, wb0 * s_.x), __builtin_fmaf(wb1, t.y, wb0 * s_.y),
-                         __builtin_fmaf(wb1, t.z, wb0 * s_.z), __builtin_fmaf(wb1, t.w, wb0 * s_.w)};
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const cf x0 = keep ? (e ? cf{h0.z, h0.w} : cf{h0.x, h0.y}) : cf{0.f, 0.f};
-        const cf x1 = keep ? (e ? cf{h1.z, h1.w} : cf{h1.x, h1.y}) : cf{0.f, 0.f};
-        const cf y = e ? cf{yy.z, yy.w} : cf{yy.x, yy.y};
-        gp_kstep(a0, x0, y);
-        gp_kstep(a1, x1, y);
-        const cf xu = cf{x0.r + x1.r, x0.i + x1.i};
-        u1 = mfma(xu.r, xu.r, u1);
-        u2 = mfma(xu.i, xu.i, u2);
-        u3 = mfma(xu.r - xu.i, xu.r + xu.i, u3);
+      for (int u = 0; u < KS / 2; ++u) {
+        const int b = frag_beam(2 * u, q);
+        la0[u] = load_pair_even(LSb + ta.x, b, nb);
+        la1[u] = load_pair_even(LSb + ta.z, b, nb);
+        lb0[u] = load_pair_even(LSb + tb.x, b, nb);
+        lb1[u] = load_pair_even(LSb + tb.z, b, nb);
+        yv[u] = load_pair_even(yrow, b, nb);
       }
+      GpAcc a0{z4, z4, z4, z4, z4, z4}, a1{z4, z4, z4, z4, z4, z4};
+      f32x4 u1 = z4, u2 = z4, u3 = z4;
+#pragma unroll
+      for (int u = 0; u < KS / 2; ++u) {
+        const int b = frag_beam(2 * u, q);
+        const bool keep = live && b < nb;
+        const float4 p = la0[u], r = la1[u], s_ = lb0[u], t = lb1[u], yy = yv[u];
+        const float4 h0 = {__builtin_fmaf(wa1, r.x, wa0 * p.x), __builtin_fmaf(wa1, r.y, wa0 * p.y),
+                           __builtin_fmaf(wa1, r.z, wa0 * p.z), __builtin_fmaf(wa1, r.w, wa0 * p.w)};
+        const float4 h1 = {__builtin_fmaf(wb1, t.x, wb0 * s_.x), __builtin_fmaf(wb1, t.y, wb0 * s_.y),
+                           __builtin_fmaf(wb1, t.z, wb0 * s_.z), __builtin_fmaf(wb1, t.w, wb0 * s_.w)};
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const cf x0 = keep ? (e ? cf{h0.z, h0.w} : cf{h0.x, h0.y}) : cf{0.f, 0.f};
+          const cf x1 = keep ? (e ? cf{h1.z, h1.w} : cf{h1.x, h1.y}) : cf{0.f, 0.f};
+          const cf y = e ? cf{yy.z, yy.w} : cf{yy.x, yy.y};
+          gp_kstep(a0, x0, y);
+          gp_kstep(a1, x1, y);
+          const cf xu = cf{x0.r + x1.r, x0.i + x1.i};
+          u1 = mfma(xu.r, xu.r, u1);
+          u2 = mfma(xu.i, xu.i, u2);
+          u3 = mfma(xu.r - xu.i, xu.r + xu.i, u3);
+        }
+      }
+      // padding rows beyond n_ue (and a subcarrier past n_sc) get 1, so
+      // their part of every factor is the identity
+      tv_store(lds, a0, a1, u1, u2, u3, al_lane, (c16 < nue && k < nsc) ? s2 : 1.0f, q, c16);
     }
-    tv_store(lds, sc, a0, a1, u1, u2, u3, al_lane, q, c16);
-  }
-  __syncthreads();
-
-  // ---- per data symbol: Gram matrix, Crout factorisation and both
-  // substitutions, lane (q, c16) holding row c16 of subcarrier q
-  const int grp = q, i = c16;
-  const int k = k0 + grp;
-  const float s2 = g.sigma2_item ? g.sigma2_item[bi] : g.sigma2;
-  // padding rows beyond n_ue (and a subcarrier past n_sc) stay the identity
-  const float dreg = (i < nue && k < nsc) ? s2 : 1.0f;
-  const cf* G0r = lds.G0 + grp * kTri + tri(i);
-  const cf* G1r = lds.G1 + grp * kTri + tri(i);
-  const cf* Gur = lds.Gu + grp * kTri + tri(i);
-  cf* Ltg = lds.Lt + grp * 256;
-  int fail_any = 0;
-#pragma unroll 1
-  for (int d = 0; d < nd; ++d) {
-    const float al = weight(d);
-    const float c00 = (1.f - al) * (1.f - 2.f * al), c11 = al * (2.f * al - 1.f), cu = al * (1.f - al);
-    // row i of the Gram matrix (every lane reads 16 entries, in bounds of the
-    // triangle, and keeps those at or below its diagonal: no divergent loads)
-    cf L[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const cf a = G0r[j], b = G1r[j], c = Gur[j];
-      const cf v = cf{c00 * a.r + c11 * b.r + cu * c.r + (j == i ? dreg : 0.f), c00 * a.i + c11 * b.i + cu * c.i};
-      L[j] = j <= i ? v : cf{0.f, 0.f};
-    }
-    float dvi;
-    const int fail = crout_rows(L, i, nue, nullptr, dvi);
-    // the strictly lower part of L, zero elsewhere (the forward substitution
-    // then needs no per-lane branch), and the rows to LDS for the column reads
-#pragma unroll
-    for (int j = 0; j < 16; ++j) L[j] = j < i ? L[j] : cf{0.f, 0.f};
-#pragma unroll
-    for (int j = 0; j < 16; ++j) Ltg[i * 16 + j] = L[j];
     __syncthreads();
-    // right-hand side H_d^H y_d, component i
-    cf zi = lds.P[grp * kMatP<NDP> + i * kRowP<NDP> + d];
-    // L z = b: z_m is final on lane m, broadcast, and removed from the rows
-    // below (L[m] is zero on the lanes at or above row m)
+
+    // ---- per data symbol: Gram matrix, Crout factorisation and both
+    // substitutions, lane (q, c16) holding row c16; group q takes data
+    // symbols q, q + 4, ... (a group past n_data repeats the last one and
+    // stores nothing, so every lane reaches the barriers)
+    int fail_any = 0;
+#pragma unroll 1
+    for (int d0 = 0; d0 < nd; d0 += kSPW) {
+      const bool act = d0 + grp < nd;
+      const int d = act ? d0 + grp : nd - 1;
+      const float al = weight(d);
+      const float c00 = (1.f - al) * (1.f - 2.f * al), c11 = al * (2.f * al - 1.f), cu = al * (1.f - al);
+      // row i of the Gram matrix (every lane reads 16 entries, in bounds of
+      // the triangles: no divergent loads; the entries past its diagonal are
+      // other rows' and only feed columns above the diagonal, which the
+      // factorisation computes but never reads)
+      cf L[16];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      if (m < nue) {
-        const cf zm = row_bcast_c(cf{zi.r * dvi, zi.i * dvi}, m);
-        csub_mul(zi, L[m], zm);
-        zi = i == m ? zm : zi;
+      for (int j = 0; j < 16; ++j) {
+        const cf a = G0r[j], b = G1r[j], c = Gur[j];
+        L[j] = cf{c00 * a.r + c11 * b.r + cu * c.r, c00 * a.i + c11 * b.i + cu * c.i};
       }
-    }
-    // L^H x = z: column i of L from LDS (zero at and above the diagonal); x_m
-    // final on lane m, broadcast, and removed from the rows above
-    cf Lc[16];
+      float dvi;
+      const int fail = crout_rows(L, i, nue, nullptr, dvi);
+      // the strictly lower part of L, zero elsewhere (the forward
+      // substitution then needs no per-lane branch), and the rows to LDS for
+      // the column reads
 #pragma unroll
-    for (int m = 0; m < 16; ++m) Lc[m] = Ltg[m * 16 + i];
-#pragma unroll
-    for (int m = 15; m >= 0; --m) {
-      if (m < nue) {
-        const cf xm = row_bcast_c(cf{zi.r * dvi, zi.i * dvi}, m);
-        csub_conj_mul(zi, Lc[m], xm);
-        zi = i == m ? xm : zi;
+      for (int j = 0; j < 16; ++j) {
+        L[j] = j < i ? L[j] : cf{0.f, 0.f};
+        if (j < i) Ltg[tri(i) + j] = L[j];
       }
+      __syncthreads();
+      // right-hand side H_d^H y_d, component i
+      cf zi = lds.P[i * kRowP<NDP> + d];
+      // L z = b: lane m's value is complete once the rows above it are
+      // removed; z_m = that / L_mm is broadcast and removed from the rows
+      // below (L[m] is zero on the lanes at or above row m, so a lane's own
+      // value stays put after its turn)
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        if (m < nue) {
+          const cf zm = row_bcast_c(cf{zi.r * dvi, zi.i * dvi}, m);
+          csub_mul(zi, L[m], zm);
+        }
+      }
+      zi = cf{zi.r * dvi, zi.i * dvi};
+      // L^H x = z: column i of L (entries of rows m > i; the reads of rows
+      // m <= i stay inside the group's triangle and are replaced by zero);
+      // x_m final on lane m, broadcast, and removed from the rows above
+      cf Lc[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const cf v = Ltg[tri(m) + i];
+        Lc[m] = m > i ? v : cf{0.f, 0.f};
+      }
+#pragma unroll
+      for (int m = 15; m >= 0; --m) {
+        if (m < nue) {
+          const cf xm = row_bcast_c(cf{zi.r * dvi, zi.i * dvi}, m);
+          csub_conj_mul(zi, Lc[m], xm);
+        }
+      }
+      zi = cf{zi.r * dvi, zi.i * dvi};
+      if (act && k < nsc && i < nue) Xh[bi * g.x_batch + ((long long)d * nsc + k) * nue + i] = fail ? cf{0.f, 0.f} : zi;
+      fail_any |= act ? fail : 0;
+      __syncthreads();  // the next data symbols write their factors over these
     }
-    if (k < nsc && i < nue) Xh[bi * g.x_batch + ((long long)d * nsc + k) * nue + i] = fail ? cf{0.f, 0.f} : zi;
-    fail_any |= fail;
-    __syncthreads();  // the next data symbol writes its factor over this one
-  }
-  if (k < nsc && i == 0 && st) {
-    int* sp = st + bi * g.st_batch + k;
-    *sp = g.st_or ? (*sp | fail_any) : fail_any;
+    // the subcarrier's flag: any of its data symbols, over the four groups
+    fail_any |= __shfl_xor(fail_any, 16);
+    fail_any |= __shfl_xor(fail_any, 32);
+    if (k < nsc && lane == 0 && st) {
+      int* sp = st + bi * g.st_batch + k;
+      *sp = g.st_or ? (*sp | fail_any) : fail_any;
+    }
   }
 }
 
 template <int KS>
 hipError_t launch_tv_ks(const cf* Y, const int2* taps, const ChestGeom& cg, cf* Xh, int* st, const MmseGeom& g,
                         long long nblk, int nblk_batch, hipStream_t s) {
-  if (g.n_data <= 12)
-    hipLaunchKernelGGL((k_mmse_tv<KS, 12>), dim3((unsigned)nblk), dim3(64), 0, s, Y, taps, Xh, st, g, cg, nblk_batch);
+  const bool full = g.n_ue == 16;
+  if (g.n_data <= 12 && full)
+    hipLaunchKernelGGL((k_mmse_tv<KS, 12, true>), dim3((unsigned)nblk), dim3(64), 0, s, Y, taps, Xh, st, g, cg,
+                       nblk_batch);
+  else if (g.n_data <= 12)
+    hipLaunchKernelGGL((k_mmse_tv<KS, 12, false>), dim3((unsigned)nblk), dim3(64), 0, s, Y, taps, Xh, st, g, cg,
+                       nblk_batch);
+  else if (full)
+    hipLaunchKernelGGL((k_mmse_tv<KS, kMaxD, true>), dim3((unsigned)nblk), dim3(64), 0, s, Y, taps, Xh, st, g, cg,
+                       nblk_batch);
   else
-    hipLaunchKernelGGL((k_mmse_tv<KS, kMaxD>), dim3((unsigned)nblk), dim3(64), 0, s, Y, taps, Xh, st, g, cg,
+    hipLaunchKernelGGL((k_mmse_tv<KS, kMaxD, false>), dim3((unsigned)nblk), dim3(64), 0, s, Y, taps, Xh, st, g, cg,
                        nblk_batch);
   return hipGetLastError();
 }
