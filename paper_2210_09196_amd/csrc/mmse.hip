@@ -616,19 +616,17 @@ __device__ __forceinline__ int crout_rows(cf (&L)[16], const int i, const int nu
     // the diagonal there (zero rows of H) and 1 on it, so is L, and the
     // substitutions never read that part (a uniform branch)
     if (j < nue) {
-      // sum_m L_im conj(L_jm) as positive multiply-adds of broadcast values
-      // (each one can take the broadcast as its DPP operand), then t
-      float sr = 0.f, sp = 0.f, sm = 0.f;
+      // t = G_ij - sum_m L_im conj(L_jm), row j's entries broadcast
+      float tr = L[j].r, ti = L[j].i;
 #pragma unroll
       for (int m = 0; m < j; ++m) {
         const cf c = row_bcast_c(L[m], j);
-        const float cr = c.r, ci = c.i;
-        sr = __builtin_fmaf(cr, L[m].r, sr);
-        sr = __builtin_fmaf(ci, L[m].i, sr);
-        sp = __builtin_fmaf(cr, L[m].i, sp);
-        sm = __builtin_fmaf(ci, L[m].r, sm);
+        tr = __builtin_fmaf(-c.r, L[m].r, tr);
+        tr = __builtin_fmaf(-c.i, L[m].i, tr);
+        ti = __builtin_fmaf(-c.r, L[m].i, ti);
+        ti = __builtin_fmaf(c.i, L[m].r, ti);
       }
-      const cf t = cf{L[j].r - sr, L[j].i - (sp - sm)};
+      const cf t = cf{tr, ti};
       const float dpiv = row_bcast(t.r, j);
       fail |= (dpiv > 0.f && dpiv <= 3.402823466e38f) ? 0 : 1;
       const float inv = rsqrtf(dpiv);  // 1 / L_jj
@@ -1002,9 +1000,12 @@ __global__ __launch_bounds__(64) void k_mmse_mfma_any(MmseCells t) {
 //   H_d^H H_d = (1 - a)(1 - 2a) H_0^H H_0 + a(2a - 1) H_1^H H_1 + a(1 - a) H_u^H H_u,  H_u = H_0 + H_1,
 //   H_d^H y_d = (1 - a) H_0^H y_d + a H_1^H y_d:
 // one pass of MFMAs per subcarrier (9 + 6 per K-step) gives every data
-// symbol's Gram matrix and matched filter, and each data symbol is then
-// factored (Crout, as the static kernel) and solved with one lane per row:
-// forward and back substitution step through the rows, each final
+// symbol's Gram matrix and matched filter.  Written as a polynomial in a,
+//   H_d^H H_d = A + a (B + a C),  A = H_0^H H_0,  B = H_u^H H_u - 3 A - H_1^H H_1,
+//   C = 2 A + 2 H_1^H H_1 - H_u^H H_u,
+// it costs two multiply-adds per entry and data symbol.  Each data symbol is
+// then factored (Crout, as the static kernel) and solved with one lane per
+// row: forward and back substitution step through the rows, each final
 // component reaching the other rows by a DPP row broadcast.
 
 // Grid index of data symbol d: the d-th from d_first that is not a pilot grid.
@@ -1016,26 +1017,23 @@ __device__ __forceinline__ int data_symbol(const MmseGeom& g, int d) {
   return s;
 }
 
-// LDS of a workgroup: the lower triangles of H_0^H H_0, H_1^H H_1 and
-// H_u^H H_u of the subcarrier in work, its matched filters
+// LDS of a workgroup: the lower triangles of A (with the regularisation on
+// its diagonal), B and C of the subcarrier in work, its matched filters
 // H_d^H y_d = (1 - a_d) H_0^H y_d + a_d H_1^H y_d (rows of NDP data symbols,
 // as MfmaLds), and per lane group the factor of the data symbol it is
-// solving (strictly lower part, packed by rows as the triangles: row i at
-// tri(i), so a row written by 16 lanes and a column read by them each spread
-// over the banks).
+// solving (strictly lower part, each row divided by its diagonal entry,
+// packed by rows as the triangles: row i at tri(i), so a row written by 16
+// lanes and a column read by them each spread over the banks).
 template <int NDP>
 struct TvLds {
-  cf G0[kTri];
-  cf G1[kTri];
-  cf Gu[kTri];
+  cf GA[kTri];
+  cf GB[kTri];
+  cf GC[kTri];
   cf P[kMatP<NDP>];
   cf Lt[kSPW * kTri];
 };
 
-// dreg: the regularisation of row c16.  It goes onto the diagonals of the
-// three products with weights 1, 1 and 4: for every time weight a,
-// (1 - a)(1 - 2a) + a(2a - 1) + 4a(1 - a) = 1, so each data symbol's Gram
-// matrix carries exactly dreg on its diagonal.
+// dreg: the regularisation of row c16, on the diagonal of A.
 template <int NDP>
 __device__ __forceinline__ void tv_store(TvLds<NDP>& lds, const GpAcc& c0, const GpAcc& c1, f32x4 u1, f32x4 u2,
                                          f32x4 u3, float al, float dreg, int q, int c16) {
@@ -1044,10 +1042,12 @@ __device__ __forceinline__ void tv_store(TvLds<NDP>& lds, const GpAcc& c0, const
     const int i = 4 * q + v;
     if (i >= c16) {
       const int e = tri(i) + c16;
-      const float dg = i == c16 ? dreg : 0.f;
-      lds.G0[e] = cf{c0.g1[v] + c0.g2[v] + dg, c0.g3[v] - c0.g1[v] + c0.g2[v]};
-      lds.G1[e] = cf{c1.g1[v] + c1.g2[v] + dg, c1.g3[v] - c1.g1[v] + c1.g2[v]};
-      lds.Gu[e] = cf{u1[v] + u2[v] + 4.f * dg, u3[v] - u1[v] + u2[v]};
+      const cf g0 = cf{c0.g1[v] + c0.g2[v], c0.g3[v] - c0.g1[v] + c0.g2[v]};
+      const cf g1 = cf{c1.g1[v] + c1.g2[v], c1.g3[v] - c1.g1[v] + c1.g2[v]};
+      const cf gu = cf{u1[v] + u2[v], u3[v] - u1[v] + u2[v]};
+      lds.GA[e] = cf{g0.r + (i == c16 ? dreg : 0.f), g0.i};
+      lds.GB[e] = cf{gu.r - 3.f * g0.r - g1.r, gu.i - 3.f * g0.i - g1.i};
+      lds.GC[e] = cf{2.f * (g0.r + g1.r) - gu.r, 2.f * (g0.i + g1.i) - gu.i};
     }
     if (c16 < kRowP<NDP>) {  // column c16: data symbol c16, time weight al
       const cf p0 = cf{c0.p1[v] + c0.p2[v], c0.p3[v] - c0.p1[v] + c0.p2[v]};
@@ -1088,9 +1088,9 @@ __global__ __launch_bounds__(64, 3) void k_mmse_tv(const cf* __restrict__ Y, con
   const float al_lane = weight(c16 < nd ? c16 : 0);  // this lane's matched-filter column
   const float s2 = g.sigma2_item ? g.sigma2_item[bi] : g.sigma2;
   const int grp = q, i = c16;
-  const cf* G0r = lds.G0 + tri(i);
-  const cf* G1r = lds.G1 + tri(i);
-  const cf* Gur = lds.Gu + tri(i);
+  const cf* GAr = lds.GA + tri(i);
+  const cf* GBr = lds.GB + tri(i);
+  const cf* GCr = lds.GC + tri(i);
   cf* Ltg = lds.Lt + grp * kTri;
 
 #pragma unroll 1
@@ -1156,45 +1156,48 @@ __global__ __launch_bounds__(64, 3) void k_mmse_tv(const cf* __restrict__ Y, con
       const bool act = d0 + grp < nd;
       const int d = act ? d0 + grp : nd - 1;
       const float al = weight(d);
-      const float c00 = (1.f - al) * (1.f - 2.f * al), c11 = al * (2.f * al - 1.f), cu = al * (1.f - al);
-      // row i of the Gram matrix (every lane reads 16 entries, in bounds of
-      // the triangles: no divergent loads; the entries past its diagonal are
-      // other rows' and only feed columns above the diagonal, which the
-      // factorisation computes but never reads)
+      // row i of the Gram matrix A + a (B + a C) (every lane reads 16
+      // entries, in bounds of the triangles: no divergent loads; the entries
+      // past its diagonal are other rows' and only feed columns above the
+      // diagonal, which the factorisation computes but never reads)
       cf L[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const cf a = G0r[j], b = G1r[j], c = Gur[j];
-        L[j] = cf{c00 * a.r + c11 * b.r + cu * c.r, c00 * a.i + c11 * b.i + cu * c.i};
+        const cf a = GAr[j], b = GBr[j], c = GCr[j];
+        L[j] = cf{__builtin_fmaf(al, __builtin_fmaf(al, c.r, b.r), a.r),
+                  __builtin_fmaf(al, __builtin_fmaf(al, c.i, b.i), a.i)};
       }
       float dvi;
       const int fail = crout_rows(L, i, nue, nullptr, dvi);
-      // the strictly lower part of L, zero elsewhere (the forward
-      // substitution then needs no per-lane branch), and the rows to LDS for
-      // the column reads
+      // L = D L' with D = diag(L_ii): row i of the unit lower triangle L'
+      // (L_ij / L_ii below the diagonal, zero elsewhere, so the forward
+      // substitution needs no per-lane branch), and the rows to LDS for the
+      // column reads.  G x = b is then L' z = D^-1 b, L'^H w = z, x = D^-1 w,
+      // with no division inside either substitution.
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        L[j] = j < i ? L[j] : cf{0.f, 0.f};
+        L[j] = j < i ? cf{L[j].r * dvi, L[j].i * dvi} : cf{0.f, 0.f};
         if (j < i) Ltg[tri(i) + j] = L[j];
       }
       __syncthreads();
-      // right-hand side H_d^H y_d, component i
-      cf zi = lds.P[i * kRowP<NDP> + d];
-      // L z = b: lane m's value is complete once the rows above it are
-      // removed; z_m = that / L_mm is broadcast and removed from the rows
-      // below (L[m] is zero on the lanes at or above row m, so a lane's own
-      // value stays put after its turn)
+      // right-hand side H_d^H y_d, component i, divided by L_ii
+      const cf bi_ = lds.P[i * kRowP<NDP> + d];
+      cf zi = cf{bi_.r * dvi, bi_.i * dvi};
+      // L' z = D^-1 b: lane m's value is final once the rows above it are
+      // removed; it is broadcast and removed from the rows below (L'[m] is
+      // zero on the lanes at or above row m, so a lane's own value stays put
+      // after its turn)
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
         if (m < nue) {
-          const cf zm = row_bcast_c(cf{zi.r * dvi, zi.i * dvi}, m);
+          const cf zm = row_bcast_c(zi, m);
           csub_mul(zi, L[m], zm);
         }
       }
-      zi = cf{zi.r * dvi, zi.i * dvi};
-      // L^H x = z: column i of L (entries of rows m > i; the reads of rows
+      // L'^H w = z: column i of L' (entries of rows m > i; the reads of rows
       // m <= i stay inside the group's triangle and are replaced by zero);
-      // x_m final on lane m, broadcast, and removed from the rows above
+      // w_m final on lane m, broadcast, and removed from the rows above;
+      // then x_i = w_i / L_ii
       cf Lc[16];
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
@@ -1204,8 +1207,8 @@ __global__ __launch_bounds__(64, 3) void k_mmse_tv(const cf* __restrict__ Y, con
 #pragma unroll
       for (int m = 15; m >= 0; --m) {
         if (m < nue) {
-          const cf xm = row_bcast_c(cf{zi.r * dvi, zi.i * dvi}, m);
-          csub_conj_mul(zi, Lc[m], xm);
+          const cf wm = row_bcast_c(zi, m);
+          csub_conj_mul(zi, Lc[m], wm);
         }
       }
       zi = cf{zi.r * dvi, zi.i * dvi};
