@@ -13,9 +13,10 @@ time measured with HIP events that the library records on the launch stream
 around every stage in a second pass over the same steps, the roofline of the
 dominant kernel (the HBM or the FP32 roof, whichever binds at the kernel's
 algorithmic intensity), the FP64 CPU oracle timed on a bounded sample of the
-same slots (serial, and on every host core of the GPU's share), and the same batch through the mixed-precision chain, through
-the chain with the noise variance estimated from the pilots, and through the
-chain with a channel estimate per data symbol.
+same slots (serial, and on every host core of the GPU's share), and the same
+batch through the FP16 and the bfloat16 reduced-precision chains, through the
+chain with the noise variance estimated from the pilots, and through the chain
+with a channel estimate per data symbol.
 """
 from __future__ import annotations
 
@@ -236,6 +237,21 @@ def bench_mixed(args, cfg, batch, x, p, x_hat32, nd: int, ms32: float) -> dict:
             "value": round(N_SLOT / (ms / 1e3), 1), "unit": "slots/s", "us_per_slot": round(1e3 * ms / N_SLOT, 3),
             "speedup_vs_fp32": round(ms32 / ms, 3), "stage_us_per_launch": stage_us,
             "evm_db_fp32": round(e32, 3), "evm_db_mixed": round(e16, 3), "evm_gap_db": round(e16 - e32, 4),
+            "evm_slots": nd, "status_flags": int(st.sum().item())}
+
+
+def bench_bf16(args, cfg, batch, x, p, x_hat32, nd: int, ms32: float) -> dict:
+    """The same batch through pusch_slot_bf16 (bfloat16 active-bin grids, no
+    row scales, BF16-MFMA beamforming): time per step and EVM, as bench_mixed."""
+    ms, stage_us, xh, st, _ = _run_variant(args, cfg, batch, x, p, x_hat32, "bf16", batch["sigma2"])
+    data = batch["data"][:nd].transpose(0, 1, 3, 2)
+    e32 = _evm_db(x_hat32[:nd].cpu().numpy(), data)
+    eb = _evm_db(xh[:nd].cpu().numpy(), data)
+    return {"precision": "bfloat16 active-bin grids between FFT and beamforming (no scaling), beamforming on "
+                         "BF16 MFMA with FP32 accumulation, FP32 estimation and detection",
+            "value": round(N_SLOT / (ms / 1e3), 1), "unit": "slots/s", "us_per_slot": round(1e3 * ms / N_SLOT, 3),
+            "speedup_vs_fp32": round(ms32 / ms, 3), "stage_us_per_launch": stage_us,
+            "evm_db_fp32": round(e32, 3), "evm_db_bf16": round(eb, 3), "evm_gap_db": round(eb - e32, 4),
             "evm_slots": nd, "status_flags": int(st.sum().item())}
 
 
@@ -559,6 +575,7 @@ def main() -> int:
                      "us_per_launch": st_dom["us_per_launch"]})
     chain_bytes = sum(STAGE_BYTES.values()) * N_SLOT
     mixed = bench_mixed(args, cfg, batch, x, p, x_hat, nd, ms_per_step)
+    bf16 = bench_bf16(args, cfg, batch, x, p, x_hat, nd, ms_per_step)
     noise = bench_noise_est(args, cfg, batch, x, p, x_hat, nd, ms_per_step)
     timevar = bench_time_varying(args, cfg, batch, x, p, x_hat, ms_per_step)
     out = {
@@ -591,6 +608,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "status_flags": bad,
         "mixed": mixed,
+        "bf16": bf16,
         "noise_est": noise,
         "time_varying": timevar,
     }

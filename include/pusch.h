@@ -281,6 +281,19 @@ int pusch_slot_mixed(const pusch_slot_desc* d, long long n_slot, const pusch_c32
                      int32_t* status, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * The same reduced-precision form with bfloat16 in place of FP16 (Sec. VI's
+ * 32-bit words narrowed the other way: 8 significant bits, FP32's exponent
+ * range): the active-bin grids are stored as bfloat16 pairs rounded to
+ * nearest even, with no row scaling, and beamforming runs on BF16 matrix
+ * cores with FP32 accumulation (W rounded to BF16).  The extra error is
+ * relative 2^-9 per grid value and W entry.  Arguments, results, workspace
+ * size and limits as pusch_slot_mixed.
+ */
+size_t pusch_slot_bf16_workspace_bytes(const pusch_slot_desc* d, long long n_slot);
+int pusch_slot_bf16(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td, pusch_c32* x_hat,
+                    int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Many independent cells of different geometries in one call (the paper runs
  * many independent small problems side by side, each on its own group of
  * cores between barriers: Sec. V, Sec. VI).  Cell c is a pusch_slot call

@@ -566,8 +566,10 @@ pusch::MmseGeom mmse_geom(const pusch_slot_desc* d, const float* s2) {
 }
 
 // Launch sequence of one fused slot call on stream s (arguments checked).
+// mixed: 4-byte grids between the FFT and beamforming, FP16 with row scales,
+// or bfloat16 with bf16 (the exponent table is then not used).
 int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td, pusch_c32* x_hat,
-             int32_t* status, char* base, hipStream_t s, bool profile, bool mixed = false) {
+             int32_t* status, char* base, hipStream_t s, bool profile, bool mixed = false, bool bf16 = false) {
   const SlotLayout lay = slot_layout(d, n_slot, mixed);
   const int S = d->n_symb, R = d->n_ant, K = d->n_sc, B = d->n_beams, L = d->n_ue, P = d->n_pilot;
   const int D = S - P;
@@ -615,7 +617,7 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   if (!mark(0)) return PUSCH_EHIP;
   const long long KP = mixed ? (long long)xa_pitch_h16(K) : (long long)xa_pitch(K);
   unsigned* Xh = mixed ? reinterpret_cast<unsigned*>(base + lay.off_xa) : nullptr;
-  signed char* ex = mixed ? reinterpret_cast<signed char*>(base + lay.off_ex) : nullptr;
+  signed char* ex = mixed && !bf16 ? reinterpret_cast<signed char*>(base + lay.off_ex) : nullptr;
   if (pusch::launch_fft(reinterpret_cast<const cf*>(x_td), Xa, d->n_fft, n_slot * S * R, K, K / 2, KP, t->twiddles,
                         t->n_cu, s, Xh, ex, R) != hipSuccess)
     return PUSCH_EHIP;
@@ -924,6 +926,20 @@ int pusch_slot_mixed(const pusch_slot_desc* d, long long n_slot, const pusch_c32
   if (int rc = device_tables(&t)) return rc;
   return run_slot(t, d, n_slot, x_td, x_hat, status, static_cast<char*>(ws), static_cast<hipStream_t>(stream), true,
                   true);
+}
+
+size_t pusch_slot_bf16_workspace_bytes(const pusch_slot_desc* d, long long n_slot) {
+  return pusch_slot_mixed_workspace_bytes(d, n_slot);
+}
+
+int pusch_slot_bf16(const pusch_slot_desc* d, long long n_slot, const pusch_c32* x_td, pusch_c32* x_hat,
+                    int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_slot_call(d, n_slot, x_td, x_hat, status, ws, ws_bytes, true)) return rc;
+  if (n_slot == 0) return PUSCH_OK;
+  DeviceTables* t = nullptr;
+  if (int rc = device_tables(&t)) return rc;
+  return run_slot(t, d, n_slot, x_td, x_hat, status, static_cast<char*>(ws), static_cast<hipStream_t>(stream), true,
+                  true, true);
 }
 
 size_t pusch_cells_workspace_bytes(const pusch_slot_desc* d, int n_cells, const long long* n_slot, int flags) {

@@ -15,6 +15,7 @@
 //     the next tile during the current one's v_mfma_f32_16x16x4_f32s;
 //   k_beamform_h16 (mixed-precision slot): the same tiles from FP16 grids
 //     with per-row power-of-two scales, on v_mfma_f32_16x16x16_f16;
+//     k_beamform_b16 from bfloat16 grids on v_mfma_f32_16x16x16_bf16;
 //   k_beamform (any antenna count): 32-RE tiles walking the antenna axis in
 //     double-buffered chunks of 16.
 // Operand layouts of the 16x16x4 instruction: lane l supplies A[l%16][l/16]
@@ -374,13 +375,28 @@ hipError_t launch_k(const cf* W, const cf* X, cf* Y, int nb, int na, int nre,
 // drops below the FP16 range, where it is negligible next to the row with
 // e_min), and 2^-e_min is applied to the FP32 accumulators.  W is rounded to
 // FP16 (entries of a beamformer are O(1); |W| must lie inside FP16's range).
+//
+// BF (bfloat16 input, Xh written by the FFT's BF16 form): no exponents, the
+// words are bfloat16 pairs whose halves are the MFMA operands as they stand;
+// only the sum xr + xi of the three-product form is rounded again (to
+// nearest even), and the product runs on v_mfma_f32_16x16x16_bf16 (W
+// rounded to BF16).
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef short b4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f32x4 mfma16(h4 a, h4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f32x4 mfmab16(b4 a, b4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+// FP32 to bfloat16 bits, round to nearest even (finite values)
+__device__ __forceinline__ short bf16_bits(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
 
-template <int MT, int J>
+template <int MT, int J, bool BF = false>
 __device__ __forceinline__ void bf_h16_body(int vb, int vg, const cf* __restrict__ W, const unsigned* __restrict__ Xh,
                                             const signed char* __restrict__ ex, cf* __restrict__ Y, int nb, int na,
                                             int nre, long long ldx, long long sx, long long sy, int ntiles, int ntn,
@@ -400,9 +416,15 @@ __device__ __forceinline__ void bf_h16_body(int vb, int vg, const cf* __restrict
     for (int i = 0; i < 4; ++i) {
       const int a = 4 * (4 * j + i) + q;
       const cf w = (a < na && b < nb) ? W[b * na + a] : cf{0.f, 0.f};
-      wr[i] = (_Float16)w.r;
-      wi[i] = (_Float16)w.i;
-      ws[i] = (_Float16)(w.r + w.i);
+      if constexpr (BF) {
+        wr[i] = __builtin_bit_cast(_Float16, bf16_bits(w.r));
+        wi[i] = __builtin_bit_cast(_Float16, bf16_bits(w.i));
+        ws[i] = __builtin_bit_cast(_Float16, bf16_bits(w.r + w.i));
+      } else {
+        wr[i] = (_Float16)w.r;
+        wi[i] = (_Float16)w.i;
+        ws[i] = (_Float16)(w.r + w.i);
+      }
     }
     wh[3 * e] = wr;
     wh[3 * e + 1] = wi;
@@ -427,7 +449,7 @@ __device__ __forceinline__ void bf_h16_body(int vb, int vg, const cf* __restrict
       const int a = ks * 4 + kq;
       xb.w[ks] = base[(unsigned)(a < na ? a : na - 1) * (unsigned)ldx + nn];
     }
-    xb.e = *reinterpret_cast<const int4*>(ex + (long long)bi * 64 + kq * 16);
+    if constexpr (!BF) xb.e = *reinterpret_cast<const int4*>(ex + (long long)bi * 64 + kq * 16);
   };
   auto compute = [&](const Buf& xb, int tile) {
     const int bi = tile / ntn;
@@ -435,42 +457,62 @@ __device__ __forceinline__ void bf_h16_body(int vb, int vg, const cf* __restrict
     // this lane's exponents (antennas past n_ant: never written, ignored)
     int ev[KS];
     int emin = 127;
+    if constexpr (!BF) {
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int word = (ks >> 2) == 0 ? xb.e.x : ((ks >> 2) == 1 ? xb.e.y : ((ks >> 2) == 2 ? xb.e.z : xb.e.w));
-      const bool ok = ks * 4 + kq < na;
-      ev[ks] = ok ? (int)__builtin_amdgcn_sbfe((unsigned)word, 8 * (ks & 3), 8) : 127;
-      emin = ev[ks] < emin ? ev[ks] : emin;
+      for (int ks = 0; ks < KS; ++ks) {
+        const int word = (ks >> 2) == 0 ? xb.e.x : ((ks >> 2) == 1 ? xb.e.y : ((ks >> 2) == 2 ? xb.e.z : xb.e.w));
+        const bool ok = ks * 4 + kq < na;
+        ev[ks] = ok ? (int)__builtin_amdgcn_sbfe((unsigned)word, 8 * (ks & 3), 8) : 127;
+        emin = ev[ks] < emin ? ev[ks] : emin;
+      }
+      // symbol-wide minimum: the four antenna groups kq sit 16 lanes apart
+      emin = min(emin, __shfl_xor(emin, 16));
+      emin = min(emin, __shfl_xor(emin, 32));
     }
-    // symbol-wide minimum: the four antenna groups kq sit 16 lanes apart
-    emin = min(emin, __shfl_xor(emin, 16));
-    emin = min(emin, __shfl_xor(emin, 32));
     f32x4 t1[MT], t2[MT], t3[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) t1[m] = t2[m] = t3[m] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      h4 ar, ai, as;
+      if constexpr (BF) {
+        b4 ar, ai, as;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int ks = 4 * j + i;
-        const unsigned u = xb.w[ks];
-        const int d = ev[ks] == 127 ? 0 : emin - ev[ks];  // <= 0: scale down to the common exponent
-        const float xr = ldexpf(__half2float(__ushort_as_half((unsigned short)(u & 0xffffu))), d);
-        const float xi = ldexpf(__half2float(__ushort_as_half((unsigned short)(u >> 16))), d);
-        ar[i] = (_Float16)xr;
-        ai[i] = (_Float16)xi;
-        as[i] = (_Float16)(xr + xi);
-      }
+        for (int i = 0; i < 4; ++i) {
+          const unsigned u = xb.w[4 * j + i];
+          ar[i] = (short)(u & 0xffffu);
+          ai[i] = (short)(u >> 16);
+          as[i] = bf16_bits(__uint_as_float(u << 16) + __uint_as_float(u & 0xffff0000u));
+        }
 #pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        const h4* w = wh + 3 * ((j * MT + m) * 64 + lane);
-        t1[m] = mfma16(ar, w[0], t1[m]);
-        t2[m] = mfma16(ai, w[1], t2[m]);
-        t3[m] = mfma16(as, w[2], t3[m]);
+        for (int m = 0; m < MT; ++m) {
+          const h4* w = wh + 3 * ((j * MT + m) * 64 + lane);
+          t1[m] = mfmab16(ar, __builtin_bit_cast(b4, w[0]), t1[m]);
+          t2[m] = mfmab16(ai, __builtin_bit_cast(b4, w[1]), t2[m]);
+          t3[m] = mfmab16(as, __builtin_bit_cast(b4, w[2]), t3[m]);
+        }
+      } else {
+        h4 ar, ai, as;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int ks = 4 * j + i;
+          const unsigned u = xb.w[ks];
+          const int d = ev[ks] == 127 ? 0 : emin - ev[ks];  // <= 0: scale down to the common exponent
+          const float xr = ldexpf(__half2float(__ushort_as_half((unsigned short)(u & 0xffffu))), d);
+          const float xi = ldexpf(__half2float(__ushort_as_half((unsigned short)(u >> 16))), d);
+          ar[i] = (_Float16)xr;
+          ai[i] = (_Float16)xi;
+          as[i] = (_Float16)(xr + xi);
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          const h4* w = wh + 3 * ((j * MT + m) * 64 + lane);
+          t1[m] = mfma16(ar, w[0], t1[m]);
+          t2[m] = mfma16(ai, w[1], t2[m]);
+          t3[m] = mfma16(as, w[2], t3[m]);
+        }
       }
     }
-    const float escale = ldexpf(1.f, emin == 127 ? 0 : -emin);
+    const float escale = BF ? 1.f : ldexpf(1.f, emin == 127 ? 0 : -emin);
     // optional LS epilogue for pilot symbols: y * conj(p) / |p|^2 per RE
     cf sc[4] = {cf{escale, 0.f}, cf{escale, 0.f}, cf{escale, 0.f}, cf{escale, 0.f}};
     if (ps.pilots) {
@@ -539,6 +581,17 @@ __global__ __launch_bounds__(64 * kWaves) void k_beamform_h16(const cf* __restri
                      ntn, ps);
 }
 
+// The same on bfloat16 grids (ex unused).
+template <int MT, int J>
+__global__ __launch_bounds__(64 * kWaves) void k_beamform_b16(const cf* __restrict__ W,
+                                                              const unsigned* __restrict__ Xh,
+                                                              cf* __restrict__ Y, int nb, int na, int nre,
+                                                              long long ldx, long long sx, long long sy, int ntiles,
+                                                              int ntn, PilotScale ps) {
+  bf_h16_body<MT, J, true>(xcd_block(blockIdx.x, gridDim.x), gridDim.x, W, Xh, nullptr, Y, nb, na, nre, ldx, sx, sy,
+                           ntiles, ntn, ps);
+}
+
 template <int MT, int J>
 __global__ __launch_bounds__(64 * kWaves) void k_beamform_h16_cells(BfCells t) {
   const int blk = xcd_block(blockIdx.x, gridDim.x);  // as k_beamform_h16
@@ -571,10 +624,36 @@ hipError_t launch_h16(const cf* W, const unsigned* Xh, const signed char* ex, cf
   return hipGetLastError();
 }
 
+template <int MT, int J>
+hipError_t launch_b16(const cf* W, const unsigned* Xh, cf* Y, int nb, int na, int nre, long long ldx, long long sx,
+                      long long sy, long long batch, const PilotScale& ps, int n_cu, hipStream_t s) {
+  const int ntn = (nre + 15) / 16;
+  const long long tiles = batch * ntn;  // < 2^30 (checked by the caller)
+  const size_t lds = (size_t)J * MT * 64 * 3 * sizeof(h4);
+  static const int per_cu = [&] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_beamform_b16<MT, J>, 64 * kWaves, lds) != hipSuccess ||
+        n < 1)
+      n = 1;
+    return n;
+  }();
+  long long blocks = (tiles + kWaves - 1) / kWaves;
+  const long long cap = (long long)n_cu * per_cu;
+  if (blocks > cap) blocks = cap;
+  hipLaunchKernelGGL((k_beamform_b16<MT, J>), dim3((unsigned)blocks), dim3(64 * kWaves), lds, s, W, Xh, Y, nb, na,
+                     nre, ldx, sx, sy, (int)tiles, ntn, ps);
+  return hipGetLastError();
+}
+
 template <int MT>
 hipError_t launch_k_mt(const cf* W, const cf* X, const unsigned* Xh, const signed char* ex, cf* Y, int nb, int na,
                        int nre, long long ldx, long long sx, long long sy, long long batch, const PilotScale& ps,
                        int n_cu, hipStream_t s) {
+  if (Xh && !ex) {
+    if (na <= 16) return launch_b16<MT, 1>(W, Xh, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+    if (na <= 32) return launch_b16<MT, 2>(W, Xh, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+    return launch_b16<MT, 4>(W, Xh, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
+  }
   if (Xh) {
     if (na <= 16) return launch_h16<MT, 1>(W, Xh, ex, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);
     if (na <= 32) return launch_h16<MT, 2>(W, Xh, ex, Y, nb, na, nre, ldx, sx, sy, batch, ps, n_cu, s);

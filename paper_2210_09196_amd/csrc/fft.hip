@@ -151,6 +151,15 @@ __device__ __forceinline__ unsigned pack_h2(float re, float im) {
   return (unsigned)__half_as_ushort(__float2half_rn(re)) | ((unsigned)__half_as_ushort(__float2half_rn(im)) << 16);
 }
 
+// BF16 output: the same words as bfloat16 pairs (re in the low half), rounded
+// to nearest even and not scaled (bfloat16 has FP32's exponent range); no
+// exponent table.  Finite inputs only (an FFT of finite samples).
+__device__ __forceinline__ unsigned bf16_rne(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ unsigned pack_bf2(float re, float im) { return bf16_rne(re) | (bf16_rne(im) << 16); }
+
 // LDS of a workgroup: FPB = kThreads / (N / 16) padded transforms, the same
 // 4352 complex values at every size (so one buffer serves every size of a
 // grouped launch).
@@ -158,8 +167,9 @@ constexpr int kLdsCf = 4352;
 
 // The transform loop of one launch (or of one cell's share of a grouped
 // launch): workgroup vb of vg walks transforms vb*FPB, (vb + vg)*FPB, ...
-// lds: kLdsCf values; red: kThreads / 64 floats (per-wave partial norms, H16).
-template <int N, bool H16>
+// lds: kLdsCf values; red: kThreads / 64 floats (per-wave partial norms, FP16).
+// FMT: 0 FP32 output, 1 FP16 (scaled rows, exponent table), 2 BF16.
+template <int N, int FMT>
 __device__ __forceinline__ void fft_body(cf* __restrict__ lds, float* __restrict__ red, int vb, int vg,
                                          const cf* __restrict__ x, cf* __restrict__ X, unsigned* __restrict__ Xh,
                                          signed char* __restrict__ ex, int rows, const cf* __restrict__ tw,
@@ -170,6 +180,8 @@ __device__ __forceinline__ void fft_body(cf* __restrict__ lds, float* __restrict
   constexpr int P = Shape<N>::P;
   constexpr int LSTR = lds_pad(N);
   static_assert(FPB * LSTR == kLdsCf, "one LDS size for every transform size");
+  constexpr bool HW = FMT != 0;   // 4-byte words out
+  constexpr bool H16 = FMT == 1;  // FP16 with a power-of-two row scale
 
   const int fl = threadIdx.x / T;
   const int t = threadIdx.x % T;
@@ -190,7 +202,7 @@ __device__ __forceinline__ void fft_body(cf* __restrict__ lds, float* __restrict
     }
   }
 
-  // With FP16 output the kernel no longer saturates HBM, so the input of the
+  // With FP16 or BF16 output the kernel no longer saturates HBM, so the input of the
   // workgroup's next transform is loaded during the current one's passes (a
   // transform past the batch re-reads the last one and is never stored).
   // With FP32 output the traffic is already at the bandwidth limit and the
@@ -199,18 +211,18 @@ __device__ __forceinline__ void fft_body(cf* __restrict__ lds, float* __restrict
   // the paper-scale slot, the FFT then takes ~4 us longer and the
   // beamforming that reads its output ~10 us less.
   const long long fstep = (long long)vg * FPB;
-  cf vn[H16 ? 16 : 1];
+  cf vn[HW ? 16 : 1];
   auto prefetch = [&](long long f) {
     const cf* src = x + (f < batch ? f : batch - 1) * N;
 #pragma unroll
     for (int m = 0; m < 16; ++m) vn[m] = src[t + m * T];
   };
-  if constexpr (H16) prefetch((long long)vb * FPB + fl);
+  if constexpr (HW) prefetch((long long)vb * FPB + fl);
   for (long long f0 = (long long)vb * FPB; f0 < batch; f0 += fstep) {
     const long long fft = f0 + fl;
     const bool act = fft < batch;
     cf v[16];
-    if constexpr (H16) {
+    if constexpr (HW) {
 #pragma unroll
       for (int m = 0; m < 16; ++m) v[m] = act ? vn[m] : cf{0.f, 0.f};
       prefetch(fft + fstep);
@@ -283,13 +295,13 @@ __device__ __forceinline__ void fft_body(cf* __restrict__ lds, float* __restrict
         __syncthreads();
       } else if (act) {
         // last pass: Ns = N/16 = T, so bin f = t + r*T
-        if constexpr (H16) {
+        if constexpr (HW) {
           unsigned* dst = Xh + fft * ldo;
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
             int k = t + r * T + shift;
             if (k >= N) k -= N;
-            if (k < out_len) dst[k] = pack_h2(v[r].r * scale, v[r].i * scale);
+            if (k < out_len) dst[k] = H16 ? pack_h2(v[r].r * scale, v[r].i * scale) : pack_bf2(v[r].r, v[r].i);
           }
         } else {
           cf* dst = X + fft * ldo;
@@ -305,14 +317,14 @@ __device__ __forceinline__ void fft_body(cf* __restrict__ lds, float* __restrict
   }
 }
 
-template <int N, bool H16>
+template <int N, int FMT>
 __global__ __launch_bounds__(kThreads) void k_fft(const cf* __restrict__ x, cf* __restrict__ X,
                                                   unsigned* __restrict__ Xh, signed char* __restrict__ ex, int rows,
                                                   const cf* __restrict__ tw, long long batch, int out_len,
                                                   int shift, long long ldo) {
   __shared__ cf lds[kLdsCf];
   __shared__ float red[kThreads / 64];
-  fft_body<N, H16>(lds, red, blockIdx.x, gridDim.x, x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo);
+  fft_body<N, FMT>(lds, red, blockIdx.x, gridDim.x, x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo);
 }
 
 // Many cells of any transform sizes in one launch: cell c owns workgroups
@@ -328,19 +340,19 @@ __global__ __launch_bounds__(kThreads) void k_fft_cells(FftCells t) {
   const int vb = blockIdx.x - t.start[c], vg = t.start[c + 1] - t.start[c];
   switch (e.n_fft) {
     case 64:
-      fft_body<64, H16>(lds, red, vb, vg, e.x, e.X, e.Xh, e.ex, e.rows, e.tw, e.batch, e.out_len, e.shift, e.ldo);
+      fft_body<64, H16 ? 1 : 0>(lds, red, vb, vg, e.x, e.X, e.Xh, e.ex, e.rows, e.tw, e.batch, e.out_len, e.shift, e.ldo);
       break;
     case 256:
-      fft_body<256, H16>(lds, red, vb, vg, e.x, e.X, e.Xh, e.ex, e.rows, e.tw, e.batch, e.out_len, e.shift, e.ldo);
+      fft_body<256, H16 ? 1 : 0>(lds, red, vb, vg, e.x, e.X, e.Xh, e.ex, e.rows, e.tw, e.batch, e.out_len, e.shift, e.ldo);
       break;
     case 1024:
-      fft_body<1024, H16>(lds, red, vb, vg, e.x, e.X, e.Xh, e.ex, e.rows, e.tw, e.batch, e.out_len, e.shift, e.ldo);
+      fft_body<1024, H16 ? 1 : 0>(lds, red, vb, vg, e.x, e.X, e.Xh, e.ex, e.rows, e.tw, e.batch, e.out_len, e.shift, e.ldo);
       break;
     case 2048:
-      fft_body<2048, H16>(lds, red, vb, vg, e.x, e.X, e.Xh, e.ex, e.rows, e.tw, e.batch, e.out_len, e.shift, e.ldo);
+      fft_body<2048, H16 ? 1 : 0>(lds, red, vb, vg, e.x, e.X, e.Xh, e.ex, e.rows, e.tw, e.batch, e.out_len, e.shift, e.ldo);
       break;
     default:
-      fft_body<4096, H16>(lds, red, vb, vg, e.x, e.X, e.Xh, e.ex, e.rows, e.tw, e.batch, e.out_len, e.shift, e.ldo);
+      fft_body<4096, H16 ? 1 : 0>(lds, red, vb, vg, e.x, e.X, e.Xh, e.ex, e.rows, e.tw, e.batch, e.out_len, e.shift, e.ldo);
       break;
   }
 }
@@ -395,26 +407,28 @@ void fft_fill_twiddles(cf* host) {
 namespace {
 // Persistent grid of exactly the resident workgroups (no second round of
 // workgroups and its tail).
-template <int N, bool H16>
+template <int N, int FMT>
 hipError_t launch_nh(const cf* x, cf* X, unsigned* Xh, signed char* ex, int rows, const cf* tw, long long batch,
                      int out_len, int shift, long long ldo, long long blocks, int n_cu, hipStream_t s) {
   static const int per_cu = [] {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fft<N, H16>, kThreads, 0) != hipSuccess || n < 1) n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fft<N, FMT>, kThreads, 0) != hipSuccess || n < 1) n = 1;
     return n;
   }();
   const long long cap = (long long)n_cu * per_cu;
   if (blocks > cap) blocks = cap;
-  hipLaunchKernelGGL((k_fft<N, H16>), dim3((unsigned)blocks), dim3(kThreads), 0, s, x, X, Xh, ex, rows, tw, batch,
+  hipLaunchKernelGGL((k_fft<N, FMT>), dim3((unsigned)blocks), dim3(kThreads), 0, s, x, X, Xh, ex, rows, tw, batch,
                      out_len, shift, ldo);
   return hipGetLastError();
 }
 
+// FP32 output (Xh null), FP16 (Xh and ex), BF16 (Xh, ex null)
 template <int N>
 hipError_t launch_n(const cf* x, cf* X, unsigned* Xh, signed char* ex, int rows, const cf* tw, long long batch,
                     int out_len, int shift, long long ldo, long long blocks, int n_cu, hipStream_t s) {
-  return Xh ? launch_nh<N, true>(x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo, blocks, n_cu, s)
-            : launch_nh<N, false>(x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
+  if (!Xh) return launch_nh<N, 0>(x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
+  if (ex) return launch_nh<N, 1>(x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
+  return launch_nh<N, 2>(x, X, Xh, ex, rows, tw, batch, out_len, shift, ldo, blocks, n_cu, s);
 }
 }  // namespace
 
@@ -451,7 +465,7 @@ hipError_t launch_fft_cells(FftCells& t, bool h16, const cf* twiddles, int n_cu,
 
 hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_len, int shift, long long ldo,
                       const cf* twiddles, int n_cu, hipStream_t s, unsigned* Xh, signed char* ex, int rows) {
-  if (Xh && (rows < 1 || rows > 64 || !ex)) return hipErrorInvalidValue;
+  if (Xh && ex && (rows < 1 || rows > 64)) return hipErrorInvalidValue;
   if (batch <= 0) return hipSuccess;
   const int si = fft_size_index(n_fft);
   const TwiddleLayout lay = fft_twiddle_layout();

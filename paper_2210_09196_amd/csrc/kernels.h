@@ -32,7 +32,8 @@ int fft_size_index(int n_fft);  // 0..4, or -1 if unsupported
 // output rows ldo elements apart (>= out_len).  With Xh set, the rows are
 // written as FP16 pairs (half2 words, re low) scaled by 2^e per row instead
 // (X unused): transform i = g * rows + a (rows <= 64) stores e in
-// ex[g * 64 + (a % 4) * 16 + a / 4].
+// ex[g * 64 + (a % 4) * 16 + a / 4].  With Xh set and ex null, the rows are
+// bfloat16 pairs (re low), rounded to nearest even and not scaled.
 hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_len, int shift, long long ldo,
                       const cf* twiddles, int n_cu, hipStream_t s, unsigned* Xh = nullptr,
                       signed char* ex = nullptr, int rows = 0);
@@ -117,7 +118,9 @@ struct PilotScale {
 // instead as FP16 pairs (half2 words, pitches in words) with row a of batch
 // item i scaled by 2^e, e from launch_fft's exponent table (rows = n_ant),
 // and the product runs on FP16 matrix cores with FP32 accumulation (W
-// rounded to FP16); up to 64 antennas.
+// rounded to FP16); up to 64 antennas.  With Xh set and ex null, X is read
+// as bfloat16 pairs (no scales) and the product runs on BF16 matrix cores (W
+// rounded to BF16).
 hipError_t launch_beamform(const cf* W, const cf* X, cf* Y, int n_beams, int n_ant, int n_re, long long ldx,
                            long long sx, long long sy, long long batch, int n_cu, hipStream_t s,
                            const PilotScale* pilot_scale = nullptr, const unsigned* Xh = nullptr,

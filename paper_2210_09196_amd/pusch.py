@@ -77,6 +77,8 @@ _SIG = {
     "pusch_slot": (_I, [ctypes.POINTER(SlotDesc), _LL, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "pusch_slot_mixed_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SlotDesc), _LL]),
     "pusch_slot_mixed": (_I, [ctypes.POINTER(SlotDesc), _LL, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "pusch_slot_bf16_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SlotDesc), _LL]),
+    "pusch_slot_bf16": (_I, [ctypes.POINTER(SlotDesc), _LL, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "pusch_cells_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SlotDesc), _I, ctypes.POINTER(_LL), _I]),
     "pusch_cells": (_I, [ctypes.POINTER(SlotDesc), _I, ctypes.POINTER(_LL), ctypes.POINTER(_P), ctypes.POINTER(_P),
                          ctypes.POINTER(_P), _P, ctypes.c_size_t, _I, _P]),
@@ -308,7 +310,8 @@ class Slot:
 
     precision="mixed" uses pusch_slot_mixed (FP16 active-bin grids between
     OFDM demodulation and beamforming, beamforming on FP16 matrix cores with
-    FP32 accumulation, FP32 estimation and detection).  sigma2=None estimates
+    FP32 accumulation, FP32 estimation and detection); precision="bf16" uses
+    pusch_slot_bf16 (the same with bfloat16 grids and BF16 matrix cores).  sigma2=None estimates
     every slot's noise variance from its pilot symbols; each call leaves the
     estimates in self.sigma2_est ([n_slot] float32).  refine=True adds one
     iterative-refinement step to the MIMO solve.  time_varying=True gives
@@ -321,8 +324,9 @@ class Slot:
                  sigma2: float | None, n_slot: int, W: torch.Tensor | None = None, device="cuda",
                  precision: str = "fp32", refine: bool = False, time_varying: bool = False,
                  comb_aligned: bool = False):
-        if precision not in ("fp32", "mixed"):
-            raise PuschError("precision is 'fp32' or 'mixed'")
+        if precision not in ("fp32", "mixed", "bf16"):
+            raise PuschError("precision is 'fp32', 'mixed' or 'bf16'")
+        self.precision = precision
         self.mixed = precision == "mixed"
         pilot_symb = list(pilot_symb)
         if not 1 <= len(pilot_symb) <= MAX_PILOTS:
@@ -341,7 +345,8 @@ class Slot:
         d.W = _ptr(self.W)
         self.n_slot = n_slot
         self.n_data = n_symb - len(pilot_symb)
-        wsb = lib().pusch_slot_mixed_workspace_bytes if self.mixed else lib().pusch_slot_workspace_bytes
+        wsb = {"fp32": lib().pusch_slot_workspace_bytes, "mixed": lib().pusch_slot_mixed_workspace_bytes,
+               "bf16": lib().pusch_slot_bf16_workspace_bytes}[precision]
         nbytes = wsb(ctypes.byref(d), n_slot)
         if nbytes == 0 and n_slot > 0:
             raise PuschError("the library rejected the slot geometry (workspace size 0)")
@@ -364,7 +369,8 @@ class Slot:
         if self.n_slot == 0:
             return x_hat, status
         d.pilots = pilots.data_ptr()
-        fn, name = (lib().pusch_slot_mixed, "pusch_slot_mixed") if self.mixed else (lib().pusch_slot, "pusch_slot")
+        name = {"fp32": "pusch_slot", "mixed": "pusch_slot_mixed", "bf16": "pusch_slot_bf16"}[self.precision]
+        fn = getattr(lib(), name)
         _check(fn(ctypes.byref(d), self.n_slot, x_td.data_ptr(), x_hat.data_ptr(), _ptr(status), self.ws.data_ptr(),
                   self.ws_bytes, _stream()), name)
         return x_hat, status

@@ -23,7 +23,7 @@ def lib():
 
 def test_exports_every_declared_symbol(lib):
     names = pusch.header_symbols()
-    assert len(names) == 27
+    assert len(names) == 29
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(pusch._SIG)
@@ -315,6 +315,24 @@ def test_slot_mixed_workspace_and_validation(lib):
     assert f(ctypes.byref(many), 1, FAKE, FAKE2, None, ws, 1 << 40, None) == EUNSUP
     assert f(ctypes.byref(_desc(sigma2=-1.0)), 1, FAKE, FAKE2, None, ws, 1 << 40, None) == EINVAL
     need = lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(d), 2)
+    assert f(ctypes.byref(d), 2, FAKE, FAKE2, None, ws, need - 1, None) == ENOMEM
+    assert f(ctypes.byref(d), 0, FAKE, FAKE2, None, ws, need, None) == 0
+
+
+def test_slot_bf16_workspace_and_validation(lib):
+    # the bfloat16 form uses the mixed layout (its exponent table unused)
+    d = _desc()
+    for n in (1, 16):
+        assert lib.pusch_slot_bf16_workspace_bytes(ctypes.byref(d), n) == \
+            lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(d), n)
+    many = _desc(n_ant=65, n_beams=32)
+    assert lib.pusch_slot_bf16_workspace_bytes(ctypes.byref(many), 4) == 0
+    ws = ctypes.c_void_p(0x4000000000)
+    f = lib.pusch_slot_bf16
+    assert f(ctypes.byref(many), 1, FAKE, FAKE2, None, ws, 1 << 40, None) == EUNSUP
+    assert f(ctypes.byref(_desc(sigma2=-1.0)), 1, FAKE, FAKE2, None, ws, 1 << 40, None) == EINVAL
+    assert f(ctypes.byref(d), 1, None, FAKE2, None, ws, 1 << 40, None) == EINVAL
+    need = lib.pusch_slot_bf16_workspace_bytes(ctypes.byref(d), 2)
     assert f(ctypes.byref(d), 2, FAKE, FAKE2, None, ws, need - 1, None) == ENOMEM
     assert f(ctypes.byref(d), 0, FAKE, FAKE2, None, ws, need, None) == 0
 
