@@ -62,7 +62,7 @@ STAGE_FLOPS = {
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 (vector and MFMA, dense)
 RIDGE = FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)  # flop/B where the two roofs meet
 SLOT_FLOOR_BYTES = S * R * N * 8 + D * K * L * 8 + K * 4  # time-domain input + detected symbols
-STAGE_KERNEL = {"fft": "k_fft<4096, false>", "beamform": "k_beamform_k<2, 16>", "mmse": "k_mmse_mfma<8, true, 2, 12>"}
+STAGE_KERNEL = {"fft": "k_fft<4096, 0>", "beamform": "k_beamform_k<2, 16>", "mmse": "k_mmse_mfma<8, true, 2, 12>"}
 STAGE_SOURCE = {"fft": "fft.hip", "beamform": "beamform.hip", "mmse": "mmse.hip"}
 TRAFFIC_FILE = "profiles/hbm_traffic_paper_scale.md"
 
