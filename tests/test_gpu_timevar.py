@@ -50,6 +50,13 @@ def oracle(cfg, b, k, sigma2="given"):
     dict(n_ant=32, n_fft=2048, n_sc=1650, n_beams=16, n_ue=8, pilot_symb=(0, 4, 7, 11), qam_bits=4, channel="tdl"),
     # flat channel, pilots late in the slot (first data symbols held)
     dict(n_ant=16, n_fft=256, n_sc=240, n_beams=16, n_ue=4, pilot_symb=(5, 12), qam_bits=4, channel="flat"),
+    # 16 symbols: 14 data symbols (more than 12, not a multiple of the four
+    # lane groups), 16 UEs, a ragged last block of subcarriers
+    dict(n_ant=32, n_fft=1024, n_sc=825, n_beams=32, n_ue=16, n_symb=16, pilot_symb=(1, 14), qam_bits=4,
+         channel="tdl"),
+    # 11 symbols: 9 data symbols, 6 UEs (padding rows), ragged subcarriers
+    dict(n_ant=16, n_fft=1024, n_sc=601, n_beams=8, n_ue=6, n_symb=11, pilot_symb=(2, 8), qam_bits=2,
+         channel="tdl"),
 ])
 def test_time_varying_chain_matches_oracle(geom):
     cfg = synth.CFG1.replace(snr_db=25.0, doppler_hz=300.0, **geom)
