@@ -11,7 +11,9 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  * Numbers     complex values are interleaved FP32 pairs (pusch_c32, the same
- *             bytes as torch.complex64); all arithmetic on the GPU is FP32.
+ *             bytes as torch.complex64); arithmetic on the GPU is FP32 except
+ *             where an entry point states a narrower form (pusch_slot_mixed,
+ *             pusch_slot_bf16, the denoiser's bfloat16 layers).
  * Pointers    every data pointer is a caller-owned DEVICE buffer on the
  *             current HIP device.  The library never frees, retains or
  *             reallocates one after the call returns.  Buffers must be 8-byte
