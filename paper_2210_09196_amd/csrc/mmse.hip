@@ -1033,26 +1033,38 @@ struct TvLds {
   cf Lt[kSPW * kTri];
 };
 
-// dreg: the regularisation of row c16, on the diagonal of A.
-template <int NDP>
-__device__ __forceinline__ void tv_store(TvLds<NDP>& lds, const GpAcc& c0, const GpAcc& c1, f32x4 u1, f32x4 u2,
-                                         f32x4 u3, float al, float dreg, int q, int c16) {
+// dreg: the regularisation of row c16, on the diagonal of A.  g*: the three
+// Hermitian products as three real products each (GpAcc's g1, g2, g3).
+__device__ __forceinline__ void tv_store_g(cf* __restrict__ GA, cf* __restrict__ GB, cf* __restrict__ GC,
+                                           const f32x4 (&g0)[3], const f32x4 (&g1)[3], const f32x4 (&gu)[3],
+                                           float dreg, int q, int c16) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int i = 4 * q + v;
     if (i >= c16) {
       const int e = tri(i) + c16;
-      const cf g0 = cf{c0.g1[v] + c0.g2[v], c0.g3[v] - c0.g1[v] + c0.g2[v]};
-      const cf g1 = cf{c1.g1[v] + c1.g2[v], c1.g3[v] - c1.g1[v] + c1.g2[v]};
-      const cf gu = cf{u1[v] + u2[v], u3[v] - u1[v] + u2[v]};
-      lds.GA[e] = cf{g0.r + (i == c16 ? dreg : 0.f), g0.i};
-      lds.GB[e] = cf{gu.r - 3.f * g0.r - g1.r, gu.i - 3.f * g0.i - g1.i};
-      lds.GC[e] = cf{2.f * (g0.r + g1.r) - gu.r, 2.f * (g0.i + g1.i) - gu.i};
+      const cf a0 = cf{g0[0][v] + g0[1][v], g0[2][v] - g0[0][v] + g0[1][v]};
+      const cf a1 = cf{g1[0][v] + g1[1][v], g1[2][v] - g1[0][v] + g1[1][v]};
+      const cf au = cf{gu[0][v] + gu[1][v], gu[2][v] - gu[0][v] + gu[1][v]};
+      GA[e] = cf{a0.r + (i == c16 ? dreg : 0.f), a0.i};
+      GB[e] = cf{au.r - 3.f * a0.r - a1.r, au.i - 3.f * a0.i - a1.i};
+      GC[e] = cf{2.f * (a0.r + a1.r) - au.r, 2.f * (a0.i + a1.i) - au.i};
     }
-    if (c16 < kRowP<NDP>) {  // column c16: data symbol c16, time weight al
-      const cf p0 = cf{c0.p1[v] + c0.p2[v], c0.p3[v] - c0.p1[v] + c0.p2[v]};
-      const cf p1 = cf{c1.p1[v] + c1.p2[v], c1.p3[v] - c1.p1[v] + c1.p2[v]};
-      lds.P[i * kRowP<NDP> + c16] = cf{(1.f - al) * p0.r + al * p1.r, (1.f - al) * p0.i + al * p1.i};
+  }
+}
+
+// The time-weighted matched filter of column c16 (data symbol c16, weight al)
+// from both pilot symbols' products p0, p1 (three real products each).
+template <int NDP>
+__device__ __forceinline__ void tv_store_p(cf* __restrict__ P, const f32x4 (&p0)[3], const f32x4 (&p1)[3], float al,
+                                           int q, int c16) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 4 * q + v;
+    if (c16 < kRowP<NDP>) {
+      const cf b0 = cf{p0[0][v] + p0[1][v], p0[2][v] - p0[0][v] + p0[1][v]};
+      const cf b1 = cf{p1[0][v] + p1[1][v], p1[2][v] - p1[0][v] + p1[1][v]};
+      P[i * kRowP<NDP> + c16] = cf{(1.f - al) * b0.r + al * b1.r, (1.f - al) * b0.i + al * b1.i};
     }
   }
 }
@@ -1106,43 +1118,71 @@ __global__ __launch_bounds__(64, 3) void k_mmse_tv(const cf* __restrict__ Y, con
       const float wb0 = __int_as_float(tb.y), wb1 = __int_as_float(tb.w);
       const cf* yrow = Y + bi * g.y_batch + ysym + (long long)kk * nb;
       const bool live = c16 < nue && k < nsc;  // else zero rows of H
-      float4 la0[KS / 2], la1[KS / 2], lb0[KS / 2], lb1[KS / 2], yv[KS / 2];
-#pragma unroll
-      for (int u = 0; u < KS / 2; ++u) {
+      // both pilot symbols' estimates of K-step pair u (beams of fragment
+      // slots 2u, 2u + 1), zero on rows past n_ue and beams past n_beams
+      auto est = [&](int u, float4& h0, float4& h1) {
         const int b = frag_beam(2 * u, q);
-        la0[u] = load_pair_even(LSb + ta.x, b, nb);
-        la1[u] = load_pair_even(LSb + ta.z, b, nb);
-        lb0[u] = load_pair_even(LSb + tb.x, b, nb);
-        lb1[u] = load_pair_even(LSb + tb.z, b, nb);
-        yv[u] = load_pair_even(yrow, b, nb);
-      }
-      GpAcc a0{z4, z4, z4, z4, z4, z4}, a1{z4, z4, z4, z4, z4, z4};
-      f32x4 u1 = z4, u2 = z4, u3 = z4;
-#pragma unroll
-      for (int u = 0; u < KS / 2; ++u) {
-        const int b = frag_beam(2 * u, q);
+        const float4 p = load_pair_even(LSb + ta.x, b, nb), r = load_pair_even(LSb + ta.z, b, nb);
+        const float4 s_ = load_pair_even(LSb + tb.x, b, nb), t = load_pair_even(LSb + tb.z, b, nb);
         const bool keep = live && b < nb;
-        const float4 p = la0[u], r = la1[u], s_ = lb0[u], t = lb1[u], yy = yv[u];
-        const float4 h0 = {__builtin_fmaf(wa1, r.x, wa0 * p.x), __builtin_fmaf(wa1, r.y, wa0 * p.y),
-                           __builtin_fmaf(wa1, r.z, wa0 * p.z), __builtin_fmaf(wa1, r.w, wa0 * p.w)};
-        const float4 h1 = {__builtin_fmaf(wb1, t.x, wb0 * s_.x), __builtin_fmaf(wb1, t.y, wb0 * s_.y),
-                           __builtin_fmaf(wb1, t.z, wb0 * s_.z), __builtin_fmaf(wb1, t.w, wb0 * s_.w)};
+        h0 = float4{__builtin_fmaf(wa1, r.x, wa0 * p.x), __builtin_fmaf(wa1, r.y, wa0 * p.y),
+                    __builtin_fmaf(wa1, r.z, wa0 * p.z), __builtin_fmaf(wa1, r.w, wa0 * p.w)};
+        h1 = float4{__builtin_fmaf(wb1, t.x, wb0 * s_.x), __builtin_fmaf(wb1, t.y, wb0 * s_.y),
+                    __builtin_fmaf(wb1, t.z, wb0 * s_.z), __builtin_fmaf(wb1, t.w, wb0 * s_.w)};
+        if (!keep) h0 = h1 = float4{0.f, 0.f, 0.f, 0.f};
+      };
+      // pass 1: the three Hermitian products (9 MFMAs per K-step), to LDS
+      {
+        f32x4 g0[3] = {z4, z4, z4}, g1[3] = {z4, z4, z4}, gu[3] = {z4, z4, z4};
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const cf x0 = keep ? (e ? cf{h0.z, h0.w} : cf{h0.x, h0.y}) : cf{0.f, 0.f};
-          const cf x1 = keep ? (e ? cf{h1.z, h1.w} : cf{h1.x, h1.y}) : cf{0.f, 0.f};
-          const cf y = e ? cf{yy.z, yy.w} : cf{yy.x, yy.y};
-          gp_kstep(a0, x0, y);
-          gp_kstep(a1, x1, y);
-          const cf xu = cf{x0.r + x1.r, x0.i + x1.i};
-          u1 = mfma(xu.r, xu.r, u1);
-          u2 = mfma(xu.i, xu.i, u2);
-          u3 = mfma(xu.r - xu.i, xu.r + xu.i, u3);
+        for (int u = 0; u < KS / 2; ++u) {
+          float4 h0, h1;
+          est(u, h0, h1);
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const cf x0 = e ? cf{h0.z, h0.w} : cf{h0.x, h0.y};
+            const cf x1 = e ? cf{h1.z, h1.w} : cf{h1.x, h1.y};
+            const cf xu = cf{x0.r + x1.r, x0.i + x1.i};
+            g0[0] = mfma(x0.r, x0.r, g0[0]);
+            g0[1] = mfma(x0.i, x0.i, g0[1]);
+            g0[2] = mfma(x0.r - x0.i, x0.r + x0.i, g0[2]);
+            g1[0] = mfma(x1.r, x1.r, g1[0]);
+            g1[1] = mfma(x1.i, x1.i, g1[1]);
+            g1[2] = mfma(x1.r - x1.i, x1.r + x1.i, g1[2]);
+            gu[0] = mfma(xu.r, xu.r, gu[0]);
+            gu[1] = mfma(xu.i, xu.i, gu[1]);
+            gu[2] = mfma(xu.r - xu.i, xu.r + xu.i, gu[2]);
+          }
         }
+        // padding rows beyond n_ue (and a subcarrier past n_sc) get 1, so
+        // their part of every factor is the identity
+        tv_store_g(lds.GA, lds.GB, lds.GC, g0, g1, gu, (c16 < nue && k < nsc) ? s2 : 1.0f, q, c16);
       }
-      // padding rows beyond n_ue (and a subcarrier past n_sc) get 1, so
-      // their part of every factor is the identity
-      tv_store(lds, a0, a1, u1, u2, u3, al_lane, (c16 < nue && k < nsc) ? s2 : 1.0f, q, c16);
+      // pass 2: both matched filters (6 MFMAs per K-step; the estimates are
+      // formed again from the same LS values, L2 hits), to LDS
+      {
+        f32x4 p0[3] = {z4, z4, z4}, p1[3] = {z4, z4, z4};
+#pragma unroll
+        for (int u = 0; u < KS / 2; ++u) {
+          float4 h0, h1;
+          est(u, h0, h1);
+          const float4 yy = load_pair_even(yrow, frag_beam(2 * u, q), nb);
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const cf x0 = e ? cf{h0.z, h0.w} : cf{h0.x, h0.y};
+            const cf x1 = e ? cf{h1.z, h1.w} : cf{h1.x, h1.y};
+            const cf y = e ? cf{yy.z, yy.w} : cf{yy.x, yy.y};
+            const float ys = y.r + y.i;
+            p0[0] = mfma(x0.r, y.r, p0[0]);
+            p0[1] = mfma(x0.i, y.i, p0[1]);
+            p0[2] = mfma(x0.r - x0.i, ys, p0[2]);
+            p1[0] = mfma(x1.r, y.r, p1[0]);
+            p1[1] = mfma(x1.i, y.i, p1[1]);
+            p1[2] = mfma(x1.r - x1.i, ys, p1[2]);
+          }
+        }
+        tv_store_p<NDP>(lds.P, p0, p1, al_lane, q, c16);
+      }
     }
     __syncthreads();
 
