@@ -192,7 +192,8 @@ def _evm_db(xh, xt) -> float:  # 10 log10(sum |x_hat - x|^2 / sum |x|^2)
     return float(10.0 * np.log10(np.sum(np.abs(xh - xt) ** 2) / np.sum(np.abs(xt) ** 2)))
 
 
-def _run_variant(args, cfg, batch, x, p, x_hat32, precision: str, sigma2, time_varying: bool = False):
+def _run_variant(args, cfg, batch, x, p, x_hat32, precision: str, sigma2, time_varying: bool = False,
+                 fft_mfma: bool = False):
     """Time the 16-slot launch of one chain variant with the same protocol as
     the headline run; returns (ms per step, stage us per launch, x_hat, status, slot)."""
     import torch
@@ -201,7 +202,8 @@ def _run_variant(args, cfg, batch, x, p, x_hat32, precision: str, sigma2, time_v
 
     dev = x.device
     slot = pusch.Slot(cfg.n_ant, cfg.n_fft, cfg.n_sc, cfg.n_symb, cfg.n_beams, cfg.n_ue, cfg.pilot_symb,
-                      sigma2, N_SLOT, device=dev, precision=precision, time_varying=time_varying)
+                      sigma2, N_SLOT, device=dev, precision=precision, time_varying=time_varying,
+                      fft_mfma=fft_mfma)
     xh = torch.empty_like(x_hat32)
     st = torch.empty(N_SLOT, cfg.n_sc, dtype=torch.int32, device=dev)
     for _ in range(args.warmup):
@@ -253,6 +255,22 @@ def bench_bf16(args, cfg, batch, x, p, x_hat32, nd: int, ms32: float) -> dict:
             "speedup_vs_fp32": round(ms32 / ms, 3), "stage_us_per_launch": stage_us,
             "evm_db_fp32": round(e32, 3), "evm_db_bf16": round(eb, 3), "evm_gap_db": round(eb - e32, 4),
             "evm_slots": nd, "status_flags": int(st.sum().item())}
+
+
+def bench_fft_mfma(args, cfg, batch, x, p, x_hat32, nd: int, ms32: float) -> dict:
+    """The FP16 and bfloat16 chains with the FFT's radix-16 passes on the
+    matrix cores (slot option fft_mfma): time per step, FFT stage time and EVM."""
+    data = batch["data"][:nd].transpose(0, 1, 3, 2)
+    e32 = _evm_db(x_hat32[:nd].cpu().numpy(), data)
+    out = {"what": "radix-16 FFT passes as 16x16 DFT-matrix products on FP16 / BF16 MFMA, FP32 accumulation"}
+    for prec in ("mixed", "bf16"):
+        ms, stage_us, xh, st, _ = _run_variant(args, cfg, batch, x, p, x_hat32, prec, batch["sigma2"], fft_mfma=True)
+        e = _evm_db(xh[:nd].cpu().numpy(), data)
+        out[prec] = {"value": round(N_SLOT / (ms / 1e3), 1), "unit": "slots/s",
+                     "us_per_slot": round(1e3 * ms / N_SLOT, 3), "speedup_vs_fp32": round(ms32 / ms, 3),
+                     "stage_us_per_launch": stage_us, "evm_gap_db": round(e - e32, 4),
+                     "status_flags": int(st.sum().item())}
+    return out
 
 
 def bench_noise_est(args, cfg, batch, x, p, x_hat32, nd: int, ms32: float) -> dict:
@@ -576,6 +594,7 @@ def main() -> int:
     chain_bytes = sum(STAGE_BYTES.values()) * N_SLOT
     mixed = bench_mixed(args, cfg, batch, x, p, x_hat, nd, ms_per_step)
     bf16 = bench_bf16(args, cfg, batch, x, p, x_hat, nd, ms_per_step)
+    fft_mfma = bench_fft_mfma(args, cfg, batch, x, p, x_hat, nd, ms_per_step)
     noise = bench_noise_est(args, cfg, batch, x, p, x_hat, nd, ms_per_step)
     timevar = bench_time_varying(args, cfg, batch, x, p, x_hat, ms_per_step)
     out = {
@@ -609,6 +628,7 @@ def main() -> int:
         "status_flags": bad,
         "mixed": mixed,
         "bf16": bf16,
+        "fft_mfma": fft_mfma,
         "noise_est": noise,
         "time_varying": timevar,
     }

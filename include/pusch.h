@@ -242,6 +242,14 @@ typedef struct {
                                        the noise estimate predicts from neighbouring positions and
                                        counts the channel's variation between them as noise.
                                        pusch_slot_denoised: 0 only (PUSCH_EUNSUPPORTED otherwise) */
+  int fft_mfma;                     /* nonzero: OFDM demodulation with every radix-16 butterfly on the
+                                       matrix cores -- each pass of the 4096-point Stockham FFT is
+                                       the 16 x 16 DFT matrix times the butterflies' inputs, with
+                                       FP16 (pusch_slot_mixed) or BF16 (pusch_slot_bf16) operands
+                                       rounded as they enter each pass and FP32 accumulation.  Only
+                                       for those two entry points with n_fft = 4096
+                                       (PUSCH_EUNSUPPORTED otherwise, and in pusch_cells and
+                                       pusch_slot_denoised) */
 } pusch_slot_desc;
 
 /* Bytes of device workspace pusch_slot needs for n_slot slots (0 on bad input). */

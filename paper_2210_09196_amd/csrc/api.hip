@@ -490,6 +490,8 @@ int check_slot_call(const pusch_slot_desc* d, long long n_slot, const pusch_c32*
   if (n_slot < 0 || !x_td || !x_hat || !ws) return PUSCH_EINVAL;
   if (reinterpret_cast<uintptr_t>(ws) & 255) return PUSCH_EINVAL;
   if (mixed && !mixed_supported(d, n_slot)) return PUSCH_EUNSUPPORTED;
+  // matrix-core FFT passes: the 4-byte grids of the reduced-precision forms, 4096 points
+  if (d->fft_mfma && (!mixed || d->n_fft != 4096)) return PUSCH_EUNSUPPORTED;
   // per-symbol estimates: the detection kernel that interpolates the channel
   // itself (up to 16 UEs, an even number of beams), without refinement
   if (d->time_varying && !slot_fused(d)) return PUSCH_EUNSUPPORTED;
@@ -618,9 +620,14 @@ int run_slot(DeviceTables* t, const pusch_slot_desc* d, long long n_slot, const 
   const long long KP = mixed ? (long long)xa_pitch_h16(K) : (long long)xa_pitch(K);
   unsigned* Xh = mixed ? reinterpret_cast<unsigned*>(base + lay.off_xa) : nullptr;
   signed char* ex = mixed && !bf16 ? reinterpret_cast<signed char*>(base + lay.off_ex) : nullptr;
-  if (pusch::launch_fft(reinterpret_cast<const cf*>(x_td), Xa, d->n_fft, n_slot * S * R, K, K / 2, KP, t->twiddles,
-                        t->n_cu, s, Xh, ex, R) != hipSuccess)
+  if (mixed && d->fft_mfma) {
+    if (pusch::launch_fft_mfma(reinterpret_cast<const cf*>(x_td), d->n_fft, n_slot * S * R, K, K / 2, KP,
+                               t->twiddles, t->n_cu, s, Xh, ex, R) != hipSuccess)
+      return PUSCH_EHIP;
+  } else if (pusch::launch_fft(reinterpret_cast<const cf*>(x_td), Xa, d->n_fft, n_slot * S * R, K, K / 2, KP,
+                               t->twiddles, t->n_cu, s, Xh, ex, R) != hipSuccess) {
     return PUSCH_EHIP;
+  }
   // beamforming of every symbol, RE-major output; when the detection
   // kernel estimates the channel itself, the pilot symbols leave this stage
   // already divided by their pilots (the LS division of the channel estimate)
@@ -1045,6 +1052,7 @@ int cells_call(const pusch_slot_desc* d, int n_cells, const long long* n_slot, c
   for (int c = 0; c < n_cells; ++c) {
     if (int rc = check_geom(&d[c])) return rc;
     if (n_slot[c] < 0) return PUSCH_EINVAL;
+    if (d[c].fft_mfma) return PUSCH_EUNSUPPORTED;  // the grouped FFT runs on the vector units
     slice[c] = align256(slot_layout(&d[c], n_slot[c], mx).total);
     base[c] = static_cast<char*>(ws) + wall;
     wall += slice[c];
@@ -1228,7 +1236,7 @@ DnSlotLayout dn_slot_layout(const pusch_slot_desc* d, long long n_slot) {
 
 int check_dn_slot_geom(const pusch_slot_desc* d) {
   if (int rc = check_geom(d)) return rc;
-  if (d->refine || d->time_varying || d->noise_est || d->comb_aligned) return PUSCH_EUNSUPPORTED;
+  if (d->refine || d->time_varying || d->noise_est || d->comb_aligned || d->fft_mfma) return PUSCH_EUNSUPPORTED;
   if (!(d->sigma2 > 0.f) || !std::isfinite(d->sigma2)) return PUSCH_EINVAL;  // the network's unit
   if (d->n_ant > 1024) return PUSCH_EUNSUPPORTED;
   return PUSCH_OK;

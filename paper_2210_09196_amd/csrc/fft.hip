@@ -463,6 +463,248 @@ hipError_t launch_fft_cells(FftCells& t, bool h16, const cf* twiddles, int n_cu,
   return h16 ? launch_cells_h<true>(t, n_cu, s) : launch_cells_h<false>(t, n_cu, s);
 }
 
+namespace {
+// ---------------------------------------------------------------- radix-16 passes on matrix cores
+// The reduced-precision chains' FFT with every radix-16 butterfly on the
+// matrix cores: for N = 4096 = 16^3 each of the three Stockham passes is, per
+// transform, the 16 x 16 DFT matrix F[m][r] = exp(-2 pi i m r / 16) times the
+// 16 x 256 matrix of the butterflies' (twiddled) inputs, computed as four
+// real 16x16x16 products (FP16 or BF16 operands, FP32 accumulation):
+// Re = Fr Br - Fi Bi, Im = Fr Bi + Fi Br.  A workgroup of four waves takes
+// one transform at a time; wave w owns butterflies 64 w .. 64 w + 63 as four
+// 16-column blocks, and lane (q, c16) supplies inputs r = 4q .. 4q + 3 of
+// butterfly 16 b + c16 (the B operand) and receives outputs m = 4q .. 4q + 3
+// (the D operand), so the LDS exchange between passes, the twiddles and the
+// output are those of the VALU kernel's Stockham formulation (k_fft):
+// butterfly c of a pass with stride ns reads elements c + 256 r and writes
+// (c / ns) 16 ns + c % ns + m ns.  Values are rounded to the operand format
+// only as they enter a pass; LDS and the accumulators stay FP32.  FMT 1: FP16
+// operands, every row scaled by a power of two from its L1 norm before the
+// first pass (the partial sums of every pass are bounded by that norm, so no
+// value leaves FP16's range) and stored as FP16 pairs with that exponent, as
+// k_fft<N, 1>; FMT 2: BF16 operands and output, no scaling.
+typedef _Float16 mh4 __attribute__((ext_vector_type(4)));
+typedef short mb4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int FMT>
+struct MmaOp;
+template <>
+struct MmaOp<1> {
+  using T = mh4;
+  static __device__ __forceinline__ T pack(float a, float b, float c, float d) {
+    return T{(_Float16)a, (_Float16)b, (_Float16)c, (_Float16)d};
+  }
+  static __device__ __forceinline__ f32x4 mma(T a, T b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct MmaOp<2> {
+  using T = mb4;
+  static __device__ __forceinline__ T pack(float a, float b, float c, float d) {
+    return T{(short)bf16_rne(a), (short)bf16_rne(b), (short)bf16_rne(c), (short)bf16_rne(d)};
+  }
+  static __device__ __forceinline__ f32x4 mma(T a, T b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+
+// cos(2 pi k / 16) from the three constants of the 16-point DFT
+__device__ __forceinline__ float cos_16th(int k) {
+  switch (k & 15) {
+    case 0: return 1.f;
+    case 1: return kC1;
+    case 2: return kR2;
+    case 3: return kS1;
+    case 4: return 0.f;
+    case 5: return -kS1;
+    case 6: return -kR2;
+    case 7: return -kC1;
+    case 8: return -1.f;
+    case 9: return -kC1;
+    case 10: return -kR2;
+    case 11: return -kS1;
+    case 12: return 0.f;
+    case 13: return kS1;
+    case 14: return kR2;
+    default: return kC1;
+  }
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kThreads) void k_fft_mfma(const cf* __restrict__ x, unsigned* __restrict__ Xh,
+                                                       signed char* __restrict__ ex, int rows,
+                                                       const cf* __restrict__ tw, long long batch, int out_len,
+                                                       int shift, long long ldo) {
+  constexpr int N = 4096, T = N / 16;
+  using O = MmaOp<FMT>;
+  static_assert(kThreads == 256 && lds_pad(N - 1) < kLdsCf, "four waves, one transform in LDS");
+  __shared__ cf lds[kLdsCf];
+  __shared__ float red[kThreads / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int q = lane >> 4, c16 = lane & 15;
+  // A operand: F[c16][4q + i] as (re, im, -im)
+  typename O::T Ar, Ai, An;
+  {
+    float fr[4], fi[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = c16 * (4 * q + i);
+      fr[i] = cos_16th(k);
+      fi[i] = -cos_16th(k - 4);  // -sin(2 pi k / 16)
+    }
+    Ar = O::pack(fr[0], fr[1], fr[2], fr[3]);
+    Ai = O::pack(fi[0], fi[1], fi[2], fi[3]);
+    An = O::pack(-fi[0], -fi[1], -fi[2], -fi[3]);
+  }
+  // twiddles of this lane's inputs r = 4q + i: the pass with stride 16 needs
+  // exp(-2 pi i (c % 16) r / 256), the same for the lane's four butterflies;
+  // the pass with stride 256 exp(-2 pi i c r / 4096) (table blocks as k_fft)
+  cf w1[4], w2[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = 4 * q + i;
+    w1[i] = r ? tw[(r - 1) * 16 + c16] : cf{1.f, 0.f};
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+      const int c = (wv * 4 + bb) * 16 + c16;
+      w2[bb][i] = r ? tw[15 * 16 + (r - 1) * T + c] : cf{1.f, 0.f};
+    }
+  }
+  const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
+  // one 16-column block: D = F B for the lane's four inputs (FP32 values)
+  auto dft_block = [&](const cf (&v)[4], f32x4& dr, f32x4& di) {
+    const typename O::T br = O::pack(v[0].r, v[1].r, v[2].r, v[3].r);
+    const typename O::T bi = O::pack(v[0].i, v[1].i, v[2].i, v[3].i);
+    dr = O::mma(An, bi, O::mma(Ar, br, z4));
+    di = O::mma(Ai, br, O::mma(Ar, bi, z4));
+  };
+
+  // the next transform's input is loaded during the current one's passes (as
+  // k_fft with 4-byte output; a transform past the batch re-reads the last)
+  cf vn[4][4];
+  auto load = [&](long long ff) {
+    const cf* src = x + (ff < batch ? ff : batch - 1) * N;
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) vn[bb][i] = src[(wv * 4 + bb) * 16 + c16 + (4 * q + i) * T];
+  };
+  load(blockIdx.x);
+  for (long long f = blockIdx.x; f < batch; f += gridDim.x) {
+    cf v[4][4];
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[bb][i] = vn[bb][i];
+    load(f + gridDim.x);
+    if constexpr (FMT == 1) {
+      float s1 = 0.f;
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s1 += fabsf(v[bb][i].r) + fabsf(v[bb][i].i);
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) s1 += __shfl_xor(s1, o);
+      if (lane == 0) red[wv] = s1;
+      __syncthreads();
+      s1 = red[0] + red[1] + red[2] + red[3];
+      int k = 0;
+      (void)frexpf(s1, &k);
+      int e = s1 > 0.f ? 14 - k : 0;
+      e = e < -100 ? -100 : (e > 100 ? 100 : e);
+      const float scale = ldexpf(1.f, e);
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[bb][i] = cf{v[bb][i].r * scale, v[bb][i].i * scale};
+      if (threadIdx.x == 0) {
+        const long long grp = f / rows;
+        const int a = (int)(f - grp * rows);
+        ex[grp * 64 + (a & 3) * 16 + (a >> 2)] = (signed char)e;
+      }
+    }
+    // pass 1 of 3 (stride 1, no twiddles): output m of butterfly c to c * 16 + m
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+      f32x4 dr, di;
+      dft_block(v[bb], dr, di);
+      const int c = (wv * 4 + bb) * 16 + c16;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) lds[lds_pad(c * 16 + 4 * q + u)] = cf{dr[u], di[u]};
+    }
+    __syncthreads();
+    // pass 2 (stride 16)
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[bb][i] = lds[lds_pad((wv * 4 + bb) * 16 + c16 + (4 * q + i) * T)];
+    __syncthreads();
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[bb][i] = cmul(v[bb][i], w1[i]);
+      f32x4 dr, di;
+      dft_block(v[bb], dr, di);
+      const int cb = wv * 4 + bb;  // c / 16; c % 16 = c16
+#pragma unroll
+      for (int u = 0; u < 4; ++u) lds[lds_pad(cb * 256 + c16 + (4 * q + u) * 16)] = cf{dr[u], di[u]};
+    }
+    __syncthreads();
+    // pass 3 (stride 256): output m of butterfly c is bin c + 256 m
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[bb][i] = lds[lds_pad((wv * 4 + bb) * 16 + c16 + (4 * q + i) * T)];
+    __syncthreads();  // the next transform's first pass writes LDS
+    unsigned* dst = Xh + f * ldo;
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[bb][i] = cmul(v[bb][i], w2[bb][i]);
+      f32x4 dr, di;
+      dft_block(v[bb], dr, di);
+      const int c = (wv * 4 + bb) * 16 + c16;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int k = c + (4 * q + u) * T + shift;
+        if (k >= N) k -= N;
+        if (k < out_len) dst[k] = FMT == 1 ? pack_h2(dr[u], di[u]) : pack_bf2(dr[u], di[u]);
+      }
+    }
+  }
+}
+// Persistent grid of exactly the resident workgroups, as k_fft.
+template <int FMT>
+hipError_t launch_mfma_fmt(const cf* x, unsigned* Xh, signed char* ex, int rows, const cf* tw, long long batch,
+                           int out_len, int shift, long long ldo, int n_cu, hipStream_t s) {
+  static const int per_cu = [] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fft_mfma<FMT>, kThreads, 0) != hipSuccess || n < 1) n = 1;
+    return n;
+  }();
+  long long blocks = batch;
+  const long long cap = (long long)n_cu * per_cu;
+  if (blocks > cap) blocks = cap;
+  hipLaunchKernelGGL((k_fft_mfma<FMT>), dim3((unsigned)blocks), dim3(kThreads), 0, s, x, Xh, ex, rows, tw, batch,
+                     out_len, shift, ldo);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_fft_mfma(const cf* x, int n_fft, long long batch, int out_len, int shift, long long ldo,
+                           const cf* twiddles, int n_cu, hipStream_t s, unsigned* Xh, signed char* ex, int rows) {
+  if (n_fft != 4096 || !Xh || (ex && (rows < 1 || rows > 64)) || out_len > n_fft || shift < 0 || shift >= n_fft ||
+      ldo < out_len)
+    return hipErrorInvalidValue;
+  if (batch <= 0) return hipSuccess;
+  const TwiddleLayout lay = fft_twiddle_layout();
+  const cf* tw = twiddles + lay.offset[fft_size_index(n_fft)];
+  return ex ? launch_mfma_fmt<1>(x, Xh, ex, rows, tw, batch, out_len, shift, ldo, n_cu, s)
+            : launch_mfma_fmt<2>(x, Xh, ex, rows, tw, batch, out_len, shift, ldo, n_cu, s);
+}
+
 hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_len, int shift, long long ldo,
                       const cf* twiddles, int n_cu, hipStream_t s, unsigned* Xh, signed char* ex, int rows) {
   if (Xh && ex && (rows < 1 || rows > 64)) return hipErrorInvalidValue;

@@ -37,6 +37,11 @@ int fft_size_index(int n_fft);  // 0..4, or -1 if unsupported
 hipError_t launch_fft(const cf* x, cf* X, int n_fft, long long batch, int out_len, int shift, long long ldo,
                       const cf* twiddles, int n_cu, hipStream_t s, unsigned* Xh = nullptr,
                       signed char* ex = nullptr, int rows = 0);
+// The same outputs in the 4-byte forms (Xh required: FP16 with ex, bfloat16
+// without) with every radix-16 butterfly on the matrix cores (FP16 or BF16
+// operands, FP32 accumulation); n_fft = 4096 only.
+hipError_t launch_fft_mfma(const cf* x, int n_fft, long long batch, int out_len, int shift, long long ldo,
+                           const cf* twiddles, int n_cu, hipStream_t s, unsigned* Xh, signed char* ex, int rows);
 
 // Workgroups of a grouped persistent launch.  Cell c needs rounds(c)
 // workgroup-rounds of work (its items over what one workgroup takes per

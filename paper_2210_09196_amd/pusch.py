@@ -49,6 +49,7 @@ class SlotDesc(ctypes.Structure):
         ("refine", ctypes.c_int),
         ("time_varying", ctypes.c_int),
         ("comb_aligned", ctypes.c_int),
+        ("fft_mfma", ctypes.c_int),
     ]
 
 
@@ -318,12 +319,13 @@ class Slot:
     every data symbol its own channel estimate (interpolated in time between
     the pilot symbols) and its own factorisation.  comb_aligned=True: the
     pilot comb without stagger (each UE on the same subcarriers in every pilot
-    symbol)."""
+    symbol).  fft_mfma=True (with precision "mixed" or "bf16", n_fft 4096):
+    the FFT's radix-16 passes on the matrix cores."""
 
     def __init__(self, n_ant: int, n_fft: int, n_sc: int, n_symb: int, n_beams: int, n_ue: int, pilot_symb,
                  sigma2: float | None, n_slot: int, W: torch.Tensor | None = None, device="cuda",
                  precision: str = "fp32", refine: bool = False, time_varying: bool = False,
-                 comb_aligned: bool = False):
+                 comb_aligned: bool = False, fft_mfma: bool = False):
         if precision not in ("fp32", "mixed", "bf16"):
             raise PuschError("precision is 'fp32', 'mixed' or 'bf16'")
         self.precision = precision
@@ -341,6 +343,7 @@ class Slot:
         d.refine = 1 if refine else 0
         d.time_varying = 1 if time_varying else 0
         d.comb_aligned = 1 if comb_aligned else 0
+        d.fft_mfma = 1 if fft_mfma else 0
         self.W = None if W is None else _beamformer(W, n_beams, n_ant, "W")
         d.W = _ptr(self.W)
         self.n_slot = n_slot

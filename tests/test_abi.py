@@ -319,6 +319,21 @@ def test_slot_mixed_workspace_and_validation(lib):
     assert f(ctypes.byref(d), 0, FAKE, FAKE2, None, ws, need, None) == 0
 
 
+def test_fft_mfma_is_for_the_reduced_precision_4096_point_slots(lib):
+    ws = ctypes.c_void_p(0x4000000000)
+    d = _desc()
+    d.fft_mfma = 1
+    # the FP32 chain has no matrix-core FFT
+    assert lib.pusch_slot(ctypes.byref(d), 1, FAKE, FAKE2, None, ws, 1 << 40, None) == EUNSUP
+    small = _desc(n_fft=2048, n_sc=1650)
+    small.fft_mfma = 1
+    for f in (lib.pusch_slot_mixed, lib.pusch_slot_bf16):
+        assert f(ctypes.byref(small), 1, FAKE, FAKE2, None, ws, 1 << 40, None) == EUNSUP
+        need = lib.pusch_slot_mixed_workspace_bytes(ctypes.byref(d), 2)
+        assert f(ctypes.byref(d), 2, FAKE, FAKE2, None, ws, need - 1, None) == ENOMEM  # accepted up to the size check
+        assert f(ctypes.byref(d), 0, FAKE, FAKE2, None, ws, need, None) == 0
+
+
 def test_slot_bf16_workspace_and_validation(lib):
     # the bfloat16 form uses the mixed layout (its exponent table unused)
     d = _desc()
