@@ -390,11 +390,8 @@ __device__ __forceinline__ f32x4 mfma16(h4 a, h4 b, f32x4 c) {
 __device__ __forceinline__ f32x4 mfmab16(b4 a, b4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
-// FP32 to bfloat16 bits, round to nearest even (finite values)
-__device__ __forceinline__ short bf16_bits(float f) {
-  const unsigned u = __float_as_uint(f);
-  return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
+// FP32 to bfloat16 bits, round to nearest even (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ short bf16_bits(float f) { return __builtin_bit_cast(short, (__bf16)f); }
 
 template <int MT, int J, bool BF = false>
 __device__ __forceinline__ void bf_h16_body(int vb, int vg, const cf* __restrict__ W, const unsigned* __restrict__ Xh,

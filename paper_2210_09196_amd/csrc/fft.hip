@@ -152,13 +152,13 @@ __device__ __forceinline__ unsigned pack_h2(float re, float im) {
 }
 
 // BF16 output: the same words as bfloat16 pairs (re in the low half), rounded
-// to nearest even and not scaled (bfloat16 has FP32's exponent range); no
-// exponent table.  Finite inputs only (an FFT of finite samples).
-__device__ __forceinline__ unsigned bf16_rne(float f) {
-  const unsigned u = __float_as_uint(f);
-  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+// to nearest even (one v_cvt_pk_bf16_f32) and not scaled (bfloat16 has FP32's
+// exponent range); no exponent table.
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned pack_bf2(float re, float im) {
+  const bf2v v = {(__bf16)re, (__bf16)im};
+  return __builtin_bit_cast(unsigned, v);
 }
-__device__ __forceinline__ unsigned pack_bf2(float re, float im) { return bf16_rne(re) | (bf16_rne(im) << 16); }
 
 // LDS of a workgroup: FPB = kThreads / (N / 16) padded transforms, the same
 // 4352 complex values at every size (so one buffer serves every size of a
@@ -503,7 +503,7 @@ template <>
 struct MmaOp<2> {
   using T = mb4;
   static __device__ __forceinline__ T pack(float a, float b, float c, float d) {
-    return T{(short)bf16_rne(a), (short)bf16_rne(b), (short)bf16_rne(c), (short)bf16_rne(d)};
+    return __builtin_bit_cast(T, make_uint2(pack_bf2(a, b), pack_bf2(c, d)));
   }
   static __device__ __forceinline__ f32x4 mma(T a, T b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
