@@ -28,11 +28,11 @@ def host(t):
     return t.cpu().numpy()
 
 
-def run(cfg, b, time_varying, sigma2="given", precision="fp32"):
+def run(cfg, b, time_varying, sigma2="given", precision="fp32", fft_mfma=False):
     n = b["x_td"].shape[0]
     s2 = b["sigma2"] if sigma2 == "given" else None
     slot = pusch.Slot(cfg.n_ant, cfg.n_fft, cfg.n_sc, cfg.n_symb, cfg.n_beams, cfg.n_ue, cfg.pilot_symb, s2, n,
-                      precision=precision, time_varying=time_varying)
+                      precision=precision, time_varying=time_varying, fft_mfma=fft_mfma)
     xh, st = slot(dev(b["x_td"]), dev(b["pilots"]))
     return host(xh), host(st)
 
@@ -99,6 +99,19 @@ def test_time_varying_with_estimated_noise_and_mixed_precision():
     x16, st16 = run(cfg, b, True, sigma2=None, precision="mixed")
     assert np.all(st16 == 0)
     assert_xhat(x16[0], ref["x_hat"], 2e-3)
+
+
+@pytest.mark.parametrize("precision,tol", [("mixed", 4e-3), ("bf16", 1.6e-2)])
+def test_time_varying_estimated_noise_reduced_precision_and_matrix_core_fft(precision, tol):
+    # every option at once on the paper-scale geometry: per-symbol channel,
+    # estimated noise, 4-byte grids and the FFT's passes on the matrix cores
+    # (tolerances of the matrix-core FFT's tests)
+    cfg = synth.CFG2.replace(doppler_hz=300.0, snr_db=25.0)
+    b = synth.make_batch(cfg, [46])
+    xh, st = run(cfg, b, True, sigma2=None, precision=precision, fft_mfma=True)
+    assert np.all(st == 0)
+    ref = oracle(cfg, b, 0, sigma2=None)
+    assert_xhat(xh[0], ref["x_hat"], tol, precision)
 
 
 def test_time_varying_status_flags_accumulate_over_symbols():
