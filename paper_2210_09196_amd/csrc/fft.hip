@@ -238,21 +238,12 @@ __device__ __forceinline__ void fft_body(cf* __restrict__ lds, float* __restrict
       for (int m = 0; m < 16; ++m) v[m] = cf{0.f, 0.f};
     }
 
+    // FP16: the row's scale, from its L1 norm; it is applied only to the
+    // output, so a transform wider than a wave leaves its per-wave partial
+    // norms in LDS and adds them after pass 0's barrier (no barrier of its own)
     float scale = 1.f;
-    if constexpr (H16) {
-      float s1 = 0.f;
-#pragma unroll
-      for (int m = 0; m < 16; ++m) s1 += fabsf(v[m].r) + fabsf(v[m].i);
-      constexpr int WL = T < 64 ? T : 64;  // lanes of this transform in one wave
-#pragma unroll
-      for (int o = 1; o < WL; o <<= 1) s1 += __shfl_xor(s1, o);
-      if constexpr (T > 64) {
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s1;
-        __syncthreads();
-        s1 = 0.f;
-#pragma unroll
-        for (int w = 0; w < T / 64; ++w) s1 += red[fl * (T / 64) + w];
-      }
+    float s1 = 0.f;
+    auto set_scale = [&]() {
       int k = 0;
       (void)frexpf(s1, &k);
       int e = s1 > 0.f ? 14 - k : 0;
@@ -262,6 +253,18 @@ __device__ __forceinline__ void fft_body(cf* __restrict__ lds, float* __restrict
         const long long grp = fft / rows;
         const int a = (int)(fft - grp * rows);
         ex[grp * 64 + (a & 3) * 16 + (a >> 2)] = (signed char)e;
+      }
+    };
+    if constexpr (H16) {
+#pragma unroll
+      for (int m = 0; m < 16; ++m) s1 += fabsf(v[m].r) + fabsf(v[m].i);
+      constexpr int WL = T < 64 ? T : 64;  // lanes of this transform in one wave
+#pragma unroll
+      for (int o = 1; o < WL; o <<= 1) s1 += __shfl_xor(s1, o);
+      if constexpr (T > 64) {
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s1;
+      } else {
+        set_scale();
       }
     }
 
@@ -278,6 +281,12 @@ __device__ __forceinline__ void fft_body(cf* __restrict__ lds, float* __restrict
       for (int r = 0; r < R0; ++r) L[lds_pad(j * R0 + r)] = b[r];
     }
     __syncthreads();
+    if constexpr (H16 && T > 64) {
+      s1 = 0.f;
+#pragma unroll
+      for (int w = 0; w < T / 64; ++w) s1 += red[fl * (T / 64) + w];
+      set_scale();
+    }
 
 #pragma unroll
     for (int p = 0; p < P; ++p) {
