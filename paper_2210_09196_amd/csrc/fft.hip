@@ -16,7 +16,9 @@
 // thread loads its pass twiddles once, into registers.  Twiddles come from an
 // FP32 table computed in FP64 on the host.  The final pass writes straight
 // from registers to global memory, optionally keeping only the active
-// subcarriers (fused gather).
+// subcarriers (fused gather), as FP32, FP16 with a per-row power of two, or
+// bfloat16.  k_fft_mfma runs the same 4096-point passes with the butterflies
+// on the matrix cores (reduced-precision outputs only).
 #include <hip/hip_fp16.h>
 
 #include <cmath>

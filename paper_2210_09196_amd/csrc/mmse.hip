@@ -5,7 +5,7 @@
 // subcarrier and reused for every data symbol.
 //
 // The paper runs many independent small decompositions per core between
-// barriers (Sec. VI).  Two gfx950 kernels:
+// barriers (Sec. VI).  Three gfx950 kernels:
 //
 // k_mmse_mfma (n_ue <= 16): one wavefront takes 4 subcarriers per pass.
 //   Phase A runs the two dense products of each subcarrier -- the Gram
@@ -31,6 +31,12 @@
 //   subcarrier whose condition estimate exceeds 1e4 (||G||_F times a
 //   Hutchinson estimate of ||G^-1||_F from +-1 probe vectors solved in the
 //   spare right-hand-side slots), solved with the same factor.
+//
+// k_mmse_tv (time-varying channel, two pilot symbols, n_ue <= 16): every
+//   data symbol d has its own estimate (1 - a_d) H_0 + a_d H_1 and its own
+//   Gram matrix, formed from three Hermitian products per subcarrier; one
+//   workgroup takes 4 subcarriers one at a time, its four lane groups four
+//   data symbols at a time (details at the kernel).
 #include <cmath>
 
 #include "kernels.h"
