@@ -74,3 +74,30 @@ def test_precision_form_main_shape(n_beams, snr_db):
         # (2^-11 per value) is amplified by it -- refinement removes the solver's error, not
         # the data's, so the mixed chain's distance to the oracle is stated, with a loose bound
         assert res["mixed", True][1]["nrmse"] <= 1e-2
+
+
+@pytest.mark.parametrize("snr_db", [10.0, 30.0])
+def test_precision_form_main_shape_bfloat16(snr_db):
+    # the same main shape (64 x 64 DFT beamformer, 32 UEs: the detection's
+    # 17..32-UE kernel) through the bfloat16 chain, with and without the
+    # matrix-core FFT: EVM within 0.1 dB of FP32, NRMSE within the bfloat16
+    # form's bound (8e-3; 1.6e-2 with the FFT's three roundings)
+    cfg = synth.CFG2.replace(n_beams=64, n_ue=32, snr_db=snr_db)
+    b = synth.make_batch(cfg, [3100 + int(snr_db)])
+    ref = O.receive_slot(b["x_td"][0], b["pilots"][0], cfg.pilot_symb, cfg.n_ue, cfg.n_sc, b["sigma2"],
+                         n_beams=cfg.n_beams)
+    data = np.swapaxes(b["data"][0], 1, 2)
+    x32, st32 = run(cfg, b, "fp32", False)
+    assert np.all(st32 == 0)
+    e32 = M.evm_db(x32[0], data)
+    for fft_mfma, tol in ((False, 8e-3), (True, 1.6e-2)):
+        slot = pusch.Slot(cfg.n_ant, cfg.n_fft, cfg.n_sc, cfg.n_symb, cfg.n_beams, cfg.n_ue, cfg.pilot_symb,
+                          b["sigma2"], 1, precision="bf16", fft_mfma=fft_mfma)
+        xh, st = slot(dev(b["x_td"]), dev(b["pilots"]))
+        torch.cuda.synchronize()
+        xh, st = xh.cpu().numpy(), st.cpu().numpy()
+        assert np.all(st == 0)
+        gap = M.evm_db(xh[0], data) - e32
+        print(f"[precision] bf16 fft_mfma={int(fft_mfma)} {snr_db} dB: EVM gap {gap:.4f} dB", flush=True)
+        assert abs(gap) <= 0.1
+        assert_xhat(xh[0], ref["x_hat"], tol, f"bf16 fft_mfma={int(fft_mfma)}")
